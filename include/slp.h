@@ -1,0 +1,155 @@
+/*
+ * slp.h — smooth part of the single-layer potential by non-uniform FFT on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Exl & Schrefl, "Non-uniform FFT for the finite element computation of
+ * the micromagnetic scalar potential". For a closed triangulated surface with
+ * nodes x_i and a density g sampled at the three quadrature points of every
+ * triangle, the library evaluates at every node
+ *
+ *   phi_s(x_i) = 1/(4 pi) sum_k w_k g_k K_F(x~_i - y~_k),
+ *   K_F(xi)    = Re sum_{l in I_n} c_l(N_s) e^{2 pi i l.xi},
+ *
+ * the smooth part of the split kernel (Sec. 2.2, eq. approx2 and smooth_phi)
+ * with N_s an exponential sum for 1/r (Sec. 3.3) and its Fourier coefficients
+ * on the torus (eq. Fcoeff). It is computed as in eq. (convtheo) /
+ * (BEM_NFFT_compact2): Gaussian gridding of the charges w_k g_k on the
+ * oversampled grid (Sec. 3.1, eq. gridding), 3-D FFT (eq. FFT), deconvolution
+ * and multiplication by c_l (eq. deconv, Alg. 1), inverse FFT and
+ * interpolation at the nodes (type-2 NFFT).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SLP_OK (0) or a negative slp_status. No exception crosses
+ *    the ABI. slp_last_error() returns a message for the calling thread's last
+ *    failure (valid until that thread's next call).
+ *  - "stream" is a hipStream_t (NULL = the legacy default stream). Work is
+ *    enqueued asynchronously; the host returns before the device finishes.
+ *  - Pointers documented as "host" are read during the call only. Pointers
+ *    documented as "device" must stay valid until the stream has passed the
+ *    work that reads or writes them. The library never frees caller memory.
+ *  - A context (slp_geom) may be used by one stream at a time.
+ *  - Index conventions: triangles are 0-based node triples, counter-clockwise
+ *    seen from outside; quadrature point s (0..2) of triangle j has the long
+ *    index k = j + s*M (eq. naive_gridding) and barycentric weight 2/3 on
+ *    vertex s, 1/6 on the other two; its weight is |S_j|/3.
+ */
+#ifndef SLP_H
+#define SLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SLP_OK = 0,
+  SLP_EINVAL = -1,    /* invalid argument, shape or parameter */
+  SLP_ENOMEM = -2,    /* device or host allocation failed; nothing was created */
+  SLP_EDEVICE = -3,   /* a HIP call failed (message names it) */
+  SLP_EBUSY = -4,     /* server: no slot or memory free for the request now */
+  SLP_ENOTREADY = -5  /* server: request not finished yet */
+} slp_status;
+
+typedef enum { SLP_FP64 = 0, SLP_FP32 = 1 } slp_precision;
+
+/* Parameters of one geometry (Alg. 1, Require line: n in 2N^3, alpha >= 2,
+ * cut-off m; and the exponential sum of Sec. 3.3). */
+typedef struct {
+  int32_t grid[3];        /* oversampled grid N_q = alpha * n_q; n_q even; power of two, 8..2048 */
+  int32_t alpha;          /* oversampling factor alpha >= 2 (the paper fixes 2) */
+  int32_t m;              /* window cut-off: 2m grid points per axis, 1 <= m <= 10 */
+  int32_t precision;      /* slp_precision: FP32 runs gridding, FFT and interpolation in
+                             FP32 with the per-node sum in FP64; kernel tables are built
+                             in FP64 either way */
+  const double *es_w;     /* host [es_terms]: exponential-sum weights omega_t (physical units) */
+  const double *es_gamma; /* host [es_terms]: exponents gamma_t, 1/r ~ sum omega_t e^{-gamma_t r^2} */
+  int32_t es_terms;       /* number of terms S (>= 1) */
+  int32_t reserved0;
+  double eta2;            /* keep term t iff (pi n_q/2)^2 s_q^2 / gamma_t >= eta2 on every axis
+                             (Sec. 5, eq. error_est3: eta^2 bounds the Fourier tail); 37 by default */
+} slp_params;
+
+typedef struct slp_geom slp_geom;   /* opaque; owns device tables and work buffers */
+
+/* Geometry facts computed at setup (for tests and reports). */
+typedef struct {
+  double centre[3];       /* body centre c (bounding-box midpoint) */
+  double scale[3];        /* x~ = s (x - c); s_q N_q equal on all axes, body in [-0.2, 0.2]^3 */
+  double window_b;        /* Gaussian shape b = 2 alpha m / ((2 alpha - 1) pi), grid units */
+  int64_t n_nodes, n_tris, n_src;
+  int32_t terms_kept;     /* S' after the eta2 truncation */
+  int32_t lo[3];          /* first grid index of the region touched by any stencil */
+  int32_t extent[3];      /* its length per axis */
+  int32_t tiles[3];       /* 8^3 tiles covering the region */
+  int64_t device_bytes;   /* device memory held by the context */
+} slp_geom_info;
+
+/* Setup phase of Alg. 1 for one surface (Sec. 3.1-3.3). Scales the body into
+ * (-0.2, 0.2)^3 of the torus, forms the quadrature sources, bins sources and
+ * nodes by grid tiles, builds the Fourier coefficients of the kept
+ * exponential-sum terms (eq. Fcoeff, FP64 on the device) and the combined
+ * multiplier table, and allocates every work buffer.
+ *   out     : receives the new context (NULL on failure)
+ *   nodes   : host float64 [n_nodes][3], physical coordinates
+ *   tris    : host int32 [n_tris][3], 0-based
+ *   p       : host, see slp_params
+ * Errors: EINVAL for non-finite coordinates, out-of-range node indices,
+ * degenerate triangles, unsupported grid/m/alpha, or a stencil that would wrap
+ * around the torus (m too large for the grid); ENOMEM; EDEVICE. */
+int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes,
+                       const int32_t *tris, int64_t n_tris, const slp_params *p,
+                       void *stream);
+
+/* Charges q_k = w_k g_k for the next evaluation (eq. naive_gridding).
+ *   dens : device float64 [3 * n_tris], density at the quadrature points in
+ *          long-index order k = j + s*M. Read by a kernel on `stream`. */
+int slp_set_density(slp_geom *g, const double *dens, void *stream);
+
+/* phi_s at every node for the charges of the last slp_set_density
+ * (computation phase of Alg. 1, smooth part).
+ *   phi : device float64 [n_nodes], written in the caller's node order,
+ *         physical units (the 1/(4 pi) of the Newton kernel included). */
+int slp_eval_single_layer(slp_geom *g, double *phi, void *stream);
+
+/* Batched evaluation: item b uses geometry geoms[b], density dens[b] (device
+ * float64 [3 * n_tris(geoms[b])]) and writes phi[b] (device float64
+ * [n_nodes(geoms[b])]). Repeating one geometry evaluates several densities on
+ * one mesh. Items run in order on `stream`; equal to calling set_density +
+ * eval for each item. geoms/dens/phi are host arrays of length batch >= 1. */
+int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
+                     int32_t batch, void *stream);
+
+int slp_geom_get_info(const slp_geom *g, slp_geom_info *info);
+
+/* Per-stage device timing. When enabled, eval records HIP events around each
+ * stage on the eval stream: 0 charges, 1 spread, 2 FFT x fwd, 3 FFT y fwd,
+ * 4 FFT z (fwd, multiply, inv), 5 FFT y inv, 6 FFT x inv, 7 interpolation.
+ * slp_stage_times synchronises the last recorded eval and accumulates into
+ * ms[8] (summed over evals since the last reset) and *count (evals). */
+int slp_set_timing(slp_geom *g, int32_t enable);
+int slp_stage_times(slp_geom *g, double *ms, int64_t *count, int32_t reset);
+
+/* Copy an intermediate array of the last evaluation to a device buffer, for
+ * stage-by-stage comparison (which: 0 = spread grid, region [P_z][P_y][P_x] with
+ * P = 8*tiles; 1 = grid after the inverse FFT, [extent_z][extent_y][extent_x]).
+ * Values are in the context's precision; dst must hold the array. */
+int slp_debug_copy(const slp_geom *g, int32_t which, void *dst, size_t dst_bytes, void *stream);
+
+/* Exponential sum by the trapezoidal rule on 1/r = 2/sqrt(pi) int exp(-r^2 e^{2u} + u) du
+ * (Sec. 3.3 uses a tabulated sum of this family): nodes u_t = u_lo + t h up to
+ * u_hi = ln(7/r_lo), u_lo = ln(tol sqrt(pi) / (2 r_hi)); omega_t = 2 h e^{u_t}/sqrt(pi),
+ * gamma_t = e^{2 u_t}. Host arrays of capacity cap; *count receives the number of
+ * terms (EINVAL if cap is too small, with *count set to the required size). */
+int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omega,
+                    double *gamma, int32_t cap, int32_t *count);
+
+int slp_geom_destroy(slp_geom *g);
+const char *slp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLP_H */

@@ -1,0 +1,243 @@
+"""Python binding of libslp (include/slp.h): argument marshalling only.
+
+Every arithmetic step of the single-layer-potential path runs in the HIP
+library; this module converts torch device tensors and numpy host arrays into
+pointers and raises SlpError on a non-zero status. If libslp.so has not been
+built, importing the binding's functions raises (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "SlpError", "load_library", "expsum_sinc", "setup_geometry", "set_density",
+    "eval_single_layer", "eval_batched", "geom_get_info", "set_timing", "stage_times",
+    "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "STAGES",
+]
+
+FP64, FP32 = 0, 1
+STAGES = ("charges", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv",
+          "fft_x_inv", "interp")
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libslp.so")
+
+
+class SlpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libslp status {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32 * 3), ("alpha", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("es_w", ctypes.POINTER(ctypes.c_double)),
+                ("es_gamma", ctypes.POINTER(ctypes.c_double)), ("es_terms", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("eta2", ctypes.c_double)]
+
+
+class GeomInfo(ctypes.Structure):
+    _fields_ = [("centre", ctypes.c_double * 3), ("scale", ctypes.c_double * 3),
+                ("window_b", ctypes.c_double), ("n_nodes", ctypes.c_int64),
+                ("n_tris", ctypes.c_int64), ("n_src", ctypes.c_int64),
+                ("terms_kept", ctypes.c_int32), ("lo", ctypes.c_int32 * 3),
+                ("extent", ctypes.c_int32 * 3), ("tiles", ctypes.c_int32 * 3),
+                ("device_bytes", ctypes.c_int64)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def load_library():
+    """Load libslp.so (built in-tree by paper_1305_3162_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libslp is not built ({LIB_PATH} missing); run "
+                          "`python -m paper_1305_3162_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "slp_setup_geometry": [ctypes.POINTER(_VP), _VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                               ctypes.POINTER(Params), _VP],
+        "slp_set_density": [_VP, _VP, _VP],
+        "slp_eval_single_layer": [_VP, _VP, _VP],
+        "slp_eval_batched": [_VP, _VP, _VP, ctypes.c_int32, _VP],
+        "slp_geom_get_info": [_VP, ctypes.POINTER(GeomInfo)],
+        "slp_set_timing": [_VP, ctypes.c_int32],
+        "slp_stage_times": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                            ctypes.c_int32],
+        "slp_debug_copy": [_VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP],
+        "slp_expsum_sinc": [ctypes.c_double] * 4 + [_VP, _VP, ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_int32)],
+        "slp_geom_destroy": [_VP],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.slp_last_error.argtypes = []
+    lib.slp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SlpError(rc, load_library().slp_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return _VP(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _VP(stream)
+    return _VP(stream.cuda_stream)
+
+
+def _dev_f64(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} elements (has {t.numel()})")
+    return _VP(t.data_ptr())
+
+
+def expsum_sinc(h, r_lo, r_hi, tol):
+    """Exponential sum for 1/r (slp_expsum_sinc): returns (omega, gamma) float64 arrays."""
+    lib = load_library()
+    cnt = ctypes.c_int32(0)
+    lib.slp_expsum_sinc(h, r_lo, r_hi, tol, None, None, 0, ctypes.byref(cnt))
+    n = cnt.value
+    if n <= 0:
+        _check(-1)
+    w = np.empty(n)
+    g = np.empty(n)
+    _check(lib.slp_expsum_sinc(h, r_lo, r_hi, tol, w.ctypes.data, g.ctypes.data, n,
+                               ctypes.byref(cnt)))
+    return w, g
+
+
+def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
+                   stream=None):
+    """slp_setup_geometry: returns an opaque handle (int)."""
+    lib = load_library()
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    if nodes.ndim != 2 or nodes.shape[1] != 3 or tris.ndim != 2 or tris.shape[1] != 3:
+        raise ValueError("nodes must be [N, 3] and tris [M, 3]")
+    es_w = np.ascontiguousarray(es_w, dtype=np.float64)
+    es_gamma = np.ascontiguousarray(es_gamma, dtype=np.float64)
+    if es_w.shape != es_gamma.shape or es_w.ndim != 1:
+        raise ValueError("es_w and es_gamma must be 1-D of equal length")
+    p = Params()
+    p.grid[:] = [int(g) for g in grid]
+    p.alpha, p.m, p.precision = int(alpha), int(m), int(precision)
+    p.es_w = es_w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.es_gamma = es_gamma.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.es_terms = int(es_w.size)
+    p.eta2 = float(eta2)
+    h = _VP()
+    _check(lib.slp_setup_geometry(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
+                                  tris.ctypes.data, tris.shape[0], ctypes.byref(p),
+                                  _stream_ptr(stream)))
+    return h.value
+
+
+def set_density(geom, dens, stream=None):
+    info = geom_get_info(geom)
+    _check(load_library().slp_set_density(_VP(geom), _dev_f64(dens, info["n_src"], "dens"),
+                                          _stream_ptr(stream)))
+
+
+def eval_single_layer(geom, phi, stream=None):
+    info = geom_get_info(geom)
+    _check(load_library().slp_eval_single_layer(_VP(geom), _dev_f64(phi, info["n_nodes"], "phi"),
+                                                _stream_ptr(stream)))
+
+
+def eval_batched(geoms, dens, phis, stream=None):
+    n = len(geoms)
+    if not (len(dens) == len(phis) == n) or n < 1:
+        raise ValueError("geoms, dens and phis must have the same length >= 1")
+    G = (_VP * n)(*[_VP(g) for g in geoms])
+    D = (_VP * n)()
+    P = (_VP * n)()
+    for i, g in enumerate(geoms):
+        info = geom_get_info(g)
+        D[i] = _dev_f64(dens[i], info["n_src"], f"dens[{i}]").value
+        P[i] = _dev_f64(phis[i], info["n_nodes"], f"phi[{i}]").value
+    _check(load_library().slp_eval_batched(G, D, P, n, _stream_ptr(stream)))
+
+
+def geom_get_info(geom):
+    gi = GeomInfo()
+    _check(load_library().slp_geom_get_info(_VP(geom), ctypes.byref(gi)))
+    return {"centre": list(gi.centre), "scale": list(gi.scale), "window_b": gi.window_b,
+            "n_nodes": gi.n_nodes, "n_tris": gi.n_tris, "n_src": gi.n_src,
+            "terms_kept": gi.terms_kept, "lo": list(gi.lo), "extent": list(gi.extent),
+            "tiles": list(gi.tiles), "device_bytes": gi.device_bytes}
+
+
+def set_timing(geom, enable=True):
+    _check(load_library().slp_set_timing(_VP(geom), int(bool(enable))))
+
+
+def stage_times(geom, reset=False):
+    ms = (ctypes.c_double * 8)()
+    cnt = ctypes.c_int64(0)
+    _check(load_library().slp_stage_times(_VP(geom), ms, ctypes.byref(cnt), int(bool(reset))))
+    return dict(zip(STAGES, list(ms))), cnt.value
+
+
+def debug_copy(geom, which, dst, stream=None):
+    import torch
+    if not isinstance(dst, torch.Tensor) or not dst.is_cuda or not dst.is_contiguous():
+        raise TypeError("dst must be a contiguous CUDA tensor")
+    nbytes = dst.numel() * dst.element_size()
+    _check(load_library().slp_debug_copy(_VP(geom), int(which), _VP(dst.data_ptr()), nbytes,
+                                         _stream_ptr(stream)))
+
+
+def geom_destroy(geom):
+    _check(load_library().slp_geom_destroy(_VP(geom)))
+
+
+class Geometry:
+    """Owning wrapper around one slp_geom context."""
+
+    def __init__(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
+                 eta2=37.0, stream=None):
+        self.handle = setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision,
+                                     eta2, stream)
+        self.info = geom_get_info(self.handle)
+        self.precision = precision
+
+    def set_density(self, dens, stream=None):
+        set_density(self.handle, dens, stream)
+
+    def eval(self, phi, stream=None):
+        eval_single_layer(self.handle, phi, stream)
+
+    def solve(self, dens, stream=None):
+        import torch
+        phi = torch.empty(self.info["n_nodes"], dtype=torch.float64, device=dens.device)
+        self.set_density(dens, stream)
+        self.eval(phi, stream)
+        return phi
+
+    def close(self):
+        if self.handle:
+            geom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,717 @@
+// Host side of libslp: argument checking, the setup phase (scaling, quadrature
+// sources, binning, kernel tables) and the orchestration of the evaluation
+// passes. Every arithmetic step of the evaluation runs in slp_kernels.hip.
+#include "slp.h"
+#include "slp_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+using slp::kTile;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(SLP_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.141592653589793238462643383279502884;
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Stable counting sort of items by bin id; returns order (sorted -> item) and
+// bin_start [nbins + 1].
+void counting_sort(const std::vector<int32_t> &bin, int64_t nbins, std::vector<int32_t> &order,
+                   std::vector<int32_t> &start) {
+  start.assign(nbins + 1, 0);
+  for (int32_t b : bin) start[b + 1]++;
+  for (int64_t i = 0; i < nbins; ++i) start[i + 1] += start[i];
+  std::vector<int32_t> fill(start.begin(), start.end() - 1);
+  order.resize(bin.size());
+  for (size_t i = 0; i < bin.size(); ++i) order[fill[bin[i]]++] = (int32_t)i;
+}
+
+}  // namespace
+
+struct slp_geom {
+  int prec = SLP_FP64;
+  int N[3]{}, n[3]{}, alpha = 2, m = 4;
+  double b = 0.0;
+  double c[3]{}, s[3]{};
+  int64_t n_nodes = 0, n_tris = 0, n_src = 0;
+  int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
+  int32_t terms_kept = 0;
+  // device buffers
+  int32_t *src_cell = nullptr;
+  void *src_frac = nullptr;
+  double *src_w = nullptr;
+  int32_t *src_perm = nullptr;
+  int32_t *bin_start = nullptr;
+  void *q = nullptr;
+  int32_t *tgt_cell = nullptr;
+  void *tgt_frac = nullptr;
+  int32_t *tgt_perm = nullptr;
+  void *grid_a = nullptr;
+  void *S1 = nullptr;
+  void *S2 = nullptr;
+  void *grid_g = nullptr;
+  void *mu = nullptr;
+  void *tw[3] = {nullptr, nullptr, nullptr};
+  int64_t bytes = 0;
+  std::vector<void *> allocs;
+  // timing: a ring of event sets, one per evaluation, read back lazily
+  static constexpr int kRing = 32;
+  bool timing = false;
+  bool ev_ready = false;
+  bool density_marked = false;
+  hipEvent_t ev[kRing][9]{};
+  bool used[kRing]{};
+  int cur = 0;
+  double acc_ms[8]{};
+  int64_t count = 0;
+  hipEvent_t *evs() { return ev[cur]; }
+
+  size_t esz() const { return prec == SLP_FP64 ? sizeof(double) : sizeof(float); }
+
+  hipError_t alloc(void **p, size_t bytes_) {
+    *p = nullptr;
+    if (bytes_ == 0) bytes_ = 256;
+    hipError_t e = hipMalloc(p, bytes_);
+    if (e == hipSuccess) {
+      allocs.push_back(*p);
+      bytes += (int64_t)bytes_;
+    }
+    return e;
+  }
+  ~slp_geom() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (ev_ready)
+      for (auto &set : ev)
+        for (auto &e : set) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+int validate_params(const slp_params *p) {
+  if (!p) return fail(SLP_EINVAL, "params is NULL");
+  if (p->alpha < 2) return fail(SLP_EINVAL, "alpha must be >= 2 (got %d)", p->alpha);
+  if (p->m < 1 || p->m > slp::kMaxM)
+    return fail(SLP_EINVAL, "m must be in [1, %d] (got %d)", slp::kMaxM, p->m);
+  if (p->precision != SLP_FP64 && p->precision != SLP_FP32)
+    return fail(SLP_EINVAL, "precision must be SLP_FP64 or SLP_FP32");
+  for (int q = 0; q < 3; ++q) {
+    const int N = p->grid[q];
+    if (!is_pow2(N) || N < 8 || N > 2048)
+      return fail(SLP_EINVAL, "grid[%d] = %d: must be a power of two in [8, 2048]", q, N);
+    if (N % p->alpha != 0 || (N / p->alpha) % 2 != 0)
+      return fail(SLP_EINVAL, "grid[%d] = %d: must be alpha * n with n even", q, N);
+  }
+  if (p->es_terms < 1 || !p->es_w || !p->es_gamma)
+    return fail(SLP_EINVAL, "exponential sum: es_terms >= 1 and both arrays required");
+  for (int t = 0; t < p->es_terms; ++t)
+    if (!std::isfinite(p->es_w[t]) || !std::isfinite(p->es_gamma[t]) || p->es_gamma[t] <= 0.0)
+      return fail(SLP_EINVAL, "exponential sum term %d is not finite / gamma <= 0", t);
+  if (!(p->eta2 > 0.0) || !std::isfinite(p->eta2))
+    return fail(SLP_EINVAL, "eta2 must be positive and finite");
+  return SLP_OK;
+}
+
+template <typename T>
+void split_coords(const std::vector<double> &t, const std::vector<int32_t> &order,
+                  const int32_t lo[3], int64_t n, std::vector<int32_t> &cell, std::vector<T> &frac) {
+  cell.resize(3 * n);
+  frac.resize(3 * n);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t o = order[i];
+    for (int q = 0; q < 3; ++q) {
+      const double v = t[3 * o + q];
+      const double f = std::floor(v);
+      cell[q * n + i] = (int32_t)f - lo[q];
+      frac[q * n + i] = (T)(v - f);
+    }
+  }
+}
+
+template <typename T>
+int upload_tables(slp_geom *G, const std::vector<double> &ts, const std::vector<int32_t> &sorder,
+                  const std::vector<double> &tt, const std::vector<int32_t> &torder,
+                  hipStream_t st, std::vector<int32_t> &cellbuf_s, std::vector<T> &fracbuf_s,
+                  std::vector<int32_t> &cellbuf_t, std::vector<T> &fracbuf_t) {
+  split_coords<T>(ts, sorder, G->lo, G->n_src, cellbuf_s, fracbuf_s);
+  split_coords<T>(tt, torder, G->lo, G->n_nodes, cellbuf_t, fracbuf_t);
+  HIP_TRY(hipMemcpyAsync(G->src_cell, cellbuf_s.data(), cellbuf_s.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->src_frac, fracbuf_s.data(), fracbuf_s.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_cell, cellbuf_t.data(), cellbuf_t.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_frac, fracbuf_t.data(), fracbuf_t.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return SLP_OK;
+}
+
+template <typename T>
+int upload_twiddles(slp_geom *G, hipStream_t st, std::vector<std::vector<T>> &hold) {
+  const double pi = 3.141592653589793238462643383279502884;
+  hold.resize(3);
+  for (int q = 0; q < 3; ++q) {
+    const int N = G->N[q];
+    hold[q].resize(2 * (size_t)N);
+    for (int k = 0; k < N; ++k) {
+      const double a = 2.0 * pi * (double)k / (double)N;
+      hold[q][2 * k] = (T)std::cos(a);
+      hold[q][2 * k + 1] = (T)(-std::sin(a));
+    }
+    HIP_TRY(hipMemcpyAsync(G->tw[q], hold[q].data(), hold[q].size() * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+  return SLP_OK;
+}
+
+template <typename T>
+int run_eval(slp_geom *G, double *phi, hipStream_t st) {
+  const bool tm = G->timing;
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
+  // spread
+  {
+    slp::SpreadArgs<T> a{};
+    a.cell = G->src_cell;
+    a.frac = static_cast<const T *>(G->src_frac);
+    a.q = static_cast<const T *>(G->q);
+    a.bin_start = G->bin_start;
+    a.grid = static_cast<T *>(G->grid_a);
+    for (int i = 0; i < 3; ++i) a.tiles[i] = G->tiles[i];
+    a.ns = G->n_src;
+    a.inv_b = (T)(1.0 / G->b);
+    HIP_TRY(slp::launch_spread<T>(a, G->m, st));
+  }
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
+  const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
+  const int64_t Px = G->P[0], Py = G->P[1];
+  const int64_t Kx = G->K[0], Ky = G->K[1], Kz = G->K[2];
+  const int nx = G->n[0], ny = G->n[1], nz = G->n[2];
+  // x forward: real region rows -> kx = 0..n_x/2
+  {
+    slp::FftPass<T> p{};
+    p.in = G->grid_a; p.out = G->S1; p.tw = G->tw[0];
+    p.n_lines = Ry * Rz; p.l1 = Ry;
+    p.in_s1 = Px; p.in_s2 = Py * Px; p.in_es = 1; p.in_cnt = (int)Rx; p.in_shift = G->lo[0];
+    p.out_s1 = Kx; p.out_s2 = Ry * Kx; p.out_es = 1; p.out_cnt = (int)Kx; p.out_shift = 0;
+    p.sign = -1; p.in_real = 1;
+    HIP_TRY(slp::launch_fft<T>(p, G->N[0], st));
+  }
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
+  // y forward: region y -> ky = -n_y/2..n_y/2
+  {
+    slp::FftPass<T> p{};
+    p.in = G->S1; p.out = G->S2; p.tw = G->tw[1];
+    p.n_lines = Kx * Rz; p.l1 = Kx;
+    p.in_s1 = 1; p.in_s2 = Ry * Kx; p.in_es = Kx; p.in_cnt = (int)Ry; p.in_shift = G->lo[1];
+    p.out_s1 = 1; p.out_s2 = Ky * Kx; p.out_es = Kx; p.out_cnt = (int)Ky; p.out_shift = -ny / 2;
+    p.sign = -1;
+    HIP_TRY(slp::launch_fft<T>(p, G->N[1], st));
+  }
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
+  // z forward, multiply by mu on kz = -n_z/2..n_z/2, z inverse back to the region
+  {
+    slp::FftPass<T> p{};
+    p.in = G->S2; p.out = G->S2; p.tw = G->tw[2];
+    p.mu = static_cast<const T *>(G->mu);
+    p.n_lines = Kx * Ky; p.l1 = Kx;
+    p.in_s1 = 1; p.in_s2 = Kx; p.in_es = Ky * Kx; p.in_cnt = (int)Rz; p.in_shift = G->lo[2];
+    p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
+    p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
+    p.sign = -1; p.mul_inv = 1;
+    HIP_TRY(slp::launch_fft<T>(p, G->N[2], st));
+  }
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
+  // y inverse: ky -> region y
+  {
+    slp::FftPass<T> p{};
+    p.in = G->S2; p.out = G->S1; p.tw = G->tw[1];
+    p.n_lines = Kx * Rz; p.l1 = Kx;
+    p.in_s1 = 1; p.in_s2 = Ky * Kx; p.in_es = Kx; p.in_cnt = (int)Ky; p.in_shift = -ny / 2;
+    p.out_s1 = 1; p.out_s2 = Ry * Kx; p.out_es = Kx; p.out_cnt = (int)Ry; p.out_shift = G->lo[1];
+    p.sign = +1;
+    HIP_TRY(slp::launch_fft<T>(p, G->N[1], st));
+  }
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
+  // x inverse (Hermitian half spectrum -> real region rows)
+  {
+    slp::FftPass<T> p{};
+    p.in = G->S1; p.out = G->grid_g; p.tw = G->tw[0];
+    p.n_lines = Ry * Rz; p.l1 = Ry;
+    p.in_s1 = Kx; p.in_s2 = Ry * Kx; p.in_es = 1; p.in_cnt = (int)Kx; p.in_shift = 0;
+    p.in_hermitian = 1;
+    p.out_s1 = Rx; p.out_s2 = Ry * Rx; p.out_es = 1; p.out_cnt = (int)Rx; p.out_shift = G->lo[0];
+    p.out_real = 1; p.sign = +1;
+    HIP_TRY(slp::launch_fft<T>(p, G->N[0], st));
+  }
+  (void)nx;
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
+  {
+    slp::InterpArgs<T> a{};
+    a.cell = G->tgt_cell;
+    a.frac = static_cast<const T *>(G->tgt_frac);
+    a.perm = G->tgt_perm;
+    a.g = static_cast<const T *>(G->grid_g);
+    a.phi = phi;
+    for (int i = 0; i < 3; ++i) a.R[i] = G->R[i];
+    a.nt = G->n_nodes;
+    a.inv_b = (T)(1.0 / G->b);
+    HIP_TRY(slp::launch_interp<T>(a, G->m, st));
+  }
+  if (tm) {
+    HIP_TRY(hipEventRecord(G->evs()[8], st));
+    G->used[G->cur] = true;
+    G->cur = (G->cur + 1) % slp_geom::kRing;
+  }
+  return SLP_OK;
+}
+
+int collect_one(slp_geom *G, int r) {
+  if (!G->used[r]) return SLP_OK;
+  HIP_TRY(hipEventSynchronize(G->ev[r][8]));
+  for (int i = 0; i < 8; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, G->ev[r][i], G->ev[r][i + 1]));
+    G->acc_ms[i] += ms;
+  }
+  G->count += 1;
+  G->used[r] = false;
+  return SLP_OK;
+}
+
+// Accumulate every recorded evaluation (synchronises with the newest one).
+int collect_timing(slp_geom *G) {
+  for (int k = 0; k < slp_geom::kRing; ++k) {
+    int rc = collect_one(G, (G->cur + k) % slp_geom::kRing);
+    if (rc) return rc;
+  }
+  return SLP_OK;
+}
+
+int ensure_events(slp_geom *G) {
+  if (G->ev_ready) return SLP_OK;
+  for (auto &set : G->ev)
+    for (auto &e : set) HIP_TRY(hipEventCreate(&e));
+  G->ev_ready = true;
+  return SLP_OK;
+}
+
+// Start the event set of the next evaluation: the oldest set in the ring is
+// read back first if it is still pending (long completed in steady state).
+int begin_timed(slp_geom *G, hipStream_t st) {
+  int rc = ensure_events(G);
+  if (!rc) rc = collect_one(G, G->cur);
+  if (rc) return rc;
+  HIP_TRY(hipEventRecord(G->evs()[0], st));
+  return SLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *slp_last_error(void) { return g_err.c_str(); }
+
+int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omega, double *gamma,
+                    int32_t cap, int32_t *count) {
+  if (!(h > 0) || !(r_lo > 0) || !(r_hi > r_lo) || !(tol > 0) || !count)
+    return fail(SLP_EINVAL, "expsum: need h > 0, 0 < r_lo < r_hi, tol > 0, count != NULL");
+  const double sqrt_pi = std::sqrt(3.141592653589793238462643383279502884);
+  const double u_hi = std::log(7.0 / r_lo);
+  const double u_lo = std::log(tol * sqrt_pi / (2.0 * r_hi));
+  const int32_t n = (int32_t)std::floor((u_hi - u_lo) / h) + 1;
+  *count = n;
+  if (n > cap || !omega || !gamma) return fail(SLP_EINVAL, "expsum: capacity %d < %d terms", cap, n);
+  for (int32_t t = 0; t < n; ++t) {
+    const double u = u_lo + h * t;
+    omega[t] = (2.0 / sqrt_pi) * h * std::exp(u);
+    gamma[t] = std::exp(2.0 * u);
+  }
+  return SLP_OK;
+}
+
+int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, const int32_t *tris,
+                       int64_t n_tris, const slp_params *p, void *stream) {
+  if (!out) return fail(SLP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_params(p);
+  if (rc) return rc;
+  if (!nodes || !tris || n_nodes < 3 || n_tris < 1)
+    return fail(SLP_EINVAL, "need >= 3 nodes and >= 1 triangle");
+  if (3 * n_tris > (int64_t)std::numeric_limits<int32_t>::max() ||
+      n_nodes > (int64_t)std::numeric_limits<int32_t>::max())
+    return fail(SLP_EINVAL, "mesh too large for 32-bit indices");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // bounding box, scaling into (-0.2, 0.2)^3 with s_q N_q equal on every axis
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < n_nodes; ++i)
+    for (int q = 0; q < 3; ++q) {
+      const double v = nodes[3 * i + q];
+      if (!std::isfinite(v)) return fail(SLP_EINVAL, "node %lld has a non-finite coordinate", (long long)i);
+      lo[q] = std::min(lo[q], v);
+      hi[q] = std::max(hi[q], v);
+    }
+  for (int64_t j = 0; j < 3 * n_tris; ++j)
+    if (tris[j] < 0 || tris[j] >= n_nodes)
+      return fail(SLP_EINVAL, "triangle %lld references node %d out of range", (long long)(j / 3), tris[j]);
+
+  slp_geom *G = new (std::nothrow) slp_geom();
+  if (!G) return fail(SLP_ENOMEM, "host allocation failed");
+  struct Guard {
+    slp_geom *g;
+    ~Guard() { delete g; }
+  } guard{G};
+
+  G->prec = p->precision;
+  G->alpha = p->alpha;
+  G->m = p->m;
+  G->b = 2.0 * p->alpha * p->m / ((2.0 * p->alpha - 1.0) * 3.141592653589793238462643383279502884);
+  G->n_nodes = n_nodes;
+  G->n_tris = n_tris;
+  G->n_src = 3 * n_tris;
+  double Kmin = INFINITY;
+  for (int q = 0; q < 3; ++q) {
+    G->N[q] = p->grid[q];
+    G->n[q] = p->grid[q] / p->alpha;
+    G->c[q] = 0.5 * (lo[q] + hi[q]);
+    const double ext = hi[q] - lo[q];
+    if (ext > 0) Kmin = std::min(Kmin, 0.4 * G->N[q] / ext);
+  }
+  if (!std::isfinite(Kmin)) return fail(SLP_EINVAL, "all nodes coincide");
+  for (int q = 0; q < 3; ++q) G->s[q] = Kmin / G->N[q];
+
+  // quadrature sources (k = j + s M) and grid-unit coordinates t = (x~ + 1/2) N
+  const int64_t M = n_tris, Ms = G->n_src;
+  std::vector<double> ts(3 * Ms), wsrc(Ms), tt(3 * n_nodes);
+  const double bary[3][3] = {{4.0 / 6, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 4.0 / 6, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 4.0 / 6}};
+  for (int64_t j = 0; j < M; ++j) {
+    const double *P0 = nodes + 3 * (int64_t)tris[3 * j];
+    const double *P1 = nodes + 3 * (int64_t)tris[3 * j + 1];
+    const double *P2 = nodes + 3 * (int64_t)tris[3 * j + 2];
+    double e1[3], e2[3];
+    for (int q = 0; q < 3; ++q) { e1[q] = P1[q] - P0[q]; e2[q] = P2[q] - P0[q]; }
+    const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    if (!(area > 0.0)) return fail(SLP_EINVAL, "triangle %lld is degenerate", (long long)j);
+    for (int s = 0; s < 3; ++s) {
+      const int64_t k = j + s * M;
+      wsrc[k] = area / 3.0;
+      for (int q = 0; q < 3; ++q) {
+        const double y = bary[s][0] * P0[q] + bary[s][1] * P1[q] + bary[s][2] * P2[q];
+        ts[3 * k + q] = ((y - G->c[q]) * G->s[q] + 0.5) * G->N[q];
+      }
+    }
+  }
+  for (int64_t i = 0; i < n_nodes; ++i)
+    for (int q = 0; q < 3; ++q)
+      tt[3 * i + q] = ((nodes[3 * i + q] - G->c[q]) * G->s[q] + 0.5) * G->N[q];
+
+  // region touched by any stencil {floor(t) - m + 1 .. floor(t) + m}
+  int64_t cmin[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, cmax[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  auto upd = [&](const std::vector<double> &t, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int q = 0; q < 3; ++q) {
+        const int64_t f = (int64_t)std::floor(t[3 * i + q]);
+        cmin[q] = std::min(cmin[q], f);
+        cmax[q] = std::max(cmax[q], f);
+      }
+  };
+  upd(ts, Ms);
+  upd(tt, n_nodes);
+  for (int q = 0; q < 3; ++q) {
+    const int64_t rlo = cmin[q] - G->m + 1, rhi = cmax[q] + G->m;
+    if (rlo < 0 || rhi > G->N[q] - 1)
+      return fail(SLP_EINVAL, "axis %d: stencils reach [%lld, %lld] outside the grid [0, %d): "
+                  "m = %d is too large for grid %d", q, (long long)rlo, (long long)rhi, G->N[q], G->m, G->N[q]);
+    G->lo[q] = (int32_t)rlo;
+    G->R[q] = (int32_t)(rhi - rlo + 1);
+    G->tiles[q] = (G->R[q] + kTile - 1) / kTile;
+    G->P[q] = G->tiles[q] * kTile;
+  }
+  G->K[0] = G->n[0] / 2 + 1;
+  G->K[1] = G->n[1] + 1;
+  G->K[2] = G->n[2] + 1;
+
+  // exponential-sum truncation (keep the terms the grid resolves)
+  std::vector<double> om, gam;
+  for (int t = 0; t < p->es_terms; ++t) {
+    bool keep = true;
+    for (int q = 0; q < 3; ++q) {
+      const double lim = std::pow(3.141592653589793238462643383279502884 * G->n[q] / 2.0, 2) / p->eta2;
+      if (p->es_gamma[t] / (G->s[q] * G->s[q]) > lim) keep = false;
+    }
+    if (keep) { om.push_back(p->es_w[t]); gam.push_back(p->es_gamma[t]); }
+  }
+  if (om.empty()) return fail(SLP_EINVAL, "no exponential-sum term is resolved by the grid");
+  G->terms_kept = (int32_t)om.size();
+
+  // binning of sources and targets by 8^3 tiles of the region
+  const int64_t ntiles = (int64_t)G->tiles[0] * G->tiles[1] * G->tiles[2];
+  auto tile_of = [&](const double *t) {
+    int32_t id[3];
+    for (int q = 0; q < 3; ++q) id[q] = ((int32_t)std::floor(t[q]) - G->lo[q]) / kTile;
+    return id[0] + G->tiles[0] * (id[1] + G->tiles[1] * id[2]);
+  };
+  std::vector<int32_t> sbin(Ms), tbin(n_nodes), sorder, sstart, torder, tstart;
+  for (int64_t k = 0; k < Ms; ++k) sbin[k] = tile_of(&ts[3 * k]);
+  for (int64_t i = 0; i < n_nodes; ++i) tbin[i] = tile_of(&tt[3 * i]);
+  counting_sort(sbin, ntiles, sorder, sstart);
+  counting_sort(tbin, ntiles, torder, tstart);
+  std::vector<double> wsorted(Ms);
+  for (int64_t i = 0; i < Ms; ++i) wsorted[i] = wsrc[sorder[i]];
+
+  // device allocations
+  const size_t e = G->esz();
+  const int64_t Gsz = (int64_t)G->P[0] * G->P[1] * G->P[2];
+  const int64_t S1n = (int64_t)G->R[2] * G->R[1] * G->K[0];
+  const int64_t S2n = (int64_t)G->R[2] * G->K[1] * G->K[0];
+  const int64_t gn = (int64_t)G->R[0] * G->R[1] * G->R[2];
+  const int64_t mun = (int64_t)G->K[0] * G->K[1] * G->K[2];
+  void *tmp = nullptr;
+  bool ok = true;
+  ok &= G->alloc(&tmp, 3 * Ms * 4) == hipSuccess; G->src_cell = (int32_t *)tmp;
+  ok &= ok && G->alloc(&G->src_frac, 3 * Ms * e) == hipSuccess;
+  ok &= ok && G->alloc(&tmp, Ms * 8) == hipSuccess; G->src_w = (double *)tmp;
+  ok &= ok && G->alloc(&tmp, Ms * 4) == hipSuccess; G->src_perm = (int32_t *)tmp;
+  ok &= ok && G->alloc(&tmp, (ntiles + 1) * 4) == hipSuccess; G->bin_start = (int32_t *)tmp;
+  ok &= ok && G->alloc(&G->q, Ms * e) == hipSuccess;
+  ok &= ok && G->alloc(&tmp, 3 * n_nodes * 4) == hipSuccess; G->tgt_cell = (int32_t *)tmp;
+  ok &= ok && G->alloc(&G->tgt_frac, 3 * n_nodes * e) == hipSuccess;
+  ok &= ok && G->alloc(&tmp, n_nodes * 4) == hipSuccess; G->tgt_perm = (int32_t *)tmp;
+  ok &= ok && G->alloc(&G->grid_a, Gsz * e) == hipSuccess;
+  ok &= ok && G->alloc(&G->S1, S1n * 2 * e) == hipSuccess;
+  ok &= ok && G->alloc(&G->S2, S2n * 2 * e) == hipSuccess;
+  ok &= ok && G->alloc(&G->grid_g, gn * e) == hipSuccess;
+  ok &= ok && G->alloc(&G->mu, mun * e) == hipSuccess;
+  for (int q = 0; q < 3; ++q) ok &= ok && G->alloc(&G->tw[q], (size_t)G->N[q] * 2 * e) == hipSuccess;
+  if (!ok) return fail(SLP_ENOMEM, "device allocation failed (%lld bytes so far)", (long long)G->bytes);
+
+  HIP_TRY(hipMemcpyAsync(G->src_w, wsorted.data(), Ms * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->src_perm, sorder.data(), Ms * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->bin_start, sstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_nodes * 4, hipMemcpyHostToDevice, st));
+  std::vector<int32_t> cs, ct;
+  std::vector<double> fs64, ft64;
+  std::vector<float> fs32, ft32;
+  std::vector<std::vector<double>> tw64;
+  std::vector<std::vector<float>> tw32;
+  if (G->prec == SLP_FP64) {
+    rc = upload_tables<double>(G, ts, sorder, tt, torder, st, cs, fs64, ct, ft64);
+    if (!rc) rc = upload_twiddles<double>(G, st, tw64);
+  } else {
+    rc = upload_tables<float>(G, ts, sorder, tt, torder, st, cs, fs32, ct, ft32);
+    if (!rc) rc = upload_twiddles<float>(G, st, tw32);
+  }
+  if (rc) return rc;
+
+  // kernel Fourier coefficients (FP64) and the multiplier table
+  {
+    std::vector<double> glx, glw;
+    const int order = 16;
+    gauss_legendre(order, glx, glw);
+    const int S = G->terms_kept;
+    double *d_gl = nullptr, *d_om = nullptr, *d_gam = nullptr, *d_C[3] = {nullptr, nullptr, nullptr};
+    std::vector<void *> tmps;
+    auto talloc = [&](double **ptr, size_t n) {
+      hipError_t er = hipMalloc((void **)ptr, n * sizeof(double));
+      if (er == hipSuccess) tmps.push_back(*ptr);
+      return er;
+    };
+    struct TmpGuard {
+      std::vector<void *> &v;
+      ~TmpGuard() { for (void *x : v) (void)hipFree(x); }
+    } tguard{tmps};
+    int L[3];
+    for (int q = 0; q < 3; ++q) L[q] = G->n[q] / 2 + 1;
+    if (talloc(&d_gl, 2 * order) != hipSuccess || talloc(&d_om, S) != hipSuccess ||
+        talloc(&d_gam, 3 * (size_t)S) != hipSuccess || talloc(&d_C[0], (size_t)S * L[0]) != hipSuccess ||
+        talloc(&d_C[1], (size_t)S * L[1]) != hipSuccess || talloc(&d_C[2], (size_t)S * L[2]) != hipSuccess)
+      return fail(SLP_ENOMEM, "device allocation for kernel tables failed");
+    std::vector<double> gl(2 * order), gsc(3 * (size_t)S);
+    for (int j = 0; j < order; ++j) { gl[j] = glx[j]; gl[order + j] = glw[j]; }
+    for (int q = 0; q < 3; ++q)
+      for (int t = 0; t < S; ++t) gsc[(size_t)q * S + t] = gam[t] / (G->s[q] * G->s[q]);
+    HIP_TRY(hipMemcpyAsync(d_gl, gl.data(), gl.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_om, om.data(), om.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_gam, gsc.data(), gsc.size() * 8, hipMemcpyHostToDevice, st));
+    for (int q = 0; q < 3; ++q) {
+      const int panels = std::max(G->n[q] / 2 + 8, 16);
+      HIP_TRY(slp::launch_chat(d_C[q], d_gam + (size_t)q * S, S, L[q], d_gl, d_gl + order, order, panels, st));
+    }
+    if (G->prec == SLP_FP64)
+      HIP_TRY(slp::launch_mu<double>((double *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->N, G->K, G->b, st));
+    else
+      HIP_TRY(slp::launch_mu<float>((float *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->N, G->K, G->b, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  guard.g = nullptr;
+  *out = G;
+  return SLP_OK;
+}
+
+int slp_set_density(slp_geom *G, const double *dens, void *stream) {
+  if (!G || !dens) return fail(SLP_EINVAL, "geometry and density must be non-NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (G->timing) {
+    int rc = begin_timed(G, st);
+    if (rc) return rc;
+    G->density_marked = true;
+  }
+  if (G->prec == SLP_FP64)
+    HIP_TRY(slp::launch_charges<double>(dens, G->src_w, G->src_perm, (double *)G->q, G->n_src, st));
+  else
+    HIP_TRY(slp::launch_charges<float>(dens, G->src_w, G->src_perm, (float *)G->q, G->n_src, st));
+  return SLP_OK;
+}
+
+int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
+  if (!G || !phi) return fail(SLP_EINVAL, "geometry and phi must be non-NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (G->timing && !G->density_marked) {
+    int rc = begin_timed(G, st);
+    if (rc) return rc;
+  }
+  G->density_marked = false;
+  return G->prec == SLP_FP64 ? run_eval<double>(G, phi, st) : run_eval<float>(G, phi, st);
+}
+
+int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
+                     int32_t batch, void *stream) {
+  if (batch < 1 || !geoms || !dens || !phi) return fail(SLP_EINVAL, "batched: batch >= 1 and non-NULL arrays");
+  for (int32_t b = 0; b < batch; ++b)
+    if (!geoms[b] || !dens[b] || !phi[b]) return fail(SLP_EINVAL, "batched: item %d has a NULL pointer", b);
+  for (int32_t b = 0; b < batch; ++b) {
+    int rc = slp_set_density(geoms[b], dens[b], stream);
+    if (rc) return rc;
+    rc = slp_eval_single_layer(geoms[b], phi[b], stream);
+    if (rc) return rc;
+  }
+  return SLP_OK;
+}
+
+int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
+  if (!G || !info) return fail(SLP_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  for (int q = 0; q < 3; ++q) {
+    info->centre[q] = G->c[q];
+    info->scale[q] = G->s[q];
+    info->lo[q] = G->lo[q];
+    info->extent[q] = G->R[q];
+    info->tiles[q] = G->tiles[q];
+  }
+  info->window_b = G->b;
+  info->n_nodes = G->n_nodes;
+  info->n_tris = G->n_tris;
+  info->n_src = G->n_src;
+  info->terms_kept = G->terms_kept;
+  info->device_bytes = G->bytes;
+  return SLP_OK;
+}
+
+int slp_set_timing(slp_geom *G, int32_t enable) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (enable) {
+    int rc = ensure_events(G);
+    if (rc) return rc;
+  }
+  G->timing = enable != 0;
+  G->density_marked = false;
+  return SLP_OK;
+}
+
+int slp_stage_times(slp_geom *G, double *ms, int64_t *count, int32_t reset) {
+  if (!G || !ms || !count) return fail(SLP_EINVAL, "NULL argument");
+  int rc = collect_timing(G);
+  if (rc) return rc;
+  for (int i = 0; i < 8; ++i) ms[i] = G->acc_ms[i];
+  *count = G->count;
+  if (reset) {
+    for (double &v : G->acc_ms) v = 0.0;
+    G->count = 0;
+  }
+  return SLP_OK;
+}
+
+int slp_debug_copy(const slp_geom *G, int32_t which, void *dst, size_t dst_bytes, void *stream) {
+  if (!G || !dst) return fail(SLP_EINVAL, "NULL argument");
+  const size_t e = G->esz();
+  size_t need;
+  const void *src;
+  if (which == 0) {
+    need = (size_t)G->P[0] * G->P[1] * G->P[2] * e;
+    src = G->grid_a;
+  } else if (which == 1) {
+    need = (size_t)G->R[0] * G->R[1] * G->R[2] * e;
+    src = G->grid_g;
+  } else {
+    return fail(SLP_EINVAL, "debug_copy: which must be 0 or 1");
+  }
+  if (dst_bytes < need) return fail(SLP_EINVAL, "debug_copy: dst holds %zu bytes, need %zu", dst_bytes, need);
+  HIP_TRY(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return SLP_OK;
+}
+
+int slp_geom_destroy(slp_geom *G) {
+  if (!G) return SLP_OK;
+  (void)hipDeviceSynchronize();
+  delete G;
+  return SLP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations shared by the host API (slp_api.cpp) and the device
+// code (slp_kernels.hip). Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace slp {
+
+constexpr int kTile = 8;      // grid tile edge used by spread and interpolation bins
+constexpr int kMaxM = 10;     // largest supported window cut-off
+
+// Gridding (type-1 spread) of binned sources onto the tiled region.
+template <typename T>
+struct SpreadArgs {
+  const int32_t *cell;   // [3][ns] local cell index floor(t) - lo, sorted by tile
+  const T *frac;         // [3][ns] t - floor(t) in [0, 1)
+  const T *q;            // [ns] charges in sorted order
+  const int32_t *bin_start;  // [tiles + 1] source ranges per tile
+  T *grid;               // [P_z][P_y][P_x] output, P = 8 * tiles
+  int32_t tiles[3];
+  int64_t ns;
+  T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
+};
+
+// Interpolation (type-2 gather) at the tile-sorted targets.
+template <typename T>
+struct InterpArgs {
+  const int32_t *cell;   // [3][nt]
+  const T *frac;         // [3][nt]
+  const int32_t *perm;   // [nt] sorted -> caller index
+  const T *g;            // [R_z][R_y][R_x] grid after the inverse FFT
+  double *phi;           // [nt] output, caller order
+  int32_t R[3];
+  int64_t nt;
+  T inv_b;
+};
+
+// One batched 1-D FFT pass over "lines" of a 3-D array. Element e of line L is
+// read at in + (L % l1) * in_s1 + (L / l1) * in_s2 + e * in_es and placed at
+// LDS position (e + in_shift) mod N; after the transform, position
+// (e + out_shift) mod N is written to the analogous output address.
+template <typename T>
+struct FftPass {
+  const void *in;
+  void *out;
+  const void *tw;        // [N] e^{-2 pi i k / N}
+  const T *mu;           // fused multiplier (mode kMulInv), same addressing as `in`
+  int64_t n_lines;
+  int64_t l1;
+  int64_t in_s1, in_s2, in_es;
+  int64_t out_s1, out_s2, out_es;
+  int32_t in_cnt, in_shift;
+  int32_t out_cnt, out_shift;
+  int32_t mu_cnt, mu_shift;
+  int32_t sign;          // -1 forward, +1 inverse
+  int32_t in_real;       // input is real (T) instead of complex
+  int32_t in_hermitian;  // also place conj(v_e) at N - e (e >= 1)
+  int32_t out_real;      // store the real part only
+  int32_t mul_inv;       // forward, multiply by mu (zero elsewhere), inverse
+};
+
+template <typename T>
+hipError_t launch_charges(const double *dens, const double *w, const int32_t *perm, T *q,
+                          int64_t ns, hipStream_t s);
+template <typename T>
+hipError_t launch_spread(const SpreadArgs<T> &a, int m, hipStream_t s);
+template <typename T>
+hipError_t launch_interp(const InterpArgs<T> &a, int m, hipStream_t s);
+template <typename T>
+hipError_t launch_fft(const FftPass<T> &p, int N, hipStream_t s);
+
+// FP64 setup kernels.
+hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t L,
+                       const double *gl_x, const double *gl_w, int32_t order, int32_t panels,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2,
+                     const double *omega, int32_t S, const int32_t n[3], const int32_t N[3],
+                     const int32_t K[3], double b, hipStream_t s);
+
+}  // namespace slp

@@ -1,0 +1,90 @@
+"""The C ABI library loads, exports what include/slp.h declares, and rejects bad
+input on the host before touching a device (CPU only)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1305_3162_amd as slp
+from oracle import kernel
+from synth import icosphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:int|const char \*|size_t)\s*\*?\s*(slp_\w+)\s*\(", txt,
+                                    flags=re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = slp.load_library()
+    names = _declared()
+    assert {"slp_setup_geometry", "slp_set_density", "slp_eval_single_layer",
+            "slp_eval_batched"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_expsum_matches_oracle():
+    for (h, lo, hi, tol) in [(0.2, 1.7e-3, 1.73, 1e-12), (0.35, 1e-2, 1.0, 1e-8)]:
+        w1, g1 = slp.expsum_sinc(h, lo, hi, tol)
+        w2, g2 = kernel.expsum_sinc(h, lo, hi, tol)
+        assert w1.shape == w2.shape
+        assert np.allclose(w1, w2, rtol=1e-14, atol=0) and np.allclose(g1, g2, rtol=1e-14, atol=0)
+
+
+def _es():
+    return slp.expsum_sinc(0.2, 2e-3, 2.0, 1e-12)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(grid=(64, 64, 48)), "power of two"),
+    (dict(grid=(64, 64, 64), alpha=1), "alpha"),
+    (dict(grid=(64, 64, 64), m=0), "m must be"),
+    (dict(grid=(64, 64, 64), m=11), "m must be"),
+    (dict(grid=(8, 8, 8), m=4), "too large for grid"),
+    (dict(grid=(64, 64, 64), precision=7), "precision"),
+    (dict(grid=(64, 64, 64), eta2=-1.0), "eta2"),
+])
+def test_setup_rejects_bad_parameters(kw, msg):
+    nodes, tris = icosphere(1)
+    w, g = _es()
+    args = dict(grid=(64, 64, 64), m=4, alpha=2, precision=slp.FP64, eta2=37.0)
+    args.update(kw)
+    with pytest.raises(slp.SlpError) as ei:
+        slp.setup_geometry(nodes, tris, args["grid"], args["m"], w, g, args["alpha"],
+                           args["precision"], args["eta2"], stream=0)
+    assert ei.value.code == -1 and msg in str(ei.value)
+
+
+def test_setup_rejects_bad_mesh():
+    nodes, tris = icosphere(1)
+    w, g = _es()
+    bad = nodes.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(slp.SlpError, match="non-finite"):
+        slp.setup_geometry(bad, tris, (64,) * 3, 4, w, g, stream=0)
+    t2 = tris.copy()
+    t2[5, 2] = nodes.shape[0]
+    with pytest.raises(slp.SlpError, match="out of range"):
+        slp.setup_geometry(nodes, t2, (64,) * 3, 4, w, g, stream=0)
+    t3 = tris.copy()
+    t3[2] = [t3[2, 0], t3[2, 0], t3[2, 1]]
+    with pytest.raises(slp.SlpError, match="degenerate"):
+        slp.setup_geometry(nodes, t3, (64,) * 3, 4, w, g, stream=0)
+    with pytest.raises(slp.SlpError, match="es_terms"):
+        slp.setup_geometry(nodes, tris, (64,) * 3, 4, w[:0], g[:0], stream=0)
+
+
+def test_unresolved_expsum_rejected():
+    nodes, tris = icosphere(1)
+    # a single very sharp term cannot be resolved by an 8-point tensor grid
+    with pytest.raises(slp.SlpError, match="no exponential-sum term"):
+        slp.setup_geometry(nodes, tris, (16,) * 3, 1, np.array([1.0]), np.array([1e9]), stream=0)
