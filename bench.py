@@ -1,0 +1,193 @@
+"""Throughput of the smooth-part single-layer potential on one MI355X.
+
+One step = one pass of the whole hot path on the resident workload: charges
+q = w g (set_density), gridding, the pruned 3-D FFT with the fused kernel
+multiplier, the inverse FFT and the interpolation at the nodes
+(eval_single_layer). Metric: (M_q + N) points per second, M_q quadrature
+sources and N nodes, stated with the relative L2 error against the FP64
+oracle (the NDFT route of the definition).
+
+Default workload: unit cube, 64 x 64 cells per face (49,152 triangles, 24,578
+nodes, 147,456 sources), seeded smooth magnetisation (seed 2), grid 128^3,
+FP64 with cut-off m = 8. Usage:
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32] [--m M]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # published MI355X figures
+    "hbm_GBps": 8000.0,
+    "f64_vector_TFLOPs": 78.6,
+    "f32_vector_TFLOPs": 157.3,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--workload", default="cube64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_units(stage, info, m, esz):
+    """(amount, unit, bound) of algorithmic work of one launch of `stage`.
+
+    spread: 2 (2m)^3 + (2m)^2 flops per source (tensor-product accumulate);
+    interp: 2 (2m)^3 + (2m)^2 flops per node; FFT passes: bytes read + written
+    by the pass over the pruned region (complex = 2 esz bytes)."""
+    w = 2 * m
+    R = info["extent"]
+    n = info["_n"]
+    Kx, Ky, Kz = n[0] // 2 + 1, n[1] + 1, n[2] + 1
+    c = 2 * esz
+    if stage == "spread":
+        return info["n_src"] * (2.0 * w ** 3 + w ** 2), "flop", "alu"
+    if stage == "interp":
+        return info["n_nodes"] * (2.0 * w ** 3 + w ** 2), "flop", "alu"
+    if stage == "fft_x_fwd":
+        return R[2] * R[1] * (R[0] * esz + Kx * c), "byte", "hbm"
+    if stage == "fft_y_fwd":
+        return R[2] * Kx * (R[1] * c + Ky * c), "byte", "hbm"
+    if stage == "fft_z_mul_inv":
+        return Kx * Ky * (2 * R[2] * c + Kz * esz), "byte", "hbm"
+    if stage == "fft_y_inv":
+        return R[2] * Kx * (Ky * c + R[1] * c), "byte", "hbm"
+    if stage == "fft_x_inv":
+        return R[2] * R[1] * (Kx * c + R[0] * esz), "byte", "hbm"
+    if stage == "charges":
+        return info["n_src"] * (8 + 8 + 4 + esz), "byte", "hbm"
+    raise KeyError(stage)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
+              "part of it", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1305_3162_amd as slp
+    from synth.workloads import make_workload
+
+    prec = slp.FP64 if args.precision == "fp64" else slp.FP32
+    m = args.m if args.m is not None else (8 if prec == slp.FP64 else 5)
+    wl = make_workload(args.workload, m)
+    esz = 8 if prec == slp.FP64 else 4
+    w, g = slp.expsum_sinc(wl.es_h, wl.es_r_lo, wl.es_r_hi, wl.es_tol)
+    stream = torch.cuda.current_stream()
+    geom = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2)
+    info = dict(geom.info)
+    info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
+    dens = torch.as_tensor(wl.dens, device="cuda")
+    phi = torch.empty(wl.n_nodes, dtype=torch.float64, device="cuda")
+
+    def step():
+        geom.set_density(dens, stream)
+        geom.eval(phi, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps, per-stage HIP events recorded on the eval stream
+    slp.set_timing(geom.handle, True)
+    slp.stage_times(geom.handle, reset=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms, cnt = slp.stage_times(geom.handle, reset=True)
+    slp.set_timing(geom.handle, False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = max(wall * 1e3, gpu_ms) / args.steps
+    pts = wl.n_src + wl.n_nodes
+    value = pts / (ms_per_step * 1e-3)
+    avg = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
+
+    # roofline of the dominant kernel
+    dom = max(avg, key=avg.get)
+    amount, unit, bound = algorithmic_units(dom, info, m, esz)
+    dur_s = avg[dom] * 1e-3
+    if bound == "hbm":
+        achieved, peak, runit = amount / dur_s / 1e9, PEAK["hbm_GBps"], "GB/s"
+    else:
+        achieved = amount / dur_s / 1e12
+        peak = PEAK["f64_vector_TFLOPs"] if prec == slp.FP64 else PEAK["f32_vector_TFLOPs"]
+        runit = "TFLOP/s"
+    roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,
+                "frac": round(achieved / peak, 5), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(avg[dom] * 1e3, 3)}
+
+    out_phi = phi.cpu().numpy()
+    rel_err = None
+    cpu_baseline = None
+    if not args.no_oracle:
+        from oracle import direct
+        p = direct.prepare_workload(wl)
+        t1 = time.perf_counter()
+        ref = direct.phi_ndft(p)
+        t_cpu = time.perf_counter() - t1
+        rel_err = float(np.linalg.norm(out_phi - ref) / np.linalg.norm(ref))
+        if not args.no_cpu_baseline:
+            try:
+                from threadpoolctl import threadpool_info
+                cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+            except Exception:
+                cores = os.cpu_count()
+            cpu_baseline = {"value": round(pts / t_cpu, 2), "unit": "pts/s", "cores": cores,
+                            "kind": "oracle",
+                            "sample": f"R2 NDFT definition over all {wl.n_src} sources and "
+                                      f"{wl.n_nodes} nodes of the same workload (one solve, "
+                                      f"{t_cpu:.2f} s)"}
+
+    rec = {
+        "metric": "SL-potential NUFFT (M+N) pts/s at stated rel err",
+        "value": round(value, 1),
+        "unit": "pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == slp.FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: unit cube 64x64 cells per face, {wl.tris.shape[0]} "
+                               f"triangles, {wl.n_nodes} nodes, {wl.n_src} quadrature sources, "
+                               f"grid {wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]}, alpha 2, "
+                               f"Gaussian cut-off m={m}" if args.workload == "cube64" else wl.name,
+                   "m": m, "precision": args.precision, "points": pts},
+        "rel_l2_err_vs_oracle": rel_err,
+        "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu_baseline,
+    }
+    print(json.dumps(rec), flush=True)
+    geom.close()
+
+
+if __name__ == "__main__":
+    main()
