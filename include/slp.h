@@ -59,7 +59,7 @@ typedef enum { SLP_FP64 = 0, SLP_FP32 = 1 } slp_precision;
 typedef struct {
   int32_t grid[3];        /* oversampled grid N_q = alpha * n_q; n_q even; power of two, 8..2048 */
   int32_t alpha;          /* oversampling factor alpha >= 2 (the paper fixes 2) */
-  int32_t m;              /* window cut-off: 2m grid points per axis, 1 <= m <= 10 */
+  int32_t m;              /* window cut-off: 2m grid points per axis, 1 <= m <= 8 */
   int32_t precision;      /* slp_precision: FP32 runs gridding, FFT and interpolation in
                              FP32 with the per-node sum in FP64; kernel tables are built
                              in FP64 either way */

@@ -96,16 +96,22 @@ struct slp_geom {
   int64_t n_nodes = 0, n_tris = 0, n_src = 0;
   int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
   int32_t terms_kept = 0;
+  int32_t n_slots = 0;           // non-empty source bins
+  int32_t n_tgt_tiles = 0;       // tiles holding targets
   // device buffers
-  int32_t *src_cell = nullptr;
   void *src_frac = nullptr;
   double *src_w = nullptr;
   int32_t *src_perm = nullptr;
-  int32_t *bin_start = nullptr;
+  int4 *bin_runs = nullptr;
+  int4 *runs = nullptr;
+  int32_t *slot_of_tile = nullptr;
+  void *scratch = nullptr;
   void *q = nullptr;
   int32_t *tgt_cell = nullptr;
   void *tgt_frac = nullptr;
   int32_t *tgt_perm = nullptr;
+  int32_t *tgt_tile_start = nullptr;
+  int32_t *tgt_active = nullptr;
   void *grid_a = nullptr;
   void *S1 = nullptr;
   void *S2 = nullptr;
@@ -195,7 +201,6 @@ int upload_tables(slp_geom *G, const std::vector<double> &ts, const std::vector<
                   std::vector<int32_t> &cellbuf_t, std::vector<T> &fracbuf_t) {
   split_coords<T>(ts, sorder, G->lo, G->n_src, cellbuf_s, fracbuf_s);
   split_coords<T>(tt, torder, G->lo, G->n_nodes, cellbuf_t, fracbuf_t);
-  HIP_TRY(hipMemcpyAsync(G->src_cell, cellbuf_s.data(), cellbuf_s.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->src_frac, fracbuf_s.data(), fracbuf_s.size() * sizeof(T), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_cell, cellbuf_t.data(), cellbuf_t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_frac, fracbuf_t.data(), fracbuf_t.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -225,16 +230,21 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
   if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
   // spread
   {
-    slp::SpreadArgs<T> a{};
-    a.cell = G->src_cell;
+    slp::SpreadBinsArgs<T> a{};
     a.frac = static_cast<const T *>(G->src_frac);
     a.q = static_cast<const T *>(G->q);
-    a.bin_start = G->bin_start;
-    a.grid = static_cast<T *>(G->grid_a);
-    for (int i = 0; i < 3; ++i) a.tiles[i] = G->tiles[i];
+    a.bin_runs = G->bin_runs;
+    a.runs = G->runs;
+    a.scratch = static_cast<T *>(G->scratch);
     a.ns = G->n_src;
     a.inv_b = (T)(1.0 / G->b);
-    HIP_TRY(slp::launch_spread<T>(a, G->m, st));
+    a.step_ratio = (T)std::exp(-2.0 / G->b);
+    slp::SpreadReduceArgs<T> r{};
+    r.scratch = static_cast<const T *>(G->scratch);
+    r.slot_of_tile = G->slot_of_tile;
+    r.grid = static_cast<T *>(G->grid_a);
+    for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
+    HIP_TRY(slp::launch_spread<T>(a, r, G->n_slots, G->m, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
   const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
@@ -305,12 +315,17 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     a.cell = G->tgt_cell;
     a.frac = static_cast<const T *>(G->tgt_frac);
     a.perm = G->tgt_perm;
+    a.tile_start = G->tgt_tile_start;
+    a.active = G->tgt_active;
     a.g = static_cast<const T *>(G->grid_g);
     a.phi = phi;
-    for (int i = 0; i < 3; ++i) a.R[i] = G->R[i];
+    for (int i = 0; i < 3; ++i) {
+      a.R[i] = G->R[i];
+      a.tiles[i] = G->tiles[i];
+    }
     a.nt = G->n_nodes;
     a.inv_b = (T)(1.0 / G->b);
-    HIP_TRY(slp::launch_interp<T>(a, G->m, st));
+    HIP_TRY(slp::launch_interp<T>(a, G->n_tgt_tiles, G->m, st));
   }
   if (tm) {
     HIP_TRY(hipEventRecord(G->evs()[8], st));
@@ -500,20 +515,60 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, con
   if (om.empty()) return fail(SLP_EINVAL, "no exponential-sum term is resolved by the grid");
   G->terms_kept = (int32_t)om.size();
 
-  // binning of sources and targets by 8^3 tiles of the region
+  // binning: sources by (tile, cell in tile), targets by tile
   const int64_t ntiles = (int64_t)G->tiles[0] * G->tiles[1] * G->tiles[2];
-  auto tile_of = [&](const double *t) {
-    int32_t id[3];
-    for (int q = 0; q < 3; ++q) id[q] = ((int32_t)std::floor(t[q]) - G->lo[q]) / kTile;
-    return id[0] + G->tiles[0] * (id[1] + G->tiles[1] * id[2]);
+  auto cell_key = [&](const double *t, int32_t *tile, int32_t *incell) {
+    int32_t id[3], in[3];
+    for (int q = 0; q < 3; ++q) {
+      const int32_t c = (int32_t)std::floor(t[q]) - G->lo[q];
+      id[q] = c / kTile;
+      in[q] = c % kTile;
+    }
+    *tile = id[0] + G->tiles[0] * (id[1] + G->tiles[1] * id[2]);
+    *incell = in[0] | (in[1] << 4) | (in[2] << 8);
   };
-  std::vector<int32_t> sbin(Ms), tbin(n_nodes), sorder, sstart, torder, tstart;
-  for (int64_t k = 0; k < Ms; ++k) sbin[k] = tile_of(&ts[3 * k]);
-  for (int64_t i = 0; i < n_nodes; ++i) tbin[i] = tile_of(&tt[3 * i]);
-  counting_sort(sbin, ntiles, sorder, sstart);
+  std::vector<int32_t> skey(Ms), sincell(Ms), tbin(n_nodes), sorder, sstart, torder, tstart;
+  for (int64_t k = 0; k < Ms; ++k) {
+    int32_t tile, inc;
+    cell_key(&ts[3 * k], &tile, &inc);
+    sincell[k] = inc;
+    skey[k] = tile * 512 + ((inc & 7) + 8 * ((inc >> 4) & 7) + 64 * (inc >> 8));
+  }
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    int32_t tile, inc;
+    cell_key(&tt[3 * i], &tile, &inc);
+    tbin[i] = tile;
+  }
+  counting_sort(skey, ntiles * 512, sorder, sstart);
   counting_sort(tbin, ntiles, torder, tstart);
   std::vector<double> wsorted(Ms);
   for (int64_t i = 0; i < Ms; ++i) wsorted[i] = wsrc[sorder[i]];
+
+  // bins -> runs of sources sharing one grid cell
+  std::vector<int32_t> slot_of_tile(ntiles, -1);
+  std::vector<int4> bin_runs, runs;
+  {
+    int64_t i = 0;
+    while (i < Ms) {
+      const int32_t tile = skey[sorder[i]] / 512;
+      slot_of_tile[tile] = (int32_t)bin_runs.size();
+      int4 br = {(int)runs.size(), 0, tile, 0};
+      while (i < Ms && skey[sorder[i]] / 512 == tile) {
+        const int32_t key = skey[sorder[i]];
+        int64_t e = i;
+        while (e < Ms && skey[sorder[e]] == key) ++e;
+        runs.push_back({sincell[sorder[i]], (int)i, (int)(e - i), 0});
+        i = e;
+      }
+      br.y = (int)runs.size();
+      bin_runs.push_back(br);
+    }
+  }
+  G->n_slots = (int32_t)bin_runs.size();
+  std::vector<int32_t> tgt_active;
+  for (int64_t t = 0; t < ntiles; ++t)
+    if (tstart[t + 1] > tstart[t]) tgt_active.push_back((int32_t)t);
+  G->n_tgt_tiles = (int32_t)tgt_active.size();
 
   // device allocations
   const size_t e = G->esz();
@@ -524,11 +579,15 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, con
   const int64_t mun = (int64_t)G->K[0] * G->K[1] * G->K[2];
   void *tmp = nullptr;
   bool ok = true;
-  ok &= G->alloc(&tmp, 3 * Ms * 4) == hipSuccess; G->src_cell = (int32_t *)tmp;
-  ok &= ok && G->alloc(&G->src_frac, 3 * Ms * e) == hipSuccess;
+  ok &= G->alloc(&G->src_frac, 3 * Ms * e) == hipSuccess;
   ok &= ok && G->alloc(&tmp, Ms * 8) == hipSuccess; G->src_w = (double *)tmp;
   ok &= ok && G->alloc(&tmp, Ms * 4) == hipSuccess; G->src_perm = (int32_t *)tmp;
-  ok &= ok && G->alloc(&tmp, (ntiles + 1) * 4) == hipSuccess; G->bin_start = (int32_t *)tmp;
+  ok &= ok && G->alloc(&tmp, bin_runs.size() * sizeof(int4)) == hipSuccess; G->bin_runs = (int4 *)tmp;
+  ok &= ok && G->alloc(&tmp, runs.size() * sizeof(int4)) == hipSuccess; G->runs = (int4 *)tmp;
+  ok &= ok && G->alloc(&tmp, ntiles * 4) == hipSuccess; G->slot_of_tile = (int32_t *)tmp;
+  ok &= ok && G->alloc(&G->scratch, (size_t)G->n_slots * slp::pad_cells(G->m) * e) == hipSuccess;
+  ok &= ok && G->alloc(&tmp, (ntiles + 1) * 4) == hipSuccess; G->tgt_tile_start = (int32_t *)tmp;
+  ok &= ok && G->alloc(&tmp, tgt_active.size() * 4) == hipSuccess; G->tgt_active = (int32_t *)tmp;
   ok &= ok && G->alloc(&G->q, Ms * e) == hipSuccess;
   ok &= ok && G->alloc(&tmp, 3 * n_nodes * 4) == hipSuccess; G->tgt_cell = (int32_t *)tmp;
   ok &= ok && G->alloc(&G->tgt_frac, 3 * n_nodes * e) == hipSuccess;
@@ -543,7 +602,11 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, con
 
   HIP_TRY(hipMemcpyAsync(G->src_w, wsorted.data(), Ms * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->src_perm, sorder.data(), Ms * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->bin_start, sstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->bin_runs, bin_runs.data(), bin_runs.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->slot_of_tile, slot_of_tile.data(), ntiles * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_nodes * 4, hipMemcpyHostToDevice, st));
   std::vector<int32_t> cs, ct;
   std::vector<double> fs64, ft64;

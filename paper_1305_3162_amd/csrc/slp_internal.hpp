@@ -9,30 +9,45 @@
 namespace slp {
 
 constexpr int kTile = 8;      // grid tile edge used by spread and interpolation bins
-constexpr int kMaxM = 10;     // largest supported window cut-off
+constexpr int kMaxM = 8;      // largest supported window cut-off
 
-// Gridding (type-1 spread) of binned sources onto the tiled region.
+// Gridding (type-1 spread). Sources are sorted by (tile, cell in tile); every
+// non-empty tile ("bin") owns a padded accumulation block of (8 + 2m - 1)^3
+// cells in `scratch` (slot order). A run is a maximal sequence of sources that
+// share one grid cell.
 template <typename T>
-struct SpreadArgs {
-  const int32_t *cell;   // [3][ns] local cell index floor(t) - lo, sorted by tile
-  const T *frac;         // [3][ns] t - floor(t) in [0, 1)
-  const T *q;            // [ns] charges in sorted order
-  const int32_t *bin_start;  // [tiles + 1] source ranges per tile
-  T *grid;               // [P_z][P_y][P_x] output, P = 8 * tiles
-  int32_t tiles[3];
+struct SpreadBinsArgs {
+  const T *frac;         // [3][ns] t - floor(t), sorted order
+  const T *q;            // [ns] charges, sorted order
+  const int4 *bin_runs;      // [n_slots] {first run, end run, tile id, 0}
+  const int4 *runs;          // {cell in tile x | y << 4 | z << 8, first source, count, 0}
+  T *scratch;            // [n_slots][PD^3]
   int64_t ns;
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
+  T step_ratio;          // exp(-2 / b): ratio of consecutive weight ratios
+};
+
+// Sum of the padded blocks of the neighbouring bins into the region grid.
+template <typename T>
+struct SpreadReduceArgs {
+  const T *scratch;
+  const int32_t *slot_of_tile;   // [tiles] slot or -1
+  T *grid;                       // [P_z][P_y][P_x]
+  int32_t tiles[3];
 };
 
 // Interpolation (type-2 gather) at the tile-sorted targets.
 template <typename T>
 struct InterpArgs {
-  const int32_t *cell;   // [3][nt]
+  const int32_t *cell;   // [3][nt] local cell, sorted by tile
   const T *frac;         // [3][nt]
   const int32_t *perm;   // [nt] sorted -> caller index
+  const int32_t *tile_start;  // [tiles + 1]
+  const int32_t *active;      // [n_active] tiles holding targets
   const T *g;            // [R_z][R_y][R_x] grid after the inverse FFT
   double *phi;           // [nt] output, caller order
   int32_t R[3];
+  int32_t tiles[3];
   int64_t nt;
   T inv_b;
 };
@@ -65,9 +80,12 @@ template <typename T>
 hipError_t launch_charges(const double *dens, const double *w, const int32_t *perm, T *q,
                           int64_t ns, hipStream_t s);
 template <typename T>
-hipError_t launch_spread(const SpreadArgs<T> &a, int m, hipStream_t s);
+hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
+                         int m, hipStream_t s);
 template <typename T>
-hipError_t launch_interp(const InterpArgs<T> &a, int m, hipStream_t s);
+hipError_t launch_interp(const InterpArgs<T> &a, int n_active, int m, hipStream_t s);
+// Cells of the padded accumulation block of one bin: (8 + 2m - 1)^3.
+int64_t pad_cells(int m);
 template <typename T>
 hipError_t launch_fft(const FftPass<T> &p, int N, hipStream_t s);
 

@@ -41,154 +41,273 @@ hipError_t launch_charges(const double *dens, const double *w, const int32_t *pe
 }
 
 // ----------------------------------------------------------------- spread ---
-// One 64-lane workgroup owns one 8x8x8 output tile: lane (x, y) keeps the 8
-// z-cells of its column in registers. Sources whose stencil can reach the tile
-// are read from the neighbouring bins; per source the lanes first build the
-// tile-restricted 1-D window factors in LDS, then every lane accumulates
-// q wx(x) wy(y) wz(z). Each output cell is written once, without atomics.
-template <typename T, int M>
-__global__ __launch_bounds__(64) void k_spread(SpreadArgs<T> a) {
-  constexpr int TL = kTile;
-  constexpr int RLO = (M + TL - 1) / TL;       // bins below that can reach the tile
-  constexpr int RHI = (TL + M - 2) / TL;       // bins above
-  __shared__ T W[64][3 * TL + 1];
+// Phase A (one workgroup of 8 waves per non-empty bin): the bin's sources are
+// scattered into an LDS block covering the bin plus the stencil halo,
+// (8 + 2m - 1)^3 cells. Each wave independently takes every 8th run of sources
+// that share one grid cell; its lanes cover the 2m x 2m (dx, dy) columns of the
+// stencil in ceil(4m^2 / 64) passes and keep the 2m z-values of each column in
+// registers over the whole run, adding them to the LDS block once per run. The
+// 1-D Gaussian factors of up to 16 sources at a time are built in a
+// wave-private LDS slice with the fast-Gaussian-gridding recurrence
+// w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b): two exponentials per source and
+// axis.
+// Phase B (one workgroup per region tile): every cell sums the blocks of the
+// neighbouring bins that cover it, in a fixed order, and writes the grid.
+template <int M>
+struct SpreadShape {
+  static constexpr int W = 2 * M;
+  static constexpr int PD = kTile + W - 1;
+  static constexpr int P3 = PD * PD * PD;
+  static constexpr int COLS = W * W;
+  static constexpr int NP = (COLS + 63) / 64;          // column passes per wave
+  static constexpr int WAVES = 8;
+  static constexpr int SBW = 16;                       // sources per wave chunk
+  static constexpr int WST = 3 * W + 1;                // LDS stride of one source's factors
+};
 
+int64_t pad_cells(int m) {
+  const int64_t pd = kTile + 2 * m - 1;
+  return pd * pd * pd;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(SpreadShape<M>::WAVES * 64) void k_spread_bins(SpreadBinsArgs<T> a) {
+  using S = SpreadShape<M>;
+  constexpr int W = S::W, PD = S::PD, NP = S::NP;
+  __shared__ T pad[S::P3];
+  __shared__ T wts[S::WAVES * S::SBW * S::WST];
+
+  const int slot = blockIdx.x;
+  const int4 br = a.bin_runs[slot];
+  for (int i = threadIdx.x; i < S::P3; i += blockDim.x) pad[i] = T(0);
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  T *ww = wts + wave * S::SBW * S::WST;
+  int dxp[NP], dyp[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int col = lane + 64 * p;
+    dxp[p] = col % W;
+    dyp[p] = col / W;
+  }
+  const bool last_act = (lane + 64 * (NP - 1)) < S::COLS;
+  const int64_t ns = a.ns;
+
+  for (int r = br.x + wave; r < br.y; r += S::WAVES) {
+    const int4 run = a.runs[r];
+    const int cx = run.x & 15, cy = (run.x >> 4) & 15, cz = run.x >> 8;
+    T acc[NP][W];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int j = 0; j < W; ++j) acc[p][j] = T(0);
+    for (int c0 = 0; c0 < run.z; c0 += S::SBW) {
+      const int n = min(S::SBW, run.z - c0);
+      for (int task = lane; task < 3 * n; task += 64) {
+        const int sl = task % n, ax = task / n;
+        const int64_t src = (int64_t)run.y + c0 + sl;
+        const T f = a.frac[ax * ns + src] + T(M - 1);
+        T w = wexp(-f * f * a.inv_b);
+        T rr = wexp((T(2) * f - T(1)) * a.inv_b);
+        if (ax == 0) w *= a.q[src];
+        T *dst = ww + sl * S::WST + ax * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          dst[j] = w;
+          w *= rr;
+          rr *= a.step_ratio;
+        }
+      }
+      wave_sync();
+      for (int sl = 0; sl < n; ++sl) {
+        const T *f3 = ww + sl * S::WST;
+        T wz[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          if (p == NP - 1 && !last_act) continue;
+          const T pw = f3[dxp[p]] * f3[W + dyp[p]];
+#pragma unroll
+          for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
+        }
+      }
+      wave_sync();
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (p == NP - 1 && !last_act) continue;
+      T *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+#pragma unroll
+      for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, acc[p][j]);
+    }
+  }
+  __syncthreads();
+  T *dst = a.scratch + (int64_t)slot * S::P3;
+  for (int i = threadIdx.x; i < S::P3; i += blockDim.x) dst[i] = pad[i];
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
+  using S = SpreadShape<M>;
+  constexpr int PD = S::PD;
   const int tile = blockIdx.x;
   const int tx = tile % a.tiles[0];
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
-  const int X0 = tx * TL, Y0 = ty * TL, Z0 = tz * TL;
-  const int lane = threadIdx.x;
-  const int x = lane & 7, y = lane >> 3;
-  const int64_t ns = a.ns;
-
-  T acc[TL];
-#pragma unroll
-  for (int z = 0; z < TL; ++z) acc[z] = T(0);
-
-  for (int dz = -RLO; dz <= RHI; ++dz) {
-    const int bz = tz + dz;
-    if (bz < 0 || bz >= a.tiles[2]) continue;
-    for (int dy = -RLO; dy <= RHI; ++dy) {
-      const int by = ty + dy;
-      if (by < 0 || by >= a.tiles[1]) continue;
-      for (int dx = -RLO; dx <= RHI; ++dx) {
-        const int bx = tx + dx;
-        if (bx < 0 || bx >= a.tiles[0]) continue;
-        const int bin = bx + a.tiles[0] * (by + a.tiles[1] * bz);
-        const int s0 = a.bin_start[bin], s1 = a.bin_start[bin + 1];
-        for (int c = s0; c < s1; c += 64) {
-          const int s = c + lane;
-          if (s < s1) {
-            const int cx = a.cell[s], cy = a.cell[ns + s], cz = a.cell[2 * ns + s];
-            const T fx = a.frac[s], fy = a.frac[ns + s], fz = a.frac[2 * ns + s];
-            const T qv = a.q[s];
-#pragma unroll
-            for (int j = 0; j < TL; ++j) {
-              const int kx = X0 + j - cx, ky = Y0 + j - cy, kz = Z0 + j - cz;
-              const T ddx = fx - (T)kx, ddy = fy - (T)ky, ddz = fz - (T)kz;
-              W[lane][j] = (kx > -M && kx <= M) ? qv * wexp(-ddx * ddx * a.inv_b) : T(0);
-              W[lane][TL + j] = (ky > -M && ky <= M) ? wexp(-ddy * ddy * a.inv_b) : T(0);
-              W[lane][2 * TL + j] = (kz > -M && kz <= M) ? wexp(-ddz * ddz * a.inv_b) : T(0);
-            }
-          }
-          __syncthreads();
-          const int cnt = min(64, s1 - c);
-          for (int si = 0; si < cnt; ++si) {
-            const T p = W[si][x] * W[si][TL + y];
-#pragma unroll
-            for (int z = 0; z < TL; ++z) acc[z] += p * W[si][2 * TL + z];
-          }
-          __syncthreads();
+  const int64_t Px = (int64_t)a.tiles[0] * kTile, Py = (int64_t)a.tiles[1] * kTile;
+  for (int c = threadIdx.x; c < kTile * kTile * kTile; c += blockDim.x) {
+    const int gx = tx * kTile + (c & 7), gy = ty * kTile + ((c >> 3) & 7), gz = tz * kTile + (c >> 6);
+    T v = T(0);
+    for (int bz = tz - 1; bz <= tz + 1; ++bz) {
+      const int iz = gz - (bz * kTile - M + 1);
+      if (bz < 0 || bz >= a.tiles[2] || iz < 0 || iz >= PD) continue;
+      for (int by = ty - 1; by <= ty + 1; ++by) {
+        const int iy = gy - (by * kTile - M + 1);
+        if (by < 0 || by >= a.tiles[1] || iy < 0 || iy >= PD) continue;
+        for (int bx = tx - 1; bx <= tx + 1; ++bx) {
+          const int ix = gx - (bx * kTile - M + 1);
+          if (bx < 0 || bx >= a.tiles[0] || ix < 0 || ix >= PD) continue;
+          const int slot = a.slot_of_tile[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
+          if (slot < 0) continue;
+          v += a.scratch[(int64_t)slot * S::P3 + (iz * PD + iy) * PD + ix];
         }
       }
     }
+    a.grid[(gz * Py + gy) * Px + gx] = v;
   }
-  const int64_t Px = (int64_t)a.tiles[0] * TL, Py = (int64_t)a.tiles[1] * TL;
-#pragma unroll
-  for (int z = 0; z < TL; ++z)
-    a.grid[((int64_t)(Z0 + z) * Py + (Y0 + y)) * Px + (X0 + x)] = acc[z];
 }
 
 template <typename T, int M>
-static hipError_t spread_m(const SpreadArgs<T> &a, hipStream_t s) {
-  const int64_t tiles = (int64_t)a.tiles[0] * a.tiles[1] * a.tiles[2];
-  hipLaunchKernelGGL((k_spread<T, M>), dim3((unsigned)tiles), dim3(64), 0, s, a);
+static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
+                           hipStream_t s) {
+  using S = SpreadShape<M>;
+  if (n_slots > 0)
+    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots), dim3(S::WAVES * 64), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
+  hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_spread(const SpreadArgs<T> &a, int m, hipStream_t s) {
+hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
+                         int m, hipStream_t s) {
   switch (m) {
-    case 1: return spread_m<T, 1>(a, s);
-    case 2: return spread_m<T, 2>(a, s);
-    case 3: return spread_m<T, 3>(a, s);
-    case 4: return spread_m<T, 4>(a, s);
-    case 5: return spread_m<T, 5>(a, s);
-    case 6: return spread_m<T, 6>(a, s);
-    case 7: return spread_m<T, 7>(a, s);
-    case 8: return spread_m<T, 8>(a, s);
-    case 9: return spread_m<T, 9>(a, s);
-    case 10: return spread_m<T, 10>(a, s);
+    case 1: return spread_m<T, 1>(a, r, n_slots, s);
+    case 2: return spread_m<T, 2>(a, r, n_slots, s);
+    case 3: return spread_m<T, 3>(a, r, n_slots, s);
+    case 4: return spread_m<T, 4>(a, r, n_slots, s);
+    case 5: return spread_m<T, 5>(a, r, n_slots, s);
+    case 6: return spread_m<T, 6>(a, r, n_slots, s);
+    case 7: return spread_m<T, 7>(a, r, n_slots, s);
+    case 8: return spread_m<T, 8>(a, r, n_slots, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // ----------------------------------------------------------------- interp ---
-// One thread per target: the 2m x 2m x 2m stencil gather with separable
-// Gaussian factors. Rows along x are summed in T, the row contributions are
-// accumulated in FP64 (the per-node sum), result written in caller order.
+// One workgroup per tile holding targets: the grid values of the tile plus the
+// stencil halo are staged in LDS, the 1-D factors of a batch of 64 targets are
+// computed, then each wave takes one target at a time: its lanes cover the
+// (dy, dz) rows of the stencil, sum the 2m values of each row in T and
+// accumulate row * wy * wz in FP64; a wave reduction gives the node value.
+template <int M>
+struct InterpShape {
+  static constexpr int W = 2 * M;
+  static constexpr int PD = kTile + W - 1;
+  static constexpr int P3 = PD * PD * PD;
+  static constexpr int WAVES = 16;
+  static constexpr int TB = 64;       // targets per batch
+};
+
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_interp(InterpArgs<T> a) {
-  constexpr int W2 = 2 * M;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.nt) return;
-  const int64_t nt = a.nt;
-  const int cx = a.cell[i], cy = a.cell[nt + i], cz = a.cell[2 * nt + i];
-  const T fx = a.frac[i], fy = a.frac[nt + i], fz = a.frac[2 * nt + i];
-  T wx[W2], wy[W2], wz[W2];
-#pragma unroll
-  for (int j = 0; j < W2; ++j) {
-    const T k = (T)(j - M + 1);
-    wx[j] = wexp(-(fx - k) * (fx - k) * a.inv_b);
-    wy[j] = wexp(-(fy - k) * (fy - k) * a.inv_b);
-    wz[j] = wexp(-(fz - k) * (fz - k) * a.inv_b);
-  }
+__global__ __launch_bounds__(InterpShape<M>::WAVES * 64) void k_interp(InterpArgs<T> a) {
+  using S = InterpShape<M>;
+  constexpr int W = S::W, PD = S::PD;
+  __shared__ T gt[S::P3];
+  __shared__ T wts[S::TB][3][W];
+
+  const int tile = a.active[blockIdx.x];
+  const int tx = tile % a.tiles[0];
+  const int ty = (tile / a.tiles[0]) % a.tiles[1];
+  const int tz = tile / (a.tiles[0] * a.tiles[1]);
+  const int ox = tx * kTile - M + 1, oy = ty * kTile - M + 1, oz = tz * kTile - M + 1;
   const int64_t Rx = a.R[0], Ry = a.R[1];
-  double acc = 0.0;
-  for (int jz = 0; jz < W2; ++jz) {
-    for (int jy = 0; jy < W2; ++jy) {
-      const T *row = a.g + ((int64_t)(cz + jz - M + 1) * Ry + (cy + jy - M + 1)) * Rx + (cx - M + 1);
-      T r = T(0);
+  for (int i = threadIdx.x; i < S::P3; i += blockDim.x) {
+    const int ix = i % PD, iy = (i / PD) % PD, iz = i / (PD * PD);
+    const int gx = ox + ix, gy = oy + iy, gz = oz + iz;
+    T v = T(0);
+    if (gx >= 0 && gx < a.R[0] && gy >= 0 && gy < a.R[1] && gz >= 0 && gz < a.R[2])
+      v = a.g[((int64_t)gz * Ry + gy) * Rx + gx];
+    gt[i] = v;
+  }
+  const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nt = a.nt;
+  for (int b0 = t0; b0 < t1; b0 += S::TB) {
+    const int nb = min(S::TB, t1 - b0);
+    __syncthreads();   // grid tile loaded / previous batch finished with wts
+    for (int task = threadIdx.x; task < 3 * nb * W; task += blockDim.x) {
+      const int j = task % W, s = (task / W) % nb, ax = task / (W * nb);
+      const T k = T(j - M + 1);
+      const T d = a.frac[ax * nt + b0 + s] - k;
+      wts[s][ax][j] = wexp(-d * d * a.inv_b);
+    }
+    __syncthreads();
+    for (int s = wave; s < nb; s += S::WAVES) {
+      const int i = b0 + s;
+      const int cx = a.cell[i] - tx * kTile, cy = a.cell[nt + i] - ty * kTile,
+                cz = a.cell[2 * nt + i] - tz * kTile;
+      T wx[W];
 #pragma unroll
-      for (int jx = 0; jx < W2; ++jx) r += row[jx] * wx[jx];
-      acc += (double)(r * (wy[jy] * wz[jz]));
+      for (int j = 0; j < W; ++j) wx[j] = wts[s][0][j];
+      double acc = 0.0;
+      for (int r = lane; r < W * W; r += 64) {
+        const int dy = r % W, dz = r / W;
+        const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int j = 0; j < W; j += 2) {
+          s0 += row[j] * wx[j];
+          s1 += row[j + 1] * wx[j + 1];
+        }
+        acc += (double)((s0 + s1) * (wts[s][1][dy] * wts[s][2][dz]));
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+      if (lane == 0) a.phi[a.perm[i]] = acc;
     }
   }
-  a.phi[a.perm[i]] = acc;
 }
 
 template <typename T, int M>
-static hipError_t interp_m(const InterpArgs<T> &a, hipStream_t s) {
-  if (a.nt == 0) return hipSuccess;
-  const int64_t blocks = (a.nt + 255) / 256;
-  hipLaunchKernelGGL((k_interp<T, M>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+static hipError_t interp_m(const InterpArgs<T> &a, int n_active, hipStream_t s) {
+  if (n_active == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_interp<T, M>), dim3((unsigned)n_active), dim3(InterpShape<M>::WAVES * 64),
+                     0, s, a);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_interp(const InterpArgs<T> &a, int m, hipStream_t s) {
+hipError_t launch_interp(const InterpArgs<T> &a, int n_active, int m, hipStream_t s) {
   switch (m) {
-    case 1: return interp_m<T, 1>(a, s);
-    case 2: return interp_m<T, 2>(a, s);
-    case 3: return interp_m<T, 3>(a, s);
-    case 4: return interp_m<T, 4>(a, s);
-    case 5: return interp_m<T, 5>(a, s);
-    case 6: return interp_m<T, 6>(a, s);
-    case 7: return interp_m<T, 7>(a, s);
-    case 8: return interp_m<T, 8>(a, s);
-    case 9: return interp_m<T, 9>(a, s);
-    case 10: return interp_m<T, 10>(a, s);
+    case 1: return interp_m<T, 1>(a, n_active, s);
+    case 2: return interp_m<T, 2>(a, n_active, s);
+    case 3: return interp_m<T, 3>(a, n_active, s);
+    case 4: return interp_m<T, 4>(a, n_active, s);
+    case 5: return interp_m<T, 5>(a, n_active, s);
+    case 6: return interp_m<T, 6>(a, n_active, s);
+    case 7: return interp_m<T, 7>(a, n_active, s);
+    case 8: return interp_m<T, 8>(a, n_active, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -271,33 +390,61 @@ __device__ __forceinline__ int wrap_pos(int e, int shift, int N) {
   return p < 0 ? p + N : p;
 }
 
+// A workgroup of 128 threads transforms B = 512 / N lines (at least one) held
+// in LDS: 16 KiB (FP64) per workgroup, so many workgroups share a CU and
+// hide the global-memory latency of the pruned loads and stores.
+constexpr int kFftThreads = 128;
+constexpr int kFftElems = 512;
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_fft(FftPass<T> p, int B) {
+__global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
   using C = typename Cplx<T>::type;
-  extern __shared__ unsigned char smem_raw[];
-  C *buf0 = reinterpret_cast<C *>(smem_raw);
-  C *buf1 = buf0 + (size_t)B * N;
+  constexpr int B = (kFftElems / N) > 0 ? (kFftElems / N) : 1;
+  constexpr int PER = (B * N + kFftThreads - 1) / kFftThreads;   // elements per thread
+  __shared__ C buf0[B * N];
+  __shared__ C buf1[B * N];
   const C *tw = reinterpret_cast<const C *>(p.tw);
   const int64_t L0 = (int64_t)blockIdx.x * B;
   const int nb = (int)min((int64_t)B, p.n_lines - L0);
+  const int tid = threadIdx.x;
 
-  for (int j = threadIdx.x; j < B * N; j += blockDim.x) { buf0[j].x = T(0); buf0[j].y = T(0); }
-  __syncthreads();
-
-  // load (coalesced along e when the element stride is 1, along lines otherwise)
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int j = tid + k * kFftThreads;
+    if (j < B * N) { buf0[j].x = T(0); buf0[j].y = T(0); }
+  }
+  // issue every global load of the thread before touching LDS
   const int total_in = nb * p.in_cnt;
-  for (int idx = threadIdx.x; idx < total_in; idx += blockDim.x) {
-    int b, e;
-    if (p.in_es == 1) { e = idx % p.in_cnt; b = idx / p.in_cnt; }
-    else { b = idx % nb; e = idx / nb; }
-    const int64_t L = L0 + b;
-    const int64_t off = (L % p.l1) * p.in_s1 + (L / p.l1) * p.in_s2 + (int64_t)e * p.in_es;
-    C v;
-    if (p.in_real) { v.x = reinterpret_cast<const T *>(p.in)[off]; v.y = T(0); }
-    else { v = reinterpret_cast<const C *>(p.in)[off]; }
-    const int pos = wrap_pos(e, p.in_shift, N);
-    buf0[b * N + pos] = v;
-    if (p.in_hermitian && e > 0) { C c = v; c.y = -c.y; buf0[b * N + (N - pos)] = c; }
+  C v[PER];
+  int pos[PER], bl[PER], el[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = tid + k * kFftThreads;
+    bl[k] = -1;
+    if (idx < total_in) {
+      int b, e;
+      if (p.in_es == 1) { e = idx % p.in_cnt; b = idx / p.in_cnt; }
+      else { b = idx % nb; e = idx / nb; }
+      const int64_t L = L0 + b;
+      const int64_t off = (L % p.l1) * p.in_s1 + (L / p.l1) * p.in_s2 + (int64_t)e * p.in_es;
+      if (p.in_real) { v[k].x = reinterpret_cast<const T *>(p.in)[off]; v[k].y = T(0); }
+      else { v[k] = reinterpret_cast<const C *>(p.in)[off]; }
+      bl[k] = b;
+      el[k] = e;
+      pos[k] = wrap_pos(e, p.in_shift, N);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    if (bl[k] >= 0) {
+      buf0[bl[k] * N + pos[k]] = v[k];
+      if (p.in_hermitian && el[k] > 0) {
+        C c = v[k];
+        c.y = -c.y;
+        buf0[bl[k] * N + (N - pos[k])] = c;
+      }
+    }
   }
   __syncthreads();
 
@@ -305,18 +452,35 @@ __global__ __launch_bounds__(256) void k_fft(FftPass<T> p, int B) {
 
   if (p.mul_inv) {
     C *oth = (res == buf0) ? buf1 : buf0;
-    for (int j = threadIdx.x; j < B * N; j += blockDim.x) { oth[j].x = T(0); oth[j].y = T(0); }
-    __syncthreads();
     const int total_mu = nb * p.mu_cnt;
-    for (int idx = threadIdx.x; idx < total_mu; idx += blockDim.x) {
-      const int b = idx % nb, e = idx / nb;
-      const int64_t L = L0 + b;
-      const int64_t off = (L % p.l1) * p.in_s1 + (L / p.l1) * p.in_s2 + (int64_t)e * p.in_es;
-      const T mu = p.mu[off];
-      const int pos = wrap_pos(e, p.mu_shift, N);
-      C v = res[b * N + pos];
-      v.x *= mu; v.y *= mu;
-      oth[b * N + pos] = v;
+    T mu[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * kFftThreads;
+      mu[k] = T(0);
+      if (idx < total_mu) {
+        const int b = idx % nb, e = idx / nb;
+        const int64_t L = L0 + b;
+        mu[k] = p.mu[(L % p.l1) * p.in_s1 + (L / p.l1) * p.in_s2 + (int64_t)e * p.in_es];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int j = tid + k * kFftThreads;
+      if (j < B * N) { oth[j].x = T(0); oth[j].y = T(0); }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = tid + k * kFftThreads;
+      if (idx < total_mu) {
+        const int b = idx % nb, e = idx / nb;
+        const int ps = wrap_pos(e, p.mu_shift, N);
+        C x = res[b * N + ps];
+        x.x *= mu[k];
+        x.y *= mu[k];
+        oth[b * N + ps] = x;
+      }
     }
     __syncthreads();
     C *spare = (oth == buf0) ? buf1 : buf0;
@@ -324,27 +488,28 @@ __global__ __launch_bounds__(256) void k_fft(FftPass<T> p, int B) {
   }
 
   const int total_out = nb * p.out_cnt;
-  for (int idx = threadIdx.x; idx < total_out; idx += blockDim.x) {
-    int b, e;
-    if (p.out_es == 1) { e = idx % p.out_cnt; b = idx / p.out_cnt; }
-    else { b = idx % nb; e = idx / nb; }
-    const int64_t L = L0 + b;
-    const int64_t off = (L % p.l1) * p.out_s1 + (L / p.l1) * p.out_s2 + (int64_t)e * p.out_es;
-    const C v = res[b * N + wrap_pos(e, p.out_shift, N)];
-    if (p.out_real) reinterpret_cast<T *>(p.out)[off] = v.x;
-    else reinterpret_cast<C *>(p.out)[off] = v;
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = tid + k * kFftThreads;
+    if (idx < total_out) {
+      int b, e;
+      if (p.out_es == 1) { e = idx % p.out_cnt; b = idx / p.out_cnt; }
+      else { b = idx % nb; e = idx / nb; }
+      const int64_t L = L0 + b;
+      const int64_t off = (L % p.l1) * p.out_s1 + (L / p.l1) * p.out_s2 + (int64_t)e * p.out_es;
+      const C x = res[b * N + wrap_pos(e, p.out_shift, N)];
+      if (p.out_real) reinterpret_cast<T *>(p.out)[off] = x.x;
+      else reinterpret_cast<C *>(p.out)[off] = x;
+    }
   }
 }
 
 template <typename T, int N>
 static hipError_t fft_n(const FftPass<T> &p, hipStream_t s) {
-  using C = typename Cplx<T>::type;
-  constexpr int kElems = (sizeof(T) == 8) ? 2048 : 4096;   // 64 KiB of LDS per workgroup
-  constexpr int B = (kElems / N) > 0 ? (kElems / N) : 1;
+  constexpr int B = (kFftElems / N) > 0 ? (kFftElems / N) : 1;
   if (p.n_lines == 0) return hipSuccess;
   const int64_t blocks = (p.n_lines + B - 1) / B;
-  const size_t shmem = 2 * (size_t)B * N * sizeof(C);
-  hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)blocks), dim3(256), shmem, s, p, B);
+  hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)blocks), dim3(kFftThreads), 0, s, p);
   return hipGetLastError();
 }
 
@@ -451,10 +616,12 @@ template hipError_t launch_charges<float>(const double *, const double *, const 
                                           int64_t, hipStream_t);
 template hipError_t launch_charges<double>(const double *, const double *, const int32_t *,
                                            double *, int64_t, hipStream_t);
-template hipError_t launch_spread<float>(const SpreadArgs<float> &, int, hipStream_t);
-template hipError_t launch_spread<double>(const SpreadArgs<double> &, int, hipStream_t);
-template hipError_t launch_interp<float>(const InterpArgs<float> &, int, hipStream_t);
-template hipError_t launch_interp<double>(const InterpArgs<double> &, int, hipStream_t);
+template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
+                                         const SpreadReduceArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_spread<double>(const SpreadBinsArgs<double> &,
+                                          const SpreadReduceArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_interp<float>(const InterpArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_interp<double>(const InterpArgs<double> &, int, int, hipStream_t);
 template hipError_t launch_fft<float>(const FftPass<float> &, int, hipStream_t);
 template hipError_t launch_fft<double>(const FftPass<double> &, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,
