@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--workload", default="cube64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first copy this many MiB device-to-device (a kernel of known "
+                         "traffic, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -86,6 +89,14 @@ def main():
     import paper_1305_3162_amd as slp
     from synth.workloads import make_workload
 
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        src_c = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst_c = torch.empty_like(src_c)
+        for _ in range(3):
+            dst_c.copy_(src_c)
+        torch.cuda.synchronize()
+        del src_c, dst_c
     prec = slp.FP64 if args.precision == "fp64" else slp.FP32
     m = args.m if args.m is not None else (8 if prec == slp.FP64 else 5)
     wl = make_workload(args.workload, m)

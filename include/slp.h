@@ -102,6 +102,12 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes,
                        const int32_t *tris, int64_t n_tris, const slp_params *p,
                        void *stream);
 
+/* Device bytes slp_setup_geometry would hold for these arguments, computed on
+ * the host without touching a device (same validation and errors). Used for
+ * admission by memory. */
+int slp_geometry_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,
+                              int64_t n_tris, const slp_params *p, int64_t *bytes);
+
 /* Charges q_k = w_k g_k for the next evaluation (eq. naive_gridding).
  *   dens : device float64 [3 * n_tris], density at the quadrature points in
  *          long-index order k = j + s*M. Read by a kernel on `stream`. */
@@ -147,6 +153,49 @@ int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omeg
 
 int slp_geom_destroy(slp_geom *g);
 const char *slp_last_error(void);
+
+/* ---- Queued / served evaluation ----------------------------------------------
+ * A server owns a worker thread, n_slots HIP streams and a device-memory budget.
+ * Registered geometries are built on the device when first needed (setup phase
+ * of Alg. 1) and stay resident; when admitting one would exceed the budget, idle
+ * geometries are evicted, least recently used first, and rebuilt on their next
+ * request. Requests are admitted in arrival order as slots and memory free up,
+ * except that a request whose geometry is already running never blocks later
+ * requests for other geometries; it is chained onto that geometry's stream
+ * instead (continuous batching). A geometry larger than the whole budget fails
+ * its requests with SLP_ENOMEM. The server calls are thread-safe. */
+typedef struct slp_server slp_server;
+
+typedef struct {
+  double p50_s, p99_s, mean_s;  /* latency of completed requests, submit -> result ready */
+  double pts_per_s;             /* sum of (M_q + N) over completed requests / (last completion -
+                                   first submission) */
+  int64_t completed, failed, queued, in_flight;
+  int64_t resident_bytes, setups, evictions;
+} slp_server_stats;
+
+/* n_slots in [1, 64] streams; device_budget_bytes > 0 bounds the device memory
+ * held by resident geometries. Uses the calling thread's current device. */
+int slp_server_create(slp_server **out, size_t device_budget_bytes, int32_t n_slots);
+/* Register a geometry (host arrays copied; same meaning as slp_setup_geometry,
+ * p->es_w / p->es_gamma copied as well). *geom_id receives its id (>= 0). */
+int slp_server_add_geometry(slp_server *s, const double *nodes, int64_t n_nodes,
+                            const int32_t *tris, int64_t n_tris, const slp_params *p,
+                            int64_t *geom_id);
+/* Queue one solve: dens device float64 [3 * n_tris], phi device float64 [n_nodes]
+ * (caller owned; both must stay valid until the request is done).
+ * *ticket identifies the request. */
+int slp_server_submit(slp_server *s, int64_t geom_id, const double *dens, double *phi,
+                      uint64_t *ticket);
+/* *done = 1 once phi is written (status SLP_OK) or the request failed (its negative
+ * status is returned); 0 while queued or running. */
+int slp_server_poll(slp_server *s, uint64_t ticket, int32_t *done);
+/* Block until the request is done (SLP_OK), failed (its status) or timeout_s passed
+ * (SLP_ENOTREADY); timeout_s <= 0 waits without limit. */
+int slp_server_wait(slp_server *s, uint64_t ticket, double timeout_s);
+int slp_server_get_stats(slp_server *s, slp_server_stats *st, int32_t reset);
+/* Finishes every admitted request, then frees streams and resident geometries. */
+int slp_server_destroy(slp_server *s);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,8 @@ __all__ = [
     "SlpError", "load_library", "expsum_sinc", "setup_geometry", "set_density",
     "eval_single_layer", "eval_batched", "geom_get_info", "set_timing", "stage_times",
     "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "STAGES",
+    "geometry_device_bytes", "server_create", "server_add_geometry", "server_submit",
+    "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
 ]
 
 FP64, FP32 = 0, 1
@@ -47,6 +49,15 @@ class GeomInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("p50_s", ctypes.c_double), ("p99_s", ctypes.c_double),
+                ("mean_s", ctypes.c_double), ("pts_per_s", ctypes.c_double),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_int64), ("setups", ctypes.c_int64),
+                ("evictions", ctypes.c_int64)]
+
+
 _lib = None
 _VP = ctypes.c_void_p
 
@@ -74,6 +85,16 @@ def load_library():
         "slp_expsum_sinc": [ctypes.c_double] * 4 + [_VP, _VP, ctypes.c_int32,
                                                      ctypes.POINTER(ctypes.c_int32)],
         "slp_geom_destroy": [_VP],
+        "slp_geometry_device_bytes": [_VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                                      ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int64)],
+        "slp_server_create": [ctypes.POINTER(_VP), ctypes.c_size_t, ctypes.c_int32],
+        "slp_server_add_geometry": [_VP, _VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                                    ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int64)],
+        "slp_server_submit": [_VP, ctypes.c_int64, _VP, _VP, ctypes.POINTER(ctypes.c_uint64)],
+        "slp_server_poll": [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)],
+        "slp_server_wait": [_VP, ctypes.c_uint64, ctypes.c_double],
+        "slp_server_get_stats": [_VP, ctypes.POINTER(ServerStats), ctypes.c_int32],
+        "slp_server_destroy": [_VP],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -123,10 +144,7 @@ def expsum_sinc(h, r_lo, r_hi, tol):
     return w, g
 
 
-def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
-                   stream=None):
-    """slp_setup_geometry: returns an opaque handle (int)."""
-    lib = load_library()
+def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2):
     nodes = np.ascontiguousarray(nodes, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     if nodes.ndim != 2 or nodes.shape[1] != 3 or tris.ndim != 2 or tris.shape[1] != 3:
@@ -142,11 +160,83 @@ def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64
     p.es_gamma = es_gamma.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.es_terms = int(es_w.size)
     p.eta2 = float(eta2)
+    return nodes, tris, es_w, es_gamma, p     # arrays kept alive by the caller
+
+
+def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
+                   stream=None):
+    """slp_setup_geometry: returns an opaque handle (int)."""
+    lib = load_library()
+    nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
+                                              precision, eta2)
     h = _VP()
     _check(lib.slp_setup_geometry(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
                                   tris.ctypes.data, tris.shape[0], ctypes.byref(p),
                                   _stream_ptr(stream)))
     return h.value
+
+
+def geometry_device_bytes(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
+                          eta2=37.0):
+    """slp_geometry_device_bytes: device bytes a context would hold (host only)."""
+    lib = load_library()
+    nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
+                                              precision, eta2)
+    out = ctypes.c_int64(0)
+    _check(lib.slp_geometry_device_bytes(nodes.ctypes.data, nodes.shape[0], tris.ctypes.data,
+                                         tris.shape[0], ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def server_create(device_budget_bytes, n_slots):
+    h = _VP()
+    _check(load_library().slp_server_create(ctypes.byref(h), int(device_budget_bytes),
+                                            int(n_slots)))
+    return h.value
+
+
+def server_add_geometry(server, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
+                        eta2=37.0):
+    nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
+                                              precision, eta2)
+    gid = ctypes.c_int64(-1)
+    _check(load_library().slp_server_add_geometry(_VP(server), nodes.ctypes.data, nodes.shape[0],
+                                                  tris.ctypes.data, tris.shape[0],
+                                                  ctypes.byref(p), ctypes.byref(gid)))
+    return gid.value
+
+
+def server_submit(server, geom_id, dens, phi):
+    """dens / phi: CUDA float64 tensors (kept alive by the caller until done)."""
+    import torch
+    for name, t in (("dens", dens), ("phi", phi)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous CUDA float64 tensor")
+    tk = ctypes.c_uint64(0)
+    _check(load_library().slp_server_submit(_VP(server), int(geom_id), _VP(dens.data_ptr()),
+                                            _VP(phi.data_ptr()), ctypes.byref(tk)))
+    return tk.value
+
+
+def server_poll(server, ticket):
+    done = ctypes.c_int32(0)
+    _check(load_library().slp_server_poll(_VP(server), int(ticket), ctypes.byref(done)))
+    return bool(done.value)
+
+
+def server_wait(server, ticket, timeout_s=0.0):
+    _check(load_library().slp_server_wait(_VP(server), int(ticket), float(timeout_s)))
+
+
+def server_get_stats(server, reset=False):
+    st = ServerStats()
+    _check(load_library().slp_server_get_stats(_VP(server), ctypes.byref(st), int(bool(reset))))
+    return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+
+def server_destroy(server):
+    _check(load_library().slp_server_destroy(_VP(server)))
 
 
 def set_density(geom, dens, stream=None):
@@ -234,6 +324,41 @@ class Geometry:
     def close(self):
         if self.handle:
             geom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Owning wrapper around one slp_server (queued / served evaluation)."""
+
+    def __init__(self, device_budget_bytes, n_slots=4):
+        self.handle = server_create(device_budget_bytes, n_slots)
+
+    def add_geometry(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
+                     eta2=37.0):
+        return server_add_geometry(self.handle, nodes, tris, grid, m, es_w, es_gamma, alpha,
+                                   precision, eta2)
+
+    def submit(self, geom_id, dens, phi):
+        return server_submit(self.handle, geom_id, dens, phi)
+
+    def poll(self, ticket):
+        return server_poll(self.handle, ticket)
+
+    def wait(self, ticket, timeout_s=0.0):
+        server_wait(self.handle, ticket, timeout_s)
+
+    def stats(self, reset=False):
+        return server_get_stats(self.handle, reset)
+
+    def close(self):
+        if self.handle:
+            server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libslp.so")
 
-SOURCES = ["slp_kernels.hip", "slp_api.cpp"]
+SOURCES = ["slp_kernels.hip", "slp_api.cpp", "slp_server.cpp"]
 ARCH = os.environ.get("SLP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -45,7 +45,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -88,6 +88,8 @@ void counting_sort(const std::vector<int32_t> &bin, int64_t nbins, std::vector<i
 
 }  // namespace
 
+void slp::set_error_message(const char *msg) { g_err = msg; }
+
 struct slp_geom {
   int prec = SLP_FP64;
   int N[3]{}, n[3]{}, alpha = 2, m = 4;
@@ -102,8 +104,9 @@ struct slp_geom {
   void *src_frac = nullptr;
   double *src_w = nullptr;
   int32_t *src_perm = nullptr;
-  int4 *bin_runs = nullptr;
-  int4 *runs = nullptr;
+  int4 *bin_chunks = nullptr;
+  int4 *chunks = nullptr;
+  int32_t *runs = nullptr;
   int32_t *slot_of_tile = nullptr;
   void *scratch = nullptr;
   void *q = nullptr;
@@ -134,9 +137,10 @@ struct slp_geom {
 
   size_t esz() const { return prec == SLP_FP64 ? sizeof(double) : sizeof(float); }
 
+  static constexpr size_t kMinAlloc = 256;
   hipError_t alloc(void **p, size_t bytes_) {
     *p = nullptr;
-    if (bytes_ == 0) bytes_ = 256;
+    if (bytes_ < kMinAlloc) bytes_ = kMinAlloc;
     hipError_t e = hipMalloc(p, bytes_);
     if (e == hipSuccess) {
       allocs.push_back(*p);
@@ -233,7 +237,8 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     slp::SpreadBinsArgs<T> a{};
     a.frac = static_cast<const T *>(G->src_frac);
     a.q = static_cast<const T *>(G->q);
-    a.bin_runs = G->bin_runs;
+    a.bin_chunks = G->bin_chunks;
+    a.chunks = G->chunks;
     a.runs = G->runs;
     a.scratch = static_cast<T *>(G->scratch);
     a.ns = G->n_src;
@@ -399,10 +404,14 @@ int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omeg
   return SLP_OK;
 }
 
-int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, const int32_t *tris,
-                       int64_t n_tris, const slp_params *p, void *stream) {
-  if (!out) return fail(SLP_EINVAL, "out is NULL");
-  *out = nullptr;
+namespace {
+
+// Setup phase. With dry_bytes != NULL only the host part runs and the device
+// bytes the context would hold are returned (no device call is made).
+int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32_t *tris,
+               int64_t n_tris, const slp_params *p, void *stream, int64_t *dry_bytes) {
+  if (!out && !dry_bytes) return fail(SLP_EINVAL, "out is NULL");
+  if (out) *out = nullptr;
   int rc = validate_params(p);
   if (rc) return rc;
   if (!nodes || !tris || n_nodes < 3 || n_tris < 1)
@@ -544,27 +553,44 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, con
   std::vector<double> wsorted(Ms);
   for (int64_t i = 0; i < Ms; ++i) wsorted[i] = wsrc[sorder[i]];
 
-  // bins -> runs of sources sharing one grid cell
+  // bins -> chunks of <= kSpreadChunk sources -> runs of sources sharing one cell
   std::vector<int32_t> slot_of_tile(ntiles, -1);
-  std::vector<int4> bin_runs, runs;
+  std::vector<int4> bin_chunks, chunks;
+  std::vector<int32_t> runs;
   {
+    const int CH = slp::kSpreadChunk;
     int64_t i = 0;
     while (i < Ms) {
       const int32_t tile = skey[sorder[i]] / 512;
-      slot_of_tile[tile] = (int32_t)bin_runs.size();
-      int4 br = {(int)runs.size(), 0, tile, 0};
+      slot_of_tile[tile] = (int32_t)bin_chunks.size();
+      int4 bc = {(int)chunks.size(), 0, tile, 0};
+      int4 cur = {(int)i, 0, (int)runs.size(), 0};
       while (i < Ms && skey[sorder[i]] / 512 == tile) {
         const int32_t key = skey[sorder[i]];
         int64_t e = i;
         while (e < Ms && skey[sorder[e]] == key) ++e;
-        runs.push_back({sincell[sorder[i]], (int)i, (int)(e - i), 0});
+        const int32_t inc = sincell[sorder[i]];
+        const int32_t cell = (inc & 7) | (((inc >> 4) & 7) << 3) | ((inc >> 8) << 6);
+        int64_t pos = i;
+        while (pos < e) {
+          if (cur.y == CH) {
+            chunks.push_back(cur);
+            cur = {(int)pos, 0, (int)runs.size(), 0};
+          }
+          const int take = (int)std::min<int64_t>(e - pos, CH - cur.y);
+          runs.push_back(cell | (cur.y << 9) | (take << 19));
+          cur.y += take;
+          cur.w += 1;
+          pos += take;
+        }
         i = e;
       }
-      br.y = (int)runs.size();
-      bin_runs.push_back(br);
+      chunks.push_back(cur);
+      bc.y = (int)chunks.size();
+      bin_chunks.push_back(bc);
     }
   }
-  G->n_slots = (int32_t)bin_runs.size();
+  G->n_slots = (int32_t)bin_chunks.size();
   std::vector<int32_t> tgt_active;
   for (int64_t t = 0; t < ntiles; ++t)
     if (tstart[t + 1] > tstart[t]) tgt_active.push_back((int32_t)t);
@@ -577,33 +603,49 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, con
   const int64_t S2n = (int64_t)G->R[2] * G->K[1] * G->K[0];
   const int64_t gn = (int64_t)G->R[0] * G->R[1] * G->R[2];
   const int64_t mun = (int64_t)G->K[0] * G->K[1] * G->K[2];
-  void *tmp = nullptr;
+  struct AllocReq {
+    void **dst;
+    size_t bytes;
+  };
+  const AllocReq reqs[] = {
+      {&G->src_frac, (size_t)(3 * Ms) * e},
+      {reinterpret_cast<void **>(&G->src_w), (size_t)Ms * 8},
+      {reinterpret_cast<void **>(&G->src_perm), (size_t)Ms * 4},
+      {reinterpret_cast<void **>(&G->bin_chunks), bin_chunks.size() * sizeof(int4)},
+      {reinterpret_cast<void **>(&G->chunks), chunks.size() * sizeof(int4)},
+      {reinterpret_cast<void **>(&G->runs), runs.size() * sizeof(int32_t)},
+      {reinterpret_cast<void **>(&G->slot_of_tile), (size_t)ntiles * 4},
+      {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
+      {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
+      {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
+      {&G->q, (size_t)Ms * e},
+      {reinterpret_cast<void **>(&G->tgt_cell), (size_t)(3 * n_nodes) * 4},
+      {&G->tgt_frac, (size_t)(3 * n_nodes) * e},
+      {reinterpret_cast<void **>(&G->tgt_perm), (size_t)n_nodes * 4},
+      {&G->grid_a, (size_t)Gsz * e},
+      {&G->S1, (size_t)S1n * 2 * e},
+      {&G->S2, (size_t)S2n * 2 * e},
+      {&G->grid_g, (size_t)gn * e},
+      {&G->mu, (size_t)mun * e},
+      {&G->tw[0], (size_t)G->N[0] * 2 * e},
+      {&G->tw[1], (size_t)G->N[1] * 2 * e},
+      {&G->tw[2], (size_t)G->N[2] * 2 * e},
+  };
+  if (dry_bytes) {
+    int64_t tot = 0;
+    for (const AllocReq &r : reqs) tot += (int64_t)std::max<size_t>(r.bytes, slp_geom::kMinAlloc);
+    *dry_bytes = tot;
+    return SLP_OK;
+  }
   bool ok = true;
-  ok &= G->alloc(&G->src_frac, 3 * Ms * e) == hipSuccess;
-  ok &= ok && G->alloc(&tmp, Ms * 8) == hipSuccess; G->src_w = (double *)tmp;
-  ok &= ok && G->alloc(&tmp, Ms * 4) == hipSuccess; G->src_perm = (int32_t *)tmp;
-  ok &= ok && G->alloc(&tmp, bin_runs.size() * sizeof(int4)) == hipSuccess; G->bin_runs = (int4 *)tmp;
-  ok &= ok && G->alloc(&tmp, runs.size() * sizeof(int4)) == hipSuccess; G->runs = (int4 *)tmp;
-  ok &= ok && G->alloc(&tmp, ntiles * 4) == hipSuccess; G->slot_of_tile = (int32_t *)tmp;
-  ok &= ok && G->alloc(&G->scratch, (size_t)G->n_slots * slp::pad_cells(G->m) * e) == hipSuccess;
-  ok &= ok && G->alloc(&tmp, (ntiles + 1) * 4) == hipSuccess; G->tgt_tile_start = (int32_t *)tmp;
-  ok &= ok && G->alloc(&tmp, tgt_active.size() * 4) == hipSuccess; G->tgt_active = (int32_t *)tmp;
-  ok &= ok && G->alloc(&G->q, Ms * e) == hipSuccess;
-  ok &= ok && G->alloc(&tmp, 3 * n_nodes * 4) == hipSuccess; G->tgt_cell = (int32_t *)tmp;
-  ok &= ok && G->alloc(&G->tgt_frac, 3 * n_nodes * e) == hipSuccess;
-  ok &= ok && G->alloc(&tmp, n_nodes * 4) == hipSuccess; G->tgt_perm = (int32_t *)tmp;
-  ok &= ok && G->alloc(&G->grid_a, Gsz * e) == hipSuccess;
-  ok &= ok && G->alloc(&G->S1, S1n * 2 * e) == hipSuccess;
-  ok &= ok && G->alloc(&G->S2, S2n * 2 * e) == hipSuccess;
-  ok &= ok && G->alloc(&G->grid_g, gn * e) == hipSuccess;
-  ok &= ok && G->alloc(&G->mu, mun * e) == hipSuccess;
-  for (int q = 0; q < 3; ++q) ok &= ok && G->alloc(&G->tw[q], (size_t)G->N[q] * 2 * e) == hipSuccess;
+  for (const AllocReq &r : reqs) ok = ok && G->alloc(r.dst, r.bytes) == hipSuccess;
   if (!ok) return fail(SLP_ENOMEM, "device allocation failed (%lld bytes so far)", (long long)G->bytes);
 
   HIP_TRY(hipMemcpyAsync(G->src_w, wsorted.data(), Ms * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->src_perm, sorder.data(), Ms * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->bin_runs, bin_runs.data(), bin_runs.size() * sizeof(int4), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->bin_chunks, bin_chunks.data(), bin_chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->slot_of_tile, slot_of_tile.data(), ntiles * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
@@ -666,6 +708,19 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, con
   guard.g = nullptr;
   *out = G;
   return SLP_OK;
+}
+
+}  // namespace
+
+int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, const int32_t *tris,
+                       int64_t n_tris, const slp_params *p, void *stream) {
+  return setup_impl(out, nodes, n_nodes, tris, n_tris, p, stream, nullptr);
+}
+
+int slp_geometry_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,
+                              int64_t n_tris, const slp_params *p, int64_t *bytes) {
+  if (!bytes) return fail(SLP_EINVAL, "bytes is NULL");
+  return setup_impl(nullptr, nodes, n_nodes, tris, n_tris, p, nullptr, bytes);
 }
 
 int slp_set_density(slp_geom *G, const double *dens, void *stream) {

@@ -13,14 +13,17 @@ constexpr int kMaxM = 8;      // largest supported window cut-off
 
 // Gridding (type-1 spread). Sources are sorted by (tile, cell in tile); every
 // non-empty tile ("bin") owns a padded accumulation block of (8 + 2m - 1)^3
-// cells in `scratch` (slot order). A run is a maximal sequence of sources that
-// share one grid cell.
+// cells in `scratch` (slot order). A bin is cut into chunks of at most
+// kSpreadChunk sources that end on run boundaries; a run is a sequence of
+// sources that share one grid cell (longer runs are cut at chunk size).
+constexpr int kSpreadChunk = 512;
 template <typename T>
 struct SpreadBinsArgs {
   const T *frac;         // [3][ns] t - floor(t), sorted order
   const T *q;            // [ns] charges, sorted order
-  const int4 *bin_runs;      // [n_slots] {first run, end run, tile id, 0}
-  const int4 *runs;          // {cell in tile x | y << 4 | z << 8, first source, count, 0}
+  const int4 *bin_chunks;    // [n_slots] {first chunk, end chunk, tile id, 0}
+  const int4 *chunks;        // {first source, source count, first run, run count}
+  const int32_t *runs;       // cell x | y << 3 | z << 6 | offset in chunk << 9 | count << 19
   T *scratch;            // [n_slots][PD^3]
   int64_t ns;
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
@@ -88,6 +91,9 @@ hipError_t launch_interp(const InterpArgs<T> &a, int n_active, int m, hipStream_
 int64_t pad_cells(int m);
 template <typename T>
 hipError_t launch_fft(const FftPass<T> &p, int N, hipStream_t s);
+
+// Message returned by slp_last_error() on the calling thread.
+void set_error_message(const char *msg);
 
 // FP64 setup kernels.
 hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t L,

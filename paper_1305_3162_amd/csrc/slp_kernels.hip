@@ -53,7 +53,7 @@ hipError_t launch_charges(const double *dens, const double *w, const int32_t *pe
 // axis.
 // Phase B (one workgroup per region tile): every cell sums the blocks of the
 // neighbouring bins that cover it, in a fixed order, and writes the grid.
-template <int M>
+template <typename T, int M>
 struct SpreadShape {
   static constexpr int W = 2 * M;
   static constexpr int PD = kTile + W - 1;
@@ -61,8 +61,11 @@ struct SpreadShape {
   static constexpr int COLS = W * W;
   static constexpr int NP = (COLS + 63) / 64;          // column passes per wave
   static constexpr int WAVES = 8;
-  static constexpr int SBW = 16;                       // sources per wave chunk
+  static constexpr int THREADS = WAVES * 64;
+  static constexpr int SBW = 12;                       // sources per wave chunk of factors
   static constexpr int WST = 3 * W + 1;                // LDS stride of one source's factors
+  static constexpr int CH = kSpreadChunk;              // sources staged per block chunk
+  static constexpr int PER = (4 * CH + THREADS - 1) / THREADS;
 };
 
 int64_t pad_cells(int m) {
@@ -77,18 +80,20 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(SpreadShape<M>::WAVES * 64) void k_spread_bins(SpreadBinsArgs<T> a) {
-  using S = SpreadShape<M>;
-  constexpr int W = S::W, PD = S::PD, NP = S::NP;
+__global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a) {
+  using S = SpreadShape<T, M>;
+  constexpr int W = S::W, PD = S::PD, NP = S::NP, CH = S::CH;
   __shared__ T pad[S::P3];
   __shared__ T wts[S::WAVES * S::SBW * S::WST];
+  __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
+  __shared__ int32_t rrec[CH];      // runs of the chunk
 
   const int slot = blockIdx.x;
-  const int4 br = a.bin_runs[slot];
-  for (int i = threadIdx.x; i < S::P3; i += blockDim.x) pad[i] = T(0);
-  __syncthreads();
+  const int4 bc = a.bin_chunks[slot];
+  for (int i = threadIdx.x; i < S::P3; i += S::THREADS) pad[i] = T(0);
 
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   T *ww = wts + wave * S::SBW * S::WST;
   int dxp[NP], dyp[NP];
 #pragma unroll
@@ -100,63 +105,91 @@ __global__ __launch_bounds__(SpreadShape<M>::WAVES * 64) void k_spread_bins(Spre
   const bool last_act = (lane + 64 * (NP - 1)) < S::COLS;
   const int64_t ns = a.ns;
 
-  for (int r = br.x + wave; r < br.y; r += S::WAVES) {
-    const int4 run = a.runs[r];
-    const int cx = run.x & 15, cy = (run.x >> 4) & 15, cz = run.x >> 8;
-    T acc[NP][W];
+  for (int c = bc.x; c < bc.y; ++c) {
+    const int4 ch = a.chunks[c];     // {first source, count, first run, run count}
+    // issue every global load of the chunk before writing LDS
+    T v[S::PER];
+    int32_t rv = 0;
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int j = 0; j < W; ++j) acc[p][j] = T(0);
-    for (int c0 = 0; c0 < run.z; c0 += S::SBW) {
-      const int n = min(S::SBW, run.z - c0);
-      for (int task = lane; task < 3 * n; task += 64) {
-        const int sl = task % n, ax = task / n;
-        const int64_t src = (int64_t)run.y + c0 + sl;
-        const T f = a.frac[ax * ns + src] + T(M - 1);
-        T w = wexp(-f * f * a.inv_b);
-        T rr = wexp((T(2) * f - T(1)) * a.inv_b);
-        if (ax == 0) w *= a.q[src];
-        T *dst = ww + sl * S::WST + ax * W;
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          dst[j] = w;
-          w *= rr;
-          rr *= a.step_ratio;
-        }
+    for (int k = 0; k < S::PER; ++k) {
+      const int i = tid + k * S::THREADS;
+      if (i < 4 * ch.y) {
+        const int comp = i / ch.y, sl = i - comp * ch.y;
+        v[k] = comp < 3 ? a.frac[comp * ns + ch.x + sl] : a.q[ch.x + sl];
       }
-      wave_sync();
-      for (int sl = 0; sl < n; ++sl) {
-        const T *f3 = ww + sl * S::WST;
-        T wz[W];
-#pragma unroll
-        for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (p == NP - 1 && !last_act) continue;
-          const T pw = f3[dxp[p]] * f3[W + dyp[p]];
-#pragma unroll
-          for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
-        }
-      }
-      wave_sync();
     }
+    if (tid < ch.w) rv = a.runs[ch.z + tid];
+    __syncthreads();                 // previous chunk finished with src / rrec
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      if (p == NP - 1 && !last_act) continue;
-      T *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+    for (int k = 0; k < S::PER; ++k) {
+      const int i = tid + k * S::THREADS;
+      if (i < 4 * ch.y) {
+        const int comp = i / ch.y, sl = i - comp * ch.y;
+        src[comp][sl] = v[k];
+      }
+    }
+    if (tid < ch.w) rrec[tid] = rv;
+    __syncthreads();
+
+    for (int r = wave; r < ch.w; r += S::WAVES) {
+      const int rec = rrec[r];
+      const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
+      const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
+      T acc[NP][W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, acc[p][j]);
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[p][j] = T(0);
+      for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
+        const int n = min(S::SBW, cnt - c0);
+        if (lane < 3 * n) {
+          const int ax = lane / n, sl = lane - ax * n;
+          const int si = off + c0 + sl;
+          const T f = src[ax][si] + T(M - 1);
+          T w = wexp(-f * f * a.inv_b);
+          T rr = wexp((T(2) * f - T(1)) * a.inv_b);
+          if (ax == 0) w *= src[3][si];
+          T *dst = ww + sl * S::WST + ax * W;
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            dst[j] = w;
+            w *= rr;
+            rr *= a.step_ratio;
+          }
+        }
+        wave_sync();
+        for (int sl = 0; sl < n; ++sl) {
+          const T *f3 = ww + sl * S::WST;
+          T wz[W];
+#pragma unroll
+          for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            if (p == NP - 1 && !last_act) continue;
+            const T pw = f3[dxp[p]] * f3[W + dyp[p]];
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
+          }
+        }
+        wave_sync();
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        if (p == NP - 1 && !last_act) continue;
+        T *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+#pragma unroll
+        for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, acc[p][j]);
+      }
     }
   }
   __syncthreads();
   T *dst = a.scratch + (int64_t)slot * S::P3;
-  for (int i = threadIdx.x; i < S::P3; i += blockDim.x) dst[i] = pad[i];
+  for (int i = tid; i < S::P3; i += S::THREADS) dst[i] = pad[i];
 }
 
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
-  using S = SpreadShape<M>;
+  using S = SpreadShape<T, M>;
   constexpr int PD = S::PD;
   const int tile = blockIdx.x;
   const int tx = tile % a.tiles[0];
@@ -188,9 +221,9 @@ __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
 template <typename T, int M>
 static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
                            hipStream_t s) {
-  using S = SpreadShape<M>;
+  using S = SpreadShape<T, M>;
   if (n_slots > 0)
-    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots), dim3(S::WAVES * 64), 0, s, a);
+    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots), dim3(S::THREADS), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
@@ -220,53 +253,85 @@ hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &
 // computed, then each wave takes one target at a time: its lanes cover the
 // (dy, dz) rows of the stencil, sum the 2m values of each row in T and
 // accumulate row * wy * wz in FP64; a wave reduction gives the node value.
-template <int M>
+template <typename T, int M>
 struct InterpShape {
   static constexpr int W = 2 * M;
   static constexpr int PD = kTile + W - 1;
   static constexpr int P3 = PD * PD * PD;
   static constexpr int WAVES = 16;
+  static constexpr int THREADS = WAVES * 64;
   static constexpr int TB = 64;       // targets per batch
+  static constexpr int PERG = (P3 + THREADS - 1) / THREADS;
 };
 
 template <typename T, int M>
-__global__ __launch_bounds__(InterpShape<M>::WAVES * 64) void k_interp(InterpArgs<T> a) {
-  using S = InterpShape<M>;
+__global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpArgs<T> a) {
+  using S = InterpShape<T, M>;
   constexpr int W = S::W, PD = S::PD;
   __shared__ T gt[S::P3];
   __shared__ T wts[S::TB][3][W];
+  __shared__ int32_t tcell[S::TB][3];
+  __shared__ int32_t tperm[S::TB];
 
+  const int tid = threadIdx.x;
   const int tile = a.active[blockIdx.x];
   const int tx = tile % a.tiles[0];
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int ox = tx * kTile - M + 1, oy = ty * kTile - M + 1, oz = tz * kTile - M + 1;
   const int64_t Rx = a.R[0], Ry = a.R[1];
-  for (int i = threadIdx.x; i < S::P3; i += blockDim.x) {
-    const int ix = i % PD, iy = (i / PD) % PD, iz = i / (PD * PD);
-    const int gx = ox + ix, gy = oy + iy, gz = oz + iz;
-    T v = T(0);
-    if (gx >= 0 && gx < a.R[0] && gy >= 0 && gy < a.R[1] && gz >= 0 && gz < a.R[2])
-      v = a.g[((int64_t)gz * Ry + gy) * Rx + gx];
-    gt[i] = v;
+  {
+    // issue all loads of the tile + halo before writing LDS
+    T v[S::PERG];
+#pragma unroll
+    for (int k = 0; k < S::PERG; ++k) {
+      const int i = tid + k * S::THREADS;
+      v[k] = T(0);
+      if (i < S::P3) {
+        const int ix = i % PD, iy = (i / PD) % PD, iz = i / (PD * PD);
+        const int gx = ox + ix, gy = oy + iy, gz = oz + iz;
+        if (gx >= 0 && gx < a.R[0] && gy >= 0 && gy < a.R[1] && gz >= 0 && gz < a.R[2])
+          v[k] = a.g[((int64_t)gz * Ry + gy) * Rx + gx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < S::PERG; ++k) {
+      const int i = tid + k * S::THREADS;
+      if (i < S::P3) gt[i] = v[k];
+    }
   }
   const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t nt = a.nt;
   for (int b0 = t0; b0 < t1; b0 += S::TB) {
     const int nb = min(S::TB, t1 - b0);
-    __syncthreads();   // grid tile loaded / previous batch finished with wts
-    for (int task = threadIdx.x; task < 3 * nb * W; task += blockDim.x) {
-      const int j = task % W, s = (task / W) % nb, ax = task / (W * nb);
-      const T k = T(j - M + 1);
-      const T d = a.frac[ax * nt + b0 + s] - k;
-      wts[s][ax][j] = wexp(-d * d * a.inv_b);
+    // target data of the batch: 3 cells, 3 fractions, permutation (one load per thread)
+    int32_t ci = 0;
+    T fr = T(0);
+    const int item = tid % S::TB, kind = tid / S::TB;   // kind 0..2 cell, 3..5 frac, 6 perm
+    if (item < nb && kind < 7) {
+      const int64_t i = b0 + item;
+      if (kind < 3) ci = a.cell[kind * nt + i];
+      else if (kind < 6) fr = a.frac[(kind - 3) * nt + i];
+      else ci = a.perm[i];
+    }
+    __syncthreads();   // grid tile loaded / previous batch finished
+    if (item < nb && kind < 7) {
+      if (kind < 3) tcell[item][kind] = ci;
+      else if (kind == 6) tperm[item] = ci;
+      else {
+        const int ax = kind - 3;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          const T d = fr - T(j - M + 1);
+          wts[item][ax][j] = wexp(-d * d * a.inv_b);
+        }
+      }
     }
     __syncthreads();
     for (int s = wave; s < nb; s += S::WAVES) {
-      const int i = b0 + s;
-      const int cx = a.cell[i] - tx * kTile, cy = a.cell[nt + i] - ty * kTile,
-                cz = a.cell[2 * nt + i] - tz * kTile;
+      const int cx = tcell[s][0] - tx * kTile, cy = tcell[s][1] - ty * kTile,
+                cz = tcell[s][2] - tz * kTile;
       T wx[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) wx[j] = wts[s][0][j];
@@ -283,8 +348,8 @@ __global__ __launch_bounds__(InterpShape<M>::WAVES * 64) void k_interp(InterpArg
         acc += (double)((s0 + s1) * (wts[s][1][dy] * wts[s][2][dz]));
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-      if (lane == 0) a.phi[a.perm[i]] = acc;
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) a.phi[tperm[s]] = acc;
     }
   }
 }
@@ -292,7 +357,7 @@ __global__ __launch_bounds__(InterpShape<M>::WAVES * 64) void k_interp(InterpArg
 template <typename T, int M>
 static hipError_t interp_m(const InterpArgs<T> &a, int n_active, hipStream_t s) {
   if (n_active == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_interp<T, M>), dim3((unsigned)n_active), dim3(InterpShape<M>::WAVES * 64),
+  hipLaunchKernelGGL((k_interp<T, M>), dim3((unsigned)n_active), dim3(InterpShape<T, M>::THREADS),
                      0, s, a);
   return hipGetLastError();
 }
