@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--workload", default="cube64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="served mix: Poisson request stream through the request server")
+    ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--rho", type=float, default=0.8, help="offered load / capacity")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known "
                          "traffic, to scale hardware byte counters)")
@@ -78,8 +82,113 @@ def algorithmic_units(stage, info, m, esz):
     raise KeyError(stage)
 
 
+def serve(args):
+    """Served mix: Poisson arrivals over resident geometries (icosphere L3-L6, cubes
+    16-256 cells per edge), fresh seeded magnetisation per request drawn from a pool
+    of densities per shape, FP32; p50/p99 latency and pts/s from the server, next to
+    the plain FP64 path (one stream, one solve after the other) on the same mix."""
+    import torch
+
+    import paper_1305_3162_amd as slp
+    from synth import icosphere, cube, RandomSmoothMagnetisation, density_from_magnetisation
+    from synth.workloads import expsum_interval
+
+    shapes = [("sphere", L) for L in (3, 4, 5, 6)] + [("cube", c) for c in (16, 32, 64, 128, 256)]
+    rng = np.random.default_rng(5)
+    geo = []
+    for kind, size in shapes:
+        nodes, tris = icosphere(size) if kind == "sphere" else cube(size)
+        # mean edge length after scaling into (-0.2, 0.2): 0.4 * edge / extent
+        e = nodes[tris[:, [1, 2, 0]]] - nodes[tris]
+        hbar = 0.4 * float(np.linalg.norm(e, axis=2).mean()) / float((nodes.max(0) - nodes.min(0)).max())
+        N = int(min(512, max(64, 2 ** int(np.floor(np.log2(1.0 / hbar))))))
+        r_lo, r_hi = expsum_interval(nodes)
+        w, g = slp.expsum_sinc(0.2, r_lo, r_hi, 1e-12)
+        dens = []
+        for k in range(2):
+            mf = RandomSmoothMagnetisation(5000 + 10 * len(geo) + k, nodes.min(0), nodes.max(0))
+            dens.append(torch.as_tensor(density_from_magnetisation(nodes, tris, mf), device="cuda"))
+        geo.append(dict(kind=kind, size=size, nodes=nodes, tris=tris, N=N, w=w, g=g, dens=dens,
+                        pts=3 * tris.shape[0] + nodes.shape[0]))
+    m32, m64 = 5, 7
+    budget = 8 << 30
+    srv = slp.Server(budget, 4)
+    for G in geo:
+        G["id"] = srv.add_geometry(G["nodes"], G["tris"], (G["N"],) * 3, m32, G["w"], G["g"], 2,
+                                   slp.FP32)
+        G["phi"] = [torch.empty(G["nodes"].shape[0], dtype=torch.float64, device="cuda")
+                    for _ in range(8)]
+    torch.cuda.synchronize()
+    # warm-up: build every geometry, then measure capacity at saturation
+    for G in geo:
+        srv.wait(srv.submit(G["id"], G["dens"][0], G["phi"][0]), 120)
+    picks = rng.integers(len(geo), size=args.requests)
+    srv.stats(reset=True)
+    t0 = time.perf_counter()
+    tks = [srv.submit(geo[i]["id"], geo[i]["dens"][0], geo[i]["phi"][k % 8])
+           for k, i in enumerate(picks[:200])]
+    for tk in tks:
+        srv.wait(tk, 120)
+    cap = 200 / (time.perf_counter() - t0)
+    srv.stats(reset=True)
+    lam = args.rho * cap
+    gaps = rng.exponential(1.0 / lam, size=args.requests)
+    arrive = np.cumsum(gaps)
+    tks = []
+    t0 = time.perf_counter()
+    for k, i in enumerate(picks):
+        while time.perf_counter() - t0 < arrive[k]:
+            pass
+        G = geo[i]
+        tks.append(srv.submit(G["id"], G["dens"][k % 2], G["phi"][k % 8]))
+    for tk in tks:
+        srv.wait(tk, 120)
+    st = srv.stats()
+    srv.close()
+    # plain FP64 path on the same mix, one stream
+    plain = []
+    for G in geo:
+        gg = slp.Geometry(G["nodes"], G["tris"], (G["N"],) * 3, m64, G["w"], G["g"], 2, slp.FP64)
+        phi = torch.empty(G["nodes"].shape[0], dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            gg.set_density(G["dens"][0]); gg.eval(phi)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(10):
+            gg.set_density(G["dens"][0]); gg.eval(phi)
+        torch.cuda.synchronize()
+        plain.append((time.perf_counter() - t1) / 10)
+        gg.close()
+    mix_pts = float(np.mean([geo[i]["pts"] for i in picks]))
+    mix_time64 = float(np.mean([plain[i] for i in picks]))
+    rec = {
+        "metric": "served SL-potential NUFFT latency and (M+N) pts/s",
+        "value": round(st["pts_per_s"], 1), "unit": "pts/s", "n_gpus": 1,
+        "requests": args.requests, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic",
+        "p50_ms": round(st["p50_s"] * 1e3, 4), "p99_ms": round(st["p99_s"] * 1e3, 4),
+        "mean_ms": round(st["mean_s"] * 1e3, 4),
+        "offered_rate_per_s": round(lam, 1), "capacity_per_s": round(cap, 1), "rho": args.rho,
+        "completed": st["completed"], "failed": st["failed"], "setups": st["setups"],
+        "evictions": st["evictions"],
+        "plain_fp64_pts_per_s": round(mix_pts / mix_time64, 1), "plain_fp64_m": m64,
+        "served_m": m32,
+        "config": {"workload": "Poisson stream over icosphere L3-L6 and cubes 16/32/64/128/256 "
+                               "cells per edge (uniform pick, seed 5), 2 seeded magnetisations "
+                               "per shape, grid clamp(prevpow2(1/mean scaled edge), 64, 512)^3",
+                   "slots": 4, "budget_bytes": budget},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
+    if args.serve:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        serve(args)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU runs are not "
               "part of it", file=sys.stderr)

@@ -590,10 +590,32 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       bin_chunks.push_back(bc);
     }
   }
+  // largest bins first: the hardware hands out workgroups in launch order, so
+  // the long ones start early and the short ones fill the tail
+  {
+    std::vector<int32_t> order(bin_chunks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    auto nsrc = [&](int32_t b) {
+      int64_t n = 0;
+      for (int c = bin_chunks[b].x; c < bin_chunks[b].y; ++c) n += chunks[c].y;
+      return n;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return nsrc(a) > nsrc(b); });
+    std::vector<int4> sorted(bin_chunks.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+      sorted[i] = bin_chunks[order[i]];
+      slot_of_tile[sorted[i].z] = (int32_t)i;
+    }
+    bin_chunks.swap(sorted);
+  }
   G->n_slots = (int32_t)bin_chunks.size();
   std::vector<int32_t> tgt_active;
   for (int64_t t = 0; t < ntiles; ++t)
     if (tstart[t + 1] > tstart[t]) tgt_active.push_back((int32_t)t);
+  std::stable_sort(tgt_active.begin(), tgt_active.end(), [&](int32_t a, int32_t b) {
+    return tstart[a + 1] - tstart[a] > tstart[b + 1] - tstart[b];
+  });
   G->n_tgt_tiles = (int32_t)tgt_active.size();
 
   // device allocations

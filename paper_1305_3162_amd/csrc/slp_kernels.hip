@@ -41,7 +41,7 @@ hipError_t launch_charges(const double *dens, const double *w, const int32_t *pe
 }
 
 // ----------------------------------------------------------------- spread ---
-// Phase A (one workgroup of 8 waves per non-empty bin): the bin's sources are
+// Phase A (one workgroup of 8 or 16 waves per non-empty bin): the bin's sources are
 // scattered into an LDS block covering the bin plus the stencil halo,
 // (8 + 2m - 1)^3 cells. Each wave independently takes every 8th run of sources
 // that share one grid cell; its lanes cover the 2m x 2m (dx, dy) columns of the
@@ -60,7 +60,7 @@ struct SpreadShape {
   static constexpr int P3 = PD * PD * PD;
   static constexpr int COLS = W * W;
   static constexpr int NP = (COLS + 63) / 64;          // column passes per wave
-  static constexpr int WAVES = 8;
+  static constexpr int WAVES = M <= 5 ? 16 : 8;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int SBW = 12;                       // sources per wave chunk of factors
   static constexpr int WST = 3 * W + 1;                // LDS stride of one source's factors
@@ -83,14 +83,17 @@ template <typename T, int M>
 __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a) {
   using S = SpreadShape<T, M>;
   constexpr int W = S::W, PD = S::PD, NP = S::NP, CH = S::CH;
-  __shared__ T pad[S::P3];
+  // The block is accumulated in FP64 in both precisions: LDS FP64 atomic adds
+  // are native and fast on gfx950, FP32 LDS atomic adds measured several times
+  // slower; the block is stored in T.
+  __shared__ double pad[S::P3];
   __shared__ T wts[S::WAVES * S::SBW * S::WST];
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
 
   const int slot = blockIdx.x;
   const int4 bc = a.bin_chunks[slot];
-  for (int i = threadIdx.x; i < S::P3; i += S::THREADS) pad[i] = T(0);
+  for (int i = threadIdx.x; i < S::P3; i += S::THREADS) pad[i] = 0.0;
 
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
@@ -176,15 +179,15 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         if (p == NP - 1 && !last_act) continue;
-        T *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+        double *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
 #pragma unroll
-        for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, acc[p][j]);
+        for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[p][j]);
       }
     }
   }
   __syncthreads();
   T *dst = a.scratch + (int64_t)slot * S::P3;
-  for (int i = tid; i < S::P3; i += S::THREADS) dst[i] = pad[i];
+  for (int i = tid; i < S::P3; i += S::THREADS) dst[i] = (T)pad[i];
 }
 
 template <typename T, int M>
