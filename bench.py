@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--workload", default="cube64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="densities per step on the one geometry (batched launch)")
     ap.add_argument("--serve", action="store_true",
                     help="served mix: Poisson request stream through the request server")
     ap.add_argument("--requests", type=int, default=1000)
@@ -217,10 +219,22 @@ def main():
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     dens = torch.as_tensor(wl.dens, device="cuda")
     phi = torch.empty(wl.n_nodes, dtype=torch.float64, device="cuda")
+    nb = max(1, args.batch)
+    if nb > 1:
+        from synth import RandomSmoothMagnetisation, density_from_magnetisation
+        dl = [dens] + [torch.as_tensor(density_from_magnetisation(
+            wl.nodes, wl.tris, RandomSmoothMagnetisation(4000 + k, wl.nodes.min(0),
+                                                         wl.nodes.max(0))), device="cuda")
+            for k in range(1, nb)]
+        pl = [phi] + [torch.empty_like(phi) for _ in range(1, nb)]
+        hl = [geom.handle] * nb
 
     def step():
-        geom.set_density(dens, stream)
-        geom.eval(phi, stream)
+        if nb > 1:
+            slp.eval_batched(hl, dl, pl, stream)
+        else:
+            geom.set_density(dens, stream)
+            geom.eval(phi, stream)
 
     for _ in range(args.warmup):
         step()
@@ -242,13 +256,14 @@ def main():
     slp.set_timing(geom.handle, False)
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = max(wall * 1e3, gpu_ms) / args.steps
-    pts = wl.n_src + wl.n_nodes
+    pts = (wl.n_src + wl.n_nodes) * nb
     value = pts / (ms_per_step * 1e-3)
     avg = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
 
     # roofline of the dominant kernel
     dom = max(avg, key=avg.get)
     amount, unit, bound = algorithmic_units(dom, info, m, esz)
+    amount *= nb
     dur_s = avg[dom] * 1e-3
     if bound == "hbm":
         achieved, peak, runit = amount / dur_s / 1e9, PEAK["hbm_GBps"], "GB/s"
@@ -299,7 +314,7 @@ def main():
                                f"triangles, {wl.n_nodes} nodes, {wl.n_src} quadrature sources, "
                                f"grid {wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]}, alpha 2, "
                                f"Gaussian cut-off m={m}" if args.workload == "cube64" else wl.name,
-                   "m": m, "precision": args.precision, "points": pts},
+                   "m": m, "precision": args.precision, "points": pts, "densities_per_step": nb},
         "rel_l2_err_vs_oracle": rel_err,
         "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
         "roofline": roofline,

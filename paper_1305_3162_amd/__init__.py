@@ -258,8 +258,11 @@ def eval_batched(geoms, dens, phis, stream=None):
     G = (_VP * n)(*[_VP(g) for g in geoms])
     D = (_VP * n)()
     P = (_VP * n)()
+    infos = {}
     for i, g in enumerate(geoms):
-        info = geom_get_info(g)
+        info = infos.get(g)
+        if info is None:
+            info = infos[g] = geom_get_info(g)
         D[i] = _dev_f64(dens[i], info["n_src"], f"dens[{i}]").value
         P[i] = _dev_f64(phis[i], info["n_nodes"], f"phi[{i}]").value
     _check(load_library().slp_eval_batched(G, D, P, n, _stream_ptr(stream)))

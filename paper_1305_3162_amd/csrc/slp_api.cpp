@@ -99,6 +99,8 @@ struct slp_geom {
   int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
   int32_t terms_kept = 0;
   int32_t n_slots = 0;           // non-empty source bins
+  int32_t cap = 1;               // batch items the per-item buffers hold
+  int64_t item_elems[6]{};       // per item: q, scratch, grid_a, S1 (complex), S2 (complex), grid_g
   int32_t n_tgt_tiles = 0;       // tiles holding targets
   // device buffers
   void *src_frac = nullptr;
@@ -144,10 +146,22 @@ struct slp_geom {
     hipError_t e = hipMalloc(p, bytes_);
     if (e == hipSuccess) {
       allocs.push_back(*p);
+      alloc_bytes.push_back((int64_t)bytes_);
       bytes += (int64_t)bytes_;
     }
     return e;
   }
+  void release(void *p) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        (void)hipFree(p);
+        bytes -= alloc_bytes[i];
+        allocs.erase(allocs.begin() + i);
+        alloc_bytes.erase(alloc_bytes.begin() + i);
+        return;
+      }
+  }
+  std::vector<int64_t> alloc_bytes;
   ~slp_geom() {
     for (void *p : allocs) (void)hipFree(p);
     if (ev_ready)
@@ -228,8 +242,41 @@ int upload_twiddles(slp_geom *G, hipStream_t st, std::vector<std::vector<T>> &ho
   return SLP_OK;
 }
 
+// Grow the per-item work buffers to hold nb batch items (synchronises the
+// stream before freeing the old ones).
+int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
+  if (nb <= G->cap) return SLP_OK;
+  HIP_TRY(hipStreamSynchronize(st));
+  void **bufs[6] = {&G->q, &G->scratch, &G->grid_a, &G->S1, &G->S2, &G->grid_g};
+  const size_t e = G->esz();
+  const size_t per[6] = {e, e, e, 2 * e, 2 * e, e};
+  for (int i = 0; i < 6; ++i) {
+    G->release(*bufs[i]);
+    *bufs[i] = nullptr;
+  }
+  for (int i = 0; i < 6; ++i)
+    if (G->alloc(bufs[i], (size_t)G->item_elems[i] * per[i] * nb) != hipSuccess) {
+      // leave a usable single-item context behind
+      for (int k = 0; k < 6; ++k)
+        if (*bufs[k]) { G->release(*bufs[k]); *bufs[k] = nullptr; }
+      bool ok = true;
+      for (int k = 0; k < 6; ++k) ok = ok && G->alloc(bufs[k], (size_t)G->item_elems[k] * per[k]) == hipSuccess;
+      G->cap = 1;
+      return fail(ok ? SLP_ENOMEM : SLP_EDEVICE, "batch buffers for %d items: allocation failed", nb);
+    }
+  G->cap = nb;
+  return SLP_OK;
+}
+
 template <typename T>
-int run_eval(slp_geom *G, double *phi, hipStream_t st) {
+int launch_charges_items(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
+  HIP_TRY(slp::launch_charges<T>(ptrs, G->src_w, G->src_perm, static_cast<T *>(G->q), G->n_src,
+                                 G->item_elems[0], nb, st));
+  return SLP_OK;
+}
+
+template <typename T>
+int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
   const bool tm = G->timing;
   if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
   // spread
@@ -242,14 +289,18 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     a.runs = G->runs;
     a.scratch = static_cast<T *>(G->scratch);
     a.ns = G->n_src;
+    a.q_bstride = G->item_elems[0];
+    a.scratch_bstride = G->item_elems[1];
     a.inv_b = (T)(1.0 / G->b);
     a.step_ratio = (T)std::exp(-2.0 / G->b);
     slp::SpreadReduceArgs<T> r{};
     r.scratch = static_cast<const T *>(G->scratch);
     r.slot_of_tile = G->slot_of_tile;
     r.grid = static_cast<T *>(G->grid_a);
+    r.scratch_bstride = G->item_elems[1];
+    r.grid_bstride = G->item_elems[2];
     for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
-    HIP_TRY(slp::launch_spread<T>(a, r, G->n_slots, G->m, st));
+    HIP_TRY(slp::launch_spread<T>(a, r, G->n_slots, G->m, nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
   const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
@@ -264,7 +315,8 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     p.in_s1 = Px; p.in_s2 = Py * Px; p.in_es = 1; p.in_cnt = (int)Rx; p.in_shift = G->lo[0];
     p.out_s1 = Kx; p.out_s2 = Ry * Kx; p.out_es = 1; p.out_cnt = (int)Kx; p.out_shift = 0;
     p.sign = -1; p.in_real = 1;
-    HIP_TRY(slp::launch_fft<T>(p, G->N[0], st));
+    p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[3];
+    HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
   // y forward: region y -> ky = -n_y/2..n_y/2
@@ -275,7 +327,8 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     p.in_s1 = 1; p.in_s2 = Ry * Kx; p.in_es = Kx; p.in_cnt = (int)Ry; p.in_shift = G->lo[1];
     p.out_s1 = 1; p.out_s2 = Ky * Kx; p.out_es = Kx; p.out_cnt = (int)Ky; p.out_shift = -ny / 2;
     p.sign = -1;
-    HIP_TRY(slp::launch_fft<T>(p, G->N[1], st));
+    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[4];
+    HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
   // z forward, multiply by mu on kz = -n_z/2..n_z/2, z inverse back to the region
@@ -288,7 +341,8 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
     p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
     p.sign = -1; p.mul_inv = 1;
-    HIP_TRY(slp::launch_fft<T>(p, G->N[2], st));
+    p.in_bstride = G->item_elems[4]; p.out_bstride = G->item_elems[4];
+    HIP_TRY(slp::launch_fft<T>(p, G->N[2], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
   // y inverse: ky -> region y
@@ -299,7 +353,8 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     p.in_s1 = 1; p.in_s2 = Ky * Kx; p.in_es = Kx; p.in_cnt = (int)Ky; p.in_shift = -ny / 2;
     p.out_s1 = 1; p.out_s2 = Ry * Kx; p.out_es = Kx; p.out_cnt = (int)Ry; p.out_shift = G->lo[1];
     p.sign = +1;
-    HIP_TRY(slp::launch_fft<T>(p, G->N[1], st));
+    p.in_bstride = G->item_elems[4]; p.out_bstride = G->item_elems[3];
+    HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
   // x inverse (Hermitian half spectrum -> real region rows)
@@ -311,7 +366,8 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     p.in_hermitian = 1;
     p.out_s1 = Rx; p.out_s2 = Ry * Rx; p.out_es = 1; p.out_cnt = (int)Rx; p.out_shift = G->lo[0];
     p.out_real = 1; p.sign = +1;
-    HIP_TRY(slp::launch_fft<T>(p, G->N[0], st));
+    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[5];
+    HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
   (void)nx;
   if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
@@ -323,14 +379,14 @@ int run_eval(slp_geom *G, double *phi, hipStream_t st) {
     a.tile_start = G->tgt_tile_start;
     a.active = G->tgt_active;
     a.g = static_cast<const T *>(G->grid_g);
-    a.phi = phi;
+    a.g_bstride = G->item_elems[5];
     for (int i = 0; i < 3; ++i) {
       a.R[i] = G->R[i];
       a.tiles[i] = G->tiles[i];
     }
     a.nt = G->n_nodes;
     a.inv_b = (T)(1.0 / G->b);
-    HIP_TRY(slp::launch_interp<T>(a, G->n_tgt_tiles, G->m, st));
+    HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
   }
   if (tm) {
     HIP_TRY(hipEventRecord(G->evs()[8], st));
@@ -625,6 +681,12 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   const int64_t S2n = (int64_t)G->R[2] * G->K[1] * G->K[0];
   const int64_t gn = (int64_t)G->R[0] * G->R[1] * G->R[2];
   const int64_t mun = (int64_t)G->K[0] * G->K[1] * G->K[2];
+  G->item_elems[0] = Ms;
+  G->item_elems[1] = (int64_t)G->n_slots * slp::pad_cells(G->m);
+  G->item_elems[2] = Gsz;
+  G->item_elems[3] = S1n;
+  G->item_elems[4] = S2n;
+  G->item_elems[5] = gn;
   struct AllocReq {
     void **dst;
     size_t bytes;
@@ -753,11 +815,10 @@ int slp_set_density(slp_geom *G, const double *dens, void *stream) {
     if (rc) return rc;
     G->density_marked = true;
   }
-  if (G->prec == SLP_FP64)
-    HIP_TRY(slp::launch_charges<double>(dens, G->src_w, G->src_perm, (double *)G->q, G->n_src, st));
-  else
-    HIP_TRY(slp::launch_charges<float>(dens, G->src_w, G->src_perm, (float *)G->q, G->n_src, st));
-  return SLP_OK;
+  slp::BatchPtrs ptrs{};
+  ptrs.dens[0] = dens;
+  return G->prec == SLP_FP64 ? launch_charges_items<double>(G, ptrs, 1, st)
+                             : launch_charges_items<float>(G, ptrs, 1, st);
 }
 
 int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
@@ -768,7 +829,9 @@ int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
     if (rc) return rc;
   }
   G->density_marked = false;
-  return G->prec == SLP_FP64 ? run_eval<double>(G, phi, st) : run_eval<float>(G, phi, st);
+  slp::BatchPtrs ptrs{};
+  ptrs.phi[0] = phi;
+  return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, 1, st) : run_eval<float>(G, ptrs, 1, st);
 }
 
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
@@ -776,11 +839,31 @@ int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *
   if (batch < 1 || !geoms || !dens || !phi) return fail(SLP_EINVAL, "batched: batch >= 1 and non-NULL arrays");
   for (int32_t b = 0; b < batch; ++b)
     if (!geoms[b] || !dens[b] || !phi[b]) return fail(SLP_EINVAL, "batched: item %d has a NULL pointer", b);
-  for (int32_t b = 0; b < batch; ++b) {
-    int rc = slp_set_density(geoms[b], dens[b], stream);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // consecutive items on one geometry share every launch (up to kMaxBatch)
+  int32_t b = 0;
+  while (b < batch) {
+    slp_geom *G = geoms[b];
+    int32_t e = b + 1;
+    while (e < batch && geoms[e] == G && e - b < slp::kMaxBatch) ++e;
+    const int nb = e - b;
+    int rc = ensure_capacity(G, nb, st);
     if (rc) return rc;
-    rc = slp_eval_single_layer(geoms[b], phi[b], stream);
+    slp::BatchPtrs ptrs{};
+    for (int i = 0; i < nb; ++i) {
+      ptrs.dens[i] = dens[b + i];
+      ptrs.phi[i] = phi[b + i];
+    }
+    if (G->timing) {
+      rc = begin_timed(G, st);
+      if (rc) return rc;
+    }
+    G->density_marked = false;
+    rc = G->prec == SLP_FP64 ? launch_charges_items<double>(G, ptrs, nb, st)
+                             : launch_charges_items<float>(G, ptrs, nb, st);
+    if (!rc) rc = G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st) : run_eval<float>(G, ptrs, nb, st);
     if (rc) return rc;
+    b = e;
   }
   return SLP_OK;
 }

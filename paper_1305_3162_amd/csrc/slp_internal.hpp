@@ -17,6 +17,14 @@ constexpr int kMaxM = 8;      // largest supported window cut-off
 // kSpreadChunk sources that end on run boundaries; a run is a sequence of
 // sources that share one grid cell (longer runs are cut at chunk size).
 constexpr int kSpreadChunk = 512;
+// Densities evaluated on one geometry by one launch of every stage.
+constexpr int kMaxBatch = 64;
+
+// Per-item caller pointers of a batched launch (passed by value).
+struct BatchPtrs {
+  const double *dens[kMaxBatch];
+  double *phi[kMaxBatch];
+};
 template <typename T>
 struct SpreadBinsArgs {
   const T *frac;         // [3][ns] t - floor(t), sorted order
@@ -26,6 +34,7 @@ struct SpreadBinsArgs {
   const int32_t *runs;       // cell x | y << 3 | z << 6 | offset in chunk << 9 | count << 19
   T *scratch;            // [n_slots][PD^3]
   int64_t ns;
+  int64_t q_bstride, scratch_bstride;   // per batch item (blockIdx.y)
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
   T step_ratio;          // exp(-2 / b): ratio of consecutive weight ratios
 };
@@ -37,6 +46,7 @@ struct SpreadReduceArgs {
   const int32_t *slot_of_tile;   // [tiles] slot or -1
   T *grid;                       // [P_z][P_y][P_x]
   int32_t tiles[3];
+  int64_t scratch_bstride, grid_bstride;
 };
 
 // Interpolation (type-2 gather) at the tile-sorted targets.
@@ -48,7 +58,7 @@ struct InterpArgs {
   const int32_t *tile_start;  // [tiles + 1]
   const int32_t *active;      // [n_active] tiles holding targets
   const T *g;            // [R_z][R_y][R_x] grid after the inverse FFT
-  double *phi;           // [nt] output, caller order
+  int64_t g_bstride;
   int32_t R[3];
   int32_t tiles[3];
   int64_t nt;
@@ -77,20 +87,23 @@ struct FftPass {
   int32_t in_hermitian;  // also place conj(v_e) at N - e (e >= 1)
   int32_t out_real;      // store the real part only
   int32_t mul_inv;       // forward, multiply by mu (zero elsewhere), inverse
+  int64_t in_bstride, out_bstride;   // per batch item (blockIdx.y)
 };
 
+// Every launch covers nb batch items (gridDim.y = nb, 1 <= nb <= kMaxBatch).
 template <typename T>
-hipError_t launch_charges(const double *dens, const double *w, const int32_t *perm, T *q,
-                          int64_t ns, hipStream_t s);
+hipError_t launch_charges(const BatchPtrs &p, const double *w, const int32_t *perm, T *q,
+                          int64_t ns, int64_t q_bstride, int nb, hipStream_t s);
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
-                         int m, hipStream_t s);
+                         int m, int nb, hipStream_t s);
 template <typename T>
-hipError_t launch_interp(const InterpArgs<T> &a, int n_active, int m, hipStream_t s);
+hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int m, int nb,
+                         hipStream_t s);
 // Cells of the padded accumulation block of one bin: (8 + 2m - 1)^3.
 int64_t pad_cells(int m);
 template <typename T>
-hipError_t launch_fft(const FftPass<T> &p, int N, hipStream_t s);
+hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s);
 
 // Message returned by slp_last_error() on the calling thread.
 void set_error_message(const char *msg);

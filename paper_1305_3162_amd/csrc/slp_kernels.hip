@@ -25,18 +25,21 @@ __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
 // ---------------------------------------------------------------- charges ---
 template <typename T>
-__global__ void k_charges(const double *__restrict__ dens, const double *__restrict__ w,
-                          const int32_t *__restrict__ perm, T *__restrict__ q, int64_t ns) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ns) q[i] = (T)(w[i] * dens[perm[i]]);
+__global__ void k_charges(BatchPtrs ptrs, const double *__restrict__ w,
+                          const int32_t *__restrict__ perm, T *__restrict__ q, int64_t ns,
+                          int64_t q_bstride) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int item = blockIdx.y;
+  if (i < ns) q[item * q_bstride + i] = (T)(w[i] * ptrs.dens[item][perm[i]]);
 }
 
 template <typename T>
-hipError_t launch_charges(const double *dens, const double *w, const int32_t *perm, T *q,
-                          int64_t ns, hipStream_t s) {
+hipError_t launch_charges(const BatchPtrs &p, const double *w, const int32_t *perm, T *q,
+                          int64_t ns, int64_t q_bstride, int nb, hipStream_t s) {
   if (ns == 0) return hipSuccess;
   int64_t blocks = (ns + 255) / 256;
-  hipLaunchKernelGGL(k_charges<T>, dim3((unsigned)blocks), dim3(256), 0, s, dens, w, perm, q, ns);
+  hipLaunchKernelGGL(k_charges<T>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, p, w,
+                     perm, q, ns, q_bstride);
   return hipGetLastError();
 }
 
@@ -93,6 +96,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
 
   const int slot = blockIdx.x;
   const int4 bc = a.bin_chunks[slot];
+  const T *qv = a.q + blockIdx.y * a.q_bstride;
   for (int i = threadIdx.x; i < S::P3; i += S::THREADS) pad[i] = 0.0;
 
   const int tid = threadIdx.x;
@@ -118,7 +122,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
       const int i = tid + k * S::THREADS;
       if (i < 4 * ch.y) {
         const int comp = i / ch.y, sl = i - comp * ch.y;
-        v[k] = comp < 3 ? a.frac[comp * ns + ch.x + sl] : a.q[ch.x + sl];
+        v[k] = comp < 3 ? a.frac[comp * ns + ch.x + sl] : qv[ch.x + sl];
       }
     }
     if (tid < ch.w) rv = a.runs[ch.z + tid];
@@ -186,7 +190,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
     }
   }
   __syncthreads();
-  T *dst = a.scratch + (int64_t)slot * S::P3;
+  T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)slot * S::P3;
   for (int i = tid; i < S::P3; i += S::THREADS) dst[i] = (T)pad[i];
 }
 
@@ -199,6 +203,8 @@ __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int64_t Px = (int64_t)a.tiles[0] * kTile, Py = (int64_t)a.tiles[1] * kTile;
+  const T *scr = a.scratch + blockIdx.y * a.scratch_bstride;
+  T *grid = a.grid + blockIdx.y * a.grid_bstride;
   for (int c = threadIdx.x; c < kTile * kTile * kTile; c += blockDim.x) {
     const int gx = tx * kTile + (c & 7), gy = ty * kTile + ((c >> 3) & 7), gz = tz * kTile + (c >> 6);
     T v = T(0);
@@ -213,39 +219,41 @@ __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
           if (bx < 0 || bx >= a.tiles[0] || ix < 0 || ix >= PD) continue;
           const int slot = a.slot_of_tile[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
           if (slot < 0) continue;
-          v += a.scratch[(int64_t)slot * S::P3 + (iz * PD + iy) * PD + ix];
+          v += scr[(int64_t)slot * S::P3 + (iz * PD + iy) * PD + ix];
         }
       }
     }
-    a.grid[(gz * Py + gy) * Px + gx] = v;
+    grid[(gz * Py + gy) * Px + gx] = v;
   }
 }
 
 template <typename T, int M>
 static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
-                           hipStream_t s) {
+                           int nb, hipStream_t s) {
   using S = SpreadShape<T, M>;
   if (n_slots > 0)
-    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots), dim3(S::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots, (unsigned)nb),
+                       dim3(S::THREADS), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
-  hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles), dim3(256), 0, s, r);
+  hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles, (unsigned)nb), dim3(256), 0, s,
+                     r);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
-                         int m, hipStream_t s) {
+                         int m, int nb, hipStream_t s) {
   switch (m) {
-    case 1: return spread_m<T, 1>(a, r, n_slots, s);
-    case 2: return spread_m<T, 2>(a, r, n_slots, s);
-    case 3: return spread_m<T, 3>(a, r, n_slots, s);
-    case 4: return spread_m<T, 4>(a, r, n_slots, s);
-    case 5: return spread_m<T, 5>(a, r, n_slots, s);
-    case 6: return spread_m<T, 6>(a, r, n_slots, s);
-    case 7: return spread_m<T, 7>(a, r, n_slots, s);
-    case 8: return spread_m<T, 8>(a, r, n_slots, s);
+    case 1: return spread_m<T, 1>(a, r, n_slots, nb, s);
+    case 2: return spread_m<T, 2>(a, r, n_slots, nb, s);
+    case 3: return spread_m<T, 3>(a, r, n_slots, nb, s);
+    case 4: return spread_m<T, 4>(a, r, n_slots, nb, s);
+    case 5: return spread_m<T, 5>(a, r, n_slots, nb, s);
+    case 6: return spread_m<T, 6>(a, r, n_slots, nb, s);
+    case 7: return spread_m<T, 7>(a, r, n_slots, nb, s);
+    case 8: return spread_m<T, 8>(a, r, n_slots, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -268,7 +276,8 @@ struct InterpShape {
 };
 
 template <typename T, int M>
-__global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpArgs<T> a) {
+__global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpArgs<T> a,
+                                                                          BatchPtrs ptrs) {
   using S = InterpShape<T, M>;
   constexpr int W = S::W, PD = S::PD;
   __shared__ T gt[S::P3];
@@ -283,6 +292,8 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int ox = tx * kTile - M + 1, oy = ty * kTile - M + 1, oz = tz * kTile - M + 1;
   const int64_t Rx = a.R[0], Ry = a.R[1];
+  const T *gsrc = a.g + blockIdx.y * a.g_bstride;
+  double *phi = ptrs.phi[blockIdx.y];
   {
     // issue all loads of the tile + halo before writing LDS
     T v[S::PERG];
@@ -294,7 +305,7 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
         const int ix = i % PD, iy = (i / PD) % PD, iz = i / (PD * PD);
         const int gx = ox + ix, gy = oy + iy, gz = oz + iz;
         if (gx >= 0 && gx < a.R[0] && gy >= 0 && gy < a.R[1] && gz >= 0 && gz < a.R[2])
-          v[k] = a.g[((int64_t)gz * Ry + gy) * Rx + gx];
+          v[k] = gsrc[((int64_t)gz * Ry + gy) * Rx + gx];
       }
     }
 #pragma unroll
@@ -352,30 +363,32 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) a.phi[tperm[s]] = acc;
+      if (lane == 0) phi[tperm[s]] = acc;
     }
   }
 }
 
 template <typename T, int M>
-static hipError_t interp_m(const InterpArgs<T> &a, int n_active, hipStream_t s) {
+static hipError_t interp_m(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int nb,
+                           hipStream_t s) {
   if (n_active == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_interp<T, M>), dim3((unsigned)n_active), dim3(InterpShape<T, M>::THREADS),
-                     0, s, a);
+  hipLaunchKernelGGL((k_interp<T, M>), dim3((unsigned)n_active, (unsigned)nb),
+                     dim3(InterpShape<T, M>::THREADS), 0, s, a, p);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_interp(const InterpArgs<T> &a, int n_active, int m, hipStream_t s) {
+hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int m, int nb,
+                         hipStream_t s) {
   switch (m) {
-    case 1: return interp_m<T, 1>(a, n_active, s);
-    case 2: return interp_m<T, 2>(a, n_active, s);
-    case 3: return interp_m<T, 3>(a, n_active, s);
-    case 4: return interp_m<T, 4>(a, n_active, s);
-    case 5: return interp_m<T, 5>(a, n_active, s);
-    case 6: return interp_m<T, 6>(a, n_active, s);
-    case 7: return interp_m<T, 7>(a, n_active, s);
-    case 8: return interp_m<T, 8>(a, n_active, s);
+    case 1: return interp_m<T, 1>(a, p, n_active, nb, s);
+    case 2: return interp_m<T, 2>(a, p, n_active, nb, s);
+    case 3: return interp_m<T, 3>(a, p, n_active, nb, s);
+    case 4: return interp_m<T, 4>(a, p, n_active, nb, s);
+    case 5: return interp_m<T, 5>(a, p, n_active, nb, s);
+    case 6: return interp_m<T, 6>(a, p, n_active, nb, s);
+    case 7: return interp_m<T, 7>(a, p, n_active, nb, s);
+    case 8: return interp_m<T, 8>(a, p, n_active, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -459,58 +472,79 @@ __device__ __forceinline__ int wrap_pos(int e, int shift, int N) {
 }
 
 // A workgroup of 128 threads transforms B = 512 / N lines (at least one) held
-// in LDS: 16 KiB (FP64) per workgroup, so many workgroups share a CU and
-// hide the global-memory latency of the pruned loads and stores.
+// in LDS: 16 KiB (FP64) per workgroup, so many workgroups share a CU and hide
+// the latency of the pruned loads and stores. Line base offsets are computed
+// once per line; elements are mapped to threads without divisions: along the
+// line when the element stride is 1, across lines otherwise (coalesced).
 constexpr int kFftThreads = 128;
 constexpr int kFftElems = 512;
+
+template <int N>
+struct FftShape {
+  static constexpr int B = (kFftElems / N) > 0 ? (kFftElems / N) : 1;     // lines per block
+  static constexpr int TPL = kFftThreads / B > 0 ? kFftThreads / B : 1;   // threads per line
+  static constexpr int PER = (B * N + kFftThreads - 1) / kFftThreads;     // elements per thread
+};
 
 template <typename T, int N>
 __global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
   using C = typename Cplx<T>::type;
-  constexpr int B = (kFftElems / N) > 0 ? (kFftElems / N) : 1;
-  constexpr int PER = (B * N + kFftThreads - 1) / kFftThreads;   // elements per thread
+  using F = FftShape<N>;
+  constexpr int B = F::B, TPL = F::TPL, PER = F::PER;
   __shared__ C buf0[B * N];
   __shared__ C buf1[B * N];
+  __shared__ int64_t in_base[B], out_base[B];
   const C *tw = reinterpret_cast<const C *>(p.tw);
   const int64_t L0 = (int64_t)blockIdx.x * B;
   const int nb = (int)min((int64_t)B, p.n_lines - L0);
   const int tid = threadIdx.x;
 
+  if (tid < nb) {
+    const int64_t L = L0 + tid;
+    const int64_t l1i = L % p.l1, l2i = L / p.l1;
+    in_base[tid] = l1i * p.in_s1 + l2i * p.in_s2 + blockIdx.y * p.in_bstride;
+    out_base[tid] = l1i * p.out_s1 + l2i * p.out_s2 + blockIdx.y * p.out_bstride;
+  }
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int j = tid + k * kFftThreads;
     if (j < B * N) { buf0[j].x = T(0); buf0[j].y = T(0); }
   }
-  // issue every global load of the thread before touching LDS
-  const int total_in = nb * p.in_cnt;
+  __syncthreads();
+
+  // thread -> (line, element) maps
+  const bool in_contig = p.in_es == 1;
+  auto map_in = [&](int k, int &b, int &e) {
+    if (in_contig) { b = tid / TPL; e = tid % TPL + k * TPL; }
+    else { b = tid % B; e = tid / B + k * (kFftThreads / B); }
+  };
+  // issue every global load (data and multiplier) before touching LDS
   C v[PER];
-  int pos[PER], bl[PER], el[PER];
+  T mu[PER];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int idx = tid + k * kFftThreads;
-    bl[k] = -1;
-    if (idx < total_in) {
-      int b, e;
-      if (p.in_es == 1) { e = idx % p.in_cnt; b = idx / p.in_cnt; }
-      else { b = idx % nb; e = idx / nb; }
-      const int64_t L = L0 + b;
-      const int64_t off = (L % p.l1) * p.in_s1 + (L / p.l1) * p.in_s2 + (int64_t)e * p.in_es;
+    int b, e;
+    map_in(k, b, e);
+    if (b < nb && e < p.in_cnt) {
+      const int64_t off = in_base[b] + (int64_t)e * p.in_es;
       if (p.in_real) { v[k].x = reinterpret_cast<const T *>(p.in)[off]; v[k].y = T(0); }
       else { v[k] = reinterpret_cast<const C *>(p.in)[off]; }
-      bl[k] = b;
-      el[k] = e;
-      pos[k] = wrap_pos(e, p.in_shift, N);
     }
+    mu[k] = T(0);
+    if (p.mul_inv && b < nb && e < p.mu_cnt)
+      mu[k] = p.mu[in_base[b] - blockIdx.y * p.in_bstride + (int64_t)e * p.in_es];
   }
-  __syncthreads();
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    if (bl[k] >= 0) {
-      buf0[bl[k] * N + pos[k]] = v[k];
-      if (p.in_hermitian && el[k] > 0) {
+    int b, e;
+    map_in(k, b, e);
+    if (b < nb && e < p.in_cnt) {
+      const int pos = wrap_pos(e, p.in_shift, N);
+      buf0[b * N + pos] = v[k];
+      if (p.in_hermitian && e > 0) {
         C c = v[k];
         c.y = -c.y;
-        buf0[bl[k] * N + (N - pos[k])] = c;
+        buf0[b * N + (N - pos)] = c;
       }
     }
   }
@@ -520,18 +554,6 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
 
   if (p.mul_inv) {
     C *oth = (res == buf0) ? buf1 : buf0;
-    const int total_mu = nb * p.mu_cnt;
-    T mu[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * kFftThreads;
-      mu[k] = T(0);
-      if (idx < total_mu) {
-        const int b = idx % nb, e = idx / nb;
-        const int64_t L = L0 + b;
-        mu[k] = p.mu[(L % p.l1) * p.in_s1 + (L / p.l1) * p.in_s2 + (int64_t)e * p.in_es];
-      }
-    }
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int j = tid + k * kFftThreads;
@@ -540,9 +562,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const int idx = tid + k * kFftThreads;
-      if (idx < total_mu) {
-        const int b = idx % nb, e = idx / nb;
+      int b, e;
+      map_in(k, b, e);
+      if (b < nb && e < p.mu_cnt) {
         const int ps = wrap_pos(e, p.mu_shift, N);
         C x = res[b * N + ps];
         x.x *= mu[k];
@@ -555,16 +577,14 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
     res = lds_fft<T, N>(oth, spare, B, -p.sign, tw);
   }
 
-  const int total_out = nb * p.out_cnt;
+  const bool out_contig = p.out_es == 1;
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
-    const int idx = tid + k * kFftThreads;
-    if (idx < total_out) {
-      int b, e;
-      if (p.out_es == 1) { e = idx % p.out_cnt; b = idx / p.out_cnt; }
-      else { b = idx % nb; e = idx / nb; }
-      const int64_t L = L0 + b;
-      const int64_t off = (L % p.l1) * p.out_s1 + (L / p.l1) * p.out_s2 + (int64_t)e * p.out_es;
+    int b, e;
+    if (out_contig) { b = tid / TPL; e = tid % TPL + k * TPL; }
+    else { b = tid % B; e = tid / B + k * (kFftThreads / B); }
+    if (b < nb && e < p.out_cnt) {
+      const int64_t off = out_base[b] + (int64_t)e * p.out_es;
       const C x = res[b * N + wrap_pos(e, p.out_shift, N)];
       if (p.out_real) reinterpret_cast<T *>(p.out)[off] = x.x;
       else reinterpret_cast<C *>(p.out)[off] = x;
@@ -573,26 +593,27 @@ __global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
 }
 
 template <typename T, int N>
-static hipError_t fft_n(const FftPass<T> &p, hipStream_t s) {
-  constexpr int B = (kFftElems / N) > 0 ? (kFftElems / N) : 1;
+static hipError_t fft_n(const FftPass<T> &p, int nb, hipStream_t s) {
+  constexpr int B = FftShape<N>::B;
   if (p.n_lines == 0) return hipSuccess;
   const int64_t blocks = (p.n_lines + B - 1) / B;
-  hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)blocks), dim3(kFftThreads), 0, s, p);
+  hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)blocks, (unsigned)nb), dim3(kFftThreads), 0, s,
+                     p);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fft(const FftPass<T> &p, int N, hipStream_t s) {
+hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s) {
   switch (N) {
-    case 8: return fft_n<T, 8>(p, s);
-    case 16: return fft_n<T, 16>(p, s);
-    case 32: return fft_n<T, 32>(p, s);
-    case 64: return fft_n<T, 64>(p, s);
-    case 128: return fft_n<T, 128>(p, s);
-    case 256: return fft_n<T, 256>(p, s);
-    case 512: return fft_n<T, 512>(p, s);
-    case 1024: return fft_n<T, 1024>(p, s);
-    case 2048: return fft_n<T, 2048>(p, s);
+    case 8: return fft_n<T, 8>(p, nb, s);
+    case 16: return fft_n<T, 16>(p, nb, s);
+    case 32: return fft_n<T, 32>(p, nb, s);
+    case 64: return fft_n<T, 64>(p, nb, s);
+    case 128: return fft_n<T, 128>(p, nb, s);
+    case 256: return fft_n<T, 256>(p, nb, s);
+    case 512: return fft_n<T, 512>(p, nb, s);
+    case 1024: return fft_n<T, 1024>(p, nb, s);
+    case 2048: return fft_n<T, 2048>(p, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -680,18 +701,22 @@ hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2
 }
 
 // explicit instantiations
-template hipError_t launch_charges<float>(const double *, const double *, const int32_t *, float *,
-                                          int64_t, hipStream_t);
-template hipError_t launch_charges<double>(const double *, const double *, const int32_t *,
-                                           double *, int64_t, hipStream_t);
+template hipError_t launch_charges<float>(const BatchPtrs &, const double *, const int32_t *, float *,
+                                          int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_charges<double>(const BatchPtrs &, const double *, const int32_t *,
+                                           double *, int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
-                                         const SpreadReduceArgs<float> &, int, int, hipStream_t);
+                                         const SpreadReduceArgs<float> &, int, int, int,
+                                         hipStream_t);
 template hipError_t launch_spread<double>(const SpreadBinsArgs<double> &,
-                                          const SpreadReduceArgs<double> &, int, int, hipStream_t);
-template hipError_t launch_interp<float>(const InterpArgs<float> &, int, int, hipStream_t);
-template hipError_t launch_interp<double>(const InterpArgs<double> &, int, int, hipStream_t);
-template hipError_t launch_fft<float>(const FftPass<float> &, int, hipStream_t);
-template hipError_t launch_fft<double>(const FftPass<double> &, int, hipStream_t);
+                                          const SpreadReduceArgs<double> &, int, int, int,
+                                          hipStream_t);
+template hipError_t launch_interp<float>(const InterpArgs<float> &, const BatchPtrs &, int, int,
+                                         int, hipStream_t);
+template hipError_t launch_interp<double>(const InterpArgs<double> &, const BatchPtrs &, int, int,
+                                          int, hipStream_t);
+template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
+template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,
                                      const double *, int32_t, const int32_t *, const int32_t *,
                                      const int32_t *, double, hipStream_t);

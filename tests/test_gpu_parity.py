@@ -195,3 +195,31 @@ def test_timing_reports_every_stage():
     assert cnt == 40
     assert all(v > 0 for v in ms.values()), ms
     G.close()
+
+
+@pytest.mark.parametrize("prec", [slp.FP64, slp.FP32])
+def test_multi_density_batch_equals_single(prec):
+    """Consecutive items on one geometry share every launch (grid y = item):
+    70 items on one sphere run as 64 + 6, interleaved with another geometry."""
+    log(f"case multi-density batch prec={prec}")
+    wla = sphere_random(2, 21, 64, 5)
+    wlb = sphere_random(1, 22, 32, 3)
+    Ga, Gb = make_geometry(wla, 5, prec), make_geometry(wlb, 3, prec)
+    rng = np.random.default_rng(4)
+    geoms, dens, phis = [], [], []
+    for k in range(71):
+        G, wl = (Gb, wlb) if k == 35 else (Ga, wla)
+        geoms.append(G.handle)
+        dens.append(torch.as_tensor(rng.normal(size=wl.n_src)).cuda())
+        phis.append(torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda"))
+    slp.eval_batched(geoms, dens, phis)
+    torch.cuda.synchronize()
+    tol = 1e-14 if prec == slp.FP64 else 1e-6
+    for k in (0, 1, 34, 35, 36, 63, 64, 70):
+        G = Gb if k == 35 else Ga
+        ref = G.solve(dens[k])
+        torch.cuda.synchronize()
+        assert rel_l2(phis[k].cpu().numpy(), ref.cpu().numpy()) <= tol, k
+    assert all(torch.isfinite(p).all().item() for p in phis)
+    Ga.close()
+    Gb.close()
