@@ -79,8 +79,6 @@ def algorithmic_units(stage, info, m, esz):
         return R[2] * Kx * (Ky * c + R[1] * c), "byte", "hbm"
     if stage == "fft_x_inv":
         return R[2] * R[1] * (Kx * c + R[0] * esz), "byte", "hbm"
-    if stage == "charges":
-        return info["n_src"] * (8 + 8 + 4 + esz), "byte", "hbm"
     raise KeyError(stage)
 
 

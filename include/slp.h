@@ -108,9 +108,12 @@ int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes,
 int slp_geometry_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,
                               int64_t n_tris, const slp_params *p, int64_t *bytes);
 
-/* Charges q_k = w_k g_k for the next evaluation (eq. naive_gridding).
+/* Density for the next slp_eval_single_layer on this context.
  *   dens : device float64 [3 * n_tris], density at the quadrature points in
- *          long-index order k = j + s*M. Read by a kernel on `stream`. */
+ *          long-index order k = j + s*M. Only the pointer is recorded: the
+ *          gridding of the next evaluation forms the charges q_k = w_k g_k
+ *          (eq. naive_gridding) from it, so it must stay valid until that
+ *          evaluation has run on its stream. */
 int slp_set_density(slp_geom *g, const double *dens, void *stream);
 
 /* phi_s at every node for the charges of the last slp_set_density
@@ -129,11 +132,12 @@ int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *
 
 int slp_geom_get_info(const slp_geom *g, slp_geom_info *info);
 
-/* Per-stage device timing. When enabled, eval records HIP events around each
- * stage on the eval stream: 0 charges, 1 spread, 2 FFT x fwd, 3 FFT y fwd,
- * 4 FFT z (fwd, multiply, inv), 5 FFT y inv, 6 FFT x inv, 7 interpolation.
- * slp_stage_times synchronises the last recorded eval and accumulates into
- * ms[8] (summed over evals since the last reset) and *count (evals). */
+/* Per-stage device timing. When enabled, every evaluation (one single eval, or
+ * one launch group of slp_eval_batched) records HIP events around each stage on
+ * its stream: 0 gridding (charges included), 1 FFT x fwd, 2 FFT y fwd,
+ * 3 FFT z (fwd, multiply, inv), 4 FFT y inv, 5 FFT x inv, 6 interpolation.
+ * slp_stage_times synchronises the recorded evaluations and accumulates into
+ * ms[7] (summed since the last reset) and *count (evaluations). */
 int slp_set_timing(slp_geom *g, int32_t enable);
 int slp_stage_times(slp_geom *g, double *ms, int64_t *count, int32_t reset);
 

@@ -21,8 +21,8 @@ __all__ = [
 ]
 
 FP64, FP32 = 0, 1
-STAGES = ("charges", "spread", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv",
-          "fft_x_inv", "interp")
+STAGES = ("spread", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv", "fft_x_inv",
+          "interp")
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libslp.so")
 
@@ -282,7 +282,7 @@ def set_timing(geom, enable=True):
 
 
 def stage_times(geom, reset=False):
-    ms = (ctypes.c_double * 8)()
+    ms = (ctypes.c_double * len(STAGES))()
     cnt = ctypes.c_int64(0)
     _check(load_library().slp_stage_times(_VP(geom), ms, ctypes.byref(cnt), int(bool(reset))))
     return dict(zip(STAGES, list(ms))), cnt.value

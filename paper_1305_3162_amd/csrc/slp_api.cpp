@@ -100,7 +100,8 @@ struct slp_geom {
   int32_t terms_kept = 0;
   int32_t n_slots = 0;           // non-empty source bins
   int32_t cap = 1;               // batch items the per-item buffers hold
-  int64_t item_elems[6]{};       // per item: q, scratch, grid_a, S1 (complex), S2 (complex), grid_g
+  int64_t item_elems[5]{};       // per item: scratch, grid_a, S1 (complex), S2 (complex), grid_g
+  const double *dens = nullptr;  // density of the next single evaluation (caller's device buffer)
   int32_t n_tgt_tiles = 0;       // tiles holding targets
   // device buffers
   void *src_frac = nullptr;
@@ -111,7 +112,6 @@ struct slp_geom {
   int32_t *runs = nullptr;
   int32_t *slot_of_tile = nullptr;
   void *scratch = nullptr;
-  void *q = nullptr;
   int32_t *tgt_cell = nullptr;
   void *tgt_frac = nullptr;
   int32_t *tgt_perm = nullptr;
@@ -129,11 +129,11 @@ struct slp_geom {
   static constexpr int kRing = 32;
   bool timing = false;
   bool ev_ready = false;
-  bool density_marked = false;
-  hipEvent_t ev[kRing][9]{};
+  static constexpr int kStages = 7;
+  hipEvent_t ev[kRing][kStages + 1]{};
   bool used[kRing]{};
   int cur = 0;
-  double acc_ms[8]{};
+  double acc_ms[kStages]{};
   int64_t count = 0;
   hipEvent_t *evs() { return ev[cur]; }
 
@@ -247,20 +247,20 @@ int upload_twiddles(slp_geom *G, hipStream_t st, std::vector<std::vector<T>> &ho
 int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
   if (nb <= G->cap) return SLP_OK;
   HIP_TRY(hipStreamSynchronize(st));
-  void **bufs[6] = {&G->q, &G->scratch, &G->grid_a, &G->S1, &G->S2, &G->grid_g};
+  void **bufs[5] = {&G->scratch, &G->grid_a, &G->S1, &G->S2, &G->grid_g};
   const size_t e = G->esz();
-  const size_t per[6] = {e, e, e, 2 * e, 2 * e, e};
-  for (int i = 0; i < 6; ++i) {
+  const size_t per[5] = {e, e, 2 * e, 2 * e, e};
+  for (int i = 0; i < 5; ++i) {
     G->release(*bufs[i]);
     *bufs[i] = nullptr;
   }
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 5; ++i)
     if (G->alloc(bufs[i], (size_t)G->item_elems[i] * per[i] * nb) != hipSuccess) {
       // leave a usable single-item context behind
-      for (int k = 0; k < 6; ++k)
+      for (int k = 0; k < 5; ++k)
         if (*bufs[k]) { G->release(*bufs[k]); *bufs[k] = nullptr; }
       bool ok = true;
-      for (int k = 0; k < 6; ++k) ok = ok && G->alloc(bufs[k], (size_t)G->item_elems[k] * per[k]) == hipSuccess;
+      for (int k = 0; k < 5; ++k) ok = ok && G->alloc(bufs[k], (size_t)G->item_elems[k] * per[k]) == hipSuccess;
       G->cap = 1;
       return fail(ok ? SLP_ENOMEM : SLP_EDEVICE, "batch buffers for %d items: allocation failed", nb);
     }
@@ -269,40 +269,32 @@ int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
 }
 
 template <typename T>
-int launch_charges_items(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
-  HIP_TRY(slp::launch_charges<T>(ptrs, G->src_w, G->src_perm, static_cast<T *>(G->q), G->n_src,
-                                 G->item_elems[0], nb, st));
-  return SLP_OK;
-}
-
-template <typename T>
 int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
   const bool tm = G->timing;
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
-  // spread
+  // spread (the charges q = w g are formed inside the gridding)
   {
     slp::SpreadBinsArgs<T> a{};
     a.frac = static_cast<const T *>(G->src_frac);
-    a.q = static_cast<const T *>(G->q);
+    a.w = G->src_w;
+    a.perm = G->src_perm;
     a.bin_chunks = G->bin_chunks;
     a.chunks = G->chunks;
     a.runs = G->runs;
     a.scratch = static_cast<T *>(G->scratch);
     a.ns = G->n_src;
-    a.q_bstride = G->item_elems[0];
-    a.scratch_bstride = G->item_elems[1];
+    a.scratch_bstride = G->item_elems[0];
     a.inv_b = (T)(1.0 / G->b);
     a.step_ratio = (T)std::exp(-2.0 / G->b);
     slp::SpreadReduceArgs<T> r{};
     r.scratch = static_cast<const T *>(G->scratch);
     r.slot_of_tile = G->slot_of_tile;
     r.grid = static_cast<T *>(G->grid_a);
-    r.scratch_bstride = G->item_elems[1];
-    r.grid_bstride = G->item_elems[2];
+    r.scratch_bstride = G->item_elems[0];
+    r.grid_bstride = G->item_elems[1];
     for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
-    HIP_TRY(slp::launch_spread<T>(a, r, G->n_slots, G->m, nb, st));
+    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_slots, G->m, nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
   const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
   const int64_t Px = G->P[0], Py = G->P[1];
   const int64_t Kx = G->K[0], Ky = G->K[1], Kz = G->K[2];
@@ -315,10 +307,10 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_s1 = Px; p.in_s2 = Py * Px; p.in_es = 1; p.in_cnt = (int)Rx; p.in_shift = G->lo[0];
     p.out_s1 = Kx; p.out_s2 = Ry * Kx; p.out_es = 1; p.out_cnt = (int)Kx; p.out_shift = 0;
     p.sign = -1; p.in_real = 1;
-    p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[3];
+    p.in_bstride = G->item_elems[1]; p.out_bstride = G->item_elems[2];
     HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
   // y forward: region y -> ky = -n_y/2..n_y/2
   {
     slp::FftPass<T> p{};
@@ -327,10 +319,10 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_s1 = 1; p.in_s2 = Ry * Kx; p.in_es = Kx; p.in_cnt = (int)Ry; p.in_shift = G->lo[1];
     p.out_s1 = 1; p.out_s2 = Ky * Kx; p.out_es = Kx; p.out_cnt = (int)Ky; p.out_shift = -ny / 2;
     p.sign = -1;
-    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[4];
+    p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[3];
     HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
   // z forward, multiply by mu on kz = -n_z/2..n_z/2, z inverse back to the region
   {
     slp::FftPass<T> p{};
@@ -341,10 +333,10 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
     p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
     p.sign = -1; p.mul_inv = 1;
-    p.in_bstride = G->item_elems[4]; p.out_bstride = G->item_elems[4];
+    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[3];
     HIP_TRY(slp::launch_fft<T>(p, G->N[2], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
   // y inverse: ky -> region y
   {
     slp::FftPass<T> p{};
@@ -353,10 +345,10 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_s1 = 1; p.in_s2 = Ky * Kx; p.in_es = Kx; p.in_cnt = (int)Ky; p.in_shift = -ny / 2;
     p.out_s1 = 1; p.out_s2 = Ry * Kx; p.out_es = Kx; p.out_cnt = (int)Ry; p.out_shift = G->lo[1];
     p.sign = +1;
-    p.in_bstride = G->item_elems[4]; p.out_bstride = G->item_elems[3];
+    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[2];
     HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
   // x inverse (Hermitian half spectrum -> real region rows)
   {
     slp::FftPass<T> p{};
@@ -366,11 +358,11 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_hermitian = 1;
     p.out_s1 = Rx; p.out_s2 = Ry * Rx; p.out_es = 1; p.out_cnt = (int)Rx; p.out_shift = G->lo[0];
     p.out_real = 1; p.sign = +1;
-    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[5];
+    p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[4];
     HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
   (void)nx;
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
   {
     slp::InterpArgs<T> a{};
     a.cell = G->tgt_cell;
@@ -379,7 +371,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     a.tile_start = G->tgt_tile_start;
     a.active = G->tgt_active;
     a.g = static_cast<const T *>(G->grid_g);
-    a.g_bstride = G->item_elems[5];
+    a.g_bstride = G->item_elems[4];
     for (int i = 0; i < 3; ++i) {
       a.R[i] = G->R[i];
       a.tiles[i] = G->tiles[i];
@@ -389,7 +381,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
   }
   if (tm) {
-    HIP_TRY(hipEventRecord(G->evs()[8], st));
+    HIP_TRY(hipEventRecord(G->evs()[slp_geom::kStages], st));
     G->used[G->cur] = true;
     G->cur = (G->cur + 1) % slp_geom::kRing;
   }
@@ -398,8 +390,8 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
 
 int collect_one(slp_geom *G, int r) {
   if (!G->used[r]) return SLP_OK;
-  HIP_TRY(hipEventSynchronize(G->ev[r][8]));
-  for (int i = 0; i < 8; ++i) {
+  HIP_TRY(hipEventSynchronize(G->ev[r][slp_geom::kStages]));
+  for (int i = 0; i < slp_geom::kStages; ++i) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, G->ev[r][i], G->ev[r][i + 1]));
     G->acc_ms[i] += ms;
@@ -681,12 +673,11 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   const int64_t S2n = (int64_t)G->R[2] * G->K[1] * G->K[0];
   const int64_t gn = (int64_t)G->R[0] * G->R[1] * G->R[2];
   const int64_t mun = (int64_t)G->K[0] * G->K[1] * G->K[2];
-  G->item_elems[0] = Ms;
-  G->item_elems[1] = (int64_t)G->n_slots * slp::pad_cells(G->m);
-  G->item_elems[2] = Gsz;
-  G->item_elems[3] = S1n;
-  G->item_elems[4] = S2n;
-  G->item_elems[5] = gn;
+  G->item_elems[0] = (int64_t)G->n_slots * slp::pad_cells(G->m);
+  G->item_elems[1] = Gsz;
+  G->item_elems[2] = S1n;
+  G->item_elems[3] = S2n;
+  G->item_elems[4] = gn;
   struct AllocReq {
     void **dst;
     size_t bytes;
@@ -702,7 +693,6 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
       {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
       {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
-      {&G->q, (size_t)Ms * e},
       {reinterpret_cast<void **>(&G->tgt_cell), (size_t)(3 * n_nodes) * 4},
       {&G->tgt_frac, (size_t)(3 * n_nodes) * e},
       {reinterpret_cast<void **>(&G->tgt_perm), (size_t)n_nodes * 4},
@@ -809,27 +799,21 @@ int slp_geometry_device_bytes(const double *nodes, int64_t n_nodes, const int32_
 
 int slp_set_density(slp_geom *G, const double *dens, void *stream) {
   if (!G || !dens) return fail(SLP_EINVAL, "geometry and density must be non-NULL");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (G->timing) {
-    int rc = begin_timed(G, st);
-    if (rc) return rc;
-    G->density_marked = true;
-  }
-  slp::BatchPtrs ptrs{};
-  ptrs.dens[0] = dens;
-  return G->prec == SLP_FP64 ? launch_charges_items<double>(G, ptrs, 1, st)
-                             : launch_charges_items<float>(G, ptrs, 1, st);
+  (void)stream;
+  G->dens = dens;
+  return SLP_OK;
 }
 
 int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
   if (!G || !phi) return fail(SLP_EINVAL, "geometry and phi must be non-NULL");
+  if (!G->dens) return fail(SLP_EINVAL, "no density set (slp_set_density)");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (G->timing && !G->density_marked) {
+  if (G->timing) {
     int rc = begin_timed(G, st);
     if (rc) return rc;
   }
-  G->density_marked = false;
   slp::BatchPtrs ptrs{};
+  ptrs.dens[0] = G->dens;
   ptrs.phi[0] = phi;
   return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, 1, st) : run_eval<float>(G, ptrs, 1, st);
 }
@@ -858,10 +842,7 @@ int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *
       rc = begin_timed(G, st);
       if (rc) return rc;
     }
-    G->density_marked = false;
-    rc = G->prec == SLP_FP64 ? launch_charges_items<double>(G, ptrs, nb, st)
-                             : launch_charges_items<float>(G, ptrs, nb, st);
-    if (!rc) rc = G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st) : run_eval<float>(G, ptrs, nb, st);
+    rc = G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st) : run_eval<float>(G, ptrs, nb, st);
     if (rc) return rc;
     b = e;
   }
@@ -894,7 +875,6 @@ int slp_set_timing(slp_geom *G, int32_t enable) {
     if (rc) return rc;
   }
   G->timing = enable != 0;
-  G->density_marked = false;
   return SLP_OK;
 }
 
@@ -902,7 +882,7 @@ int slp_stage_times(slp_geom *G, double *ms, int64_t *count, int32_t reset) {
   if (!G || !ms || !count) return fail(SLP_EINVAL, "NULL argument");
   int rc = collect_timing(G);
   if (rc) return rc;
-  for (int i = 0; i < 8; ++i) ms[i] = G->acc_ms[i];
+  for (int i = 0; i < slp_geom::kStages; ++i) ms[i] = G->acc_ms[i];
   *count = G->count;
   if (reset) {
     for (double &v : G->acc_ms) v = 0.0;

@@ -28,13 +28,14 @@ struct BatchPtrs {
 template <typename T>
 struct SpreadBinsArgs {
   const T *frac;         // [3][ns] t - floor(t), sorted order
-  const T *q;            // [ns] charges, sorted order
+  const double *w;       // [ns] quadrature weights, sorted order
+  const int32_t *perm;   // [ns] sorted -> caller (long) index of the density
   const int4 *bin_chunks;    // [n_slots] {first chunk, end chunk, tile id, 0}
   const int4 *chunks;        // {first source, source count, first run, run count}
   const int32_t *runs;       // cell x | y << 3 | z << 6 | offset in chunk << 9 | count << 19
   T *scratch;            // [n_slots][PD^3]
   int64_t ns;
-  int64_t q_bstride, scratch_bstride;   // per batch item (blockIdx.y)
+  int64_t scratch_bstride;   // per batch item (blockIdx.y)
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
   T step_ratio;          // exp(-2 / b): ratio of consecutive weight ratios
 };
@@ -91,12 +92,10 @@ struct FftPass {
 };
 
 // Every launch covers nb batch items (gridDim.y = nb, 1 <= nb <= kMaxBatch).
+// The gridding forms the charges q = w g itself from the density pointers.
 template <typename T>
-hipError_t launch_charges(const BatchPtrs &p, const double *w, const int32_t *perm, T *q,
-                          int64_t ns, int64_t q_bstride, int nb, hipStream_t s);
-template <typename T>
-hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
-                         int m, int nb, hipStream_t s);
+hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
+                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s);
 template <typename T>
 hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int m, int nb,
                          hipStream_t s);

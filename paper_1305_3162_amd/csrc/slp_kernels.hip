@@ -1,8 +1,8 @@
 // Device code for the smooth-part single-layer potential (gfx950).
 //
 // Stages (Sec. 3, Alg. 1 computation phase, eq. BEM_NFFT_compact2):
-//   charges  q = w * g gathered into tile order             (eq. naive_gridding)
-//   spread   a_r = sum_k q_k prod_q psi(t_kq - r_q)         (eq. gridding)
+//   spread   a_r = sum_k q_k prod_q psi(t_kq - r_q), with the charges
+//            q_k = w_k g_k formed while staging          (eq. gridding, naive_gridding)
 //   fft      pruned 3-D FFT, multiply by mu, inverse FFT    (eq. FFT, deconv, Alg. 1)
 //   interp   phi_i = sum_r g_r prod_q psi(t_iq - r_q)       (type-2 NFFT)
 // mu folds the two window deconvolutions, c_l(N_s), the Hermitian weights of
@@ -22,26 +22,6 @@ struct Cplx<double> { using type = double2; };
 
 __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
-
-// ---------------------------------------------------------------- charges ---
-template <typename T>
-__global__ void k_charges(BatchPtrs ptrs, const double *__restrict__ w,
-                          const int32_t *__restrict__ perm, T *__restrict__ q, int64_t ns,
-                          int64_t q_bstride) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int item = blockIdx.y;
-  if (i < ns) q[item * q_bstride + i] = (T)(w[i] * ptrs.dens[item][perm[i]]);
-}
-
-template <typename T>
-hipError_t launch_charges(const BatchPtrs &p, const double *w, const int32_t *perm, T *q,
-                          int64_t ns, int64_t q_bstride, int nb, hipStream_t s) {
-  if (ns == 0) return hipSuccess;
-  int64_t blocks = (ns + 255) / 256;
-  hipLaunchKernelGGL(k_charges<T>, dim3((unsigned)blocks, (unsigned)nb), dim3(256), 0, s, p, w,
-                     perm, q, ns, q_bstride);
-  return hipGetLastError();
-}
 
 // ----------------------------------------------------------------- spread ---
 // Phase A (one workgroup of 8 or 16 waves per non-empty bin): the bin's sources are
@@ -83,7 +63,8 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a) {
+__global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a,
+                                                                               BatchPtrs ptrs) {
   using S = SpreadShape<T, M>;
   constexpr int W = S::W, PD = S::PD, NP = S::NP, CH = S::CH;
   // The block is accumulated in FP64 in both precisions: LDS FP64 atomic adds
@@ -96,7 +77,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
 
   const int slot = blockIdx.x;
   const int4 bc = a.bin_chunks[slot];
-  const T *qv = a.q + blockIdx.y * a.q_bstride;
+  const double *dens = ptrs.dens[blockIdx.y];
   for (int i = threadIdx.x; i < S::P3; i += S::THREADS) pad[i] = 0.0;
 
   const int tid = threadIdx.x;
@@ -122,7 +103,8 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
       const int i = tid + k * S::THREADS;
       if (i < 4 * ch.y) {
         const int comp = i / ch.y, sl = i - comp * ch.y;
-        v[k] = comp < 3 ? a.frac[comp * ns + ch.x + sl] : qv[ch.x + sl];
+        const int64_t src = (int64_t)ch.x + sl;
+        v[k] = comp < 3 ? a.frac[comp * ns + src] : (T)(a.w[src] * dens[a.perm[src]]);
       }
     }
     if (tid < ch.w) rv = a.runs[ch.z + tid];
@@ -228,12 +210,12 @@ __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
 }
 
 template <typename T, int M>
-static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
-                           int nb, hipStream_t s) {
+static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
+                           const BatchPtrs &p, int n_slots, int nb, hipStream_t s) {
   using S = SpreadShape<T, M>;
   if (n_slots > 0)
     hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots, (unsigned)nb),
-                       dim3(S::THREADS), 0, s, a);
+                       dim3(S::THREADS), 0, s, a, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
@@ -243,17 +225,17 @@ static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T>
 }
 
 template <typename T>
-hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r, int n_slots,
-                         int m, int nb, hipStream_t s) {
+hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
+                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s) {
   switch (m) {
-    case 1: return spread_m<T, 1>(a, r, n_slots, nb, s);
-    case 2: return spread_m<T, 2>(a, r, n_slots, nb, s);
-    case 3: return spread_m<T, 3>(a, r, n_slots, nb, s);
-    case 4: return spread_m<T, 4>(a, r, n_slots, nb, s);
-    case 5: return spread_m<T, 5>(a, r, n_slots, nb, s);
-    case 6: return spread_m<T, 6>(a, r, n_slots, nb, s);
-    case 7: return spread_m<T, 7>(a, r, n_slots, nb, s);
-    case 8: return spread_m<T, 8>(a, r, n_slots, nb, s);
+    case 1: return spread_m<T, 1>(a, r, p, n_slots, nb, s);
+    case 2: return spread_m<T, 2>(a, r, p, n_slots, nb, s);
+    case 3: return spread_m<T, 3>(a, r, p, n_slots, nb, s);
+    case 4: return spread_m<T, 4>(a, r, p, n_slots, nb, s);
+    case 5: return spread_m<T, 5>(a, r, p, n_slots, nb, s);
+    case 6: return spread_m<T, 6>(a, r, p, n_slots, nb, s);
+    case 7: return spread_m<T, 7>(a, r, p, n_slots, nb, s);
+    case 8: return spread_m<T, 8>(a, r, p, n_slots, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -701,16 +683,12 @@ hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2
 }
 
 // explicit instantiations
-template hipError_t launch_charges<float>(const BatchPtrs &, const double *, const int32_t *, float *,
-                                          int64_t, int64_t, int, hipStream_t);
-template hipError_t launch_charges<double>(const BatchPtrs &, const double *, const int32_t *,
-                                           double *, int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
-                                         const SpreadReduceArgs<float> &, int, int, int,
-                                         hipStream_t);
+                                         const SpreadReduceArgs<float> &, const BatchPtrs &, int,
+                                         int, int, hipStream_t);
 template hipError_t launch_spread<double>(const SpreadBinsArgs<double> &,
-                                          const SpreadReduceArgs<double> &, int, int, int,
-                                          hipStream_t);
+                                          const SpreadReduceArgs<double> &, const BatchPtrs &,
+                                          int, int, int, hipStream_t);
 template hipError_t launch_interp<float>(const InterpArgs<float> &, const BatchPtrs &, int, int,
                                          int, hipStream_t);
 template hipError_t launch_interp<double>(const InterpArgs<double> &, const BatchPtrs &, int, int,
