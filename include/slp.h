@@ -116,6 +116,20 @@ int slp_geometry_device_bytes(const double *nodes, int64_t n_nodes, const int32_
  *          evaluation has run on its stream. */
 int slp_set_density(slp_geom *g, const double *dens, void *stream);
 
+/* Density of the paper's P1 ansatz (Sec. 2): g = m.n - dphi1/dn with m.n
+ * projected onto element-wise constants by its integral mean over each flat
+ * triangle (for affine m the mean of the three vertex values, dotted with the
+ * unit outward normal from the vertex order), and dphi1/dn constant per
+ * triangle. Every quadrature source of triangle j carries g_j. The density is
+ * formed on `stream` in a buffer the context owns (allocated at setup) and
+ * replaces any pointer recorded by slp_set_density for the next evaluation.
+ *   m_nodes  : device float64 [n_nodes][3], nodal magnetisation (caller's node order)
+ *   dphi1_dn : device float64 [n_tris], interior normal derivative of phi_1 per
+ *              triangle, or NULL for zero (divergence-free m: phi_1 = 0)
+ * Both need only stay valid until the call's kernel has run on `stream`. */
+int slp_set_density_from_m(slp_geom *g, const double *m_nodes, const double *dphi1_dn,
+                           void *stream);
+
 /* phi_s at every node for the charges of the last slp_set_density
  * (computation phase of Alg. 1, smooth part).
  *   phi : device float64 [n_nodes], written in the caller's node order,
@@ -132,19 +146,22 @@ int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *
 
 int slp_geom_get_info(const slp_geom *g, slp_geom_info *info);
 
-/* Per-stage device timing. When enabled, every evaluation (one single eval, or
- * one launch group of slp_eval_batched) records HIP events around each stage on
- * its stream: 0 gridding (charges included), 1 FFT x fwd, 2 FFT y fwd,
- * 3 FFT z (fwd, multiply, inv), 4 FFT y inv, 5 FFT x inv, 6 interpolation.
- * slp_stage_times synchronises the recorded evaluations and accumulates into
- * ms[7] (summed since the last reset) and *count (evaluations). */
-int slp_set_timing(slp_geom *g, int32_t enable);
+/* Per-stage device timing. With every = k >= 1, every k-th evaluation (one
+ * single eval, or one launch group of slp_eval_batched) records HIP events
+ * around each stage on its stream: 0 gridding into per-bin blocks (charges
+ * included), 1 sum of the blocks into the grid, 2 FFT x fwd, 3 FFT y fwd,
+ * 4 FFT z (fwd, multiply, inv), 5 FFT y inv, 6 FFT x inv, 7 interpolation. Sampling keeps the cost of the event packets off the other
+ * evaluations; every = 0 switches timing off. slp_stage_times synchronises the
+ * recorded evaluations and accumulates into ms[8] (summed since the last reset)
+ * and *count (recorded evaluations). */
+int slp_set_timing(slp_geom *g, int32_t every);
 int slp_stage_times(slp_geom *g, double *ms, int64_t *count, int32_t reset);
 
 /* Copy an intermediate array of the last evaluation to a device buffer, for
  * stage-by-stage comparison (which: 0 = spread grid, region [P_z][P_y][P_x] with
- * P = 8*tiles; 1 = grid after the inverse FFT, [extent_z][extent_y][extent_x]).
- * Values are in the context's precision; dst must hold the array. */
+ * P = 8*tiles; 1 = grid after the inverse FFT, [extent_z][extent_y][extent_x];
+ * 2 = the float64 [3 n_tris] density formed by slp_set_density_from_m).
+ * Values of 0 and 1 are in the context's precision; dst must hold the array. */
 int slp_debug_copy(const slp_geom *g, int32_t which, void *dst, size_t dst_bytes, void *stream);
 
 /* Exponential sum by the trapezoidal rule on 1/r = 2/sqrt(pi) int exp(-r^2 e^{2u} + u) du

@@ -59,3 +59,25 @@ def scaling(nodes, grid):
 def to_torus(x, c, s):
     """x~ = S (x - c)."""
     return (np.asarray(x, dtype=np.float64) - c) * s
+
+
+def density_p1(nodes, tris, m_nodes, dphi1_dn=None):
+    """Element-constant density g_j = (1/|S_j|) int_{S_j} m.n - dphi1/dn_j of the P1
+    ansatz (Sec. 2): m is the affine nodal interpolant on each flat triangle, its
+    normal component is projected onto constants by the integral mean, and the
+    normal derivative of phi_1 is already constant per triangle. The integral is
+    taken with the degree-2 rule of `quadrature`, exact for affine integrands.
+    Returns g_k for the long index k = j + s*M (the same value for s = 0, 1, 2)."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    m_nodes = np.asarray(m_nodes, dtype=np.float64)
+    M = tris.shape[0]
+    area, nrm = triangle_areas_normals(nodes, tris)
+    integral = np.zeros(M)
+    for s in range(3):
+        m_at_y = (_B[s, 0] * m_nodes[tris[:, 0]] + _B[s, 1] * m_nodes[tris[:, 1]]
+                  + _B[s, 2] * m_nodes[tris[:, 2]])
+        integral += area / 3.0 * (m_at_y * nrm).sum(axis=1)
+    g = integral / area
+    if dphi1_dn is not None:
+        g = g - np.asarray(dphi1_dn, dtype=np.float64)
+    return np.tile(g, 3)

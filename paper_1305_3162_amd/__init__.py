@@ -14,14 +14,14 @@ import numpy as np
 
 __all__ = [
     "SlpError", "load_library", "expsum_sinc", "setup_geometry", "set_density",
-    "eval_single_layer", "eval_batched", "geom_get_info", "set_timing", "stage_times",
+    "set_density_from_m", "eval_single_layer", "eval_batched", "geom_get_info", "set_timing", "stage_times",
     "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "STAGES",
     "geometry_device_bytes", "server_create", "server_add_geometry", "server_submit",
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
 ]
 
 FP64, FP32 = 0, 1
-STAGES = ("spread", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv", "fft_x_inv",
+STAGES = ("spread_bins", "spread_reduce", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv", "fft_x_inv",
           "interp")
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libslp.so")
@@ -75,6 +75,7 @@ def load_library():
         "slp_setup_geometry": [ctypes.POINTER(_VP), _VP, ctypes.c_int64, _VP, ctypes.c_int64,
                                ctypes.POINTER(Params), _VP],
         "slp_set_density": [_VP, _VP, _VP],
+        "slp_set_density_from_m": [_VP, _VP, _VP, _VP],
         "slp_eval_single_layer": [_VP, _VP, _VP],
         "slp_eval_batched": [_VP, _VP, _VP, ctypes.c_int32, _VP],
         "slp_geom_get_info": [_VP, ctypes.POINTER(GeomInfo)],
@@ -245,6 +246,15 @@ def set_density(geom, dens, stream=None):
                                           _stream_ptr(stream)))
 
 
+def set_density_from_m(geom, m_nodes, dphi1_dn=None, stream=None):
+    """Element-constant density m.n - dphi1/dn from a nodal magnetisation, formed on
+    the device (m_nodes: CUDA float64 [n_nodes, 3]; dphi1_dn: [n_tris] or None)."""
+    info = geom_get_info(geom)
+    mp = _dev_f64(m_nodes, 3 * info["n_nodes"], "m_nodes")
+    dp = None if dphi1_dn is None else _dev_f64(dphi1_dn, info["n_tris"], "dphi1_dn")
+    _check(load_library().slp_set_density_from_m(_VP(geom), mp, dp, _stream_ptr(stream)))
+
+
 def eval_single_layer(geom, phi, stream=None):
     info = geom_get_info(geom)
     _check(load_library().slp_eval_single_layer(_VP(geom), _dev_f64(phi, info["n_nodes"], "phi"),
@@ -277,8 +287,9 @@ def geom_get_info(geom):
             "tiles": list(gi.tiles), "device_bytes": gi.device_bytes}
 
 
-def set_timing(geom, enable=True):
-    _check(load_library().slp_set_timing(_VP(geom), int(bool(enable))))
+def set_timing(geom, every=1):
+    """Record stage events on every `every`-th evaluation (0 or False: off)."""
+    _check(load_library().slp_set_timing(_VP(geom), int(every)))
 
 
 def stage_times(geom, reset=False):
@@ -313,6 +324,9 @@ class Geometry:
 
     def set_density(self, dens, stream=None):
         set_density(self.handle, dens, stream)
+
+    def set_density_from_m(self, m_nodes, dphi1_dn=None, stream=None):
+        set_density_from_m(self.handle, m_nodes, dphi1_dn, stream)
 
     def eval(self, phi, stream=None):
         eval_single_layer(self.handle, phi, stream)

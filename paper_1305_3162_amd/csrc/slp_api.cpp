@@ -123,13 +123,18 @@ struct slp_geom {
   void *grid_g = nullptr;
   void *mu = nullptr;
   void *tw[3] = {nullptr, nullptr, nullptr};
+  int32_t *tri_v = nullptr;      // [3][M] vertex indices, component-major
+  double *tri_n = nullptr;       // [3][M] unit outward normals, component-major
+  double *own_dens = nullptr;    // [3M] density formed by slp_set_density_from_m
   int64_t bytes = 0;
   std::vector<void *> allocs;
   // timing: a ring of event sets, one per evaluation, read back lazily
   static constexpr int kRing = 32;
   bool timing = false;
+  int32_t every = 1;             // record the stage events of every k-th evaluation
+  int64_t evals = 0;             // evaluations since timing was enabled
   bool ev_ready = false;
-  static constexpr int kStages = 7;
+  static constexpr int kStages = 8;
   hipEvent_t ev[kRing][kStages + 1]{};
   bool used[kRing]{};
   int cur = 0;
@@ -269,8 +274,7 @@ int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
 }
 
 template <typename T>
-int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
-  const bool tm = G->timing;
+int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bool tm) {
   // spread (the charges q = w g are formed inside the gridding)
   {
     slp::SpreadBinsArgs<T> a{};
@@ -292,9 +296,10 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     r.scratch_bstride = G->item_elems[0];
     r.grid_bstride = G->item_elems[1];
     for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
-    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_slots, G->m, nb, st));
+    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_slots, G->m, nb, st,
+                                  tm ? G->evs()[1] : nullptr));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
   const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
   const int64_t Px = G->P[0], Py = G->P[1];
   const int64_t Kx = G->K[0], Ky = G->K[1], Kz = G->K[2];
@@ -310,7 +315,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_bstride = G->item_elems[1]; p.out_bstride = G->item_elems[2];
     HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
   // y forward: region y -> ky = -n_y/2..n_y/2
   {
     slp::FftPass<T> p{};
@@ -322,7 +327,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[3];
     HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
   // z forward, multiply by mu on kz = -n_z/2..n_z/2, z inverse back to the region
   {
     slp::FftPass<T> p{};
@@ -336,7 +341,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[3];
     HIP_TRY(slp::launch_fft<T>(p, G->N[2], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
   // y inverse: ky -> region y
   {
     slp::FftPass<T> p{};
@@ -348,7 +353,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[2];
     HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
   // x inverse (Hermitian half spectrum -> real region rows)
   {
     slp::FftPass<T> p{};
@@ -362,7 +367,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
   (void)nx;
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
+  if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
   {
     slp::InterpArgs<T> a{};
     a.cell = G->tgt_cell;
@@ -509,7 +514,8 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
 
   // quadrature sources (k = j + s M) and grid-unit coordinates t = (x~ + 1/2) N
   const int64_t M = n_tris, Ms = G->n_src;
-  std::vector<double> ts(3 * Ms), wsrc(Ms), tt(3 * n_nodes);
+  std::vector<double> ts(3 * Ms), wsrc(Ms), tt(3 * n_nodes), tnrm(3 * M);
+  std::vector<int32_t> tv(3 * M);
   const double bary[3][3] = {{4.0 / 6, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 4.0 / 6, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 4.0 / 6}};
   for (int64_t j = 0; j < M; ++j) {
     const double *P0 = nodes + 3 * (int64_t)tris[3 * j];
@@ -520,6 +526,10 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
     const double area = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
     if (!(area > 0.0)) return fail(SLP_EINVAL, "triangle %lld is degenerate", (long long)j);
+    for (int q = 0; q < 3; ++q) {
+      tnrm[q * M + j] = cr[q] / (2.0 * area);
+      tv[q * M + j] = tris[3 * j + q];
+    }
     for (int s = 0; s < 3; ++s) {
       const int64_t k = j + s * M;
       wsrc[k] = area / 3.0;
@@ -704,6 +714,9 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {&G->tw[0], (size_t)G->N[0] * 2 * e},
       {&G->tw[1], (size_t)G->N[1] * 2 * e},
       {&G->tw[2], (size_t)G->N[2] * 2 * e},
+      {reinterpret_cast<void **>(&G->tri_v), (size_t)(3 * M) * 4},
+      {reinterpret_cast<void **>(&G->tri_n), (size_t)(3 * M) * 8},
+      {reinterpret_cast<void **>(&G->own_dens), (size_t)(3 * M) * 8},
   };
   if (dry_bytes) {
     int64_t tot = 0;
@@ -724,6 +737,8 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_nodes * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tri_v, tv.data(), tv.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tri_n, tnrm.data(), tnrm.size() * 8, hipMemcpyHostToDevice, st));
   std::vector<int32_t> cs, ct;
   std::vector<double> fs64, ft64;
   std::vector<float> fs32, ft32;
@@ -804,18 +819,29 @@ int slp_set_density(slp_geom *G, const double *dens, void *stream) {
   return SLP_OK;
 }
 
+int slp_set_density_from_m(slp_geom *G, const double *m_nodes, const double *dphi1_dn,
+                           void *stream) {
+  if (!G || !m_nodes) return fail(SLP_EINVAL, "geometry and m_nodes must be non-NULL");
+  HIP_TRY(slp::launch_density_from_m(G->tri_v, G->tri_n, m_nodes, dphi1_dn, G->n_tris,
+                                     G->own_dens, static_cast<hipStream_t>(stream)));
+  G->dens = G->own_dens;
+  return SLP_OK;
+}
+
 int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
   if (!G || !phi) return fail(SLP_EINVAL, "geometry and phi must be non-NULL");
   if (!G->dens) return fail(SLP_EINVAL, "no density set (slp_set_density)");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (G->timing) {
+  const bool tm = G->timing && (G->evals++ % G->every == 0);
+  if (tm) {
     int rc = begin_timed(G, st);
     if (rc) return rc;
   }
   slp::BatchPtrs ptrs{};
   ptrs.dens[0] = G->dens;
   ptrs.phi[0] = phi;
-  return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, 1, st) : run_eval<float>(G, ptrs, 1, st);
+  return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, 1, st, tm)
+                             : run_eval<float>(G, ptrs, 1, st, tm);
 }
 
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
@@ -838,11 +864,13 @@ int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *
       ptrs.dens[i] = dens[b + i];
       ptrs.phi[i] = phi[b + i];
     }
-    if (G->timing) {
+    const bool tm = G->timing && (G->evals++ % G->every == 0);
+    if (tm) {
       rc = begin_timed(G, st);
       if (rc) return rc;
     }
-    rc = G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st) : run_eval<float>(G, ptrs, nb, st);
+    rc = G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st, tm)
+                             : run_eval<float>(G, ptrs, nb, st, tm);
     if (rc) return rc;
     b = e;
   }
@@ -868,13 +896,15 @@ int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
   return SLP_OK;
 }
 
-int slp_set_timing(slp_geom *G, int32_t enable) {
-  if (!G) return fail(SLP_EINVAL, "NULL geometry");
-  if (enable) {
+int slp_set_timing(slp_geom *G, int32_t every) {
+  if (!G || every < 0) return fail(SLP_EINVAL, "NULL geometry or every < 0");
+  if (every) {
     int rc = ensure_events(G);
     if (rc) return rc;
   }
-  G->timing = enable != 0;
+  G->timing = every != 0;
+  G->every = every ? every : 1;
+  G->evals = 0;
   return SLP_OK;
 }
 
@@ -902,8 +932,11 @@ int slp_debug_copy(const slp_geom *G, int32_t which, void *dst, size_t dst_bytes
   } else if (which == 1) {
     need = (size_t)G->R[0] * G->R[1] * G->R[2] * e;
     src = G->grid_g;
+  } else if (which == 2) {
+    need = (size_t)G->n_src * sizeof(double);
+    src = G->own_dens;
   } else {
-    return fail(SLP_EINVAL, "debug_copy: which must be 0 or 1");
+    return fail(SLP_EINVAL, "debug_copy: which must be 0, 1 or 2");
   }
   if (dst_bytes < need) return fail(SLP_EINVAL, "debug_copy: dst holds %zu bytes, need %zu", dst_bytes, need);
   HIP_TRY(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));

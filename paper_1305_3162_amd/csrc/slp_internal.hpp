@@ -95,7 +95,8 @@ struct FftPass {
 // The gridding forms the charges q = w g itself from the density pointers.
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s);
+                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s,
+                         hipEvent_t between);   // recorded between the two kernels if set
 template <typename T>
 hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int m, int nb,
                          hipStream_t s);
@@ -106,6 +107,12 @@ hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s);
 
 // Message returned by slp_last_error() on the calling thread.
 void set_error_message(const char *msg);
+
+// g_j = (m_a + m_b + m_c) . n_j / 3 - dphi1_dn[j] for every triangle j, written to
+// dens[j], dens[j + M], dens[j + 2M] (one value per quadrature source).
+hipError_t launch_density_from_m(const int32_t *tri_v, const double *tri_n, const double *m_nodes,
+                                 const double *dphi1_dn, int64_t n_tris, double *dens,
+                                 hipStream_t s);
 
 // FP64 setup kernels.
 hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t L,

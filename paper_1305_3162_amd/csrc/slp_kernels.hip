@@ -211,13 +211,18 @@ __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
 
 template <typename T, int M>
 static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                           const BatchPtrs &p, int n_slots, int nb, hipStream_t s) {
+                           const BatchPtrs &p, int n_slots, int nb, hipStream_t s,
+                           hipEvent_t between) {
   using S = SpreadShape<T, M>;
   if (n_slots > 0)
     hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots, (unsigned)nb),
                        dim3(S::THREADS), 0, s, a, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (between) {
+    e = hipEventRecord(between, s);
+    if (e != hipSuccess) return e;
+  }
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
   hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles, (unsigned)nb), dim3(256), 0, s,
                      r);
@@ -226,16 +231,17 @@ static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T>
 
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s) {
+                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s,
+                         hipEvent_t between) {
   switch (m) {
-    case 1: return spread_m<T, 1>(a, r, p, n_slots, nb, s);
-    case 2: return spread_m<T, 2>(a, r, p, n_slots, nb, s);
-    case 3: return spread_m<T, 3>(a, r, p, n_slots, nb, s);
-    case 4: return spread_m<T, 4>(a, r, p, n_slots, nb, s);
-    case 5: return spread_m<T, 5>(a, r, p, n_slots, nb, s);
-    case 6: return spread_m<T, 6>(a, r, p, n_slots, nb, s);
-    case 7: return spread_m<T, 7>(a, r, p, n_slots, nb, s);
-    case 8: return spread_m<T, 8>(a, r, p, n_slots, nb, s);
+    case 1: return spread_m<T, 1>(a, r, p, n_slots, nb, s, between);
+    case 2: return spread_m<T, 2>(a, r, p, n_slots, nb, s, between);
+    case 3: return spread_m<T, 3>(a, r, p, n_slots, nb, s, between);
+    case 4: return spread_m<T, 4>(a, r, p, n_slots, nb, s, between);
+    case 5: return spread_m<T, 5>(a, r, p, n_slots, nb, s, between);
+    case 6: return spread_m<T, 6>(a, r, p, n_slots, nb, s, between);
+    case 7: return spread_m<T, 7>(a, r, p, n_slots, nb, s, between);
+    case 8: return spread_m<T, 8>(a, r, p, n_slots, nb, s, between);
     default: return hipErrorInvalidValue;
   }
 }
@@ -600,6 +606,38 @@ hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s) {
   }
 }
 
+// ---------------------------------------------------------------- density ---
+// Element-constant density of the P1 ansatz: the integral mean of the affine
+// m . n over a flat triangle is its value at the centroid, i.e. the vertex mean;
+// the normal derivative of phi_1 is constant per triangle and subtracted.
+__global__ __launch_bounds__(256) void k_density_from_m(const int32_t *__restrict__ tri_v,
+                                                        const double *__restrict__ tri_n,
+                                                        const double *__restrict__ m_nodes,
+                                                        const double *__restrict__ dphi1_dn,
+                                                        int64_t M, double *__restrict__ dens) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M) return;
+  const int64_t a = tri_v[j], b = tri_v[M + j], c = tri_v[2 * M + j];
+  double g = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    g += tri_n[q * M + j] * (m_nodes[3 * a + q] + m_nodes[3 * b + q] + m_nodes[3 * c + q]);
+  g *= 1.0 / 3.0;
+  if (dphi1_dn) g -= dphi1_dn[j];
+  dens[j] = g;
+  dens[M + j] = g;
+  dens[2 * M + j] = g;
+}
+
+hipError_t launch_density_from_m(const int32_t *tri_v, const double *tri_n, const double *m_nodes,
+                                 const double *dphi1_dn, int64_t n_tris, double *dens,
+                                 hipStream_t s) {
+  if (n_tris <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_density_from_m, dim3((unsigned)((n_tris + 255) / 256)), dim3(256), 0, s,
+                     tri_v, tri_n, m_nodes, dphi1_dn, (int64_t)n_tris, dens);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ setup (FP64) ---
 // c_{t,q}(l) = int_{-1/2}^{1/2} exp(-gamma xi^2) cos(2 pi l xi) dxi (eq. Fcoeff of
 // one separable factor), composite Gauss-Legendre on [0, 1/2], doubled.
@@ -685,10 +723,10 @@ hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2
 // explicit instantiations
 template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
                                          const SpreadReduceArgs<float> &, const BatchPtrs &, int,
-                                         int, int, hipStream_t);
+                                         int, int, hipStream_t, hipEvent_t);
 template hipError_t launch_spread<double>(const SpreadBinsArgs<double> &,
                                           const SpreadReduceArgs<double> &, const BatchPtrs &,
-                                          int, int, int, hipStream_t);
+                                          int, int, int, hipStream_t, hipEvent_t);
 template hipError_t launch_interp<float>(const InterpArgs<float> &, const BatchPtrs &, int, int,
                                          int, hipStream_t);
 template hipError_t launch_interp<double>(const InterpArgs<double> &, const BatchPtrs &, int, int,

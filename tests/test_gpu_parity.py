@@ -223,3 +223,38 @@ def test_multi_density_batch_equals_single(prec):
     assert all(torch.isfinite(p).all().item() for p in phis)
     Ga.close()
     Gb.close()
+
+
+@pytest.mark.parametrize("with_dphi", [False, True])
+def test_density_from_nodal_m(with_dphi):
+    """Element-constant density from a nodal magnetisation (P1 ansatz) formed on
+    the device, then the whole solve, against the oracle's density and definition."""
+    from synth import RandomSmoothMagnetisation
+    from oracle import geometry
+    wl = make_workload("sphere_l3", 6)
+    log(f"case density_from_m sphere_l3 m=6 dphi={with_dphi}")
+    mf = RandomSmoothMagnetisation(21, wl.nodes.min(0), wl.nodes.max(0))
+    m_nodes = mf(wl.nodes)
+    rng = np.random.default_rng(22)
+    dphi = rng.normal(size=wl.tris.shape[0]) if with_dphi else None
+    g_ref = geometry.density_p1(wl.nodes, wl.tris, m_nodes, dphi)
+    G = make_geometry(wl, 6, slp.FP64)
+    G.set_density_from_m(torch.as_tensor(m_nodes).cuda().contiguous(),
+                         None if dphi is None else torch.as_tensor(dphi).cuda())
+    phi = torch.empty(wl.n_nodes, dtype=torch.float64, device="cuda")
+    G.eval(phi)
+    dev_g = torch.empty(wl.n_src, dtype=torch.float64, device="cuda")
+    slp.debug_copy(G.handle, 2, dev_g)
+    torch.cuda.synchronize()
+    assert np.allclose(dev_g.cpu().numpy(), g_ref, rtol=1e-14, atol=1e-15)
+    # the same solve from the oracle's density through set_density
+    phi2 = G.solve(torch.as_tensor(g_ref).cuda())
+    torch.cuda.synchronize()
+    assert rel_l2(phi.cpu().numpy(), phi2.cpu().numpy()) <= 1e-13
+    # against the definition (NDFT route) with the oracle's density
+    p = oracle_problem(wl)
+    p.g = g_ref
+    e = rel_l2(phi.cpu().numpy(), direct.phi_ndft(p))
+    log(f"  rel-L2 vs definition {e:.3e}")
+    assert e <= 4 * np.exp(-2 * np.pi * 6 / 3)
+    G.close()

@@ -88,3 +88,44 @@ def test_scaling_rule(grid):
     assert np.allclose(sN, sN[0], rtol=1e-15)
     # the limiting axis touches the box boundary
     assert np.isclose(np.abs(xt).max(), 0.2, rtol=1e-14)
+
+
+def _closed_volume(nodes, tris):
+    """Volume of a closed, outward-oriented polyhedron: (1/6) sum p0 . (p1 x p2)."""
+    p = nodes[tris]
+    return np.einsum("ij,ij->i", p[:, 0], np.cross(p[:, 1], p[:, 2])).sum() / 6.0
+
+
+def test_density_p1_constant_and_affine_fields():
+    nodes, tris = icosphere(2)
+    M = tris.shape[0]
+    _, nrm = geometry.triangle_areas_normals(nodes, tris)
+    # constant m: g_j = m . n_j
+    mc = np.array([0.3, -0.2, 0.9])
+    g = geometry.density_p1(nodes, tris, np.tile(mc, (nodes.shape[0], 1)))
+    assert np.allclose(g[:M], nrm @ mc, rtol=0, atol=1e-15)
+    assert np.array_equal(g[:M], g[M:2 * M]) and np.array_equal(g[:M], g[2 * M:])
+    # affine m(x) = A x + b: the integral mean is the value at the centroid
+    rng = np.random.default_rng(3)
+    A, b = rng.normal(size=(3, 3)), rng.normal(size=3)
+    g = geometry.density_p1(nodes, tris, nodes @ A.T + b)
+    cen = nodes[tris].mean(axis=1)
+    assert np.allclose(g[:M], ((cen @ A.T + b) * nrm).sum(axis=1), rtol=0, atol=1e-13)
+    # dphi1/dn is subtracted per triangle
+    d = rng.normal(size=M)
+    g2 = geometry.density_p1(nodes, tris, nodes @ A.T + b, d)
+    assert np.allclose(g2[:M], g[:M] - d, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("mesh", ["sphere", "cube"])
+def test_density_p1_divergence_theorem(mesh):
+    """sum_j |S_j| g_j = int_{dOmega} m.n = int_Omega div m: 0 for a uniform m,
+    3 Vol for m(x) = x (exact on the polyhedron: m is affine, the faces flat)."""
+    nodes, tris = icosphere(3) if mesh == "sphere" else cube(6)
+    area, _ = geometry.triangle_areas_normals(nodes, tris)
+    M = tris.shape[0]
+    g = geometry.density_p1(nodes, tris, np.tile([0.0, 0.0, 1.0], (nodes.shape[0], 1)))
+    assert abs(area @ g[:M]) < 1e-13
+    vol = _closed_volume(nodes, tris)
+    g = geometry.density_p1(nodes, tris, nodes)
+    assert np.isclose(area @ g[:M], 3.0 * vol, rtol=1e-13)
