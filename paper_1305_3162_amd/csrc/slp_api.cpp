@@ -13,6 +13,7 @@
 #include <cstring>
 #include <limits>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -98,7 +99,8 @@ struct slp_geom {
   int64_t n_nodes = 0, n_tris = 0, n_src = 0;
   int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
   int32_t terms_kept = 0;
-  int32_t n_slots = 0;           // non-empty source bins
+  int32_t n_slots = 0;           // segments (padded gridding blocks)
+  int32_t n_units = 0;           // gridding work units (workgroups per item)
   int32_t cap = 1;               // batch items the per-item buffers hold
   int64_t item_elems[5]{};       // per item: scratch, grid_a, S1 (complex), S2 (complex), grid_g
   const double *dens = nullptr;  // density of the next single evaluation (caller's device buffer)
@@ -107,10 +109,12 @@ struct slp_geom {
   void *src_frac = nullptr;
   double *src_w = nullptr;
   int32_t *src_perm = nullptr;
-  int4 *bin_chunks = nullptr;
+  int32_t *unit_segs = nullptr;
+  int32_t *seg_list = nullptr;
+  int4 *segs = nullptr;
   int4 *chunks = nullptr;
   int32_t *runs = nullptr;
-  int32_t *slot_of_tile = nullptr;
+  int2 *tile_slots = nullptr;
   void *scratch = nullptr;
   int32_t *tgt_cell = nullptr;
   void *tgt_frac = nullptr;
@@ -281,7 +285,9 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     a.frac = static_cast<const T *>(G->src_frac);
     a.w = G->src_w;
     a.perm = G->src_perm;
-    a.bin_chunks = G->bin_chunks;
+    a.unit_segs = G->unit_segs;
+    a.seg_list = G->seg_list;
+    a.segs = G->segs;
     a.chunks = G->chunks;
     a.runs = G->runs;
     a.scratch = static_cast<T *>(G->scratch);
@@ -291,12 +297,12 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     a.step_ratio = (T)std::exp(-2.0 / G->b);
     slp::SpreadReduceArgs<T> r{};
     r.scratch = static_cast<const T *>(G->scratch);
-    r.slot_of_tile = G->slot_of_tile;
+    r.tile_slots = G->tile_slots;
     r.grid = static_cast<T *>(G->grid_a);
     r.scratch_bstride = G->item_elems[0];
     r.grid_bstride = G->item_elems[1];
     for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
-    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_slots, G->m, nb, st,
+    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_units, G->m, nb, st,
                                   tm ? G->evs()[1] : nullptr));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
@@ -611,63 +617,120 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   std::vector<double> wsorted(Ms);
   for (int64_t i = 0; i < Ms; ++i) wsorted[i] = wsrc[sorder[i]];
 
-  // bins -> chunks of <= kSpreadChunk sources -> runs of sources sharing one cell
-  std::vector<int32_t> slot_of_tile(ntiles, -1);
-  std::vector<int4> bin_chunks, chunks;
+  // segments: the sources of one tile, cut into equal pieces where a tile holds
+  // more than 1.5x the average share of one workgroup slot of the chip (every
+  // CU holding as many gridding workgroups as its LDS allows). Each segment is
+  // cut into chunks of <= kSpreadChunk sources and runs of sources sharing one
+  // cell. (At least max(64, (8 + 2m - 1)^3 / 20) sources per share, so that
+  // small problems do not pay more for storing and summing blocks than for
+  // gridding.)
+  const int per_cu = slp::spread_units_per_cu(G->m, G->prec == SLP_FP64);
+  const int64_t min_src = std::max<int64_t>(64, slp::pad_cells(G->m) / 20);
+  const int64_t max_units = std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)slp::kComputeUnits * per_cu, Ms / min_src));
+  // (a share below ~300 sources makes storing and summing the extra blocks cost
+  // more than the better balance gains, measured on MI355X for m = 4..8)
+  const int64_t share = std::max<int64_t>(300, (Ms + max_units - 1) / max_units);
+  std::vector<int4> segs, chunks;
   std::vector<int32_t> runs;
+  std::vector<int64_t> seg_size;
   {
     const int CH = slp::kSpreadChunk;
     int64_t i = 0;
     while (i < Ms) {
       const int32_t tile = skey[sorder[i]] / 512;
-      slot_of_tile[tile] = (int32_t)bin_chunks.size();
-      int4 bc = {(int)chunks.size(), 0, tile, 0};
-      int4 cur = {(int)i, 0, (int)runs.size(), 0};
-      while (i < Ms && skey[sorder[i]] / 512 == tile) {
-        const int32_t key = skey[sorder[i]];
-        int64_t e = i;
-        while (e < Ms && skey[sorder[e]] == key) ++e;
-        const int32_t inc = sincell[sorder[i]];
-        const int32_t cell = (inc & 7) | (((inc >> 4) & 7) << 3) | ((inc >> 8) << 6);
-        int64_t pos = i;
-        while (pos < e) {
-          if (cur.y == CH) {
-            chunks.push_back(cur);
-            cur = {(int)pos, 0, (int)runs.size(), 0};
+      int64_t te = i;
+      while (te < Ms && skey[sorder[te]] / 512 == tile) ++te;
+      const int64_t n = te - i;
+      const int64_t pieces = n * 2 > share * 3 ? (n + share - 1) / share : 1;
+      for (int64_t pc = 0; pc < pieces; ++pc) {
+        const int64_t pb = i + n * pc / pieces, pe = i + n * (pc + 1) / pieces;
+        int4 sg = {(int)chunks.size(), 0, tile, 0};
+        int4 cur = {(int)pb, 0, (int)runs.size(), 0};
+        int64_t k = pb;
+        while (k < pe) {
+          const int32_t key = skey[sorder[k]];
+          int64_t e = k;
+          while (e < pe && skey[sorder[e]] == key) ++e;
+          const int32_t inc = sincell[sorder[k]];
+          const int32_t cell = (inc & 7) | (((inc >> 4) & 7) << 3) | ((inc >> 8) << 6);
+          int64_t pos = k;
+          while (pos < e) {
+            if (cur.y == CH) {
+              chunks.push_back(cur);
+              cur = {(int)pos, 0, (int)runs.size(), 0};
+            }
+            const int take = (int)std::min<int64_t>(e - pos, CH - cur.y);
+            runs.push_back(cell | (cur.y << 9) | (take << 19));
+            cur.y += take;
+            cur.w += 1;
+            pos += take;
           }
-          const int take = (int)std::min<int64_t>(e - pos, CH - cur.y);
-          runs.push_back(cell | (cur.y << 9) | (take << 19));
-          cur.y += take;
-          cur.w += 1;
-          pos += take;
+          k = e;
         }
-        i = e;
+        chunks.push_back(cur);
+        sg.y = (int)chunks.size();
+        segs.push_back(sg);
+        seg_size.push_back(pe - pb);
       }
-      chunks.push_back(cur);
-      bc.y = (int)chunks.size();
-      bin_chunks.push_back(bc);
+      i = te;
     }
   }
-  // largest bins first: the hardware hands out workgroups in launch order, so
-  // the long ones start early and the short ones fill the tail
+  // one workgroup per segment, longest first: the hardware hands out
+  // workgroups in launch order to whichever CU frees up, which balances the
+  // actual run times better than any static packing by source count
+  const int64_t n_units = (int64_t)segs.size();
+  std::vector<int32_t> unit_segs(n_units + 1, 0), seg_list(segs.size());
   {
-    std::vector<int32_t> order(bin_chunks.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
-    auto nsrc = [&](int32_t b) {
-      int64_t n = 0;
-      for (int c = bin_chunks[b].x; c < bin_chunks[b].y; ++c) n += chunks[c].y;
-      return n;
-    };
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t a, int32_t b) { return nsrc(a) > nsrc(b); });
-    std::vector<int4> sorted(bin_chunks.size());
-    for (size_t i = 0; i < order.size(); ++i) {
-      sorted[i] = bin_chunks[order[i]];
-      slot_of_tile[sorted[i].z] = (int32_t)i;
-    }
-    bin_chunks.swap(sorted);
+    for (size_t k = 0; k < seg_list.size(); ++k) seg_list[k] = (int32_t)k;
+    std::stable_sort(seg_list.begin(), seg_list.end(),
+                     [&](int32_t a, int32_t b) { return seg_size[a] > seg_size[b]; });
+    for (int64_t u = 0; u < n_units; ++u) unit_segs[u + 1] = (int32_t)(u + 1);
   }
-  G->n_slots = (int32_t)bin_chunks.size();
+  // consistency of the tables the gridding kernel indexes with (cheap, host side)
+  {
+    int64_t next_src = 0;
+    bool ok = unit_segs.back() == (int32_t)segs.size();
+    for (size_t u = 0; ok && u + 1 < unit_segs.size(); ++u) ok = unit_segs[u] <= unit_segs[u + 1];
+    std::vector<char> seen(segs.size(), 0);
+    for (size_t k = 0; ok && k < seg_list.size(); ++k) {
+      ok = seg_list[k] >= 0 && seg_list[k] < (int32_t)segs.size() && !seen[seg_list[k]];
+      if (ok) seen[seg_list[k]] = 1;
+    }
+    for (size_t sgi = 0; ok && sgi < segs.size(); ++sgi) {
+      const int4 sg = segs[sgi];
+      ok = sg.x < sg.y && sg.z >= 0 && sg.z < ntiles;
+      for (int c = sg.x; ok && c < sg.y; ++c) {
+        const int4 ch = chunks[c];
+        ok = ch.x == next_src && ch.y >= 1 && ch.y <= slp::kSpreadChunk && ch.w >= 1 &&
+             ch.w <= slp::kSpreadChunk && ch.z + ch.w <= (int)runs.size();
+        int expect_off = 0;
+        for (int r = 0; ok && r < ch.w; ++r) {
+          const int32_t rec = runs[ch.z + r];
+          const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
+          ok = off == expect_off && cnt >= 1;
+          for (int k = 0; ok && k < cnt; ++k) {
+            const int32_t key = skey[sorder[ch.x + off + k]];
+            const int32_t cl = key % 512;
+            ok = key / 512 == sg.z && (rec & 511) == cl;
+          }
+          expect_off += cnt;
+        }
+        ok = ok && expect_off == ch.y;
+        next_src += ch.y;
+      }
+    }
+    if (!ok || next_src != Ms) return fail(SLP_EDEVICE, "internal error: gridding tables inconsistent");
+  }
+  // the segments of one tile are consecutive (sources sorted by tile)
+  std::vector<int2> tile_slots(ntiles, int2{0, 0});
+  for (size_t sgi = 0; sgi < segs.size(); ++sgi) {
+    int2 &ts = tile_slots[segs[sgi].z];
+    if (ts.y == 0) ts.x = (int)sgi;
+    ts.y += 1;
+  }
+  G->n_units = (int32_t)n_units;
+  G->n_slots = (int32_t)segs.size();
   std::vector<int32_t> tgt_active;
   for (int64_t t = 0; t < ntiles; ++t)
     if (tstart[t + 1] > tstart[t]) tgt_active.push_back((int32_t)t);
@@ -696,10 +759,12 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {&G->src_frac, (size_t)(3 * Ms) * e},
       {reinterpret_cast<void **>(&G->src_w), (size_t)Ms * 8},
       {reinterpret_cast<void **>(&G->src_perm), (size_t)Ms * 4},
-      {reinterpret_cast<void **>(&G->bin_chunks), bin_chunks.size() * sizeof(int4)},
+      {reinterpret_cast<void **>(&G->unit_segs), unit_segs.size() * sizeof(int32_t)},
+      {reinterpret_cast<void **>(&G->segs), segs.size() * sizeof(int4)},
+      {reinterpret_cast<void **>(&G->seg_list), seg_list.size() * sizeof(int32_t)},
       {reinterpret_cast<void **>(&G->chunks), chunks.size() * sizeof(int4)},
       {reinterpret_cast<void **>(&G->runs), runs.size() * sizeof(int32_t)},
-      {reinterpret_cast<void **>(&G->slot_of_tile), (size_t)ntiles * 4},
+      {reinterpret_cast<void **>(&G->tile_slots), (size_t)ntiles * sizeof(int2)},
       {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
       {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
       {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
@@ -730,10 +795,12 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
 
   HIP_TRY(hipMemcpyAsync(G->src_w, wsorted.data(), Ms * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->src_perm, sorder.data(), Ms * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->bin_chunks, bin_chunks.data(), bin_chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->unit_segs, unit_segs.data(), unit_segs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->segs, segs.data(), segs.size() * sizeof(int4), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->seg_list, seg_list.data(), seg_list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->slot_of_tile, slot_of_tile.data(), ntiles * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int2), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_nodes * 4, hipMemcpyHostToDevice, st));

@@ -11,12 +11,18 @@ namespace slp {
 constexpr int kTile = 8;      // grid tile edge used by spread and interpolation bins
 constexpr int kMaxM = 8;      // largest supported window cut-off
 
-// Gridding (type-1 spread). Sources are sorted by (tile, cell in tile); every
-// non-empty tile ("bin") owns a padded accumulation block of (8 + 2m - 1)^3
-// cells in `scratch` (slot order). A bin is cut into chunks of at most
-// kSpreadChunk sources that end on run boundaries; a run is a sequence of
-// sources that share one grid cell (longer runs are cut at chunk size).
+// Gridding (type-1 spread). Sources are sorted by (tile, cell in tile). The
+// sources of one tile form a segment (tiles with far more sources than the
+// average share of a workgroup slot are cut into several); every segment owns a
+// padded accumulation block of (8 + 2m - 1)^3 cells in `scratch` (slot =
+// segment index, the segments of a tile consecutive; blocked layout, see
+// pad_block_index). A work unit (one workgroup) takes a list of segments; the
+// setup gives every unit one segment, longest first. A segment is cut into
+// chunks of at most kSpreadChunk sources; a run is a sequence of sources of one
+// chunk that share one grid cell.
 constexpr int kSpreadChunk = 512;
+// Units are sized for this many compute units (MI355X).
+constexpr int kComputeUnits = 256;
 // Densities evaluated on one geometry by one launch of every stage.
 constexpr int kMaxBatch = 64;
 
@@ -30,21 +36,24 @@ struct SpreadBinsArgs {
   const T *frac;         // [3][ns] t - floor(t), sorted order
   const double *w;       // [ns] quadrature weights, sorted order
   const int32_t *perm;   // [ns] sorted -> caller (long) index of the density
-  const int4 *bin_chunks;    // [n_slots] {first chunk, end chunk, tile id, 0}
+  const int32_t *unit_segs;  // [n_units + 1] first entry of each unit in seg_list
+  const int32_t *seg_list;   // [n_slots] segments of unit u: seg_list[unit_segs[u] ..]
+  const int4 *segs;          // [n_slots] {first chunk, end chunk, tile id, 0}
   const int4 *chunks;        // {first source, source count, first run, run count}
   const int32_t *runs;       // cell x | y << 3 | z << 6 | offset in chunk << 9 | count << 19
-  T *scratch;            // [n_slots][PD^3]
+  T *scratch;            // [n_slots][PD^3], blocked layout
   int64_t ns;
   int64_t scratch_bstride;   // per batch item (blockIdx.y)
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
   T step_ratio;          // exp(-2 / b): ratio of consecutive weight ratios
 };
 
-// Sum of the padded blocks of the neighbouring bins into the region grid.
+// Sum of the padded blocks of the segments in the neighbouring tiles into the
+// region grid.
 template <typename T>
 struct SpreadReduceArgs {
   const T *scratch;
-  const int32_t *slot_of_tile;   // [tiles] slot or -1
+  const int2 *tile_slots;        // [tiles] {first slot, slot count}
   T *grid;                       // [P_z][P_y][P_x]
   int32_t tiles[3];
   int64_t scratch_bstride, grid_bstride;
@@ -95,8 +104,11 @@ struct FftPass {
 // The gridding forms the charges q = w g itself from the density pointers.
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s,
+                         const BatchPtrs &p, int n_units, int m, int nb, hipStream_t s,
                          hipEvent_t between);   // recorded between the two kernels if set
+// Work units per compute unit for the gridding kernel of cut-off m (how many
+// of its workgroups fit in one CU's LDS, at most 2). Host-only.
+int spread_units_per_cu(int m, bool fp64);
 template <typename T>
 hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int m, int nb,
                          hipStream_t s);

@@ -24,9 +24,11 @@ __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
 // ----------------------------------------------------------------- spread ---
-// Phase A (one workgroup of 8 or 16 waves per non-empty bin): the bin's sources are
-// scattered into an LDS block covering the bin plus the stencil halo,
-// (8 + 2m - 1)^3 cells. Each wave independently takes every 8th run of sources
+// Phase A (one workgroup of 8 or 16 waves per work unit, a run of the sorted
+// sources of nearly equal length for every unit): the sources of each segment
+// (the unit's sources in one tile) are scattered into an LDS block covering the
+// tile plus the stencil halo, (8 + 2m - 1)^3 cells, which is then stored to the
+// segment's slot. Each wave independently takes every 8th run of sources
 // that share one grid cell; its lanes cover the 2m x 2m (dx, dy) columns of the
 // stencil in ceil(4m^2 / 64) passes and keep the 2m z-values of each column in
 // registers over the whole run, adding them to the LDS block once per run. The
@@ -35,7 +37,14 @@ __device__ __forceinline__ double wexp(double x) { return exp(x); }
 // w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b): two exponentials per source and
 // axis.
 // Phase B (one workgroup per region tile): every cell sums the blocks of the
-// neighbouring bins that cover it, in a fixed order, and writes the grid.
+// segments of the neighbouring tiles that cover it, in a fixed order, and
+// writes the grid.
+//
+// Blocked layout of a stored block: along each axis the padded range splits
+// into the part that lands in the previous tile (m - 1 cells), in the own tile
+// (8) and in the next tile (m); the 27 sub-blocks are stored one after the
+// other (z part, then y part, then x part), each row-major, so the reduction
+// for one tile reads every contributing sub-block as one contiguous range.
 template <typename T, int M>
 struct SpreadShape {
   static constexpr int W = 2 * M;
@@ -54,6 +63,47 @@ struct SpreadShape {
 int64_t pad_cells(int m) {
   const int64_t pd = kTile + 2 * m - 1;
   return pd * pd * pd;
+}
+
+int spread_units_per_cu(int m, bool fp64) {
+  auto lds = [](auto shape, size_t esz) {
+    using S = decltype(shape);
+    return (size_t)S::P3 * 8 + (size_t)S::WAVES * S::SBW * S::WST * esz +
+           4 * (size_t)S::CH * esz + (size_t)S::CH * 4;
+  };
+  size_t b = 0;
+  switch (m) {
+#define SLP_LDS_CASE(MM)                                                            \
+  case MM:                                                                          \
+    b = fp64 ? lds(SpreadShape<double, MM>{}, 8) : lds(SpreadShape<float, MM>{}, 4); \
+    break;
+    SLP_LDS_CASE(1) SLP_LDS_CASE(2) SLP_LDS_CASE(3) SLP_LDS_CASE(4)
+    SLP_LDS_CASE(5) SLP_LDS_CASE(6) SLP_LDS_CASE(7) SLP_LDS_CASE(8)
+#undef SLP_LDS_CASE
+    default: return 1;
+  }
+  const int fit = (int)((size_t)160 * 1024 / b);
+  return fit < 1 ? 1 : (fit > 2 ? 2 : fit);
+}
+
+// Part of the padded range holding pad coordinate c, its first coordinate and
+// its length (m - 1, 8, m).
+template <int M>
+__device__ __forceinline__ void pad_part(int c, int &part, int &start, int &len) {
+  if (c < M - 1) { part = 0; start = 0; len = M - 1; }
+  else if (c < M + kTile - 1) { part = 1; start = M - 1; len = kTile; }
+  else { part = 2; start = M + kTile - 1; len = M; }
+}
+
+// Blocked index of pad cell (x, y, z).
+template <int M>
+__device__ __forceinline__ int pad_block_index(int x, int y, int z) {
+  constexpr int PD = kTile + 2 * M - 1;
+  int px, sx, lx, py, sy, ly, pz, sz, lz;
+  pad_part<M>(x, px, sx, lx);
+  pad_part<M>(y, py, sy, ly);
+  pad_part<M>(z, pz, sz, lz);
+  return sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx);
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -75,11 +125,8 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
 
-  const int slot = blockIdx.x;
-  const int4 bc = a.bin_chunks[slot];
+  const int unit = blockIdx.x;
   const double *dens = ptrs.dens[blockIdx.y];
-  for (int i = threadIdx.x; i < S::P3; i += S::THREADS) pad[i] = 0.0;
-
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   T *ww = wts + wave * S::SBW * S::WST;
@@ -93,6 +140,10 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   const bool last_act = (lane + 64 * (NP - 1)) < S::COLS;
   const int64_t ns = a.ns;
 
+  for (int q = a.unit_segs[unit]; q < a.unit_segs[unit + 1]; ++q) {
+  const int sg = a.seg_list[q];
+  const int4 bc = a.segs[sg];
+  for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
   for (int c = bc.x; c < bc.y; ++c) {
     const int4 ch = a.chunks[c];     // {first source, count, first run, run count}
     // issue every global load of the chunk before writing LDS
@@ -172,12 +223,33 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
     }
   }
   __syncthreads();
-  T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)slot * S::P3;
-  for (int i = tid; i < S::P3; i += S::THREADS) dst[i] = (T)pad[i];
+  T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)sg * S::P3;
+  {
+    // 32 lanes per pad row: x is fixed per thread, rows advance
+    const int x = tid & 31;
+    if (x < PD) {
+      int px, sx, lx;
+      pad_part<M>(x, px, sx, lx);
+      for (int rw = tid >> 5; rw < PD * PD; rw += S::THREADS / 32) {
+        const int y = rw % PD, z = rw / PD;
+        int py, sy, ly, pz, sz, lz;
+        pad_part<M>(y, py, sy, ly);
+        pad_part<M>(z, pz, sz, lz);
+        dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
+            (T)pad[rw * PD + x];
+      }
+    }
+  }
+  __syncthreads();                   // block stored before the next segment clears it
+  }
 }
 
+// One workgroup of 512 threads per region tile, one thread per cell. For each
+// of the 27 neighbouring tiles (fixed order) and each of its segments, the
+// threads whose cell the block covers read the matching sub-block, which is
+// contiguous in the blocked layout.
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
+__global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
   using S = SpreadShape<T, M>;
   constexpr int PD = S::PD;
   const int tile = blockIdx.x;
@@ -187,35 +259,37 @@ __global__ __launch_bounds__(256) void k_spread_reduce(SpreadReduceArgs<T> a) {
   const int64_t Px = (int64_t)a.tiles[0] * kTile, Py = (int64_t)a.tiles[1] * kTile;
   const T *scr = a.scratch + blockIdx.y * a.scratch_bstride;
   T *grid = a.grid + blockIdx.y * a.grid_bstride;
-  for (int c = threadIdx.x; c < kTile * kTile * kTile; c += blockDim.x) {
-    const int gx = tx * kTile + (c & 7), gy = ty * kTile + ((c >> 3) & 7), gz = tz * kTile + (c >> 6);
-    T v = T(0);
-    for (int bz = tz - 1; bz <= tz + 1; ++bz) {
-      const int iz = gz - (bz * kTile - M + 1);
-      if (bz < 0 || bz >= a.tiles[2] || iz < 0 || iz >= PD) continue;
-      for (int by = ty - 1; by <= ty + 1; ++by) {
-        const int iy = gy - (by * kTile - M + 1);
-        if (by < 0 || by >= a.tiles[1] || iy < 0 || iy >= PD) continue;
-        for (int bx = tx - 1; bx <= tx + 1; ++bx) {
-          const int ix = gx - (bx * kTile - M + 1);
-          if (bx < 0 || bx >= a.tiles[0] || ix < 0 || ix >= PD) continue;
-          const int slot = a.slot_of_tile[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
-          if (slot < 0) continue;
-          v += scr[(int64_t)slot * S::P3 + (iz * PD + iy) * PD + ix];
-        }
+  const int c = threadIdx.x;
+  const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
+  T v = T(0);
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int bz = tz + dz;
+    const int iz = cz + kTile * (-dz) + M - 1;     // pad coordinate in the neighbour's block
+    if (bz < 0 || bz >= a.tiles[2] || iz < 0 || iz >= PD) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int by = ty + dy;
+      const int iy = cy + kTile * (-dy) + M - 1;
+      if (by < 0 || by >= a.tiles[1] || iy < 0 || iy >= PD) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int bx = tx + dx;
+        const int ix = cx + kTile * (-dx) + M - 1;
+        if (bx < 0 || bx >= a.tiles[0] || ix < 0 || ix >= PD) continue;
+        const int2 ts = a.tile_slots[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
+        const int off = pad_block_index<M>(ix, iy, iz);
+        for (int k = 0; k < ts.y; ++k) v += scr[(int64_t)(ts.x + k) * S::P3 + off];
       }
     }
-    grid[(gz * Py + gy) * Px + gx] = v;
   }
+  grid[((tz * kTile + cz) * Py + ty * kTile + cy) * Px + tx * kTile + cx] = v;
 }
 
 template <typename T, int M>
 static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                           const BatchPtrs &p, int n_slots, int nb, hipStream_t s,
+                           const BatchPtrs &p, int n_units, int nb, hipStream_t s,
                            hipEvent_t between) {
   using S = SpreadShape<T, M>;
-  if (n_slots > 0)
-    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_slots, (unsigned)nb),
+  if (n_units > 0)
+    hipLaunchKernelGGL((k_spread_bins<T, M>), dim3((unsigned)n_units, (unsigned)nb),
                        dim3(S::THREADS), 0, s, a, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -224,24 +298,24 @@ static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T>
     if (e != hipSuccess) return e;
   }
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
-  hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles, (unsigned)nb), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles, (unsigned)nb), dim3(512), 0, s,
                      r);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                         const BatchPtrs &p, int n_slots, int m, int nb, hipStream_t s,
+                         const BatchPtrs &p, int n_units, int m, int nb, hipStream_t s,
                          hipEvent_t between) {
   switch (m) {
-    case 1: return spread_m<T, 1>(a, r, p, n_slots, nb, s, between);
-    case 2: return spread_m<T, 2>(a, r, p, n_slots, nb, s, between);
-    case 3: return spread_m<T, 3>(a, r, p, n_slots, nb, s, between);
-    case 4: return spread_m<T, 4>(a, r, p, n_slots, nb, s, between);
-    case 5: return spread_m<T, 5>(a, r, p, n_slots, nb, s, between);
-    case 6: return spread_m<T, 6>(a, r, p, n_slots, nb, s, between);
-    case 7: return spread_m<T, 7>(a, r, p, n_slots, nb, s, between);
-    case 8: return spread_m<T, 8>(a, r, p, n_slots, nb, s, between);
+    case 1: return spread_m<T, 1>(a, r, p, n_units, nb, s, between);
+    case 2: return spread_m<T, 2>(a, r, p, n_units, nb, s, between);
+    case 3: return spread_m<T, 3>(a, r, p, n_units, nb, s, between);
+    case 4: return spread_m<T, 4>(a, r, p, n_units, nb, s, between);
+    case 5: return spread_m<T, 5>(a, r, p, n_units, nb, s, between);
+    case 6: return spread_m<T, 6>(a, r, p, n_units, nb, s, between);
+    case 7: return spread_m<T, 7>(a, r, p, n_units, nb, s, between);
+    case 8: return spread_m<T, 8>(a, r, p, n_units, nb, s, between);
     default: return hipErrorInvalidValue;
   }
 }

@@ -50,7 +50,7 @@ def test_device_bytes_estimate_matches_setup():
         G.close()
 
 
-@pytest.mark.parametrize("budget_mb,slots", [(4096, 4), (12, 2)])
+@pytest.mark.parametrize("budget_mb,slots", [(4096, 4), (16, 2)])
 def test_results_same_alone_and_in_mix(budget_mb, slots):
     log(f"case server budget={budget_mb}MB slots={slots}")
     mix = _mix()
