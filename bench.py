@@ -46,6 +46,8 @@ def parse():
                     help="densities per step on the one geometry (batched launch)")
     ap.add_argument("--serve", action="store_true",
                     help="served mix: Poisson request stream through the request server")
+    ap.add_argument("--mix32", action="store_true",
+                    help="multi-mesh batch: 32 icospheres of levels 2-6 in one batched call")
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--rho", type=float, default=0.8, help="offered load / capacity")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -102,10 +104,7 @@ def serve(args):
     geo = []
     for kind, size in shapes:
         nodes, tris = icosphere(size) if kind == "sphere" else cube(size)
-        # mean edge length after scaling into (-0.2, 0.2): 0.4 * edge / extent
-        e = nodes[tris[:, [1, 2, 0]]] - nodes[tris]
-        hbar = 0.4 * float(np.linalg.norm(e, axis=2).mean()) / float((nodes.max(0) - nodes.min(0)).max())
-        N = int(min(512, max(64, 2 ** int(np.floor(np.log2(1.0 / hbar))))))
+        N = grid_rule(nodes, tris)
         r_lo, r_hi = expsum_interval(nodes)
         w, g = slp.expsum_sinc(0.2, r_lo, r_hi, 1e-12)
         dens = []
@@ -185,8 +184,88 @@ def serve(args):
     print(json.dumps(rec), flush=True)
 
 
+def grid_rule(nodes, tris):
+    """N_q = clamp(prevpow2(1 / mean scaled edge), 64, 512) (scaled into (-0.2, 0.2))."""
+    e = nodes[tris[:, [1, 2, 0]]] - nodes[tris]
+    hbar = 0.4 * float(np.linalg.norm(e, axis=2).mean()) / float((nodes.max(0) - nodes.min(0)).max())
+    return int(min(512, max(64, 2 ** int(np.floor(np.log2(1.0 / hbar))))))
+
+
+def mix32(args):
+    """Multi-mesh batch: 32 icospheres, levels uniform in {2..6} (seed 4100), each with
+    its own seeded magnetisation (seeds 4101-4132) and grid by the rule above, evaluated
+    by one slp_eval_batched call per step (groups of different meshes overlap on the
+    library's lanes); beside it the same items one after the other on one stream."""
+    import torch
+
+    import paper_1305_3162_amd as slp
+    from synth import icosphere, RandomSmoothMagnetisation, density_from_magnetisation
+    from synth.workloads import expsum_interval
+
+    prec = slp.FP64 if args.precision == "fp64" else slp.FP32
+    m = args.m if args.m is not None else (8 if prec == slp.FP64 else 5)
+    levels = np.random.default_rng(4100).integers(2, 7, size=32)
+    geos, dens, phis, pts = [], [], [], 0
+    cache = {}
+    for i, L in enumerate(levels):
+        if L not in cache:
+            nodes, tris = icosphere(int(L))
+            r_lo, r_hi = expsum_interval(nodes)
+            w, g = slp.expsum_sinc(0.2, r_lo, r_hi, 1e-12)
+            cache[L] = (nodes, tris, w, g, grid_rule(nodes, tris))
+        nodes, tris, w, g, N = cache[L]
+        geos.append(slp.Geometry(nodes, tris, (N,) * 3, m, w, g, 2, prec))
+        mf = RandomSmoothMagnetisation(4101 + i, nodes.min(0), nodes.max(0))
+        dens.append(torch.as_tensor(density_from_magnetisation(nodes, tris, mf), device="cuda"))
+        phis.append(torch.empty(nodes.shape[0], dtype=torch.float64, device="cuda"))
+        pts += 3 * tris.shape[0] + nodes.shape[0]
+    handles = [G.handle for G in geos]
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        slp.eval_batched(handles, dens, phis, stream)
+
+    def one_by_one():
+        for G, d, p in zip(geos, dens, phis):
+            G.set_density(d, stream)
+            G.eval(p, stream)
+
+    out = {}
+    for name, fn in (("batched", batched), ("one_by_one", one_by_one)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) / args.steps
+    for G in geos:
+        G.close()
+    rec = {
+        "metric": "multi-mesh batched SL-potential NUFFT (M+N) pts/s",
+        "value": round(pts / out["batched"], 1), "unit": "pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(out["batched"] * 1e3, 5), "higher_is_better": True,
+        "dtype": "f64" if prec == slp.FP64 else "f32", "data": "synthetic",
+        "one_by_one_pts_per_s": round(pts / out["one_by_one"], 1),
+        "one_by_one_ms_per_step": round(out["one_by_one"] * 1e3, 5),
+        "config": {"workload": "32 icospheres, levels uniform in 2..6 (seed 4100), seeded "
+                               "magnetisations 4101-4132, grid clamp(prevpow2(1/mean scaled "
+                               "edge), 64, 512)^3 per mesh", "m": m,
+                   "levels": [int(x) for x in levels], "points": pts},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
+    if args.mix32:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        mix32(args)
+        return
     if args.serve:
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)

@@ -12,6 +12,8 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
@@ -911,37 +913,105 @@ int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
                              : run_eval<float>(G, ptrs, 1, st, tm);
 }
 
+namespace {
+
+// Streams on which the launch groups of different geometries of one batched
+// call overlap (per device, created on first use, default priority).
+constexpr int kLanes = 4;
+struct Lanes {
+  hipStream_t s[kLanes]{};
+  hipEvent_t fork{};
+  hipEvent_t join[kLanes]{};
+};
+std::mutex g_lanes_mu;              // guards the table and every fork/join section
+std::map<int, Lanes> g_lanes;
+
+int get_lanes(Lanes **out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  auto it = g_lanes.find(dev);
+  if (it == g_lanes.end()) {
+    Lanes L;
+    for (int i = 0; i < kLanes; ++i) {
+      HIP_TRY(hipStreamCreateWithFlags(&L.s[i], hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&L.join[i], hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&L.fork, hipEventDisableTiming));
+    it = g_lanes.emplace(dev, L).first;
+  }
+  *out = &it->second;
+  return SLP_OK;
+}
+
+// One launch group: consecutive items of one geometry (at most kMaxBatch).
+int run_group(slp_geom *G, const double *const *dens, double *const *phi, int nb, hipStream_t st) {
+  int rc = ensure_capacity(G, nb, st);
+  if (rc) return rc;
+  slp::BatchPtrs ptrs{};
+  for (int i = 0; i < nb; ++i) {
+    ptrs.dens[i] = dens[i];
+    ptrs.phi[i] = phi[i];
+  }
+  const bool tm = G->timing && (G->evals++ % G->every == 0);
+  if (tm) {
+    rc = begin_timed(G, st);
+    if (rc) return rc;
+  }
+  return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st, tm)
+                             : run_eval<float>(G, ptrs, nb, st, tm);
+}
+
+}  // namespace
+
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
                      int32_t batch, void *stream) {
   if (batch < 1 || !geoms || !dens || !phi) return fail(SLP_EINVAL, "batched: batch >= 1 and non-NULL arrays");
   for (int32_t b = 0; b < batch; ++b)
     if (!geoms[b] || !dens[b] || !phi[b]) return fail(SLP_EINVAL, "batched: item %d has a NULL pointer", b);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // consecutive items on one geometry share every launch (up to kMaxBatch)
-  int32_t b = 0;
-  while (b < batch) {
-    slp_geom *G = geoms[b];
+  // launch groups: consecutive items on one geometry share every launch
+  struct Group { slp_geom *G; int32_t b, e; };
+  std::vector<Group> groups;
+  for (int32_t b = 0; b < batch;) {
     int32_t e = b + 1;
-    while (e < batch && geoms[e] == G && e - b < slp::kMaxBatch) ++e;
-    const int nb = e - b;
-    int rc = ensure_capacity(G, nb, st);
-    if (rc) return rc;
-    slp::BatchPtrs ptrs{};
-    for (int i = 0; i < nb; ++i) {
-      ptrs.dens[i] = dens[b + i];
-      ptrs.phi[i] = phi[b + i];
-    }
-    const bool tm = G->timing && (G->evals++ % G->every == 0);
-    if (tm) {
-      rc = begin_timed(G, st);
-      if (rc) return rc;
-    }
-    rc = G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st, tm)
-                             : run_eval<float>(G, ptrs, nb, st, tm);
-    if (rc) return rc;
+    while (e < batch && geoms[e] == geoms[b] && e - b < slp::kMaxBatch) ++e;
+    groups.push_back({geoms[b], b, e});
     b = e;
   }
-  return SLP_OK;
+  // every geometry gets one lane (its work buffers serve one group at a time)
+  std::map<slp_geom *, int> lane_of;
+  for (const Group &g : groups)
+    if (!lane_of.count(g.G)) {
+      const int l = (int)lane_of.size() % kLanes;
+      lane_of[g.G] = l;
+    }
+  if (lane_of.size() == 1) {
+    for (const Group &g : groups) {
+      const int rc = run_group(g.G, dens + g.b, phi + g.b, g.e - g.b, st);
+      if (rc) return rc;
+    }
+    return SLP_OK;
+  }
+  // several geometries: their groups overlap on the lanes, forked from and
+  // joined back into the caller's stream
+  std::lock_guard<std::mutex> lock(g_lanes_mu);
+  Lanes *L = nullptr;
+  int rc = get_lanes(&L);
+  if (rc) return rc;
+  const int used = std::min<int>(kLanes, (int)lane_of.size());
+  HIP_TRY(hipEventRecord(L->fork, st));
+  for (int l = 0; l < used; ++l) HIP_TRY(hipStreamWaitEvent(L->s[l], L->fork, 0));
+  for (const Group &g : groups) {
+    rc = run_group(g.G, dens + g.b, phi + g.b, g.e - g.b, L->s[lane_of[g.G]]);
+    if (rc) break;
+  }
+  // join even after an error, so the caller's stream never runs ahead of work
+  // already enqueued on the lanes
+  for (int l = 0; l < used; ++l) {
+    HIP_TRY(hipEventRecord(L->join[l], L->s[l]));
+    HIP_TRY(hipStreamWaitEvent(st, L->join[l], 0));
+  }
+  return rc;
 }
 
 int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {

@@ -258,3 +258,34 @@ def test_density_from_nodal_m(with_dphi):
     log(f"  rel-L2 vs definition {e:.3e}")
     assert e <= 4 * np.exp(-2 * np.pi * 6 / 3)
     G.close()
+
+
+def test_multi_mesh_batch_overlaps_and_joins():
+    """Items on six geometries (two precisions, more geometries than overlap
+    lanes, repeats interleaved) in one batched call, twice in a row: every result
+    equals its single solve, and work queued on the caller's stream afterwards
+    sees the finished results."""
+    log("case multi-mesh batch (6 geometries, lanes)")
+    specs = [(sphere_random(1, 31, 32, 3), 3, slp.FP64), (sphere_random(2, 32, 64, 5), 5, slp.FP32),
+             (sphere_random(3, 33, 64, 4), 4, slp.FP64), (sphere_random(2, 34, 64, 6), 6, slp.FP64),
+             (sphere_random(1, 35, 32, 2), 2, slp.FP32), (sphere_random(3, 36, 128, 5), 5, slp.FP32)]
+    geos = [(make_geometry(wl, m, p), wl, p) for wl, m, p in specs]
+    rng = np.random.default_rng(9)
+    order = [0, 1, 2, 3, 4, 5, 5, 2, 0, 0, 3, 1, 4]
+    dens = [torch.as_tensor(rng.normal(size=geos[i][1].n_src)).cuda() for i in order]
+    torch.cuda.synchronize()
+    for rep in range(2):
+        phis = [torch.full((geos[i][1].n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+                for i in order]
+        slp.eval_batched([geos[i][0].handle for i in order], dens, phis)
+        sums = torch.stack([p.sum() for p in phis])        # on the caller's stream
+        torch.cuda.synchronize()
+        assert torch.isfinite(sums).all().item(), rep
+        for k, i in enumerate(order):
+            G, wl, p = geos[i]
+            ref = G.solve(dens[k])
+            torch.cuda.synchronize()
+            tol = 1e-14 if p == slp.FP64 else 1e-6
+            assert rel_l2(phis[k].cpu().numpy(), ref.cpu().numpy()) <= tol, (rep, k)
+    for G, _, _ in geos:
+        G.close()
