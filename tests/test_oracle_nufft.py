@@ -76,3 +76,52 @@ def test_nufft_anisotropic_grid_and_alpha3():
     ref = direct.phi_pairs(p)
     phi = nufft.phi_nufft(p, 3)
     assert np.linalg.norm(phi - ref) < 2e-3 * np.linalg.norm(ref)
+
+
+def _kb_bound(m, alpha=2):
+    """Relative error bound of the NFFT with the Kaiser-Bessel window
+    (eq. error_bound_nufft)."""
+    return 4 * np.pi * (np.sqrt(m) + m) * (1 - 1 / alpha) ** 0.25 * np.exp(
+        -2 * np.pi * m * np.sqrt(1 - 1 / alpha))
+
+
+@pytest.mark.parametrize("m", [3, 4, 6])
+def test_kb_fourier_pair(m):
+    """eq. cFB against a numerical Fourier transform of eq. KBfct on the whole
+    line: the inner part by adaptive quadrature, the oscillatory tail |tau| > m
+    (sin branch) after tau = sqrt(u^2 + m^2) by QAWF with weight sin(b u)."""
+    alpha, N = 2, 64
+    b = nufft.kb_shape(alpha)
+    for l in (0, 3, 11, N // 4):
+        w = 2 * np.pi * l / N
+        inner, _ = integrate.quad(lambda t: nufft.psi_kb(t, m, b) * np.cos(w * t), 0, m,
+                                  limit=200, epsabs=0, epsrel=1e-13)
+        tail, _ = integrate.quad(
+            lambda u: np.cos(w * np.sqrt(u * u + m * m)) / (np.pi * np.sqrt(u * u + m * m)),
+            0, np.inf, weight="sin", wvar=b, limlst=200)
+        ft = 2 * (inner + tail)
+        assert abs(ft - N * nufft.psi_hat_kb(l, N, m, b)) <= 1e-9 * ft, (m, l)
+
+
+def test_kb_window_values():
+    m, b = 4, nufft.kb_shape(2)
+    tau = np.array([-m - 0.5, -m, -1.0, 0.0, 2.5, m])
+    v = nufft.psi_kb(tau, m, b)
+    assert v[0] == 0.0
+    assert np.isclose(v[1], b / np.pi) and np.isclose(v[5], b / np.pi)
+    assert np.isclose(v[3], np.sinh(b * m) / (np.pi * m))
+    assert np.isclose(v[2], np.sinh(b * np.sqrt(15.0)) / (np.pi * np.sqrt(15.0)))
+
+
+@pytest.mark.parametrize("m", [2, 3, 4, 5])
+def test_kb_composite_error_within_bound(m):
+    """R3 with the Kaiser-Bessel window against the definition (R2) on the
+    icosphere L3: within the univariate bound of eq. error_bound_nufft, and far
+    below the Gaussian's error at the same m."""
+    wl = make_workload("sphere_l3", m)
+    p = direct.prepare_workload(wl)
+    ref = direct.phi_ndft(p)
+    e_kb = np.linalg.norm(nufft.phi_nufft(p, m, window="kb") - ref) / np.linalg.norm(ref)
+    e_g = np.linalg.norm(nufft.phi_nufft(p, m) - ref) / np.linalg.norm(ref)
+    assert e_kb <= _kb_bound(m)
+    assert e_kb < 0.1 * e_g
