@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--window", choices=["gauss", "kb"], default="gauss",
+                    help="Gaussian (default m: 8 FP64, 5 FP32) or Kaiser-Bessel (4 FP64, 3 FP32)")
     ap.add_argument("--workload", default="cube64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true")
@@ -290,12 +292,17 @@ def main():
         torch.cuda.synchronize()
         del src_c, dst_c
     prec = slp.FP64 if args.precision == "fp64" else slp.FP32
-    m = args.m if args.m is not None else (8 if prec == slp.FP64 else 5)
+    kb = args.window == "kb"
+    if args.m is not None:
+        m = args.m
+    else:
+        m = (4 if prec == slp.FP64 else 3) if kb else (8 if prec == slp.FP64 else 5)
     wl = make_workload(args.workload, m)
     esz = 8 if prec == slp.FP64 else 4
     w, g = slp.expsum_sinc(wl.es_h, wl.es_r_lo, wl.es_r_hi, wl.es_tol)
     stream = torch.cuda.current_stream()
-    geom = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2)
+    geom = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2,
+                        window=slp.WINDOW_KB if kb else slp.WINDOW_GAUSS)
     info = dict(geom.info)
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     dens = torch.as_tensor(wl.dens, device="cuda")
@@ -400,8 +407,10 @@ def main():
         "config": {"workload": f"{wl.name}: unit cube 64x64 cells per face, {wl.tris.shape[0]} "
                                f"triangles, {wl.n_nodes} nodes, {wl.n_src} quadrature sources, "
                                f"grid {wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]}, alpha 2, "
-                               f"Gaussian cut-off m={m}" if args.workload == "cube64" else wl.name,
-                   "m": m, "precision": args.precision, "points": pts, "densities_per_step": nb},
+                               f"{'Kaiser-Bessel' if kb else 'Gaussian'} window cut-off m={m}"
+                               if args.workload == "cube64" else wl.name,
+                   "m": m, "window": args.window, "precision": args.precision, "points": pts,
+                   "densities_per_step": nb},
         "rel_l2_err_vs_oracle": rel_err,
         "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
         "roofline": roofline,

@@ -56,6 +56,14 @@ typedef enum { SLP_FP64 = 0, SLP_FP32 = 1 } slp_precision;
 
 /* Parameters of one geometry (Alg. 1, Require line: n in 2N^3, alpha >= 2,
  * cut-off m; and the exponential sum of Sec. 3.3). */
+/* Window of the gridding and the NFFT (Sec. 3.2). Gaussian: exp(-tau^2 / b)
+ * in grid units, b = 2 alpha m / ((2 alpha - 1) pi). Kaiser-Bessel (eq. KBfct):
+ * sinh(b sqrt(m^2 - tau^2)) / sqrt(m^2 - tau^2) for |tau| <= m, b = pi (2 - 1/alpha),
+ * whose error decays much faster in m (eq. error_bound_nufft). Both are
+ * truncated to the 2m grid points floor(t) - m + 1 .. floor(t) + m per axis;
+ * the deconvolution uses each window's Fourier coefficients (eq. cFB for KB). */
+typedef enum { SLP_WINDOW_GAUSS = 0, SLP_WINDOW_KB = 1 } slp_window;
+
 typedef struct {
   int32_t grid[3];        /* oversampled grid N_q = alpha * n_q; n_q even; power of two, 8..2048 */
   int32_t alpha;          /* oversampling factor alpha >= 2 (the paper fixes 2) */
@@ -66,7 +74,7 @@ typedef struct {
   const double *es_w;     /* host [es_terms]: exponential-sum weights omega_t (physical units) */
   const double *es_gamma; /* host [es_terms]: exponents gamma_t, 1/r ~ sum omega_t e^{-gamma_t r^2} */
   int32_t es_terms;       /* number of terms S (>= 1) */
-  int32_t reserved0;
+  int32_t window;         /* slp_window: SLP_WINDOW_GAUSS (0) or SLP_WINDOW_KB (1), Sec. 3.2 */
   double eta2;            /* keep term t iff (pi n_q/2)^2 s_q^2 / gamma_t >= eta2 on every axis
                              (Sec. 5, eq. error_est3: eta^2 bounds the Fourier tail); 37 by default */
 } slp_params;
@@ -77,7 +85,8 @@ typedef struct slp_geom slp_geom;   /* opaque; owns device tables and work buffe
 typedef struct {
   double centre[3];       /* body centre c (bounding-box midpoint) */
   double scale[3];        /* x~ = s (x - c); s_q N_q equal on all axes, body in [-0.2, 0.2]^3 */
-  double window_b;        /* Gaussian shape b = 2 alpha m / ((2 alpha - 1) pi), grid units */
+  double window_b;        /* window shape b: Gaussian 2 alpha m / ((2 alpha - 1) pi) (grid
+                             units), Kaiser-Bessel pi (2 - 1/alpha) (eq. KBfct) */
   int64_t n_nodes, n_tris, n_src;
   int32_t terms_kept;     /* S' after the eta2 truncation */
   int32_t lo[3];          /* first grid index of the region touched by any stencil */

@@ -15,12 +15,13 @@ import numpy as np
 __all__ = [
     "SlpError", "load_library", "expsum_sinc", "setup_geometry", "set_density",
     "set_density_from_m", "eval_single_layer", "eval_batched", "geom_get_info", "set_timing", "stage_times",
-    "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "STAGES",
+    "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "WINDOW_GAUSS", "WINDOW_KB", "STAGES",
     "geometry_device_bytes", "server_create", "server_add_geometry", "server_submit",
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
 ]
 
 FP64, FP32 = 0, 1
+WINDOW_GAUSS, WINDOW_KB = 0, 1
 STAGES = ("spread_bins", "spread_reduce", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv", "fft_x_inv",
           "interp")
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,7 +38,7 @@ class Params(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32 * 3), ("alpha", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("es_w", ctypes.POINTER(ctypes.c_double)),
                 ("es_gamma", ctypes.POINTER(ctypes.c_double)), ("es_terms", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("eta2", ctypes.c_double)]
+                ("window", ctypes.c_int32), ("eta2", ctypes.c_double)]
 
 
 class GeomInfo(ctypes.Structure):
@@ -145,7 +146,7 @@ def expsum_sinc(h, r_lo, r_hi, tol):
     return w, g
 
 
-def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2):
+def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, window=0):
     nodes = np.ascontiguousarray(nodes, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     if nodes.ndim != 2 or nodes.shape[1] != 3 or tris.ndim != 2 or tris.shape[1] != 3:
@@ -161,15 +162,16 @@ def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2):
     p.es_gamma = es_gamma.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.es_terms = int(es_w.size)
     p.eta2 = float(eta2)
+    p.window = int(window)
     return nodes, tris, es_w, es_gamma, p     # arrays kept alive by the caller
 
 
 def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
-                   stream=None):
+                   stream=None, window=WINDOW_GAUSS):
     """slp_setup_geometry: returns an opaque handle (int)."""
     lib = load_library()
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                              precision, eta2)
+                                              precision, eta2, window)
     h = _VP()
     _check(lib.slp_setup_geometry(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
                                   tris.ctypes.data, tris.shape[0], ctypes.byref(p),
@@ -178,11 +180,11 @@ def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64
 
 
 def geometry_device_bytes(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                          eta2=37.0):
+                          eta2=37.0, window=WINDOW_GAUSS):
     """slp_geometry_device_bytes: device bytes a context would hold (host only)."""
     lib = load_library()
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                              precision, eta2)
+                                              precision, eta2, window)
     out = ctypes.c_int64(0)
     _check(lib.slp_geometry_device_bytes(nodes.ctypes.data, nodes.shape[0], tris.ctypes.data,
                                          tris.shape[0], ctypes.byref(p), ctypes.byref(out)))
@@ -197,9 +199,9 @@ def server_create(device_budget_bytes, n_slots):
 
 
 def server_add_geometry(server, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                        eta2=37.0):
+                        eta2=37.0, window=WINDOW_GAUSS):
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                              precision, eta2)
+                                              precision, eta2, window)
     gid = ctypes.c_int64(-1)
     _check(load_library().slp_server_add_geometry(_VP(server), nodes.ctypes.data, nodes.shape[0],
                                                   tris.ctypes.data, tris.shape[0],
@@ -316,9 +318,9 @@ class Geometry:
     """Owning wrapper around one slp_geom context."""
 
     def __init__(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                 eta2=37.0, stream=None):
+                 eta2=37.0, stream=None, window=WINDOW_GAUSS):
         self.handle = setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision,
-                                     eta2, stream)
+                                     eta2, stream, window)
         self.info = geom_get_info(self.handle)
         self.precision = precision
 
@@ -357,9 +359,9 @@ class Server:
         self.handle = server_create(device_budget_bytes, n_slots)
 
     def add_geometry(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                     eta2=37.0):
+                     eta2=37.0, window=WINDOW_GAUSS):
         return server_add_geometry(self.handle, nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                   precision, eta2)
+                                   precision, eta2, window)
 
     def submit(self, geom_id, dens, phi):
         return server_submit(self.handle, geom_id, dens, phi)

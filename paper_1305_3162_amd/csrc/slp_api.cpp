@@ -96,7 +96,9 @@ void slp::set_error_message(const char *msg) { g_err = msg; }
 struct slp_geom {
   int prec = SLP_FP64;
   int N[3]{}, n[3]{}, alpha = 2, m = 4;
-  double b = 0.0;
+  double b = 0.0;                // window shape
+  int32_t window = SLP_WINDOW_GAUSS;
+  double kb_inv_norm = 1.0;      // m / sinh(b m) (Kaiser-Bessel scaled to 1 at tau = 0)
   double c[3]{}, s[3]{};
   int64_t n_nodes = 0, n_tris = 0, n_src = 0;
   int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
@@ -190,6 +192,8 @@ int validate_params(const slp_params *p) {
     return fail(SLP_EINVAL, "m must be in [1, %d] (got %d)", slp::kMaxM, p->m);
   if (p->precision != SLP_FP64 && p->precision != SLP_FP32)
     return fail(SLP_EINVAL, "precision must be SLP_FP64 or SLP_FP32");
+  if (p->window != SLP_WINDOW_GAUSS && p->window != SLP_WINDOW_KB)
+    return fail(SLP_EINVAL, "window must be SLP_WINDOW_GAUSS or SLP_WINDOW_KB");
   for (int q = 0; q < 3; ++q) {
     const int N = p->grid[q];
     if (!is_pow2(N) || N < 8 || N > 2048)
@@ -297,6 +301,9 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     a.scratch_bstride = G->item_elems[0];
     a.inv_b = (T)(1.0 / G->b);
     a.step_ratio = (T)std::exp(-2.0 / G->b);
+    a.window = G->window;
+    a.kb_b = (T)G->b;
+    a.kb_inv_norm = (T)G->kb_inv_norm;
     slp::SpreadReduceArgs<T> r{};
     r.scratch = static_cast<const T *>(G->scratch);
     r.tile_slots = G->tile_slots;
@@ -391,6 +398,9 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     }
     a.nt = G->n_nodes;
     a.inv_b = (T)(1.0 / G->b);
+    a.window = G->window;
+    a.kb_b = (T)G->b;
+    a.kb_inv_norm = (T)G->kb_inv_norm;
     HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
   }
   if (tm) {
@@ -505,7 +515,16 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   G->prec = p->precision;
   G->alpha = p->alpha;
   G->m = p->m;
-  G->b = 2.0 * p->alpha * p->m / ((2.0 * p->alpha - 1.0) * 3.141592653589793238462643383279502884);
+  {
+    const double pi = 3.141592653589793238462643383279502884;
+    G->window = p->window;
+    if (p->window == SLP_WINDOW_GAUSS) {
+      G->b = 2.0 * p->alpha * p->m / ((2.0 * p->alpha - 1.0) * pi);
+    } else {
+      G->b = pi * (2.0 - 1.0 / p->alpha);
+      G->kb_inv_norm = p->m / std::sinh(G->b * p->m);
+    }
+  }
   G->n_nodes = n_nodes;
   G->n_tris = n_tris;
   G->n_src = 3 * n_tris;
@@ -846,6 +865,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
         talloc(&d_C[1], (size_t)S * L[1]) != hipSuccess || talloc(&d_C[2], (size_t)S * L[2]) != hipSuccess)
       return fail(SLP_ENOMEM, "device allocation for kernel tables failed");
     std::vector<double> gl(2 * order), gsc(3 * (size_t)S);
+    std::vector<double> dec_host[3];
     for (int j = 0; j < order; ++j) { gl[j] = glx[j]; gl[order + j] = glw[j]; }
     for (int q = 0; q < 3; ++q)
       for (int t = 0; t < S; ++t) gsc[(size_t)q * S + t] = gam[t] / (G->s[q] * G->s[q]);
@@ -856,10 +876,35 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       const int panels = std::max(G->n[q] / 2 + 8, 16);
       HIP_TRY(slp::launch_chat(d_C[q], d_gam + (size_t)q * S, S, L[q], d_gl, d_gl + order, order, panels, st));
     }
+    // per-axis deconvolution factors 1 / u^(l / N)^2 of the window the kernels
+    // evaluate (u^ its Fourier transform in grid units): Gaussian exp(-tau^2 / b)
+    // -> sqrt(pi b) exp(-pi^2 b w^2); Kaiser-Bessel sinh(b s) / s * inv_norm ->
+    // pi inv_norm I_0(m sqrt(b^2 - (2 pi w)^2)) (eq. cFB)
+    double *d_dec[3] = {nullptr, nullptr, nullptr};
+    for (int q = 0; q < 3; ++q) {
+      if (talloc(&d_dec[q], L[q]) != hipSuccess)
+        return fail(SLP_ENOMEM, "device allocation for kernel tables failed");
+      const double pi = 3.141592653589793238462643383279502884;
+      std::vector<double> &dec = dec_host[q];
+      dec.resize(L[q]);
+      for (int l = 0; l < L[q]; ++l) {
+        const double w = (double)l / G->N[q];
+        double uhat;
+        if (G->window == SLP_WINDOW_GAUSS)
+          uhat = std::sqrt(pi * G->b) * std::exp(-pi * pi * G->b * w * w);
+        else
+          uhat = pi * G->kb_inv_norm *
+                 std::cyl_bessel_i(0.0, G->m * std::sqrt(G->b * G->b - 4.0 * pi * pi * w * w));
+        dec[l] = 1.0 / (uhat * uhat);
+      }
+      HIP_TRY(hipMemcpyAsync(d_dec[q], dec.data(), dec.size() * 8, hipMemcpyHostToDevice, st));
+    }
     if (G->prec == SLP_FP64)
-      HIP_TRY(slp::launch_mu<double>((double *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->N, G->K, G->b, st));
+      HIP_TRY(slp::launch_mu<double>((double *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->K,
+                                     d_dec[0], d_dec[1], d_dec[2], st));
     else
-      HIP_TRY(slp::launch_mu<float>((float *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->N, G->K, G->b, st));
+      HIP_TRY(slp::launch_mu<float>((float *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->K,
+                                    d_dec[0], d_dec[1], d_dec[2], st));
     HIP_TRY(hipStreamSynchronize(st));
   }
   HIP_TRY(hipStreamSynchronize(st));

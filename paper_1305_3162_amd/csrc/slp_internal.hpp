@@ -46,6 +46,9 @@ struct SpreadBinsArgs {
   int64_t scratch_bstride;   // per batch item (blockIdx.y)
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
   T step_ratio;          // exp(-2 / b): ratio of consecutive weight ratios
+  int32_t window;        // 0 Gaussian (recurrence), 1 Kaiser-Bessel
+  T kb_b;                // b of the Kaiser-Bessel window
+  T kb_inv_norm;         // m / sinh(b m): the KB window scaled to 1 at tau = 0
 };
 
 // Sum of the padded blocks of the segments in the neighbouring tiles into the
@@ -73,6 +76,8 @@ struct InterpArgs {
   int32_t tiles[3];
   int64_t nt;
   T inv_b;
+  int32_t window;
+  T kb_b, kb_inv_norm;
 };
 
 // One batched 1-D FFT pass over "lines" of a 3-D array. Element e of line L is
@@ -130,9 +135,12 @@ hipError_t launch_density_from_m(const int32_t *tri_v, const double *tri_n, cons
 hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t L,
                        const double *gl_x, const double *gl_w, int32_t order, int32_t panels,
                        hipStream_t s);
+// mu_l = h(l) c_l dec_x[|l_x|] dec_y[|l_y|] dec_z[|l_z|] / (4 pi), with dec_q the
+// per-axis deconvolution factors 1 / u^(l_q / N_q)^2 of the window (FP64 tables
+// of n_q/2 + 1 entries each).
 template <typename T>
 hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2,
-                     const double *omega, int32_t S, const int32_t n[3], const int32_t N[3],
-                     const int32_t K[3], double b, hipStream_t s);
+                     const double *omega, int32_t S, const int32_t n[3], const int32_t K[3],
+                     const double *dec0, const double *dec1, const double *dec2, hipStream_t s);
 
 }  // namespace slp

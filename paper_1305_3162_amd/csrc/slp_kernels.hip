@@ -23,6 +23,18 @@ struct Cplx<double> { using type = double2; };
 __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
+// Kaiser-Bessel window of eq. KBfct in grid units, scaled to 1 at tau = 0:
+// sinh(b s) / s * inv_norm with s = sqrt(m^2 - tau^2) (|tau| <= m on every
+// stencil point; the limit b at s = 0).
+template <typename T>
+__device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
+  const T s2 = m * m - tau * tau;
+  const T s = s2 > T(0) ? sqrt(s2) : T(0);
+  if (s < T(1e-4)) return b * inv_norm;
+  const T e = wexp(b * s);
+  return (e - T(1) / e) * T(0.5) / s * inv_norm;
+}
+
 // ----------------------------------------------------------------- spread ---
 // Phase A (one workgroup of 8 or 16 waves per work unit, a run of the sorted
 // sources of nearly equal length for every unit): the sources of each segment
@@ -182,19 +194,32 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
         for (int j = 0; j < W; ++j) acc[p][j] = T(0);
       for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
         const int n = min(S::SBW, cnt - c0);
-        if (lane < 3 * n) {
-          const int ax = lane / n, sl = lane - ax * n;
-          const int si = off + c0 + sl;
-          const T f = src[ax][si] + T(M - 1);
-          T w = wexp(-f * f * a.inv_b);
-          T rr = wexp((T(2) * f - T(1)) * a.inv_b);
-          if (ax == 0) w *= src[3][si];
-          T *dst = ww + sl * S::WST + ax * W;
+        if (a.window == 0) {
+          // Gaussian: w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b), two exponentials per axis
+          if (lane < 3 * n) {
+            const int ax = lane / n, sl = lane - ax * n;
+            const int si = off + c0 + sl;
+            const T f = src[ax][si] + T(M - 1);
+            T w = wexp(-f * f * a.inv_b);
+            T rr = wexp((T(2) * f - T(1)) * a.inv_b);
+            if (ax == 0) w *= src[3][si];
+            T *dst = ww + sl * S::WST + ax * W;
 #pragma unroll
-          for (int j = 0; j < W; ++j) {
-            dst[j] = w;
-            w *= rr;
-            rr *= a.step_ratio;
+            for (int j = 0; j < W; ++j) {
+              dst[j] = w;
+              w *= rr;
+              rr *= a.step_ratio;
+            }
+          }
+        } else {
+          // Kaiser-Bessel: every lane evaluates stencil points directly
+          for (int idx = lane; idx < 3 * n * W; idx += 64) {
+            const int j = idx % W, rest = idx / W;
+            const int ax = rest / n, sl = rest - ax * n;
+            const int si = off + c0 + sl;
+            T w = kb_weight<T>(src[ax][si] + T(M - 1 - j), T(M), a.kb_b, a.kb_inv_norm);
+            if (ax == 0) w *= src[3][si];
+            ww[sl * S::WST + ax * W + j] = w;
           }
         }
         wave_sync();
@@ -397,10 +422,16 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
       else if (kind == 6) tperm[item] = ci;
       else {
         const int ax = kind - 3;
+        if (a.window == 0) {
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
-          const T d = fr - T(j - M + 1);
-          wts[item][ax][j] = wexp(-d * d * a.inv_b);
+          for (int j = 0; j < W; ++j) {
+            const T d = fr - T(j - M + 1);
+            wts[item][ax][j] = wexp(-d * d * a.inv_b);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < W; ++j)
+            wts[item][ax][j] = kb_weight<T>(fr - T(j - M + 1), T(M), a.kb_b, a.kb_inv_norm);
         }
       }
     }
@@ -756,7 +787,8 @@ hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t
 template <typename T>
 __global__ void k_mu(T *mu, const double *__restrict__ C0, const double *__restrict__ C1,
                      const double *__restrict__ C2, const double *__restrict__ omega, int32_t S,
-                     int3 n, int3 N, int3 K, double b) {
+                     int3 n, int3 K, const double *__restrict__ dec0,
+                     const double *__restrict__ dec1, const double *__restrict__ dec2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t tot = (int64_t)K.x * K.y * K.z;
   if (i >= tot) return;
@@ -776,21 +808,19 @@ __global__ void k_mu(T *mu, const double *__restrict__ C0, const double *__restr
     for (int t = 0; t < S; ++t)
       c += omega[t] * C0[(int64_t)t * Lx + ax] * C1[(int64_t)t * Ly + ay] * C2[(int64_t)t * Lz + az];
     const double pi = 3.141592653589793238462643383279502884;
-    const double ex = (double)kx / N.x, ey = (double)ky / N.y, ez = (double)kz / N.z;
-    const double dec = exp(2.0 * b * pi * pi * (ex * ex + ey * ey + ez * ez));
-    v = h * c * dec / (pi * b * pi * b * pi * b) / (4.0 * pi);
+    v = h * c * dec0[ax] * dec1[ay] * dec2[az] / (4.0 * pi);
   }
   mu[i] = (T)v;
 }
 
 template <typename T>
 hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2,
-                     const double *omega, int32_t S, const int32_t n[3], const int32_t N[3],
-                     const int32_t K[3], double b, hipStream_t s) {
+                     const double *omega, int32_t S, const int32_t n[3], const int32_t K[3],
+                     const double *dec0, const double *dec1, const double *dec2, hipStream_t s) {
   const int64_t tot = (int64_t)K[0] * K[1] * K[2];
   hipLaunchKernelGGL(k_mu<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, mu, C0, C1, C2,
-                     omega, S, make_int3(n[0], n[1], n[2]), make_int3(N[0], N[1], N[2]),
-                     make_int3(K[0], K[1], K[2]), b);
+                     omega, S, make_int3(n[0], n[1], n[2]), make_int3(K[0], K[1], K[2]), dec0,
+                     dec1, dec2);
   return hipGetLastError();
 }
 
@@ -809,9 +839,9 @@ template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStrea
 template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,
                                      const double *, int32_t, const int32_t *, const int32_t *,
-                                     const int32_t *, double, hipStream_t);
+                                     const double *, const double *, const double *, hipStream_t);
 template hipError_t launch_mu<double>(double *, const double *, const double *, const double *,
                                       const double *, int32_t, const int32_t *, const int32_t *,
-                                      const int32_t *, double, hipStream_t);
+                                      const double *, const double *, const double *, hipStream_t);
 
 }  // namespace slp

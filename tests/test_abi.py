@@ -88,3 +88,13 @@ def test_unresolved_expsum_rejected():
     # a single very sharp term cannot be resolved by an 8-point tensor grid
     with pytest.raises(slp.SlpError, match="no exponential-sum term"):
         slp.setup_geometry(nodes, tris, (16,) * 3, 1, np.array([1.0]), np.array([1e9]), stream=0)
+
+
+def test_setup_rejects_unknown_window():
+    nodes, tris = icosphere(1)
+    w, g = _es()
+    with pytest.raises(slp.SlpError, match="window"):
+        slp.setup_geometry(nodes, tris, (64,) * 3, 4, w, g, stream=0, window=2)
+    # the Kaiser-Bessel window is accepted (host-only dry run)
+    assert slp.geometry_device_bytes(nodes, tris, (64,) * 3, 4, w, g,
+                                     window=slp.WINDOW_KB) > 0
