@@ -370,6 +370,7 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
   __shared__ T gt[S::P3];
   __shared__ T wts[S::TB][3][W];
   __shared__ int32_t tcell[S::TB][3];
+  __shared__ T tfrac[S::TB][3];
   __shared__ int32_t tperm[S::TB];
 
   const int tid = threadIdx.x;
@@ -420,20 +421,16 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
     if (item < nb && kind < 7) {
       if (kind < 3) tcell[item][kind] = ci;
       else if (kind == 6) tperm[item] = ci;
-      else {
-        const int ax = kind - 3;
-        if (a.window == 0) {
-#pragma unroll
-          for (int j = 0; j < W; ++j) {
-            const T d = fr - T(j - M + 1);
-            wts[item][ax][j] = wexp(-d * d * a.inv_b);
-          }
-        } else {
-#pragma unroll
-          for (int j = 0; j < W; ++j)
-            wts[item][ax][j] = kb_weight<T>(fr - T(j - M + 1), T(M), a.kb_b, a.kb_inv_norm);
-        }
-      }
+      else tfrac[item][kind - 3] = fr;
+    }
+    __syncthreads();
+    // the 1-D window factors of the batch, one stencil point per thread
+    for (int idx = tid; idx < nb * 3 * W; idx += S::THREADS) {
+      const int j = idx % W, rest = idx / W;
+      const int ax = rest % 3, it = rest / 3;
+      const T d = tfrac[it][ax] - T(j - M + 1);
+      wts[it][ax][j] = a.window == 0 ? wexp(-d * d * a.inv_b)
+                                     : kb_weight<T>(d, T(M), a.kb_b, a.kb_inv_norm);
     }
     __syncthreads();
     for (int s = wave; s < nb; s += S::WAVES) {
