@@ -90,6 +90,24 @@ def algorithmic_units(stage, info, m, esz):
     raise KeyError(stage)
 
 
+def measured_traffic(args, m, stage, nb):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (profiles/traffic_cube64.json, counters scaled by
+    a 256 MiB copy), or None when no run covers this configuration or the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_cube64.json")
+    if stage != "spread_bins" or nb != 1 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    e = rec["entries"].get(f"{args.workload}/{args.precision}/{args.window}/m{m}")
+    return None if e is None else e["bytes_per_launch"]
+
+
 def serve(args):
     """Served mix: Poisson arrivals over resident geometries (icosphere L3-L6, cubes
     16-256 cells per edge), fresh seeded magnetisation per request drawn from a pool
@@ -362,7 +380,8 @@ def main():
         peak = PEAK["f64_vector_TFLOPs"] if prec == slp.FP64 else PEAK["f32_vector_TFLOPs"]
         runit = "TFLOP/s"
     roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,
-                "frac": round(achieved / peak, 5), "traffic": None, "kernel": dom,
+                "frac": round(achieved / peak, 5),
+                "traffic": measured_traffic(args, m, dom, nb), "kernel": dom,
                 "avg_launch_us": round(avg[dom] * 1e3, 3)}
 
     out_phi = phi.cpu().numpy()
@@ -391,6 +410,29 @@ def main():
                                       f"{wl.n_src} sources and {wl.n_nodes} nodes of the same "
                                       f"workload, {reps} solves in {t_cpu:.2f} s"}
 
+    # the same solve with the Kaiser-Bessel window of Sec. 3.2 at the cut-off that
+    # meets the same precision gate (FP64 m = 4, FP32 m = 3), for comparison
+    alt = None
+    if args.window == "gauss" and nb == 1 and not args.no_oracle:
+        mk = 4 if prec == slp.FP64 else 3
+        gk = slp.Geometry(wl.nodes, wl.tris, wl.grid, mk, w, g, wl.alpha, prec, wl.eta2,
+                          window=slp.WINDOW_KB)
+        pk = torch.empty_like(phi)
+        for _ in range(args.warmup):
+            gk.set_density(dens, stream)
+            gk.eval(pk, stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            gk.set_density(dens, stream)
+            gk.eval(pk, stream)
+        torch.cuda.synchronize()
+        tk = (time.perf_counter() - t1) / args.steps
+        ek = float(np.linalg.norm(pk.cpu().numpy() - ref) / np.linalg.norm(ref))
+        gk.close()
+        alt = {"window": "kb", "m": mk, "value": round(pts / tk, 1), "ms_per_step": round(tk * 1e3, 5),
+               "rel_l2_err_vs_oracle": ek}
+
     rec = {
         "metric": "SL-potential NUFFT (M+N) pts/s at stated rel err",
         "value": round(value, 1),
@@ -415,6 +457,7 @@ def main():
         "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
+        "kaiser_bessel_same_gate": alt,
     }
     print(json.dumps(rec), flush=True)
     geom.close()
