@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--window", choices=["gauss", "kb"], default="gauss",
                     help="Gaussian (default m: 8 FP64, 5 FP32) or Kaiser-Bessel (4 FP64, 3 FP32)")
     ap.add_argument("--workload", default="cube64")
+    ap.add_argument("--volume-targets", action="store_true",
+                    help="cube64 only: evaluate at all (65^3) nodes of the structured "
+                         "tetrahedral mesh of the cube instead of the boundary nodes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--batch", type=int, default=1,
@@ -76,7 +79,7 @@ def algorithmic_units(stage, info, m, esz):
     if stage == "spread_reduce":
         return R[0] * R[1] * R[2] * esz, "byte", "hbm"
     if stage == "interp":
-        return info["n_nodes"] * (2.0 * w ** 3 + w ** 2), "flop", "alu"
+        return info["n_targets"] * (2.0 * w ** 3 + w ** 2), "flop", "alu"
     if stage == "fft_x_fwd":
         return R[2] * R[1] * (R[0] * esz + Kx * c), "byte", "hbm"
     if stage == "fft_y_fwd":
@@ -319,12 +322,19 @@ def main():
     esz = 8 if prec == slp.FP64 else 4
     w, g = slp.expsum_sinc(wl.es_h, wl.es_r_lo, wl.es_r_hi, wl.es_tol)
     stream = torch.cuda.current_stream()
+    targets = None
+    if args.volume_targets:
+        from synth import cube_volume_nodes
+        if args.workload != "cube64":
+            sys.exit("bench.py: --volume-targets needs the cube64 workload")
+        targets = cube_volume_nodes(64)
     geom = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2,
-                        window=slp.WINDOW_KB if kb else slp.WINDOW_GAUSS)
+                        window=slp.WINDOW_KB if kb else slp.WINDOW_GAUSS, targets=targets)
+    n_tgt = geom.info["n_targets"]
     info = dict(geom.info)
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     dens = torch.as_tensor(wl.dens, device="cuda")
-    phi = torch.empty(wl.n_nodes, dtype=torch.float64, device="cuda")
+    phi = torch.empty(n_tgt, dtype=torch.float64, device="cuda")
     nb = max(1, args.batch)
     if nb > 1:
         from synth import RandomSmoothMagnetisation, density_from_magnetisation
@@ -364,7 +374,7 @@ def main():
     slp.set_timing(geom.handle, False)
     gpu_ms = ev0.elapsed_time(ev1)
     ms_per_step = max(wall * 1e3, gpu_ms) / args.steps
-    pts = (wl.n_src + wl.n_nodes) * nb
+    pts = (wl.n_src + n_tgt) * nb
     value = pts / (ms_per_step * 1e-3)
     avg = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
 
@@ -389,7 +399,8 @@ def main():
     cpu_baseline = None
     if not args.no_oracle:
         from oracle import direct
-        p = direct.prepare_workload(wl)
+        p = direct.prepare(wl.nodes, wl.tris, wl.dens, wl.grid, wl.alpha, wl.es_h, wl.es_r_lo,
+                           wl.es_r_hi, wl.es_tol, wl.eta2, targets=targets)
         # whole solves of the oracle until about 10 s of CPU time have passed
         reps, t_cpu = 0, 0.0
         while reps == 0 or (t_cpu < 10.0 and not args.no_cpu_baseline):
@@ -407,7 +418,7 @@ def main():
             cpu_baseline = {"value": round(pts * reps / t_cpu, 2), "unit": "pts/s",
                             "cores": cores, "kind": "oracle",
                             "sample": f"oracle NDFT route of the definition over all "
-                                      f"{wl.n_src} sources and {wl.n_nodes} nodes of the same "
+                                      f"{wl.n_src} sources and {n_tgt} targets of the same "
                                       f"workload, {reps} solves in {t_cpu:.2f} s"}
 
     # the same solve with the Kaiser-Bessel window of Sec. 3.2 at the cut-off that
@@ -416,7 +427,7 @@ def main():
     if args.window == "gauss" and nb == 1 and not args.no_oracle:
         mk = 4 if prec == slp.FP64 else 3
         gk = slp.Geometry(wl.nodes, wl.tris, wl.grid, mk, w, g, wl.alpha, prec, wl.eta2,
-                          window=slp.WINDOW_KB)
+                          window=slp.WINDOW_KB, targets=targets)
         pk = torch.empty_like(phi)
         for _ in range(args.warmup):
             gk.set_density(dens, stream)
@@ -446,10 +457,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == slp.FP64 else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: unit cube 64x64 cells per face, {wl.tris.shape[0]} "
-                               f"triangles, {wl.n_nodes} nodes, {wl.n_src} quadrature sources, "
-                               f"grid {wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]}, alpha 2, "
-                               f"{'Kaiser-Bessel' if kb else 'Gaussian'} window cut-off m={m}"
+        "config": {"workload": (f"{wl.name}: unit cube 64x64 cells per face, {wl.tris.shape[0]} "
+                                f"triangles, {wl.n_nodes} nodes, {wl.n_src} quadrature sources, "
+                                + (f"{n_tgt} targets (all nodes of the structured tetrahedral "
+                                   f"mesh), " if targets is not None else "")
+                                + f"grid {wl.grid[0]}x{wl.grid[1]}x{wl.grid[2]}, alpha 2, "
+                                f"{'Kaiser-Bessel' if kb else 'Gaussian'} window cut-off m={m}")
                                if args.workload == "cube64" else wl.name,
                    "m": m, "window": args.window, "precision": args.precision, "points": pts,
                    "densities_per_step": nb},

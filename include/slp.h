@@ -88,6 +88,7 @@ typedef struct {
   double window_b;        /* window shape b: Gaussian 2 alpha m / ((2 alpha - 1) pi) (grid
                              units), Kaiser-Bessel pi (2 - 1/alpha) (eq. KBfct) */
   int64_t n_nodes, n_tris, n_src;
+  int64_t n_targets;      /* evaluation points (n_nodes unless set up with targets) */
   int32_t terms_kept;     /* S' after the eta2 truncation */
   int32_t lo[3];          /* first grid index of the region touched by any stencil */
   int32_t extent[3];      /* its length per axis */
@@ -110,6 +111,17 @@ typedef struct {
 int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes,
                        const int32_t *tris, int64_t n_tris, const slp_params *p,
                        void *stream);
+
+/* As slp_setup_geometry, but the potential is evaluated at the given points
+ * instead of the boundary nodes: the paper evaluates phi at every node of the
+ * tetrahedral volume mesh (Sec. 2, Tables 3-4), which only changes the target
+ * list of the interpolation. The body (its nodes) still sets the scaling.
+ *   targets : host float64 [n_targets][3], physical coordinates
+ * Errors as slp_setup_geometry; EINVAL also for non-finite targets and for
+ * targets whose stencil would leave the grid (far outside the body's box). */
+int slp_setup_geometry_targets(slp_geom **out, const double *nodes, int64_t n_nodes,
+                               const int32_t *tris, int64_t n_tris, const double *targets,
+                               int64_t n_targets, const slp_params *p, void *stream);
 
 /* Device bytes slp_setup_geometry would hold for these arguments, computed on
  * the host without touching a device (same validation and errors). Used for
@@ -139,15 +151,16 @@ int slp_set_density(slp_geom *g, const double *dens, void *stream);
 int slp_set_density_from_m(slp_geom *g, const double *m_nodes, const double *dphi1_dn,
                            void *stream);
 
-/* phi_s at every node for the charges of the last slp_set_density
+/* phi_s at every target for the charges of the last slp_set_density
  * (computation phase of Alg. 1, smooth part).
- *   phi : device float64 [n_nodes], written in the caller's node order,
- *         physical units (the 1/(4 pi) of the Newton kernel included). */
+ *   phi : device float64 [n_targets] (= n_nodes unless the context was set up
+ *         with separate targets), written in the caller's order, physical
+ *         units (the 1/(4 pi) of the Newton kernel included). */
 int slp_eval_single_layer(slp_geom *g, double *phi, void *stream);
 
 /* Batched evaluation: item b uses geometry geoms[b], density dens[b] (device
  * float64 [3 * n_tris(geoms[b])]) and writes phi[b] (device float64
- * [n_nodes(geoms[b])]). Repeating one geometry evaluates several densities on
+ * [n_targets(geoms[b])]). Repeating one geometry evaluates several densities on
  * one mesh. Items run in order on `stream`; equal to calling set_density +
  * eval for each item. geoms/dens/phi are host arrays of length batch >= 1. */
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,

@@ -55,7 +55,10 @@ class Problem:
 
 
 def prepare(nodes, tris, dens, grid, alpha=2, es_h=0.2, es_r_lo=None, es_r_hi=None,
-            es_tol=1e-12, eta2=37.0):
+            es_tol=1e-12, eta2=37.0, targets=None):
+    """The problem instance. The potential is evaluated at the nodes, or at
+    `targets` [P, 3] (e.g. all nodes of a volume mesh); the scaling always
+    follows the body's nodes."""
     nodes = np.asarray(nodes, dtype=np.float64)
     grid = np.asarray(grid, dtype=np.int64)
     if np.any(grid % alpha) or np.any((grid // alpha) % 2):
@@ -66,7 +69,8 @@ def prepare(nodes, tris, dens, grid, alpha=2, es_h=0.2, es_r_lo=None, es_r_hi=No
     om, ga = kernel.expsum_sinc(es_h, es_r_lo, es_r_hi, es_tol)
     om, ga = kernel.truncate(om, ga, s, n, eta2)
     C = kernel.separable_coefficients(om, ga, s, n)
-    return Problem(y=y, w=w, g=np.asarray(dens, dtype=np.float64), x=nodes, c=c, s=s,
+    x = nodes if targets is None else np.asarray(targets, dtype=np.float64)
+    return Problem(y=y, w=w, g=np.asarray(dens, dtype=np.float64), x=x, c=c, s=s,
                    grid=grid, n=n, alpha=int(alpha), omega=om, gamma=ga, C=C)
 
 

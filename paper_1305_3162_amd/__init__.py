@@ -45,7 +45,7 @@ class GeomInfo(ctypes.Structure):
     _fields_ = [("centre", ctypes.c_double * 3), ("scale", ctypes.c_double * 3),
                 ("window_b", ctypes.c_double), ("n_nodes", ctypes.c_int64),
                 ("n_tris", ctypes.c_int64), ("n_src", ctypes.c_int64),
-                ("terms_kept", ctypes.c_int32), ("lo", ctypes.c_int32 * 3),
+                ("n_targets", ctypes.c_int64), ("terms_kept", ctypes.c_int32), ("lo", ctypes.c_int32 * 3),
                 ("extent", ctypes.c_int32 * 3), ("tiles", ctypes.c_int32 * 3),
                 ("device_bytes", ctypes.c_int64)]
 
@@ -75,6 +75,9 @@ def load_library():
     sig = {
         "slp_setup_geometry": [ctypes.POINTER(_VP), _VP, ctypes.c_int64, _VP, ctypes.c_int64,
                                ctypes.POINTER(Params), _VP],
+        "slp_setup_geometry_targets": [ctypes.POINTER(_VP), _VP, ctypes.c_int64, _VP,
+                                       ctypes.c_int64, _VP, ctypes.c_int64,
+                                       ctypes.POINTER(Params), _VP],
         "slp_set_density": [_VP, _VP, _VP],
         "slp_set_density_from_m": [_VP, _VP, _VP, _VP],
         "slp_eval_single_layer": [_VP, _VP, _VP],
@@ -167,15 +170,25 @@ def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, windo
 
 
 def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
-                   stream=None, window=WINDOW_GAUSS):
-    """slp_setup_geometry: returns an opaque handle (int)."""
+                   stream=None, window=WINDOW_GAUSS, targets=None):
+    """slp_setup_geometry (slp_setup_geometry_targets when `targets` [P, 3] is given):
+    returns an opaque handle (int)."""
     lib = load_library()
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
                                               precision, eta2, window)
     h = _VP()
-    _check(lib.slp_setup_geometry(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
-                                  tris.ctypes.data, tris.shape[0], ctypes.byref(p),
-                                  _stream_ptr(stream)))
+    if targets is None:
+        _check(lib.slp_setup_geometry(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
+                                      tris.ctypes.data, tris.shape[0], ctypes.byref(p),
+                                      _stream_ptr(stream)))
+    else:
+        targets = np.ascontiguousarray(targets, dtype=np.float64)
+        if targets.ndim != 2 or targets.shape[1] != 3:
+            raise ValueError("targets must be [P, 3]")
+        _check(lib.slp_setup_geometry_targets(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
+                                              tris.ctypes.data, tris.shape[0],
+                                              targets.ctypes.data, targets.shape[0],
+                                              ctypes.byref(p), _stream_ptr(stream)))
     return h.value
 
 
@@ -259,7 +272,7 @@ def set_density_from_m(geom, m_nodes, dphi1_dn=None, stream=None):
 
 def eval_single_layer(geom, phi, stream=None):
     info = geom_get_info(geom)
-    _check(load_library().slp_eval_single_layer(_VP(geom), _dev_f64(phi, info["n_nodes"], "phi"),
+    _check(load_library().slp_eval_single_layer(_VP(geom), _dev_f64(phi, info["n_targets"], "phi"),
                                                 _stream_ptr(stream)))
 
 
@@ -276,7 +289,7 @@ def eval_batched(geoms, dens, phis, stream=None):
         if info is None:
             info = infos[g] = geom_get_info(g)
         D[i] = _dev_f64(dens[i], info["n_src"], f"dens[{i}]").value
-        P[i] = _dev_f64(phis[i], info["n_nodes"], f"phi[{i}]").value
+        P[i] = _dev_f64(phis[i], info["n_targets"], f"phi[{i}]").value
     _check(load_library().slp_eval_batched(G, D, P, n, _stream_ptr(stream)))
 
 
@@ -285,6 +298,7 @@ def geom_get_info(geom):
     _check(load_library().slp_geom_get_info(_VP(geom), ctypes.byref(gi)))
     return {"centre": list(gi.centre), "scale": list(gi.scale), "window_b": gi.window_b,
             "n_nodes": gi.n_nodes, "n_tris": gi.n_tris, "n_src": gi.n_src,
+            "n_targets": gi.n_targets,
             "terms_kept": gi.terms_kept, "lo": list(gi.lo), "extent": list(gi.extent),
             "tiles": list(gi.tiles), "device_bytes": gi.device_bytes}
 
@@ -318,9 +332,9 @@ class Geometry:
     """Owning wrapper around one slp_geom context."""
 
     def __init__(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                 eta2=37.0, stream=None, window=WINDOW_GAUSS):
+                 eta2=37.0, stream=None, window=WINDOW_GAUSS, targets=None):
         self.handle = setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision,
-                                     eta2, stream, window)
+                                     eta2, stream, window, targets)
         self.info = geom_get_info(self.handle)
         self.precision = precision
 
@@ -335,7 +349,7 @@ class Geometry:
 
     def solve(self, dens, stream=None):
         import torch
-        phi = torch.empty(self.info["n_nodes"], dtype=torch.float64, device=dens.device)
+        phi = torch.empty(self.info["n_targets"], dtype=torch.float64, device=dens.device)
         self.set_density(dens, stream)
         self.eval(phi, stream)
         return phi

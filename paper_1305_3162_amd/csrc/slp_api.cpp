@@ -101,6 +101,7 @@ struct slp_geom {
   double kb_inv_norm = 1.0;      // m / sinh(b m) (Kaiser-Bessel scaled to 1 at tau = 0)
   double c[3]{}, s[3]{};
   int64_t n_nodes = 0, n_tris = 0, n_src = 0;
+  int64_t n_tgt = 0;             // evaluation points (the nodes unless given separately)
   int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
   int32_t terms_kept = 0;
   int32_t n_slots = 0;           // segments (padded gridding blocks)
@@ -233,7 +234,7 @@ int upload_tables(slp_geom *G, const std::vector<double> &ts, const std::vector<
                   hipStream_t st, std::vector<int32_t> &cellbuf_s, std::vector<T> &fracbuf_s,
                   std::vector<int32_t> &cellbuf_t, std::vector<T> &fracbuf_t) {
   split_coords<T>(ts, sorder, G->lo, G->n_src, cellbuf_s, fracbuf_s);
-  split_coords<T>(tt, torder, G->lo, G->n_nodes, cellbuf_t, fracbuf_t);
+  split_coords<T>(tt, torder, G->lo, G->n_tgt, cellbuf_t, fracbuf_t);
   HIP_TRY(hipMemcpyAsync(G->src_frac, fracbuf_s.data(), fracbuf_s.size() * sizeof(T), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_cell, cellbuf_t.data(), cellbuf_t.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_frac, fracbuf_t.data(), fracbuf_t.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -396,7 +397,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
       a.R[i] = G->R[i];
       a.tiles[i] = G->tiles[i];
     }
-    a.nt = G->n_nodes;
+    a.nt = G->n_tgt;
     a.inv_b = (T)(1.0 / G->b);
     a.window = G->window;
     a.kb_b = (T)G->b;
@@ -480,16 +481,26 @@ namespace {
 // Setup phase. With dry_bytes != NULL only the host part runs and the device
 // bytes the context would hold are returned (no device call is made).
 int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32_t *tris,
-               int64_t n_tris, const slp_params *p, void *stream, int64_t *dry_bytes) {
+               int64_t n_tris, const double *targets, int64_t n_tgt, const slp_params *p,
+               void *stream, int64_t *dry_bytes) {
   if (!out && !dry_bytes) return fail(SLP_EINVAL, "out is NULL");
   if (out) *out = nullptr;
   int rc = validate_params(p);
   if (rc) return rc;
   if (!nodes || !tris || n_nodes < 3 || n_tris < 1)
     return fail(SLP_EINVAL, "need >= 3 nodes and >= 1 triangle");
+  if (!targets) {
+    targets = nodes;
+    n_tgt = n_nodes;
+  }
+  if (n_tgt < 1) return fail(SLP_EINVAL, "need >= 1 target point");
   if (3 * n_tris > (int64_t)std::numeric_limits<int32_t>::max() ||
-      n_nodes > (int64_t)std::numeric_limits<int32_t>::max())
+      n_nodes > (int64_t)std::numeric_limits<int32_t>::max() ||
+      n_tgt > (int64_t)std::numeric_limits<int32_t>::max())
     return fail(SLP_EINVAL, "mesh too large for 32-bit indices");
+  for (int64_t i = 0; i < 3 * n_tgt; ++i)
+    if (!std::isfinite(targets[i]))
+      return fail(SLP_EINVAL, "target %lld has a non-finite coordinate", (long long)(i / 3));
   hipStream_t st = static_cast<hipStream_t>(stream);
 
   // bounding box, scaling into (-0.2, 0.2)^3 with s_q N_q equal on every axis
@@ -526,6 +537,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     }
   }
   G->n_nodes = n_nodes;
+  G->n_tgt = n_tgt;
   G->n_tris = n_tris;
   G->n_src = 3 * n_tris;
   double Kmin = INFINITY;
@@ -541,7 +553,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
 
   // quadrature sources (k = j + s M) and grid-unit coordinates t = (x~ + 1/2) N
   const int64_t M = n_tris, Ms = G->n_src;
-  std::vector<double> ts(3 * Ms), wsrc(Ms), tt(3 * n_nodes), tnrm(3 * M);
+  std::vector<double> ts(3 * Ms), wsrc(Ms), tt(3 * n_tgt), tnrm(3 * M);
   std::vector<int32_t> tv(3 * M);
   const double bary[3][3] = {{4.0 / 6, 1.0 / 6, 1.0 / 6}, {1.0 / 6, 4.0 / 6, 1.0 / 6}, {1.0 / 6, 1.0 / 6, 4.0 / 6}};
   for (int64_t j = 0; j < M; ++j) {
@@ -566,9 +578,9 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       }
     }
   }
-  for (int64_t i = 0; i < n_nodes; ++i)
+  for (int64_t i = 0; i < n_tgt; ++i)
     for (int q = 0; q < 3; ++q)
-      tt[3 * i + q] = ((nodes[3 * i + q] - G->c[q]) * G->s[q] + 0.5) * G->N[q];
+      tt[3 * i + q] = ((targets[3 * i + q] - G->c[q]) * G->s[q] + 0.5) * G->N[q];
 
   // region touched by any stencil {floor(t) - m + 1 .. floor(t) + m}
   int64_t cmin[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, cmax[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
@@ -581,7 +593,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       }
   };
   upd(ts, Ms);
-  upd(tt, n_nodes);
+  upd(tt, n_tgt);
   for (int q = 0; q < 3; ++q) {
     const int64_t rlo = cmin[q] - G->m + 1, rhi = cmax[q] + G->m;
     if (rlo < 0 || rhi > G->N[q] - 1)
@@ -621,14 +633,14 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     *tile = id[0] + G->tiles[0] * (id[1] + G->tiles[1] * id[2]);
     *incell = in[0] | (in[1] << 4) | (in[2] << 8);
   };
-  std::vector<int32_t> skey(Ms), sincell(Ms), tbin(n_nodes), sorder, sstart, torder, tstart;
+  std::vector<int32_t> skey(Ms), sincell(Ms), tbin(n_tgt), sorder, sstart, torder, tstart;
   for (int64_t k = 0; k < Ms; ++k) {
     int32_t tile, inc;
     cell_key(&ts[3 * k], &tile, &inc);
     sincell[k] = inc;
     skey[k] = tile * 512 + ((inc & 7) + 8 * ((inc >> 4) & 7) + 64 * (inc >> 8));
   }
-  for (int64_t i = 0; i < n_nodes; ++i) {
+  for (int64_t i = 0; i < n_tgt; ++i) {
     int32_t tile, inc;
     cell_key(&tt[3 * i], &tile, &inc);
     tbin[i] = tile;
@@ -789,9 +801,9 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
       {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
       {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
-      {reinterpret_cast<void **>(&G->tgt_cell), (size_t)(3 * n_nodes) * 4},
-      {&G->tgt_frac, (size_t)(3 * n_nodes) * e},
-      {reinterpret_cast<void **>(&G->tgt_perm), (size_t)n_nodes * 4},
+      {reinterpret_cast<void **>(&G->tgt_cell), (size_t)(3 * n_tgt) * 4},
+      {&G->tgt_frac, (size_t)(3 * n_tgt) * e},
+      {reinterpret_cast<void **>(&G->tgt_perm), (size_t)n_tgt * 4},
       {&G->grid_a, (size_t)Gsz * e},
       {&G->S1, (size_t)S1n * 2 * e},
       {&G->S2, (size_t)S2n * 2 * e},
@@ -824,7 +836,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int2), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_nodes * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_tgt * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tri_v, tv.data(), tv.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tri_n, tnrm.data(), tnrm.size() * 8, hipMemcpyHostToDevice, st));
   std::vector<int32_t> cs, ct;
@@ -917,13 +929,20 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
 
 int slp_setup_geometry(slp_geom **out, const double *nodes, int64_t n_nodes, const int32_t *tris,
                        int64_t n_tris, const slp_params *p, void *stream) {
-  return setup_impl(out, nodes, n_nodes, tris, n_tris, p, stream, nullptr);
+  return setup_impl(out, nodes, n_nodes, tris, n_tris, nullptr, 0, p, stream, nullptr);
+}
+
+int slp_setup_geometry_targets(slp_geom **out, const double *nodes, int64_t n_nodes,
+                               const int32_t *tris, int64_t n_tris, const double *targets,
+                               int64_t n_targets, const slp_params *p, void *stream) {
+  if (!targets) return fail(SLP_EINVAL, "targets is NULL");
+  return setup_impl(out, nodes, n_nodes, tris, n_tris, targets, n_targets, p, stream, nullptr);
 }
 
 int slp_geometry_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,
                               int64_t n_tris, const slp_params *p, int64_t *bytes) {
   if (!bytes) return fail(SLP_EINVAL, "bytes is NULL");
-  return setup_impl(nullptr, nodes, n_nodes, tris, n_tris, p, nullptr, bytes);
+  return setup_impl(nullptr, nodes, n_nodes, tris, n_tris, nullptr, 0, p, nullptr, bytes);
 }
 
 int slp_set_density(slp_geom *G, const double *dens, void *stream) {
@@ -1071,6 +1090,7 @@ int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
   }
   info->window_b = G->b;
   info->n_nodes = G->n_nodes;
+  info->n_targets = G->n_tgt;
   info->n_tris = G->n_tris;
   info->n_src = G->n_src;
   info->terms_kept = G->terms_kept;

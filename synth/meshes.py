@@ -102,6 +102,17 @@ def cube(cells_per_edge: int):
     return box_surface((1.0, 1.0, 1.0), (c, c, c))
 
 
+def cube_volume_nodes(cells_per_edge: int):
+    """Nodes of the structured tetrahedral mesh of the unit cube whose boundary
+    triangulation is cube(cells_per_edge): the (c+1)^3 lattice points of
+    [-1/2, 1/2]^3 (every lattice cell split into tetrahedra adds no node).
+    Its boundary points are exactly the nodes of cube(c)."""
+    c = int(cells_per_edge)
+    t = np.linspace(-0.5, 0.5, c + 1)
+    x, y, z = np.meshgrid(t, t, t, indexing="ij")
+    return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+
 def thin_film(cells_xy: int = 512, cells_z: int = 10, thickness: float = 0.02):
     """Thin film 1 x 1 x thickness: cells_xy^2 cells on the large faces and
     cells_xy x cells_z cells on each side face."""

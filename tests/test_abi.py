@@ -98,3 +98,15 @@ def test_setup_rejects_unknown_window():
     # the Kaiser-Bessel window is accepted (host-only dry run)
     assert slp.geometry_device_bytes(nodes, tris, (64,) * 3, 4, w, g,
                                      window=slp.WINDOW_KB) > 0
+
+
+def test_setup_targets_rejects_bad_points():
+    nodes, tris = icosphere(1)
+    w, g = _es()
+    bad = np.zeros((4, 3))
+    bad[2, 0] = np.inf
+    with pytest.raises(slp.SlpError, match="target 2 has a non-finite"):
+        slp.setup_geometry(nodes, tris, (64,) * 3, 4, w, g, stream=0, targets=bad)
+    far = np.array([[0.0, 0.0, 0.0], [40.0, 0.0, 0.0]])
+    with pytest.raises(slp.SlpError, match="outside the grid"):
+        slp.setup_geometry(nodes, tris, (64,) * 3, 4, w, g, stream=0, targets=far)

@@ -173,3 +173,22 @@ def test_radial_magnetisation_gives_zero_density():
                                   nrm), 3)
     p = direct.prepare(nodes, tris, np.zeros_like(g), (16, 16, 16), es_r_lo=2e-3, es_r_hi=2.0)
     assert np.all(direct.phi_ndft(p) == 0.0)
+
+
+def test_targets_off_the_surface_both_routes():
+    """R1 (pair sum) and R2 (NDFT) agree at volume lattice points inside the
+    cube, and at the nodes the targets option gives the default result."""
+    from synth import cube, cube_volume_nodes, RandomSmoothMagnetisation, density_from_magnetisation
+    nodes, tris = cube(4)
+    mf = RandomSmoothMagnetisation(17, nodes.min(0), nodes.max(0))
+    dens = density_from_magnetisation(nodes, tris, mf)
+    from synth.workloads import expsum_interval
+    r_lo, r_hi = expsum_interval(nodes)
+    kw = dict(es_r_lo=r_lo, es_r_hi=r_hi)
+    tg = cube_volume_nodes(4)
+    p = direct.prepare(nodes, tris, dens, (32, 32, 32), targets=tg, **kw)
+    a, b = direct.phi_pairs(p), direct.phi_ndft(p)
+    assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+    p0 = direct.prepare(nodes, tris, dens, (32, 32, 32), **kw)
+    p1 = direct.prepare(nodes, tris, dens, (32, 32, 32), targets=nodes, **kw)
+    assert np.array_equal(direct.phi_ndft(p0), direct.phi_ndft(p1))

@@ -129,3 +129,14 @@ def test_density_p1_divergence_theorem(mesh):
     vol = _closed_volume(nodes, tris)
     g = geometry.density_p1(nodes, tris, nodes)
     assert np.isclose(area @ g[:M], 3.0 * vol, rtol=1e-13)
+
+
+def test_cube_volume_nodes():
+    from synth import cube_volume_nodes
+    for c in (2, 5, 16):
+        v = cube_volume_nodes(c)
+        assert v.shape == ((c + 1) ** 3, 3)
+        nodes, _ = cube(c)
+        on_boundary = v[np.any(np.isclose(np.abs(v), 0.5), axis=1)]
+        key = lambda a: set(map(tuple, np.round(a * 2 * c).astype(int)))
+        assert key(on_boundary) == key(nodes)
