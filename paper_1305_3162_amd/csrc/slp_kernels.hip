@@ -23,6 +23,16 @@ struct Cplx<double> { using type = double2; };
 __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
+// Value of v in lane j (j the same on every lane), as a wave-uniform value.
+__device__ __forceinline__ float read_lane(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ double read_lane(double v, int j) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
+  return __hiloint2double(hi, lo);
+}
+
 // Kaiser-Bessel window of eq. KBfct in grid units, scaled to 1 at tau = 0:
 // sinh(b s) / s * inv_norm with s = sqrt(m^2 - tau^2) (|tau| <= m on every
 // stencil point; the limit b at s = 0).
@@ -382,8 +392,32 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
   const int64_t Rx = a.R[0], Ry = a.R[1];
   const T *gsrc = a.g + blockIdx.y * a.g_bstride;
   double *phi = ptrs.phi[blockIdx.y];
+  const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int64_t nt = a.nt;
+  // target data of a batch (3 cells, 3 fractions, permutation), loaded into
+  // registers one batch ahead so that its latency overlaps the previous batch
+  constexpr int LPT = (7 * S::TB + S::THREADS - 1) / S::THREADS;
+  int32_t ci[LPT];
+  T fr[LPT];
+  auto load_batch = [&](int b0) {
+    const int nb = min(S::TB, t1 - b0);
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int idx = tid + k * S::THREADS;
+      const int item = idx % S::TB, kind = idx / S::TB;   // kind 0..2 cell, 3..5 frac, 6 perm
+      ci[k] = 0;
+      fr[k] = T(0);
+      if (item < nb && kind < 7) {
+        const int64_t i = b0 + item;
+        if (kind < 3) ci[k] = a.cell[kind * nt + i];
+        else if (kind < 6) fr[k] = a.frac[(kind - 3) * nt + i];
+        else ci[k] = a.perm[i];
+      }
+    }
+  };
   {
-    // issue all loads of the tile + halo before writing LDS
+    // issue all loads of the tile + halo and of the first batch before writing LDS
     T v[S::PERG];
 #pragma unroll
     for (int k = 0; k < S::PERG; ++k) {
@@ -396,33 +430,27 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
           v[k] = gsrc[((int64_t)gz * Ry + gy) * Rx + gx];
       }
     }
+    load_batch(t0);
 #pragma unroll
     for (int k = 0; k < S::PERG; ++k) {
       const int i = tid + k * S::THREADS;
       if (i < S::P3) gt[i] = v[k];
     }
   }
-  const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int64_t nt = a.nt;
   for (int b0 = t0; b0 < t1; b0 += S::TB) {
     const int nb = min(S::TB, t1 - b0);
-    // target data of the batch: 3 cells, 3 fractions, permutation (one load per thread)
-    int32_t ci = 0;
-    T fr = T(0);
-    const int item = tid % S::TB, kind = tid / S::TB;   // kind 0..2 cell, 3..5 frac, 6 perm
-    if (item < nb && kind < 7) {
-      const int64_t i = b0 + item;
-      if (kind < 3) ci = a.cell[kind * nt + i];
-      else if (kind < 6) fr = a.frac[(kind - 3) * nt + i];
-      else ci = a.perm[i];
-    }
     __syncthreads();   // grid tile loaded / previous batch finished
-    if (item < nb && kind < 7) {
-      if (kind < 3) tcell[item][kind] = ci;
-      else if (kind == 6) tperm[item] = ci;
-      else tfrac[item][kind - 3] = fr;
+#pragma unroll
+    for (int k = 0; k < LPT; ++k) {
+      const int idx = tid + k * S::THREADS;
+      const int item = idx % S::TB, kind = idx / S::TB;
+      if (item < nb && kind < 7) {
+        if (kind < 3) tcell[item][kind] = ci[k];
+        else if (kind == 6) tperm[item] = ci[k];
+        else tfrac[item][kind - 3] = fr[k];
+      }
     }
+    if (b0 + S::TB < t1) load_batch(b0 + S::TB);
     __syncthreads();
     // the 1-D window factors of the batch, one stencil point per thread
     for (int idx = tid; idx < nb * 3 * W; idx += S::THREADS) {
@@ -433,13 +461,23 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
                                      : kb_weight<T>(d, T(M), a.kb_b, a.kb_inv_norm);
     }
     __syncthreads();
-    for (int s = wave; s < nb; s += S::WAVES) {
+    // each wave takes TPW targets of the batch and reduces their sums together,
+    // so the latency of the cross-lane reduction is paid once per TPW targets
+    constexpr int TPW = S::TB / S::WAVES;
+    double acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+      const int s = wave + q * S::WAVES;
+      acc[q] = 0.0;
+      if (s >= nb) continue;
       const int cx = tcell[s][0] - tx * kTile, cy = tcell[s][1] - ty * kTile,
                 cz = tcell[s][2] - tz * kTile;
+      // x factors are the same for every lane: one LDS read per lane, then
+      // moved to scalar registers (readlane) instead of W LDS broadcasts
+      const T wxl = wts[s][0][lane % W];
       T wx[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) wx[j] = wts[s][0][j];
-      double acc = 0.0;
+      for (int j = 0; j < W; ++j) wx[j] = read_lane(wxl, j);
       for (int r = lane; r < W * W; r += 64) {
         const int dy = r % W, dz = r / W;
         const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
@@ -449,11 +487,19 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
           s0 += row[j] * wx[j];
           s1 += row[j + 1] * wx[j + 1];
         }
-        acc += (double)((s0 + s1) * (wts[s][1][dy] * wts[s][2][dz]));
+        acc[q] += (double)((s0 + s1) * (wts[s][1][dy] * wts[s][2][dz]));
       }
+    }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) phi[tperm[s]] = acc;
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) acc[q] += __shfl_xor(acc[q], o);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < TPW; ++q) {
+        const int s = wave + q * S::WAVES;
+        if (s < nb) phi[tperm[s]] = acc[q];
+      }
     }
   }
 }
