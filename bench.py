@@ -47,6 +47,8 @@ def parse():
                          "tetrahedral mesh of the cube instead of the boundary nodes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the evaluation through a captured HIP graph")
     ap.add_argument("--batch", type=int, default=1,
                     help="densities per step on the one geometry (batched launch)")
     ap.add_argument("--serve", action="store_true",
@@ -352,6 +354,8 @@ def main():
             geom.set_density(dens, stream)
             geom.eval(phi, stream)
 
+    if args.graph:
+        slp.set_graph(geom.handle, True)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -378,21 +382,23 @@ def main():
     value = pts / (ms_per_step * 1e-3)
     avg = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel (graph replays record no stage events)
+    if cnt == 0:
+        avg = {k: 0.0 for k in avg}
     dom = max(avg, key=avg.get)
     amount, unit, bound = algorithmic_units(dom, info, m, esz)
     amount *= nb
-    dur_s = avg[dom] * 1e-3
+    dur_s = max(avg[dom] * 1e-3, 1e-12)
     if bound == "hbm":
         achieved, peak, runit = amount / dur_s / 1e9, PEAK["hbm_GBps"], "GB/s"
     else:
         achieved = amount / dur_s / 1e12
         peak = PEAK["f64_vector_TFLOPs"] if prec == slp.FP64 else PEAK["f32_vector_TFLOPs"]
         runit = "TFLOP/s"
-    roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,
-                "frac": round(achieved / peak, 5),
-                "traffic": measured_traffic(args, m, dom, nb), "kernel": dom,
-                "avg_launch_us": round(avg[dom] * 1e3, 3)}
+    roofline = None if cnt == 0 else {
+        "bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,
+        "frac": round(achieved / peak, 5), "traffic": measured_traffic(args, m, dom, nb),
+        "kernel": dom, "avg_launch_us": round(avg[dom] * 1e3, 3)}
 
     out_phi = phi.cpu().numpy()
     rel_err = None

@@ -168,6 +168,17 @@ int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *
 
 int slp_geom_get_info(const slp_geom *g, slp_geom_info *info);
 
+/* Replay evaluations through HIP graphs (enable != 0) or launch every kernel
+ * directly (0, the default). With graphs, the kernel sequence of one
+ * evaluation with a given number of batch items is captured once (on first
+ * use, on a stream of the context) and each later evaluation only updates the
+ * density and result pointers of the gridding and interpolation launches and
+ * launches the graph on the caller's stream: one submission instead of one per
+ * kernel. The results are those of direct launches. Stage timing
+ * (slp_set_timing) records only direct launches. Growing the batch capacity or
+ * switching graphs off drops the captured graphs (synchronising the device). */
+int slp_set_graph(slp_geom *g, int32_t enable);
+
 /* Per-stage device timing. With every = k >= 1, every k-th evaluation (one
  * single eval, or one launch group of slp_eval_batched) records HIP events
  * around each stage on its stream: 0 gridding into per-bin blocks (charges

@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "SlpError", "load_library", "expsum_sinc", "setup_geometry", "set_density",
-    "set_density_from_m", "eval_single_layer", "eval_batched", "geom_get_info", "set_timing", "stage_times",
+    "set_density_from_m", "eval_single_layer", "eval_batched", "geom_get_info", "set_graph", "set_timing", "stage_times",
     "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "WINDOW_GAUSS", "WINDOW_KB", "STAGES",
     "geometry_device_bytes", "server_create", "server_add_geometry", "server_submit",
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
@@ -84,6 +84,7 @@ def load_library():
         "slp_eval_batched": [_VP, _VP, _VP, ctypes.c_int32, _VP],
         "slp_geom_get_info": [_VP, ctypes.POINTER(GeomInfo)],
         "slp_set_timing": [_VP, ctypes.c_int32],
+        "slp_set_graph": [_VP, ctypes.c_int32],
         "slp_stage_times": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int32],
         "slp_debug_copy": [_VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP],
@@ -301,6 +302,11 @@ def geom_get_info(geom):
             "n_targets": gi.n_targets,
             "terms_kept": gi.terms_kept, "lo": list(gi.lo), "extent": list(gi.extent),
             "tiles": list(gi.tiles), "device_bytes": gi.device_bytes}
+
+
+def set_graph(geom, enable=True):
+    """Replay evaluations of this context through captured HIP graphs."""
+    _check(load_library().slp_set_graph(_VP(geom), int(bool(enable))))
 
 
 def set_timing(geom, every=1):

@@ -137,6 +137,24 @@ struct slp_geom {
   double *own_dens = nullptr;    // [3M] density formed by slp_set_density_from_m
   int64_t bytes = 0;
   std::vector<void *> allocs;
+  // captured evaluations, one per batch size (replayed when use_graph is set)
+  struct Captured {
+    int nb = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t spread_node = nullptr, interp_node = nullptr;
+    hipKernelNodeParams spread_p{}, interp_p{};
+  };
+  bool use_graph = false;
+  std::vector<Captured> graphs;
+  hipStream_t cap_stream = nullptr;
+  void drop_graphs() {
+    for (Captured &c : graphs) {
+      if (c.exec) (void)hipGraphExecDestroy(c.exec);
+      if (c.graph) (void)hipGraphDestroy(c.graph);
+    }
+    graphs.clear();
+  }
   // timing: a ring of event sets, one per evaluation, read back lazily
   static constexpr int kRing = 32;
   bool timing = false;
@@ -177,6 +195,8 @@ struct slp_geom {
   }
   std::vector<int64_t> alloc_bytes;
   ~slp_geom() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void *p : allocs) (void)hipFree(p);
     if (ev_ready)
       for (auto &set : ev)
@@ -263,6 +283,8 @@ int upload_twiddles(slp_geom *G, hipStream_t st, std::vector<std::vector<T>> &ho
 int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
   if (nb <= G->cap) return SLP_OK;
   HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
+  G->drop_graphs();                    // they hold the old buffer addresses
   void **bufs[5] = {&G->scratch, &G->grid_a, &G->S1, &G->S2, &G->grid_g};
   const size_t e = G->esz();
   const size_t per[5] = {e, e, 2 * e, 2 * e, e};
@@ -285,26 +307,54 @@ int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
 }
 
 template <typename T>
+slp::SpreadBinsArgs<T> spread_args(const slp_geom *G) {
+  slp::SpreadBinsArgs<T> a{};
+  a.frac = static_cast<const T *>(G->src_frac);
+  a.w = G->src_w;
+  a.perm = G->src_perm;
+  a.unit_segs = G->unit_segs;
+  a.seg_list = G->seg_list;
+  a.segs = G->segs;
+  a.chunks = G->chunks;
+  a.runs = G->runs;
+  a.scratch = static_cast<T *>(G->scratch);
+  a.ns = G->n_src;
+  a.scratch_bstride = G->item_elems[0];
+  a.inv_b = (T)(1.0 / G->b);
+  a.step_ratio = (T)std::exp(-2.0 / G->b);
+  a.window = G->window;
+  a.kb_b = (T)G->b;
+  a.kb_inv_norm = (T)G->kb_inv_norm;
+  return a;
+}
+
+template <typename T>
+slp::InterpArgs<T> interp_args(const slp_geom *G) {
+  slp::InterpArgs<T> a{};
+  a.cell = G->tgt_cell;
+  a.frac = static_cast<const T *>(G->tgt_frac);
+  a.perm = G->tgt_perm;
+  a.tile_start = G->tgt_tile_start;
+  a.active = G->tgt_active;
+  a.g = static_cast<const T *>(G->grid_g);
+  a.g_bstride = G->item_elems[4];
+  for (int i = 0; i < 3; ++i) {
+    a.R[i] = G->R[i];
+    a.tiles[i] = G->tiles[i];
+  }
+  a.nt = G->n_tgt;
+  a.inv_b = (T)(1.0 / G->b);
+  a.window = G->window;
+  a.kb_b = (T)G->b;
+  a.kb_inv_norm = (T)G->kb_inv_norm;
+  return a;
+}
+
+template <typename T>
 int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bool tm) {
   // spread (the charges q = w g are formed inside the gridding)
   {
-    slp::SpreadBinsArgs<T> a{};
-    a.frac = static_cast<const T *>(G->src_frac);
-    a.w = G->src_w;
-    a.perm = G->src_perm;
-    a.unit_segs = G->unit_segs;
-    a.seg_list = G->seg_list;
-    a.segs = G->segs;
-    a.chunks = G->chunks;
-    a.runs = G->runs;
-    a.scratch = static_cast<T *>(G->scratch);
-    a.ns = G->n_src;
-    a.scratch_bstride = G->item_elems[0];
-    a.inv_b = (T)(1.0 / G->b);
-    a.step_ratio = (T)std::exp(-2.0 / G->b);
-    a.window = G->window;
-    a.kb_b = (T)G->b;
-    a.kb_inv_norm = (T)G->kb_inv_norm;
+    const slp::SpreadBinsArgs<T> a = spread_args<T>(G);
     slp::SpreadReduceArgs<T> r{};
     r.scratch = static_cast<const T *>(G->scratch);
     r.tile_slots = G->tile_slots;
@@ -385,23 +435,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
   (void)nx;
   if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
   {
-    slp::InterpArgs<T> a{};
-    a.cell = G->tgt_cell;
-    a.frac = static_cast<const T *>(G->tgt_frac);
-    a.perm = G->tgt_perm;
-    a.tile_start = G->tgt_tile_start;
-    a.active = G->tgt_active;
-    a.g = static_cast<const T *>(G->grid_g);
-    a.g_bstride = G->item_elems[4];
-    for (int i = 0; i < 3; ++i) {
-      a.R[i] = G->R[i];
-      a.tiles[i] = G->tiles[i];
-    }
-    a.nt = G->n_tgt;
-    a.inv_b = (T)(1.0 / G->b);
-    a.window = G->window;
-    a.kb_b = (T)G->b;
-    a.kb_inv_norm = (T)G->kb_inv_norm;
+    const slp::InterpArgs<T> a = interp_args<T>(G);
     HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
   }
   if (tm) {
@@ -410,6 +444,84 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     G->cur = (G->cur + 1) % slp_geom::kRing;
   }
   return SLP_OK;
+}
+
+// Evaluation through a captured HIP graph: the kernel sequence of one
+// evaluation with nb items is captured once per batch size on a private stream;
+// a replay updates the per-item pointers of the gridding and interpolation
+// launches (their other arguments are rebuilt from the context, unchanged
+// since capture) and launches the graph on the caller's stream.
+template <typename T>
+int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
+  slp_geom::Captured *cg = nullptr;
+  for (slp_geom::Captured &c : G->graphs)
+    if (c.nb == nb) cg = &c;
+  if (!cg) {
+    if (!G->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking));
+    slp_geom::Captured c;
+    c.nb = nb;
+    HIP_TRY(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
+    const int rc = run_eval<T>(G, ptrs, nb, G->cap_stream, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(G->cap_stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    HIP_TRY(ec);
+    c.graph = graph;
+    size_t n = 0;
+    HIP_TRY(hipGraphGetNodes(graph, nullptr, &n));
+    std::vector<hipGraphNode_t> nodes(n);
+    HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &n));
+    const void *fs = slp::spread_bins_kernel<T>(G->m), *fi = slp::interp_kernel<T>(G->m);
+    for (hipGraphNode_t nd : nodes) {
+      hipGraphNodeType ty;
+      HIP_TRY(hipGraphNodeGetType(nd, &ty));
+      if (ty != hipGraphNodeTypeKernel) continue;
+      hipKernelNodeParams kp{};
+      HIP_TRY(hipGraphKernelNodeGetParams(nd, &kp));
+      if (kp.func == fs) { c.spread_node = nd; c.spread_p = kp; }
+      if (kp.func == fi) { c.interp_node = nd; c.interp_p = kp; }
+    }
+    if (!c.spread_node || !c.interp_node) {
+      (void)hipGraphDestroy(graph);
+      return fail(SLP_EDEVICE, "captured evaluation lacks the gridding or interpolation launch");
+    }
+    HIP_TRY(hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0));
+    G->graphs.push_back(c);
+    cg = &G->graphs.back();
+  }
+  slp::BatchPtrs p = ptrs;
+  slp::SpreadBinsArgs<T> sa = spread_args<T>(G);
+  slp::InterpArgs<T> ia = interp_args<T>(G);
+  void *sargs[2] = {&sa, &p};
+  void *iargs[2] = {&ia, &p};
+  hipKernelNodeParams kp = cg->spread_p;
+  kp.kernelParams = sargs;
+  kp.extra = nullptr;
+  HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->spread_node, &kp));
+  kp = cg->interp_p;
+  kp.kernelParams = iargs;
+  kp.extra = nullptr;
+  HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->interp_node, &kp));
+  HIP_TRY(hipGraphLaunch(cg->exec, st));
+  return SLP_OK;
+}
+
+int begin_timed(slp_geom *G, hipStream_t st);
+
+// One evaluation of nb items on the context's buffers: replayed graph or
+// direct launches (the latter also record the sampled stage events).
+template <typename T>
+int eval_items(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
+  if (G->use_graph) return run_graph<T>(G, ptrs, nb, st);
+  const bool tm = G->timing && (G->evals++ % G->every == 0);
+  if (tm) {
+    const int rc = begin_timed(G, st);
+    if (rc) return rc;
+  }
+  return run_eval<T>(G, ptrs, nb, st, tm);
 }
 
 int collect_one(slp_geom *G, int r) {
@@ -965,16 +1077,11 @@ int slp_eval_single_layer(slp_geom *G, double *phi, void *stream) {
   if (!G || !phi) return fail(SLP_EINVAL, "geometry and phi must be non-NULL");
   if (!G->dens) return fail(SLP_EINVAL, "no density set (slp_set_density)");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const bool tm = G->timing && (G->evals++ % G->every == 0);
-  if (tm) {
-    int rc = begin_timed(G, st);
-    if (rc) return rc;
-  }
   slp::BatchPtrs ptrs{};
   ptrs.dens[0] = G->dens;
   ptrs.phi[0] = phi;
-  return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, 1, st, tm)
-                             : run_eval<float>(G, ptrs, 1, st, tm);
+  return G->prec == SLP_FP64 ? eval_items<double>(G, ptrs, 1, st)
+                             : eval_items<float>(G, ptrs, 1, st);
 }
 
 namespace {
@@ -1016,13 +1123,8 @@ int run_group(slp_geom *G, const double *const *dens, double *const *phi, int nb
     ptrs.dens[i] = dens[i];
     ptrs.phi[i] = phi[i];
   }
-  const bool tm = G->timing && (G->evals++ % G->every == 0);
-  if (tm) {
-    rc = begin_timed(G, st);
-    if (rc) return rc;
-  }
-  return G->prec == SLP_FP64 ? run_eval<double>(G, ptrs, nb, st, tm)
-                             : run_eval<float>(G, ptrs, nb, st, tm);
+  return G->prec == SLP_FP64 ? eval_items<double>(G, ptrs, nb, st)
+                             : eval_items<float>(G, ptrs, nb, st);
 }
 
 }  // namespace
@@ -1095,6 +1197,16 @@ int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
   info->n_src = G->n_src;
   info->terms_kept = G->terms_kept;
   info->device_bytes = G->bytes;
+  return SLP_OK;
+}
+
+int slp_set_graph(slp_geom *G, int32_t enable) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (!enable && G->use_graph) {
+    HIP_TRY(hipDeviceSynchronize());
+    G->drop_graphs();
+  }
+  G->use_graph = enable != 0;
   return SLP_OK;
 }
 

@@ -122,6 +122,13 @@ int64_t pad_cells(int m);
 template <typename T>
 hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s);
 
+// Host handles of the two kernels that take the per-item pointers (their
+// launches are updated in place when a captured evaluation is replayed).
+template <typename T>
+const void *spread_bins_kernel(int m);
+template <typename T>
+const void *interp_kernel(int m);
+
 // Message returned by slp_last_error() on the calling thread.
 void set_error_message(const char *msg);
 

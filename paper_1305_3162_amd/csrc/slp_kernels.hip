@@ -867,7 +867,41 @@ hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2
   return hipGetLastError();
 }
 
+template <typename T>
+const void *spread_bins_kernel(int m) {
+  switch (m) {
+    case 1: return reinterpret_cast<const void *>(&k_spread_bins<T, 1>);
+    case 2: return reinterpret_cast<const void *>(&k_spread_bins<T, 2>);
+    case 3: return reinterpret_cast<const void *>(&k_spread_bins<T, 3>);
+    case 4: return reinterpret_cast<const void *>(&k_spread_bins<T, 4>);
+    case 5: return reinterpret_cast<const void *>(&k_spread_bins<T, 5>);
+    case 6: return reinterpret_cast<const void *>(&k_spread_bins<T, 6>);
+    case 7: return reinterpret_cast<const void *>(&k_spread_bins<T, 7>);
+    case 8: return reinterpret_cast<const void *>(&k_spread_bins<T, 8>);
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+const void *interp_kernel(int m) {
+  switch (m) {
+    case 1: return reinterpret_cast<const void *>(&k_interp<T, 1>);
+    case 2: return reinterpret_cast<const void *>(&k_interp<T, 2>);
+    case 3: return reinterpret_cast<const void *>(&k_interp<T, 3>);
+    case 4: return reinterpret_cast<const void *>(&k_interp<T, 4>);
+    case 5: return reinterpret_cast<const void *>(&k_interp<T, 5>);
+    case 6: return reinterpret_cast<const void *>(&k_interp<T, 6>);
+    case 7: return reinterpret_cast<const void *>(&k_interp<T, 7>);
+    case 8: return reinterpret_cast<const void *>(&k_interp<T, 8>);
+    default: return nullptr;
+  }
+}
+
 // explicit instantiations
+template const void *spread_bins_kernel<float>(int);
+template const void *spread_bins_kernel<double>(int);
+template const void *interp_kernel<float>(int);
+template const void *interp_kernel<double>(int);
 template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
                                          const SpreadReduceArgs<float> &, const BatchPtrs &, int,
                                          int, int, hipStream_t, hipEvent_t);
