@@ -163,119 +163,119 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   const int64_t ns = a.ns;
 
   for (int q = a.unit_segs[unit]; q < a.unit_segs[unit + 1]; ++q) {
-  const int sg = a.seg_list[q];
-  const int4 bc = a.segs[sg];
-  for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
-  for (int c = bc.x; c < bc.y; ++c) {
-    const int4 ch = a.chunks[c];     // {first source, count, first run, run count}
-    // issue every global load of the chunk before writing LDS
-    T v[S::PER];
-    int32_t rv = 0;
+    const int sg = a.seg_list[q];
+    const int4 bc = a.segs[sg];
+    for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
+    for (int c = bc.x; c < bc.y; ++c) {
+      const int4 ch = a.chunks[c];     // {first source, count, first run, run count}
+      // issue every global load of the chunk before writing LDS
+      T v[S::PER];
+      int32_t rv = 0;
 #pragma unroll
-    for (int k = 0; k < S::PER; ++k) {
-      const int i = tid + k * S::THREADS;
-      if (i < 4 * ch.y) {
-        const int comp = i / ch.y, sl = i - comp * ch.y;
-        const int64_t src = (int64_t)ch.x + sl;
-        v[k] = comp < 3 ? a.frac[comp * ns + src] : (T)(a.w[src] * dens[a.perm[src]]);
+      for (int k = 0; k < S::PER; ++k) {
+        const int i = tid + k * S::THREADS;
+        if (i < 4 * ch.y) {
+          const int comp = i / ch.y, sl = i - comp * ch.y;
+          const int64_t src = (int64_t)ch.x + sl;
+          v[k] = comp < 3 ? a.frac[comp * ns + src] : (T)(a.w[src] * dens[a.perm[src]]);
+        }
       }
-    }
-    if (tid < ch.w) rv = a.runs[ch.z + tid];
-    __syncthreads();                 // previous chunk finished with src / rrec
+      if (tid < ch.w) rv = a.runs[ch.z + tid];
+      __syncthreads();                 // previous chunk finished with src / rrec
 #pragma unroll
-    for (int k = 0; k < S::PER; ++k) {
-      const int i = tid + k * S::THREADS;
-      if (i < 4 * ch.y) {
-        const int comp = i / ch.y, sl = i - comp * ch.y;
-        src[comp][sl] = v[k];
+      for (int k = 0; k < S::PER; ++k) {
+        const int i = tid + k * S::THREADS;
+        if (i < 4 * ch.y) {
+          const int comp = i / ch.y, sl = i - comp * ch.y;
+          src[comp][sl] = v[k];
+        }
       }
-    }
-    if (tid < ch.w) rrec[tid] = rv;
-    __syncthreads();
+      if (tid < ch.w) rrec[tid] = rv;
+      __syncthreads();
 
-    for (int r = wave; r < ch.w; r += S::WAVES) {
-      const int rec = rrec[r];
-      const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
-      const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
-      T acc[NP][W];
+      for (int r = wave; r < ch.w; r += S::WAVES) {
+        const int rec = rrec[r];
+        const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
+        const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
+        T acc[NP][W];
 #pragma unroll
-      for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
-        for (int j = 0; j < W; ++j) acc[p][j] = T(0);
-      for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
-        const int n = min(S::SBW, cnt - c0);
-        if (a.window == 0) {
-          // Gaussian: w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b), two exponentials per axis
-          if (lane < 3 * n) {
-            const int ax = lane / n, sl = lane - ax * n;
-            const int si = off + c0 + sl;
-            const T f = src[ax][si] + T(M - 1);
-            T w = wexp(-f * f * a.inv_b);
-            T rr = wexp((T(2) * f - T(1)) * a.inv_b);
-            if (ax == 0) w *= src[3][si];
-            T *dst = ww + sl * S::WST + ax * W;
+          for (int j = 0; j < W; ++j) acc[p][j] = T(0);
+        for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
+          const int n = min(S::SBW, cnt - c0);
+          if (a.window == 0) {
+            // Gaussian: w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b), two exponentials per axis
+            if (lane < 3 * n) {
+              const int ax = lane / n, sl = lane - ax * n;
+              const int si = off + c0 + sl;
+              const T f = src[ax][si] + T(M - 1);
+              T w = wexp(-f * f * a.inv_b);
+              T rr = wexp((T(2) * f - T(1)) * a.inv_b);
+              if (ax == 0) w *= src[3][si];
+              T *dst = ww + sl * S::WST + ax * W;
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-              dst[j] = w;
-              w *= rr;
-              rr *= a.step_ratio;
+              for (int j = 0; j < W; ++j) {
+                dst[j] = w;
+                w *= rr;
+                rr *= a.step_ratio;
+              }
+            }
+          } else {
+            // Kaiser-Bessel: every lane evaluates stencil points directly
+            for (int idx = lane; idx < 3 * n * W; idx += 64) {
+              const int j = idx % W, rest = idx / W;
+              const int ax = rest / n, sl = rest - ax * n;
+              const int si = off + c0 + sl;
+              T w = kb_weight<T>(src[ax][si] + T(M - 1 - j), T(M), a.kb_b, a.kb_inv_norm);
+              if (ax == 0) w *= src[3][si];
+              ww[sl * S::WST + ax * W + j] = w;
             }
           }
-        } else {
-          // Kaiser-Bessel: every lane evaluates stencil points directly
-          for (int idx = lane; idx < 3 * n * W; idx += 64) {
-            const int j = idx % W, rest = idx / W;
-            const int ax = rest / n, sl = rest - ax * n;
-            const int si = off + c0 + sl;
-            T w = kb_weight<T>(src[ax][si] + T(M - 1 - j), T(M), a.kb_b, a.kb_inv_norm);
-            if (ax == 0) w *= src[3][si];
-            ww[sl * S::WST + ax * W + j] = w;
+          wave_sync();
+          for (int sl = 0; sl < n; ++sl) {
+            const T *f3 = ww + sl * S::WST;
+            T wz[W];
+#pragma unroll
+            for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              if (p == NP - 1 && !last_act) continue;
+              const T pw = f3[dxp[p]] * f3[W + dyp[p]];
+#pragma unroll
+              for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
+            }
           }
+          wave_sync();
         }
-        wave_sync();
-        for (int sl = 0; sl < n; ++sl) {
-          const T *f3 = ww + sl * S::WST;
-          T wz[W];
 #pragma unroll
-          for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
+        for (int p = 0; p < NP; ++p) {
+          if (p == NP - 1 && !last_act) continue;
+          double *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
 #pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            if (p == NP - 1 && !last_act) continue;
-            const T pw = f3[dxp[p]] * f3[W + dyp[p]];
-#pragma unroll
-            for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
-          }
+          for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[p][j]);
         }
-        wave_sync();
-      }
-#pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        if (p == NP - 1 && !last_act) continue;
-        double *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
-#pragma unroll
-        for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[p][j]);
       }
     }
-  }
-  __syncthreads();
-  T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)sg * S::P3;
-  {
-    // 32 lanes per pad row: x is fixed per thread, rows advance
-    const int x = tid & 31;
-    if (x < PD) {
-      int px, sx, lx;
-      pad_part<M>(x, px, sx, lx);
-      for (int rw = tid >> 5; rw < PD * PD; rw += S::THREADS / 32) {
-        const int y = rw % PD, z = rw / PD;
-        int py, sy, ly, pz, sz, lz;
-        pad_part<M>(y, py, sy, ly);
-        pad_part<M>(z, pz, sz, lz);
-        dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
-            (T)pad[rw * PD + x];
+    __syncthreads();
+    T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)sg * S::P3;
+    {
+      // 32 lanes per pad row: x is fixed per thread, rows advance
+      const int x = tid & 31;
+      if (x < PD) {
+        int px, sx, lx;
+        pad_part<M>(x, px, sx, lx);
+        for (int rw = tid >> 5; rw < PD * PD; rw += S::THREADS / 32) {
+          const int y = rw % PD, z = rw / PD;
+          int py, sy, ly, pz, sz, lz;
+          pad_part<M>(y, py, sy, ly);
+          pad_part<M>(z, pz, sz, lz);
+          dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
+              (T)pad[rw * PD + x];
+        }
       }
     }
-  }
-  __syncthreads();                   // block stored before the next segment clears it
+    __syncthreads();                   // block stored before the next segment clears it
   }
 }
 
