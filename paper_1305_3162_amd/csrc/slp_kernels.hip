@@ -296,24 +296,32 @@ __global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
   T *grid = a.grid + blockIdx.y * a.grid_bstride;
   const int c = threadIdx.x;
   const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
+  // the segment ranges of the 27 neighbouring tiles, read once per workgroup
+  __shared__ int2 nts[27];
+  if (c < 27) {
+    const int bx = tx + c % 3 - 1, by = ty + (c / 3) % 3 - 1, bz = tz + c / 9 - 1;
+    int2 ts = make_int2(0, 0);
+    if (bx >= 0 && bx < a.tiles[0] && by >= 0 && by < a.tiles[1] && bz >= 0 && bz < a.tiles[2])
+      ts = a.tile_slots[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
+    nts[c] = ts;
+  }
+  __syncthreads();
   T v = T(0);
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int bz = tz + dz;
-    const int iz = cz + kTile * (-dz) + M - 1;     // pad coordinate in the neighbour's block
-    if (bz < 0 || bz >= a.tiles[2] || iz < 0 || iz >= PD) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int by = ty + dy;
-      const int iy = cy + kTile * (-dy) + M - 1;
-      if (by < 0 || by >= a.tiles[1] || iy < 0 || iy >= PD) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int bx = tx + dx;
-        const int ix = cx + kTile * (-dx) + M - 1;
-        if (bx < 0 || bx >= a.tiles[0] || ix < 0 || ix >= PD) continue;
-        const int2 ts = a.tile_slots[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
-        const int off = pad_block_index<M>(ix, iy, iz);
-        for (int k = 0; k < ts.y; ++k) v += scr[(int64_t)(ts.x + k) * S::P3 + off];
-      }
-    }
+#pragma unroll
+  for (int d = 0; d < 27; ++d) {
+    const int2 ts = nts[d];
+    if (ts.y == 0) continue;
+    const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+    // pad coordinate of this cell in the neighbour's block
+    const int ix = cx - kTile * dx + M - 1, iy = cy - kTile * dy + M - 1, iz = cz - kTile * dz + M - 1;
+    if (ix < 0 || ix >= PD || iy < 0 || iy >= PD || iz < 0 || iz >= PD) continue;
+    const int off = pad_block_index<M>(ix, iy, iz);
+    // the first two segments without a loop, so that the loads of all
+    // neighbours can be issued before any of them is waited for
+    const T *p0 = scr + (int64_t)ts.x * S::P3 + off;
+    v += p0[0];
+    if (ts.y > 1) v += p0[S::P3];
+    for (int k = 2; k < ts.y; ++k) v += p0[(int64_t)k * S::P3];
   }
   grid[((tz * kTile + cz) * Py + ty * kTile + cy) * Px + tx * kTile + cx] = v;
 }
