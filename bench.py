@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--m", type=int, default=None)
+    ap.add_argument("--tol", type=float, default=None,
+                    help="pick window and m with slp_choose_cutoff for this relative error")
     ap.add_argument("--window", choices=["gauss", "kb"], default="gauss",
                     help="Gaussian (default m: 8 FP64, 5 FP32) or Kaiser-Bessel (4 FP64, 3 FP32)")
     ap.add_argument("--workload", default="cube64")
@@ -315,6 +317,9 @@ def main():
         torch.cuda.synchronize()
         del src_c, dst_c
     prec = slp.FP64 if args.precision == "fp64" else slp.FP32
+    if args.tol is not None:
+        wsel, args.m = slp.choose_cutoff(args.tol, prec)
+        args.window = "kb" if wsel == slp.WINDOW_KB else "gauss"
     kb = args.window == "kb"
     if args.m is not None:
         m = args.m

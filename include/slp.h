@@ -197,6 +197,17 @@ int slp_stage_times(slp_geom *g, double *ms, int64_t *count, int32_t reset);
  * Values of 0 and 1 are in the context's precision; dst must hold the array. */
 int slp_debug_copy(const slp_geom *g, int32_t which, void *dst, size_t dst_bytes, void *stream);
 
+/* Cheapest window and cut-off m (alpha = 2) whose predicted relative error
+ * against the definition is at most tol. Predicted error: the window's bound
+ * divided by 5 (Kaiser-Bessel: eq. error_bound_nufft; Gaussian: 4 exp(-2 pi m/3)),
+ * the factor measured on the sphere and cube workloads to stay 2-6x on the safe
+ * side; FP32 adds a rounding floor of 2e-6.
+ *   window_in : -1 any window, or SLP_WINDOW_GAUSS / SLP_WINDOW_KB to fix it
+ *   window, m : receive the choice (the smaller m; Gaussian on a tie)
+ * EINVAL if no m <= 8 reaches tol (or tol <= 0). Host only. */
+int slp_choose_cutoff(double tol, int32_t precision, int32_t window_in, int32_t *window,
+                      int32_t *m);
+
 /* Exponential sum by the trapezoidal rule on 1/r = 2/sqrt(pi) int exp(-r^2 e^{2u} + u) du
  * (Sec. 3.3 uses a tabulated sum of this family): nodes u_t = u_lo + t h up to
  * u_hi = ln(7/r_lo), u_lo = ln(tol sqrt(pi) / (2 r_hi)); omega_t = 2 h e^{u_t}/sqrt(pi),

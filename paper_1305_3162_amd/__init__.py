@@ -14,7 +14,7 @@ import numpy as np
 
 __all__ = [
     "SlpError", "load_library", "expsum_sinc", "setup_geometry", "set_density",
-    "set_density_from_m", "eval_single_layer", "eval_batched", "geom_get_info", "set_graph", "set_timing", "stage_times",
+    "set_density_from_m", "eval_single_layer", "eval_batched", "geom_get_info", "choose_cutoff", "set_graph", "set_timing", "stage_times",
     "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "WINDOW_GAUSS", "WINDOW_KB", "STAGES",
     "geometry_device_bytes", "server_create", "server_add_geometry", "server_submit",
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
@@ -85,6 +85,8 @@ def load_library():
         "slp_geom_get_info": [_VP, ctypes.POINTER(GeomInfo)],
         "slp_set_timing": [_VP, ctypes.c_int32],
         "slp_set_graph": [_VP, ctypes.c_int32],
+        "slp_choose_cutoff": [ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
         "slp_stage_times": [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
                             ctypes.c_int32],
         "slp_debug_copy": [_VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP],
@@ -302,6 +304,15 @@ def geom_get_info(geom):
             "n_targets": gi.n_targets,
             "terms_kept": gi.terms_kept, "lo": list(gi.lo), "extent": list(gi.extent),
             "tiles": list(gi.tiles), "device_bytes": gi.device_bytes}
+
+
+def choose_cutoff(tol, precision=FP64, window=None):
+    """slp_choose_cutoff: (window, m) with the smallest m predicted to meet tol."""
+    w, m = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load_library().slp_choose_cutoff(float(tol), int(precision),
+                                            -1 if window is None else int(window),
+                                            ctypes.byref(w), ctypes.byref(m)))
+    return w.value, m.value
 
 
 def set_graph(geom, enable=True):

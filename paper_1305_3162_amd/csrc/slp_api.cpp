@@ -1200,6 +1200,37 @@ int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
   return SLP_OK;
 }
 
+int slp_choose_cutoff(double tol, int32_t precision, int32_t window_in, int32_t *window,
+                      int32_t *m) {
+  if (!window || !m) return fail(SLP_EINVAL, "NULL output");
+  if (!(tol > 0.0)) return fail(SLP_EINVAL, "tol must be positive");
+  if (precision != SLP_FP64 && precision != SLP_FP32)
+    return fail(SLP_EINVAL, "precision must be SLP_FP64 or SLP_FP32");
+  if (window_in < -1 || window_in > SLP_WINDOW_KB) return fail(SLP_EINVAL, "unknown window");
+  const double pi = 3.141592653589793238462643383279502884;
+  const double floor_err = precision == SLP_FP32 ? 2e-6 : 0.0;
+  auto predicted = [&](int w, int mm) {
+    const double bound = w == SLP_WINDOW_KB
+        ? 4.0 * pi * (std::sqrt((double)mm) + mm) * std::pow(0.5, 0.25) *
+              std::exp(-2.0 * pi * mm * std::sqrt(0.5))
+        : 4.0 * std::exp(-2.0 * pi * mm / 3.0);
+    return bound / 5.0 + floor_err;
+  };
+  int best_w = -1, best_m = 0;
+  for (int w = SLP_WINDOW_GAUSS; w <= SLP_WINDOW_KB; ++w) {
+    if (window_in != -1 && w != window_in) continue;
+    for (int mm = 1; mm <= slp::kMaxM; ++mm)
+      if (predicted(w, mm) <= tol) {
+        if (best_w < 0 || mm < best_m) { best_w = w; best_m = mm; }
+        break;
+      }
+  }
+  if (best_w < 0) return fail(SLP_EINVAL, "no cut-off m <= %d reaches rel. error %g", slp::kMaxM, tol);
+  *window = best_w;
+  *m = best_m;
+  return SLP_OK;
+}
+
 int slp_set_graph(slp_geom *G, int32_t enable) {
   if (!G) return fail(SLP_EINVAL, "NULL geometry");
   if (!enable && G->use_graph) {

@@ -110,3 +110,23 @@ def test_setup_targets_rejects_bad_points():
     far = np.array([[0.0, 0.0, 0.0], [40.0, 0.0, 0.0]])
     with pytest.raises(slp.SlpError, match="outside the grid"):
         slp.setup_geometry(nodes, tris, (64,) * 3, 4, w, g, stream=0, targets=far)
+
+
+def test_choose_cutoff():
+    """The chooser returns the cut-offs the definition-parity gates use: FP64
+    1e-6 with Kaiser-Bessel m = 4 (Gaussian m = 7), FP32 1e-4 with
+    Kaiser-Bessel m = 3 (Gaussian m = 5); unreachable tolerances are errors."""
+    assert slp.choose_cutoff(1e-6, slp.FP64) == (slp.WINDOW_KB, 4)
+    assert slp.choose_cutoff(1e-6, slp.FP64, slp.WINDOW_GAUSS) == (slp.WINDOW_GAUSS, 7)
+    assert slp.choose_cutoff(1e-4, slp.FP32) == (slp.WINDOW_KB, 3)
+    assert slp.choose_cutoff(1e-4, slp.FP32, slp.WINDOW_GAUSS) == (slp.WINDOW_GAUSS, 5)
+    # monotone: a tighter tolerance never needs a smaller m
+    last = 0
+    for tol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8, 1e-9):
+        _, m = slp.choose_cutoff(tol, slp.FP64)
+        assert m >= last
+        last = m
+    with pytest.raises(slp.SlpError):
+        slp.choose_cutoff(1e-7, slp.FP32)          # below the FP32 rounding floor
+    with pytest.raises(slp.SlpError):
+        slp.choose_cutoff(1e-13, slp.FP64, slp.WINDOW_GAUSS)

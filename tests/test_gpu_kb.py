@@ -115,3 +115,20 @@ def test_kb_cube64_against_definition(m, prec, tol):
     e = rel_l2(phi, ref)
     log(f"  rel-L2 vs definition {e:.3e}")
     assert e <= tol
+
+
+@pytest.mark.parametrize("tol,prec,window", [(1e-6, slp.FP64, None), (1e-6, slp.FP64, slp.WINDOW_GAUSS),
+                                             (1e-4, slp.FP32, None), (1e-4, slp.FP32, slp.WINDOW_GAUSS)])
+def test_chosen_cutoff_meets_tolerance(tol, prec, window):
+    """The window and m picked by slp_choose_cutoff reach the tolerance on cube64."""
+    w_, m = slp.choose_cutoff(tol, prec, window)
+    wl = make_workload("cube64", m)
+    log(f"case chosen cutoff tol={tol} prec={prec} -> window={w_} m={m}")
+    ref = direct.phi_ndft(oracle_problem(wl))
+    w, g = es_for(wl)
+    G = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2, window=w_)
+    phi = _solve(G, wl.dens)
+    G.close()
+    e = rel_l2(phi, ref)
+    log(f"  rel-L2 vs definition {e:.3e}")
+    assert e <= tol
