@@ -181,7 +181,7 @@ int slp_set_graph(slp_geom *g, int32_t enable);
 
 /* Per-stage device timing. With every = k >= 1, every k-th evaluation (one
  * single eval, or one launch group of slp_eval_batched) records HIP events
- * around each stage on its stream: 0 gridding into per-bin blocks (charges
+ * around each stage on its stream: 0 gridding into per-segment blocks (charges
  * included), 1 sum of the blocks into the grid, 2 FFT x fwd, 3 FFT y fwd,
  * 4 FFT z (fwd, multiply, inv), 5 FFT y inv, 6 FFT x inv, 7 interpolation. Sampling keeps the cost of the event packets off the other
  * evaluations; every = 0 switches timing off. slp_stage_times synchronises the

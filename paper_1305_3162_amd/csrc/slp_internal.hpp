@@ -8,7 +8,7 @@
 
 namespace slp {
 
-constexpr int kTile = 8;      // grid tile edge used by spread and interpolation bins
+constexpr int kTile = 8;      // edge of the grid tiles that sort sources and targets
 constexpr int kMaxM = 8;      // largest supported window cut-off
 
 // Gridding (type-1 spread). Sources are sorted by (tile, cell in tile). The
@@ -117,7 +117,7 @@ int spread_units_per_cu(int m, bool fp64);
 template <typename T>
 hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int m, int nb,
                          hipStream_t s);
-// Cells of the padded accumulation block of one bin: (8 + 2m - 1)^3.
+// Cells of the padded accumulation block of one segment: (8 + 2m - 1)^3.
 int64_t pad_cells(int m);
 template <typename T>
 hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s);

@@ -46,18 +46,19 @@ __device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
 }
 
 // ----------------------------------------------------------------- spread ---
-// Phase A (one workgroup of 8 or 16 waves per work unit, a run of the sorted
-// sources of nearly equal length for every unit): the sources of each segment
-// (the unit's sources in one tile) are scattered into an LDS block covering the
-// tile plus the stencil halo, (8 + 2m - 1)^3 cells, which is then stored to the
-// segment's slot. Each wave independently takes every 8th run of sources
-// that share one grid cell; its lanes cover the 2m x 2m (dx, dy) columns of the
-// stencil in ceil(4m^2 / 64) passes and keep the 2m z-values of each column in
-// registers over the whole run, adding them to the LDS block once per run. The
-// 1-D Gaussian factors of up to 16 sources at a time are built in a
-// wave-private LDS slice with the fast-Gaussian-gridding recurrence
-// w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b): two exponentials per source and
-// axis.
+// Phase A (one workgroup of 8 or 16 waves per work unit; the setup gives every
+// unit one segment, the sources of one tile or an equal piece of a crowded
+// tile, longest first): the segment's sources are scattered into an FP64 LDS
+// block covering the tile plus the stencil halo, (8 + 2m - 1)^3 cells, which is
+// then stored to the segment's slot. Each wave independently takes every
+// WAVES-th run of sources that share one grid cell; its lanes cover the 2m x 2m
+// (dx, dy) columns of the stencil in ceil(4m^2 / 64) passes and keep the 2m
+// z-values of each column in registers over the whole run, adding them to the
+// LDS block once per run. The 1-D window factors of up to SBW sources at a time
+// are built in a wave-private LDS slice: Gaussian factors with the
+// fast-Gaussian-gridding recurrence w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b)
+// (two exponentials per source and axis), Kaiser-Bessel factors directly, one
+// stencil point per lane.
 // Phase B (one workgroup per region tile): every cell sums the blocks of the
 // segments of the neighbouring tiles that cover it, in a fixed order, and
 // writes the grid.
