@@ -97,19 +97,28 @@ def algorithmic_units(stage, info, m, esz):
     raise KeyError(stage)
 
 
+def code_only(src):
+    """C++ source without comments and with whitespace collapsed: what the
+    compiler sees, so that a comment edit does not invalidate measurements."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def measured_traffic(args, m, stage, nb):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (profiles/traffic_cube64.json, counters scaled by
     a 256 MiB copy), or None when no run covers this configuration or the kernel
-    source has changed since the counters were taken."""
+    source (without comments) has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_cube64.json")
     if stage != "spread_bins" or nb != 1 or not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+    with open(os.path.join(ROOT, rec["source"])) as f:
+        if hashlib.sha256(code_only(f.read()).encode()).hexdigest() != rec["source_sha256"]:
             return None
     e = rec["entries"].get(f"{args.workload}/{args.precision}/{args.window}/m{m}")
     return None if e is None else e["bytes_per_launch"]
