@@ -23,8 +23,11 @@ eq. (smooth_phi). Modules:
              route of eq. (smooth_phi)
   nufft      R3: the gridding / FFT / deconvolution / NFFT pipeline of
              Sec. 3 step by step (Gaussian window), for stage-wise comparison
+  nearfield  the near-field correction of Sec. 3.4 (kernel 1/r - N_s on the
+             pairs within eps), exact triangle integrals, the complete
+             potential phi_s + phi_NF and the exact-integral reference
 
 Parity pins live in tests/test_oracle_*.py. Functions without an independent
 pin are marked "parity unpinned" in their docstrings.
 """
-from . import geometry, kernel, direct, nufft  # noqa: F401
+from . import geometry, kernel, direct, nufft, nearfield  # noqa: F401
