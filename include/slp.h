@@ -183,10 +183,11 @@ int slp_set_graph(slp_geom *g, int32_t enable);
  * single eval, or one launch group of slp_eval_batched) records HIP events
  * around each stage on its stream: 0 gridding into per-segment blocks (charges
  * included), 1 sum of the blocks into the grid, 2 FFT x fwd, 3 FFT y fwd,
- * 4 FFT z (fwd, multiply, inv), 5 FFT y inv, 6 FFT x inv, 7 interpolation. Sampling keeps the cost of the event packets off the other
- * evaluations; every = 0 switches timing off. slp_stage_times synchronises the
- * recorded evaluations and accumulates into ms[8] (summed since the last reset)
- * and *count (recorded evaluations). */
+ * 4 FFT z (fwd, multiply, inv), 5 FFT y inv, 6 FFT x inv, 7 interpolation,
+ * 8 near-field correction (zero time without one). Sampling keeps the cost of
+ * the event packets off the other evaluations; every = 0 switches timing off.
+ * slp_stage_times synchronises the recorded evaluations and accumulates into
+ * ms[9] (summed since the last reset) and *count (recorded evaluations). */
 int slp_set_timing(slp_geom *g, int32_t every);
 int slp_stage_times(slp_geom *g, double *ms, int64_t *count, int32_t reset);
 
@@ -215,6 +216,72 @@ int slp_choose_cutoff(double tol, int32_t precision, int32_t window_in, int32_t 
  * terms (EINVAL if cap is too small, with *count set to the required size). */
 int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omega,
                     double *gamma, int32_t cap, int32_t *count);
+
+/* ---- Near-field correction (Sec. 3.4) -----------------------------------------
+ * The kernel is split as 1/r = (1/r - N_s) + N_s (eq. splitting1) with N_s the
+ * kept exponential-sum terms. The smooth part above carries N_s through its
+ * Fourier series; the near field adds, for every target x_i and every triangle
+ * S_j at distance d(x_i, S_j) <= eps (index set of eq. nf_index),
+ *   phi_i += 1/(4 pi) gbar_j C_ij,                                  (eq. nfcorr)
+ *   C_ij  = int_{S_j} dsigma(y) / |x_i - y| - |S_j|/3 sum_s N_s(|x_i - y_{j,s}|),
+ * gbar_j the mean of the triangle's three density values (g_j itself for the
+ * element-constant densities of the P1 ansatz). The first term is the exact
+ * integral (closed form for flat triangles, so the weakly singular case needs
+ * no special quadrature); the second removes the smooth kernel with the same
+ * three-point rule the gridding uses, so that near pairs end up with the exact
+ * integral of 1/r. With eps at least the radius from which N_s matches 1/r
+ * (slp_near_radius), phi becomes the complete single-layer potential up to the
+ * Fourier error of N_s and the three-point rule on the far pairs. */
+
+/* Build the near field of a context: the index sets on the host (uniform cell
+ * grid over triangle centroids, up to 16 threads), the matrix C on the device
+ * (one FP64 value per pair; FP32 for an FP32 context), held as CSR over the
+ * targets: int64 row offsets; rows padded to groups of 4 entries, or, when
+ * rows average 2048 pairs or more, to chunks of 256 stored lane-interleaved
+ * with their triangle indices packed as one int32 base per chunk plus a 16-bit
+ * offset per entry (int32 indices if a chunk spans 65535 triangles or more).
+ * Every later evaluation
+ * of this context (single, batched, graph replay) adds phi_NF after the
+ * interpolation; geometries built by a server carry no near field.
+ * eps <= 0 removes the near field. Synchronises `stream` and the device;
+ * drops captured graphs.
+ *   eps : physical distance, the paper's eps of Alg. 1 (Require line)
+ * Errors: EINVAL for non-finite eps; ENOMEM when the pattern does not fit in
+ * host or device memory (the context is left without a near field). */
+int slp_setup_near_field(slp_geom *g, double eps, void *stream);
+
+/* Smallest eps on the scan r_k = r_max * 0.999^k (k = 0, 1, ...), r_max the
+ * bounding-box diagonal of nodes and targets, from which up to r_max the kept
+ * exponential sum matches 1/r to |N_s(r) r - 1| <= tol at every scan point
+ * (Sec. 3.3: the truncated sum is accurate on [eps, 1/2] only). EINVAL if
+ * tol <= 0 or if r_max itself misses tol. Host only. */
+int slp_near_radius(const slp_geom *g, double tol, double *eps);
+
+/* eps, pairs (nnz), r_max, stored entries (pairs plus row padding) and whether
+ * the columns are packed, of a context (any pointer may be NULL). */
+int slp_near_field_info(const slp_geom *g, double *eps, int64_t *nnz, double *r_max,
+                        int64_t *stored, int32_t *packed);
+
+/* Copy the near-field matrix to host memory (synchronises the device):
+ * rowptr int64 [n_targets + 1], cols int32 [nnz] (may be NULL), vals float64
+ * [nnz] (may be NULL; FP32 values converted). cap = room in cols / vals;
+ * EINVAL if it is below nnz. */
+int slp_debug_copy_near(const slp_geom *g, int64_t *rowptr, int32_t *cols, double *vals,
+                        int64_t cap);
+
+/* Host-only versions of the near-field building blocks (no device needed).
+ * slp_near_pattern_host: the index sets as CSR; pass cols = NULL to learn nnz
+ * (EINVAL if cols_cap < nnz), rowptr int64 [n_targets + 1] may be NULL.
+ * slp_triangle_potential_host: out[i] = int over the flat triangle
+ * (a_i, b_i, c_i) of 1/|x_i - y|, all arrays [count][3] float64.
+ * slp_near_radius_host: the radius of slp_near_radius for given terms and r_max. */
+int slp_near_pattern_host(const double *nodes, int64_t n_nodes, const int32_t *tris,
+                          int64_t n_tris, const double *targets, int64_t n_targets, double eps,
+                          int64_t *rowptr, int32_t *cols, int64_t cols_cap, int64_t *nnz);
+int slp_triangle_potential_host(const double *x, const double *a, const double *b,
+                                const double *c, int64_t count, double *out);
+int slp_near_radius_host(const double *es_w, const double *es_gamma, int32_t terms, double r_max,
+                         double tol, double *eps);
 
 int slp_geom_destroy(slp_geom *g);
 const char *slp_last_error(void);

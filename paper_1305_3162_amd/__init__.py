@@ -18,12 +18,14 @@ __all__ = [
     "debug_copy", "geom_destroy", "Geometry", "FP64", "FP32", "WINDOW_GAUSS", "WINDOW_KB", "STAGES",
     "geometry_device_bytes", "server_create", "server_add_geometry", "server_submit",
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
+    "setup_near_field", "near_radius", "near_field_info", "debug_copy_near",
+    "near_pattern_host", "triangle_potential_host", "near_radius_host",
 ]
 
 FP64, FP32 = 0, 1
 WINDOW_GAUSS, WINDOW_KB = 0, 1
 STAGES = ("spread_bins", "spread_reduce", "fft_x_fwd", "fft_y_fwd", "fft_z_mul_inv", "fft_y_inv", "fft_x_inv",
-          "interp")
+          "interp", "near")
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libslp.so")
 
@@ -103,6 +105,18 @@ def load_library():
         "slp_server_wait": [_VP, ctypes.c_uint64, ctypes.c_double],
         "slp_server_get_stats": [_VP, ctypes.POINTER(ServerStats), ctypes.c_int32],
         "slp_server_destroy": [_VP],
+        "slp_setup_near_field": [_VP, ctypes.c_double, _VP],
+        "slp_near_radius": [_VP, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+        "slp_near_field_info": [_VP, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)],
+        "slp_debug_copy_near": [_VP, _VP, _VP, _VP, ctypes.c_int64],
+        "slp_near_pattern_host": [_VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                                  ctypes.c_double, _VP, _VP, ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_int64)],
+        "slp_triangle_potential_host": [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP],
+        "slp_near_radius_host": [_VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_double)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -341,6 +355,81 @@ def debug_copy(geom, which, dst, stream=None):
                                          _stream_ptr(stream)))
 
 
+def setup_near_field(geom, eps, stream=None):
+    """slp_setup_near_field: near-field correction within physical distance eps
+    (eps <= 0 removes it)."""
+    _check(load_library().slp_setup_near_field(_VP(geom), float(eps), _stream_ptr(stream)))
+
+
+def near_radius(geom, tol):
+    """slp_near_radius: eps from which the kept exponential sum matches 1/r to tol."""
+    out = ctypes.c_double(0.0)
+    _check(load_library().slp_near_radius(_VP(geom), float(tol), ctypes.byref(out)))
+    return out.value
+
+
+def near_field_info(geom):
+    eps, nnz, rmax = ctypes.c_double(0.0), ctypes.c_int64(0), ctypes.c_double(0.0)
+    stored, packed = ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(load_library().slp_near_field_info(_VP(geom), ctypes.byref(eps), ctypes.byref(nnz),
+                                              ctypes.byref(rmax), ctypes.byref(stored),
+                                              ctypes.byref(packed)))
+    return {"eps": eps.value, "nnz": nnz.value, "r_max": rmax.value, "stored": stored.value,
+            "packed": bool(packed.value)}
+
+
+def debug_copy_near(geom):
+    """The near-field matrix as host arrays (rowptr int64, cols int32, vals float64)."""
+    info = geom_get_info(geom)
+    nnz = near_field_info(geom)["nnz"]
+    rowptr = np.zeros(info["n_targets"] + 1, dtype=np.int64)
+    cols = np.zeros(max(nnz, 1), dtype=np.int32)
+    vals = np.zeros(max(nnz, 1), dtype=np.float64)
+    _check(load_library().slp_debug_copy_near(_VP(geom), rowptr.ctypes.data, cols.ctypes.data,
+                                              vals.ctypes.data, cols.size))
+    return rowptr, cols[:nnz], vals[:nnz]
+
+
+def near_pattern_host(nodes, tris, targets, eps):
+    """slp_near_pattern_host: (rowptr, cols) of the index sets, computed on the host."""
+    lib = load_library()
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    targets = np.ascontiguousarray(targets, dtype=np.float64)
+    nnz = ctypes.c_int64(0)
+    args = (nodes.ctypes.data, nodes.shape[0], tris.ctypes.data, tris.shape[0],
+            targets.ctypes.data, targets.shape[0], float(eps))
+    _check(lib.slp_near_pattern_host(*args, None, None, 0, ctypes.byref(nnz)))
+    rowptr = np.zeros(targets.shape[0] + 1, dtype=np.int64)
+    cols = np.zeros(max(nnz.value, 1), dtype=np.int32)
+    _check(lib.slp_near_pattern_host(*args, rowptr.ctypes.data, cols.ctypes.data, cols.size,
+                                     ctypes.byref(nnz)))
+    return rowptr, cols[:nnz.value]
+
+
+def triangle_potential_host(x, a, b, c):
+    """slp_triangle_potential_host over arrays [count, 3] (broadcast first)."""
+    x, a, b, c = (np.ascontiguousarray(v, dtype=np.float64)
+                  for v in np.broadcast_arrays(x, a, b, c))
+    shape = x.shape[:-1]
+    x, a, b, c = (np.ascontiguousarray(v.reshape(-1, 3)) for v in (x, a, b, c))
+    out = np.empty(x.shape[0])
+    _check(load_library().slp_triangle_potential_host(x.ctypes.data, a.ctypes.data,
+                                                      b.ctypes.data, c.ctypes.data,
+                                                      x.shape[0], out.ctypes.data))
+    return out.reshape(shape)
+
+
+def near_radius_host(es_w, es_gamma, r_max, tol):
+    es_w = np.ascontiguousarray(es_w, dtype=np.float64)
+    es_gamma = np.ascontiguousarray(es_gamma, dtype=np.float64)
+    out = ctypes.c_double(0.0)
+    _check(load_library().slp_near_radius_host(es_w.ctypes.data, es_gamma.ctypes.data,
+                                               es_w.size, float(r_max), float(tol),
+                                               ctypes.byref(out)))
+    return out.value
+
+
 def geom_destroy(geom):
     _check(load_library().slp_geom_destroy(_VP(geom)))
 
@@ -363,6 +452,16 @@ class Geometry:
 
     def eval(self, phi, stream=None):
         eval_single_layer(self.handle, phi, stream)
+
+    def setup_near_field(self, eps, stream=None):
+        setup_near_field(self.handle, eps, stream)
+        self.info = geom_get_info(self.handle)
+
+    def near_radius(self, tol):
+        return near_radius(self.handle, tol)
+
+    def near_field_info(self):
+        return near_field_info(self.handle)
 
     def solve(self, dens, stream=None):
         import torch

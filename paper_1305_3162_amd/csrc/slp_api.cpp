@@ -3,10 +3,12 @@
 // passes. Every arithmetic step of the evaluation runs in slp_kernels.hip.
 #include "slp.h"
 #include "slp_internal.hpp"
+#include "slp_near.hpp"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,6 +19,7 @@
 #include <new>
 #include <queue>
 #include <string>
+#include <thread>
 #include <vector>
 
 using slp::kTile;
@@ -135,6 +138,24 @@ struct slp_geom {
   int32_t *tri_v = nullptr;      // [3][M] vertex indices, component-major
   double *tri_n = nullptr;       // [3][M] unit outward normals, component-major
   double *own_dens = nullptr;    // [3M] density formed by slp_set_density_from_m
+  // host copies kept for the near-field setup: physical nodes, triangles,
+  // targets, the kept exponential-sum terms and the body diameter
+  std::vector<double> h_nodes, h_tgt, kept_w, kept_g;
+  std::vector<int32_t> h_tris;
+  double r_max = 0.0;
+  // near-field correction (empty unless slp_setup_near_field ran with eps > 0)
+  double nf_eps = 0.0;
+  int64_t nf_nnz = 0;            // pairs
+  int64_t nf_stored = 0;         // entries including the padding of every row to a group
+  int64_t *nf_rowptr = nullptr;
+  int32_t *nf_cols = nullptr;    // unless packed
+  int32_t *nf_bases = nullptr;   // packed: chunk bases
+  uint16_t *nf_offs = nullptr;   // packed: per-entry offsets
+  bool nf_packed = false;
+  bool nf_chunked = false;
+  std::vector<int64_t> nf_rows;  // host: pairs per row (to strip the padding on copies)
+  void *nf_vals = nullptr;
+  double *nf_gbar = nullptr;     // [cap][M] element means of the densities
   int64_t bytes = 0;
   std::vector<void *> allocs;
   // captured evaluations, one per batch size (replayed when use_graph is set)
@@ -143,7 +164,8 @@ struct slp_geom {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t spread_node = nullptr, interp_node = nullptr;
-    hipKernelNodeParams spread_p{}, interp_p{};
+    hipGraphNode_t gbar_node = nullptr, near_node = nullptr;
+    hipKernelNodeParams spread_p{}, interp_p{}, gbar_p{}, near_p{};
   };
   bool use_graph = false;
   std::vector<Captured> graphs;
@@ -161,9 +183,10 @@ struct slp_geom {
   int32_t every = 1;             // record the stage events of every k-th evaluation
   int64_t evals = 0;             // evaluations since timing was enabled
   bool ev_ready = false;
-  static constexpr int kStages = 8;
+  static constexpr int kStages = 9;
   hipEvent_t ev[kRing][kStages + 1]{};
   bool used[kRing]{};
+  bool with_near[kRing]{};       // the set recorded the near-field stage
   int cur = 0;
   double acc_ms[kStages]{};
   int64_t count = 0;
@@ -285,6 +308,13 @@ int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
   G->drop_graphs();                    // they hold the old buffer addresses
+  if (G->nf_gbar) {                    // element means of the near field, nb items
+    void *q = nullptr;
+    if (G->alloc(&q, (size_t)G->n_tris * 8 * nb) != hipSuccess)
+      return fail(SLP_ENOMEM, "near-field buffer for %d items: allocation failed", nb);
+    G->release(G->nf_gbar);
+    G->nf_gbar = static_cast<double *>(q);
+  }
   void **bufs[5] = {&G->scratch, &G->grid_a, &G->S1, &G->S2, &G->grid_g};
   const size_t e = G->esz();
   const size_t per[5] = {e, e, 2 * e, 2 * e, e};
@@ -347,6 +377,20 @@ slp::InterpArgs<T> interp_args(const slp_geom *G) {
   a.window = G->window;
   a.kb_b = (T)G->b;
   a.kb_inv_norm = (T)G->kb_inv_norm;
+  return a;
+}
+
+template <typename T>
+slp::NearArgs<T> near_args(const slp_geom *G) {
+  slp::NearArgs<T> a{};
+  a.rowptr = G->nf_rowptr;
+  a.cols = G->nf_cols;
+  a.bases = G->nf_bases;
+  a.offs = G->nf_offs;
+  a.vals = static_cast<T *>(G->nf_vals);
+  a.gbar = G->nf_gbar;
+  a.rows = G->n_tgt;
+  a.M = G->n_tris;
   return a;
 }
 
@@ -438,7 +482,11 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     const slp::InterpArgs<T> a = interp_args<T>(G);
     HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
   }
+  const bool near = G->nf_nnz > 0;
+  if (tm && near) HIP_TRY(hipEventRecord(G->evs()[8], st));
+  if (near) HIP_TRY(slp::launch_near_apply<T>(near_args<T>(G), ptrs, nb, G->nf_packed, st));
   if (tm) {
+    G->with_near[G->cur] = near;
     HIP_TRY(hipEventRecord(G->evs()[slp_geom::kStages], st));
     G->used[G->cur] = true;
     G->cur = (G->cur + 1) % slp_geom::kRing;
@@ -475,6 +523,7 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     std::vector<hipGraphNode_t> nodes(n);
     HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &n));
     const void *fs = slp::spread_bins_kernel<T>(G->m), *fi = slp::interp_kernel<T>(G->m);
+    const void *fn = slp::near_apply_kernel<T>(nb, G->nf_packed), *fg = slp::near_gbar_kernel();
     for (hipGraphNode_t nd : nodes) {
       hipGraphNodeType ty;
       HIP_TRY(hipGraphNodeGetType(nd, &ty));
@@ -483,10 +532,14 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
       HIP_TRY(hipGraphKernelNodeGetParams(nd, &kp));
       if (kp.func == fs) { c.spread_node = nd; c.spread_p = kp; }
       if (kp.func == fi) { c.interp_node = nd; c.interp_p = kp; }
+      if (kp.func == fn) { c.near_node = nd; c.near_p = kp; }
+      if (kp.func == fg) { c.gbar_node = nd; c.gbar_p = kp; }
     }
-    if (!c.spread_node || !c.interp_node) {
+    const bool near = G->nf_nnz > 0;
+    if (!c.spread_node || !c.interp_node || near != (c.near_node != nullptr) ||
+        near != (c.gbar_node != nullptr)) {
       (void)hipGraphDestroy(graph);
-      return fail(SLP_EDEVICE, "captured evaluation lacks the gridding or interpolation launch");
+      return fail(SLP_EDEVICE, "captured evaluation lacks the gridding, interpolation or near-field launch");
     }
     HIP_TRY(hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0));
     G->graphs.push_back(c);
@@ -505,6 +558,22 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
   kp.kernelParams = iargs;
   kp.extra = nullptr;
   HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->interp_node, &kp));
+  if (cg->near_node) {
+    slp::NearArgs<T> na = near_args<T>(G);
+    int32_t nbv = nb;
+    double *gbar = G->nf_gbar;
+    int64_t M = G->n_tris;
+    void *gargs[3] = {&p, &gbar, &M};
+    kp = cg->gbar_p;
+    kp.kernelParams = gargs;
+    kp.extra = nullptr;
+    HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->gbar_node, &kp));
+    void *nargs[3] = {&na, &p, &nbv};
+    kp = cg->near_p;
+    kp.kernelParams = nargs;
+    kp.extra = nullptr;
+    HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->near_node, &kp));
+  }
   HIP_TRY(hipGraphLaunch(cg->exec, st));
   return SLP_OK;
 }
@@ -527,9 +596,13 @@ int eval_items(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) 
 int collect_one(slp_geom *G, int r) {
   if (!G->used[r]) return SLP_OK;
   HIP_TRY(hipEventSynchronize(G->ev[r][slp_geom::kStages]));
-  for (int i = 0; i < slp_geom::kStages; ++i) {
+  // without a near field, event 8 is not recorded: the interpolation ends at
+  // the last event and the near-field stage takes no time
+  const int last = G->with_near[r] ? slp_geom::kStages : slp_geom::kStages - 1;
+  for (int i = 0; i < last; ++i) {
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, G->ev[r][i], G->ev[r][i + 1]));
+    const int to = (i + 1 == last) ? slp_geom::kStages : i + 1;
+    HIP_TRY(hipEventElapsedTime(&ms, G->ev[r][i], G->ev[r][to]));
     G->acc_ms[i] += ms;
   }
   G->count += 1;
@@ -732,6 +805,8 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   }
   if (om.empty()) return fail(SLP_EINVAL, "no exponential-sum term is resolved by the grid");
   G->terms_kept = (int32_t)om.size();
+  G->kept_w = om;
+  G->kept_g = gam;
 
   // binning: sources by (tile, cell in tile), targets by tile
   const int64_t ntiles = (int64_t)G->tiles[0] * G->tiles[1] * G->tiles[2];
@@ -937,6 +1012,25 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   bool ok = true;
   for (const AllocReq &r : reqs) ok = ok && G->alloc(r.dst, r.bytes) == hipSuccess;
   if (!ok) return fail(SLP_ENOMEM, "device allocation failed (%lld bytes so far)", (long long)G->bytes);
+  try {
+    G->h_nodes.assign(nodes, nodes + 3 * n_nodes);
+    G->h_tris.assign(tris, tris + 3 * n_tris);
+    G->h_tgt.assign(targets, targets + 3 * n_tgt);
+  } catch (const std::bad_alloc &) {
+    return fail(SLP_ENOMEM, "host copy of the geometry failed");
+  }
+  {
+    double blo[3], bhi[3];
+    for (int q = 0; q < 3; ++q) { blo[q] = lo[q]; bhi[q] = hi[q]; }
+    for (int64_t i = 0; i < n_tgt; ++i)
+      for (int q = 0; q < 3; ++q) {
+        blo[q] = std::min(blo[q], targets[3 * i + q]);
+        bhi[q] = std::max(bhi[q], targets[3 * i + q]);
+      }
+    double d2 = 0.0;
+    for (int q = 0; q < 3; ++q) d2 += (bhi[q] - blo[q]) * (bhi[q] - blo[q]);
+    G->r_max = std::sqrt(d2);
+  }
 
   HIP_TRY(hipMemcpyAsync(G->src_w, wsorted.data(), Ms * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->src_perm, sorder.data(), Ms * 4, hipMemcpyHostToDevice, st));
@@ -1285,6 +1379,316 @@ int slp_debug_copy(const slp_geom *G, int32_t which, void *dst, size_t dst_bytes
   }
   if (dst_bytes < need) return fail(SLP_EINVAL, "debug_copy: dst holds %zu bytes, need %zu", dst_bytes, need);
   HIP_TRY(hipMemcpyAsync(dst, src, need, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  return SLP_OK;
+}
+
+// ------------------------------------------------------------ near field ---
+
+namespace {
+int host_threads() {
+  const unsigned hw = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+}
+
+void drop_near(slp_geom *G) {
+  G->release(G->nf_rowptr);
+  G->release(G->nf_cols);
+  G->release(G->nf_bases);
+  G->release(G->nf_offs);
+  G->release(G->nf_vals);
+  G->release(G->nf_gbar);
+  G->nf_rowptr = nullptr;
+  G->nf_cols = nullptr;
+  G->nf_bases = nullptr;
+  G->nf_offs = nullptr;
+  G->nf_packed = false;
+  G->nf_chunked = false;
+  std::vector<int64_t>().swap(G->nf_rows);
+  G->nf_vals = nullptr;
+  G->nf_gbar = nullptr;
+  G->nf_nnz = 0;
+  G->nf_stored = 0;
+  G->nf_eps = 0.0;
+}
+}  // namespace
+
+int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (!std::isfinite(eps)) return fail(SLP_EINVAL, "eps must be finite");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
+  G->drop_graphs();                    // they were captured with the old near field
+  drop_near(G);
+  if (eps <= 0.0) return SLP_OK;
+
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> cols;
+  std::string err;
+  if (!slp::build_near_pattern(G->h_nodes.data(), G->n_nodes, G->h_tris.data(), G->n_tris,
+                               G->h_tgt.data(), G->n_tgt, eps, host_threads(), rowptr, cols, err))
+    return fail(SLP_ENOMEM, "%s", err.c_str());
+  const int64_t nnz = rowptr.back();
+  G->nf_eps = eps;
+  if (nnz == 0) return SLP_OK;
+
+  // every row padded with column -1 to a multiple of the group size, or of the
+  // interleaved chunk when rows are long (padding then below a few per cent)
+  const int64_t P = G->n_tgt;
+  const bool chunked = nnz >= (int64_t)8 * slp::kNearChunk * P;
+  const int64_t grp = chunked ? slp::kNearChunk : slp::kNearGroup;
+  std::vector<int64_t> prow(P + 1, 0);
+  for (int64_t i = 0; i < P; ++i) {
+    const int64_t n = rowptr[i + 1] - rowptr[i];
+    prow[i + 1] = prow[i] + (n + grp - 1) / grp * grp;
+  }
+  const int64_t stored = prow[P];
+  if (stored != nnz || chunked) {
+    std::vector<int32_t> pc;
+    try {
+      pc.assign(stored, -1);
+    } catch (const std::bad_alloc &) {
+      G->nf_eps = 0.0;
+      return fail(SLP_ENOMEM, "host allocation for the padded near-field pattern failed");
+    }
+    for (int64_t i = 0; i < P; ++i) {
+      const int64_t n = rowptr[i + 1] - rowptr[i];
+      if (!chunked) {
+        std::copy(cols.begin() + rowptr[i], cols.begin() + rowptr[i + 1], pc.begin() + prow[i]);
+        continue;
+      }
+      // entry e = c * 256 + 64 k + l of the row goes to c * 256 + 4 l + k
+      for (int64_t e = 0; e < n; ++e) {
+        const int64_t c = e / slp::kNearChunk, r = e % slp::kNearChunk;
+        const int64_t k = r / 64, l = r % 64;
+        pc[prow[i] + c * slp::kNearChunk + 4 * l + k] = cols[rowptr[i] + e];
+      }
+    }
+    cols.swap(pc);
+  }
+  std::vector<int64_t> counts(P);
+  for (int64_t i = 0; i < P; ++i) counts[i] = rowptr[i + 1] - rowptr[i];
+  rowptr.swap(prow);
+
+  // packed columns: chunk base + 16-bit offsets, if every chunk spans < 65535
+  std::vector<int32_t> bases;
+  std::vector<uint16_t> offs;
+  bool packed = chunked;
+  if (packed) {
+    const int64_t nch = stored / slp::kNearChunk;
+    bases.assign(nch, 0);
+    for (int64_t c = 0; c < nch && packed; ++c) {
+      int32_t lo = std::numeric_limits<int32_t>::max(), hi = -1;
+      for (int64_t e = c * slp::kNearChunk; e < (c + 1) * slp::kNearChunk; ++e)
+        if (cols[e] >= 0) { lo = std::min(lo, cols[e]); hi = std::max(hi, cols[e]); }
+      if (hi < 0) lo = hi = 0;
+      if ((int64_t)hi - lo >= 65535) packed = false;
+      bases[c] = lo;
+    }
+    if (packed) {
+      offs.assign(stored, 0);
+      for (int64_t e = 0; e < stored; ++e)
+        if (cols[e] >= 0) offs[e] = (uint16_t)(cols[e] - bases[e / slp::kNearChunk]);
+    } else {
+      std::vector<int32_t>().swap(bases);
+    }
+  }
+
+  // persistent: pattern, values, element means; temporary: coordinates,
+  // triangles, terms (and the int32 columns when packed)
+  void *rp = nullptr, *cl = nullptr, *bs = nullptr, *of = nullptr, *vl = nullptr, *gb = nullptr;
+  bool ok = G->alloc(&rp, rowptr.size() * sizeof(int64_t)) == hipSuccess &&
+            G->alloc(&vl, (size_t)stored * G->esz()) == hipSuccess &&
+            G->alloc(&gb, (size_t)G->n_tris * 8 * G->cap) == hipSuccess;
+  if (ok && packed)
+    ok = G->alloc(&bs, bases.size() * sizeof(int32_t)) == hipSuccess &&
+         G->alloc(&of, offs.size() * sizeof(uint16_t)) == hipSuccess;
+  else if (ok)
+    ok = G->alloc(&cl, (size_t)stored * sizeof(int32_t)) == hipSuccess;
+  if (!ok) {
+    for (void *q : {rp, cl, bs, of, vl, gb}) G->release(q);
+    G->nf_eps = 0.0;
+    return fail(SLP_ENOMEM, "near field: %lld entries do not fit in device memory", (long long)nnz);
+  }
+  G->nf_rowptr = static_cast<int64_t *>(rp);
+  G->nf_cols = static_cast<int32_t *>(cl);
+  G->nf_bases = static_cast<int32_t *>(bs);
+  G->nf_offs = static_cast<uint16_t *>(of);
+  G->nf_packed = packed;
+  G->nf_chunked = chunked;
+  G->nf_rows.swap(counts);
+  G->nf_vals = vl;
+  G->nf_gbar = static_cast<double *>(gb);
+  G->nf_nnz = nnz;
+  G->nf_stored = stored;
+  const int S = G->terms_kept;
+  double *d_tg = nullptr, *d_nodes = nullptr, *d_terms = nullptr;
+  int32_t *d_tris = nullptr, *d_cols = G->nf_cols;
+  struct Temp {
+    std::vector<void *> p;
+    ~Temp() { for (void *q : p) (void)hipFree(q); }
+  } tmp;
+  auto talloc = [&](void **q, size_t bytes) {
+    hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) tmp.p.push_back(*q);
+    return e;
+  };
+  if (talloc((void **)&d_tg, G->h_tgt.size() * 8) != hipSuccess ||
+      talloc((void **)&d_nodes, G->h_nodes.size() * 8) != hipSuccess ||
+      talloc((void **)&d_tris, G->h_tris.size() * 4) != hipSuccess ||
+      talloc((void **)&d_terms, (size_t)2 * S * 8) != hipSuccess ||
+      (packed && talloc((void **)&d_cols, (size_t)stored * 4) != hipSuccess)) {
+    drop_near(G);
+    return fail(SLP_ENOMEM, "near field: temporary device buffers failed");
+  }
+  HIP_TRY(hipMemcpyAsync(G->nf_rowptr, rowptr.data(), rowptr.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_cols, cols.data(), (size_t)stored * 4, hipMemcpyHostToDevice, st));
+  if (packed) {
+    HIP_TRY(hipMemcpyAsync(G->nf_bases, bases.data(), bases.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(G->nf_offs, offs.data(), offs.size() * 2, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(d_tg, G->h_tgt.data(), G->h_tgt.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_nodes, G->h_nodes.data(), G->h_nodes.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_tris, G->h_tris.data(), G->h_tris.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_terms, G->kept_w.data(), (size_t)S * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_terms + S, G->kept_g.data(), (size_t)S * 8, hipMemcpyHostToDevice, st));
+  if (G->prec == SLP_FP64) {
+    slp::NearArgs<double> na = near_args<double>(G);
+    na.cols = d_cols;
+    HIP_TRY(slp::launch_near_values<double>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S, st));
+  } else {
+    slp::NearArgs<float> na = near_args<float>(G);
+    na.cols = d_cols;
+    HIP_TRY(slp::launch_near_values<float>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));   // host vectors and temporaries go out of scope
+  return SLP_OK;
+}
+
+int slp_near_radius(const slp_geom *G, double tol, double *eps) {
+  if (!G || !eps) return fail(SLP_EINVAL, "NULL argument");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(SLP_EINVAL, "tol must be positive");
+  const double r = slp::near_radius(G->kept_w.data(), G->kept_g.data(), G->terms_kept, G->r_max, tol);
+  if (r < 0.0)
+    return fail(SLP_EINVAL, "the kept exponential sum misses 1/r by more than %g at the body diameter %g",
+                tol, G->r_max);
+  *eps = r;
+  return SLP_OK;
+}
+
+int slp_near_field_info(const slp_geom *G, double *eps, int64_t *nnz, double *r_max,
+                        int64_t *stored, int32_t *packed) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (eps) *eps = G->nf_eps;
+  if (nnz) *nnz = G->nf_nnz;
+  if (r_max) *r_max = G->r_max;
+  if (stored) *stored = G->nf_stored;
+  if (packed) *packed = G->nf_packed ? 1 : 0;
+  return SLP_OK;
+}
+
+int slp_debug_copy_near(const slp_geom *G, int64_t *rowptr, int32_t *cols, double *vals,
+                        int64_t cap) {
+  if (!G || !rowptr) return fail(SLP_EINVAL, "NULL argument");
+  if (G->nf_nnz > cap) return fail(SLP_EINVAL, "debug_copy_near: %lld entries, room for %lld",
+                                   (long long)G->nf_nnz, (long long)cap);
+  HIP_TRY(hipDeviceSynchronize());
+  if (G->nf_nnz == 0) {
+    for (int64_t i = 0; i <= G->n_tgt; ++i) rowptr[i] = 0;
+    return SLP_OK;
+  }
+  // the stored rows carry padding (column -1) at their ends: drop it
+  const int64_t P = G->n_tgt, S = G->nf_stored;
+  std::vector<int64_t> prow(P + 1);
+  std::vector<int32_t> pc(S);
+  std::vector<double> pv(vals ? S : 0);
+  HIP_TRY(hipMemcpy(prow.data(), G->nf_rowptr, (size_t)(P + 1) * 8, hipMemcpyDeviceToHost));
+  if (G->nf_packed) {
+    // columns from chunk bases and offsets; padding from the row lengths
+    std::vector<int32_t> bs((size_t)(S / slp::kNearChunk));
+    std::vector<uint16_t> of((size_t)S);
+    HIP_TRY(hipMemcpy(bs.data(), G->nf_bases, bs.size() * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(of.data(), G->nf_offs, of.size() * 2, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < P; ++i)
+      for (int64_t p = prow[i]; p < prow[i + 1]; ++p) {
+        const int64_t w = p - prow[i], c = w / slp::kNearChunk, r = w % slp::kNearChunk;
+        const int64_t e = c * slp::kNearChunk + 64 * (r % 4) + r / 4;
+        pc[p] = e < G->nf_rows[i] ? bs[p / slp::kNearChunk] + of[p] : -1;
+      }
+  } else {
+    HIP_TRY(hipMemcpy(pc.data(), G->nf_cols, (size_t)S * 4, hipMemcpyDeviceToHost));
+  }
+  if (vals) {
+    if (G->prec == SLP_FP64) {
+      HIP_TRY(hipMemcpy(pv.data(), G->nf_vals, (size_t)S * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<float> f((size_t)S);
+      HIP_TRY(hipMemcpy(f.data(), G->nf_vals, f.size() * 4, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < f.size(); ++i) pv[i] = f[i];
+    }
+  }
+  // rows in increasing triangle order (long rows are stored interleaved)
+  int64_t k = 0;
+  rowptr[0] = 0;
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t i = 0; i < P; ++i) {
+    row.clear();
+    for (int64_t e = prow[i]; e < prow[i + 1]; ++e)
+      if (pc[e] >= 0) row.emplace_back(pc[e], vals ? pv[e] : 0.0);
+    std::sort(row.begin(), row.end(),
+              [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                return a.first < b.first;
+              });
+    for (const auto &ent : row) {
+      if (cols) cols[k] = ent.first;
+      if (vals) vals[k] = ent.second;
+      ++k;
+    }
+    rowptr[i + 1] = k;
+  }
+  return SLP_OK;
+}
+
+int slp_near_pattern_host(const double *nodes, int64_t n_nodes, const int32_t *tris,
+                          int64_t n_tris, const double *targets, int64_t n_targets, double eps,
+                          int64_t *rowptr, int32_t *cols, int64_t cols_cap, int64_t *nnz) {
+  if (!nodes || !tris || !targets || !nnz) return fail(SLP_EINVAL, "NULL argument");
+  if (n_nodes < 3 || n_tris < 1 || n_targets < 1) return fail(SLP_EINVAL, "empty mesh or targets");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SLP_EINVAL, "eps must be finite and >= 0");
+  for (int64_t j = 0; j < 3 * n_tris; ++j)
+    if (tris[j] < 0 || tris[j] >= n_nodes)
+      return fail(SLP_EINVAL, "triangle %lld references node %d out of range", (long long)(j / 3), tris[j]);
+  std::vector<int64_t> rp;
+  std::vector<int32_t> cl;
+  std::string err;
+  if (!slp::build_near_pattern(nodes, n_nodes, tris, n_tris, targets, n_targets, eps, host_threads(),
+                               rp, cl, err))
+    return fail(SLP_ENOMEM, "%s", err.c_str());
+  *nnz = rp.back();
+  if (rowptr) std::copy(rp.begin(), rp.end(), rowptr);
+  if (cols) {
+    if (cols_cap < rp.back()) return fail(SLP_EINVAL, "cols holds %lld entries, need %lld",
+                                          (long long)cols_cap, (long long)rp.back());
+    std::copy(cl.begin(), cl.end(), cols);
+  }
+  return SLP_OK;
+}
+
+int slp_triangle_potential_host(const double *x, const double *a, const double *b,
+                                const double *c, int64_t count, double *out) {
+  if (!x || !a || !b || !c || !out || count < 0) return fail(SLP_EINVAL, "NULL argument or count < 0");
+  for (int64_t i = 0; i < count; ++i)
+    out[i] = slp::triangle_potential(x + 3 * i, a + 3 * i, b + 3 * i, c + 3 * i);
+  return SLP_OK;
+}
+
+int slp_near_radius_host(const double *es_w, const double *es_gamma, int32_t terms, double r_max,
+                         double tol, double *eps) {
+  if (!es_w || !es_gamma || !eps || terms < 1) return fail(SLP_EINVAL, "NULL argument or no terms");
+  if (!(tol > 0.0) || !(r_max > 0.0)) return fail(SLP_EINVAL, "tol and r_max must be positive");
+  const double r = slp::near_radius(es_w, es_gamma, terms, r_max, tol);
+  if (r < 0.0) return fail(SLP_EINVAL, "the sum misses 1/r by more than %g at r_max", tol);
+  *eps = r;
   return SLP_OK;
 }
 

@@ -129,6 +129,54 @@ const void *spread_bins_kernel(int m);
 template <typename T>
 const void *interp_kernel(int m);
 
+// Near-field correction (Sec. 3.4, eq. nfcorr). CSR over the targets: row i
+// lists the triangles j within eps of target i (eq. nf_index) with
+//   C_ij = int_{S_j} dsigma / |x_i - y| - |S_j| / 3 sum_s N_s(|x_i - y_{j,s}|),
+// N_s the kept exponential sum (physical units), y_{j,s} the three quadrature
+// points of triangle j.
+// Rows are stored in groups of four entries: every row starts at a multiple of
+// four and is padded to one with entries of column -1 and value 0, so that a
+// lane reads four entries with one 16-byte column load. When rows are long,
+// they are padded to chunks of 4 x 64 entries instead, and within a chunk the
+// group of lane l holds entries l, l + 64, l + 128, l + 192: the four density
+// gathers of a wave then read consecutive triangles of the sorted row.
+constexpr int kNearGroup = 4;
+constexpr int kNearChunk = 4 * 64;
+// Chunked rows may also store their columns packed: one int32 base per chunk
+// and a 16-bit offset per entry (padding: offset 0, value 0), used when every
+// chunk spans fewer than 65535 triangles.
+template <typename T>
+struct NearArgs {
+  const int64_t *rowptr;   // [rows + 1], multiples of kNearGroup (kNearChunk if chunked)
+  const int32_t *cols;     // triangle of each entry, -1 = padding (values kernel; the
+                           // product too unless packed)
+  const int32_t *bases;    // packed: [stored / kNearChunk] smallest triangle of each chunk
+  const uint16_t *offs;    // packed: [stored] triangle - base
+  T *vals;                 // C_ij (0 on padding)
+  double *gbar;            // [items][M] element means of the densities of one launch
+  int64_t rows;            // targets
+  int64_t M;               // triangles; density value s of triangle j at j + s M
+};
+// Fills a.vals from the pattern. targets [rows][3], nodes [n][3], tris [M][3]
+// (device, FP64 physical coordinates); es_w / es_g [terms] the kept terms.
+template <typename T>
+hipError_t launch_near_values(const NearArgs<T> &a, const double *targets, const double *nodes,
+                              const int32_t *tris, const double *es_w, const double *es_g,
+                              int32_t terms, hipStream_t s);
+// phi_i += 1/(4 pi) sum_j C_ij gbar_j for every batch item, gbar_j =
+// (g_j + g_{j+M} + g_{j+2M}) / 3 formed first into a.gbar (density and
+// potential from the per-item pointers). Up to eight items share one pass over
+// the matrix.
+template <typename T>
+hipError_t launch_near_apply(const NearArgs<T> &a, const BatchPtrs &p, int nb, bool packed,
+                             hipStream_t s);
+// Host handles of the two kernels of launch_near_apply (the element means, the
+// product), whose per-item pointers are updated when a captured evaluation is
+// replayed.
+const void *near_gbar_kernel();
+template <typename T>
+const void *near_apply_kernel(int nb, bool packed);
+
 // Message returned by slp_last_error() on the calling thread.
 void set_error_message(const char *msg);
 

@@ -8,6 +8,7 @@
 // mu folds the two window deconvolutions, c_l(N_s), the Hermitian weights of
 // the asymmetric index set and 1/(4 pi) into one real factor per mode.
 #include "slp_internal.hpp"
+#include "slp_near.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -876,6 +877,209 @@ hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ near field ---
+// One wave per target row; lanes take the row's entries in turn. Padding
+// entries (column -1) get the value 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_near_values(NearArgs<T> a, const double *__restrict__ tg,
+                                                     const double *__restrict__ nodes,
+                                                     const int32_t *__restrict__ tris,
+                                                     const double *__restrict__ es_w,
+                                                     const double *__restrict__ es_g,
+                                                     int32_t terms) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.rows) return;
+  const int lane = threadIdx.x & 63;
+  const double x[3] = {tg[3 * row], tg[3 * row + 1], tg[3 * row + 2]};
+  const int64_t e1 = a.rowptr[row + 1];
+  for (int64_t e = a.rowptr[row] + lane; e < e1; e += 64) {
+    const int64_t j = a.cols[e];
+    if (j < 0) {
+      a.vals[e] = (T)0;
+      continue;
+    }
+    double v[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int64_t nd = tris[3 * j + k];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) v[k][q] = nodes[3 * nd + q];
+    }
+    const double exact = triangle_potential(x, v[0], v[1], v[2]);
+    double e1v[3], e2v[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) { e1v[q] = v[1][q] - v[0][q]; e2v[q] = v[2][q] - v[0][q]; }
+    const double cx = e1v[1] * e2v[2] - e1v[2] * e2v[1];
+    const double cy = e1v[2] * e2v[0] - e1v[0] * e2v[2];
+    const double cz = e1v[0] * e2v[1] - e1v[1] * e2v[0];
+    const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+    // quadrature point s: weight 2/3 on vertex s, 1/6 on the other two
+    double smooth = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      double r2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double wq0 = (s == 0) ? 4.0 / 6 : 1.0 / 6;
+        const double wq1 = (s == 1) ? 4.0 / 6 : 1.0 / 6;
+        const double wq2 = (s == 2) ? 4.0 / 6 : 1.0 / 6;
+        const double y = wq0 * v[0][q] + wq1 * v[1][q] + wq2 * v[2][q];
+        r2 += (x[q] - y) * (x[q] - y);
+      }
+      for (int t = 0; t < terms; ++t) smooth += es_w[t] * exp(-es_g[t] * r2);
+    }
+    a.vals[e] = (T)(exact - area / 3.0 * smooth);
+  }
+}
+
+template <typename T>
+hipError_t launch_near_values(const NearArgs<T> &a, const double *targets, const double *nodes,
+                              const int32_t *tris, const double *es_w, const double *es_g,
+                              int32_t terms, hipStream_t s) {
+  if (a.rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_near_values<T>, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a,
+                     targets, nodes, tris, es_w, es_g, terms);
+  return hipGetLastError();
+}
+
+// gbar[item][j] = (g_j + g_{j+M} + g_{j+2M}) / 3 for item = blockIdx.y.
+__global__ __launch_bounds__(256) void k_near_gbar(BatchPtrs p, double *__restrict__ gbar,
+                                                   int64_t M) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= M) return;
+  const double *__restrict__ g = p.dens[blockIdx.y];
+  gbar[blockIdx.y * M + j] = (g[j] + g[j + M] + g[j + 2 * M]) * (1.0 / 3.0);
+}
+
+// Four entries (their triangles and values) times the element means of IB
+// items. Padding entries carry value 0 and read a valid triangle.
+template <int IB>
+__device__ __forceinline__ void near_group(int64_t j0, int64_t j1, int64_t j2, int64_t j3,
+                                           const double v[4], const double *__restrict__ gb,
+                                           int64_t M, int n_it, double acc[IB]) {
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    if (i < n_it) {
+      const double *__restrict__ g = gb + i * M;
+      acc[i] += v[0] * g[j0] + v[1] * g[j1] + v[2] * g[j2] + v[3] * g[j3];
+    }
+  }
+}
+
+__device__ __forceinline__ void load_group(const double *vals, int64_t q, double v[4]) {
+  const double2 a = reinterpret_cast<const double2 *>(vals)[2 * q];
+  const double2 b = reinterpret_cast<const double2 *>(vals)[2 * q + 1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load_group(const float *vals, int64_t q, double v[4]) {
+  const float4 a = reinterpret_cast<const float4 *>(vals)[q];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+// Triangles of the group at q: 16-byte column load, or packed base + four
+// 16-bit offsets (the base of the chunk q / 64 is the same on every lane).
+template <bool PACKED, typename A>
+__device__ __forceinline__ void group_cols(const A &a, int64_t q, int64_t j[4]) {
+  if constexpr (PACKED) {
+    const int32_t base = a.bases[__builtin_amdgcn_readfirstlane((int)(q >> 6))];
+    const uint2 o = reinterpret_cast<const uint2 *>(a.offs)[q];
+    j[0] = base + (int32_t)(o.x & 0xffffu);
+    j[1] = base + (int32_t)(o.x >> 16);
+    j[2] = base + (int32_t)(o.y & 0xffffu);
+    j[3] = base + (int32_t)(o.y >> 16);
+  } else {
+    const int4 c = reinterpret_cast<const int4 *>(a.cols)[q];
+    j[0] = c.x < 0 ? 0 : c.x;
+    j[1] = c.y < 0 ? 0 : c.y;
+    j[2] = c.z < 0 ? 0 : c.z;
+    j[3] = c.w < 0 ? 0 : c.w;
+  }
+}
+
+// phi_i += sum_j C_ij gbar_j / (4 pi). One wave per row; a lane takes groups
+// of four entries, two groups in flight; the IB items of blockIdx.y share the
+// matrix reads. FP64 accumulation.
+template <typename T, int IB, bool PACKED>
+__global__ __launch_bounds__(256) void k_near_apply(NearArgs<T> a, BatchPtrs p, int32_t nb) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.rows) return;
+  const int lane = threadIdx.x & 63;
+  const int item0 = blockIdx.y * IB;
+  const int n_it = nb - item0 < IB ? nb - item0 : IB;
+  const int64_t M = a.M;
+  const double *__restrict__ gb = a.gbar + (int64_t)item0 * M;
+  const int64_t q1 = a.rowptr[row + 1] / kNearGroup;
+  int64_t q = a.rowptr[row] / kNearGroup + lane;
+  double acc[IB];
+#pragma unroll
+  for (int i = 0; i < IB; ++i) acc[i] = 0.0;
+  for (; q + 64 < q1; q += 128) {
+    int64_t j0[4], j1[4];
+    group_cols<PACKED>(a, q, j0);
+    group_cols<PACKED>(a, q + 64, j1);
+    double v0[4], v1[4];
+    load_group(a.vals, q, v0);
+    load_group(a.vals, q + 64, v1);
+    near_group<IB>(j0[0], j0[1], j0[2], j0[3], v0, gb, M, n_it, acc);
+    near_group<IB>(j1[0], j1[1], j1[2], j1[3], v1, gb, M, n_it, acc);
+  }
+  if (q < q1) {
+    int64_t j0[4];
+    group_cols<PACKED>(a, q, j0);
+    double v0[4];
+    load_group(a.vals, q, v0);
+    near_group<IB>(j0[0], j0[1], j0[2], j0[3], v0, gb, M, n_it, acc);
+  }
+  const double inv4pi = 1.0 / (4.0 * 3.141592653589793238462643383279502884);
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    double s = acc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0 && i < n_it) p.phi[item0 + i][row] += s * inv4pi;
+  }
+}
+
+template <typename T, bool PACKED>
+const void *near_apply_kernel_p(int nb) {
+  if (nb >= 8) return reinterpret_cast<const void *>(&k_near_apply<T, 8, PACKED>);
+  if (nb >= 4) return reinterpret_cast<const void *>(&k_near_apply<T, 4, PACKED>);
+  if (nb >= 2) return reinterpret_cast<const void *>(&k_near_apply<T, 2, PACKED>);
+  return reinterpret_cast<const void *>(&k_near_apply<T, 1, PACKED>);
+}
+
+template <typename T>
+const void *near_apply_kernel(int nb, bool packed) {
+  return packed ? near_apply_kernel_p<T, true>(nb) : near_apply_kernel_p<T, false>(nb);
+}
+
+const void *near_gbar_kernel() { return reinterpret_cast<const void *>(&k_near_gbar); }
+
+template <typename T, bool PACKED>
+void launch_near_apply_p(const NearArgs<T> &a, const BatchPtrs &p, int nb, hipStream_t s) {
+  const int ib = nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
+  const dim3 grid((unsigned)((a.rows + 3) / 4), (unsigned)((nb + ib - 1) / ib));
+  switch (ib) {
+    case 8: hipLaunchKernelGGL((k_near_apply<T, 8, PACKED>), grid, dim3(256), 0, s, a, p, nb); break;
+    case 4: hipLaunchKernelGGL((k_near_apply<T, 4, PACKED>), grid, dim3(256), 0, s, a, p, nb); break;
+    case 2: hipLaunchKernelGGL((k_near_apply<T, 2, PACKED>), grid, dim3(256), 0, s, a, p, nb); break;
+    default: hipLaunchKernelGGL((k_near_apply<T, 1, PACKED>), grid, dim3(256), 0, s, a, p, nb); break;
+  }
+}
+
+template <typename T>
+hipError_t launch_near_apply(const NearArgs<T> &a, const BatchPtrs &p, int nb, bool packed,
+                             hipStream_t s) {
+  if (a.rows <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_near_gbar, dim3((unsigned)((a.M + 255) / 256), (unsigned)nb), dim3(256), 0,
+                     s, p, a.gbar, a.M);
+  if (packed)
+    launch_near_apply_p<T, true>(a, p, nb, s);
+  else
+    launch_near_apply_p<T, false>(a, p, nb, s);
+  return hipGetLastError();
+}
+
 template <typename T>
 const void *spread_bins_kernel(int m) {
   switch (m) {
@@ -921,6 +1125,18 @@ template hipError_t launch_interp<float>(const InterpArgs<float> &, const BatchP
                                          int, hipStream_t);
 template hipError_t launch_interp<double>(const InterpArgs<double> &, const BatchPtrs &, int, int,
                                           int, hipStream_t);
+template hipError_t launch_near_values<float>(const NearArgs<float> &, const double *,
+                                              const double *, const int32_t *, const double *,
+                                              const double *, int32_t, hipStream_t);
+template hipError_t launch_near_values<double>(const NearArgs<double> &, const double *,
+                                               const double *, const int32_t *, const double *,
+                                               const double *, int32_t, hipStream_t);
+template hipError_t launch_near_apply<float>(const NearArgs<float> &, const BatchPtrs &, int,
+                                             bool, hipStream_t);
+template hipError_t launch_near_apply<double>(const NearArgs<double> &, const BatchPtrs &, int,
+                                              bool, hipStream_t);
+template const void *near_apply_kernel<float>(int, bool);
+template const void *near_apply_kernel<double>(int, bool);
 template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
 template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,

@@ -1,0 +1,198 @@
+"""Near-field correction (Sec. 3.4) on the device: the index sets and matrix
+values against the oracle; the complete potential phi_s + phi_NF against the
+oracle's NDFT route plus its near-field sum, against the exact surface
+integrals and against the closed form of the uniformly magnetised sphere;
+batched, graph-replayed and volume-target evaluations; and the full-size cube
+on sampled rows."""
+import numpy as np
+import pytest
+
+import paper_1305_3162_amd as slp
+from oracle import direct, nearfield as nfo
+from synth import cube, cube_volume_nodes, RandomSmoothMagnetisation, density_from_magnetisation
+from synth.workloads import expsum_interval, make_workload, sphere_uniform
+from slp_testlib import es_for, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check_row(a, b, dist_b, eps, x, nodes, tris):
+    """One row of the library's index sets (a) against the oracle's (b, with its
+    distances): equal, except for triangles at distance eps within rounding,
+    which either side may hold. Returns the mask of b's entries found in a."""
+    in_a = np.isin(b, a)
+    tie_b = np.abs(dist_b - eps) <= 1e-12 * eps
+    assert np.all(in_a | tie_b)
+    extra = np.setdiff1d(a, b)
+    if extra.size:
+        d = nfo.point_triangle_distance(x, nodes[tris[extra, 0]], nodes[tris[extra, 1]],
+                                        nodes[tris[extra, 2]])
+        assert np.all(np.abs(d - eps) <= 1e-12 * eps)
+    assert np.all(np.diff(a) > 0)
+    return in_a
+
+
+@pytest.fixture(scope="module")
+def sphere3():
+    wl = sphere_uniform(3, 64, 8)
+    prob = direct.prepare_workload(wl)
+    gbar = nfo.element_mean_density(prob, wl.tris.shape[0])
+    exact = nfo.phi_exact_integrals(wl.nodes, wl.tris, gbar, wl.nodes)
+    far = direct.phi_ndft(prob)
+    eps = nfo.near_radius(prob, 1e-3, wl.es_r_hi)
+    near, rp, cols, vals = nfo.phi_near(prob, wl.nodes, wl.tris, eps)
+    _, _, dist = nfo.near_pairs(wl.nodes, wl.tris, wl.nodes, eps)
+    return wl, prob, exact, far, eps, (near, rp, cols, vals, dist)
+
+
+@pytest.mark.parametrize("m,prec,window,tol", [(8, slp.FP64, slp.WINDOW_GAUSS, 1e-6),
+                                               (4, slp.FP64, slp.WINDOW_KB, 1e-6),
+                                               (5, slp.FP32, slp.WINDOW_GAUSS, 1e-4)])
+def test_sphere_near_field_against_oracle(sphere3, m, prec, window, tol):
+    wl, prob, exact, far, eps_o, (near, rp_o, cols_o, vals_o, dist_o) = sphere3
+    log(f"case near sphere_l3 m={m} prec={prec} window={window}")
+    w, g = es_for(wl)
+    G = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2, window=window)
+    eps = G.near_radius(1e-3)
+    assert eps == pytest.approx(eps_o, rel=2.1e-3)
+    d = torch.as_tensor(wl.dens).cuda()
+    smooth = G.solve(d).cpu().numpy()
+    G.setup_near_field(eps_o)
+    info = G.near_field_info()
+    log(f"  eps {info['eps']:.4f} nnz {info['nnz']}")
+    rp, cols, vals = slp.debug_copy_near(G.handle)
+    scale = np.abs(vals_o).max()
+    vtol = 1e-12 if prec == slp.FP64 else 1e-7
+    for i in range(wl.n_nodes):
+        a, b = cols[rp[i]:rp[i + 1]], cols_o[rp_o[i]:rp_o[i + 1]]
+        both = _check_row(a, b, dist_o[rp_o[i]:rp_o[i + 1]], eps_o, wl.nodes[i], wl.nodes, wl.tris)
+        va = vals[rp[i]:rp[i + 1]][np.isin(a, b)]
+        assert np.abs(va - vals_o[rp_o[i]:rp_o[i + 1]][both]).max() <= vtol * scale, i
+    phi = G.solve(d).cpu().numpy()
+    torch.cuda.synchronize()
+    e = rel_l2(phi, far + near)
+    log(f"  complete: rel-L2 vs oracle {e:.3e}, vs exact integrals "
+        f"{np.abs(phi - exact).max() / np.abs(exact).max():.3e}, smooth part alone "
+        f"{np.abs(smooth - exact).max() / np.abs(exact).max():.3e}")
+    assert e <= tol
+    # the smooth part alone misses the exact integrals by far; the complete one
+    # matches them to the Fourier error, and z/3 to the flat-triangle error
+    assert np.abs(smooth - exact).max() > 0.1 * np.abs(exact).max()
+    assert np.abs(phi - exact).max() <= 1e-4 * np.abs(exact).max()
+    assert np.abs(phi - wl.nodes[:, 2] / 3.0).max() <= 2e-3
+    # eps <= 0 removes the near field again
+    G.setup_near_field(0.0)
+    assert G.near_field_info()["nnz"] == 0
+    again = G.solve(d).cpu().numpy()
+    assert rel_l2(again, smooth) <= (1e-14 if prec == slp.FP64 else 1e-6)
+    G.close()
+
+
+def test_near_field_batched_and_graph():
+    wl = sphere_uniform(3, 64, 6)
+    log("case near batched + graph sphere_l3 m=6 fp64")
+    w, g = es_for(wl)
+    G = slp.Geometry(wl.nodes, wl.tris, wl.grid, 6, w, g, wl.alpha, slp.FP64, wl.eta2)
+    G.setup_near_field(G.near_radius(1e-2))
+    rng = np.random.default_rng(61)
+    dens = [torch.as_tensor(rng.normal(size=wl.n_src)).cuda() for _ in range(4)]
+    ref = [G.solve(dd).cpu().numpy() for dd in dens]
+    stream = torch.cuda.current_stream()
+    phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+            for _ in range(4)]
+    slp.eval_batched([G.handle] * 4, dens, phis, stream)
+    torch.cuda.synchronize()
+    for k in range(4):
+        assert rel_l2(phis[k].cpu().numpy(), ref[k]) <= 1e-14, k
+    slp.set_graph(G.handle, True)
+    halves = [dd * 0.5 for dd in dens]        # kept alive until the replays have run
+    for rep in range(3):
+        outs = []
+        for k, dd in enumerate(dens):
+            phi = torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+            G.set_density(halves[k] if rep == 1 else dd, stream)
+            G.eval(phi, stream)
+            outs.append(phi)
+        torch.cuda.synchronize()
+        for k in range(4):
+            want = ref[k] * (0.5 if rep == 1 else 1.0)
+            assert rel_l2(outs[k].cpu().numpy(), want) <= 1e-14, (rep, k)
+        phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+                for _ in range(3)]
+        slp.eval_batched([G.handle] * 3, dens[:3], phis, stream)
+        torch.cuda.synchronize()
+        for k in range(3):
+            assert rel_l2(phis[k].cpu().numpy(), ref[k]) <= 1e-14, (rep, k)
+    slp.set_graph(G.handle, False)
+    G.close()
+
+
+def test_near_field_volume_targets():
+    nodes, tris = cube(8)
+    mf = RandomSmoothMagnetisation(62, nodes.min(0), nodes.max(0))
+    dens = density_from_magnetisation(nodes, tris, mf)
+    tg = cube_volume_nodes(8)
+    r_lo, r_hi = expsum_interval(nodes)
+    grid = (64, 64, 64)
+    log(f"case near volume targets cube8 ({tg.shape[0]} points) m=8 fp64")
+    p = direct.prepare(nodes, tris, dens, grid, es_r_lo=r_lo, es_r_hi=r_hi, targets=tg)
+    eps = nfo.near_radius(p, 1e-3, r_hi)
+    near, rp_o, cols_o, _ = nfo.phi_near(p, nodes, tris, eps, targets=tg)
+    ref = direct.phi_ndft(p) + near
+    w, g = slp.expsum_sinc(0.2, r_lo, r_hi, 1e-12)
+    G = slp.Geometry(nodes, tris, grid, 8, w, g, 2, slp.FP64, targets=tg)
+    G.setup_near_field(eps)
+    rp, cols, _ = slp.debug_copy_near(G.handle)
+    assert np.array_equal(rp, rp_o) and np.array_equal(cols, cols_o)
+    phi = G.solve(torch.as_tensor(dens).cuda()).cpu().numpy()
+    G.close()
+    e = rel_l2(phi, ref)
+    log(f"  rel-L2 vs oracle {e:.3e} (nnz {rp[-1]})")
+    assert e <= 1e-6
+
+
+def test_cube64_full_size_sampled_rows():
+    """The timed configuration (cube64, Gaussian m = 8, FP64) with the near field
+    of tol 1e-4: about 1.5e8 pairs. Rows sampled at corners, edges, faces and at
+    random; index sets and values against the oracle's, the complete potential
+    against the oracle's NDFT route plus its near-field sum on those rows."""
+    wl = make_workload("cube64", 8)
+    log("case near cube64 full size fp64 m=8 tol 1e-4")
+    prob = direct.prepare_workload(wl)
+    w, g = es_for(wl)
+    G = slp.Geometry(wl.nodes, wl.tris, wl.grid, 8, w, g, wl.alpha, slp.FP64, wl.eta2)
+    eps = nfo.near_radius(prob, 1e-4, wl.es_r_hi)
+    G.setup_near_field(eps)
+    info = G.near_field_info()
+    log(f"  eps {eps:.4f} nnz {info['nnz']} device bytes {G.info['device_bytes']}")
+    phi = G.solve(torch.as_tensor(wl.dens).cuda()).cpu().numpy()
+    rp, cols, vals = slp.debug_copy_near(G.handle)
+    G.close()
+    rng = np.random.default_rng(63)
+    corner = int(np.argmin(wl.nodes.sum(1)))
+    face = int(np.argmin(np.abs(wl.nodes - np.array([0.0, 0.0, 0.5])).sum(1)))
+    edge = int(np.argmin(np.abs(wl.nodes - np.array([0.5, 0.0, 0.5])).sum(1)))
+    rows = [corner, face, edge] + rng.choice(wl.n_nodes, 5, replace=False).tolist()
+    xs = wl.nodes[rows]
+    rp_o, cols_o, dist_o = nfo.near_pairs(wl.nodes, wl.tris, xs, eps)
+    vals_o = nfo.near_values(prob, wl.nodes, wl.tris, xs, rp_o, cols_o)
+    gbar = nfo.element_mean_density(prob, wl.tris.shape[0])
+    far = direct.phi_ndft(prob)
+    for k, i in enumerate(rows):
+        a = cols[rp[i]:rp[i + 1]]
+        b = cols_o[rp_o[k]:rp_o[k + 1]]
+        both = _check_row(a, b, dist_o[rp_o[k]:rp_o[k + 1]], eps, xs[k], wl.nodes, wl.tris)
+        va = vals[rp[i]:rp[i + 1]][np.isin(a, b)]
+        vb = vals_o[rp_o[k]:rp_o[k + 1]][both]
+        assert np.abs(va - vb).max() <= 1e-12 * np.abs(vb).max(), i
+        near_i = (vals_o[rp_o[k]:rp_o[k + 1]] @ gbar[b]) / nfo.FOUR_PI
+        want = far[i] + near_i
+        log(f"  row {i}: {a.size} pairs, phi {phi[i]:.9e} oracle {want:.9e}")
+        assert abs(phi[i] - want) <= 1e-6 * np.abs(far).max(), i
