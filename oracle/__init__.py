@@ -26,8 +26,11 @@ eq. (smooth_phi). Modules:
   nearfield  the near-field correction of Sec. 3.4 (kernel 1/r - N_s on the
              pairs within eps), exact triangle integrals, the complete
              potential phi_s + phi_NF and the exact-integral reference
+  fem        the P1 Dirichlet problem for phi_1 (Sec. 2, 2.1), its normal
+             derivative on the boundary triangles, and the complete scalar
+             potential phi_1 + phi_2 at every node (Alg. 1)
 
 Parity pins live in tests/test_oracle_*.py. Functions without an independent
 pin are marked "parity unpinned" in their docstrings.
 """
-from . import geometry, kernel, direct, nufft, nearfield  # noqa: F401
+from . import geometry, kernel, direct, nufft, nearfield, fem  # noqa: F401

@@ -113,6 +113,54 @@ def cube_volume_nodes(cells_per_edge: int):
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
 
 
+def cube_tets(cells_per_edge: int):
+    """Structured tetrahedral mesh of the unit cube [-1/2, 1/2]^3: the nodes of
+    cube_volume_nodes(c) (index (i (c+1) + j)(c+1) + k for lattice point (i, j, k))
+    and every lattice cell split into the six tetrahedra that share its diagonal
+    from the lowest to the highest corner (one per order of the three axes).
+    Each boundary face of a cell is then split along its (i, j) -> (i+1, j+1)
+    diagonal, as in cube(c). Tetrahedra are positively oriented. Returns
+    (nodes [(c+1)^3, 3], tets int32 [6 c^3, 4])."""
+    c = int(cells_per_edge)
+    nodes = cube_volume_nodes(c)
+    n1 = c + 1
+    ii, jj, kk = np.meshgrid(np.arange(c), np.arange(c), np.arange(c), indexing="ij")
+    base = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
+    tets = []
+    for order in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        corner = base.copy()
+        verts = [corner.copy()]
+        for ax in order:
+            corner[:, ax] += 1
+            verts.append(corner.copy())
+        ids = [(v[:, 0] * n1 + v[:, 1]) * n1 + v[:, 2] for v in verts]
+        tets.append(np.stack(ids, axis=1))
+    tets = np.concatenate(tets, axis=0).astype(np.int32)
+    return nodes, _orient_tets(nodes, tets)
+
+
+def ball_tets(cells_per_edge: int, radius: float = 1.0):
+    """cube_tets(c) mapped onto the ball of the given radius by
+    x -> 2 radius x |x|_inf / |x|_2 (the cube's boundary onto the sphere; the
+    map is continuous and one-to-one, tetrahedra keep their orientation for the
+    sizes used here)."""
+    nodes, tets = cube_tets(cells_per_edge)
+    r2 = np.linalg.norm(nodes, axis=1)
+    rinf = np.abs(nodes).max(axis=1)
+    fac = np.where(r2 > 0, 2.0 * radius * rinf / np.where(r2 > 0, r2, 1.0), 0.0)
+    return nodes * fac[:, None], tets
+
+
+def _orient_tets(nodes, tets):
+    """Swap two vertices of every negatively oriented tetrahedron."""
+    P = nodes[tets]
+    vol = np.einsum("ij,ij->i", np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0]), P[:, 3] - P[:, 0])
+    neg = vol < 0
+    if np.any(neg):
+        tets[neg] = tets[neg][:, [0, 2, 1, 3]]
+    return tets
+
+
 def thin_film(cells_xy: int = 512, cells_z: int = 10, thickness: float = 0.02):
     """Thin film 1 x 1 x thickness: cells_xy^2 cells on the large faces and
     cells_xy x cells_z cells on each side face."""
