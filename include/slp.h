@@ -283,6 +283,62 @@ int slp_triangle_potential_host(const double *x, const double *a, const double *
 int slp_near_radius_host(const double *es_w, const double *es_gamma, int32_t terms, double r_max,
                          double tol, double *eps);
 
+/* ---- Dirichlet problem for phi_1 and the complete scalar potential ------------
+ * Sec. 2 splits phi = phi_1 + phi_2: -Laplace phi_1 = -div m in the body with
+ * phi_1 = 0 on its boundary (eq. GR1), solved by P1 finite elements on a
+ * tetrahedral mesh (Sec. 2.1: weak form eq. varu1, free-node system eq.
+ * poisson), and phi_2 the single-layer potential of g = m.n - d phi_1/dn
+ * (eq. slayer). Alg. 1's computation phase is slp_scalar_potential. */
+typedef struct slp_fem slp_fem;   /* opaque; owns the mesh tables and the solver buffers */
+
+/* Setup for a tetrahedral mesh: gradients of the barycentric coordinates and
+ * volumes, the boundary triangles (faces of exactly one tetrahedron, oriented
+ * outward, ordered by their sorted vertex triple), the free (interior) nodes,
+ * and the stiffness matrix on the free nodes S_km = sum_T int grad eta_m .
+ * grad eta_k as CSR (FP64), all held on the device.
+ *   nodes : host float64 [n_nodes][3];  tets : host int32 [n_tets][4], 0-based
+ * Errors: EINVAL for indices out of range, non-finite coordinates, degenerate
+ * tetrahedra, faces shared by more than two tetrahedra or a mesh without
+ * boundary; ENOMEM; EDEVICE. */
+int slp_fem_setup(slp_fem **out, const double *nodes, int64_t n_nodes, const int32_t *tets,
+                  int64_t n_tets, void *stream);
+/* Free nodes, boundary triangles, stored entries of S and device bytes (any
+ * pointer may be NULL). */
+int slp_fem_info(const slp_fem *f, int64_t *n_free, int64_t *n_boundary_tris, int64_t *nnz,
+                 int64_t *device_bytes);
+/* The boundary triangles, host int32 [n_boundary_tris][3] (cap = room, in
+ * triangles): the surface mesh to hand to slp_setup_geometry together with all
+ * nodes (so that the targets are every node), in the order of dphi1_dn. */
+int slp_fem_boundary(const slp_fem *f, int32_t *tris, int64_t cap);
+/* phi_1 at every node (0 on the boundary): load vector b_k = sum_T |T| mbar_T .
+ * grad eta_k (m the nodal P1 field, mbar_T its vertex mean), then conjugate
+ * gradients with the diagonal (Jacobi) preconditioner on the free nodes until
+ * |r| <= tol |b| (checked every 16 iterations) or max_iter iterations.
+ *   m_nodes : device float64 [n_nodes][3];  phi1 : device float64 [n_nodes]
+ *   warm_start != 0: start from the free-node values phi1 holds
+ *   iters, rel_res : receive the iterations done and |r|/|b| (may be NULL)
+ * Synchronises `stream` at every check. EINVAL if tol is not met (phi1 then
+ * holds the last iterate). */
+int slp_fem_solve_phi1(slp_fem *f, const double *m_nodes, double *phi1, double tol,
+                       int32_t max_iter, int32_t warm_start, int32_t *iters, double *rel_res,
+                       void *stream);
+/* d phi_1/dn on every boundary triangle: the gradient of the P1 function phi_1
+ * in the tetrahedron owning the face, dotted with its unit outward normal.
+ *   phi1 : device float64 [n_nodes];  dphi1_dn : device float64 [n_boundary_tris] */
+int slp_fem_dphi1_dn(slp_fem *f, const double *phi1, double *dphi1_dn, void *stream);
+/* Computation phase of Alg. 1: phi_1 (as slp_fem_solve_phi1, into a buffer of
+ * the context; warm_start reuses the previous call's phi_1), d phi_1/dn, the
+ * element density g = mean(m.n) - d phi_1/dn (slp_set_density_from_m), phi_2 at
+ * every node (slp_eval_single_layer: smooth part, plus the near-field
+ * correction if g has one), and phi = phi_1 + phi_2.
+ *   g   : a context set up with all of the mesh's nodes as nodes (hence as
+ *         targets) and the triangles of slp_fem_boundary
+ *   phi : device float64 [n_nodes]
+ * EINVAL if g does not match the mesh or the solve misses tol. */
+int slp_scalar_potential(slp_fem *f, slp_geom *g, const double *m_nodes, double *phi, double tol,
+                         int32_t max_iter, int32_t warm_start, int32_t *iters, void *stream);
+int slp_fem_destroy(slp_fem *f);
+
 int slp_geom_destroy(slp_geom *g);
 const char *slp_last_error(void);
 

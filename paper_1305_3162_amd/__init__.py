@@ -20,6 +20,8 @@ __all__ = [
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
     "setup_near_field", "near_radius", "near_field_info", "debug_copy_near",
     "near_pattern_host", "triangle_potential_host", "near_radius_host",
+    "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
+    "scalar_potential", "fem_destroy", "Fem",
 ]
 
 FP64, FP32 = 0, 1
@@ -117,6 +119,16 @@ def load_library():
         "slp_triangle_potential_host": [_VP, _VP, _VP, _VP, ctypes.c_int64, _VP],
         "slp_near_radius_host": [_VP, _VP, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_double)],
+        "slp_fem_setup": [ctypes.POINTER(_VP), _VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP],
+        "slp_fem_info": [_VP] + [ctypes.POINTER(ctypes.c_int64)] * 4,
+        "slp_fem_boundary": [_VP, _VP, ctypes.c_int64],
+        "slp_fem_solve_phi1": [_VP, _VP, _VP, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
+                               _VP],
+        "slp_fem_dphi1_dn": [_VP, _VP, _VP, _VP],
+        "slp_scalar_potential": [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _VP],
+        "slp_fem_destroy": [_VP],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -430,6 +442,66 @@ def near_radius_host(es_w, es_gamma, r_max, tol):
     return out.value
 
 
+def fem_setup(nodes, tets, stream=None):
+    """slp_fem_setup: P1 Dirichlet-problem context for a tetrahedral mesh (handle)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    if nodes.ndim != 2 or nodes.shape[1] != 3 or tets.ndim != 2 or tets.shape[1] != 4:
+        raise ValueError("nodes must be [N, 3] and tets [T, 4]")
+    h = _VP()
+    _check(load_library().slp_fem_setup(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
+                                        tets.ctypes.data, tets.shape[0], _stream_ptr(stream)))
+    return h.value
+
+
+def fem_info(fem):
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    _check(load_library().slp_fem_info(_VP(fem), *[ctypes.byref(x) for x in v]))
+    return dict(zip(("n_free", "n_boundary_tris", "nnz", "device_bytes"), [x.value for x in v]))
+
+
+def fem_boundary(fem):
+    n = fem_info(fem)["n_boundary_tris"]
+    tris = np.zeros((n, 3), dtype=np.int32)
+    _check(load_library().slp_fem_boundary(_VP(fem), tris.ctypes.data, n))
+    return tris
+
+
+def fem_solve_phi1(fem, m_nodes, phi1, tol=1e-10, max_iter=20000, warm_start=False, stream=None):
+    """slp_fem_solve_phi1 (m_nodes CUDA float64 [N, 3], phi1 CUDA float64 [N]);
+    returns (iterations, relative residual)."""
+    it, rr = ctypes.c_int32(0), ctypes.c_double(0.0)
+    n = phi1.numel()
+    _check(load_library().slp_fem_solve_phi1(_VP(fem), _dev_f64(m_nodes, 3 * n, "m_nodes"),
+                                             _dev_f64(phi1, n, "phi1"), float(tol), int(max_iter),
+                                             int(bool(warm_start)), ctypes.byref(it),
+                                             ctypes.byref(rr), _stream_ptr(stream)))
+    return it.value, rr.value
+
+
+def fem_dphi1_dn(fem, phi1, dn, stream=None):
+    n = fem_info(fem)["n_boundary_tris"]
+    _check(load_library().slp_fem_dphi1_dn(_VP(fem), _dev_f64(phi1, phi1.numel(), "phi1"),
+                                           _dev_f64(dn, n, "dphi1_dn"), _stream_ptr(stream)))
+
+
+def scalar_potential(fem, geom, m_nodes, phi, tol=1e-10, max_iter=20000, warm_start=False,
+                     stream=None):
+    """slp_scalar_potential: phi = phi_1 + phi_2 at every node; returns the CG iterations."""
+    it = ctypes.c_int32(0)
+    n = phi.numel()
+    _check(load_library().slp_scalar_potential(_VP(fem), _VP(geom),
+                                               _dev_f64(m_nodes, 3 * n, "m_nodes"),
+                                               _dev_f64(phi, n, "phi"), float(tol), int(max_iter),
+                                               int(bool(warm_start)), ctypes.byref(it),
+                                               _stream_ptr(stream)))
+    return it.value
+
+
+def fem_destroy(fem):
+    _check(load_library().slp_fem_destroy(_VP(fem)))
+
+
 def geom_destroy(geom):
     _check(load_library().slp_geom_destroy(_VP(geom)))
 
@@ -473,6 +545,32 @@ class Geometry:
     def close(self):
         if self.handle:
             geom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fem:
+    """Owning wrapper around one slp_fem context."""
+
+    def __init__(self, nodes, tets, stream=None):
+        self.handle = fem_setup(nodes, tets, stream)
+        self.info = fem_info(self.handle)
+        self.boundary = fem_boundary(self.handle)
+
+    def solve_phi1(self, m_nodes, phi1, tol=1e-10, max_iter=20000, warm_start=False, stream=None):
+        return fem_solve_phi1(self.handle, m_nodes, phi1, tol, max_iter, warm_start, stream)
+
+    def dphi1_dn(self, phi1, dn, stream=None):
+        fem_dphi1_dn(self.handle, phi1, dn, stream)
+
+    def close(self):
+        if self.handle:
+            fem_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

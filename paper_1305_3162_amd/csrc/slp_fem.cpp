@@ -1,0 +1,474 @@
+// Host side of the Dirichlet problem for phi_1 (Sec. 2.1) and of the complete
+// scalar potential phi = phi_1 + phi_2 (Alg. 1): mesh analysis, the free-node
+// stiffness matrix, and the orchestration of the device solve.
+#include "slp.h"
+#include "slp_fem.hpp"
+#include "slp_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace {
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  slp::set_error_message(buf);
+  return code;
+}
+
+#define FEM_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(SLP_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+}  // namespace
+
+struct slp_fem {
+  int64_t n_nodes = 0, n_tets = 0, n_free = 0, n_btris = 0, nnz = 0;
+  std::vector<int32_t> h_btris;   // [Mb][3] outward boundary triangles
+  // device
+  int32_t *tets = nullptr;        // [T][4]
+  double *vol = nullptr;          // [T]
+  double *grad = nullptr;         // [T][4][3]
+  int32_t *inc_ptr = nullptr, *inc = nullptr;
+  int32_t *free_node = nullptr;   // [Nf] node of free index f
+  int32_t *node_free = nullptr;   // [N] free index or -1
+  int32_t *rp = nullptr, *ci = nullptr;
+  double *val = nullptr, *dinv = nullptr;
+  int32_t *owner = nullptr;       // [Mb]
+  double *nrm = nullptr;          // [Mb][3]
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *part = nullptr, *hist = nullptr;
+  int32_t hist_cap = 0;
+  double *phi1 = nullptr, *dn = nullptr;   // for slp_scalar_potential
+  double *h_pin = nullptr;                 // pinned [2] for the convergence check
+  int32_t nblk = 1;
+  int64_t bytes = 0;
+  std::vector<void *> allocs;
+  hipError_t alloc(void **p_, size_t n) {
+    *p_ = nullptr;
+    hipError_t e = hipMalloc(p_, std::max<size_t>(n, 256));
+    if (e == hipSuccess) { allocs.push_back(*p_); bytes += (int64_t)std::max<size_t>(n, 256); }
+    return e;
+  }
+  void release(void *p_) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p_) {
+        (void)hipFree(p_);
+        allocs.erase(allocs.begin() + i);
+        return;
+      }
+  }
+  ~slp_fem() {
+    for (void *p_ : allocs) (void)hipFree(p_);
+    if (h_pin) (void)hipHostFree(h_pin);
+  }
+};
+
+namespace {
+
+// Boundary faces: faces of exactly one tetrahedron, oriented away from the
+// tetrahedron's fourth vertex, ordered by their sorted vertex triple.
+struct Face {
+  std::array<int32_t, 3> key;
+  int32_t tet, local;
+};
+
+int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t *tets, int64_t T,
+                   hipStream_t st) {
+  if (!out) return fail(SLP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!nodes || !tets || N < 4 || T < 1) return fail(SLP_EINVAL, "need >= 4 nodes and >= 1 tetrahedron");
+  if (N > INT32_MAX || 4 * T > INT32_MAX) return fail(SLP_EINVAL, "mesh too large for 32-bit indices");
+  for (int64_t i = 0; i < 4 * T; ++i)
+    if (tets[i] < 0 || tets[i] >= N)
+      return fail(SLP_EINVAL, "tetrahedron %lld references node %d out of range", (long long)(i / 4), tets[i]);
+  for (int64_t i = 0; i < 3 * N; ++i)
+    if (!std::isfinite(nodes[i])) return fail(SLP_EINVAL, "node %lld has a non-finite coordinate", (long long)(i / 3));
+
+  slp_fem *F = new (std::nothrow) slp_fem();
+  if (!F) return fail(SLP_ENOMEM, "host allocation failed");
+  struct Guard {
+    slp_fem *f;
+    ~Guard() { delete f; }
+  } guard{F};
+  F->n_nodes = N;
+  F->n_tets = T;
+  try {
+    // gradients of the barycentric coordinates: rows of J^{-1}, J = [x1-x0, x2-x0, x3-x0]
+    std::vector<double> vol(T), grad(12 * T);
+    for (int64_t t = 0; t < T; ++t) {
+      const double *x0 = nodes + 3 * (int64_t)tets[4 * t];
+      double J[3][3];
+      for (int c = 0; c < 3; ++c) {
+        const double *xc = nodes + 3 * (int64_t)tets[4 * t + 1 + c];
+        for (int rr = 0; rr < 3; ++rr) J[rr][c] = xc[rr] - x0[rr];
+      }
+      const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      if (!(std::fabs(det) > 0.0)) return fail(SLP_EINVAL, "tetrahedron %lld is degenerate", (long long)t);
+      double inv[3][3];
+      inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+      inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+      inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+      inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+      inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+      inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+      inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+      inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+      inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+      vol[t] = std::fabs(det) / 6.0;
+      for (int q = 0; q < 3; ++q) {
+        double s = 0.0;
+        for (int a = 0; a < 3; ++a) {
+          grad[12 * t + 3 * (a + 1) + q] = inv[a][q];
+          s += inv[a][q];
+        }
+        grad[12 * t + q] = -s;
+      }
+    }
+
+    // boundary faces
+    std::vector<Face> faces(4 * T);
+    const int fl[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};
+    for (int64_t t = 0; t < T; ++t)
+      for (int f = 0; f < 4; ++f) {
+        Face &fc = faces[4 * t + f];
+        for (int k = 0; k < 3; ++k) fc.key[k] = tets[4 * t + fl[f][k]];
+        std::sort(fc.key.begin(), fc.key.end());
+        fc.tet = (int32_t)t;
+        fc.local = f;
+      }
+    std::sort(faces.begin(), faces.end(), [](const Face &a, const Face &b) { return a.key < b.key; });
+    std::vector<int32_t> btris, owner;
+    std::vector<double> bn;
+    std::vector<char> on_bnd(N, 0);
+    for (size_t i = 0; i < faces.size();) {
+      size_t j = i + 1;
+      while (j < faces.size() && faces[j].key == faces[i].key) ++j;
+      if (j - i > 2) return fail(SLP_EINVAL, "a face is shared by more than two tetrahedra");
+      if (j - i == 1) {
+        const Face &fc = faces[i];
+        int32_t v[3];
+        for (int k = 0; k < 3; ++k) v[k] = tets[4 * (int64_t)fc.tet + fl[fc.local][k]];
+        const int32_t opp = tets[4 * (int64_t)fc.tet + fc.local];
+        const double *a = nodes + 3 * (int64_t)v[0], *b = nodes + 3 * (int64_t)v[1], *c = nodes + 3 * (int64_t)v[2];
+        const double *o = nodes + 3 * (int64_t)opp;
+        double e1[3], e2[3], n[3];
+        for (int q = 0; q < 3; ++q) { e1[q] = b[q] - a[q]; e2[q] = c[q] - a[q]; }
+        n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        const double side = n[0] * (o[0] - a[0]) + n[1] * (o[1] - a[1]) + n[2] * (o[2] - a[2]);
+        if (side > 0) {
+          std::swap(v[1], v[2]);
+          for (double &w : n) w = -w;
+        }
+        const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+        for (int k = 0; k < 3; ++k) {
+          btris.push_back(v[k]);
+          on_bnd[v[k]] = 1;
+          bn.push_back(n[k] / len);
+        }
+        owner.push_back(fc.tet);
+      }
+      i = j;
+    }
+    std::vector<Face>().swap(faces);
+    const int64_t Mb = (int64_t)owner.size();
+    if (Mb == 0) return fail(SLP_EINVAL, "the mesh has no boundary");
+
+    // free nodes, node -> (tet, local) incidence of the free nodes
+    std::vector<int32_t> node_free(N, -1), free_node;
+    for (int64_t k = 0; k < N; ++k)
+      if (!on_bnd[k]) {
+        node_free[k] = (int32_t)free_node.size();
+        free_node.push_back((int32_t)k);
+      }
+    const int64_t Nf = (int64_t)free_node.size();
+    std::vector<int32_t> inc_ptr(Nf + 1, 0), inc;
+    for (int64_t i = 0; i < 4 * T; ++i)
+      if (node_free[tets[i]] >= 0) inc_ptr[node_free[tets[i]] + 1] += 1;
+    for (int64_t f = 0; f < Nf; ++f) inc_ptr[f + 1] += inc_ptr[f];
+    inc.resize(inc_ptr[Nf]);
+    {
+      std::vector<int32_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+      for (int64_t i = 0; i < 4 * T; ++i) {
+        const int32_t f = node_free[tets[i]];
+        if (f >= 0) inc[fill[f]++] = (int32_t)i;   // 4 t + local
+      }
+    }
+
+    // S(fn, fn) by rows: row f sums |T| grad_a . grad_b over the tetrahedra
+    // of its node; columns sorted; up to 16 threads over row ranges
+    std::vector<int32_t> rp(Nf + 1, 0);
+    std::vector<std::vector<int32_t>> pc;
+    std::vector<std::vector<double>> pv;
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(
+        std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())), Nf));
+    pc.resize(nth);
+    pv.resize(nth);
+    std::vector<int32_t> rowlen(Nf, 0);
+    auto rows = [&](int w) {
+      const int64_t f0 = Nf * w / nth, f1 = Nf * (w + 1) / nth;
+      std::vector<std::pair<int32_t, double>> ent;
+      for (int64_t f = f0; f < f1; ++f) {
+        ent.clear();
+        for (int32_t e = inc_ptr[f]; e < inc_ptr[f + 1]; ++e) {
+          const int64_t t = inc[e] >> 2;
+          const int la = inc[e] & 3;
+          for (int lb = 0; lb < 4; ++lb) {
+            const int32_t g = node_free[tets[4 * t + lb]];
+            if (g < 0) continue;
+            const double *ga = &grad[12 * t + 3 * la], *gb = &grad[12 * t + 3 * lb];
+            ent.emplace_back(g, vol[t] * (ga[0] * gb[0] + ga[1] * gb[1] + ga[2] * gb[2]));
+          }
+        }
+        std::sort(ent.begin(), ent.end(),
+                  [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
+                    return a.first < b.first;
+                  });
+        int32_t n = 0;
+        for (size_t k = 0; k < ent.size();) {
+          size_t l = k;
+          double s = 0.0;
+          while (l < ent.size() && ent[l].first == ent[k].first) s += ent[l++].second;
+          pc[w].push_back(ent[k].first);
+          pv[w].push_back(s);
+          ++n;
+          k = l;
+        }
+        rowlen[f] = n;
+      }
+    };
+    {
+      std::vector<std::thread> pool;
+      for (int w = 1; w < nth; ++w) pool.emplace_back(rows, w);
+      rows(0);
+      for (std::thread &t : pool) t.join();
+    }
+    for (int64_t f = 0; f < Nf; ++f) rp[f + 1] = rp[f] + rowlen[f];
+    const int64_t nnz = rp[Nf];
+    std::vector<int32_t> ci(nnz);
+    std::vector<double> val(nnz), dinv(Nf, 0.0);
+    for (int w = 0; w < nth; ++w) {
+      const int64_t f0 = Nf * w / nth;
+      std::copy(pc[w].begin(), pc[w].end(), ci.begin() + rp[f0]);
+      std::copy(pv[w].begin(), pv[w].end(), val.begin() + rp[f0]);
+    }
+    for (int64_t f = 0; f < Nf; ++f)
+      for (int32_t e = rp[f]; e < rp[f + 1]; ++e)
+        if (ci[e] == f) dinv[f] = 1.0 / val[e];
+
+    F->n_free = Nf;
+    F->n_btris = Mb;
+    F->nnz = nnz;
+    F->nblk = (int32_t)std::max<int64_t>(1, (Nf + slp::kFemThreads - 1) / slp::kFemThreads);
+    F->h_btris = btris;
+
+    // device buffers
+    struct Req { void **p; size_t n; };
+    const Req reqs[] = {
+        {(void **)&F->tets, (size_t)4 * T * 4}, {(void **)&F->vol, (size_t)T * 8},
+        {(void **)&F->grad, (size_t)12 * T * 8}, {(void **)&F->inc_ptr, (size_t)(Nf + 1) * 4},
+        {(void **)&F->inc, inc.size() * 4}, {(void **)&F->free_node, (size_t)std::max<int64_t>(Nf, 1) * 4},
+        {(void **)&F->node_free, (size_t)N * 4}, {(void **)&F->rp, (size_t)(Nf + 1) * 4},
+        {(void **)&F->ci, (size_t)nnz * 4}, {(void **)&F->val, (size_t)nnz * 8},
+        {(void **)&F->dinv, (size_t)Nf * 8}, {(void **)&F->owner, (size_t)Mb * 4},
+        {(void **)&F->nrm, (size_t)3 * Mb * 8}, {(void **)&F->b, (size_t)Nf * 8},
+        {(void **)&F->x, (size_t)Nf * 8}, {(void **)&F->r, (size_t)Nf * 8},
+        {(void **)&F->z, (size_t)Nf * 8}, {(void **)&F->p, (size_t)Nf * 8},
+        {(void **)&F->q, (size_t)Nf * 8}, {(void **)&F->part, (size_t)5 * F->nblk * 8},
+        {(void **)&F->phi1, (size_t)N * 8}, {(void **)&F->dn, (size_t)Mb * 8},
+    };
+    for (const Req &rq : reqs)
+      if (F->alloc(rq.p, rq.n) != hipSuccess)
+        return fail(SLP_ENOMEM, "device allocation failed (%lld bytes so far)", (long long)F->bytes);
+    FEM_TRY(hipHostMalloc((void **)&F->h_pin, 2 * sizeof(double), hipHostMallocDefault));
+    FEM_TRY(hipMemcpyAsync(F->tets, tets, (size_t)4 * T * 4, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->vol, vol.data(), (size_t)T * 8, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->grad, grad.data(), (size_t)12 * T * 8, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->inc_ptr, inc_ptr.data(), (size_t)(Nf + 1) * 4, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->inc, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, st));
+    if (Nf > 0) FEM_TRY(hipMemcpyAsync(F->free_node, free_node.data(), (size_t)Nf * 4, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->node_free, node_free.data(), (size_t)N * 4, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->rp, rp.data(), (size_t)(Nf + 1) * 4, hipMemcpyHostToDevice, st));
+    if (nnz > 0) {
+      FEM_TRY(hipMemcpyAsync(F->ci, ci.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+      FEM_TRY(hipMemcpyAsync(F->val, val.data(), (size_t)nnz * 8, hipMemcpyHostToDevice, st));
+      FEM_TRY(hipMemcpyAsync(F->dinv, dinv.data(), (size_t)Nf * 8, hipMemcpyHostToDevice, st));
+    }
+    FEM_TRY(hipMemcpyAsync(F->owner, owner.data(), (size_t)Mb * 4, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->nrm, bn.data(), (size_t)3 * Mb * 8, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipStreamSynchronize(st));
+  } catch (const std::bad_alloc &) {
+    return fail(SLP_ENOMEM, "host allocation failed during the mesh analysis");
+  }
+  guard.f = nullptr;
+  *out = F;
+  return SLP_OK;
+}
+
+slp::PcgArgs pcg_args(slp_fem *F, const double *x0) {
+  slp::PcgArgs a{};
+  a.rp = F->rp;
+  a.ci = F->ci;
+  a.val = F->val;
+  a.dinv = F->dinv;
+  a.b = F->b;
+  a.x = F->x;
+  a.r = F->r;
+  a.z = F->z;
+  a.p = F->p;
+  a.q = F->q;
+  a.part = F->part;
+  a.hist = F->hist;
+  a.node_free = F->node_free;
+  a.x0 = x0;
+  a.nf = F->n_free;
+  a.n_nodes = F->n_nodes;
+  a.nblk = F->nblk;
+  return a;
+}
+
+int solve_impl(slp_fem *F, const double *m, double *phi1, double tol, int32_t max_iter,
+               int32_t warm, int32_t *iters, double *rel_res, hipStream_t st) {
+  if (!F || !m || !phi1) return fail(SLP_EINVAL, "NULL argument");
+  if (!(tol > 0.0) || max_iter < 1) return fail(SLP_EINVAL, "tol must be positive and max_iter >= 1");
+  if (F->hist_cap < max_iter + 1) {
+    void *h = nullptr;
+    if (F->alloc(&h, (size_t)(max_iter + 1) * 8) != hipSuccess)
+      return fail(SLP_ENOMEM, "device allocation of the residual history failed");
+    F->release(F->hist);
+    F->hist = static_cast<double *>(h);
+    F->hist_cap = max_iter + 1;
+  }
+  int32_t it = 0;
+  double rel = 0.0;
+  if (F->n_free > 0) {
+    slp::FemLoadArgs la{};
+    la.inc_ptr = F->inc_ptr;
+    la.inc = F->inc;
+    la.tets = F->tets;
+    la.vol = F->vol;
+    la.grad = F->grad;
+    la.m = m;
+    la.b = F->b;
+    la.nf = F->n_free;
+    FEM_TRY(slp::launch_fem_load(la, st));
+    const slp::PcgArgs a = pcg_args(F, warm ? phi1 : nullptr);
+    FEM_TRY(slp::launch_pcg_start(a, F->free_node, st));
+    FEM_TRY(slp::launch_pcg_reduce(a, 4, 0, st));
+    // the residual of the start is the first check: r.r from the start kernel
+    // is not formed, so check after the first block of iterations
+    const int32_t every = 16;
+    double bb = -1.0;
+    for (it = 0; it < max_iter;) {
+      const int32_t n = std::min(every, max_iter - it);
+      for (int32_t k = 0; k < n; ++k, ++it) FEM_TRY(slp::launch_pcg_iteration(a, it, st));
+      FEM_TRY(slp::launch_pcg_reduce(a, 3, it, st));
+      FEM_TRY(hipMemcpyAsync(F->h_pin, F->hist, 8, hipMemcpyDeviceToHost, st));
+      FEM_TRY(hipMemcpyAsync(F->h_pin + 1, F->hist + it, 8, hipMemcpyDeviceToHost, st));
+      FEM_TRY(hipStreamSynchronize(st));
+      bb = F->h_pin[0];
+      const double rr = F->h_pin[1];
+      rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+      if (!std::isfinite(rel)) return fail(SLP_EDEVICE, "conjugate gradients broke down (residual %g)", rel);
+      if (rel <= tol) break;
+    }
+  }
+  FEM_TRY(slp::launch_fem_scatter(F->x, F->node_free, phi1, F->n_nodes, st));
+  if (iters) *iters = it;
+  if (rel_res) *rel_res = rel;
+  if (rel > tol) return fail(SLP_EINVAL, "no convergence in %d iterations (relative residual %g > %g)",
+                             max_iter, rel, tol);
+  return SLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int slp_fem_setup(slp_fem **out, const double *nodes, int64_t n_nodes, const int32_t *tets,
+                  int64_t n_tets, void *stream) {
+  return fem_setup_impl(out, nodes, n_nodes, tets, n_tets, static_cast<hipStream_t>(stream));
+}
+
+int slp_fem_info(const slp_fem *F, int64_t *n_free, int64_t *n_boundary_tris, int64_t *nnz,
+                 int64_t *device_bytes) {
+  if (!F) return fail(SLP_EINVAL, "NULL context");
+  if (n_free) *n_free = F->n_free;
+  if (n_boundary_tris) *n_boundary_tris = F->n_btris;
+  if (nnz) *nnz = F->nnz;
+  if (device_bytes) *device_bytes = F->bytes;
+  return SLP_OK;
+}
+
+int slp_fem_boundary(const slp_fem *F, int32_t *tris, int64_t cap) {
+  if (!F || !tris) return fail(SLP_EINVAL, "NULL argument");
+  if (cap < F->n_btris) return fail(SLP_EINVAL, "tris holds %lld triangles, need %lld", (long long)cap,
+                                    (long long)F->n_btris);
+  std::copy(F->h_btris.begin(), F->h_btris.end(), tris);
+  return SLP_OK;
+}
+
+int slp_fem_solve_phi1(slp_fem *F, const double *m_nodes, double *phi1, double tol,
+                       int32_t max_iter, int32_t warm_start, int32_t *iters, double *rel_res,
+                       void *stream) {
+  return solve_impl(F, m_nodes, phi1, tol, max_iter, warm_start, iters, rel_res,
+                    static_cast<hipStream_t>(stream));
+}
+
+int slp_fem_dphi1_dn(slp_fem *F, const double *phi1, double *dphi1_dn, void *stream) {
+  if (!F || !phi1 || !dphi1_dn) return fail(SLP_EINVAL, "NULL argument");
+  FEM_TRY(slp::launch_fem_dn(F->owner, F->nrm, F->tets, F->grad, phi1, dphi1_dn, F->n_btris,
+                             static_cast<hipStream_t>(stream)));
+  return SLP_OK;
+}
+
+int slp_scalar_potential(slp_fem *F, slp_geom *g, const double *m_nodes, double *phi, double tol,
+                         int32_t max_iter, int32_t warm_start, int32_t *iters, void *stream) {
+  if (!F || !g || !m_nodes || !phi) return fail(SLP_EINVAL, "NULL argument");
+  slp_geom_info gi;
+  int rc = slp_geom_get_info(g, &gi);
+  if (rc) return rc;
+  if (gi.n_nodes != F->n_nodes || gi.n_tris != F->n_btris || gi.n_targets != F->n_nodes)
+    return fail(SLP_EINVAL, "the geometry must hold the mesh's nodes (also as targets) and its "
+                            "boundary triangles from slp_fem_boundary");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  rc = solve_impl(F, m_nodes, F->phi1, tol, max_iter, warm_start, iters, nullptr, st);
+  if (rc) return rc;
+  FEM_TRY(slp::launch_fem_dn(F->owner, F->nrm, F->tets, F->grad, F->phi1, F->dn, F->n_btris, st));
+  rc = slp_set_density_from_m(g, m_nodes, F->dn, stream);
+  if (rc) return rc;
+  rc = slp_eval_single_layer(g, phi, stream);
+  if (rc) return rc;
+  FEM_TRY(slp::launch_fem_add(phi, F->phi1, F->n_nodes, st));
+  return SLP_OK;
+}
+
+int slp_fem_destroy(slp_fem *F) {
+  if (!F) return SLP_OK;
+  (void)hipDeviceSynchronize();
+  delete F;
+  return SLP_OK;
+}
+
+}  // extern "C"

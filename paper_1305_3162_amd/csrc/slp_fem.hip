@@ -1,0 +1,216 @@
+// Device code of the Dirichlet problem for phi_1 (Sec. 2.1, eq. poisson): the
+// load vector, Jacobi-preconditioned conjugate gradients on the free-node
+// system, the normal derivative on the boundary triangles, and the final sum
+// phi = phi_1 + phi_2 of Alg. 1. FP64 throughout.
+#include "slp_fem.hpp"
+
+namespace slp {
+
+namespace {
+
+// Sum over the workgroup; every thread receives the total. Fixed order.
+__device__ double block_sum(double v) {
+  __shared__ double ws[kFemThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();                       // ws may still be read by a previous call
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kFemThreads / 64; ++i) t += ws[i];
+  return t;
+}
+
+// Sum of the nblk per-workgroup partial sums of one dot product.
+__device__ double sum_parts(const double *__restrict__ part, int nblk) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kFemThreads) v += part[i];
+  return block_sum(v);
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_fem_load(FemLoadArgs a) {
+  const int64_t f = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  if (f >= a.nf) return;
+  double acc = 0.0;
+  for (int32_t e = a.inc_ptr[f]; e < a.inc_ptr[f + 1]; ++e) {
+    const int64_t t = a.inc[e] >> 2;
+    const int la = a.inc[e] & 3;
+    double mb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t nd = a.tets[4 * t + v];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) mb[q] += a.m[3 * nd + q];
+    }
+    const double *g = a.grad + 12 * t + 3 * la;
+    acc += a.vol[t] * 0.25 * (mb[0] * g[0] + mb[1] * g[1] + mb[2] * g[2]);
+  }
+  a.b[f] = acc;
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_pcg_start(PcgArgs a,
+                                                           const int32_t *__restrict__ free_node) {
+  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  double rz = 0.0, bb = 0.0;
+  if (i < a.nf) {
+    double xi = 0.0, ri = a.b[i];
+    if (a.x0) {
+      xi = a.x0[free_node[i]];
+      for (int32_t e = a.rp[i]; e < a.rp[i + 1]; ++e) ri -= a.val[e] * a.x0[free_node[a.ci[e]]];
+    }
+    const double zi = a.dinv[i] * ri;
+    a.x[i] = xi;
+    a.r[i] = ri;
+    a.z[i] = zi;
+    a.p[i] = zi;
+    rz = ri * zi;
+    bb = a.b[i] * a.b[i];
+  }
+  rz = block_sum(rz);
+  bb = block_sum(bb);
+  if (threadIdx.x == 0) {
+    a.part[1 * a.nblk + blockIdx.x] = rz;
+    a.part[4 * a.nblk + blockIdx.x] = bb;
+  }
+}
+
+// q = S p, partial p.q.
+__global__ __launch_bounds__(kFemThreads) void k_pcg_spmv(PcgArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  double pq = 0.0;
+  if (i < a.nf) {
+    double s = 0.0;
+    for (int32_t e = a.rp[i]; e < a.rp[i + 1]; ++e) s += a.val[e] * a.p[a.ci[e]];
+    a.q[i] = s;
+    pq = a.p[i] * s;
+  }
+  pq = block_sum(pq);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = pq;
+}
+
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r.
+__global__ __launch_bounds__(kFemThreads) void k_pcg_update(PcgArgs a, int32_t it) {
+  const double pq = sum_parts(a.part, a.nblk);
+  const double rz = sum_parts(a.part + (1 + (it & 1)) * a.nblk, a.nblk);
+  const double alpha = pq != 0.0 ? rz / pq : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  double rzn = 0.0, rr = 0.0;
+  if (i < a.nf) {
+    a.x[i] += alpha * a.p[i];
+    const double ri = a.r[i] - alpha * a.q[i];
+    const double zi = a.dinv[i] * ri;
+    a.r[i] = ri;
+    a.z[i] = zi;
+    rzn = ri * zi;
+    rr = ri * ri;
+  }
+  rzn = block_sum(rzn);
+  rr = block_sum(rr);
+  if (threadIdx.x == 0) {
+    a.part[(1 + ((it + 1) & 1)) * a.nblk + blockIdx.x] = rzn;
+    a.part[3 * a.nblk + blockIdx.x] = rr;
+  }
+}
+
+// beta = r.z (new) / r.z (old); p = z + beta p.
+__global__ __launch_bounds__(kFemThreads) void k_pcg_dir(PcgArgs a, int32_t it) {
+  const double rzn = sum_parts(a.part + (1 + ((it + 1) & 1)) * a.nblk, a.nblk);
+  const double rzo = sum_parts(a.part + (1 + (it & 1)) * a.nblk, a.nblk);
+  const double beta = rzo != 0.0 ? rzn / rzo : 0.0;
+  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  if (i < a.nf) a.p[i] = a.z[i] + beta * a.p[i];
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_pcg_reduce(PcgArgs a, int32_t which,
+                                                            int32_t slot) {
+  const double s = sum_parts(a.part + which * a.nblk, a.nblk);
+  if (threadIdx.x == 0) a.hist[slot] = s;
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_fem_scatter(const double *__restrict__ x,
+                                                             const int32_t *__restrict__ node_free,
+                                                             double *__restrict__ phi1, int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  if (k >= n) return;
+  const int32_t f = node_free[k];
+  phi1[k] = f >= 0 ? x[f] : 0.0;
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_fem_dn(const int32_t *__restrict__ owner,
+                                                        const double *__restrict__ nrm,
+                                                        const int32_t *__restrict__ tets,
+                                                        const double *__restrict__ grad,
+                                                        const double *__restrict__ phi1,
+                                                        double *__restrict__ dn, int64_t mb) {
+  const int64_t j = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  if (j >= mb) return;
+  const int64_t t = owner[j];
+  double g[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double u = phi1[tets[4 * t + v]];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) g[q] += u * grad[12 * t + 3 * v + q];
+  }
+  dn[j] = g[0] * nrm[3 * j] + g[1] * nrm[3 * j + 1] + g[2] * nrm[3 * j + 2];
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_fem_add(double *__restrict__ phi,
+                                                         const double *__restrict__ phi1,
+                                                         int64_t n) {
+  const int64_t k = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  if (k < n) phi[k] += phi1[k];
+}
+
+unsigned blocks(int64_t n) { return (unsigned)((n + kFemThreads - 1) / kFemThreads); }
+
+}  // namespace
+
+hipError_t launch_fem_load(const FemLoadArgs &a, hipStream_t s) {
+  if (a.nf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fem_load, dim3(blocks(a.nf)), dim3(kFemThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_start(const PcgArgs &a, const int32_t *free_node, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_start, dim3(a.nblk), dim3(kFemThreads), 0, s, a, free_node);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_iteration(const PcgArgs &a, int32_t it, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_spmv, dim3(a.nblk), dim3(kFemThreads), 0, s, a);
+  hipLaunchKernelGGL(k_pcg_update, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
+  hipLaunchKernelGGL(k_pcg_dir, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_reduce(const PcgArgs &a, int32_t which, int32_t slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_reduce, dim3(1), dim3(kFemThreads), 0, s, a, which, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_fem_scatter(const double *x, const int32_t *node_free, double *phi1,
+                              int64_t n_nodes, hipStream_t s) {
+  if (n_nodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fem_scatter, dim3(blocks(n_nodes)), dim3(kFemThreads), 0, s, x, node_free,
+                     phi1, n_nodes);
+  return hipGetLastError();
+}
+
+hipError_t launch_fem_dn(const int32_t *owner, const double *nrm, const int32_t *tets,
+                         const double *grad, const double *phi1, double *dn, int64_t mb,
+                         hipStream_t s) {
+  if (mb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fem_dn, dim3(blocks(mb)), dim3(kFemThreads), 0, s, owner, nrm, tets, grad,
+                     phi1, dn, mb);
+  return hipGetLastError();
+}
+
+hipError_t launch_fem_add(double *phi, const double *phi1, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fem_add, dim3(blocks(n)), dim3(kFemThreads), 0, s, phi, phi1, n);
+  return hipGetLastError();
+}
+
+}  // namespace slp

@@ -1,0 +1,119 @@
+"""The Dirichlet problem for phi_1 (Sec. 2.1) and the complete scalar potential
+of Alg. 1 on the device: boundary triangles, phi_1 and d phi_1/dn against the
+oracle's direct solve, phi = phi_1 + phi_2 against the oracle's Alg. 1 and the
+closed forms, warm starts, and the full-size cube mesh (residual of the
+oracle's own system, manufactured solution)."""
+import numpy as np
+import pytest
+
+import paper_1305_3162_amd as slp
+from oracle import direct, fem, nearfield as nfo
+from synth import ball_tets, cube_tets
+from synth.workloads import expsum_interval
+from slp_testlib import log
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _manufactured(nodes):
+    x, y, z = nodes.T
+    ax, ay, az = 0.25 - x * x, 0.25 - y * y, 0.25 - z * z
+    return ax * ay * az, np.stack([-2 * x * ay * az, -2 * y * ax * az, -2 * z * ax * ay], axis=1)
+
+
+def _cases():
+    n8, t8 = cube_tets(8)
+    b8, bt8 = ball_tets(8, 1.0)
+    r = np.linalg.norm(b8, axis=1)
+    return {"cube8_manufactured": (n8, t8, _manufactured(n8)[1]),
+            "ball8_radial": (b8, bt8, b8 / np.where(r > 0, r, 1.0)[:, None]),
+            "ball8_uniform": (b8, bt8, np.tile([0.0, 0.0, 1.0], (b8.shape[0], 1)))}
+
+
+@pytest.mark.parametrize("name", ["cube8_manufactured", "ball8_radial"])
+def test_phi1_and_normal_derivative_against_oracle(name):
+    nodes, tets, m = _cases()[name]
+    log(f"case fem {name} ({nodes.shape[0]} nodes, {tets.shape[0]} tets)")
+    F = slp.Fem(nodes, tets)
+    tris_o, own = fem.boundary_faces(nodes, tets)
+    assert np.array_equal(F.boundary, tris_o)
+    md = torch.as_tensor(m).cuda()
+    phi1 = torch.zeros(nodes.shape[0], dtype=torch.float64, device="cuda")
+    it, rr = F.solve_phi1(md, phi1, tol=1e-12)
+    dn = torch.zeros(tris_o.shape[0], dtype=torch.float64, device="cuda")
+    F.dphi1_dn(phi1, dn)
+    torch.cuda.synchronize()
+    ref = fem.solve_phi1(nodes, tets, m)
+    ref_dn = fem.dphi1_dn(nodes, tets, ref, tris_o, own)
+    e = np.abs(phi1.cpu().numpy() - ref).max() / np.abs(ref).max()
+    ed = np.abs(dn.cpu().numpy() - ref_dn).max() / np.abs(ref_dn).max()
+    log(f"  {it} iterations, residual {rr:.2e}; phi1 {e:.2e}, dphi1/dn {ed:.2e}")
+    assert rr <= 1e-12 and e <= 1e-9 and ed <= 1e-8
+    # warm start from the solution: converged at the first check
+    it2, rr2 = F.solve_phi1(md, phi1, tol=1e-10, warm_start=True)
+    assert it2 <= 16 and rr2 <= 1e-10
+    F.close()
+
+
+@pytest.mark.parametrize("name", ["cube8_manufactured", "ball8_radial", "ball8_uniform"])
+def test_scalar_potential_against_oracle(name):
+    nodes, tets, m = _cases()[name]
+    log(f"case scalar potential {name}")
+    lo, hi = expsum_interval(nodes)
+    grid = (64, 64, 64)
+    F = slp.Fem(nodes, tets)
+    w, g = slp.expsum_sinc(0.2, lo, hi, 1e-12)
+    G = slp.Geometry(nodes, F.boundary, grid, 8, w, g, 2, slp.FP64)
+    assert G.info["n_targets"] == nodes.shape[0]
+    tris_o, _ = fem.boundary_faces(nodes, tets)
+    prob = direct.prepare(nodes, tris_o, np.zeros(3 * tris_o.shape[0]), grid, es_r_lo=lo, es_r_hi=hi)
+    eps = nfo.near_radius(prob, 1e-3, hi)
+    G.setup_near_field(eps)
+    phi = torch.zeros(nodes.shape[0], dtype=torch.float64, device="cuda")
+    it = slp.scalar_potential(F.handle, G.handle, torch.as_tensor(m).cuda(), phi, tol=1e-12)
+    torch.cuda.synchronize()
+    got = phi.cpu().numpy()
+    G.close()
+    F.close()
+    ref = fem.scalar_potential(nodes, tets, m, grid, eps, es_r_lo=lo, es_r_hi=hi)
+    e = np.abs(got - ref).max() / np.abs(ref).max()
+    log(f"  {it} CG iterations; max error vs oracle {e:.2e} (relative to max |phi|)")
+    assert e <= 1e-6
+    if name == "ball8_uniform":
+        assert np.abs(got - nodes[:, 2] / 3.0).max() < 5e-3
+    if name == "cube8_manufactured":
+        assert np.abs(got - _manufactured(nodes)[0]).max() < 6e-3
+
+
+def test_full_size_cube_mesh():
+    """cube_tets(64): 274,625 nodes, 1,572,864 tetrahedra, 250,047 free nodes.
+    The device solution solves the oracle's own system (residual of the
+    oracle's S and b) and matches the manufactured solution to its O(h^2)
+    discretisation error."""
+    nodes, tets = cube_tets(64)
+    phie, m = _manufactured(nodes)
+    log("case fem full size cube64 tets")
+    F = slp.Fem(nodes, tets)
+    log(f"  {F.info}")
+    phi1 = torch.zeros(nodes.shape[0], dtype=torch.float64, device="cuda")
+    it, rr = F.solve_phi1(torch.as_tensor(m).cuda(), phi1, tol=1e-10)
+    torch.cuda.synchronize()
+    x = phi1.cpu().numpy()
+    F.close()
+    S = fem.stiffness(nodes, tets)
+    b = fem.load(nodes, tets, m)
+    free = ~fem.boundary_nodes(tets, nodes)
+    res = (b - S @ x)[free]
+    rel = np.linalg.norm(res) / np.linalg.norm(b[free])
+    log(f"  {it} iterations, device residual {rr:.2e}, oracle-system residual {rel:.2e}, "
+        f"max |phi1 - phi_e| {np.abs(x - phie).max():.2e}")
+    assert rr <= 1e-10 and rel <= 2e-10
+    assert np.all(x[~free] == 0.0)
+    assert np.abs(x - phie).max() < 2e-5
