@@ -63,6 +63,13 @@ def parse():
     ap.add_argument("--requests", type=int, default=1000)
     ap.add_argument("--near-tol", type=float, default=None,
                     help="add the near-field correction with eps from slp_near_radius(tol)")
+    ap.add_argument("--potential", action="store_true",
+                    help="Alg. 1 computation phase on the tetrahedral mesh of the 64-cell cube: "
+                         "phi_1 (P1 FEM, conjugate gradients), d phi_1/dn, the density, phi_2 "
+                         "at all 274,625 nodes with the near field (--near-tol, default 1e-3), "
+                         "phi = phi_1 + phi_2")
+    ap.add_argument("--cg-tol", type=float, default=1e-8,
+                    help="relative residual of the phi_1 solve (--potential)")
     ap.add_argument("--rho", type=float, default=0.8, help="offered load / capacity")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known "
@@ -310,8 +317,137 @@ def mix32(args):
     print(json.dumps(rec), flush=True)
 
 
+def potential(args):
+    """One step = Alg. 1's computation phase (slp_scalar_potential): phi_1 by
+    conjugate gradients from zero, d phi_1/dn, the element density, phi_2 at
+    every node of the tetrahedral mesh (smooth part + near field), the sum."""
+    import torch
+
+    import paper_1305_3162_amd as slp
+    from synth import cube_tets, RandomSmoothMagnetisation
+    from synth.workloads import expsum_interval
+
+    prec = slp.FP64 if args.precision == "fp64" else slp.FP32
+    m_win = args.m if args.m is not None else (8 if prec == slp.FP64 else 5)
+    near_tol = 1e-3 if args.near_tol is None else args.near_tol
+    nodes, tets = cube_tets(64)
+    mf = RandomSmoothMagnetisation(2, nodes.min(0), nodes.max(0))
+    m_nodes = mf(nodes)
+    lo, hi = expsum_interval(nodes)
+    w, g = slp.expsum_sinc(0.2, lo, hi, 1e-12)
+    stream = torch.cuda.current_stream()
+    t1 = time.perf_counter()
+    F = slp.Fem(nodes, tets, stream)
+    t_fem_setup = time.perf_counter() - t1
+    G = slp.Geometry(nodes, F.boundary, (128, 128, 128), m_win, w, g, 2, prec)
+    t1 = time.perf_counter()
+    eps = G.near_radius(near_tol) if near_tol > 0 else 0.0
+    if eps > 0:
+        G.setup_near_field(eps, stream)
+    t_near_setup = time.perf_counter() - t1
+    nf = G.near_field_info()
+    md = torch.as_tensor(m_nodes, device="cuda")
+    phi = torch.empty(nodes.shape[0], dtype=torch.float64, device="cuda")
+    iters = 0
+    for _ in range(args.warmup):
+        iters = slp.scalar_potential(F.handle, G.handle, md, phi, args.cg_tol, 20000, False, stream)
+    torch.cuda.synchronize()
+    slp.set_timing(G.handle, 1)
+    slp.stage_times(G.handle, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        iters = slp.scalar_potential(F.handle, G.handle, md, phi, args.cg_tol, 20000, False, stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms, cnt = slp.stage_times(G.handle, reset=True)
+    slp.set_timing(G.handle, False)
+    ms_per_step = wall * 1e3 / args.steps
+    avg = {k: v / max(cnt, 1) for k, v in stage_ms.items()}
+    phi2_ms = sum(avg.values())
+    n_src = 3 * F.boundary.shape[0]
+    pts = n_src + nodes.shape[0]
+    info = dict(G.info)
+    info["_n"] = [64, 64, 64]
+    info["_stored"], info["_packed"] = nf["stored"], nf["packed"]
+    esz = 8 if prec == slp.FP64 else 4
+    dom = max(avg, key=avg.get)
+    amount, unit, bound = algorithmic_units(dom, info, m_win, esz)
+    dur_s = max(avg[dom] * 1e-3, 1e-12)
+    if bound == "hbm":
+        achieved, peak, runit = amount / dur_s / 1e9, PEAK["hbm_GBps"], "GB/s"
+    else:
+        achieved = amount / dur_s / 1e12
+        peak = PEAK["f64_vector_TFLOPs"] if prec == slp.FP64 else PEAK["f32_vector_TFLOPs"]
+        runit = "TFLOP/s"
+    roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,
+                "frac": round(achieved / peak, 5), "traffic": None, "kernel": dom,
+                "avg_launch_us": round(avg[dom] * 1e3, 3)}
+    out = phi.cpu().numpy()
+    rel_err, cpu_baseline = None, None
+    if not args.no_oracle:
+        from oracle import direct, fem, geometry, nearfield as nfo
+        t1 = time.perf_counter()
+        phi1 = fem.solve_phi1(nodes, tets, m_nodes, "cg")
+        tris, owner = fem.boundary_faces(nodes, tets)
+        dn = fem.dphi1_dn(nodes, tets, phi1, tris, owner)
+        dens = geometry.density_p1(nodes, tris, m_nodes, dn)
+        prob = direct.prepare(nodes, tris, dens, (128, 128, 128), 2, 0.2, lo, hi, 1e-12, 37.0)
+        far = direct.phi_ndft(prob)
+        t_bulk = time.perf_counter() - t1
+        rows = np.random.default_rng(7).choice(nodes.shape[0], 8, replace=False)
+        t1 = time.perf_counter()
+        near = np.zeros(rows.size)
+        if eps > 0:
+            rp_o, cols_o, _ = nfo.near_pairs(nodes, tris, nodes[rows], eps)
+            vals_o = nfo.near_values(prob, nodes, tris, nodes[rows], rp_o, cols_o)
+            gbar = nfo.element_mean_density(prob, tris.shape[0])
+            nz = np.diff(rp_o) > 0
+            near[nz] = np.add.reduceat(vals_o * gbar[cols_o], rp_o[:-1][nz]) / nfo.FOUR_PI
+        t_row = (time.perf_counter() - t1) / rows.size
+        ref = phi1[rows] + far[rows] + near
+        rel_err = float(np.abs(out[rows] - ref).max() / np.abs(phi1 + far).max())
+        if not args.no_cpu_baseline:
+            t_solve = t_bulk + t_row * nodes.shape[0]
+            cpu_baseline = {"value": round(pts / t_solve, 2), "unit": "pts/s", "cores": os.cpu_count(),
+                            "kind": "oracle",
+                            "sample": f"oracle Alg. 1: phi_1 by preconditioned CG (scipy) on the whole "
+                                      f"mesh, the NDFT route of phi_2 at all {nodes.shape[0]} nodes "
+                                      f"({t_bulk:.1f} s together), and the near-field rows timed on 8 "
+                                      f"rows ({t_row:.3f} s per row) scaled to all rows"}
+    rec = {
+        "metric": "complete scalar potential, Alg. 1 computation phase (M+N) pts/s",
+        "value": round(pts / (ms_per_step * 1e-3), 1), "unit": "pts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if prec == slp.FP64 else "f32", "data": "synthetic",
+        "config": {"workload": f"tetrahedral mesh of the unit cube, 64 cells per edge: "
+                               f"{nodes.shape[0]} nodes, {tets.shape[0]} tetrahedra, "
+                               f"{F.info['n_free']} free nodes, {F.boundary.shape[0]} boundary "
+                               f"triangles ({n_src} sources), seeded smooth magnetisation (seed 2), "
+                               f"grid 128^3, Gaussian m={m_win}",
+                   "cg_tol": args.cg_tol, "cg_iterations": iters,
+                   "near_field": {"tol": near_tol, "eps": round(eps, 6), "pairs": nf["nnz"],
+                                  "stored": nf["stored"], "setup_s": round(t_near_setup, 2)},
+                   "fem_setup_s": round(t_fem_setup, 2), "points": pts},
+        "phi2_ms": round(phi2_ms, 4), "phi1_and_rest_ms": round(ms_per_step - phi2_ms, 4),
+        "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
+        "rel_err_vs_oracle": rel_err,
+        "err_kind": "max |error| over 8 seeded nodes / max |phi| (oracle phi_1 by CG to 1e-13)",
+        "roofline": roofline, "cpu_baseline": cpu_baseline,
+    }
+    print(json.dumps(rec), flush=True)
+    G.close()
+    F.close()
+
+
 def main():
     args = parse()
+    if args.potential:
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        potential(args)
+        return
     if args.mix32:
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)

@@ -86,23 +86,33 @@ def boundary_nodes(tets, nodes):
     return flag
 
 
-def solve_dirichlet(S, b, bnd, values):
+def solve_dirichlet(S, b, bnd, values, method="direct"):
     """S(fn, fn) x(fn) = b(fn) - (S x_bn)(fn) (eq. poisson), x = values on the
-    boundary nodes; sparse direct solve."""
+    boundary nodes. method "direct": sparse LU; "cg": conjugate gradients with
+    the diagonal preconditioner to a relative residual of 1e-13 (for meshes
+    where the factorisation is too slow)."""
     x = np.zeros(S.shape[0])
     x[bnd] = values
     fn = np.nonzero(~bnd)[0]
+    A = S[fn][:, fn].tocsr()
     rhs = b[fn] - S[fn][:, np.nonzero(bnd)[0]] @ x[bnd]
-    x[fn] = spla.spsolve(S[fn][:, fn].tocsc(), rhs)
+    if method == "direct":
+        x[fn] = spla.spsolve(A.tocsc(), rhs)
+    else:
+        Minv = sp.diags(1.0 / A.diagonal())
+        sol, info = spla.cg(A, rhs, rtol=1e-13, atol=0.0, maxiter=100000, M=Minv)
+        if info != 0:
+            raise RuntimeError(f"conjugate gradients did not converge (info {info})")
+        x[fn] = sol
     return x
 
 
-def solve_phi1(nodes, tets, m_nodes):
+def solve_phi1(nodes, tets, m_nodes, method="direct"):
     """phi_1 at every node (zero on the boundary), eq. GR1 by eq. poisson."""
     S = stiffness(nodes, tets)
     b = load(nodes, tets, m_nodes)
     bnd = boundary_nodes(tets, nodes)
-    return solve_dirichlet(S, b, bnd, 0.0)
+    return solve_dirichlet(S, b, bnd, 0.0, method)
 
 
 def dphi1_dn(nodes, tets, phi1, tris, owner):

@@ -49,11 +49,13 @@ struct slp_fem {
   int32_t *inc_ptr = nullptr, *inc = nullptr;
   int32_t *free_node = nullptr;   // [Nf] node of free index f
   int32_t *node_free = nullptr;   // [N] free index or -1
-  int32_t *rp = nullptr, *ci = nullptr;
+  int32_t *sptr = nullptr, *ci = nullptr;   // S_ff in 64-row slices
   double *val = nullptr, *dinv = nullptr;
   int32_t *owner = nullptr;       // [Mb]
   double *nrm = nullptr;          // [Mb][3]
-  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *b = nullptr, *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
+  double *p[2] = {nullptr, nullptr};
+  double *vm = nullptr;           // [T][3] work of the load vector
   double *part = nullptr, *hist = nullptr;
   int32_t hist_cap = 0;
   double *phi1 = nullptr, *dn = nullptr;   // for slp_scalar_potential
@@ -276,6 +278,35 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
     for (int64_t f = 0; f < Nf; ++f)
       for (int32_t e = rp[f]; e < rp[f + 1]; ++e)
         if (ci[e] == f) dinv[f] = 1.0 / val[e];
+    // sliced layout: 64 rows per slice, entries column by column
+    const int64_t ns = (Nf + 63) / 64;
+    std::vector<int32_t> sptr(ns + 1, 0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      int32_t w = 0;
+      for (int64_t f = 64 * sl; f < std::min<int64_t>(Nf, 64 * sl + 64); ++f) w = std::max(w, rp[f + 1] - rp[f]);
+      if ((int64_t)sptr[sl] + 64 * (int64_t)w > INT32_MAX)
+        return fail(SLP_EINVAL, "stiffness matrix too large for 32-bit offsets");
+      sptr[sl + 1] = sptr[sl] + 64 * w;
+    }
+    std::vector<int32_t> sci(sptr[ns]);
+    std::vector<double> sval(sptr[ns], 0.0);
+    for (int64_t sl = 0; sl < ns; ++sl) {
+      const int32_t w = (sptr[sl + 1] - sptr[sl]) / 64;
+      for (int64_t l = 0; l < 64; ++l) {
+        const int64_t f = std::min<int64_t>(64 * sl + l, Nf - 1);
+        const bool real = 64 * sl + l < Nf;
+        for (int32_t k = 0; k < w; ++k) {
+          const int64_t e = sptr[sl] + 64 * (int64_t)k + l;
+          const int32_t src = rp[f] + k;
+          if (real && src < rp[f + 1]) {
+            sci[e] = ci[src];
+            sval[e] = val[src];
+          } else {
+            sci[e] = (int32_t)f;
+          }
+        }
+      }
+    }
 
     F->n_free = Nf;
     F->n_btris = Mb;
@@ -289,12 +320,13 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
         {(void **)&F->tets, (size_t)4 * T * 4}, {(void **)&F->vol, (size_t)T * 8},
         {(void **)&F->grad, (size_t)12 * T * 8}, {(void **)&F->inc_ptr, (size_t)(Nf + 1) * 4},
         {(void **)&F->inc, inc.size() * 4}, {(void **)&F->free_node, (size_t)std::max<int64_t>(Nf, 1) * 4},
-        {(void **)&F->node_free, (size_t)N * 4}, {(void **)&F->rp, (size_t)(Nf + 1) * 4},
-        {(void **)&F->ci, (size_t)nnz * 4}, {(void **)&F->val, (size_t)nnz * 8},
+        {(void **)&F->node_free, (size_t)N * 4}, {(void **)&F->sptr, sptr.size() * 4},
+        {(void **)&F->ci, sci.size() * 4}, {(void **)&F->val, sval.size() * 8},
         {(void **)&F->dinv, (size_t)Nf * 8}, {(void **)&F->owner, (size_t)Mb * 4},
         {(void **)&F->nrm, (size_t)3 * Mb * 8}, {(void **)&F->b, (size_t)Nf * 8},
         {(void **)&F->x, (size_t)Nf * 8}, {(void **)&F->r, (size_t)Nf * 8},
-        {(void **)&F->z, (size_t)Nf * 8}, {(void **)&F->p, (size_t)Nf * 8},
+        {(void **)&F->z, (size_t)Nf * 8}, {(void **)&F->p[0], (size_t)Nf * 8},
+        {(void **)&F->p[1], (size_t)Nf * 8}, {(void **)&F->vm, (size_t)3 * T * 8},
         {(void **)&F->q, (size_t)Nf * 8}, {(void **)&F->part, (size_t)5 * F->nblk * 8},
         {(void **)&F->phi1, (size_t)N * 8}, {(void **)&F->dn, (size_t)Mb * 8},
     };
@@ -309,10 +341,10 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
     FEM_TRY(hipMemcpyAsync(F->inc, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, st));
     if (Nf > 0) FEM_TRY(hipMemcpyAsync(F->free_node, free_node.data(), (size_t)Nf * 4, hipMemcpyHostToDevice, st));
     FEM_TRY(hipMemcpyAsync(F->node_free, node_free.data(), (size_t)N * 4, hipMemcpyHostToDevice, st));
-    FEM_TRY(hipMemcpyAsync(F->rp, rp.data(), (size_t)(Nf + 1) * 4, hipMemcpyHostToDevice, st));
-    if (nnz > 0) {
-      FEM_TRY(hipMemcpyAsync(F->ci, ci.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, st));
-      FEM_TRY(hipMemcpyAsync(F->val, val.data(), (size_t)nnz * 8, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(F->sptr, sptr.data(), sptr.size() * 4, hipMemcpyHostToDevice, st));
+    if (!sci.empty()) {
+      FEM_TRY(hipMemcpyAsync(F->ci, sci.data(), sci.size() * 4, hipMemcpyHostToDevice, st));
+      FEM_TRY(hipMemcpyAsync(F->val, sval.data(), sval.size() * 8, hipMemcpyHostToDevice, st));
       FEM_TRY(hipMemcpyAsync(F->dinv, dinv.data(), (size_t)Nf * 8, hipMemcpyHostToDevice, st));
     }
     FEM_TRY(hipMemcpyAsync(F->owner, owner.data(), (size_t)Mb * 4, hipMemcpyHostToDevice, st));
@@ -328,7 +360,7 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
 
 slp::PcgArgs pcg_args(slp_fem *F, const double *x0) {
   slp::PcgArgs a{};
-  a.rp = F->rp;
+  a.sptr = F->sptr;
   a.ci = F->ci;
   a.val = F->val;
   a.dinv = F->dinv;
@@ -336,7 +368,8 @@ slp::PcgArgs pcg_args(slp_fem *F, const double *x0) {
   a.x = F->x;
   a.r = F->r;
   a.z = F->z;
-  a.p = F->p;
+  a.p[0] = F->p[0];
+  a.p[1] = F->p[1];
   a.q = F->q;
   a.part = F->part;
   a.hist = F->hist;
@@ -370,8 +403,10 @@ int solve_impl(slp_fem *F, const double *m, double *phi1, double tol, int32_t ma
     la.vol = F->vol;
     la.grad = F->grad;
     la.m = m;
+    la.vm = F->vm;
     la.b = F->b;
     la.nf = F->n_free;
+    la.nt = F->n_tets;
     FEM_TRY(slp::launch_fem_load(la, st));
     const slp::PcgArgs a = pcg_args(F, warm ? phi1 : nullptr);
     FEM_TRY(slp::launch_pcg_start(a, F->free_node, st));

@@ -29,6 +29,22 @@ __device__ double sum_parts(const double *__restrict__ part, int nblk) {
   return block_sum(v);
 }
 
+// |T| mbar_T for every tetrahedron.
+__global__ __launch_bounds__(kFemThreads) void k_fem_tet_m(FemLoadArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  if (t >= a.nt) return;
+  double mb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t nd = a.tets[4 * t + v];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) mb[q] += a.m[3 * nd + q];
+  }
+  const double f = a.vol[t] * 0.25;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) a.vm[3 * t + q] = f * mb[q];
+}
+
 __global__ __launch_bounds__(kFemThreads) void k_fem_load(FemLoadArgs a) {
   const int64_t f = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
   if (f >= a.nf) return;
@@ -36,15 +52,9 @@ __global__ __launch_bounds__(kFemThreads) void k_fem_load(FemLoadArgs a) {
   for (int32_t e = a.inc_ptr[f]; e < a.inc_ptr[f + 1]; ++e) {
     const int64_t t = a.inc[e] >> 2;
     const int la = a.inc[e] & 3;
-    double mb[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t nd = a.tets[4 * t + v];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) mb[q] += a.m[3 * nd + q];
-    }
     const double *g = a.grad + 12 * t + 3 * la;
-    acc += a.vol[t] * 0.25 * (mb[0] * g[0] + mb[1] * g[1] + mb[2] * g[2]);
+    const double *vm = a.vm + 3 * t;
+    acc += vm[0] * g[0] + vm[1] * g[1] + vm[2] * g[2];
   }
   a.b[f] = acc;
 }
@@ -57,13 +67,17 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_start(PcgArgs a,
     double xi = 0.0, ri = a.b[i];
     if (a.x0) {
       xi = a.x0[free_node[i]];
-      for (int32_t e = a.rp[i]; e < a.rp[i + 1]; ++e) ri -= a.val[e] * a.x0[free_node[a.ci[e]]];
+      const int64_t sl = i >> 6;
+      const int32_t w = (a.sptr[sl + 1] - a.sptr[sl]) >> 6;
+      for (int32_t k = 0; k < w; ++k) {
+        const int64_t e = a.sptr[sl] + 64 * k + (i & 63);
+        ri -= a.val[e] * a.x0[free_node[a.ci[e]]];
+      }
     }
     const double zi = a.dinv[i] * ri;
     a.x[i] = xi;
     a.r[i] = ri;
     a.z[i] = zi;
-    a.p[i] = zi;
     rz = ri * zi;
     bb = a.b[i] * a.b[i];
   }
@@ -75,15 +89,34 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_start(PcgArgs a,
   }
 }
 
-// q = S p, partial p.q.
-__global__ __launch_bounds__(kFemThreads) void k_pcg_spmv(PcgArgs a) {
+// p = z + beta p_old (formed on the fly for every neighbour, stored for the
+// own row), q = S p, partial p.q. One thread per row: a wave is one slice, so
+// the column and value loads of entry k are contiguous across the wave.
+__global__ __launch_bounds__(kFemThreads) void k_pcg_spmv(PcgArgs a, int32_t it) {
+  double beta = 0.0;
+  if (it > 0) {
+    const double rzn = sum_parts(a.part + (1 + (it & 1)) * a.nblk, a.nblk);
+    const double rzo = sum_parts(a.part + (1 + ((it + 1) & 1)) * a.nblk, a.nblk);
+    beta = rzo != 0.0 ? rzn / rzo : 0.0;
+  }
+  const double *__restrict__ po = a.p[(it + 1) & 1];
+  double *__restrict__ pn = a.p[it & 1];
   const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
   double pq = 0.0;
   if (i < a.nf) {
+    const int64_t sl = i >> 6;
+    const int64_t base = a.sptr[sl] + (i & 63);
+    const int32_t w = (a.sptr[sl + 1] - a.sptr[sl]) >> 6;
     double s = 0.0;
-    for (int32_t e = a.rp[i]; e < a.rp[i + 1]; ++e) s += a.val[e] * a.p[a.ci[e]];
+    for (int32_t k = 0; k < w; ++k) {
+      const int32_t j = a.ci[base + 64 * k];
+      const double pj = it > 0 ? a.z[j] + beta * po[j] : a.z[j];
+      s += a.val[base + 64 * k] * pj;
+    }
+    const double pr = it > 0 ? a.z[i] + beta * po[i] : a.z[i];
+    pn[i] = pr;
     a.q[i] = s;
-    pq = a.p[i] * s;
+    pq = pr * s;
   }
   pq = block_sum(pq);
   if (threadIdx.x == 0) a.part[blockIdx.x] = pq;
@@ -94,10 +127,11 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_update(PcgArgs a, int32_t i
   const double pq = sum_parts(a.part, a.nblk);
   const double rz = sum_parts(a.part + (1 + (it & 1)) * a.nblk, a.nblk);
   const double alpha = pq != 0.0 ? rz / pq : 0.0;
+  const double *__restrict__ p = a.p[it & 1];
   const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
   double rzn = 0.0, rr = 0.0;
   if (i < a.nf) {
-    a.x[i] += alpha * a.p[i];
+    a.x[i] += alpha * p[i];
     const double ri = a.r[i] - alpha * a.q[i];
     const double zi = a.dinv[i] * ri;
     a.r[i] = ri;
@@ -111,15 +145,6 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_update(PcgArgs a, int32_t i
     a.part[(1 + ((it + 1) & 1)) * a.nblk + blockIdx.x] = rzn;
     a.part[3 * a.nblk + blockIdx.x] = rr;
   }
-}
-
-// beta = r.z (new) / r.z (old); p = z + beta p.
-__global__ __launch_bounds__(kFemThreads) void k_pcg_dir(PcgArgs a, int32_t it) {
-  const double rzn = sum_parts(a.part + (1 + ((it + 1) & 1)) * a.nblk, a.nblk);
-  const double rzo = sum_parts(a.part + (1 + (it & 1)) * a.nblk, a.nblk);
-  const double beta = rzo != 0.0 ? rzn / rzo : 0.0;
-  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
-  if (i < a.nf) a.p[i] = a.z[i] + beta * a.p[i];
 }
 
 __global__ __launch_bounds__(kFemThreads) void k_pcg_reduce(PcgArgs a, int32_t which,
@@ -169,6 +194,7 @@ unsigned blocks(int64_t n) { return (unsigned)((n + kFemThreads - 1) / kFemThrea
 
 hipError_t launch_fem_load(const FemLoadArgs &a, hipStream_t s) {
   if (a.nf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fem_tet_m, dim3(blocks(a.nt)), dim3(kFemThreads), 0, s, a);
   hipLaunchKernelGGL(k_fem_load, dim3(blocks(a.nf)), dim3(kFemThreads), 0, s, a);
   return hipGetLastError();
 }
@@ -179,9 +205,8 @@ hipError_t launch_pcg_start(const PcgArgs &a, const int32_t *free_node, hipStrea
 }
 
 hipError_t launch_pcg_iteration(const PcgArgs &a, int32_t it, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_spmv, dim3(a.nblk), dim3(kFemThreads), 0, s, a);
+  hipLaunchKernelGGL(k_pcg_spmv, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
   hipLaunchKernelGGL(k_pcg_update, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
-  hipLaunchKernelGGL(k_pcg_dir, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
   return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@ namespace slp {
 constexpr int kFemThreads = 256;
 
 // Load vector on the free nodes: b_f = sum over the tetrahedra T holding node
-// free_node[f] (local index a) of |T| mbar_T . grad lambda_a^T.
+// free_node[f] (local index a) of |T| mbar_T . grad lambda_a^T. The products
+// |T| mbar_T are formed once per tetrahedron first.
 struct FemLoadArgs {
   const int32_t *inc_ptr;   // [Nf + 1]
   const int32_t *inc;       // 4 T + a
@@ -19,19 +20,25 @@ struct FemLoadArgs {
   const double *vol;        // [T]
   const double *grad;       // [T][4][3]
   const double *m;          // [N][3] nodal magnetisation
+  double *vm;               // [T][3] work: |T| mbar_T
   double *b;                // [Nf]
-  int64_t nf;
+  int64_t nf, nt;
 };
 hipError_t launch_fem_load(const FemLoadArgs &a, hipStream_t s);
 
 // Preconditioned conjugate gradients (Jacobi) on S_ff x = b. Partial sums
 // of the dot products are written per workgroup; every consumer sums them.
+// S_ff is stored sliced: rows in slices of 64, slice s holding its entries
+// column by column (entry k of row 64 s + l at sptr[s] + 64 k + l), slice
+// width = its longest row; padding entries point at the row itself with value 0.
 struct PcgArgs {
-  const int32_t *rp, *ci;   // CSR of S_ff
+  const int32_t *sptr;      // [n_slices + 1]
+  const int32_t *ci;        // column (free index)
   const double *val;
   const double *dinv;       // 1 / diag(S_ff)
   const double *b;
-  double *x, *r, *z, *p, *q;
+  double *x, *r, *z, *q;
+  double *p[2];             // search directions, iteration it writes p[it & 1]
   double *part;             // [5][nblk]: p.q, r.z (two slots by parity), r.r, b.b
   double *hist;             // [max_iter + 1] r.r after each iteration (slot 0: b.b)
   const int32_t *node_free; // warm start: free index of each node or -1
@@ -39,12 +46,14 @@ struct PcgArgs {
   int64_t nf, n_nodes;
   int32_t nblk;
 };
-// x = x0 (or 0), r = b - S x, z = D^-1 r, p = z; partial r.z and b.b.
+// x = x0 (or 0), r = b - S x, z = D^-1 r; partial r.z and b.b.
 hipError_t launch_pcg_start(const PcgArgs &a, const int32_t *free_node, hipStream_t s);
-// One iteration (three kernels): q = S p with p.q; x, r, z updates with r.z
-// and r.r; p = z + beta p. `it` selects the parity slot of r.z.
+// One iteration, two kernels: (1) p = z + beta p (beta = 0 in iteration 0),
+// formed on the fly for the neighbours and stored for the own row, q = S p
+// (16 lanes per row) with p.q; (2) x, r, z updates with r.z and r.r. `it`
+// selects the parity slots of r.z and of p.
 hipError_t launch_pcg_iteration(const PcgArgs &a, int32_t it, hipStream_t s);
-// hist[slot] = sum of the partial sums `which` (2: r.r, 4: b.b); one workgroup.
+// hist[slot] = sum of the partial sums `which` (3: r.r, 4: b.b); one workgroup.
 hipError_t launch_pcg_reduce(const PcgArgs &a, int32_t which, int32_t slot, hipStream_t s);
 
 // phi_1 on every node: x at the free nodes, 0 on the boundary.

@@ -54,6 +54,15 @@ def test_linear_dirichlet_data_reproduced_exactly():
     assert np.abs(x - u).max() < 1e-12
 
 
+def test_iterative_solve_matches_direct():
+    nodes, tets = ball_tets(8)
+    r = np.linalg.norm(nodes, axis=1)
+    m = nodes / np.where(r > 0, r, 1.0)[:, None]
+    a = fem.solve_phi1(nodes, tets, m, "direct")
+    b = fem.solve_phi1(nodes, tets, m, "cg")
+    assert np.abs(a - b).max() < 1e-10 * np.abs(a).max()
+
+
 def test_uniform_magnetisation_gives_zero_phi1():
     nodes, tets = ball_tets(6)
     m = np.tile([0.2, -0.5, 1.0], (nodes.shape[0], 1))
