@@ -242,7 +242,8 @@ int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omeg
  * offset per entry (int32 indices if a chunk spans 65535 triangles or more).
  * Every later evaluation
  * of this context (single, batched, graph replay) adds phi_NF after the
- * interpolation; geometries built by a server carry no near field.
+ * interpolation. Geometries of a request server get theirs from
+ * slp_server_add_geometry_near.
  * eps <= 0 removes the near field. Synchronises `stream` and the device;
  * drops captured graphs.
  *   eps : physical distance, the paper's eps of Alg. 1 (Require line)
@@ -256,6 +257,14 @@ int slp_setup_near_field(slp_geom *g, double eps, void *stream);
  * (Sec. 3.3: the truncated sum is accurate on [eps, 1/2] only). EINVAL if
  * tol <= 0 or if r_max itself misses tol. Host only. */
 int slp_near_radius(const slp_geom *g, double tol, double *eps);
+
+/* Device bytes slp_setup_near_field(eps) would add for this mesh and these
+ * targets (NULL: the nodes) in this precision, computed on the host (index
+ * sets and storage layout included, so it costs what the setup's host part
+ * costs). 0 for eps <= 0 or an empty near field. Used for admission by memory. */
+int slp_near_field_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,
+                                int64_t n_tris, const double *targets, int64_t n_targets,
+                                double eps, int32_t precision, int64_t *bytes);
 
 /* eps, pairs (nnz), r_max, stored entries (pairs plus row padding) and whether
  * the columns are packed, of a context (any pointer may be NULL). */
@@ -370,6 +379,12 @@ int slp_server_create(slp_server **out, size_t device_budget_bytes, int32_t n_sl
 int slp_server_add_geometry(slp_server *s, const double *nodes, int64_t n_nodes,
                             const int32_t *tris, int64_t n_tris, const slp_params *p,
                             int64_t *geom_id);
+/* As slp_server_add_geometry, with the near-field correction within eps
+ * (physical units, eps <= 0: none) built whenever the geometry is set up; its
+ * memory (slp_near_field_device_bytes) counts towards the budget. */
+int slp_server_add_geometry_near(slp_server *s, const double *nodes, int64_t n_nodes,
+                                 const int32_t *tris, int64_t n_tris, const slp_params *p,
+                                 double eps, int64_t *geom_id);
 /* Queue one solve: dens device float64 [3 * n_tris], phi device float64 [n_nodes]
  * (caller owned; both must stay valid until the request is done).
  * *ticket identifies the request. */

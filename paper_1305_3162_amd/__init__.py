@@ -20,7 +20,7 @@ __all__ = [
     "server_poll", "server_wait", "server_get_stats", "server_destroy", "Server",
     "setup_near_field", "near_radius", "near_field_info", "debug_copy_near",
     "near_pattern_host", "triangle_potential_host", "near_radius_host",
-    "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
+    "near_field_device_bytes", "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
     "scalar_potential", "fem_destroy", "Fem",
 ]
 
@@ -129,6 +129,12 @@ def load_library():
         "slp_scalar_potential": [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _VP],
         "slp_fem_destroy": [_VP],
+        "slp_near_field_device_bytes": [_VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP,
+                                        ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64)],
+        "slp_server_add_geometry_near": [_VP, _VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                                         ctypes.POINTER(Params), ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -241,14 +247,33 @@ def server_create(device_budget_bytes, n_slots):
 
 
 def server_add_geometry(server, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                        eta2=37.0, window=WINDOW_GAUSS):
+                        eta2=37.0, window=WINDOW_GAUSS, near_eps=0.0):
+    """slp_server_add_geometry_near (near_eps <= 0: no near field)."""
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
                                               precision, eta2, window)
     gid = ctypes.c_int64(-1)
-    _check(load_library().slp_server_add_geometry(_VP(server), nodes.ctypes.data, nodes.shape[0],
-                                                  tris.ctypes.data, tris.shape[0],
-                                                  ctypes.byref(p), ctypes.byref(gid)))
+    _check(load_library().slp_server_add_geometry_near(_VP(server), nodes.ctypes.data,
+                                                       nodes.shape[0], tris.ctypes.data,
+                                                       tris.shape[0], ctypes.byref(p),
+                                                       float(near_eps), ctypes.byref(gid)))
     return gid.value
+
+
+def near_field_device_bytes(nodes, tris, eps, precision=FP64, targets=None):
+    """slp_near_field_device_bytes (host only)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    out = ctypes.c_int64(0)
+    if targets is None:
+        tp, nt = None, 0
+    else:
+        targets = np.ascontiguousarray(targets, dtype=np.float64)
+        tp, nt = targets.ctypes.data, targets.shape[0]
+    _check(load_library().slp_near_field_device_bytes(nodes.ctypes.data, nodes.shape[0],
+                                                      tris.ctypes.data, tris.shape[0], tp, nt,
+                                                      float(eps), int(precision),
+                                                      ctypes.byref(out)))
+    return out.value
 
 
 def server_submit(server, geom_id, dens, phi):
@@ -587,9 +612,9 @@ class Server:
         self.handle = server_create(device_budget_bytes, n_slots)
 
     def add_geometry(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                     eta2=37.0, window=WINDOW_GAUSS):
+                     eta2=37.0, window=WINDOW_GAUSS, near_eps=0.0):
         return server_add_geometry(self.handle, nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                   precision, eta2, window)
+                                   precision, eta2, window, near_eps)
 
     def submit(self, geom_id, dens, phi):
         return server_submit(self.handle, geom_id, dens, phi)

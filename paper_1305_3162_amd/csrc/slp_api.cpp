@@ -1385,6 +1385,80 @@ int slp_debug_copy(const slp_geom *G, int32_t which, void *dst, size_t dst_bytes
 // ------------------------------------------------------------ near field ---
 
 namespace {
+// Stored form of a near-field pattern: every row padded with column -1 to a
+// multiple of the group size, or of the interleaved chunk when rows average
+// 2048 pairs or more (padding then a few per cent); chunked columns packed as
+// chunk base + 16-bit offsets when every chunk spans fewer than 65535.
+struct NearLayout {
+  bool chunked = false, packed = false;
+  int64_t stored = 0;
+  std::vector<int64_t> prow, counts;
+  std::vector<int32_t> cols, bases;
+  std::vector<uint16_t> offs;
+};
+
+bool near_layout(const std::vector<int64_t> &rowptr, const std::vector<int32_t> &cols, int64_t P,
+                 NearLayout &L) {
+  try {
+    const int64_t nnz = rowptr[P];
+    L.chunked = nnz >= (int64_t)8 * slp::kNearChunk * P;
+    const int64_t grp = L.chunked ? slp::kNearChunk : slp::kNearGroup;
+    L.prow.assign(P + 1, 0);
+    L.counts.resize(P);
+    for (int64_t i = 0; i < P; ++i) {
+      L.counts[i] = rowptr[i + 1] - rowptr[i];
+      L.prow[i + 1] = L.prow[i] + (L.counts[i] + grp - 1) / grp * grp;
+    }
+    L.stored = L.prow[P];
+    L.cols.assign(L.stored, -1);
+    for (int64_t i = 0; i < P; ++i) {
+      const int64_t n = L.counts[i];
+      if (!L.chunked) {
+        std::copy(cols.begin() + rowptr[i], cols.begin() + rowptr[i + 1], L.cols.begin() + L.prow[i]);
+        continue;
+      }
+      // entry e = c * 256 + 64 k + l of the row goes to c * 256 + 4 l + k
+      for (int64_t e = 0; e < n; ++e) {
+        const int64_t c = e / slp::kNearChunk, r = e % slp::kNearChunk;
+        const int64_t k = r / 64, l = r % 64;
+        L.cols[L.prow[i] + c * slp::kNearChunk + 4 * l + k] = cols[rowptr[i] + e];
+      }
+    }
+    L.packed = L.chunked;
+    if (L.packed) {
+      const int64_t nch = L.stored / slp::kNearChunk;
+      L.bases.assign(nch, 0);
+      for (int64_t c = 0; c < nch && L.packed; ++c) {
+        int32_t lo = std::numeric_limits<int32_t>::max(), hi = -1;
+        for (int64_t e = c * slp::kNearChunk; e < (c + 1) * slp::kNearChunk; ++e)
+          if (L.cols[e] >= 0) { lo = std::min(lo, L.cols[e]); hi = std::max(hi, L.cols[e]); }
+        if (hi < 0) lo = hi = 0;
+        if ((int64_t)hi - lo >= 65535) L.packed = false;
+        L.bases[c] = lo;
+      }
+      if (L.packed) {
+        L.offs.assign(L.stored, 0);
+        for (int64_t e = 0; e < L.stored; ++e)
+          if (L.cols[e] >= 0) L.offs[e] = (uint16_t)(L.cols[e] - L.bases[e / slp::kNearChunk]);
+      } else {
+        std::vector<int32_t>().swap(L.bases);
+      }
+    }
+    return true;
+  } catch (const std::bad_alloc &) {
+    return false;
+  }
+}
+
+// Device bytes of a stored near field (every buffer at least the allocation
+// minimum, as the context allocates them).
+int64_t near_bytes(const NearLayout &L, int64_t P, int64_t M, size_t esz, int cap) {
+  auto a = [](int64_t b) { return std::max<int64_t>(b, (int64_t)slp_geom::kMinAlloc); };
+  int64_t b = a((P + 1) * 8) + a(L.stored * (int64_t)esz) + a(M * 8 * cap);
+  b += L.packed ? a((int64_t)L.bases.size() * 4) + a(L.stored * 2) : a(L.stored * 4);
+  return b;
+}
+
 int host_threads() {
   const unsigned hw = std::thread::hardware_concurrency();
   return (int)std::max(1u, std::min(16u, hw ? hw : 1u));
@@ -1432,67 +1506,17 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   G->nf_eps = eps;
   if (nnz == 0) return SLP_OK;
 
-  // every row padded with column -1 to a multiple of the group size, or of the
-  // interleaved chunk when rows are long (padding then below a few per cent)
   const int64_t P = G->n_tgt;
-  const bool chunked = nnz >= (int64_t)8 * slp::kNearChunk * P;
-  const int64_t grp = chunked ? slp::kNearChunk : slp::kNearGroup;
-  std::vector<int64_t> prow(P + 1, 0);
-  for (int64_t i = 0; i < P; ++i) {
-    const int64_t n = rowptr[i + 1] - rowptr[i];
-    prow[i + 1] = prow[i] + (n + grp - 1) / grp * grp;
-  }
-  const int64_t stored = prow[P];
-  if (stored != nnz || chunked) {
-    std::vector<int32_t> pc;
-    try {
-      pc.assign(stored, -1);
-    } catch (const std::bad_alloc &) {
-      G->nf_eps = 0.0;
-      return fail(SLP_ENOMEM, "host allocation for the padded near-field pattern failed");
-    }
-    for (int64_t i = 0; i < P; ++i) {
-      const int64_t n = rowptr[i + 1] - rowptr[i];
-      if (!chunked) {
-        std::copy(cols.begin() + rowptr[i], cols.begin() + rowptr[i + 1], pc.begin() + prow[i]);
-        continue;
-      }
-      // entry e = c * 256 + 64 k + l of the row goes to c * 256 + 4 l + k
-      for (int64_t e = 0; e < n; ++e) {
-        const int64_t c = e / slp::kNearChunk, r = e % slp::kNearChunk;
-        const int64_t k = r / 64, l = r % 64;
-        pc[prow[i] + c * slp::kNearChunk + 4 * l + k] = cols[rowptr[i] + e];
-      }
-    }
-    cols.swap(pc);
-  }
-  std::vector<int64_t> counts(P);
-  for (int64_t i = 0; i < P; ++i) counts[i] = rowptr[i + 1] - rowptr[i];
-  rowptr.swap(prow);
-
-  // packed columns: chunk base + 16-bit offsets, if every chunk spans < 65535
-  std::vector<int32_t> bases;
-  std::vector<uint16_t> offs;
-  bool packed = chunked;
-  if (packed) {
-    const int64_t nch = stored / slp::kNearChunk;
-    bases.assign(nch, 0);
-    for (int64_t c = 0; c < nch && packed; ++c) {
-      int32_t lo = std::numeric_limits<int32_t>::max(), hi = -1;
-      for (int64_t e = c * slp::kNearChunk; e < (c + 1) * slp::kNearChunk; ++e)
-        if (cols[e] >= 0) { lo = std::min(lo, cols[e]); hi = std::max(hi, cols[e]); }
-      if (hi < 0) lo = hi = 0;
-      if ((int64_t)hi - lo >= 65535) packed = false;
-      bases[c] = lo;
-    }
-    if (packed) {
-      offs.assign(stored, 0);
-      for (int64_t e = 0; e < stored; ++e)
-        if (cols[e] >= 0) offs[e] = (uint16_t)(cols[e] - bases[e / slp::kNearChunk]);
-    } else {
-      std::vector<int32_t>().swap(bases);
-    }
-  }
+  NearLayout L;
+  if (!near_layout(rowptr, cols, P, L))
+    return fail(SLP_ENOMEM, "host allocation for the padded near-field pattern failed");
+  const bool chunked = L.chunked, packed = L.packed;
+  const int64_t stored = L.stored;
+  rowptr.swap(L.prow);
+  cols.swap(L.cols);
+  std::vector<int32_t> &bases = L.bases;
+  std::vector<uint16_t> &offs = L.offs;
+  std::vector<int64_t> &counts = L.counts;
 
   // persistent: pattern, values, element means; temporary: coordinates,
   // triangles, terms (and the int32 columns when packed)
@@ -1562,6 +1586,37 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
     HIP_TRY(slp::launch_near_values<float>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S, st));
   }
   HIP_TRY(hipStreamSynchronize(st));   // host vectors and temporaries go out of scope
+  return SLP_OK;
+}
+
+int slp_near_field_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,
+                                int64_t n_tris, const double *targets, int64_t n_targets,
+                                double eps, int32_t precision, int64_t *bytes) {
+  if (!nodes || !tris || !bytes) return fail(SLP_EINVAL, "NULL argument");
+  if (n_nodes < 3 || n_tris < 1) return fail(SLP_EINVAL, "empty mesh");
+  if (!std::isfinite(eps)) return fail(SLP_EINVAL, "eps must be finite");
+  if (precision != SLP_FP64 && precision != SLP_FP32)
+    return fail(SLP_EINVAL, "precision must be SLP_FP64 or SLP_FP32");
+  for (int64_t j = 0; j < 3 * n_tris; ++j)
+    if (tris[j] < 0 || tris[j] >= n_nodes)
+      return fail(SLP_EINVAL, "triangle %lld references node %d out of range", (long long)(j / 3), tris[j]);
+  if (!targets) {
+    targets = nodes;
+    n_targets = n_nodes;
+  }
+  *bytes = 0;
+  if (eps <= 0.0) return SLP_OK;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> cols;
+  std::string err;
+  if (!slp::build_near_pattern(nodes, n_nodes, tris, n_tris, targets, n_targets, eps, host_threads(),
+                               rowptr, cols, err))
+    return fail(SLP_ENOMEM, "%s", err.c_str());
+  if (rowptr.back() == 0) return SLP_OK;
+  NearLayout L;
+  if (!near_layout(rowptr, cols, n_targets, L))
+    return fail(SLP_ENOMEM, "host allocation for the padded near-field pattern failed");
+  *bytes = near_bytes(L, n_targets, n_tris, precision == SLP_FP64 ? 8 : 4, 1);
   return SLP_OK;
 }
 

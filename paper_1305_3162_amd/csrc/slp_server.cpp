@@ -34,6 +34,7 @@ struct HostGeometry {
   std::vector<int32_t> tris;
   std::vector<double> es_w, es_gamma;
   slp_params params{};
+  double near_eps = 0.0;         // near-field correction within this distance (0: none)
   slp_geom *geom = nullptr;
   int64_t points = 0;
 };
@@ -53,6 +54,14 @@ struct HipDevice {
     int rc = slp_setup_geometry(&h.geom, h.nodes.data(), (int64_t)h.nodes.size() / 3, h.tris.data(),
                                 (int64_t)h.tris.size() / 3, &p, setup_stream);
     if (rc) return rc;
+    if (h.near_eps > 0.0) {
+      rc = slp_setup_near_field(h.geom, h.near_eps, setup_stream);
+      if (rc) {
+        slp_geom_destroy(h.geom);
+        h.geom = nullptr;
+        return rc;
+      }
+    }
     slp_geom_info info;
     slp_geom_get_info(h.geom, &info);
     *bytes = info.device_bytes;
@@ -176,10 +185,11 @@ int slp_server_create(slp_server **out, size_t device_budget_bytes, int32_t n_sl
   return SLP_OK;
 }
 
-int slp_server_add_geometry(slp_server *s, const double *nodes, int64_t n_nodes, const int32_t *tris,
-                            int64_t n_tris, const slp_params *p, int64_t *geom_id) {
+int slp_server_add_geometry_near(slp_server *s, const double *nodes, int64_t n_nodes,
+                                 const int32_t *tris, int64_t n_tris, const slp_params *p,
+                                 double eps, int64_t *geom_id) {
   if (!s || !nodes || !tris || !p || !geom_id || n_nodes < 3 || n_tris < 1 || p->es_terms < 1 ||
-      !p->es_w || !p->es_gamma)
+      !p->es_w || !p->es_gamma || !std::isfinite(eps))
     return srv_fail(SLP_EINVAL, "server: invalid geometry arguments");
   HostGeometry h;
   h.nodes.assign(nodes, nodes + 3 * n_nodes);
@@ -187,13 +197,26 @@ int slp_server_add_geometry(slp_server *s, const double *nodes, int64_t n_nodes,
   h.es_w.assign(p->es_w, p->es_w + p->es_terms);
   h.es_gamma.assign(p->es_gamma, p->es_gamma + p->es_terms);
   h.params = *p;
+  h.near_eps = eps > 0.0 ? eps : 0.0;
   int64_t bytes = 0;
-  const int rc = slp_geometry_device_bytes(nodes, n_nodes, tris, n_tris, p, &bytes);
+  int rc = slp_geometry_device_bytes(nodes, n_nodes, tris, n_tris, p, &bytes);
   if (rc) return rc;
+  if (h.near_eps > 0.0) {
+    int64_t nb = 0;
+    rc = slp_near_field_device_bytes(nodes, n_nodes, tris, n_tris, nullptr, 0, h.near_eps,
+                                     p->precision, &nb);
+    if (rc) return rc;
+    bytes += nb;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   s->geoms.push_back(std::move(h));
   *geom_id = s->sched->add_geometry(bytes);
   return SLP_OK;
+}
+
+int slp_server_add_geometry(slp_server *s, const double *nodes, int64_t n_nodes, const int32_t *tris,
+                            int64_t n_tris, const slp_params *p, int64_t *geom_id) {
+  return slp_server_add_geometry_near(s, nodes, n_nodes, tris, n_tris, p, 0.0, geom_id);
 }
 
 int slp_server_submit(slp_server *s, int64_t geom_id, const double *dens, double *phi,

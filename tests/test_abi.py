@@ -130,3 +130,28 @@ def test_choose_cutoff():
         slp.choose_cutoff(1e-7, slp.FP32)          # below the FP32 rounding floor
     with pytest.raises(slp.SlpError):
         slp.choose_cutoff(1e-13, slp.FP64, slp.WINDOW_GAUSS)
+
+
+def test_fem_setup_rejects_bad_meshes():
+    """Mesh checks of slp_fem_setup run on the host before any device call."""
+    from synth import cube_tets
+    nodes, tets = cube_tets(2)
+    bad = tets.copy()
+    bad[3, 1] = nodes.shape[0]
+    with pytest.raises(slp.SlpError, match="out of range"):
+        slp.fem_setup(nodes, bad, stream=0)
+    nn = nodes.copy()
+    nn[4, 2] = np.nan
+    with pytest.raises(slp.SlpError, match="non-finite"):
+        slp.fem_setup(nn, tets, stream=0)
+    flat = tets.copy()
+    flat[0, 3] = flat[0, 2]
+    with pytest.raises(slp.SlpError, match="degenerate"):
+        slp.fem_setup(nodes, flat, stream=0)
+    # three tetrahedra on one face
+    p = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1], [0.3, 0.3, 2.0]], float)
+    t = np.array([[0, 1, 2, 3], [0, 1, 2, 4], [0, 1, 2, 5]], dtype=np.int32)
+    with pytest.raises(slp.SlpError, match="more than two"):
+        slp.fem_setup(p, t, stream=0)
+    with pytest.raises(ValueError):
+        slp.fem_setup(nodes, tets[:, :3], stream=0)

@@ -108,3 +108,33 @@ def test_oversized_geometry_fails_cleanly():
     st = srv.stats()
     assert st["failed"] == 1 and st["completed"] == 1
     srv.close()
+
+
+def test_near_field_served_and_estimated():
+    """A geometry registered with a near field: the served result equals a
+    context with the same near field, and the memory estimate used for
+    admission equals what the context holds (both precisions, plain and packed
+    layouts)."""
+    cases = [(sphere_random(3, 16, 64, 6), slp.FP64, 1e-2),
+             (cube_random(64, 17, 128, 5), slp.FP32, 1e-3)]
+    srv = slp.Server(4096 << 20, 2)
+    rng = np.random.default_rng(8)
+    for wl, prec, tol in cases:
+        log(f"case served near field {wl.name} prec={prec} tol={tol}")
+        w, g = es_for(wl)
+        G = slp.Geometry(wl.nodes, wl.tris, wl.grid, wl.m, w, g, wl.alpha, prec, wl.eta2)
+        eps = G.near_radius(tol)
+        G.setup_near_field(eps)
+        est = (slp.geometry_device_bytes(wl.nodes, wl.tris, wl.grid, wl.m, w, g, wl.alpha, prec)
+               + slp.near_field_device_bytes(wl.nodes, wl.tris, eps, prec))
+        assert G.info["device_bytes"] == est, (G.info["device_bytes"], est)
+        dens = torch.as_tensor(rng.normal(size=wl.n_src)).cuda()
+        want = G.solve(dens)
+        torch.cuda.synchronize()
+        G.close()
+        gid = srv.add_geometry(wl.nodes, wl.tris, wl.grid, wl.m, w, g, wl.alpha, prec, wl.eta2,
+                               near_eps=eps)
+        phi = torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+        srv.wait(srv.submit(gid, dens, phi), 60.0)
+        assert rel_l2(phi.cpu().numpy(), want.cpu().numpy()) <= _tol(prec)
+    srv.close()

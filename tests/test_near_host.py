@@ -116,3 +116,19 @@ def test_near_host_rejects_bad_input():
         slp.near_pattern_host(nodes, bad, nodes, 0.1)
     with pytest.raises(slp.SlpError, match="misses"):
         slp.near_radius_host(np.array([1.0]), np.array([1.0]), 2.0, 1e-6)
+
+
+def test_near_field_device_bytes_estimate():
+    """The host estimate follows the stored layout: rows padded to groups of
+    four (short rows), FP64 values, int32 columns, int64 row offsets, one
+    element-mean array; every buffer at least 256 bytes."""
+    wl = workloads.sphere_uniform(level=2, grid=32, m=4)
+    assert slp.near_field_device_bytes(wl.nodes, wl.tris, 0.0) == 0
+    a = lambda b: max(b, 256)  # noqa: E731
+    for eps in (0.2, 0.6):
+        rp, _ = slp.near_pattern_host(wl.nodes, wl.tris, wl.nodes, eps)
+        stored = int(((np.diff(rp) + 3) // 4 * 4).sum())
+        P, M = wl.nodes.shape[0], wl.tris.shape[0]
+        for prec, esz in ((slp.FP64, 8), (slp.FP32, 4)):
+            want = a((P + 1) * 8) + a(stored * esz) + a(M * 8) + a(stored * 4)
+            assert slp.near_field_device_bytes(wl.nodes, wl.tris, eps, prec) == want
