@@ -127,6 +127,39 @@ def dphi1_dn(nodes, tets, phi1, tris, owner):
     return np.einsum("ti,ti->t", grad, n)
 
 
+def stray_field_energy(nodes, tets, m_nodes, phi):
+    """E = -(1/2) int_Omega m . H = (1/2) int_Omega m . grad phi with the stray
+    field H = -grad phi (units of mu_0 Ms^2 times length^3): with m affine and
+    grad phi constant on every tetrahedron, int_T m . grad phi = |T| mbar_T .
+    grad phi_T exactly. The paper forms the field by mass lumping (Numerics
+    section), which gives the same value for uniform m."""
+    vol, G = tet_gradients(nodes, tets)
+    grad = np.einsum("ta,tai->ti", np.asarray(phi)[tets], G)
+    mbar = np.asarray(m_nodes, dtype=np.float64)[tets].mean(axis=1)
+    return 0.5 * float(np.sum(vol * np.einsum("ti,ti->t", mbar, grad)))
+
+
+def prism_demag_factor(a, b, c):
+    """Demagnetising factor along the 2c edge of a uniformly magnetised
+    rectangular prism 2a x 2b x 2c (closed form of Aharoni, J. Appl. Phys. 83,
+    3432 (1998)); the stray-field energy of the prism magnetised along that
+    edge is N V / 2 in units of mu_0 Ms^2."""
+    r = np.sqrt(a * a + b * b + c * c)
+    rab, rbc, rac = np.sqrt(a * a + b * b), np.sqrt(b * b + c * c), np.sqrt(a * a + c * c)
+    t = ((b * b - c * c) / (2 * b * c) * np.log((r - a) / (r + a))
+         + (a * a - c * c) / (2 * a * c) * np.log((r - b) / (r + b))
+         + b / (2 * c) * np.log((rab + a) / (rab - a))
+         + a / (2 * c) * np.log((rab + b) / (rab - b))
+         + c / (2 * a) * np.log((rbc - b) / (rbc + b))
+         + c / (2 * b) * np.log((rac - a) / (rac + a))
+         + 2 * np.arctan(a * b / (c * r))
+         + (a ** 3 + b ** 3 - 2 * c ** 3) / (3 * a * b * c)
+         + (a * a + b * b - 2 * c * c) / (3 * a * b * c) * r
+         + c / (a * b) * (rac + rbc)
+         - (rab ** 3 + rbc ** 3 + rac ** 3) / (3 * a * b * c))
+    return float(t / np.pi)
+
+
 def scalar_potential(nodes, tets, m_nodes, grid, eps, alpha=2, es_h=0.2, es_r_lo=None,
                      es_r_hi=None, es_tol=1e-12, eta2=37.0, parts=False):
     """phi = phi_1 + phi_2 at every node (Alg. 1): phi_1 from eq. poisson, the

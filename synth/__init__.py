@@ -7,14 +7,14 @@ the single-layer-potential arithmetic (no scaling to the torus, no kernel
 coefficients, no window, no transforms); both the HIP library and the oracle
 do that work independently from these arrays.
 """
-from .meshes import (icosphere, box_surface, cube, cube_volume_nodes, cube_tets, ball_tets,
+from .meshes import (icosphere, box_surface, cube, cube_volume_nodes, box_tets, cube_tets, ball_tets,
                      thin_film, mesh_summary)
 from .fields import RandomSmoothMagnetisation, uniform_magnetisation
 from .density import quadrature_sample_points, density_from_magnetisation
 from .workloads import Workload, make_workload, WORKLOADS
 
 __all__ = [
-    "cube_volume_nodes", "cube_tets", "ball_tets",
+    "cube_volume_nodes", "box_tets", "cube_tets", "ball_tets",
     "icosphere", "box_surface", "cube", "thin_film", "mesh_summary",
     "RandomSmoothMagnetisation", "uniform_magnetisation",
     "quadrature_sample_points", "density_from_magnetisation",

@@ -113,18 +113,20 @@ def cube_volume_nodes(cells_per_edge: int):
     return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
 
 
-def cube_tets(cells_per_edge: int):
-    """Structured tetrahedral mesh of the unit cube [-1/2, 1/2]^3: the nodes of
-    cube_volume_nodes(c) (index (i (c+1) + j)(c+1) + k for lattice point (i, j, k))
-    and every lattice cell split into the six tetrahedra that share its diagonal
-    from the lowest to the highest corner (one per order of the three axes).
-    Each boundary face of a cell is then split along its (i, j) -> (i+1, j+1)
-    diagonal, as in cube(c). Tetrahedra are positively oriented. Returns
-    (nodes [(c+1)^3, 3], tets int32 [6 c^3, 4])."""
-    c = int(cells_per_edge)
-    nodes = cube_volume_nodes(c)
-    n1 = c + 1
-    ii, jj, kk = np.meshgrid(np.arange(c), np.arange(c), np.arange(c), indexing="ij")
+def box_tets(extent, cells):
+    """Structured tetrahedral mesh of the box of the given extent centred at 0:
+    the lattice points (index (i (cy+1) + j)(cz+1) + k for lattice point
+    (i, j, k)) and every lattice cell split into the six tetrahedra that share
+    its diagonal from the lowest to the highest corner (one per order of the
+    three axes). Each boundary face of a cell is then split along its
+    (i, j) -> (i+1, j+1) diagonal, as in box_surface. Tetrahedra are positively
+    oriented. Returns (nodes [(cx+1)(cy+1)(cz+1), 3], tets int32 [6 cx cy cz, 4])."""
+    ex = np.asarray(extent, dtype=np.float64)
+    cx, cy, cz = (int(c) for c in cells)
+    axes = [np.linspace(-0.5 * ex[q], 0.5 * ex[q], n + 1) for q, n in enumerate((cx, cy, cz))]
+    x, y, z = np.meshgrid(*axes, indexing="ij")
+    nodes = np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+    ii, jj, kk = np.meshgrid(np.arange(cx), np.arange(cy), np.arange(cz), indexing="ij")
     base = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)
     tets = []
     for order in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
@@ -133,10 +135,18 @@ def cube_tets(cells_per_edge: int):
         for ax in order:
             corner[:, ax] += 1
             verts.append(corner.copy())
-        ids = [(v[:, 0] * n1 + v[:, 1]) * n1 + v[:, 2] for v in verts]
+        ids = [(v[:, 0] * (cy + 1) + v[:, 1]) * (cz + 1) + v[:, 2] for v in verts]
         tets.append(np.stack(ids, axis=1))
     tets = np.concatenate(tets, axis=0).astype(np.int32)
     return nodes, _orient_tets(nodes, tets)
+
+
+def cube_tets(cells_per_edge: int):
+    """box_tets of the unit cube [-1/2, 1/2]^3 with c cells per edge: its nodes
+    are cube_volume_nodes(c) in the same order and its boundary faces the
+    triangles of cube(c)."""
+    c = int(cells_per_edge)
+    return box_tets((1.0, 1.0, 1.0), (c, c, c))
 
 
 def ball_tets(cells_per_edge: int, radius: float = 1.0):

@@ -158,3 +158,43 @@ def test_scalar_potential_manufactured_cube():
                                                      es_r_hi=hi, parts=True)
     assert np.abs(phi1 - phie).max() < 1e-3
     assert np.abs(phi - phie).max() < 6e-3 and np.abs(phi2).max() < 6e-3
+
+
+def test_prism_demag_factor_closed_form():
+    # the cube: 1/3 by symmetry; any prism: the three factors sum to 1; a thin
+    # plate tends to 1 across its thickness
+    assert fem.prism_demag_factor(1.0, 1.0, 1.0) == pytest.approx(1.0 / 3.0, abs=1e-14)
+    rng = np.random.default_rng(31)
+    for _ in range(5):
+        a, b, c = rng.uniform(0.1, 3.0, size=3)
+        s = fem.prism_demag_factor(a, b, c) + fem.prism_demag_factor(b, c, a) + fem.prism_demag_factor(c, a, b)
+        assert s == pytest.approx(1.0, abs=1e-12)
+    thin = [fem.prism_demag_factor(1.0, 1.0, c) for c in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5)]
+    assert np.all(np.diff(thin) > 0) and thin[-1] > 0.9999
+    # the reference energy printed with Table 3 (film 1 x 1 x 0.1 magnetised across)
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "table3_film_energy.txt")
+    ref = float([l for l in open(path) if not l.startswith("#")][0])
+    assert 0.5 * fem.prism_demag_factor(0.5, 0.5, 0.05) * 0.1 == pytest.approx(ref, abs=5e-6)
+
+
+def test_energy_uniform_film_and_ball():
+    # Alg. 1 followed by E = (1/2) int m . grad phi against the closed forms:
+    # the 1 x 1 x 0.1 film magnetised across (N V / 2) and the ball (V / 6)
+    from synth import box_tets
+    grid = (64, 64, 16)
+    nodes, tets = box_tets((1.0, 1.0, 0.1), (16, 16, 2))
+    m = np.tile([0.0, 0.0, 1.0], (nodes.shape[0], 1))
+    eps, lo, hi = _eps(nodes, tets, grid, 1e-3)
+    phi = fem.scalar_potential(nodes, tets, m, grid, eps, es_r_lo=lo, es_r_hi=hi)
+    E = fem.stray_field_energy(nodes, tets, m, phi)
+    assert abs(E / (0.5 * fem.prism_demag_factor(0.5, 0.5, 0.05) * 0.1) - 1.0) < 0.02
+    errs = []
+    for c in (6, 8):
+        nodes, tets = ball_tets(c, 1.0)
+        m = np.tile([0.0, 0.0, 1.0], (nodes.shape[0], 1))
+        eps, lo, hi = _eps(nodes, tets, (64, 64, 64), 1e-3)
+        phi = fem.scalar_potential(nodes, tets, m, (64, 64, 64), eps, es_r_lo=lo, es_r_hi=hi)
+        vol, _ = fem.tet_gradients(nodes, tets)
+        errs.append(abs(fem.stray_field_energy(nodes, tets, m, phi) / (vol.sum() / 6.0) - 1.0))
+    assert errs[1] < 0.015 and errs[1] < errs[0]
