@@ -346,6 +346,15 @@ int slp_fem_dphi1_dn(slp_fem *f, const double *phi1, double *dphi1_dn, void *str
  * EINVAL if g does not match the mesh or the solve misses tol. */
 int slp_scalar_potential(slp_fem *f, slp_geom *g, const double *m_nodes, double *phi, double tol,
                          int32_t max_iter, int32_t warm_start, int32_t *iters, void *stream);
+/* Stray-field energy E = -(1/2) int m . H = (1/2) int m . grad phi (units of
+ * mu_0 Ms^2 times length^3; the quantity of Tables 3-4): with m the nodal P1
+ * field and phi a P1 potential (e.g. from slp_scalar_potential), each
+ * tetrahedron contributes |T| mbar_T . grad phi_T exactly. The paper forms the
+ * field by mass lumping, which gives the same value for uniform m.
+ *   m_nodes : device float64 [n_nodes][3];  phi : device float64 [n_nodes]
+ * Synchronises `stream`; the sum over tetrahedra is taken in a fixed order. */
+int slp_fem_energy(slp_fem *f, const double *m_nodes, const double *phi, double *energy,
+                   void *stream);
 int slp_fem_destroy(slp_fem *f);
 
 int slp_geom_destroy(slp_geom *g);

@@ -21,7 +21,7 @@ __all__ = [
     "setup_near_field", "near_radius", "near_field_info", "debug_copy_near",
     "near_pattern_host", "triangle_potential_host", "near_radius_host",
     "near_field_device_bytes", "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
-    "scalar_potential", "fem_destroy", "Fem",
+    "scalar_potential", "fem_energy", "fem_destroy", "Fem",
 ]
 
 FP64, FP32 = 0, 1
@@ -129,6 +129,7 @@ def load_library():
         "slp_scalar_potential": [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _VP],
         "slp_fem_destroy": [_VP],
+        "slp_fem_energy": [_VP, _VP, _VP, ctypes.POINTER(ctypes.c_double), _VP],
         "slp_near_field_device_bytes": [_VP, ctypes.c_int64, _VP, ctypes.c_int64, _VP,
                                         ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_int64)],
@@ -523,6 +524,16 @@ def scalar_potential(fem, geom, m_nodes, phi, tol=1e-10, max_iter=20000, warm_st
     return it.value
 
 
+def fem_energy(fem, m_nodes, phi, stream=None):
+    """slp_fem_energy: (1/2) int m . grad phi over the mesh."""
+    e = ctypes.c_double(0.0)
+    n = phi.numel()
+    _check(load_library().slp_fem_energy(_VP(fem), _dev_f64(m_nodes, 3 * n, "m_nodes"),
+                                         _dev_f64(phi, n, "phi"), ctypes.byref(e),
+                                         _stream_ptr(stream)))
+    return e.value
+
+
 def fem_destroy(fem):
     _check(load_library().slp_fem_destroy(_VP(fem)))
 
@@ -592,6 +603,9 @@ class Fem:
 
     def dphi1_dn(self, phi1, dn, stream=None):
         fem_dphi1_dn(self.handle, phi1, dn, stream)
+
+    def energy(self, m_nodes, phi, stream=None):
+        return fem_energy(self.handle, m_nodes, phi, stream)
 
     def close(self):
         if self.handle:

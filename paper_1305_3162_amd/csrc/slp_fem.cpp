@@ -59,6 +59,7 @@ struct slp_fem {
   double *part = nullptr, *hist = nullptr;
   int32_t hist_cap = 0;
   double *phi1 = nullptr, *dn = nullptr;   // for slp_scalar_potential
+  double *epart = nullptr;                 // [ceil(T / 256) + 1] energy partials and sum
   double *h_pin = nullptr;                 // pinned [2] for the convergence check
   int32_t nblk = 1;
   int64_t bytes = 0;
@@ -329,6 +330,7 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
         {(void **)&F->p[1], (size_t)Nf * 8}, {(void **)&F->vm, (size_t)3 * T * 8},
         {(void **)&F->q, (size_t)Nf * 8}, {(void **)&F->part, (size_t)5 * F->nblk * 8},
         {(void **)&F->phi1, (size_t)N * 8}, {(void **)&F->dn, (size_t)Mb * 8},
+        {(void **)&F->epart, (size_t)((T + slp::kFemThreads - 1) / slp::kFemThreads + 1) * 8},
     };
     for (const Req &rq : reqs)
       if (F->alloc(rq.p, rq.n) != hipSuccess)
@@ -496,6 +498,19 @@ int slp_scalar_potential(slp_fem *F, slp_geom *g, const double *m_nodes, double 
   rc = slp_eval_single_layer(g, phi, stream);
   if (rc) return rc;
   FEM_TRY(slp::launch_fem_add(phi, F->phi1, F->n_nodes, st));
+  return SLP_OK;
+}
+
+int slp_fem_energy(slp_fem *F, const double *m_nodes, const double *phi, double *energy,
+                   void *stream) {
+  if (!F || !m_nodes || !phi || !energy) return fail(SLP_EINVAL, "NULL argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nb = (F->n_tets + slp::kFemThreads - 1) / slp::kFemThreads;
+  FEM_TRY(slp::launch_fem_energy(F->tets, F->vol, F->grad, m_nodes, phi, F->epart, F->epart + nb,
+                                 F->n_tets, st));
+  FEM_TRY(hipMemcpyAsync(F->h_pin, F->epart + nb, 8, hipMemcpyDeviceToHost, st));
+  FEM_TRY(hipStreamSynchronize(st));
+  *energy = 0.5 * F->h_pin[0];
   return SLP_OK;
 }
 

@@ -188,6 +188,38 @@ __global__ __launch_bounds__(kFemThreads) void k_fem_add(double *__restrict__ ph
   if (k < n) phi[k] += phi1[k];
 }
 
+__global__ __launch_bounds__(kFemThreads) void k_fem_energy(const int32_t *__restrict__ tets,
+                                                            const double *__restrict__ vol,
+                                                            const double *__restrict__ grad,
+                                                            const double *__restrict__ m,
+                                                            const double *__restrict__ phi,
+                                                            double *__restrict__ part, int64_t nt) {
+  const int64_t t = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  double e = 0.0;
+  if (t < nt) {
+    double g[3] = {0.0, 0.0, 0.0}, mb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t nd = tets[4 * t + v];
+      const double u = phi[nd];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        g[q] += u * grad[12 * t + 3 * v + q];
+        mb[q] += m[3 * nd + q];
+      }
+    }
+    e = vol[t] * 0.25 * (mb[0] * g[0] + mb[1] * g[1] + mb[2] * g[2]);
+  }
+  e = block_sum(e);
+  if (threadIdx.x == 0) part[blockIdx.x] = e;
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_fem_sum(const double *__restrict__ part, int n,
+                                                         double *__restrict__ out) {
+  const double s = sum_parts(part, n);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
 unsigned blocks(int64_t n) { return (unsigned)((n + kFemThreads - 1) / kFemThreads); }
 
 }  // namespace
@@ -229,6 +261,16 @@ hipError_t launch_fem_dn(const int32_t *owner, const double *nrm, const int32_t 
   if (mb <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fem_dn, dim3(blocks(mb)), dim3(kFemThreads), 0, s, owner, nrm, tets, grad,
                      phi1, dn, mb);
+  return hipGetLastError();
+}
+
+hipError_t launch_fem_energy(const int32_t *tets, const double *vol, const double *grad,
+                             const double *m, const double *phi, double *part, double *out,
+                             int64_t nt, hipStream_t s) {
+  if (nt <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fem_energy, dim3(blocks(nt)), dim3(kFemThreads), 0, s, tets, vol, grad, m,
+                     phi, part, nt);
+  hipLaunchKernelGGL(k_fem_sum, dim3(1), dim3(kFemThreads), 0, s, part, (int)blocks(nt), out);
   return hipGetLastError();
 }
 

@@ -66,5 +66,10 @@ hipError_t launch_fem_dn(const int32_t *owner, const double *nrm, const int32_t 
                          hipStream_t s);
 // phi += phi_1.
 hipError_t launch_fem_add(double *phi, const double *phi1, int64_t n, hipStream_t s);
+// out[0] = sum over tetrahedra of |T| mbar_T . grad phi_T (per-workgroup
+// partials in part [ceil(T / kFemThreads)], then one workgroup sums them).
+hipError_t launch_fem_energy(const int32_t *tets, const double *vol, const double *grad,
+                             const double *m, const double *phi, double *part, double *out,
+                             int64_t nt, hipStream_t s);
 
 }  // namespace slp

@@ -117,3 +117,40 @@ def test_full_size_cube_mesh():
     assert rr <= 1e-10 and rel <= 2e-10
     assert np.all(x[~free] == 0.0)
     assert np.abs(x - phie).max() < 2e-5
+
+
+def _film_energy(cells, grid, tol=1e-3):
+    from synth import box_tets
+    nodes, tets = box_tets((1.0, 1.0, 0.1), cells)
+    m = np.tile([0.0, 0.0, 1.0], (nodes.shape[0], 1))
+    lo, hi = expsum_interval(nodes)
+    F = slp.Fem(nodes, tets)
+    w, g = slp.expsum_sinc(0.2, lo, hi, 1e-12)
+    G = slp.Geometry(nodes, F.boundary, grid, 8, w, g, 2, slp.FP64)
+    eps = G.near_radius(tol)
+    G.setup_near_field(eps)
+    md = torch.as_tensor(m).cuda()
+    phi = torch.zeros(nodes.shape[0], dtype=torch.float64, device="cuda")
+    slp.scalar_potential(F.handle, G.handle, md, phi, tol=1e-12)
+    E = F.energy(md, phi)
+    G.close()
+    F.close()
+    return E, nodes, tets, m, eps, (lo, hi)
+
+
+def test_film_energy_against_oracle_and_closed_form():
+    """The uniformly magnetised 1 x 1 x 0.1 film of Table 3: the device energy
+    after Alg. 1 equals the oracle's on the coarse mesh and approaches the
+    closed form N V / 2 (0.04025 with Table 3) as the mesh is refined."""
+    ref = 0.5 * fem.prism_demag_factor(0.5, 0.5, 0.05) * 0.1
+    E, nodes, tets, m, eps, (lo, hi) = _film_energy((16, 16, 2), (64, 64, 32))
+    phi_o = fem.scalar_potential(nodes, tets, m, (64, 64, 32), eps, es_r_lo=lo, es_r_hi=hi)
+    Eo = fem.stray_field_energy(nodes, tets, m, phi_o)
+    log(f"case film energy 16x16x2: device {E:.8e}, oracle {Eo:.8e}, closed form {ref:.8e}")
+    assert abs(E - Eo) <= 1e-8 * abs(Eo)
+    errs = [abs(E / ref - 1.0)]
+    for cells, grid in (((32, 32, 4), (128, 128, 32)), ((64, 64, 8), (256, 256, 32))):
+        Ec, nodes, *_ = _film_energy(cells, grid)
+        errs.append(abs(Ec / ref - 1.0))
+        log(f"  film {cells} ({nodes.shape[0]} nodes): energy {Ec:.6e}, error {errs[-1]:.3%}")
+    assert errs[0] < 0.02 and errs[1] < errs[0] and errs[2] < errs[1] and errs[2] < 0.003

@@ -182,7 +182,7 @@ def test_energy_uniform_film_and_ball():
     # Alg. 1 followed by E = (1/2) int m . grad phi against the closed forms:
     # the 1 x 1 x 0.1 film magnetised across (N V / 2) and the ball (V / 6)
     from synth import box_tets
-    grid = (64, 64, 16)
+    grid = (64, 64, 32)
     nodes, tets = box_tets((1.0, 1.0, 0.1), (16, 16, 2))
     m = np.tile([0.0, 0.0, 1.0], (nodes.shape[0], 1))
     eps, lo, hi = _eps(nodes, tets, grid, 1e-3)
