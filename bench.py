@@ -70,6 +70,10 @@ def parse():
                          "phi = phi_1 + phi_2")
     ap.add_argument("--cg-tol", type=float, default=1e-8,
                     help="relative residual of the phi_1 solve (--potential)")
+    ap.add_argument("--rotate-deg", type=float, default=0.0,
+                    help="--potential as a time stepper: the magnetisation turns by this angle "
+                         "(degrees, about the axis (1,1,1)) every step and phi_1 starts from the "
+                         "previous step's solution")
     ap.add_argument("--rho", type=float, default=0.8, help="offered load / capacity")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known "
@@ -346,19 +350,36 @@ def potential(args):
         G.setup_near_field(eps, stream)
     t_near_setup = time.perf_counter() - t1
     nf = G.near_field_info()
-    md = torch.as_tensor(m_nodes, device="cuda")
     phi = torch.empty(nodes.shape[0], dtype=torch.float64, device="cuda")
-    iters = 0
-    for _ in range(args.warmup):
-        iters = slp.scalar_potential(F.handle, G.handle, md, phi, args.cg_tol, 20000, False, stream)
+    warm = args.rotate_deg != 0.0
+    n_in = args.warmup + args.steps if warm else 1
+    # every step's magnetisation resident in HBM before the timed region: the
+    # field turned by k * rotate_deg about (1,1,1) (Rodrigues' rotation)
+    ax = np.ones(3) / np.sqrt(3.0)
+    mds = []
+    for k in range(n_in):
+        th = np.deg2rad(args.rotate_deg * k)
+        mk = (m_nodes * np.cos(th) + np.cross(ax, m_nodes) * np.sin(th)
+              + np.outer(m_nodes @ ax, ax) * (1.0 - np.cos(th)))
+        mds.append(torch.as_tensor(mk, device="cuda"))
+    iters_all = []
+    for k in range(args.warmup):
+        iters_all.append(slp.scalar_potential(F.handle, G.handle, mds[k if warm else 0], phi,
+                                              args.cg_tol, 20000, warm and k > 0, stream))
     torch.cuda.synchronize()
     slp.set_timing(G.handle, 1)
     slp.stage_times(G.handle, reset=True)
+    iters_all = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        iters = slp.scalar_potential(F.handle, G.handle, md, phi, args.cg_tol, 20000, False, stream)
+    for k in range(args.steps):
+        kk = args.warmup + k
+        iters_all.append(slp.scalar_potential(F.handle, G.handle, mds[kk if warm else 0], phi,
+                                              args.cg_tol, 20000, warm and kk > 0, stream))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    iters = int(round(float(np.mean(iters_all))))
+    md = mds[args.warmup + args.steps - 1 if warm else 0]
+    m_nodes = md.cpu().numpy()
     stage_ms, cnt = slp.stage_times(G.handle, reset=True)
     slp.set_timing(G.handle, False)
     ms_per_step = wall * 1e3 / args.steps
@@ -426,6 +447,8 @@ def potential(args):
                                f"triangles ({n_src} sources), seeded smooth magnetisation (seed 2), "
                                f"grid 128^3, Gaussian m={m_win}",
                    "cg_tol": args.cg_tol, "cg_iterations": iters,
+                   "time_stepping": ({"rotate_deg_per_step": args.rotate_deg,
+                                      "warm_start": True} if warm else None),
                    "near_field": {"tol": near_tol, "eps": round(eps, 6), "pairs": nf["nnz"],
                                   "stored": nf["stored"], "setup_s": round(t_near_setup, 2)},
                    "fem_setup_s": round(t_fem_setup, 2), "points": pts},

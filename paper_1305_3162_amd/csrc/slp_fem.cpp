@@ -64,17 +64,25 @@ struct slp_fem {
   int32_t nblk = 1;
   int64_t bytes = 0;
   std::vector<void *> allocs;
+  std::vector<int64_t> alloc_bytes;
   hipError_t alloc(void **p_, size_t n) {
     *p_ = nullptr;
-    hipError_t e = hipMalloc(p_, std::max<size_t>(n, 256));
-    if (e == hipSuccess) { allocs.push_back(*p_); bytes += (int64_t)std::max<size_t>(n, 256); }
+    const size_t b = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(p_, b);
+    if (e == hipSuccess) {
+      allocs.push_back(*p_);
+      alloc_bytes.push_back((int64_t)b);
+      bytes += (int64_t)b;
+    }
     return e;
   }
   void release(void *p_) {
     for (size_t i = 0; i < allocs.size(); ++i)
       if (allocs[i] == p_) {
         (void)hipFree(p_);
+        bytes -= alloc_bytes[i];
         allocs.erase(allocs.begin() + i);
+        alloc_bytes.erase(alloc_bytes.begin() + i);
         return;
       }
   }
