@@ -102,15 +102,19 @@ def test_near_field_batched_and_graph():
     G = slp.Geometry(wl.nodes, wl.tris, wl.grid, 6, w, g, wl.alpha, slp.FP64, wl.eta2)
     G.setup_near_field(G.near_radius(1e-2))
     rng = np.random.default_rng(61)
-    dens = [torch.as_tensor(rng.normal(size=wl.n_src)).cuda() for _ in range(4)]
+    dens = [torch.as_tensor(rng.normal(size=wl.n_src)).cuda() for _ in range(11)]
     ref = [G.solve(dd).cpu().numpy() for dd in dens]
     stream = torch.cuda.current_stream()
-    phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
-            for _ in range(4)]
-    slp.eval_batched([G.handle] * 4, dens, phis, stream)
-    torch.cuda.synchronize()
-    for k in range(4):
-        assert rel_l2(phis[k].cpu().numpy(), ref[k]) <= 1e-14, k
+    # groups of 4 and 8 items share a pass over the matrix; 5 and 11 leave a
+    # partial group
+    for nb in (4, 5, 11):
+        phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+                for _ in range(nb)]
+        slp.eval_batched([G.handle] * nb, dens[:nb], phis, stream)
+        torch.cuda.synchronize()
+        for k in range(nb):
+            assert rel_l2(phis[k].cpu().numpy(), ref[k]) <= 1e-14, (nb, k)
+    dens, ref = dens[:4], ref[:4]
     slp.set_graph(G.handle, True)
     halves = [dd * 0.5 for dd in dens]        # kept alive until the replays have run
     for rep in range(3):
