@@ -70,6 +70,9 @@ def parse():
                          "phi = phi_1 + phi_2")
     ap.add_argument("--cg-tol", type=float, default=1e-8,
                     help="relative residual of the phi_1 solve (--potential)")
+    ap.add_argument("--precond", choices=["jacobi", "amg"], default="amg",
+                    help="preconditioner of the phi_1 solve (--potential): diagonal, or a "
+                         "smoothed-aggregation multigrid V-cycle")
     ap.add_argument("--rotate-deg", type=float, default=0.0,
                     help="--potential as a time stepper: the magnetisation turns by this angle "
                          "(degrees, about the axis (1,1,1)) every step and phi_1 starts from the "
@@ -323,7 +326,7 @@ def mix32(args):
 
 def potential(args):
     """One step = Alg. 1's computation phase (slp_scalar_potential): phi_1 by
-    conjugate gradients from zero, d phi_1/dn, the element density, phi_2 at
+    preconditioned conjugate gradients from zero, d phi_1/dn, the element density, phi_2 at
     every node of the tetrahedral mesh (smooth part + near field), the sum."""
     import torch
 
@@ -343,6 +346,9 @@ def potential(args):
     t1 = time.perf_counter()
     F = slp.Fem(nodes, tets, stream)
     t_fem_setup = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    slp.fem_set_preconditioner(F.handle, args.precond, stream)
+    t_precond_setup = time.perf_counter() - t1
     G = slp.Geometry(nodes, F.boundary, (128, 128, 128), m_win, w, g, 2, prec)
     t1 = time.perf_counter()
     eps = G.near_radius(near_tol) if near_tol > 0 else 0.0
@@ -446,7 +452,8 @@ def potential(args):
                                f"{F.info['n_free']} free nodes, {F.boundary.shape[0]} boundary "
                                f"triangles ({n_src} sources), seeded smooth magnetisation (seed 2), "
                                f"grid 128^3, Gaussian m={m_win}",
-                   "cg_tol": args.cg_tol, "cg_iterations": iters,
+                   "cg_tol": args.cg_tol, "cg_iterations": iters, "precond": args.precond,
+                   "precond_setup_s": round(t_precond_setup, 3),
                    "time_stepping": ({"rotate_deg_per_step": args.rotate_deg,
                                       "warm_start": True} if warm else None),
                    "near_field": {"tol": near_tol, "eps": round(eps, 6), "pairs": nf["nnz"],

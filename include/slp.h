@@ -311,18 +311,42 @@ typedef struct slp_fem slp_fem;   /* opaque; owns the mesh tables and the solver
  * boundary; ENOMEM; EDEVICE. */
 int slp_fem_setup(slp_fem **out, const double *nodes, int64_t n_nodes, const int32_t *tets,
                   int64_t n_tets, void *stream);
-/* Free nodes, boundary triangles, stored entries of S and device bytes (any
- * pointer may be NULL). */
+/* Free nodes, boundary triangles, stored entries of S_ff (entries whose
+ * element contributions cancel to within rounding are not stored) and device
+ * bytes (any pointer may be NULL). */
 int slp_fem_info(const slp_fem *f, int64_t *n_free, int64_t *n_boundary_tris, int64_t *nnz,
                  int64_t *device_bytes);
 /* The boundary triangles, host int32 [n_boundary_tris][3] (cap = room, in
  * triangles): the surface mesh to hand to slp_setup_geometry together with all
  * nodes (so that the targets are every node), in the order of dphi1_dn. */
 int slp_fem_boundary(const slp_fem *f, int32_t *tris, int64_t cap);
+/* Preconditioner of the conjugate gradients on the free-node system (Sec. 2.1
+ * names algebraic-multigrid preconditioned CG among the solvers of eq.
+ * poisson). SLP_PRECOND_JACOBI (the default): z = D^-1 r. SLP_PRECOND_AMG:
+ * one V(1,1) cycle of smoothed-aggregation multigrid (aggregates of strongly
+ * connected nodes, |a_ij| >= theta sqrt(a_ii a_jj) with theta = 0.08 halved
+ * per level; prolongation = one damped-Jacobi step applied to the piecewise
+ * constants; Galerkin coarse operators P^T A P; damped-Jacobi pre- and
+ * post-smoothing; every Jacobi step with the l1 weights (4/3) / sum_j |a_ij|;
+ * the coarsest operator, at most 512 unknowns, inverted densely), a symmetric
+ * positive definite preconditioner. Selecting it the first time builds the
+ * hierarchy on the host and copies it to the device (synchronising `stream`).
+ * Errors: EINVAL for an unknown kind or a hierarchy that cannot be built
+ * (stalled aggregation, coarsest operator not positive definite); ENOMEM. */
+#define SLP_PRECOND_JACOBI 0
+#define SLP_PRECOND_AMG 1
+int slp_fem_set_preconditioner(slp_fem *f, int32_t kind, void *stream);
+/* Sizes and stored entries of the operators of the hierarchy, finest first
+ * (the last is the dense coarsest inverse): rows, nnz host int64 [cap] (either
+ * may be NULL). EINVAL before SLP_PRECOND_AMG was selected or if cap is too
+ * small for *n_levels. */
+int slp_fem_amg_info(const slp_fem *f, int32_t *n_levels, int64_t *rows, int64_t *nnz,
+                     int32_t cap);
 /* phi_1 at every node (0 on the boundary): load vector b_k = sum_T |T| mbar_T .
- * grad eta_k (m the nodal P1 field, mbar_T its vertex mean), then conjugate
- * gradients with the diagonal (Jacobi) preconditioner on the free nodes until
- * |r| <= tol |b| (checked every 16 iterations) or max_iter iterations.
+ * grad eta_k (m the nodal P1 field, mbar_T its vertex mean), then
+ * preconditioned conjugate gradients on the free nodes until |r| <= tol |b|
+ * (checked every 16 iterations with Jacobi, every 4 with the multigrid cycle)
+ * or max_iter iterations.
  *   m_nodes : device float64 [n_nodes][3];  phi1 : device float64 [n_nodes]
  *   warm_start != 0: start from the free-node values phi1 holds
  *   iters, rel_res : receive the iterations done and |r|/|b| (may be NULL)

@@ -21,7 +21,8 @@ __all__ = [
     "setup_near_field", "near_radius", "near_field_info", "debug_copy_near",
     "near_pattern_host", "triangle_potential_host", "near_radius_host",
     "near_field_device_bytes", "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
-    "scalar_potential", "fem_energy", "fem_destroy", "Fem",
+    "scalar_potential", "fem_energy", "fem_destroy", "Fem", "fem_set_preconditioner",
+    "fem_amg_info", "PRECOND_JACOBI", "PRECOND_AMG",
 ]
 
 FP64, FP32 = 0, 1
@@ -126,6 +127,8 @@ def load_library():
                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double),
                                _VP],
         "slp_fem_dphi1_dn": [_VP, _VP, _VP, _VP],
+        "slp_fem_set_preconditioner": [_VP, ctypes.c_int32, _VP],
+        "slp_fem_amg_info": [_VP, ctypes.POINTER(ctypes.c_int32), _VP, _VP, ctypes.c_int32],
         "slp_scalar_potential": [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _VP],
         "slp_fem_destroy": [_VP],
@@ -505,6 +508,26 @@ def fem_solve_phi1(fem, m_nodes, phi1, tol=1e-10, max_iter=20000, warm_start=Fal
     return it.value, rr.value
 
 
+PRECOND_JACOBI, PRECOND_AMG = 0, 1
+
+
+def fem_set_preconditioner(fem, kind, stream=None):
+    """slp_fem_set_preconditioner: PRECOND_JACOBI or PRECOND_AMG (or "jacobi" / "amg")."""
+    kind = {"jacobi": PRECOND_JACOBI, "amg": PRECOND_AMG}.get(kind, kind)
+    _check(load_library().slp_fem_set_preconditioner(_VP(fem), int(kind), _stream_ptr(stream)))
+
+
+def fem_amg_info(fem):
+    """slp_fem_amg_info: [(rows, stored entries)] of the hierarchy, finest first."""
+    nl = ctypes.c_int32(0)
+    _check(load_library().slp_fem_amg_info(_VP(fem), ctypes.byref(nl), None, None, 0))
+    rows = np.zeros(nl.value, dtype=np.int64)
+    nnz = np.zeros(nl.value, dtype=np.int64)
+    _check(load_library().slp_fem_amg_info(_VP(fem), ctypes.byref(nl), rows.ctypes.data,
+                                           nnz.ctypes.data, nl.value))
+    return list(zip(rows.tolist(), nnz.tolist()))
+
+
 def fem_dphi1_dn(fem, phi1, dn, stream=None):
     n = fem_info(fem)["n_boundary_tris"]
     _check(load_library().slp_fem_dphi1_dn(_VP(fem), _dev_f64(phi1, phi1.numel(), "phi1"),
@@ -593,8 +616,10 @@ class Geometry:
 class Fem:
     """Owning wrapper around one slp_fem context."""
 
-    def __init__(self, nodes, tets, stream=None):
+    def __init__(self, nodes, tets, stream=None, precond="jacobi"):
         self.handle = fem_setup(nodes, tets, stream)
+        if precond != "jacobi":
+            fem_set_preconditioner(self.handle, precond, stream)
         self.info = fem_info(self.handle)
         self.boundary = fem_boundary(self.handle)
 

@@ -2,6 +2,7 @@
 // scalar potential phi = phi_1 + phi_2 (Alg. 1): mesh analysis, the free-node
 // stiffness matrix, and the orchestration of the device solve.
 #include "slp.h"
+#include "slp_amg.hpp"
 #include "slp_fem.hpp"
 #include "slp_internal.hpp"
 
@@ -10,6 +11,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cfloat>
 #include <cstdarg>
 #include <cstdio>
 #include <new>
@@ -62,6 +64,27 @@ struct slp_fem {
   double *epart = nullptr;                 // [ceil(T / 256) + 1] energy partials and sum
   double *h_pin = nullptr;                 // pinned [2] for the convergence check
   int32_t nblk = 1;
+  // preconditioner: SLP_PRECOND_JACOBI or SLP_PRECOND_AMG (the hierarchy below)
+  int32_t precond = SLP_PRECOND_JACOBI;
+  slp::HostCsr h_S;                        // S_ff on the host, for building the hierarchy
+  struct DevCsr {
+    int32_t *rp = nullptr, *ci = nullptr;
+    double *v = nullptr;
+    int64_t rows = 0, nnz = 0;
+    int32_t lanes = 1;
+  };
+  struct DevLevel {
+    DevCsr A, P, R;                        // A unused on the finest level (the sliced S_ff)
+    double *w = nullptr;                   // omega / a_ii
+    double *f = nullptr;                   // right-hand side (the CG residual on the finest level)
+    double *x = nullptr;                   // smoothed iterate
+    double *res = nullptr;                 // residual, then the level's result
+    int64_t n = 0;
+  };
+  std::vector<DevLevel> amg;
+  bool amg_built = false;
+  DevCsr amg_coarse;                       // dense inverse of the coarsest operator, as CSR
+  double *amg_fc = nullptr, *amg_ec = nullptr;
   int64_t bytes = 0;
   std::vector<void *> allocs;
   std::vector<int64_t> alloc_bytes;
@@ -256,14 +279,22 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
                   [](const std::pair<int32_t, double> &a, const std::pair<int32_t, double> &b) {
                     return a.first < b.first;
                   });
+        // an off-diagonal entry whose contributions cancel to within the
+        // rounding of their sum is zero (on lattices of Kuhn simplices half
+        // of the stored pattern) and is not stored
         int32_t n = 0;
         for (size_t k = 0; k < ent.size();) {
           size_t l = k;
-          double s = 0.0;
-          while (l < ent.size() && ent[l].first == ent[k].first) s += ent[l++].second;
-          pc[w].push_back(ent[k].first);
-          pv[w].push_back(s);
-          ++n;
+          double s = 0.0, sa = 0.0;
+          while (l < ent.size() && ent[l].first == ent[k].first) {
+            s += ent[l].second;
+            sa += std::fabs(ent[l++].second);
+          }
+          if (ent[k].first == f || std::fabs(s) > 16.0 * DBL_EPSILON * sa) {
+            pc[w].push_back(ent[k].first);
+            pv[w].push_back(s);
+            ++n;
+          }
           k = l;
         }
         rowlen[f] = n;
@@ -318,6 +349,10 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
     }
 
     F->n_free = Nf;
+    F->h_S.rows = F->h_S.cols = Nf;
+    F->h_S.rp = std::move(rp);
+    F->h_S.ci = std::move(ci);
+    F->h_S.v = std::move(val);
     F->n_btris = Mb;
     F->nnz = nnz;
     F->nblk = (int32_t)std::max<int64_t>(1, (Nf + slp::kFemThreads - 1) / slp::kFemThreads);
@@ -388,7 +423,126 @@ slp::PcgArgs pcg_args(slp_fem *F, const double *x0) {
   a.nf = F->n_free;
   a.n_nodes = F->n_nodes;
   a.nblk = F->nblk;
+  a.jacobi = F->precond == SLP_PRECOND_AMG ? 0 : 1;
   return a;
+}
+
+// Uploads a host CSR matrix; lanes per row: the power of two nearest above
+// the mean row length, from 1 to 64.
+int upload_csr(slp_fem *F, const slp::HostCsr &H, slp_fem::DevCsr &D, hipStream_t st) {
+  D.rows = H.rows;
+  D.nnz = (int64_t)H.ci.size();
+  if (F->alloc((void **)&D.rp, H.rp.size() * 4) != hipSuccess ||
+      F->alloc((void **)&D.ci, H.ci.size() * 4) != hipSuccess ||
+      F->alloc((void **)&D.v, H.v.size() * 8) != hipSuccess)
+    return fail(SLP_ENOMEM, "device allocation of the multigrid hierarchy failed");
+  FEM_TRY(hipMemcpyAsync(D.rp, H.rp.data(), H.rp.size() * 4, hipMemcpyHostToDevice, st));
+  if (D.nnz > 0) {
+    FEM_TRY(hipMemcpyAsync(D.ci, H.ci.data(), H.ci.size() * 4, hipMemcpyHostToDevice, st));
+    FEM_TRY(hipMemcpyAsync(D.v, H.v.data(), H.v.size() * 8, hipMemcpyHostToDevice, st));
+  }
+  const double mean = H.rows > 0 ? (double)D.nnz / (double)H.rows : 1.0;
+  D.lanes = 1;
+  while (D.lanes < 64 && D.lanes < mean) D.lanes *= 2;
+  return SLP_OK;
+}
+
+int upload_amg(slp_fem *F, slp::AmgHierarchy &h, hipStream_t st);
+
+// Builds the smoothed-aggregation hierarchy of S_ff on the host and moves it
+// to the device with the vectors of the cycle.
+int build_amg_impl(slp_fem *F, hipStream_t st) {
+  if (F->amg_built) return SLP_OK;
+  slp::AmgHierarchy h;
+  char err[256] = {0};
+  try {
+    if (!slp::build_amg(F->h_S, slp::AmgParams(), h, err, sizeof err))
+      return fail(SLP_EINVAL, "multigrid setup: %s", err);
+  } catch (const std::bad_alloc &) {
+    return fail(SLP_ENOMEM, "host allocation failed while building the multigrid hierarchy");
+  }
+  const int rc = upload_amg(F, h, st);
+  // the copies read the host hierarchy, which goes out of scope here
+  const hipError_t e = hipStreamSynchronize(st);
+  if (rc) return rc;
+  FEM_TRY(e);
+  F->amg_built = true;
+  return SLP_OK;
+}
+
+int upload_amg(slp_fem *F, slp::AmgHierarchy &h, hipStream_t st) {
+  const size_t nl = h.levels.size();
+  F->amg.assign(nl, slp_fem::DevLevel());
+  for (size_t l = 0; l < nl; ++l) {
+    slp_fem::DevLevel &d = F->amg[l];
+    const slp::AmgLevel &H = h.levels[l];
+    d.n = H.A.rows;
+    int rc;
+    if (l > 0 && (rc = upload_csr(F, H.A, d.A, st)) != SLP_OK) return rc;
+    if ((rc = upload_csr(F, H.P, d.P, st)) != SLP_OK) return rc;
+    if ((rc = upload_csr(F, H.R, d.R, st)) != SLP_OK) return rc;
+    const size_t vb = (size_t)d.n * 8;
+    if (F->alloc((void **)&d.w, vb) != hipSuccess || F->alloc((void **)&d.x, vb) != hipSuccess ||
+        F->alloc((void **)&d.res, vb) != hipSuccess ||
+        (l > 0 && F->alloc((void **)&d.f, vb) != hipSuccess))
+      return fail(SLP_ENOMEM, "device allocation of the multigrid vectors failed");
+    if (l == 0) d.f = F->r;
+    FEM_TRY(hipMemcpyAsync(d.w, H.w.data(), vb, hipMemcpyHostToDevice, st));
+  }
+  slp::HostCsr C;
+  C.rows = C.cols = h.nc;
+  C.rp.resize(h.nc + 1);
+  C.ci.resize(h.nc * h.nc);
+  for (int64_t i = 0; i <= h.nc; ++i) C.rp[i] = (int32_t)(i * h.nc);
+  for (int64_t k = 0; k < h.nc * h.nc; ++k) C.ci[k] = (int32_t)(k % h.nc);
+  C.v = std::move(h.coarse_inv);
+  int rc = upload_csr(F, C, F->amg_coarse, st);
+  if (rc != SLP_OK) return rc;
+  if (nl > 0 && (F->alloc((void **)&F->amg_fc, (size_t)h.nc * 8) != hipSuccess ||
+                 F->alloc((void **)&F->amg_ec, (size_t)h.nc * 8) != hipSuccess))
+    return fail(SLP_ENOMEM, "device allocation of the multigrid vectors failed");
+  return SLP_OK;
+}
+
+// z = B r for the V(1,1) cycle B (damped-Jacobi pre- and post-smoothing,
+// R = P^T, exact coarsest solve), and the partial sums of r.z into `slot`.
+int vcycle(slp_fem *F, const slp::PcgArgs &a, int32_t slot, hipStream_t st) {
+  const int nl = (int)F->amg.size();
+  slp::AmgOp op{};
+  if (nl == 0) {   // the whole system is the coarsest: z = S_ff^-1 r
+    const slp_fem::DevCsr &C = F->amg_coarse;
+    op = slp::AmgOp{C.rp, C.ci, C.v, F->r, nullptr, nullptr, F->z, nullptr, C.rows};
+    FEM_TRY(slp::launch_amg_csr(op, slp::kAmgRestrict, C.lanes, st));
+    FEM_TRY(slp::launch_amg_dot(a, slot, st));
+    return SLP_OK;
+  }
+  for (int l = 0; l < nl; ++l) {
+    slp_fem::DevLevel &d = F->amg[l];
+    op = slp::AmgOp{d.A.rp, d.A.ci, d.A.v, d.f, d.w, d.f, d.x, d.res, d.n};
+    if (l == 0)
+      FEM_TRY(slp::launch_amg_fine(a, op, slp::kAmgPre, slot, st));
+    else
+      FEM_TRY(slp::launch_amg_csr(op, slp::kAmgPre, d.A.lanes, st));
+    double *fnext = l + 1 < nl ? F->amg[l + 1].f : F->amg_fc;
+    op = slp::AmgOp{d.R.rp, d.R.ci, d.R.v, d.res, nullptr, nullptr, fnext, nullptr, d.R.rows};
+    FEM_TRY(slp::launch_amg_csr(op, slp::kAmgRestrict, d.R.lanes, st));
+  }
+  const slp_fem::DevCsr &C = F->amg_coarse;
+  op = slp::AmgOp{C.rp, C.ci, C.v, F->amg_fc, nullptr, nullptr, F->amg_ec, nullptr, C.rows};
+  FEM_TRY(slp::launch_amg_csr(op, slp::kAmgRestrict, C.lanes, st));
+  for (int l = nl - 1; l >= 0; --l) {
+    slp_fem::DevLevel &d = F->amg[l];
+    const double *e = l + 1 < nl ? F->amg[l + 1].res : F->amg_ec;
+    op = slp::AmgOp{d.P.rp, d.P.ci, d.P.v, e, nullptr, d.x, d.x, nullptr, d.n};
+    FEM_TRY(slp::launch_amg_csr(op, slp::kAmgProlong, d.P.lanes, st));
+    double *out = l == 0 ? F->z : d.res;
+    op = slp::AmgOp{d.A.rp, d.A.ci, d.A.v, d.x, d.w, d.f, out, nullptr, d.n};
+    if (l == 0)
+      FEM_TRY(slp::launch_amg_fine(a, op, slp::kAmgPost, slot, st));
+    else
+      FEM_TRY(slp::launch_amg_csr(op, slp::kAmgPost, d.A.lanes, st));
+  }
+  return SLP_OK;
 }
 
 int solve_impl(slp_fem *F, const double *m, double *phi1, double tol, int32_t max_iter,
@@ -418,16 +572,28 @@ int solve_impl(slp_fem *F, const double *m, double *phi1, double tol, int32_t ma
     la.nf = F->n_free;
     la.nt = F->n_tets;
     FEM_TRY(slp::launch_fem_load(la, st));
+    const bool amg = F->precond == SLP_PRECOND_AMG;
     const slp::PcgArgs a = pcg_args(F, warm ? phi1 : nullptr);
     FEM_TRY(slp::launch_pcg_start(a, F->free_node, st));
+    if (amg) {
+      const int rc = vcycle(F, a, 1, st);
+      if (rc) return rc;
+    }
     FEM_TRY(slp::launch_pcg_reduce(a, 4, 0, st));
     // the residual of the start is the first check: r.r from the start kernel
-    // is not formed, so check after the first block of iterations
-    const int32_t every = 16;
+    // is not formed, so check after the first block of iterations (shorter
+    // with the multigrid cycle, which converges in tens of iterations)
+    const int32_t every = amg ? 4 : 16;
     double bb = -1.0;
     for (it = 0; it < max_iter;) {
       const int32_t n = std::min(every, max_iter - it);
-      for (int32_t k = 0; k < n; ++k, ++it) FEM_TRY(slp::launch_pcg_iteration(a, it, st));
+      for (int32_t k = 0; k < n; ++k, ++it) {
+        FEM_TRY(slp::launch_pcg_iteration(a, it, st));
+        if (amg) {
+          const int rc = vcycle(F, a, 1 + ((it + 1) & 1), st);
+          if (rc) return rc;
+        }
+      }
       FEM_TRY(slp::launch_pcg_reduce(a, 3, it, st));
       FEM_TRY(hipMemcpyAsync(F->h_pin, F->hist, 8, hipMemcpyDeviceToHost, st));
       FEM_TRY(hipMemcpyAsync(F->h_pin + 1, F->hist + it, 8, hipMemcpyDeviceToHost, st));
@@ -479,6 +645,32 @@ int slp_fem_solve_phi1(slp_fem *F, const double *m_nodes, double *phi1, double t
                        void *stream) {
   return solve_impl(F, m_nodes, phi1, tol, max_iter, warm_start, iters, rel_res,
                     static_cast<hipStream_t>(stream));
+}
+
+int slp_fem_set_preconditioner(slp_fem *F, int32_t kind, void *stream) {
+  if (!F) return fail(SLP_EINVAL, "NULL context");
+  if (kind != SLP_PRECOND_JACOBI && kind != SLP_PRECOND_AMG)
+    return fail(SLP_EINVAL, "unknown preconditioner %d", (int)kind);
+  if (kind == SLP_PRECOND_AMG && F->n_free > 0) {
+    const int rc = build_amg_impl(F, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+  }
+  F->precond = kind;
+  return SLP_OK;
+}
+
+int slp_fem_amg_info(const slp_fem *F, int32_t *n_levels, int64_t *rows, int64_t *nnz, int32_t cap) {
+  if (!F || !n_levels) return fail(SLP_EINVAL, "NULL argument");
+  if (!F->amg_built) return fail(SLP_EINVAL, "no multigrid hierarchy (select SLP_PRECOND_AMG first)");
+  const int32_t nl = (int32_t)F->amg.size() + 1;
+  *n_levels = nl;
+  if (cap < nl && (rows || nnz)) return fail(SLP_EINVAL, "cap %d < %d levels", (int)cap, (int)nl);
+  for (int32_t l = 0; l < nl; ++l) {
+    const bool last = l + 1 == nl;
+    if (rows) rows[l] = last ? F->amg_coarse.rows : F->amg[l].n;
+    if (nnz) nnz[l] = last ? F->amg_coarse.nnz : (l == 0 ? F->nnz : F->amg[l].A.nnz);
+  }
+  return SLP_OK;
 }
 
 int slp_fem_dphi1_dn(slp_fem *F, const double *phi1, double *dphi1_dn, void *stream) {

@@ -1,7 +1,8 @@
 // Device code of the Dirichlet problem for phi_1 (Sec. 2.1, eq. poisson): the
-// load vector, Jacobi-preconditioned conjugate gradients on the free-node
-// system, the normal derivative on the boundary triangles, and the final sum
-// phi = phi_1 + phi_2 of Alg. 1. FP64 throughout.
+// load vector, preconditioned conjugate gradients on the free-node system
+// (Jacobi, or a smoothed-aggregation multigrid V-cycle), the normal derivative
+// on the boundary triangles, and the final sum phi = phi_1 + phi_2 of Alg. 1.
+// FP64 throughout.
 #include "slp_fem.hpp"
 
 namespace slp {
@@ -74,17 +75,19 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_start(PcgArgs a,
         ri -= a.val[e] * a.x0[free_node[a.ci[e]]];
       }
     }
-    const double zi = a.dinv[i] * ri;
     a.x[i] = xi;
     a.r[i] = ri;
-    a.z[i] = zi;
-    rz = ri * zi;
+    if (a.jacobi) {
+      const double zi = a.dinv[i] * ri;
+      a.z[i] = zi;
+      rz = ri * zi;
+    }
     bb = a.b[i] * a.b[i];
   }
   rz = block_sum(rz);
   bb = block_sum(bb);
   if (threadIdx.x == 0) {
-    a.part[1 * a.nblk + blockIdx.x] = rz;
+    if (a.jacobi) a.part[1 * a.nblk + blockIdx.x] = rz;
     a.part[4 * a.nblk + blockIdx.x] = bb;
   }
 }
@@ -122,7 +125,8 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_spmv(PcgArgs a, int32_t it)
   if (threadIdx.x == 0) a.part[blockIdx.x] = pq;
 }
 
-// alpha = r.z / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partial r.z, r.r.
+// alpha = r.z / p.q; x += alpha p; r -= alpha q; partial r.r; with the Jacobi
+// preconditioner also z = D^-1 r and partial r.z.
 __global__ __launch_bounds__(kFemThreads) void k_pcg_update(PcgArgs a, int32_t it) {
   const double pq = sum_parts(a.part, a.nblk);
   const double rz = sum_parts(a.part + (1 + (it & 1)) * a.nblk, a.nblk);
@@ -133,18 +137,90 @@ __global__ __launch_bounds__(kFemThreads) void k_pcg_update(PcgArgs a, int32_t i
   if (i < a.nf) {
     a.x[i] += alpha * p[i];
     const double ri = a.r[i] - alpha * a.q[i];
-    const double zi = a.dinv[i] * ri;
     a.r[i] = ri;
-    a.z[i] = zi;
-    rzn = ri * zi;
+    if (a.jacobi) {
+      const double zi = a.dinv[i] * ri;
+      a.z[i] = zi;
+      rzn = ri * zi;
+    }
     rr = ri * ri;
   }
   rzn = block_sum(rzn);
   rr = block_sum(rr);
   if (threadIdx.x == 0) {
-    a.part[(1 + ((it + 1) & 1)) * a.nblk + blockIdx.x] = rzn;
+    if (a.jacobi) a.part[(1 + ((it + 1) & 1)) * a.nblk + blockIdx.x] = rzn;
     a.part[3 * a.nblk + blockIdx.x] = rr;
   }
+}
+
+// Multigrid cycle on the finest level: the sliced S_ff, one thread per row
+// (modes pre and post of AmgOp).
+template <int MODE>
+__global__ __launch_bounds__(kFemThreads) void k_amg_fine(PcgArgs a, AmgOp op, int32_t slot) {
+  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  double rz = 0.0;
+  if (i < a.nf) {
+    const int64_t sl = i >> 6;
+    const int64_t base = a.sptr[sl] + (i & 63);
+    const int32_t w = (a.sptr[sl + 1] - a.sptr[sl]) >> 6;
+    double t = 0.0;
+    for (int32_t k = 0; k < w; ++k) {
+      const int32_t j = a.ci[base + 64 * k];
+      const double vj = MODE == kAmgPre ? op.w[j] * op.in[j] : op.in[j];
+      t += a.val[base + 64 * k] * vj;
+    }
+    const double fi = op.f[i];
+    if (MODE == kAmgPre) {
+      op.o1[i] = op.w[i] * fi;
+      op.o2[i] = fi - t;
+    } else {
+      const double zi = op.in[i] + op.w[i] * (fi - t);
+      op.o1[i] = zi;
+      rz = zi * fi;
+    }
+  }
+  if (MODE == kAmgPost) {
+    rz = block_sum(rz);
+    if (threadIdx.x == 0) a.part[slot * a.nblk + blockIdx.x] = rz;
+  }
+}
+
+// Multigrid cycle on a CSR operator: L lanes per row, a row's lanes in one
+// wave, their sum by butterfly shuffles.
+template <int L, int MODE>
+__global__ __launch_bounds__(kFemThreads) void k_amg_csr(AmgOp op) {
+  const int64_t row = ((int64_t)blockIdx.x * kFemThreads + threadIdx.x) / L;
+  const int lane = threadIdx.x & (L - 1);
+  double t = 0.0;
+  if (row < op.n) {
+    const int32_t e1 = op.rp[row + 1];
+    for (int32_t e = op.rp[row] + lane; e < e1; e += L) {
+      const int32_t j = op.ci[e];
+      t += op.val[e] * (MODE == kAmgPre ? op.w[j] * op.in[j] : op.in[j]);
+    }
+  }
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, L);
+  if (row >= op.n || lane != 0) return;
+  if (MODE == kAmgPre) {
+    const double fi = op.f[row];
+    op.o1[row] = op.w[row] * fi;
+    op.o2[row] = fi - t;
+  } else if (MODE == kAmgPost) {
+    const double yi = op.in[row];
+    op.o1[row] = yi + op.w[row] * (op.f[row] - t);
+  } else if (MODE == kAmgRestrict) {
+    op.o1[row] = t;
+  } else {
+    op.o1[row] = op.f[row] + t;
+  }
+}
+
+__global__ __launch_bounds__(kFemThreads) void k_amg_dot(PcgArgs a, int32_t slot) {
+  const int64_t i = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
+  double rz = i < a.nf ? a.r[i] * a.z[i] : 0.0;
+  rz = block_sum(rz);
+  if (threadIdx.x == 0) a.part[slot * a.nblk + blockIdx.x] = rz;
 }
 
 __global__ __launch_bounds__(kFemThreads) void k_pcg_reduce(PcgArgs a, int32_t which,
@@ -239,6 +315,53 @@ hipError_t launch_pcg_start(const PcgArgs &a, const int32_t *free_node, hipStrea
 hipError_t launch_pcg_iteration(const PcgArgs &a, int32_t it, hipStream_t s) {
   hipLaunchKernelGGL(k_pcg_spmv, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
   hipLaunchKernelGGL(k_pcg_update, dim3(a.nblk), dim3(kFemThreads), 0, s, a, it);
+  return hipGetLastError();
+}
+
+namespace {
+template <int L>
+void launch_csr_lanes(const AmgOp &op, int mode, hipStream_t s) {
+  const int64_t threads = op.n * L;
+  const dim3 grid((unsigned)((threads + kFemThreads - 1) / kFemThreads));
+  switch (mode) {
+    case kAmgPre: hipLaunchKernelGGL((k_amg_csr<L, kAmgPre>), grid, dim3(kFemThreads), 0, s, op); break;
+    case kAmgPost: hipLaunchKernelGGL((k_amg_csr<L, kAmgPost>), grid, dim3(kFemThreads), 0, s, op); break;
+    case kAmgRestrict:
+      hipLaunchKernelGGL((k_amg_csr<L, kAmgRestrict>), grid, dim3(kFemThreads), 0, s, op);
+      break;
+    default: hipLaunchKernelGGL((k_amg_csr<L, kAmgProlong>), grid, dim3(kFemThreads), 0, s, op); break;
+  }
+}
+}  // namespace
+
+hipError_t launch_amg_csr(const AmgOp &op, int mode, int lanes, hipStream_t s) {
+  if (op.n <= 0) return hipSuccess;
+  switch (lanes) {
+    case 1: launch_csr_lanes<1>(op, mode, s); break;
+    case 2: launch_csr_lanes<2>(op, mode, s); break;
+    case 4: launch_csr_lanes<4>(op, mode, s); break;
+    case 8: launch_csr_lanes<8>(op, mode, s); break;
+    case 16: launch_csr_lanes<16>(op, mode, s); break;
+    case 32: launch_csr_lanes<32>(op, mode, s); break;
+    case 64: launch_csr_lanes<64>(op, mode, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_amg_fine(const PcgArgs &a, const AmgOp &op, int mode, int32_t slot,
+                           hipStream_t s) {
+  if (mode == kAmgPre)
+    hipLaunchKernelGGL(k_amg_fine<kAmgPre>, dim3(a.nblk), dim3(kFemThreads), 0, s, a, op, slot);
+  else if (mode == kAmgPost)
+    hipLaunchKernelGGL(k_amg_fine<kAmgPost>, dim3(a.nblk), dim3(kFemThreads), 0, s, a, op, slot);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_amg_dot(const PcgArgs &a, int32_t slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_amg_dot, dim3(a.nblk), dim3(kFemThreads), 0, s, a, slot);
   return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ struct FemLoadArgs {
 };
 hipError_t launch_fem_load(const FemLoadArgs &a, hipStream_t s);
 
-// Preconditioned conjugate gradients (Jacobi) on S_ff x = b. Partial sums
+// Preconditioned conjugate gradients on S_ff x = b. Partial sums
 // of the dot products are written per workgroup; every consumer sums them.
 // S_ff is stored sliced: rows in slices of 64, slice s holding its entries
 // column by column (entry k of row 64 s + l at sptr[s] + 64 k + l), slice
@@ -45,6 +45,8 @@ struct PcgArgs {
   const double *x0;         // warm start: phi_1 of the previous solve [N], or null
   int64_t nf, n_nodes;
   int32_t nblk;
+  int32_t jacobi;           // 1: z = D^-1 r in the start and update kernels; 0: the
+                            // multigrid cycle forms z and the partial r.z instead
 };
 // x = x0 (or 0), r = b - S x, z = D^-1 r; partial r.z and b.b.
 hipError_t launch_pcg_start(const PcgArgs &a, const int32_t *free_node, hipStream_t s);
@@ -53,6 +55,31 @@ hipError_t launch_pcg_start(const PcgArgs &a, const int32_t *free_node, hipStrea
 // (16 lanes per row) with p.q; (2) x, r, z updates with r.z and r.r. `it`
 // selects the parity slots of r.z and of p.
 hipError_t launch_pcg_iteration(const PcgArgs &a, int32_t it, hipStream_t s);
+// One operator application of the multigrid cycle. Matrices above the finest
+// level are CSR (rp, ci, val) with `lanes` threads per row; the finest level's
+// operator is the sliced S_ff of PcgArgs, one thread per row. Modes, with
+// (M v)_i = sum_j M_ij v_j:
+//   pre      : o1 = w f,  o2 = f - M (w f)      (one damped-Jacobi step from 0 and
+//              its residual; `in` = f)
+//   post     : o1 = in + w (f - M in)           (damped-Jacobi step from `in`)
+//   restrict : o1 = M in                        (also the dense coarse inverse)
+//   prolong  : o1 = f + M in                    (o1 may equal f)
+// On the finest level `post` also writes the per-workgroup partials of
+// o1 . f into part[slot][nblk] (the r.z of the next direction).
+enum AmgMode { kAmgPre = 0, kAmgPost = 1, kAmgRestrict = 2, kAmgProlong = 3 };
+struct AmgOp {
+  const int32_t *rp, *ci;
+  const double *val;
+  const double *in, *w, *f;
+  double *o1, *o2;
+  int64_t n;
+};
+hipError_t launch_amg_csr(const AmgOp &op, int mode, int lanes, hipStream_t s);
+hipError_t launch_amg_fine(const PcgArgs &a, const AmgOp &op, int mode, int32_t slot,
+                           hipStream_t s);
+// part[slot][nblk] = per-workgroup partials of r . z (cycles without a finest smoothing level).
+hipError_t launch_amg_dot(const PcgArgs &a, int32_t slot, hipStream_t s);
+
 // hist[slot] = sum of the partial sums `which` (3: r.r, 4: b.b); one workgroup.
 hipError_t launch_pcg_reduce(const PcgArgs &a, int32_t which, int32_t slot, hipStream_t s);
 
