@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 PEAK = {  # published MI355X figures
     "hbm_GBps": 8000.0,
     "f64_vector_TFLOPs": 78.6,
+    "f64_matrix_TFLOPs": 78.6,
     "f32_vector_TFLOPs": 157.3,
 }
 
@@ -98,7 +99,9 @@ def algorithmic_units(stage, info, m, esz):
     Kx, Ky, Kz = n[0] // 2 + 1, n[1] + 1, n[2] + 1
     c = 2 * esz
     if stage == "spread_bins":
-        return info["n_src"] * (2.0 * w ** 3 + w ** 2), "flop", "alu"
+        # FP64 with 2m = 16 accumulates each run on the matrix cores
+        bound = "mfma" if esz == 8 and w == 16 else "alu"
+        return info["n_src"] * (2.0 * w ** 3 + w ** 2), "flop", bound
     if stage == "spread_reduce":
         return R[0] * R[1] * R[2] * esz, "byte", "hbm"
     if stage == "interp":
@@ -405,6 +408,8 @@ def potential(args):
     else:
         achieved = amount / dur_s / 1e12
         peak = PEAK["f64_vector_TFLOPs"] if prec == slp.FP64 else PEAK["f32_vector_TFLOPs"]
+        if bound == "mfma":
+            peak = PEAK["f64_matrix_TFLOPs"]
         runit = "TFLOP/s"
     roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,
                 "frac": round(achieved / peak, 5), "traffic": None, "kernel": dom,
@@ -602,6 +607,8 @@ def main():
     else:
         achieved = amount / dur_s / 1e12
         peak = PEAK["f64_vector_TFLOPs"] if prec == slp.FP64 else PEAK["f32_vector_TFLOPs"]
+        if bound == "mfma":
+            peak = PEAK["f64_matrix_TFLOPs"]
         runit = "TFLOP/s"
     roofline = None if cnt == 0 else {
         "bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": runit,

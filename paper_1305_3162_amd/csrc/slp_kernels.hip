@@ -21,6 +21,9 @@ struct Cplx<float> { using type = float2; };
 template <>
 struct Cplx<double> { using type = double2; };
 
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
@@ -60,6 +63,15 @@ __device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
 // fast-Gaussian-gridding recurrence w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b)
 // (two exponentials per source and axis), Kaiser-Bessel factors directly, one
 // stencil point per lane.
+// With FP64 and 2m = 16 a run is instead accumulated by the matrix cores: for
+// the sources k of a run (cell fixed, so the stencil offsets are the same),
+// the block update is sum_k fz_k[dz] fy_k[dy] fx_k[dx], for every dy a
+// 16 x K by K x 16 product D_dy[dz][dx] += sum_k (fz_k[dz] fy_k[dy]) fx_k[dx]
+// (fx carries the charge). One v_mfma_f64_16x16x4f64 takes four sources; a
+// lane supplies A[dz = lane % 16][k = lane / 16] and B[k = lane / 16][dx =
+// lane % 16] and holds D[dz = 4 r + lane / 16][dx = lane % 16] in its
+// register r, so the sixteen dy tiles are 64 FP64 accumulators per lane, as in
+// the vector form. Missing sources of the last group of four enter as zeros.
 // Phase B (one workgroup per region tile): every cell sums the blocks of the
 // segments of the neighbouring tiles that cover it, in a fixed order, and
 // writes the grid.
@@ -82,6 +94,10 @@ struct SpreadShape {
   static constexpr int WST = 3 * W + 1;                // LDS stride of one source's factors
   static constexpr int CH = kSpreadChunk;              // sources staged per block chunk
   static constexpr int PER = (4 * CH + THREADS - 1) / THREADS;
+  // FP64 with 2m = 16: a run's update goes to the matrix cores (see
+  // k_spread_bins); the factors of a source then sit 16-byte aligned
+  static constexpr bool MX = sizeof(T) == 8 && W == 16;
+  static constexpr int FST = MX ? 3 * W + 2 : WST;     // LDS stride of one source's factors
 };
 
 int64_t pad_cells(int m) {
@@ -92,7 +108,7 @@ int64_t pad_cells(int m) {
 int spread_units_per_cu(int m, bool fp64) {
   auto lds = [](auto shape, size_t esz) {
     using S = decltype(shape);
-    return (size_t)S::P3 * 8 + (size_t)S::WAVES * S::SBW * S::WST * esz +
+    return (size_t)S::P3 * 8 + (size_t)S::WAVES * S::SBW * S::FST * esz +
            4 * (size_t)S::CH * esz + (size_t)S::CH * 4;
   };
   size_t b = 0;
@@ -144,8 +160,9 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   // The block is accumulated in FP64 in both precisions: LDS FP64 atomic adds
   // are native and fast on gfx950, FP32 LDS atomic adds measured several times
   // slower; the block is stored in T.
+  constexpr int FST = S::FST;
   __shared__ double pad[S::P3];
-  __shared__ T wts[S::WAVES * S::SBW * S::WST];
+  __shared__ __attribute__((aligned(16))) T wts[S::WAVES * S::SBW * FST];
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
 
@@ -153,7 +170,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   const double *dens = ptrs.dens[blockIdx.y];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  T *ww = wts + wave * S::SBW * S::WST;
+  T *ww = wts + wave * S::SBW * FST;
   int dxp[NP], dyp[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
@@ -199,11 +216,19 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
         const int rec = rrec[r];
         const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
         const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
-        T acc[NP][W];
+        // vector form: acc[p][j] for column lane + 64 p and dz = j; matrix
+        // form: macc[dy][r] for dx = lane % 16, dz = 4 r + lane / 16
+        T acc[S::MX ? 1 : NP][S::MX ? 1 : W];
+        dbl4 macc[S::MX ? W : 1];
+        if constexpr (S::MX) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+          for (int t = 0; t < W; ++t) macc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        } else {
 #pragma unroll
-          for (int j = 0; j < W; ++j) acc[p][j] = T(0);
+          for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc[p][j] = T(0);
+        }
         for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
           const int n = min(S::SBW, cnt - c0);
           if (a.window == 0) {
@@ -215,7 +240,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
               T w = wexp(-f * f * a.inv_b);
               T rr = wexp((T(2) * f - T(1)) * a.inv_b);
               if (ax == 0) w *= src[3][si];
-              T *dst = ww + sl * S::WST + ax * W;
+              T *dst = ww + sl * FST + ax * W;
 #pragma unroll
               for (int j = 0; j < W; ++j) {
                 dst[j] = w;
@@ -231,31 +256,59 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
               const int si = off + c0 + sl;
               T w = kb_weight<T>(src[ax][si] + T(M - 1 - j), T(M), a.kb_b, a.kb_inv_norm);
               if (ax == 0) w *= src[3][si];
-              ww[sl * S::WST + ax * W + j] = w;
+              ww[sl * FST + ax * W + j] = w;
             }
           }
           wave_sync();
-          for (int sl = 0; sl < n; ++sl) {
-            const T *f3 = ww + sl * S::WST;
-            T wz[W];
+          if constexpr (S::MX) {
+            const int lk = lane >> 4, li = lane & 15;
+            for (int g = 0; g < n; g += 4) {
+              const int sl = g + lk;
+              const bool ok = sl < n;
+              // slot 0 holds this batch's factors, so the loads stay finite
+              const double *f3 = reinterpret_cast<const double *>(ww) + (ok ? sl : 0) * FST;
+              const double bx = ok ? f3[li] : 0.0;
+              const double az = ok ? f3[2 * W + li] : 0.0;
+              const dbl2 *fy2 = reinterpret_cast<const dbl2 *>(f3 + W);
 #pragma unroll
-            for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
+              for (int t2 = 0; t2 < W / 2; ++t2) {
+                const dbl2 fy = fy2[t2];
+                macc[2 * t2] = __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.x, bx, macc[2 * t2], 0, 0, 0);
+                macc[2 * t2 + 1] =
+                    __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.y, bx, macc[2 * t2 + 1], 0, 0, 0);
+              }
+            }
+          } else {
+            for (int sl = 0; sl < n; ++sl) {
+              const T *f3 = ww + sl * FST;
+              T wz[W];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-              if (p == NP - 1 && !last_act) continue;
-              const T pw = f3[dxp[p]] * f3[W + dyp[p]];
+              for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
 #pragma unroll
-              for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
+              for (int p = 0; p < NP; ++p) {
+                if (p == NP - 1 && !last_act) continue;
+                const T pw = f3[dxp[p]] * f3[W + dyp[p]];
+#pragma unroll
+                for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
+              }
             }
           }
           wave_sync();
         }
+        if constexpr (S::MX) {
+          double *base = pad + (cz + (lane >> 4)) * PD * PD + cy * PD + cx + (lane & 15);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          if (p == NP - 1 && !last_act) continue;
-          double *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+          for (int t = 0; t < W; ++t)
 #pragma unroll
-          for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[p][j]);
+            for (int q = 0; q < 4; ++q) atomicAdd(base + 4 * q * PD * PD + t * PD, macc[t][q]);
+        } else {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            if (p == NP - 1 && !last_act) continue;
+            double *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+#pragma unroll
+            for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[p][j]);
+          }
         }
       }
     }
