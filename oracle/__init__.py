@@ -29,8 +29,11 @@ eq. (smooth_phi). Modules:
   fem        the P1 Dirichlet problem for phi_1 (Sec. 2, 2.1), its normal
              derivative on the boundary triangles, and the complete scalar
              potential phi_1 + phi_2 at every node (Alg. 1)
+  integrated the paper's integrated-window gridding (Sec. 3.1, eq. gridding2,
+             the matrix A): the window integrated over each triangle, and the
+             closed-form Fourier transform of a triangle that pins it
 
 Parity pins live in tests/test_oracle_*.py. Functions without an independent
 pin are marked "parity unpinned" in their docstrings.
 """
-from . import geometry, kernel, direct, nufft, nearfield, fem  # noqa: F401
+from . import geometry, kernel, direct, nufft, nearfield, fem, integrated  # noqa: F401
