@@ -271,6 +271,30 @@ int slp_near_field_device_bytes(const double *nodes, int64_t n_nodes, const int3
 int slp_near_field_info(const slp_geom *g, double *eps, int64_t *nnz, double *r_max,
                         int64_t *stored, int32_t *packed);
 
+/* Integrated-window gridding (Sec. 3.1, eq. gridding2 and the matrix A of
+ * eq. A): the paper's own gridding, in which the window is integrated over
+ * each triangle in the setup phase instead of being sampled at the three
+ * quadrature points, A_rj = int_{S_j} Psi(r - t(y)) dsigma(y) over the index
+ * box of S_j (eq. indexset2: floor(t_min) - m + 1 .. floor(t_max) + m per
+ * axis). The integrals are taken on the device with the collapsed Gauss rule
+ * (xi_1 = u (1 - v), xi_2 = u v, `order` Gauss-Legendre points in u and in v)
+ * and stored by grid cell; every evaluation then grids a_r = sum_j A_rj g_j,
+ * g_j the mean of the density's three values on S_j (the element density
+ * of the paper's P1 ansatz), instead of gridding the point sources. The rest
+ * of the evaluation is unchanged.
+ *   order : 1..16 Gauss points per direction (8 resolves the window to
+ *           rounding on meshes whose triangles are about a grid cell); 0
+ *           returns to the point gridding
+ * Synchronises `stream` and the device. Errors: EINVAL for an order out of
+ * range, a triangle whose index box leaves the grid region (the nodes must be
+ * among the evaluation points), a context with a near field or with captured
+ * evaluations (the two do not combine with it); ENOMEM. */
+int slp_setup_integrated_gridding(slp_geom *g, int32_t order, void *stream);
+/* order (0 = off), stored window integrals (nnz), entries including the row
+ * padding and whether the columns are packed (any pointer may be NULL). */
+int slp_integrated_gridding_info(const slp_geom *g, int32_t *order, int64_t *nnz, int64_t *stored,
+                                 int32_t *packed);
+
 /* Copy the near-field matrix to host memory (synchronises the device):
  * rowptr int64 [n_targets + 1], cols int32 [nnz] (may be NULL), vals float64
  * [nnz] (may be NULL; FP32 values converted). cap = room in cols / vals;

@@ -22,7 +22,8 @@ __all__ = [
     "near_pattern_host", "triangle_potential_host", "near_radius_host",
     "near_field_device_bytes", "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
     "scalar_potential", "fem_energy", "fem_destroy", "Fem", "fem_set_preconditioner",
-    "fem_amg_info", "PRECOND_JACOBI", "PRECOND_AMG",
+    "fem_amg_info", "PRECOND_JACOBI", "PRECOND_AMG", "setup_integrated_gridding",
+    "integrated_gridding_info",
 ]
 
 FP64, FP32 = 0, 1
@@ -128,6 +129,11 @@ def load_library():
                                _VP],
         "slp_fem_dphi1_dn": [_VP, _VP, _VP, _VP],
         "slp_fem_set_preconditioner": [_VP, ctypes.c_int32, _VP],
+        "slp_setup_integrated_gridding": [_VP, ctypes.c_int32, _VP],
+        "slp_integrated_gridding_info": [_VP, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32)],
         "slp_fem_amg_info": [_VP, ctypes.POINTER(ctypes.c_int32), _VP, _VP, ctypes.c_int32],
         "slp_scalar_potential": [_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _VP],
@@ -508,6 +514,19 @@ def fem_solve_phi1(fem, m_nodes, phi1, tol=1e-10, max_iter=20000, warm_start=Fal
     return it.value, rr.value
 
 
+def setup_integrated_gridding(geom, order=8, stream=None):
+    """slp_setup_integrated_gridding: grid the window integrated over each
+    triangle (order Gauss points per direction; 0 = point gridding)."""
+    _check(load_library().slp_setup_integrated_gridding(_VP(geom), int(order), _stream_ptr(stream)))
+
+
+def integrated_gridding_info(geom):
+    o, n, st, pk = ctypes.c_int32(0), ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(load_library().slp_integrated_gridding_info(_VP(geom), ctypes.byref(o), ctypes.byref(n),
+                                                       ctypes.byref(st), ctypes.byref(pk)))
+    return {"order": o.value, "nnz": n.value, "stored": st.value, "packed": bool(pk.value)}
+
+
 PRECOND_JACOBI, PRECOND_AMG = 0, 1
 
 
@@ -593,6 +612,12 @@ class Geometry:
 
     def near_field_info(self):
         return near_field_info(self.handle)
+
+    def setup_integrated_gridding(self, order=8, stream=None):
+        setup_integrated_gridding(self.handle, order, stream)
+
+    def integrated_gridding_info(self):
+        return integrated_gridding_info(self.handle)
 
     def solve(self, dens, stream=None):
         import torch

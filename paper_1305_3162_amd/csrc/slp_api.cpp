@@ -156,6 +156,17 @@ struct slp_geom {
   std::vector<int64_t> nf_rows;  // host: pairs per row (to strip the padding on copies)
   void *nf_vals = nullptr;
   double *nf_gbar = nullptr;     // [cap][M] element means of the densities
+  // integrated-window gridding (slp_setup_integrated_gridding): the window
+  // integrated over each triangle, by cell of the region, in the near-field
+  // layout; when set, a = A gbar replaces the gridding of the point sources
+  int32_t iw_order = 0;          // Gauss points per direction of the rule; 0 = off
+  int64_t iw_nnz = 0, iw_stored = 0, iw_rows = 0;
+  int64_t *iw_rowptr = nullptr;
+  int32_t *iw_cols = nullptr, *iw_bases = nullptr;
+  uint16_t *iw_offs = nullptr;
+  bool iw_packed = false;
+  void *iw_vals = nullptr;
+  double *iw_gbar = nullptr;     // [cap][M]
   int64_t bytes = 0;
   std::vector<void *> allocs;
   // captured evaluations, one per batch size (replayed when use_graph is set)
@@ -308,12 +319,13 @@ int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
   G->drop_graphs();                    // they hold the old buffer addresses
-  if (G->nf_gbar) {                    // element means of the near field, nb items
+  for (double **gb : {&G->nf_gbar, &G->iw_gbar}) {   // element means, nb items
+    if (!*gb) continue;
     void *q = nullptr;
     if (G->alloc(&q, (size_t)G->n_tris * 8 * nb) != hipSuccess)
-      return fail(SLP_ENOMEM, "near-field buffer for %d items: allocation failed", nb);
-    G->release(G->nf_gbar);
-    G->nf_gbar = static_cast<double *>(q);
+      return fail(SLP_ENOMEM, "element-mean buffer for %d items: allocation failed", nb);
+    G->release(*gb);
+    *gb = static_cast<double *>(q);
   }
   void **bufs[5] = {&G->scratch, &G->grid_a, &G->S1, &G->S2, &G->grid_g};
   const size_t e = G->esz();
@@ -395,9 +407,32 @@ slp::NearArgs<T> near_args(const slp_geom *G) {
 }
 
 template <typename T>
+slp::NearArgs<T> iw_args(const slp_geom *G) {
+  slp::NearArgs<T> a{};
+  a.rowptr = G->iw_rowptr;
+  a.cols = G->iw_cols;
+  a.bases = G->iw_bases;
+  a.offs = G->iw_offs;
+  a.vals = static_cast<T *>(G->iw_vals);
+  a.gbar = G->iw_gbar;
+  a.rows = G->iw_rows;
+  a.M = G->n_tris;
+  return a;
+}
+
+template <typename T>
 int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bool tm) {
-  // spread (the charges q = w g are formed inside the gridding)
-  {
+  if (G->iw_order > 0) {
+    // integrated-window gridding: a = A gbar (the whole gridding stage; the
+    // block-sum stage takes no time)
+    slp::IwOut<T> o{};
+    o.grid = static_cast<T *>(G->grid_a);
+    o.bstride = G->item_elems[1];
+    for (int i = 0; i < 3; ++i) { o.R[i] = G->R[i]; o.P[i] = G->P[i]; }
+    HIP_TRY(slp::launch_iw_apply<T>(iw_args<T>(G), o, ptrs, nb, G->iw_packed, st));
+    if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
+  } else {
+    // spread (the charges q = w g are formed inside the gridding)
     const slp::SpreadBinsArgs<T> a = spread_args<T>(G);
     slp::SpreadReduceArgs<T> r{};
     r.scratch = static_cast<const T *>(G->scratch);
@@ -1327,6 +1362,8 @@ int slp_choose_cutoff(double tol, int32_t precision, int32_t window_in, int32_t 
 
 int slp_set_graph(slp_geom *G, int32_t enable) {
   if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (enable && G->iw_order > 0)
+    return fail(SLP_EINVAL, "captured evaluations do not combine with integrated-window gridding");
   if (!enable && G->use_graph) {
     HIP_TRY(hipDeviceSynchronize());
     G->drop_graphs();
@@ -1484,11 +1521,28 @@ void drop_near(slp_geom *G) {
   G->nf_stored = 0;
   G->nf_eps = 0.0;
 }
+
+void drop_iw(slp_geom *G) {
+  for (void *q : {(void *)G->iw_rowptr, (void *)G->iw_cols, (void *)G->iw_bases, (void *)G->iw_offs,
+                  G->iw_vals, (void *)G->iw_gbar})
+    G->release(q);
+  G->iw_rowptr = nullptr;
+  G->iw_cols = nullptr;
+  G->iw_bases = nullptr;
+  G->iw_offs = nullptr;
+  G->iw_vals = nullptr;
+  G->iw_gbar = nullptr;
+  G->iw_packed = false;
+  G->iw_order = 0;
+  G->iw_nnz = G->iw_stored = G->iw_rows = 0;
+}
 }  // namespace
 
 int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   if (!G) return fail(SLP_EINVAL, "NULL geometry");
   if (!std::isfinite(eps)) return fail(SLP_EINVAL, "eps must be finite");
+  if (eps > 0.0 && G->iw_order > 0)
+    return fail(SLP_EINVAL, "a near field does not combine with integrated-window gridding");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
@@ -1628,6 +1682,176 @@ int slp_near_radius(const slp_geom *G, double tol, double *eps) {
     return fail(SLP_EINVAL, "the kept exponential sum misses 1/r by more than %g at the body diameter %g",
                 tol, G->r_max);
   *eps = r;
+  return SLP_OK;
+}
+
+
+int slp_setup_integrated_gridding(slp_geom *G, int32_t order, void *stream) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (order < 0 || order > 16) return fail(SLP_EINVAL, "order must be 0 (off) or 1..16, got %d", (int)order);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (order > 0 && G->nf_nnz > 0)
+    return fail(SLP_EINVAL, "integrated-window gridding does not combine with a near field (its values "
+                            "cancel the smooth part of the three-point sources)");
+  if (order > 0 && G->use_graph)
+    return fail(SLP_EINVAL, "integrated-window gridding does not combine with captured evaluations");
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipDeviceSynchronize());
+  G->drop_graphs();
+  drop_iw(G);
+  if (order == 0) return SLP_OK;
+
+  // vertices in grid units, areas, and each triangle's index box
+  // {floor(t_min) - m + 1 .. floor(t_max) + m} per axis (eq. indexset2),
+  // relative to the region
+  const int64_t M = G->n_tris;
+  const int64_t R0 = G->R[0], R1 = G->R[1], rows = (int64_t)G->R[0] * G->R[1] * G->R[2];
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> cols;
+  std::vector<double> tv(9 * M), area(M);
+  std::vector<int32_t> box(6 * M);
+  try {
+    for (int64_t j = 0; j < M; ++j) {
+      const double *P[3];
+      for (int k = 0; k < 3; ++k) P[k] = &G->h_nodes[3 * (int64_t)G->h_tris[3 * j + k]];
+      double e1[3], e2[3];
+      for (int q = 0; q < 3; ++q) { e1[q] = P[1][q] - P[0][q]; e2[q] = P[2][q] - P[0][q]; }
+      const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                            e1[0] * e2[1] - e1[1] * e2[0]};
+      area[j] = 0.5 * std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+      for (int q = 0; q < 3; ++q) {
+        double tmin = INFINITY, tmax = -INFINITY;
+        for (int k = 0; k < 3; ++k) {
+          const double t = ((P[k][q] - G->c[q]) * G->s[q] + 0.5) * G->N[q];
+          tv[9 * j + 3 * k + q] = t;
+          tmin = std::min(tmin, t);
+          tmax = std::max(tmax, t);
+        }
+        const int64_t blo = (int64_t)std::floor(tmin) - G->m + 1 - G->lo[q];
+        const int64_t bhi = (int64_t)std::floor(tmax) + G->m - G->lo[q];
+        if (blo < 0 || bhi >= G->R[q])
+          return fail(SLP_EINVAL, "triangle %lld: its window box leaves the region of the sources and "
+                      "targets (evaluate at the nodes, or at points that include them)", (long long)j);
+        box[6 * j + q] = (int32_t)blo;
+        box[6 * j + 3 + q] = (int32_t)bhi;
+      }
+    }
+    // rows = region cells, columns = triangles in ascending order
+    rowptr.assign(rows + 1, 0);
+    auto cells = [&](int64_t j, auto &&fn) {
+      const int32_t *b = &box[6 * j];
+      for (int64_t z = b[2]; z <= b[5]; ++z)
+        for (int64_t y = b[1]; y <= b[4]; ++y)
+          for (int64_t x = b[0]; x <= b[3]; ++x) fn(x + R0 * (y + R1 * z));
+    };
+    for (int64_t j = 0; j < M; ++j) cells(j, [&](int64_t r) { rowptr[r + 1] += 1; });
+    for (int64_t r = 0; r < rows; ++r) rowptr[r + 1] += rowptr[r];
+    cols.resize(rowptr[rows]);
+    std::vector<int64_t> fill(rowptr.begin(), rowptr.end() - 1);
+    for (int64_t j = 0; j < M; ++j) cells(j, [&](int64_t r) { cols[fill[r]++] = (int32_t)j; });
+  } catch (const std::bad_alloc &) {
+    return fail(SLP_ENOMEM, "host allocation for the integrated-window pattern failed");
+  }
+  const int64_t nnz = rowptr.back();
+  NearLayout L;
+  if (!near_layout(rowptr, cols, rows, L))
+    return fail(SLP_ENOMEM, "host allocation for the padded integrated-window pattern failed");
+  std::vector<int32_t>().swap(cols);
+
+  void *rp = nullptr, *cl = nullptr, *bs = nullptr, *of = nullptr, *vl = nullptr, *gb = nullptr;
+  bool ok = G->alloc(&rp, L.prow.size() * sizeof(int64_t)) == hipSuccess &&
+            G->alloc(&vl, (size_t)L.stored * G->esz()) == hipSuccess &&
+            G->alloc(&gb, (size_t)M * 8 * G->cap) == hipSuccess;
+  if (ok && L.packed)
+    ok = G->alloc(&bs, L.bases.size() * sizeof(int32_t)) == hipSuccess &&
+         G->alloc(&of, L.offs.size() * sizeof(uint16_t)) == hipSuccess;
+  else if (ok)
+    ok = G->alloc(&cl, (size_t)L.stored * sizeof(int32_t)) == hipSuccess;
+  if (!ok) {
+    for (void *q : {rp, cl, bs, of, vl, gb}) G->release(q);
+    return fail(SLP_ENOMEM, "integrated-window gridding: %lld entries do not fit in device memory",
+                (long long)nnz);
+  }
+  G->iw_rowptr = static_cast<int64_t *>(rp);
+  G->iw_cols = static_cast<int32_t *>(cl);
+  G->iw_bases = static_cast<int32_t *>(bs);
+  G->iw_offs = static_cast<uint16_t *>(of);
+  G->iw_vals = vl;
+  G->iw_gbar = static_cast<double *>(gb);
+  G->iw_packed = L.packed;
+  G->iw_nnz = nnz;
+  G->iw_stored = L.stored;
+  G->iw_rows = rows;
+
+  // the collapsed Gauss rule: xi_1 = u (1 - v), xi_2 = u v, weight w_u w_v u
+  std::vector<double> glx, glw, rule;
+  gauss_legendre(order, glx, glw);
+  for (int a = 0; a < order; ++a)
+    for (int b = 0; b < order; ++b) {
+      const double u = 0.5 * (glx[a] + 1.0), v = 0.5 * (glx[b] + 1.0);
+      rule.push_back(u * (1.0 - v));
+      rule.push_back(u * v);
+      rule.push_back(0.25 * glw[a] * glw[b] * u);
+    }
+  struct Temp {
+    std::vector<void *> p;
+    ~Temp() { for (void *q : p) (void)hipFree(q); }
+  } tmp;
+  auto talloc = [&](void **q, size_t bytes) {
+    hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) tmp.p.push_back(*q);
+    return e;
+  };
+  double *d_tv = nullptr, *d_area = nullptr, *d_rule = nullptr;
+  int32_t *d_cols = G->iw_cols;
+  if (talloc((void **)&d_tv, tv.size() * 8) != hipSuccess ||
+      talloc((void **)&d_area, area.size() * 8) != hipSuccess ||
+      talloc((void **)&d_rule, rule.size() * 8) != hipSuccess ||
+      (L.packed && talloc((void **)&d_cols, (size_t)L.stored * 4) != hipSuccess)) {
+    drop_iw(G);
+    return fail(SLP_ENOMEM, "integrated-window gridding: temporary device buffers failed");
+  }
+  HIP_TRY(hipMemcpyAsync(G->iw_rowptr, L.prow.data(), L.prow.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_cols, L.cols.data(), (size_t)L.stored * 4, hipMemcpyHostToDevice, st));
+  if (L.packed) {
+    HIP_TRY(hipMemcpyAsync(G->iw_bases, L.bases.data(), L.bases.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(G->iw_offs, L.offs.data(), L.offs.size() * 2, hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipMemcpyAsync(d_tv, tv.data(), tv.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_area, area.data(), area.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_rule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice, st));
+  slp::IwGeom g{};
+  g.tv = d_tv;
+  g.area = d_area;
+  g.rule = d_rule;
+  g.npts = order * order;
+  for (int q = 0; q < 3; ++q) { g.lo[q] = G->lo[q]; g.R[q] = G->R[q]; }
+  g.m = G->m;
+  g.window = G->window == SLP_WINDOW_KB ? 1 : 0;
+  g.inv_b = 1.0 / G->b;
+  g.b = G->b;
+  g.kb_inv_norm = G->kb_inv_norm;
+  if (G->prec == SLP_FP64) {
+    slp::NearArgs<double> a = iw_args<double>(G);
+    a.cols = d_cols;
+    HIP_TRY(slp::launch_iw_values<double>(a, g, st));
+  } else {
+    slp::NearArgs<float> a = iw_args<float>(G);
+    a.cols = d_cols;
+    HIP_TRY(slp::launch_iw_values<float>(a, g, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));   // host vectors and temporaries go out of scope
+  G->iw_order = order;
+  return SLP_OK;
+}
+
+int slp_integrated_gridding_info(const slp_geom *G, int32_t *order, int64_t *nnz, int64_t *stored,
+                                 int32_t *packed) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  if (order) *order = G->iw_order;
+  if (nnz) *nnz = G->iw_nnz;
+  if (stored) *stored = G->iw_stored;
+  if (packed) *packed = G->iw_packed ? 1 : 0;
   return SLP_OK;
 }
 

@@ -170,6 +170,31 @@ hipError_t launch_near_values(const NearArgs<T> &a, const double *targets, const
 template <typename T>
 hipError_t launch_near_apply(const NearArgs<T> &a, const BatchPtrs &p, int nb, bool packed,
                              hipStream_t s);
+// Integrated-window gridding (Sec. 3.1, eq. gridding2, the matrix A): the
+// window integrated over each triangle, stored by cell of the region in the
+// near-field layout (rows = region cells x + R_x (y + R_y z), columns =
+// triangles), evaluated as a = A gbar into the region grid.
+struct IwGeom {
+  const double *tv;      // [M][3][3] vertex coordinates in grid units
+  const double *area;    // [M] physical areas
+  const double *rule;    // [npts][3] collapsed Gauss rule on the unit triangle: xi_1, xi_2, weight
+  int32_t npts;
+  int32_t lo[3], R[3];   // region origin (grid index) and extent
+  int32_t m, window;     // cut-off; 0 Gaussian exp(-tau^2 / b), 1 Kaiser-Bessel
+  double inv_b, b, kb_inv_norm;
+};
+template <typename T>
+struct IwOut {
+  T *grid;               // region grid of item 0, [P_z][P_y][P_x]
+  int64_t bstride;       // elements between items
+  int32_t R[3], P[3];
+};
+template <typename T>
+hipError_t launch_iw_values(const NearArgs<T> &a, const IwGeom &g, hipStream_t s);
+// Element means of the densities (into a.gbar), then the product.
+template <typename T>
+hipError_t launch_iw_apply(const NearArgs<T> &a, const IwOut<T> &o, const BatchPtrs &p, int nb,
+                           bool packed, hipStream_t s);
 // Host handles of the two kernels of launch_near_apply (the element means, the
 // product), whose per-item pointers are updated when a captured evaluation is
 // replayed.

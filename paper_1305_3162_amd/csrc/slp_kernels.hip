@@ -1049,21 +1049,16 @@ __device__ __forceinline__ void group_cols(const A &a, int64_t q, int64_t j[4]) 
   }
 }
 
-// phi_i += sum_j C_ij gbar_j / (4 pi). One wave per row; a lane takes groups
-// of four entries, two groups in flight; the IB items of blockIdx.y share the
-// matrix reads. FP64 accumulation.
+// Lane partials of sum_j A_rj gbar_j for one row of a matrix in the
+// near-field layout: a lane takes groups of four entries, two groups in
+// flight; the IB items share the matrix reads. FP64 accumulation.
 template <typename T, int IB, bool PACKED>
-__global__ __launch_bounds__(256) void k_near_apply(NearArgs<T> a, BatchPtrs p, int32_t nb) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= a.rows) return;
-  const int lane = threadIdx.x & 63;
-  const int item0 = blockIdx.y * IB;
-  const int n_it = nb - item0 < IB ? nb - item0 : IB;
+__device__ __forceinline__ void row_partials(const NearArgs<T> &a, int64_t row, int lane,
+                                             const double *__restrict__ gb, int n_it,
+                                             double acc[IB]) {
   const int64_t M = a.M;
-  const double *__restrict__ gb = a.gbar + (int64_t)item0 * M;
   const int64_t q1 = a.rowptr[row + 1] / kNearGroup;
   int64_t q = a.rowptr[row] / kNearGroup + lane;
-  double acc[IB];
 #pragma unroll
   for (int i = 0; i < IB; ++i) acc[i] = 0.0;
   for (; q + 64 < q1; q += 128) {
@@ -1083,6 +1078,18 @@ __global__ __launch_bounds__(256) void k_near_apply(NearArgs<T> a, BatchPtrs p, 
     load_group(a.vals, q, v0);
     near_group<IB>(j0[0], j0[1], j0[2], j0[3], v0, gb, M, n_it, acc);
   }
+}
+
+// phi_i += sum_j C_ij gbar_j / (4 pi), one wave per target row.
+template <typename T, int IB, bool PACKED>
+__global__ __launch_bounds__(256) void k_near_apply(NearArgs<T> a, BatchPtrs p, int32_t nb) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.rows) return;
+  const int lane = threadIdx.x & 63;
+  const int item0 = blockIdx.y * IB;
+  const int n_it = nb - item0 < IB ? nb - item0 : IB;
+  double acc[IB];
+  row_partials<T, IB, PACKED>(a, row, lane, a.gbar + (int64_t)item0 * a.M, n_it, acc);
   const double inv4pi = 1.0 / (4.0 * 3.141592653589793238462643383279502884);
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
@@ -1091,6 +1098,100 @@ __global__ __launch_bounds__(256) void k_near_apply(NearArgs<T> a, BatchPtrs p, 
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0 && i < n_it) p.phi[item0 + i][row] += s * inv4pi;
   }
+}
+
+// ------------------------------------------ integrated-window gridding ---
+// A_rj = int_{S_j} prod_q psi(r_q - t_q(y)) [-m < r_q - t_q(y) <= m] dsigma(y)
+// for the stored entries (row r = cell of the region, column j = triangle),
+// by the collapsed Gauss rule: t(xi) = t_0 + xi_1 (t_1 - t_0) + xi_2 (t_2 - t_0)
+// in grid units, dsigma = 2 |S_j| dxi; psi the gridding's window factor.
+// One wave per row; padding entries (column -1) get 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_iw_values(NearArgs<T> a, IwGeom g) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.rows) return;
+  const int lane = threadIdx.x & 63;
+  const double r[3] = {(double)(g.lo[0] + row % g.R[0]), (double)(g.lo[1] + (row / g.R[0]) % g.R[1]),
+                       (double)(g.lo[2] + row / ((int64_t)g.R[0] * g.R[1]))};
+  const double m = (double)g.m;
+  const int64_t e1 = a.rowptr[row + 1];
+  for (int64_t e = a.rowptr[row] + lane; e < e1; e += 64) {
+    const int64_t j = a.cols[e];
+    if (j < 0) {
+      a.vals[e] = (T)0;
+      continue;
+    }
+    const double *tv = g.tv + 9 * j;     // three vertices, grid units
+    double acc = 0.0;
+    for (int p = 0; p < g.npts; ++p) {
+      const double x1 = g.rule[3 * p], x2 = g.rule[3 * p + 1];
+      double w = g.rule[3 * p + 2];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const double t = tv[q] + x1 * (tv[3 + q] - tv[q]) + x2 * (tv[6 + q] - tv[q]);
+        const double tau = r[q] - t;
+        if (!(tau > -m && tau <= m)) w = 0.0;
+        else if (g.window == 0) w *= exp(-tau * tau * g.inv_b);
+        else w *= kb_weight<double>(tau, m, g.b, g.kb_inv_norm);
+      }
+      acc += w;
+    }
+    a.vals[e] = (T)(2.0 * g.area[j] * acc);
+  }
+}
+
+template <typename T>
+hipError_t launch_iw_values(const NearArgs<T> &a, const IwGeom &g, hipStream_t s) {
+  if (a.rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iw_values<T>, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a, g);
+  return hipGetLastError();
+}
+
+// a_r = sum_j A_rj gbar_j into the region grid of every item, one wave per
+// cell of the region (row = x + R_x (y + R_y z), stored at (z P_y + y) P_x + x).
+template <typename T, int IB, bool PACKED>
+__global__ __launch_bounds__(256) void k_iw_apply(NearArgs<T> a, IwOut<T> o, int32_t nb) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.rows) return;
+  const int lane = threadIdx.x & 63;
+  const int item0 = blockIdx.y * IB;
+  const int n_it = nb - item0 < IB ? nb - item0 : IB;
+  double acc[IB];
+  row_partials<T, IB, PACKED>(a, row, lane, a.gbar + (int64_t)item0 * a.M, n_it, acc);
+  const int64_t x = row % o.R[0], y = (row / o.R[0]) % o.R[1], z = row / ((int64_t)o.R[0] * o.R[1]);
+  const int64_t at = (z * o.P[1] + y) * o.P[0] + x;
+#pragma unroll
+  for (int i = 0; i < IB; ++i) {
+    double s = acc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0 && i < n_it) o.grid[(int64_t)(item0 + i) * o.bstride + at] = (T)s;
+  }
+}
+
+template <typename T, bool PACKED>
+void launch_iw_apply_p(const NearArgs<T> &a, const IwOut<T> &o, int nb, hipStream_t s) {
+  const int ib = nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
+  const dim3 grid((unsigned)((a.rows + 3) / 4), (unsigned)((nb + ib - 1) / ib));
+  switch (ib) {
+    case 8: hipLaunchKernelGGL((k_iw_apply<T, 8, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
+    case 4: hipLaunchKernelGGL((k_iw_apply<T, 4, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
+    case 2: hipLaunchKernelGGL((k_iw_apply<T, 2, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
+    default: hipLaunchKernelGGL((k_iw_apply<T, 1, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
+  }
+}
+
+template <typename T>
+hipError_t launch_iw_apply(const NearArgs<T> &a, const IwOut<T> &o, const BatchPtrs &p, int nb,
+                           bool packed, hipStream_t s) {
+  if (a.rows <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_near_gbar, dim3((unsigned)((a.M + 255) / 256), (unsigned)nb), dim3(256), 0,
+                     s, p, a.gbar, a.M);
+  if (packed)
+    launch_iw_apply_p<T, true>(a, o, nb, s);
+  else
+    launch_iw_apply_p<T, false>(a, o, nb, s);
+  return hipGetLastError();
 }
 
 template <typename T, bool PACKED>
@@ -1190,6 +1291,12 @@ template hipError_t launch_near_apply<double>(const NearArgs<double> &, const Ba
                                               bool, hipStream_t);
 template const void *near_apply_kernel<float>(int, bool);
 template const void *near_apply_kernel<double>(int, bool);
+template hipError_t launch_iw_values<float>(const NearArgs<float> &, const IwGeom &, hipStream_t);
+template hipError_t launch_iw_values<double>(const NearArgs<double> &, const IwGeom &, hipStream_t);
+template hipError_t launch_iw_apply<float>(const NearArgs<float> &, const IwOut<float> &,
+                                           const BatchPtrs &, int, bool, hipStream_t);
+template hipError_t launch_iw_apply<double>(const NearArgs<double> &, const IwOut<double> &,
+                                            const BatchPtrs &, int, bool, hipStream_t);
 template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
 template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,

@@ -1,0 +1,95 @@
+"""Integrated-window gridding (Sec. 3.1, eq. gridding2, the matrix A) on the
+device: the complete smooth part against the oracle's integrated route on
+spheres and a cube in both windows and precisions, batched launches against
+single ones, switching back to the point gridding, and the combinations the
+library refuses."""
+import numpy as np
+import pytest
+
+import paper_1305_3162_amd as slp
+from oracle import direct, integrated as iwo
+from synth.workloads import cube_random, sphere_random
+from slp_testlib import es_for, log, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _geometry(wl, m, prec, window):
+    w, g = es_for(wl)
+    return slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2, window=window)
+
+
+CASES = {
+    "sphere_l2_gauss8_fp64": (lambda: sphere_random(2, 4, 32, 8), 8, slp.FP64, slp.WINDOW_GAUSS, 1e-6),
+    "sphere_l3_kb4_fp64": (lambda: sphere_random(3, 4, 64, 4), 4, slp.FP64, slp.WINDOW_KB, 1e-6),
+    "sphere_l3_gauss5_fp32": (lambda: sphere_random(3, 4, 64, 5), 5, slp.FP32, slp.WINDOW_GAUSS, 1e-4),
+    "cube16_kb4_fp64": (lambda: cube_random(16, 2, 64, 4), 4, slp.FP64, slp.WINDOW_KB, 1e-6),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_integrated_gridding_against_oracle(name):
+    make, m, prec, window, tol = CASES[name]
+    wl = make()
+    log(f"case integrated {name}: {wl.tris.shape[0]} triangles, grid {wl.grid}")
+    G = _geometry(wl, m, prec, window)
+    d = torch.as_tensor(wl.dens).cuda()
+    point = G.solve(d).cpu().numpy()
+    G.setup_integrated_gridding(8)
+    info = G.integrated_gridding_info()
+    got = G.solve(d).cpu().numpy()
+    torch.cuda.synchronize()
+    prob = direct.prepare_workload(wl)
+    ref = iwo.phi_integrated(prob, wl.nodes, wl.tris, m, "kb" if window == slp.WINDOW_KB else "gauss",
+                             n=12)
+    e = rel_l2(got, ref)
+    log(f"  {info}; rel-L2 vs oracle {e:.3e}; integrated vs point gridding {rel_l2(got, point):.3e}")
+    assert info["order"] == 8 and info["nnz"] > 0
+    assert np.all(np.isfinite(got)) and e <= tol
+    # the route changed (three-point quadrature vs the window integral)
+    assert rel_l2(got, point) > 1e-9
+    # back to the point gridding
+    G.setup_integrated_gridding(0)
+    again = G.solve(d).cpu().numpy()
+    assert rel_l2(again, point) <= (1e-13 if prec == slp.FP64 else 1e-6)
+    G.close()
+
+
+def test_integrated_batched_equals_single():
+    wl = sphere_random(2, 7, 32, 6)
+    G = _geometry(wl, 6, slp.FP64, slp.WINDOW_GAUSS)
+    G.setup_integrated_gridding(6)
+    rng = np.random.default_rng(8)
+    dens = [torch.as_tensor(rng.normal(size=wl.n_src)).cuda() for _ in range(11)]
+    phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda") for _ in dens]
+    slp.eval_batched([G.handle] * len(dens), dens, phis)
+    torch.cuda.synchronize()
+    for k in (0, 3, 8, 10):
+        ref = G.solve(dens[k])
+        torch.cuda.synchronize()
+        assert rel_l2(phis[k].cpu().numpy(), ref.cpu().numpy()) <= 1e-14, k
+    G.close()
+
+
+def test_integrated_gridding_refusals():
+    wl = sphere_random(2, 4, 32, 4)
+    G = _geometry(wl, 4, slp.FP64, slp.WINDOW_KB)
+    with pytest.raises(slp.SlpError, match="order"):
+        G.setup_integrated_gridding(17)
+    G.setup_integrated_gridding(4)
+    with pytest.raises(slp.SlpError, match="near field"):
+        G.setup_near_field(0.3)
+    with pytest.raises(slp.SlpError, match="captured"):
+        slp.set_graph(G.handle, True)
+    G.setup_integrated_gridding(0)
+    G.setup_near_field(0.3)
+    with pytest.raises(slp.SlpError, match="near field"):
+        G.setup_integrated_gridding(4)
+    G.close()
