@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--mix32", action="store_true",
                     help="multi-mesh batch: 32 icospheres of levels 2-6 in one batched call")
     ap.add_argument("--requests", type=int, default=1000)
+    ap.add_argument("--integrated", type=int, default=0,
+                    help="grid the window integrated over each triangle (the paper's matrix A, "
+                         "Sec. 3.1) with this many Gauss points per direction; 0 = point sources")
     ap.add_argument("--near-tol", type=float, default=None,
                     help="add the near-field correction with eps from slp_near_radius(tol)")
     ap.add_argument("--potential", action="store_true",
@@ -98,6 +101,16 @@ def algorithmic_units(stage, info, m, esz):
     n = info["_n"]
     Kx, Ky, Kz = n[0] // 2 + 1, n[1] + 1, n[2] + 1
     c = 2 * esz
+    if stage == "spread_bins" and info.get("_iw_stored"):
+        # integrated-window gridding: the stored window integrals read once
+        # (value and column), the row offsets, the density read and its
+        # element means written and read once, the region grid written
+        st = info["_iw_stored"]
+        colb = 2 * st + 4 * (st // 256) if info["_iw_packed"] else 4 * st
+        rows = R[0] * R[1] * R[2]
+        M = info["n_src"] // 3
+        return (st * esz + colb + (rows + 1) * 8 + rows * esz + info["n_src"] * 8 + 2 * M * 8,
+                "byte", "hbm")
     if stage == "spread_bins":
         # FP64 with 2m = 16 accumulates each run on the matrix cores
         bound = "mfma" if esz == 8 and w == 16 else "alu"
@@ -153,6 +166,8 @@ def measured_traffic(args, m, stage, nb):
     key = f"{args.workload}/{args.precision}/{args.window}/m{m}"
     if stage == "near":
         key += f"/near{args.near_tol:g}"
+    if getattr(args, "integrated", 0):
+        key += f"/integrated{args.integrated}"
     e = rec["entries"].get(key)
     return None if e is None else e["bytes_per_launch"]
 
@@ -543,11 +558,21 @@ def main():
                     "stored": nf["stored"], "packed_columns": nf["packed"],
                     "setup_s": round(time.perf_counter() - t1, 3),
                     "device_bytes": geom.info["device_bytes"]}
+    iw_cfg = None
+    if args.integrated:
+        t1 = time.perf_counter()
+        geom.setup_integrated_gridding(args.integrated, stream)
+        iwi = geom.integrated_gridding_info()
+        iw_cfg = {"order": iwi["order"], "window_integrals": iwi["nnz"], "stored": iwi["stored"],
+                  "packed_columns": iwi["packed"], "setup_s": round(time.perf_counter() - t1, 3),
+                  "device_bytes": slp.geom_get_info(geom.handle)["device_bytes"]}
     n_tgt = geom.info["n_targets"]
     info = dict(geom.info)
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     info["_stored"] = 0 if near_cfg is None else near_cfg["stored"]
     info["_packed"] = False if near_cfg is None else near_cfg["packed_columns"]
+    info["_iw_stored"] = 0 if iw_cfg is None else iw_cfg["stored"]
+    info["_iw_packed"] = False if iw_cfg is None else iw_cfg["packed_columns"]
     dens = torch.as_tensor(wl.dens, device="cuda")
     phi = torch.empty(n_tgt, dtype=torch.float64, device="cuda")
     nb = max(1, args.batch)
@@ -665,7 +690,7 @@ def main():
     # the same solve with the Kaiser-Bessel window of Sec. 3.2 at the cut-off that
     # meets the same precision gate (FP64 m = 4, FP32 m = 3), for comparison
     alt = None
-    if args.window == "gauss" and nb == 1 and not args.no_oracle and near_cfg is None:
+    if args.window == "gauss" and nb == 1 and not args.no_oracle and near_cfg is None and iw_cfg is None:
         mk = 4 if prec == slp.FP64 else 3
         gk = slp.Geometry(wl.nodes, wl.tris, wl.grid, mk, w, g, wl.alpha, prec, wl.eta2,
                           window=slp.WINDOW_KB, targets=targets)
@@ -706,10 +731,14 @@ def main():
                                 f"{'Kaiser-Bessel' if kb else 'Gaussian'} window cut-off m={m}")
                                if args.workload == "cube64" else wl.name,
                    "m": m, "window": args.window, "precision": args.precision, "points": pts,
-                   "densities_per_step": nb, "near_field": near_cfg},
+                   "densities_per_step": nb, "near_field": near_cfg,
+                   "integrated_gridding": iw_cfg},
         "rel_l2_err_vs_oracle": rel_err,
         "err_kind": ("relative L2 over all targets" if near_cfg is None else
-                     "max |error| over 8 seeded rows / max |phi| (oracle near field per row)"),
+                     "max |error| over 8 seeded rows / max |phi| (oracle near field per row)")
+                    + ("; against the three-point definition, from which integrated-window "
+                       "gridding differs by the three-point rule's quadrature error"
+                       if iw_cfg is not None else ""),
         "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
         "roofline": roofline,
         "cpu_baseline": cpu_baseline,
