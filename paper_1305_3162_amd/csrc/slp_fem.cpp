@@ -461,11 +461,20 @@ int build_amg_impl(slp_fem *F, hipStream_t st) {
   } catch (const std::bad_alloc &) {
     return fail(SLP_ENOMEM, "host allocation failed while building the multigrid hierarchy");
   }
-  const int rc = upload_amg(F, h, st);
+  const size_t first = F->allocs.size();
+  int rc = upload_amg(F, h, st);
   // the copies read the host hierarchy, which goes out of scope here
   const hipError_t e = hipStreamSynchronize(st);
-  if (rc) return rc;
-  FEM_TRY(e);
+  if (!rc && e != hipSuccess)
+    rc = fail(SLP_EDEVICE, "copying the multigrid hierarchy failed: %s", hipGetErrorString(e));
+  if (rc) {
+    // free what this attempt allocated (the allocations are recorded in order)
+    while (F->allocs.size() > first) F->release(F->allocs.back());
+    F->amg.clear();
+    F->amg_coarse = slp_fem::DevCsr();
+    F->amg_fc = F->amg_ec = nullptr;
+    return rc;
+  }
   F->amg_built = true;
   return SLP_OK;
 }
