@@ -366,6 +366,14 @@ int slp_fem_set_preconditioner(slp_fem *f, int32_t kind, void *stream);
  * small for *n_levels. */
 int slp_fem_amg_info(const slp_fem *f, int32_t *n_levels, int64_t *rows, int64_t *nnz,
                      int32_t cap);
+/* Host-only: builds the hierarchy of SLP_PRECOND_AMG for the symmetric
+ * positive definite CSR matrix (rowptr int64 [n + 1], cols int32, vals float64,
+ * host memory) and applies one cycle on the host, z = B r (host float64 [n]),
+ * with the steps of the device cycle; n_levels receives the operator count
+ * (may be NULL). For testing the hierarchy without a device. EINVAL for a
+ * malformed matrix or a hierarchy that cannot be built; ENOMEM. */
+int slp_amg_apply_host(int64_t n, const int64_t *rowptr, const int32_t *cols, const double *vals,
+                       const double *r, double *z, int32_t *n_levels);
 /* phi_1 at every node (0 on the boundary): load vector b_k = sum_T |T| mbar_T .
  * grad eta_k (m the nodal P1 field, mbar_T its vertex mean), then
  * preconditioned conjugate gradients on the free nodes until |r| <= tol |b|

@@ -23,7 +23,7 @@ __all__ = [
     "near_field_device_bytes", "fem_setup", "fem_info", "fem_boundary", "fem_solve_phi1", "fem_dphi1_dn",
     "scalar_potential", "fem_energy", "fem_destroy", "Fem", "fem_set_preconditioner",
     "fem_amg_info", "PRECOND_JACOBI", "PRECOND_AMG", "setup_integrated_gridding",
-    "integrated_gridding_info",
+    "integrated_gridding_info", "amg_apply_host",
 ]
 
 FP64, FP32 = 0, 1
@@ -129,6 +129,7 @@ def load_library():
                                _VP],
         "slp_fem_dphi1_dn": [_VP, _VP, _VP, _VP],
         "slp_fem_set_preconditioner": [_VP, ctypes.c_int32, _VP],
+        "slp_amg_apply_host": [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)],
         "slp_setup_integrated_gridding": [_VP, ctypes.c_int32, _VP],
         "slp_integrated_gridding_info": [_VP, ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_int64),
@@ -525,6 +526,23 @@ def integrated_gridding_info(geom):
     _check(load_library().slp_integrated_gridding_info(_VP(geom), ctypes.byref(o), ctypes.byref(n),
                                                        ctypes.byref(st), ctypes.byref(pk)))
     return {"order": o.value, "nnz": n.value, "stored": st.value, "packed": bool(pk.value)}
+
+
+def amg_apply_host(rowptr, cols, vals, r):
+    """slp_amg_apply_host: z = B r for one multigrid cycle built from the CSR
+    matrix (host arrays); returns (z, number of operators in the hierarchy)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    n = rowptr.size - 1
+    if r.size != n:
+        raise ValueError("r must have one value per row")
+    z = np.zeros(n)
+    nl = ctypes.c_int32(0)
+    _check(load_library().slp_amg_apply_host(n, rowptr.ctypes.data, cols.ctypes.data, vals.ctypes.data,
+                                             r.ctypes.data, z.ctypes.data, ctypes.byref(nl)))
+    return z, nl.value
 
 
 PRECOND_JACOBI, PRECOND_AMG = 0, 1

@@ -253,4 +253,42 @@ bool build_amg(const HostCsr &A, const AmgParams &prm, AmgHierarchy &h, char *er
   return true;
 }
 
+namespace {
+
+void spmv(const HostCsr &M, const double *x, double *y) {
+  for (int64_t i = 0; i < M.rows; ++i) {
+    double t = 0.0;
+    for (int32_t e = M.rp[i]; e < M.rp[i + 1]; ++e) t += M.v[e] * x[M.ci[e]];
+    y[i] = t;
+  }
+}
+
+void cycle(const AmgHierarchy &h, size_t l, const double *f, double *out) {
+  if (l == h.levels.size()) {
+    const int64_t n = h.nc;
+    for (int64_t i = 0; i < n; ++i) {
+      double t = 0.0;
+      for (int64_t j = 0; j < n; ++j) t += h.coarse_inv[i * n + j] * f[j];
+      out[i] = t;
+    }
+    return;
+  }
+  const AmgLevel &L = h.levels[l];
+  const int64_t n = L.A.rows, nc = L.P.cols;
+  std::vector<double> x(n), t(n), fc(nc), e(nc);
+  for (int64_t i = 0; i < n; ++i) x[i] = L.w[i] * f[i];
+  spmv(L.A, x.data(), t.data());
+  for (int64_t i = 0; i < n; ++i) t[i] = f[i] - t[i];
+  spmv(L.R, t.data(), fc.data());
+  cycle(h, l + 1, fc.data(), e.data());
+  spmv(L.P, e.data(), t.data());
+  for (int64_t i = 0; i < n; ++i) x[i] += t[i];
+  spmv(L.A, x.data(), t.data());
+  for (int64_t i = 0; i < n; ++i) out[i] = x[i] + L.w[i] * (f[i] - t[i]);
+}
+
+}  // namespace
+
+void amg_apply_host(const AmgHierarchy &h, const double *r, double *z) { cycle(h, 0, r, z); }
+
 }  // namespace slp

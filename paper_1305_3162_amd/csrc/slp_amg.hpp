@@ -43,4 +43,10 @@ struct AmgParams {
 // definite or the coarsening stalls above the dense limit.
 bool build_amg(const HostCsr &A, const AmgParams &prm, AmgHierarchy &h, char *err, size_t errlen);
 
+// z = B r for one V(1,1) cycle of the hierarchy on the host, the steps of the
+// device cycle in the same order (pre-smoothing from zero, restriction, the
+// coarser cycle or the dense inverse, prolongation, post-smoothing). The
+// hierarchy must have been built from A; `r` and `z` hold A.rows values.
+void amg_apply_host(const AmgHierarchy &h, const double *r, double *z);
+
 }  // namespace slp

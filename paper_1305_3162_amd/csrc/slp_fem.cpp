@@ -668,6 +668,34 @@ int slp_fem_set_preconditioner(slp_fem *F, int32_t kind, void *stream) {
   return SLP_OK;
 }
 
+int slp_amg_apply_host(int64_t n, const int64_t *rowptr, const int32_t *cols, const double *vals,
+                       const double *r, double *z, int32_t *n_levels) {
+  if (n <= 0 || !rowptr || !cols || !vals || !r || !z) return fail(SLP_EINVAL, "NULL argument or n <= 0");
+  if (rowptr[0] != 0 || rowptr[n] > INT32_MAX) return fail(SLP_EINVAL, "rowptr must start at 0 and fit 32 bits");
+  slp::HostCsr A;
+  A.rows = A.cols = n;
+  A.rp.resize(n + 1);
+  for (int64_t i = 0; i <= n; ++i) {
+    if (i > 0 && rowptr[i] < rowptr[i - 1]) return fail(SLP_EINVAL, "rowptr decreases at %lld", (long long)i);
+    A.rp[i] = (int32_t)rowptr[i];
+  }
+  A.ci.assign(cols, cols + rowptr[n]);
+  A.v.assign(vals, vals + rowptr[n]);
+  for (int32_t c : A.ci)
+    if (c < 0 || c >= n) return fail(SLP_EINVAL, "column %d out of range", (int)c);
+  slp::AmgHierarchy h;
+  char err[256] = {0};
+  try {
+    if (!slp::build_amg(A, slp::AmgParams(), h, err, sizeof err))
+      return fail(SLP_EINVAL, "multigrid setup: %s", err);
+    slp::amg_apply_host(h, r, z);
+  } catch (const std::bad_alloc &) {
+    return fail(SLP_ENOMEM, "host allocation failed while building the multigrid hierarchy");
+  }
+  if (n_levels) *n_levels = (int32_t)h.levels.size() + 1;
+  return SLP_OK;
+}
+
 int slp_fem_amg_info(const slp_fem *F, int32_t *n_levels, int64_t *rows, int64_t *nnz, int32_t cap) {
   if (!F || !n_levels) return fail(SLP_EINVAL, "NULL argument");
   if (!F->amg_built) return fail(SLP_EINVAL, "no multigrid hierarchy (select SLP_PRECOND_AMG first)");
