@@ -429,7 +429,8 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
     o.grid = static_cast<T *>(G->grid_a);
     o.bstride = G->item_elems[1];
     for (int i = 0; i < 3; ++i) { o.R[i] = G->R[i]; o.P[i] = G->P[i]; }
-    HIP_TRY(slp::launch_iw_apply<T>(iw_args<T>(G), o, ptrs, nb, G->iw_packed, st));
+    const bool short_rows = !G->iw_packed && G->iw_stored < 512 * G->iw_rows;
+    HIP_TRY(slp::launch_iw_apply<T>(iw_args<T>(G), o, ptrs, nb, G->iw_packed, short_rows, st));
     if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
   } else {
     // spread (the charges q = w g are formed inside the gridding)

@@ -191,10 +191,12 @@ struct IwOut {
 };
 template <typename T>
 hipError_t launch_iw_values(const NearArgs<T> &a, const IwGeom &g, hipStream_t s);
-// Element means of the densities (into a.gbar), then the product.
+// Element means of the densities (into a.gbar), then the product; short_rows
+// (unpacked rows of fewer than 512 stored entries on average) puts four cells
+// on a wave instead of one.
 template <typename T>
 hipError_t launch_iw_apply(const NearArgs<T> &a, const IwOut<T> &o, const BatchPtrs &p, int nb,
-                           bool packed, hipStream_t s);
+                           bool packed, bool short_rows, hipStream_t s);
 // Host handles of the two kernels of launch_near_apply (the element means, the
 // product), whose per-item pointers are updated when a captured evaluation is
 // replayed.

@@ -1050,24 +1050,26 @@ __device__ __forceinline__ void group_cols(const A &a, int64_t q, int64_t j[4]) 
 }
 
 // Lane partials of sum_j A_rj gbar_j for one row of a matrix in the
-// near-field layout: a lane takes groups of four entries, two groups in
-// flight; the IB items share the matrix reads. FP64 accumulation.
-template <typename T, int IB, bool PACKED>
+// near-field layout, L lanes per row: a lane takes groups of four entries, two
+// groups in flight; the IB items share the matrix reads. FP64 accumulation.
+// (Packed columns need L = 64: a wave reads the base of one chunk.)
+template <typename T, int IB, bool PACKED, int L = 64>
 __device__ __forceinline__ void row_partials(const NearArgs<T> &a, int64_t row, int lane,
                                              const double *__restrict__ gb, int n_it,
                                              double acc[IB]) {
+  static_assert(L == 64 || !PACKED, "packed columns are read a wave per row");
   const int64_t M = a.M;
   const int64_t q1 = a.rowptr[row + 1] / kNearGroup;
   int64_t q = a.rowptr[row] / kNearGroup + lane;
 #pragma unroll
   for (int i = 0; i < IB; ++i) acc[i] = 0.0;
-  for (; q + 64 < q1; q += 128) {
+  for (; q + L < q1; q += 2 * L) {
     int64_t j0[4], j1[4];
     group_cols<PACKED>(a, q, j0);
-    group_cols<PACKED>(a, q + 64, j1);
+    group_cols<PACKED>(a, q + L, j1);
     double v0[4], v1[4];
     load_group(a.vals, q, v0);
-    load_group(a.vals, q + 64, v1);
+    load_group(a.vals, q + L, v1);
     near_group<IB>(j0[0], j0[1], j0[2], j0[3], v0, gb, M, n_it, acc);
     near_group<IB>(j1[0], j1[1], j1[2], j1[3], v1, gb, M, n_it, acc);
   }
@@ -1147,50 +1149,54 @@ hipError_t launch_iw_values(const NearArgs<T> &a, const IwGeom &g, hipStream_t s
   return hipGetLastError();
 }
 
-// a_r = sum_j A_rj gbar_j into the region grid of every item, one wave per
-// cell of the region (row = x + R_x (y + R_y z), stored at (z P_y + y) P_x + x).
-template <typename T, int IB, bool PACKED>
+// a_r = sum_j A_rj gbar_j into the region grid of every item, L lanes per
+// cell of the region (row = x + R_x (y + R_y z), stored at (z P_y + y) P_x + x):
+// a wave per cell for long rows, four cells per wave for short ones.
+template <typename T, int IB, bool PACKED, int L>
 __global__ __launch_bounds__(256) void k_iw_apply(NearArgs<T> a, IwOut<T> o, int32_t nb) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= a.rows) return;
-  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (256 / L) + threadIdx.x / L;
+  if (row >= a.rows) return;   // whole groups of L lanes: a row's lanes stay together
+  const int lane = threadIdx.x & (L - 1);
   const int item0 = blockIdx.y * IB;
   const int n_it = nb - item0 < IB ? nb - item0 : IB;
   double acc[IB];
-  row_partials<T, IB, PACKED>(a, row, lane, a.gbar + (int64_t)item0 * a.M, n_it, acc);
+  row_partials<T, IB, PACKED, L>(a, row, lane, a.gbar + (int64_t)item0 * a.M, n_it, acc);
   const int64_t x = row % o.R[0], y = (row / o.R[0]) % o.R[1], z = row / ((int64_t)o.R[0] * o.R[1]);
   const int64_t at = (z * o.P[1] + y) * o.P[0] + x;
 #pragma unroll
   for (int i = 0; i < IB; ++i) {
     double s = acc[i];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
     if (lane == 0 && i < n_it) o.grid[(int64_t)(item0 + i) * o.bstride + at] = (T)s;
   }
 }
 
-template <typename T, bool PACKED>
+template <typename T, bool PACKED, int L>
 void launch_iw_apply_p(const NearArgs<T> &a, const IwOut<T> &o, int nb, hipStream_t s) {
   const int ib = nb >= 8 ? 8 : nb >= 4 ? 4 : nb >= 2 ? 2 : 1;
-  const dim3 grid((unsigned)((a.rows + 3) / 4), (unsigned)((nb + ib - 1) / ib));
+  constexpr int RPB = 256 / L;
+  const dim3 grid((unsigned)((a.rows + RPB - 1) / RPB), (unsigned)((nb + ib - 1) / ib));
   switch (ib) {
-    case 8: hipLaunchKernelGGL((k_iw_apply<T, 8, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
-    case 4: hipLaunchKernelGGL((k_iw_apply<T, 4, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
-    case 2: hipLaunchKernelGGL((k_iw_apply<T, 2, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
-    default: hipLaunchKernelGGL((k_iw_apply<T, 1, PACKED>), grid, dim3(256), 0, s, a, o, nb); break;
+    case 8: hipLaunchKernelGGL((k_iw_apply<T, 8, PACKED, L>), grid, dim3(256), 0, s, a, o, nb); break;
+    case 4: hipLaunchKernelGGL((k_iw_apply<T, 4, PACKED, L>), grid, dim3(256), 0, s, a, o, nb); break;
+    case 2: hipLaunchKernelGGL((k_iw_apply<T, 2, PACKED, L>), grid, dim3(256), 0, s, a, o, nb); break;
+    default: hipLaunchKernelGGL((k_iw_apply<T, 1, PACKED, L>), grid, dim3(256), 0, s, a, o, nb); break;
   }
 }
 
 template <typename T>
 hipError_t launch_iw_apply(const NearArgs<T> &a, const IwOut<T> &o, const BatchPtrs &p, int nb,
-                           bool packed, hipStream_t s) {
+                           bool packed, bool short_rows, hipStream_t s) {
   if (a.rows <= 0 || nb <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_near_gbar, dim3((unsigned)((a.M + 255) / 256), (unsigned)nb), dim3(256), 0,
                      s, p, a.gbar, a.M);
   if (packed)
-    launch_iw_apply_p<T, true>(a, o, nb, s);
+    launch_iw_apply_p<T, true, 64>(a, o, nb, s);
+  else if (short_rows)
+    launch_iw_apply_p<T, false, 16>(a, o, nb, s);
   else
-    launch_iw_apply_p<T, false>(a, o, nb, s);
+    launch_iw_apply_p<T, false, 64>(a, o, nb, s);
   return hipGetLastError();
 }
 
@@ -1294,9 +1300,9 @@ template const void *near_apply_kernel<double>(int, bool);
 template hipError_t launch_iw_values<float>(const NearArgs<float> &, const IwGeom &, hipStream_t);
 template hipError_t launch_iw_values<double>(const NearArgs<double> &, const IwGeom &, hipStream_t);
 template hipError_t launch_iw_apply<float>(const NearArgs<float> &, const IwOut<float> &,
-                                           const BatchPtrs &, int, bool, hipStream_t);
+                                           const BatchPtrs &, int, bool, bool, hipStream_t);
 template hipError_t launch_iw_apply<double>(const NearArgs<double> &, const IwOut<double> &,
-                                            const BatchPtrs &, int, bool, hipStream_t);
+                                            const BatchPtrs &, int, bool, bool, hipStream_t);
 template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
 template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,
