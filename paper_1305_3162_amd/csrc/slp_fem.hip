@@ -46,18 +46,24 @@ __global__ __launch_bounds__(kFemThreads) void k_fem_tet_m(FemLoadArgs a) {
   for (int q = 0; q < 3; ++q) a.vm[3 * t + q] = f * mb[q];
 }
 
+// b_f, kFemLoadLanes lanes per free node: each lane takes every
+// kFemLoadLanes-th incident tetrahedron, then a fixed-order shuffle sum.
 __global__ __launch_bounds__(kFemThreads) void k_fem_load(FemLoadArgs a) {
-  const int64_t f = (int64_t)blockIdx.x * kFemThreads + threadIdx.x;
-  if (f >= a.nf) return;
+  constexpr int L = kFemLoadLanes;
+  const int64_t f = ((int64_t)blockIdx.x * kFemThreads + threadIdx.x) / L;
+  if (f >= a.nf) return;   // whole groups of L lanes
+  const int lane = threadIdx.x & (L - 1);
   double acc = 0.0;
-  for (int32_t e = a.inc_ptr[f]; e < a.inc_ptr[f + 1]; ++e) {
+  for (int32_t e = a.inc_ptr[f] + lane; e < a.inc_ptr[f + 1]; e += L) {
     const int64_t t = a.inc[e] >> 2;
     const int la = a.inc[e] & 3;
     const double *g = a.grad + 12 * t + 3 * la;
     const double *vm = a.vm + 3 * t;
     acc += vm[0] * g[0] + vm[1] * g[1] + vm[2] * g[2];
   }
-  a.b[f] = acc;
+#pragma unroll
+  for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
+  if (lane == 0) a.b[f] = acc;
 }
 
 __global__ __launch_bounds__(kFemThreads) void k_pcg_start(PcgArgs a,
@@ -303,7 +309,7 @@ unsigned blocks(int64_t n) { return (unsigned)((n + kFemThreads - 1) / kFemThrea
 hipError_t launch_fem_load(const FemLoadArgs &a, hipStream_t s) {
   if (a.nf <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fem_tet_m, dim3(blocks(a.nt)), dim3(kFemThreads), 0, s, a);
-  hipLaunchKernelGGL(k_fem_load, dim3(blocks(a.nf)), dim3(kFemThreads), 0, s, a);
+  hipLaunchKernelGGL(k_fem_load, dim3(blocks(a.nf * kFemLoadLanes)), dim3(kFemThreads), 0, s, a);
   return hipGetLastError();
 }
 

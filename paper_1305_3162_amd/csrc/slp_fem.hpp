@@ -9,6 +9,7 @@
 namespace slp {
 
 constexpr int kFemThreads = 256;
+constexpr int kFemLoadLanes = 8;   // lanes per free node in the load vector
 
 // Load vector on the free nodes: b_f = sum over the tetrahedra T holding node
 // free_node[f] (local index a) of |T| mbar_T . grad lambda_a^T. The products
