@@ -244,8 +244,10 @@ int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omeg
  * of this context (single, batched, graph replay) adds phi_NF after the
  * interpolation. Geometries of a request server get theirs from
  * slp_server_add_geometry_near.
- * eps <= 0 removes the near field. Synchronises `stream` and the device;
- * drops captured graphs.
+ * eps <= 0 removes the near field. The smooth kernel's share of a pair is
+ * taken with the gridding's quadrature: the three-point rule, or the
+ * collapsed rule of slp_setup_integrated_gridding when that is set.
+ * Synchronises `stream` and the device; drops captured graphs.
  *   eps : physical distance, the paper's eps of Alg. 1 (Require line)
  * Errors: EINVAL for non-finite eps; ENOMEM when the pattern does not fit in
  * host or device memory (the context is left without a near field). */
@@ -285,10 +287,15 @@ int slp_near_field_info(const slp_geom *g, double *eps, int64_t *nnz, double *r_
  *   order : 1..16 Gauss points per direction (8 resolves the window to
  *           rounding on meshes whose triangles are about a grid cell); 0
  *           returns to the point gridding
- * Synchronises `stream` and the device. Errors: EINVAL for an order out of
- * range, a triangle whose index box leaves the grid region (the nodes must be
- * among the evaluation points), a context with a near field or with captured
- * evaluations (the two do not combine with it); ENOMEM. */
+ * A near field of the context (slp_setup_near_field, before or after) then
+ * subtracts the smooth kernel integrated over S_j with the same rule, so that
+ * near pairs still carry the exact integral of 1/r; switching the gridding
+ * rebuilds it. Synchronises `stream` and the device. Errors: EINVAL for an
+ * order out of range, a triangle whose index box leaves the grid region (the
+ * nodes must be among the evaluation points), or a context with captured
+ * evaluations (they do not combine with it); ENOMEM. After a failed call the
+ * context grids the point sources; an evaluation with a near field built for
+ * the other gridding fails with EINVAL until the near field is set up again. */
 int slp_setup_integrated_gridding(slp_geom *g, int32_t order, void *stream);
 /* order (0 = off), stored window integrals (nnz), entries including the row
  * padding and whether the columns are packed (any pointer may be NULL). */

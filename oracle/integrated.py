@@ -19,7 +19,10 @@ serves unchanged (its truncation of the window to -m < r - t <= m per axis is
 the truncated window of eq. wfct3). `triangle_fourier` gives the closed form
 of the integrated Fourier basis int_{S_j} exp(-2 pi i y~.l) dsigma (the
 quantity the gridding approximates after deconvolution, eq. deconv) for the
-pins.
+pins. With integrated gridding the near-field correction (Sec. 3.4, eq.
+nfcorr) subtracts the smooth kernel integrated over S_j by the same rule
+(`near_values_integrated`), so that a near pair again carries the exact
+integral of 1/r.
 
 Test infrastructure only (see oracle/__init__.py).
 """
@@ -29,7 +32,7 @@ import dataclasses
 
 import numpy as np
 
-from . import geometry, kernel, nufft
+from . import geometry, kernel, nearfield, nufft
 
 
 def duffy_rule(n):
@@ -138,3 +141,34 @@ def triangle_fourier(prob, nodes, tris, l):
     P0, P1, P2 = (nodes[tris[:, k]] for k in range(3))
     area = 0.5 * np.linalg.norm(np.cross(P1 - P0, P2 - P0), axis=1)
     return -2.0 * area * _exp_dd2(th[0], th[1], th[2])
+
+
+def near_values_integrated(prob, nodes, tris, targets, rowptr, cols, n=12, chunk=20000):
+    """C_ij = int_{S_j} dsigma / |x_i - y| - int_{S_j} N_s(|x_i - y|) dsigma for
+    the pairs of a CSR pattern: the exact integral in closed form, the smooth
+    kernel's by the collapsed rule with n x n points."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    targets = np.asarray(targets, dtype=np.float64)
+    rows = np.repeat(np.arange(len(rowptr) - 1), np.diff(rowptr))
+    j = np.asarray(cols, dtype=np.int64)
+    x = targets[rows]
+    exact = nearfield.triangle_potential(x, nodes[tris[j, 0]], nodes[tris[j, 1]], nodes[tris[j, 2]])
+    pts, wts = triangle_points(nodes, tris, n)
+    smooth = np.zeros(j.size)
+    for a in range(0, j.size, chunk):
+        b = min(j.size, a + chunk)
+        r = np.linalg.norm(x[a:b, None, :] - pts[j[a:b]], axis=2)
+        smooth[a:b] = np.sum(wts[j[a:b]] * nearfield.smooth_kernel(prob, r), axis=1)
+    return exact - smooth
+
+
+def phi_near_integrated(prob, nodes, tris, eps, targets=None, n=12):
+    """phi_NF at the targets with the values of `near_values_integrated` over
+    the index sets of eq. nf_index. Returns (phi, rowptr, cols, vals)."""
+    tg = nodes if targets is None else targets
+    rowptr, cols, _ = nearfield.near_pairs(nodes, tris, tg, eps)
+    vals = near_values_integrated(prob, nodes, tris, tg, rowptr, cols, n)
+    gj = element_density(prob, tris.shape[0])
+    rows = np.repeat(np.arange(len(rowptr) - 1), np.diff(rowptr))
+    phi = np.bincount(rows, weights=vals * gj[cols], minlength=len(rowptr) - 1) / nufft.FOUR_PI
+    return phi, rowptr, cols, vals

@@ -80,6 +80,21 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
   }
 }
 
+// The collapsed Gauss rule on the unit triangle, [order^2][3]: xi_1 = u (1 - v),
+// xi_2 = u v, weight w_u w_v u (weights sum to 1/2).
+std::vector<double> collapsed_rule(int order) {
+  std::vector<double> glx, glw, rule;
+  gauss_legendre(order, glx, glw);
+  for (int a = 0; a < order; ++a)
+    for (int b = 0; b < order; ++b) {
+      const double u = 0.5 * (glx[a] + 1.0), v = 0.5 * (glx[b] + 1.0);
+      rule.push_back(u * (1.0 - v));
+      rule.push_back(u * v);
+      rule.push_back(0.25 * glw[a] * glw[b] * u);
+    }
+  return rule;
+}
+
 // Stable counting sort of items by bin id; returns order (sorted -> item) and
 // bin_start [nbins + 1].
 void counting_sort(const std::vector<int32_t> &bin, int64_t nbins, std::vector<int32_t> &order,
@@ -156,6 +171,7 @@ struct slp_geom {
   std::vector<int64_t> nf_rows;  // host: pairs per row (to strip the padding on copies)
   void *nf_vals = nullptr;
   double *nf_gbar = nullptr;     // [cap][M] element means of the densities
+  int32_t nf_rule = 0;           // integrated-gridding order the values were built for (0: points)
   // integrated-window gridding (slp_setup_integrated_gridding): the window
   // integrated over each triangle, by cell of the region, in the near-field
   // layout; when set, a = A gbar replaces the gridding of the point sources
@@ -422,6 +438,8 @@ slp::NearArgs<T> iw_args(const slp_geom *G) {
 
 template <typename T>
 int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bool tm) {
+  if (G->nf_nnz > 0 && G->nf_rule != G->iw_order)
+    return fail(SLP_EINVAL, "the near field was built for another gridding (set it up again)");
   if (G->iw_order > 0) {
     // integrated-window gridding: a = A gbar (the whole gridding stage; the
     // block-sum stage takes no time)
@@ -1542,8 +1560,6 @@ void drop_iw(slp_geom *G) {
 int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   if (!G) return fail(SLP_EINVAL, "NULL geometry");
   if (!std::isfinite(eps)) return fail(SLP_EINVAL, "eps must be finite");
-  if (eps > 0.0 && G->iw_order > 0)
-    return fail(SLP_EINVAL, "a near field does not combine with integrated-window gridding");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
@@ -1612,10 +1628,14 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
     if (e == hipSuccess) tmp.p.push_back(*q);
     return e;
   };
+  // with integrated-window gridding the smooth share is the collapsed rule's
+  const std::vector<double> rule = G->iw_order > 0 ? collapsed_rule(G->iw_order) : std::vector<double>();
+  double *d_rule = nullptr;
   if (talloc((void **)&d_tg, G->h_tgt.size() * 8) != hipSuccess ||
       talloc((void **)&d_nodes, G->h_nodes.size() * 8) != hipSuccess ||
       talloc((void **)&d_tris, G->h_tris.size() * 4) != hipSuccess ||
       talloc((void **)&d_terms, (size_t)2 * S * 8) != hipSuccess ||
+      (!rule.empty() && talloc((void **)&d_rule, rule.size() * 8) != hipSuccess) ||
       (packed && talloc((void **)&d_cols, (size_t)stored * 4) != hipSuccess)) {
     drop_near(G);
     return fail(SLP_ENOMEM, "near field: temporary device buffers failed");
@@ -1631,14 +1651,19 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   HIP_TRY(hipMemcpyAsync(d_tris, G->h_tris.data(), G->h_tris.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_terms, G->kept_w.data(), (size_t)S * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_terms + S, G->kept_g.data(), (size_t)S * 8, hipMemcpyHostToDevice, st));
+  if (d_rule) HIP_TRY(hipMemcpyAsync(d_rule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice, st));
+  const int32_t npts = (int32_t)(rule.size() / 3);
+  G->nf_rule = G->iw_order;
   if (G->prec == SLP_FP64) {
     slp::NearArgs<double> na = near_args<double>(G);
     na.cols = d_cols;
-    HIP_TRY(slp::launch_near_values<double>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S, st));
+    HIP_TRY(slp::launch_near_values<double>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S,
+                                            d_rule, npts, st));
   } else {
     slp::NearArgs<float> na = near_args<float>(G);
     na.cols = d_cols;
-    HIP_TRY(slp::launch_near_values<float>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S, st));
+    HIP_TRY(slp::launch_near_values<float>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S,
+                                           d_rule, npts, st));
   }
   HIP_TRY(hipStreamSynchronize(st));   // host vectors and temporaries go out of scope
   return SLP_OK;
@@ -1691,16 +1716,16 @@ int slp_setup_integrated_gridding(slp_geom *G, int32_t order, void *stream) {
   if (!G) return fail(SLP_EINVAL, "NULL geometry");
   if (order < 0 || order > 16) return fail(SLP_EINVAL, "order must be 0 (off) or 1..16, got %d", (int)order);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (order > 0 && G->nf_nnz > 0)
-    return fail(SLP_EINVAL, "integrated-window gridding does not combine with a near field (its values "
-                            "cancel the smooth part of the three-point sources)");
   if (order > 0 && G->use_graph)
     return fail(SLP_EINVAL, "integrated-window gridding does not combine with captured evaluations");
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipDeviceSynchronize());
   G->drop_graphs();
   drop_iw(G);
-  if (order == 0) return SLP_OK;
+  // a near field subtracts the smooth kernel with the gridding's quadrature:
+  // rebuild its values for the new gridding
+  auto rebuild_near = [&]() { return G->nf_eps > 0.0 ? slp_setup_near_field(G, G->nf_eps, stream) : SLP_OK; };
+  if (order == 0) return rebuild_near();
 
   // vertices in grid units, areas, and each triangle's index box
   // {floor(t_min) - m + 1 .. floor(t_max) + m} per axis (eq. indexset2),
@@ -1784,16 +1809,7 @@ int slp_setup_integrated_gridding(slp_geom *G, int32_t order, void *stream) {
   G->iw_stored = L.stored;
   G->iw_rows = rows;
 
-  // the collapsed Gauss rule: xi_1 = u (1 - v), xi_2 = u v, weight w_u w_v u
-  std::vector<double> glx, glw, rule;
-  gauss_legendre(order, glx, glw);
-  for (int a = 0; a < order; ++a)
-    for (int b = 0; b < order; ++b) {
-      const double u = 0.5 * (glx[a] + 1.0), v = 0.5 * (glx[b] + 1.0);
-      rule.push_back(u * (1.0 - v));
-      rule.push_back(u * v);
-      rule.push_back(0.25 * glw[a] * glw[b] * u);
-    }
+  const std::vector<double> rule = collapsed_rule(order);
   struct Temp {
     std::vector<void *> p;
     ~Temp() { for (void *q : p) (void)hipFree(q); }
@@ -1843,7 +1859,7 @@ int slp_setup_integrated_gridding(slp_geom *G, int32_t order, void *stream) {
   }
   HIP_TRY(hipStreamSynchronize(st));   // host vectors and temporaries go out of scope
   G->iw_order = order;
-  return SLP_OK;
+  return rebuild_near();
 }
 
 int slp_integrated_gridding_info(const slp_geom *G, int32_t *order, int64_t *nnz, int64_t *stored,

@@ -158,11 +158,13 @@ struct NearArgs {
   int64_t M;               // triangles; density value s of triangle j at j + s M
 };
 // Fills a.vals from the pattern. targets [rows][3], nodes [n][3], tris [M][3]
-// (device, FP64 physical coordinates); es_w / es_g [terms] the kept terms.
+// (device, FP64 physical coordinates); es_w / es_g [terms] the kept terms;
+// rule [npts][3] the collapsed rule of integrated-window gridding, or null for
+// the three-point rule.
 template <typename T>
 hipError_t launch_near_values(const NearArgs<T> &a, const double *targets, const double *nodes,
                               const int32_t *tris, const double *es_w, const double *es_g,
-                              int32_t terms, hipStream_t s);
+                              int32_t terms, const double *rule, int32_t npts, hipStream_t s);
 // phi_i += 1/(4 pi) sum_j C_ij gbar_j for every batch item, gbar_j =
 // (g_j + g_{j+M} + g_{j+2M}) / 3 formed first into a.gbar (density and
 // potential from the per-item pointers). Up to eight items share one pass over

@@ -932,14 +932,17 @@ hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2
 
 // ------------------------------------------------------------ near field ---
 // One wave per target row; lanes take the row's entries in turn. Padding
-// entries (column -1) get the value 0.
+// entries (column -1) get the value 0. The smooth kernel's share is taken with
+// the gridding's quadrature: the three-point rule, or with integrated-window
+// gridding the collapsed rule `rule` [npts][3] (xi_1, xi_2, weight).
 template <typename T>
 __global__ __launch_bounds__(256) void k_near_values(NearArgs<T> a, const double *__restrict__ tg,
                                                      const double *__restrict__ nodes,
                                                      const int32_t *__restrict__ tris,
                                                      const double *__restrict__ es_w,
                                                      const double *__restrict__ es_g,
-                                                     int32_t terms) {
+                                                     int32_t terms, const double *__restrict__ rule,
+                                                     int32_t npts) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= a.rows) return;
   const int lane = threadIdx.x & 63;
@@ -966,32 +969,49 @@ __global__ __launch_bounds__(256) void k_near_values(NearArgs<T> a, const double
     const double cy = e1v[2] * e2v[0] - e1v[0] * e2v[2];
     const double cz = e1v[0] * e2v[1] - e1v[1] * e2v[0];
     const double area = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
-    // quadrature point s: weight 2/3 on vertex s, 1/6 on the other two
     double smooth = 0.0;
+    if (rule) {
+      for (int p = 0; p < npts; ++p) {
+        const double x1 = rule[3 * p], x2 = rule[3 * p + 1];
+        double r2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-      double r2 = 0.0;
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const double wq0 = (s == 0) ? 4.0 / 6 : 1.0 / 6;
-        const double wq1 = (s == 1) ? 4.0 / 6 : 1.0 / 6;
-        const double wq2 = (s == 2) ? 4.0 / 6 : 1.0 / 6;
-        const double y = wq0 * v[0][q] + wq1 * v[1][q] + wq2 * v[2][q];
-        r2 += (x[q] - y) * (x[q] - y);
+        for (int q = 0; q < 3; ++q) {
+          const double y = v[0][q] + x1 * e1v[q] + x2 * e2v[q];
+          r2 += (x[q] - y) * (x[q] - y);
+        }
+        double ns = 0.0;
+        for (int t = 0; t < terms; ++t) ns += es_w[t] * exp(-es_g[t] * r2);
+        smooth += rule[3 * p + 2] * ns;
       }
-      for (int t = 0; t < terms; ++t) smooth += es_w[t] * exp(-es_g[t] * r2);
+      smooth *= 2.0 * area;
+    } else {
+      // quadrature point s: weight 2/3 on vertex s, 1/6 on the other two
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double wq0 = (s == 0) ? 4.0 / 6 : 1.0 / 6;
+          const double wq1 = (s == 1) ? 4.0 / 6 : 1.0 / 6;
+          const double wq2 = (s == 2) ? 4.0 / 6 : 1.0 / 6;
+          const double y = wq0 * v[0][q] + wq1 * v[1][q] + wq2 * v[2][q];
+          r2 += (x[q] - y) * (x[q] - y);
+        }
+        for (int t = 0; t < terms; ++t) smooth += es_w[t] * exp(-es_g[t] * r2);
+      }
+      smooth *= area / 3.0;
     }
-    a.vals[e] = (T)(exact - area / 3.0 * smooth);
+    a.vals[e] = (T)(exact - smooth);
   }
 }
 
 template <typename T>
 hipError_t launch_near_values(const NearArgs<T> &a, const double *targets, const double *nodes,
                               const int32_t *tris, const double *es_w, const double *es_g,
-                              int32_t terms, hipStream_t s) {
+                              int32_t terms, const double *rule, int32_t npts, hipStream_t s) {
   if (a.rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_near_values<T>, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a,
-                     targets, nodes, tris, es_w, es_g, terms);
+                     targets, nodes, tris, es_w, es_g, terms, rule, npts);
   return hipGetLastError();
 }
 
@@ -1287,10 +1307,12 @@ template hipError_t launch_interp<double>(const InterpArgs<double> &, const Batc
                                           int, hipStream_t);
 template hipError_t launch_near_values<float>(const NearArgs<float> &, const double *,
                                               const double *, const int32_t *, const double *,
-                                              const double *, int32_t, hipStream_t);
+                                              const double *, int32_t, const double *, int32_t,
+                                              hipStream_t);
 template hipError_t launch_near_values<double>(const NearArgs<double> &, const double *,
                                                const double *, const int32_t *, const double *,
-                                               const double *, int32_t, hipStream_t);
+                                               const double *, int32_t, const double *, int32_t,
+                                               hipStream_t);
 template hipError_t launch_near_apply<float>(const NearArgs<float> &, const BatchPtrs &, int,
                                              bool, hipStream_t);
 template hipError_t launch_near_apply<double>(const NearArgs<double> &, const BatchPtrs &, int,

@@ -1,8 +1,9 @@
 """Integrated-window gridding (Sec. 3.1, eq. gridding2, the matrix A) on the
 device: the complete smooth part against the oracle's integrated route on
 spheres and a cube in both windows and precisions, batched launches against
-single ones, switching back to the point gridding, and the combinations the
-library refuses."""
+single ones, switching back to the point gridding, the combination with the
+near-field correction (the paper's complete method) against the oracle and
+the exact surface integrals, and the combination the library refuses."""
 import numpy as np
 import pytest
 
@@ -78,18 +79,52 @@ def test_integrated_batched_equals_single():
     G.close()
 
 
+def test_integrated_gridding_with_near_field():
+    """The paper's complete method: integrated-window gridding plus the
+    near-field correction whose smooth share is integrated with the same rule.
+    Against the oracle's integrated route (10^-6), the exact surface integrals
+    (the Fourier error), in either setup order; switching the gridding off
+    rebuilds the near field for the point sources."""
+    from oracle import nearfield as nfo
+    wl = sphere_random(2, 4, 64, 8)
+    prob = direct.prepare_workload(wl)
+    eps = nfo.near_radius(prob, 1e-3, wl.es_r_hi)
+    log(f"case integrated + near field sphere_l2, eps {eps:.4f}")
+    d = torch.as_tensor(wl.dens).cuda()
+    G = _geometry(wl, 8, slp.FP64, slp.WINDOW_GAUSS)
+    G.setup_integrated_gridding(8)
+    G.setup_near_field(eps)
+    got = G.solve(d).cpu().numpy()
+    G2 = _geometry(wl, 8, slp.FP64, slp.WINDOW_GAUSS)
+    G2.setup_near_field(eps)
+    point = G2.solve(d).cpu().numpy()
+    G2.setup_integrated_gridding(8)
+    got2 = G2.solve(d).cpu().numpy()
+    torch.cuda.synchronize()
+    near_i, *_ = iwo.phi_near_integrated(prob, wl.nodes, wl.tris, eps, n=12)
+    ref = iwo.phi_integrated(prob, wl.nodes, wl.tris, 8, "gauss", 12) + near_i
+    gbar = nfo.element_mean_density(prob, wl.tris.shape[0])
+    exact = nfo.phi_exact_integrals(wl.nodes, wl.tris, gbar, wl.nodes)
+    e = rel_l2(got, ref)
+    ex_i = np.abs(got - exact).max() / np.abs(exact).max()
+    ex_3 = np.abs(point - exact).max() / np.abs(exact).max()
+    log(f"  rel-L2 vs oracle {e:.3e}; vs exact integrals: integrated {ex_i:.3e}, three-point {ex_3:.3e}")
+    assert e <= 1e-6 and rel_l2(got2, got) <= 1e-13
+    assert ex_i <= 2e-4 and ex_3 >= 10 * ex_i
+    # back to the point sources: the near field follows
+    G.setup_integrated_gridding(0)
+    back = G.solve(d).cpu().numpy()
+    assert rel_l2(back, point) <= 1e-13
+    G.close()
+    G2.close()
+
+
 def test_integrated_gridding_refusals():
     wl = sphere_random(2, 4, 32, 4)
     G = _geometry(wl, 4, slp.FP64, slp.WINDOW_KB)
     with pytest.raises(slp.SlpError, match="order"):
         G.setup_integrated_gridding(17)
     G.setup_integrated_gridding(4)
-    with pytest.raises(slp.SlpError, match="near field"):
-        G.setup_near_field(0.3)
     with pytest.raises(slp.SlpError, match="captured"):
         slp.set_graph(G.handle, True)
-    G.setup_integrated_gridding(0)
-    G.setup_near_field(0.3)
-    with pytest.raises(slp.SlpError, match="near field"):
-        G.setup_integrated_gridding(4)
     G.close()

@@ -114,3 +114,35 @@ def test_gridding_is_additive_under_subdivision():
     prob2.g = np.concatenate([gk, gk, gk])
     a2 = iw.gridding_integrated(prob2, nodes2, tris2, 6, "kb", n=12)
     assert np.abs(a2 - a).max() <= 1e-10 * np.abs(a).max()
+
+
+def test_integrated_near_field_pins():
+    """The near-field values with the smooth kernel integrated over S_j: beyond
+    the radius where the kept exponential sum matches 1/r to tol, a pair's
+    value is at most tol times the exact integral of 1/r; and the complete
+    route (integrated gridding plus this near field) meets the exact surface
+    integrals of the element-constant density to the Fourier error, while the
+    three-point route misses them by its quadrature error on this coarse
+    sphere."""
+    from oracle import nearfield as nfo
+    from synth.workloads import sphere_random
+    wl = sphere_random(2, 4, 64, 8)
+    prob = direct.prepare_workload(wl)
+    tol = 1e-3
+    eps = nfo.near_radius(prob, tol, wl.es_r_hi)
+    rp, cols, dist = nfo.near_pairs(wl.nodes, wl.tris, wl.nodes, 2.0 * eps)
+    vals = iw.near_values_integrated(prob, wl.nodes, wl.tris, wl.nodes, rp, cols, n=12)
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    exact_pair = nfo.triangle_potential(wl.nodes[rows], *(wl.nodes[wl.tris[cols, k]] for k in range(3)))
+    far = dist >= eps
+    assert far.sum() > 1000
+    assert np.all(np.abs(vals[far]) <= tol * exact_pair[far])
+    gbar = nfo.element_mean_density(prob, wl.tris.shape[0])
+    exact = nfo.phi_exact_integrals(wl.nodes, wl.tris, gbar, wl.nodes)
+    near_i, *_ = iw.phi_near_integrated(prob, wl.nodes, wl.tris, eps, n=12)
+    comp_i = iw.phi_integrated(prob, wl.nodes, wl.tris, 8, "gauss", 12) + near_i
+    near_3, *_ = nfo.phi_near(prob, wl.nodes, wl.tris, eps)
+    comp_3 = direct.phi_ndft(prob) + near_3
+    scale = np.abs(exact).max()
+    assert np.abs(comp_i - exact).max() <= 2e-4 * scale
+    assert np.abs(comp_3 - exact).max() >= 10 * np.abs(comp_i - exact).max()
