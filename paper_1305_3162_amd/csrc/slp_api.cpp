@@ -881,13 +881,20 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     sincell[k] = inc;
     skey[k] = tile * 512 + ((inc & 7) + 8 * ((inc >> 4) & 7) + 64 * (inc >> 8));
   }
+  // targets by (tile, cell in tile): the targets of one cell are consecutive,
+  // so that the interpolation can read their shared stencil rows once
   for (int64_t i = 0; i < n_tgt; ++i) {
     int32_t tile, inc;
     cell_key(&tt[3 * i], &tile, &inc);
-    tbin[i] = tile;
+    tbin[i] = tile * 512 + ((inc & 7) + 8 * ((inc >> 4) & 7) + 64 * (inc >> 8));
   }
   counting_sort(skey, ntiles * 512, sorder, sstart);
-  counting_sort(tbin, ntiles, torder, tstart);
+  {
+    std::vector<int32_t> cstart;
+    counting_sort(tbin, ntiles * 512, torder, cstart);
+    tstart.resize(ntiles + 1);
+    for (int64_t t = 0; t <= ntiles; ++t) tstart[t] = cstart[t * 512];
+  }
   std::vector<double> wsorted(Ms);
   for (int64_t i = 0; i < Ms; ++i) wsorted[i] = wsrc[sorder[i]];
 

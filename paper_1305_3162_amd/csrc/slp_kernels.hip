@@ -421,9 +421,10 @@ hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &
 // ----------------------------------------------------------------- interp ---
 // One workgroup per tile holding targets: the grid values of the tile plus the
 // stencil halo are staged in LDS, the 1-D factors of a batch of 64 targets are
-// computed, then each wave takes one target at a time: its lanes cover the
-// (dy, dz) rows of the stencil, sum the 2m values of each row in T and
-// accumulate row * wy * wz in FP64; a wave reduction gives the node value.
+// computed, then each wave takes its targets one at a time, or two of one
+// cell together: its lanes cover the (dy, dz) rows of the stencil, sum the
+// 2m values of each row in T and accumulate row * wy * wz in FP64; a wave
+// reduction gives the node value.
 template <typename T, int M>
 struct InterpShape {
   static constexpr int W = 2 * M;
@@ -526,13 +527,25 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
     __syncthreads();
     // each wave takes TPW targets of the batch and reduces their sums together,
     // so the latency of the cross-lane reduction is paid once per TPW targets
+    // each wave takes TPW consecutive targets of the batch (sorted by cell);
+    // two consecutive targets of one cell read each stencil row once. A
+    // target's sum is formed in the same order either way.
     constexpr int TPW = S::TB / S::WAVES;
     double acc[TPW];
 #pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = 0.0;
+    const int sb = wave * TPW;
+    bool consumed = false;   // the previous slot took this target as its pair
+#pragma unroll
     for (int q = 0; q < TPW; ++q) {
-      const int s = wave + q * S::WAVES;
-      acc[q] = 0.0;
+      if (consumed) {
+        consumed = false;
+        continue;
+      }
+      const int s = sb + q;
       if (s >= nb) continue;
+      const bool two = q + 1 < TPW && s + 1 < nb && tcell[s + 1][0] == tcell[s][0] &&
+                       tcell[s + 1][1] == tcell[s][1] && tcell[s + 1][2] == tcell[s][2];
       const int cx = tcell[s][0] - tx * kTile, cy = tcell[s][1] - ty * kTile,
                 cz = tcell[s][2] - tz * kTile;
       // x factors are the same for every lane: one LDS read per lane, then
@@ -541,16 +554,40 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
       T wx[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) wx[j] = read_lane(wxl, j);
-      for (int r = lane; r < W * W; r += 64) {
-        const int dy = r % W, dz = r / W;
-        const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
-        T s0 = T(0), s1 = T(0);
+      if (two) {
+        const int q1 = q + 1 < TPW ? q + 1 : q;
+        const T wxl1 = wts[s + 1][0][lane % W];
+        T wx1[W];
 #pragma unroll
-        for (int j = 0; j < W; j += 2) {
-          s0 += row[j] * wx[j];
-          s1 += row[j + 1] * wx[j + 1];
+        for (int j = 0; j < W; ++j) wx1[j] = read_lane(wxl1, j);
+        for (int r = lane; r < W * W; r += 64) {
+          const int dy = r % W, dz = r / W;
+          const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
+          T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
+#pragma unroll
+          for (int j = 0; j < W; j += 2) {
+            const T g0 = row[j], g1 = row[j + 1];
+            a0 += g0 * wx[j];
+            a1 += g1 * wx[j + 1];
+            b0 += g0 * wx1[j];
+            b1 += g1 * wx1[j + 1];
+          }
+          acc[q] += (double)((a0 + a1) * (wts[s][1][dy] * wts[s][2][dz]));
+          acc[q1] += (double)((b0 + b1) * (wts[s + 1][1][dy] * wts[s + 1][2][dz]));
         }
-        acc[q] += (double)((s0 + s1) * (wts[s][1][dy] * wts[s][2][dz]));
+        consumed = true;
+      } else {
+        for (int r = lane; r < W * W; r += 64) {
+          const int dy = r % W, dz = r / W;
+          const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
+          T a0 = T(0), a1 = T(0);
+#pragma unroll
+          for (int j = 0; j < W; j += 2) {
+            a0 += row[j] * wx[j];
+            a1 += row[j + 1] * wx[j + 1];
+          }
+          acc[q] += (double)((a0 + a1) * (wts[s][1][dy] * wts[s][2][dz]));
+        }
       }
     }
 #pragma unroll
@@ -560,7 +597,7 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
     if (lane == 0) {
 #pragma unroll
       for (int q = 0; q < TPW; ++q) {
-        const int s = wave + q * S::WAVES;
+        const int s = sb + q;
         if (s < nb) phi[tperm[s]] = acc[q];
       }
     }
