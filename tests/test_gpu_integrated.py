@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import paper_1305_3162_amd as slp
-from oracle import direct, integrated as iwo
+from oracle import direct, geometry, integrated as iwo
 from synth.workloads import cube_random, sphere_random
 from slp_testlib import es_for, log, rel_l2
 
@@ -40,6 +40,7 @@ def test_integrated_gridding_against_oracle(name):
     make, m, prec, window, tol = CASES[name]
     wl = make()
     log(f"case integrated {name}: {wl.tris.shape[0]} triangles, grid {wl.grid}")
+    prob = direct.prepare_workload(wl)
     G = _geometry(wl, m, prec, window)
     d = torch.as_tensor(wl.dens).cuda()
     point = G.solve(d).cpu().numpy()
@@ -47,12 +48,19 @@ def test_integrated_gridding_against_oracle(name):
     info = G.integrated_gridding_info()
     got = G.solve(d).cpu().numpy()
     torch.cuda.synchronize()
-    prob = direct.prepare_workload(wl)
     ref = iwo.phi_integrated(prob, wl.nodes, wl.tris, m, "kb" if window == slp.WINDOW_KB else "gauss",
                              n=12)
     e = rel_l2(got, ref)
     log(f"  {info}; rel-L2 vs oracle {e:.3e}; integrated vs point gridding {rel_l2(got, point):.3e}")
-    assert info["order"] == 8 and info["nnz"] > 0
+    assert info["order"] == 8
+    # one stored integral per (triangle, cell of its index box), eq. indexset2:
+    # floor(t_min) - m + 1 .. floor(t_max) + m per axis, t the vertices in grid units
+    t = (geometry.to_torus(wl.nodes, prob.c, prob.s) + 0.5) * np.asarray(wl.grid, dtype=np.float64)
+    tv = t[wl.tris]                                   # [M, 3 vertices, 3 axes]
+    # (vertices on a cell face may round either way: bounds with t -/+ 1e-9)
+    lo = np.floor(tv.max(axis=1) - 1e-9) - np.floor(tv.min(axis=1) + 1e-9) + 2 * m
+    hi = np.floor(tv.max(axis=1) + 1e-9) - np.floor(tv.min(axis=1) - 1e-9) + 2 * m
+    assert int(np.prod(lo, axis=1).sum()) <= info["nnz"] <= int(np.prod(hi, axis=1).sum())
     assert np.all(np.isfinite(got)) and e <= tol
     # the route changed (three-point quadrature vs the window integral)
     assert rel_l2(got, point) > 1e-9
