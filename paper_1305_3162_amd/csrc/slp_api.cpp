@@ -198,9 +198,9 @@ struct slp_geom {
   std::vector<Captured> graphs;
   hipStream_t cap_stream = nullptr;
   void drop_graphs() {
-    for (Captured &c : graphs) {
-      if (c.exec) (void)hipGraphExecDestroy(c.exec);
-      if (c.graph) (void)hipGraphDestroy(c.graph);
+    for (Captured &cg : graphs) {
+      if (cg.exec) (void)hipGraphExecDestroy(cg.exec);
+      if (cg.graph) (void)hipGraphDestroy(cg.graph);
     }
     graphs.clear();
   }
@@ -1006,9 +1006,9 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   // the segments of one tile are consecutive (sources sorted by tile)
   std::vector<int2> tile_slots(ntiles, int2{0, 0});
   for (size_t sgi = 0; sgi < segs.size(); ++sgi) {
-    int2 &ts = tile_slots[segs[sgi].z];
-    if (ts.y == 0) ts.x = (int)sgi;
-    ts.y += 1;
+    int2 &slot = tile_slots[segs[sgi].z];
+    if (slot.y == 0) slot.x = (int)sgi;
+    slot.y += 1;
   }
   G->n_units = (int32_t)n_units;
   G->n_slots = (int32_t)segs.size();

@@ -90,12 +90,12 @@ struct slp_fem {
   std::vector<int64_t> alloc_bytes;
   hipError_t alloc(void **p_, size_t n) {
     *p_ = nullptr;
-    const size_t b = std::max<size_t>(n, 256);
-    hipError_t e = hipMalloc(p_, b);
+    const size_t sz = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(p_, sz);
     if (e == hipSuccess) {
       allocs.push_back(*p_);
-      alloc_bytes.push_back((int64_t)b);
-      bytes += (int64_t)b;
+      alloc_bytes.push_back((int64_t)sz);
+      bytes += (int64_t)sz;
     }
     return e;
   }

@@ -195,8 +195,8 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
         const int i = tid + k * S::THREADS;
         if (i < 4 * ch.y) {
           const int comp = i / ch.y, sl = i - comp * ch.y;
-          const int64_t src = (int64_t)ch.x + sl;
-          v[k] = comp < 3 ? a.frac[comp * ns + src] : (T)(a.w[src] * dens[a.perm[src]]);
+          const int64_t si = (int64_t)ch.x + sl;
+          v[k] = comp < 3 ? a.frac[comp * ns + si] : (T)(a.w[si] * dens[a.perm[si]]);
         }
       }
       if (tid < ch.w) rv = a.runs[ch.z + tid];
@@ -300,7 +300,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
 #pragma unroll
           for (int t = 0; t < W; ++t)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) atomicAdd(base + 4 * q * PD * PD + t * PD, macc[t][q]);
+            for (int rg = 0; rg < 4; ++rg) atomicAdd(base + 4 * rg * PD * PD + t * PD, macc[t][rg]);
         } else {
 #pragma unroll
           for (int p = 0; p < NP; ++p) {
@@ -563,17 +563,17 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
         for (int r = lane; r < W * W; r += 64) {
           const int dy = r % W, dz = r / W;
           const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
-          T a0 = T(0), a1 = T(0), b0 = T(0), b1 = T(0);
+          T a0 = T(0), a1 = T(0), c0 = T(0), c1 = T(0);
 #pragma unroll
           for (int j = 0; j < W; j += 2) {
             const T g0 = row[j], g1 = row[j + 1];
             a0 += g0 * wx[j];
             a1 += g1 * wx[j + 1];
-            b0 += g0 * wx1[j];
-            b1 += g1 * wx1[j + 1];
+            c0 += g0 * wx1[j];
+            c1 += g1 * wx1[j + 1];
           }
           acc[q] += (double)((a0 + a1) * (wts[s][1][dy] * wts[s][2][dz]));
-          acc[q1] += (double)((b0 + b1) * (wts[s + 1][1][dy] * wts[s + 1][2][dz]));
+          acc[q1] += (double)((c0 + c1) * (wts[s + 1][1][dy] * wts[s + 1][2][dz]));
         }
         consumed = true;
       } else {
