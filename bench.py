@@ -82,6 +82,10 @@ def parse():
                          "(degrees, about the axis (1,1,1)) every step and phi_1 starts from the "
                          "previous step's solution")
     ap.add_argument("--rho", type=float, default=0.8, help="offered load / capacity")
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="time the gridding split candidates before the timed region and use "
+                         "the fastest (cube workloads and --mix32); results are cached in this "
+                         "JSON file ('-' for no file)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy this many MiB device-to-device (a kernel of known "
                          "traffic, to scale hardware byte counters)")
@@ -298,7 +302,11 @@ def mix32(args):
             w, g = slp.expsum_sinc(0.2, r_lo, r_hi, 1e-12)
             cache[L] = (nodes, tris, w, g, grid_rule(nodes, tris))
         nodes, tris, w, g, N = cache[L]
-        geos.append(slp.Geometry(nodes, tris, (N,) * 3, m, w, g, 2, prec))
+        share = 0
+        if args.autotune:
+            share = tuned_share(args, nodes, tris, (N,) * 3, m, w, g, 2, prec, 37.0,
+                                slp.WINDOW_GAUSS, None)["seg_share"]
+        geos.append(slp.Geometry(nodes, tris, (N,) * 3, m, w, g, 2, prec, seg_share=share))
         mf = RandomSmoothMagnetisation(4101 + i, nodes.min(0), nodes.max(0))
         dens.append(torch.as_tensor(density_from_magnetisation(nodes, tris, mf), device="cuda"))
         phis.append(torch.empty(nodes.shape[0], dtype=torch.float64, device="cuda"))
@@ -337,7 +345,8 @@ def mix32(args):
         "config": {"workload": "32 icospheres, levels uniform in 2..6 (seed 4100), seeded "
                                "magnetisations 4101-4132, grid clamp(prevpow2(1/mean scaled "
                                "edge), 64, 512)^3 per mesh", "m": m,
-                   "levels": [int(x) for x in levels], "points": pts},
+                   "levels": [int(x) for x in levels], "points": pts,
+                   "gridding_split": "autotuned" if args.autotune else "automatic"},
     }
     print(json.dumps(rec), flush=True)
 
@@ -490,6 +499,16 @@ def potential(args):
     F.close()
 
 
+def tuned_share(args, nodes, tris, grid, m, w, g, alpha, prec, eta2, window, targets):
+    """The autotuner's split for this workload (timed now or read from the cache)."""
+    from paper_1305_3162_amd import autotune
+    cache = None if args.autotune == "-" else args.autotune
+    r = autotune.tune_share(nodes, tris, grid, m, w, g, alpha, prec, eta2, window=window,
+                            targets=targets, cache=cache)
+    return {"seg_share": r["seg_share"], "auto_share": r["auto_share"], "cached": r["cached"],
+            "candidates_us": {str(c["seg_share"]): round(c["us"], 2) for c in r["candidates"]}}
+
+
 def main():
     args = parse()
     if args.potential:
@@ -546,8 +565,13 @@ def main():
         if args.workload != "cube64":
             sys.exit("bench.py: --volume-targets needs the cube64 workload")
         targets = cube_volume_nodes(64)
+    tune = None
+    if args.autotune:
+        tune = tuned_share(args, wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2,
+                           slp.WINDOW_KB if kb else slp.WINDOW_GAUSS, targets)
     geom = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2,
-                        window=slp.WINDOW_KB if kb else slp.WINDOW_GAUSS, targets=targets)
+                        window=slp.WINDOW_KB if kb else slp.WINDOW_GAUSS, targets=targets,
+                        seg_share=tune["seg_share"] if tune else 0)
     near_cfg = None
     if args.near_tol is not None:
         t1 = time.perf_counter()
@@ -567,6 +591,7 @@ def main():
                   "packed_columns": iwi["packed"], "setup_s": round(time.perf_counter() - t1, 3),
                   "device_bytes": slp.geom_get_info(geom.handle)["device_bytes"]}
     n_tgt = geom.info["n_targets"]
+    geom_share, geom_segments = int(geom.info["seg_share"]), int(geom.info["n_segments"])
     info = dict(geom.info)
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     info["_stored"] = 0 if near_cfg is None else near_cfg["stored"]
@@ -732,7 +757,9 @@ def main():
                                if args.workload == "cube64" else wl.name,
                    "m": m, "window": args.window, "precision": args.precision, "points": pts,
                    "densities_per_step": nb, "near_field": near_cfg,
-                   "integrated_gridding": iw_cfg},
+                   "integrated_gridding": iw_cfg,
+                   "gridding_split": {"seg_share": geom_share, "segments": geom_segments,
+                                      "autotune": tune}},
         "rel_l2_err_vs_oracle": rel_err,
         "err_kind": ("relative L2 over all targets" if near_cfg is None else
                      "max |error| over 8 seeded rows / max |phi| (oracle near field per row)")

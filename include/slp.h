@@ -77,6 +77,13 @@ typedef struct {
   int32_t window;         /* slp_window: SLP_WINDOW_GAUSS (0) or SLP_WINDOW_KB (1), Sec. 3.2 */
   double eta2;            /* keep term t iff (pi n_q/2)^2 s_q^2 / gamma_t >= eta2 on every axis
                              (Sec. 5, eq. error_est3: eta^2 bounds the Fourier tail); 37 by default */
+  int32_t seg_share;      /* gridding work split (no effect on the result beyond rounding
+                             order): a tile holding more than 1.5 x seg_share sources is cut
+                             into pieces of about seg_share sources, each gridded by its own
+                             workgroup into its own block. 0 = automatic (the chip's
+                             workgroup slots shared out evenly, at least 300); otherwise
+                             64 <= seg_share <= 2^24 (EINVAL outside). A timing autotuner
+                             sets it; the automatic value is reported in slp_geom_info. */
 } slp_params;
 
 typedef struct slp_geom slp_geom;   /* opaque; owns device tables and work buffers */
@@ -94,6 +101,8 @@ typedef struct {
   int32_t extent[3];      /* its length per axis */
   int32_t tiles[3];       /* 8^3 tiles covering the region */
   int64_t device_bytes;   /* device memory held by the context */
+  int64_t seg_share;      /* sources per gridding piece in effect (see slp_params) */
+  int64_t n_segments;     /* gridding workgroups (padded blocks) per density */
 } slp_geom_info;
 
 /* Setup phase of Alg. 1 for one surface (Sec. 3.1-3.3). Scales the body into

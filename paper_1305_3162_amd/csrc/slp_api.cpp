@@ -123,6 +123,7 @@ struct slp_geom {
   int32_t lo[3]{}, R[3]{}, P[3]{}, tiles[3]{}, K[3]{};
   int32_t terms_kept = 0;
   int32_t n_slots = 0;           // segments (padded gridding blocks)
+  int64_t share = 0;             // sources per segment piece in effect
   int32_t n_units = 0;           // gridding work units (workgroups per item)
   int32_t cap = 1;               // batch items the per-item buffers hold
   int64_t item_elems[5]{};       // per item: scratch, grid_a, S1 (complex), S2 (complex), grid_g
@@ -279,6 +280,9 @@ int validate_params(const slp_params *p) {
       return fail(SLP_EINVAL, "exponential sum term %d is not finite / gamma <= 0", t);
   if (!(p->eta2 > 0.0) || !std::isfinite(p->eta2))
     return fail(SLP_EINVAL, "eta2 must be positive and finite");
+  if (p->seg_share != 0 && (p->seg_share < 64 || p->seg_share > (1 << 24)))
+    return fail(SLP_EINVAL, "seg_share must be 0 (automatic) or in [64, 2^24] (got %d)",
+                p->seg_share);
   return SLP_OK;
 }
 
@@ -911,7 +915,10 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       1, std::min<int64_t>((int64_t)slp::kComputeUnits * per_cu, Ms / min_src));
   // (a share below ~300 sources makes storing and summing the extra blocks cost
   // more than the better balance gains, measured on MI355X for m = 4..8)
-  const int64_t share = std::max<int64_t>(300, (Ms + max_units - 1) / max_units);
+  const int64_t share = p->seg_share > 0
+                            ? (int64_t)p->seg_share
+                            : std::max<int64_t>(300, (Ms + max_units - 1) / max_units);
+  G->share = share;
   std::vector<int4> segs, chunks;
   std::vector<int32_t> runs;
   std::vector<int64_t> seg_size;
@@ -1352,6 +1359,8 @@ int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
   info->n_src = G->n_src;
   info->terms_kept = G->terms_kept;
   info->device_bytes = G->bytes;
+  info->seg_share = G->share;
+  info->n_segments = G->n_slots;
   return SLP_OK;
 }
 

@@ -71,6 +71,30 @@ def test_integrated_gridding_against_oracle(name):
     G.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(slp.FP64, 1e-6), (slp.FP32, 1e-4)])
+def test_integrated_gridding_volume_targets(prec, tol):
+    """Every node of the 16-cell tetrahedral lattice of the cube as an
+    evaluation point (the paper's targets), with integrated-window gridding,
+    against the oracle's integrated route at the same points."""
+    from synth import cube_volume_nodes
+    wl = cube_random(16, 2, 64, 4)
+    tg = cube_volume_nodes(16)
+    log(f"case integrated volume targets prec={prec}: {tg.shape[0]} points")
+    prob = direct.prepare(wl.nodes, wl.tris, wl.dens, wl.grid, wl.alpha, wl.es_h, wl.es_r_lo,
+                          wl.es_r_hi, wl.es_tol, wl.eta2, targets=tg)
+    w, g = es_for(wl)
+    G = slp.Geometry(wl.nodes, wl.tris, wl.grid, 4, w, g, wl.alpha, prec, wl.eta2,
+                     window=slp.WINDOW_KB, targets=tg)
+    G.setup_integrated_gridding(8)
+    got = G.solve(torch.as_tensor(wl.dens).cuda()).cpu().numpy()
+    torch.cuda.synchronize()
+    ref = iwo.phi_integrated(prob, wl.nodes, wl.tris, 4, "kb", n=12)
+    e = rel_l2(got, ref)
+    log(f"  rel-L2 vs oracle {e:.3e}")
+    assert got.shape == (tg.shape[0],) and e <= tol
+    G.close()
+
+
 def test_integrated_batched_equals_single():
     wl = sphere_random(2, 7, 32, 6)
     G = _geometry(wl, 6, slp.FP64, slp.WINDOW_GAUSS)
