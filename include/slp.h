@@ -81,7 +81,8 @@ typedef struct {
                              order): a tile holding more than 1.5 x seg_share sources is cut
                              into pieces of about seg_share sources, each gridded by its own
                              workgroup into its own block. 0 = automatic (the chip's
-                             workgroup slots shared out evenly, at least 300); otherwise
+                             workgroup slots shared out evenly, at least 300 sources, 150
+                             for FP64 with m = 8); otherwise
                              64 <= seg_share <= 2^24 (EINVAL outside). A timing autotuner
                              sets it; the automatic value is reported in slp_geom_info. */
 } slp_params;

@@ -906,18 +906,25 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   // more than 1.5x the average share of one workgroup slot of the chip (every
   // CU holding as many gridding workgroups as its LDS allows). Each segment is
   // cut into chunks of <= kSpreadChunk sources and runs of sources sharing one
-  // cell. (At least max(64, (8 + 2m - 1)^3 / 20) sources per share, so that
+  // cell. (At least max(64, (8 + 2m - 1)^3 / 20) sources per share, / 80 for the
+  // matrix-core form, so that
   // small problems do not pay more for storing and summing blocks than for
   // gridding.)
   const int per_cu = slp::spread_units_per_cu(G->m, G->prec == SLP_FP64);
-  const int64_t min_src = std::max<int64_t>(64, slp::pad_cells(G->m) / 20);
+  // The matrix-core form (FP64, 2m = 16) grids a source several times faster
+  // than the vector form, so its pieces pay off down to fewer sources: timed
+  // splits of icospheres of 1.5e4 and 6.1e4 sources ran 19% and 9% faster at
+  // about 150 sources per piece than at the vector form's floor.
+  const bool mx = G->prec == SLP_FP64 && G->m == 8;
+  const int64_t min_src = std::max<int64_t>(64, slp::pad_cells(G->m) / (mx ? 80 : 20));
   const int64_t max_units = std::max<int64_t>(
       1, std::min<int64_t>((int64_t)slp::kComputeUnits * per_cu, Ms / min_src));
-  // (a share below ~300 sources makes storing and summing the extra blocks cost
-  // more than the better balance gains, measured on MI355X for m = 4..8)
+  // (a share below ~300 sources (150 for the matrix-core form) makes storing and
+  // summing the extra blocks cost more than the better balance gains, measured
+  // on MI355X for m = 4..8)
   const int64_t share = p->seg_share > 0
                             ? (int64_t)p->seg_share
-                            : std::max<int64_t>(300, (Ms + max_units - 1) / max_units);
+                            : std::max<int64_t>(mx ? 150 : 300, (Ms + max_units - 1) / max_units);
   G->share = share;
   std::vector<int4> segs, chunks;
   std::vector<int32_t> runs;
