@@ -394,8 +394,9 @@ int slp_amg_apply_host(int64_t n, const int64_t *rowptr, const int32_t *cols, co
 /* phi_1 at every node (0 on the boundary): load vector b_k = sum_T |T| mbar_T .
  * grad eta_k (m the nodal P1 field, mbar_T its vertex mean), then
  * preconditioned conjugate gradients on the free nodes until |r| <= tol |b|
- * (checked every 16 iterations with Jacobi, every 4 with the multigrid cycle)
- * or max_iter iterations.
+ * or max_iter iterations. The residual is checked every 16 iterations with
+ * Jacobi; with the multigrid cycle after 4 and 8 iterations, then where the
+ * rate between the last two checks predicts tol (1 to 8 iterations later).
  *   m_nodes : device float64 [n_nodes][3];  phi1 : device float64 [n_nodes]
  *   warm_start != 0: start from the free-node values phi1 holds
  *   iters, rel_res : receive the iterations done and |r|/|b| (may be NULL)

@@ -593,9 +593,15 @@ int solve_impl(slp_fem *F, const double *m, double *phi1, double tol, int32_t ma
     // is not formed, so check after the first block of iterations (shorter
     // with the multigrid cycle, which converges in tens of iterations)
     const int32_t every = amg ? 4 : 16;
-    double bb = -1.0;
+    // With the multigrid cycle (an iteration costs several checks), from the
+    // second check on the next one is placed where the rate seen between the
+    // last two checks reaches tol (at most two blocks ahead), so a solve stops
+    // within about one iteration of convergence, not one block. Jacobi
+    // iterations cost about as much as a check: every 16.
+    int32_t block = every, it_last = 0;
+    double bb = -1.0, rel_last = -1.0;
     for (it = 0; it < max_iter;) {
-      const int32_t n = std::min(every, max_iter - it);
+      const int32_t n = std::min(block, max_iter - it);
       for (int32_t k = 0; k < n; ++k, ++it) {
         FEM_TRY(slp::launch_pcg_iteration(a, it, st));
         if (amg) {
@@ -612,6 +618,14 @@ int solve_impl(slp_fem *F, const double *m, double *phi1, double tol, int32_t ma
       rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
       if (!std::isfinite(rel)) return fail(SLP_EDEVICE, "conjugate gradients broke down (residual %g)", rel);
       if (rel <= tol) break;
+      block = every;
+      if (amg && rel_last > 0.0 && rel > 0.0 && rel < rel_last) {
+        const double per_it = std::log(rel / rel_last) / (double)(it - it_last);   // < 0
+        const double need = std::ceil(std::log(tol / rel) / per_it);
+        block = (int32_t)std::max(1.0, std::min(need, 2.0 * every));
+      }
+      rel_last = rel;
+      it_last = it;
     }
   }
   FEM_TRY(slp::launch_fem_scatter(F->x, F->node_free, phi1, F->n_nodes, st));

@@ -204,6 +204,36 @@ def test_amg_preconditioner_against_oracle(name):
     F.close()
 
 
+@pytest.mark.parametrize("precond", ["amg"])
+def test_residual_checks_stop_near_convergence(precond):
+    """With the multigrid cycle the residual-check schedule stops within two
+    iterations of the first iterate that meets the tolerance: a solve capped
+    three iterations earlier does not meet it. From zero and from a slightly
+    rotated field's solution (the time stepper's warm start)."""
+    nodes, tets = cube_tets(24)
+    m = _manufactured(nodes)[1]
+    c, s_ = np.cos(0.02), np.sin(0.02)
+    m2 = m @ np.array([[c, -s_, 0.0], [s_, c, 0.0], [0.0, 0.0, 1.0]]).T
+    log(f"case fem check schedule {precond}")
+    F = slp.Fem(nodes, tets, precond=precond)
+    md, md2 = torch.as_tensor(m).cuda(), torch.as_tensor(m2).cuda()
+    tol = 1e-9
+    phi = torch.zeros(nodes.shape[0], dtype=torch.float64, device="cuda")
+    it, rr = F.solve_phi1(md, phi, tol=tol)
+    prev = phi.clone()
+    it_w, rr_w = F.solve_phi1(md2, phi, tol=tol, warm_start=True)
+    torch.cuda.synchronize()
+    log(f"  from zero {it} iterations ({rr:.2e}); warm {it_w} ({rr_w:.2e})")
+    assert rr <= tol and rr_w <= tol and it_w < it
+    for k, start, field in ((it, None, md), (it_w, prev, md2)):
+        if k <= 3:
+            continue
+        p = torch.zeros_like(phi) if start is None else start.clone()
+        with pytest.raises(slp.SlpError, match="no convergence"):
+            F.solve_phi1(field, p, tol=tol, max_iter=k - 3, warm_start=start is not None)
+    F.close()
+
+
 def test_amg_full_size_cube_mesh_and_scalar_potential():
     """cube_tets(64) with the multigrid cycle: the oracle system's residual and
     the manufactured solution as in the Jacobi test, a fraction of the
