@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--integrated", type=int, default=0,
                     help="grid the window integrated over each triangle (the paper's matrix A, "
                          "Sec. 3.1) with this many Gauss points per direction; 0 = point sources")
+    ap.add_argument("--near-storage", choices=["context", "fp64", "fp32"], default="context",
+                    help="precision the near-field values are stored in (the context's by "
+                         "default; fp32 in an FP64 context halves the bytes of the HBM-bound "
+                         "product, the sums stay FP64)")
     ap.add_argument("--near-tol", type=float, default=None,
                     help="add the near-field correction with eps from slp_near_radius(tol)")
     ap.add_argument("--potential", action="store_true",
@@ -140,7 +144,8 @@ def algorithmic_units(stage, info, m, esz):
         nt = info["n_targets"]
         st = info["_stored"]
         colb = 2 * st + 4 * (st // 256) if info["_packed"] else 4 * st
-        return (st * esz + colb + (nt + 1) * 8 + info["n_src"] * 8 + 16 * nt, "byte", "hbm")
+        vsz = info.get("_near_esz", esz)
+        return (st * vsz + colb + (nt + 1) * 8 + info["n_src"] * 8 + 16 * nt, "byte", "hbm")
     raise KeyError(stage)
 
 
@@ -170,6 +175,8 @@ def measured_traffic(args, m, stage, nb):
     key = f"{args.workload}/{args.precision}/{args.window}/m{m}"
     if stage == "near":
         key += f"/near{args.near_tol:g}"
+        if args.near_storage != "context" and args.near_storage != args.precision:
+            key += f"/stored{args.near_storage}"
     if getattr(args, "integrated", 0):
         key += f"/integrated{args.integrated}"
     e = rec["entries"].get(key)
@@ -379,8 +386,9 @@ def potential(args):
     G = slp.Geometry(nodes, F.boundary, (128, 128, 128), m_win, w, g, 2, prec)
     t1 = time.perf_counter()
     eps = G.near_radius(near_tol) if near_tol > 0 else 0.0
+    storage = near_storage(args, slp, prec)
     if eps > 0:
-        G.setup_near_field(eps, stream)
+        G.setup_near_field(eps, stream, storage)
     t_near_setup = time.perf_counter() - t1
     nf = G.near_field_info()
     phi = torch.empty(nodes.shape[0], dtype=torch.float64, device="cuda")
@@ -423,6 +431,7 @@ def potential(args):
     info = dict(G.info)
     info["_n"] = [64, 64, 64]
     info["_stored"], info["_packed"] = nf["stored"], nf["packed"]
+    info["_near_esz"] = 8 if storage == slp.FP64 else 4
     esz = 8 if prec == slp.FP64 else 4
     dom = max(avg, key=avg.get)
     amount, unit, bound = algorithmic_units(dom, info, m_win, esz)
@@ -486,7 +495,8 @@ def potential(args):
                    "time_stepping": ({"rotate_deg_per_step": args.rotate_deg,
                                       "warm_start": True} if warm else None),
                    "near_field": {"tol": near_tol, "eps": round(eps, 6), "pairs": nf["nnz"],
-                                  "stored": nf["stored"], "setup_s": round(t_near_setup, 2)},
+                                  "stored": nf["stored"], "setup_s": round(t_near_setup, 2),
+                                  "values_stored_as": "fp64" if storage == slp.FP64 else "fp32"},
                    "fem_setup_s": round(t_fem_setup, 2), "points": pts},
         "phi2_ms": round(phi2_ms, 4), "phi1_and_rest_ms": round(ms_per_step - phi2_ms, 4),
         "stage_us": {k: round(v * 1e3, 3) for k, v in avg.items()},
@@ -497,6 +507,11 @@ def potential(args):
     print(json.dumps(rec), flush=True)
     G.close()
     F.close()
+
+
+def near_storage(args, slp, prec):
+    """Storage precision of the near-field values for --near-storage."""
+    return {"context": prec, "fp64": slp.FP64, "fp32": slp.FP32}[args.near_storage]
 
 
 def tuned_share(args, nodes, tris, grid, m, w, g, alpha, prec, eta2, window, targets):
@@ -576,10 +591,12 @@ def main():
     if args.near_tol is not None:
         t1 = time.perf_counter()
         eps = geom.near_radius(args.near_tol)
-        geom.setup_near_field(eps, stream)
+        storage = near_storage(args, slp, prec)
+        geom.setup_near_field(eps, stream, storage)
         nf = geom.near_field_info()
         near_cfg = {"tol": args.near_tol, "eps": round(eps, 6), "pairs": nf["nnz"],
                     "stored": nf["stored"], "packed_columns": nf["packed"],
+                    "values_stored_as": "fp64" if storage == slp.FP64 else "fp32",
                     "setup_s": round(time.perf_counter() - t1, 3),
                     "device_bytes": geom.info["device_bytes"]}
     iw_cfg = None
@@ -596,6 +613,8 @@ def main():
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     info["_stored"] = 0 if near_cfg is None else near_cfg["stored"]
     info["_packed"] = False if near_cfg is None else near_cfg["packed_columns"]
+    if near_cfg is not None:
+        info["_near_esz"] = 8 if near_cfg["values_stored_as"] == "fp64" else 4
     info["_iw_stored"] = 0 if iw_cfg is None else iw_cfg["stored"]
     info["_iw_packed"] = False if iw_cfg is None else iw_cfg["packed_columns"]
     dens = torch.as_tensor(wl.dens, device="cuda")

@@ -263,6 +263,16 @@ int slp_expsum_sinc(double h, double r_lo, double r_hi, double tol, double *omeg
  * host or device memory (the context is left without a near field). */
 int slp_setup_near_field(slp_geom *g, double eps, void *stream);
 
+/* As slp_setup_near_field, with the values C_ij stored in `storage`
+ * (SLP_FP64 or SLP_FP32) whatever the context's precision (slp_setup_near_field
+ * stores them in the context's). They are computed in FP64 either way and
+ * rounded once when stored; the product accumulates in FP64. The product is
+ * bound by HBM, so FP32 storage in an FP64 context moves 4 + 2 instead of
+ * 8 + 2 bytes per packed entry, at a relative rounding of the stored
+ * correction of 2^-24 per entry. The choice persists when the near field is
+ * rebuilt by slp_setup_integrated_gridding. EINVAL for another storage. */
+int slp_setup_near_field_stored(slp_geom *g, double eps, int32_t storage, void *stream);
+
 /* Smallest eps on the scan r_k = r_max * 0.999^k (k = 0, 1, ...), r_max the
  * bounding-box diagonal of nodes and targets, from which up to r_max the kept
  * exponential sum matches 1/r to |N_s(r) r - 1| <= tol at every scan point
@@ -271,7 +281,7 @@ int slp_setup_near_field(slp_geom *g, double eps, void *stream);
 int slp_near_radius(const slp_geom *g, double tol, double *eps);
 
 /* Device bytes slp_setup_near_field(eps) would add for this mesh and these
- * targets (NULL: the nodes) in this precision, computed on the host (index
+ * targets (NULL: the nodes) with values stored in this precision, computed on the host (index
  * sets and storage layout included, so it costs what the setup's host part
  * costs). 0 for eps <= 0 or an empty near field. Used for admission by memory. */
 int slp_near_field_device_bytes(const double *nodes, int64_t n_nodes, const int32_t *tris,

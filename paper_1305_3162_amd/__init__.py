@@ -112,6 +112,7 @@ def load_library():
         "slp_server_get_stats": [_VP, ctypes.POINTER(ServerStats), ctypes.c_int32],
         "slp_server_destroy": [_VP],
         "slp_setup_near_field": [_VP, ctypes.c_double, _VP],
+        "slp_setup_near_field_stored": [_VP, ctypes.c_double, ctypes.c_int32, _VP],
         "slp_near_radius": [_VP, ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
         "slp_near_field_info": [_VP, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
@@ -408,10 +409,15 @@ def debug_copy(geom, which, dst, stream=None):
                                          _stream_ptr(stream)))
 
 
-def setup_near_field(geom, eps, stream=None):
+def setup_near_field(geom, eps, stream=None, storage=None):
     """slp_setup_near_field: near-field correction within physical distance eps
-    (eps <= 0 removes it)."""
-    _check(load_library().slp_setup_near_field(_VP(geom), float(eps), _stream_ptr(stream)))
+    (eps <= 0 removes it); with `storage` (FP64 / FP32) slp_setup_near_field_stored,
+    the values stored in that precision."""
+    if storage is None:
+        _check(load_library().slp_setup_near_field(_VP(geom), float(eps), _stream_ptr(stream)))
+    else:
+        _check(load_library().slp_setup_near_field_stored(_VP(geom), float(eps), int(storage),
+                                                          _stream_ptr(stream)))
 
 
 def near_radius(geom, tol):
@@ -626,8 +632,8 @@ class Geometry:
     def eval(self, phi, stream=None):
         eval_single_layer(self.handle, phi, stream)
 
-    def setup_near_field(self, eps, stream=None):
-        setup_near_field(self.handle, eps, stream)
+    def setup_near_field(self, eps, stream=None, storage=None):
+        setup_near_field(self.handle, eps, stream, storage)
         self.info = geom_get_info(self.handle)
 
     def near_radius(self, tol):

@@ -173,6 +173,7 @@ struct slp_geom {
   void *nf_vals = nullptr;
   double *nf_gbar = nullptr;     // [cap][M] element means of the densities
   int32_t nf_rule = 0;           // integrated-gridding order the values were built for (0: points)
+  int32_t nf_prec = SLP_FP64;    // storage precision of the near-field values
   // integrated-window gridding (slp_setup_integrated_gridding): the window
   // integrated over each triangle, by cell of the region, in the near-field
   // layout; when set, a = A gbar replaces the gridding of the point sources
@@ -426,6 +427,14 @@ slp::NearArgs<T> near_args(const slp_geom *G) {
   return a;
 }
 
+// The near-field product in the values' storage precision (FP32 storage in an
+// FP64 context halves the bytes of the HBM-bound product; the sums stay FP64).
+hipError_t near_apply(const slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
+  if (G->nf_prec == SLP_FP64)
+    return slp::launch_near_apply<double>(near_args<double>(G), ptrs, nb, G->nf_packed, st);
+  return slp::launch_near_apply<float>(near_args<float>(G), ptrs, nb, G->nf_packed, st);
+}
+
 template <typename T>
 slp::NearArgs<T> iw_args(const slp_geom *G) {
   slp::NearArgs<T> a{};
@@ -542,7 +551,7 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
   }
   const bool near = G->nf_nnz > 0;
   if (tm && near) HIP_TRY(hipEventRecord(G->evs()[8], st));
-  if (near) HIP_TRY(slp::launch_near_apply<T>(near_args<T>(G), ptrs, nb, G->nf_packed, st));
+  if (near) HIP_TRY(near_apply(G, ptrs, nb, st));
   if (tm) {
     G->with_near[G->cur] = near;
     HIP_TRY(hipEventRecord(G->evs()[slp_geom::kStages], st));
@@ -581,7 +590,9 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     std::vector<hipGraphNode_t> nodes(n);
     HIP_TRY(hipGraphGetNodes(graph, nodes.data(), &n));
     const void *fs = slp::spread_bins_kernel<T>(G->m), *fi = slp::interp_kernel<T>(G->m);
-    const void *fn = slp::near_apply_kernel<T>(nb, G->nf_packed), *fg = slp::near_gbar_kernel();
+    const void *fn = G->nf_prec == SLP_FP64 ? slp::near_apply_kernel<double>(nb, G->nf_packed)
+                                            : slp::near_apply_kernel<float>(nb, G->nf_packed);
+    const void *fg = slp::near_gbar_kernel();
     for (hipGraphNode_t nd : nodes) {
       hipGraphNodeType ty;
       HIP_TRY(hipGraphNodeGetType(nd, &ty));
@@ -617,7 +628,9 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
   kp.extra = nullptr;
   HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->interp_node, &kp));
   if (cg->near_node) {
-    slp::NearArgs<T> na = near_args<T>(G);
+    // the two argument types differ only in the type of the value pointer
+    slp::NearArgs<double> nad = near_args<double>(G);
+    slp::NearArgs<float> naf = near_args<float>(G);
     int32_t nbv = nb;
     double *gbar = G->nf_gbar;
     int64_t M = G->n_tris;
@@ -626,7 +639,8 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     kp.kernelParams = gargs;
     kp.extra = nullptr;
     HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->gbar_node, &kp));
-    void *nargs[3] = {&na, &p, &nbv};
+    void *nargs[3] = {G->nf_prec == SLP_FP64 ? static_cast<void *>(&nad) : static_cast<void *>(&naf),
+                      &p, &nbv};
     kp = cg->near_p;
     kp.kernelParams = nargs;
     kp.extra = nullptr;
@@ -1582,7 +1596,14 @@ void drop_iw(slp_geom *G) {
 
 int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   if (!G) return fail(SLP_EINVAL, "NULL geometry");
+  return slp_setup_near_field_stored(G, eps, G->prec, stream);
+}
+
+int slp_setup_near_field_stored(slp_geom *G, double eps, int32_t storage, void *stream) {
+  if (!G) return fail(SLP_EINVAL, "NULL geometry");
   if (!std::isfinite(eps)) return fail(SLP_EINVAL, "eps must be finite");
+  if (storage != SLP_FP64 && storage != SLP_FP32)
+    return fail(SLP_EINVAL, "storage must be SLP_FP64 or SLP_FP32");
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(hipStreamSynchronize(st));
   HIP_TRY(hipDeviceSynchronize());     // captured evaluations may still run elsewhere
@@ -1598,6 +1619,7 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
     return fail(SLP_ENOMEM, "%s", err.c_str());
   const int64_t nnz = rowptr.back();
   G->nf_eps = eps;
+  G->nf_prec = storage;
   if (nnz == 0) return SLP_OK;
 
   const int64_t P = G->n_tgt;
@@ -1616,7 +1638,7 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   // triangles, terms (and the int32 columns when packed)
   void *rp = nullptr, *cl = nullptr, *bs = nullptr, *of = nullptr, *vl = nullptr, *gb = nullptr;
   bool ok = G->alloc(&rp, rowptr.size() * sizeof(int64_t)) == hipSuccess &&
-            G->alloc(&vl, (size_t)stored * G->esz()) == hipSuccess &&
+            G->alloc(&vl, (size_t)stored * (storage == SLP_FP64 ? 8 : 4)) == hipSuccess &&
             G->alloc(&gb, (size_t)G->n_tris * 8 * G->cap) == hipSuccess;
   if (ok && packed)
     ok = G->alloc(&bs, bases.size() * sizeof(int32_t)) == hipSuccess &&
@@ -1677,7 +1699,7 @@ int slp_setup_near_field(slp_geom *G, double eps, void *stream) {
   if (d_rule) HIP_TRY(hipMemcpyAsync(d_rule, rule.data(), rule.size() * 8, hipMemcpyHostToDevice, st));
   const int32_t npts = (int32_t)(rule.size() / 3);
   G->nf_rule = G->iw_order;
-  if (G->prec == SLP_FP64) {
+  if (storage == SLP_FP64) {
     slp::NearArgs<double> na = near_args<double>(G);
     na.cols = d_cols;
     HIP_TRY(slp::launch_near_values<double>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S,
@@ -1747,7 +1769,9 @@ int slp_setup_integrated_gridding(slp_geom *G, int32_t order, void *stream) {
   drop_iw(G);
   // a near field subtracts the smooth kernel with the gridding's quadrature:
   // rebuild its values for the new gridding
-  auto rebuild_near = [&]() { return G->nf_eps > 0.0 ? slp_setup_near_field(G, G->nf_eps, stream) : SLP_OK; };
+  auto rebuild_near = [&]() {
+    return G->nf_eps > 0.0 ? slp_setup_near_field_stored(G, G->nf_eps, G->nf_prec, stream) : SLP_OK;
+  };
   if (order == 0) return rebuild_near();
 
   // vertices in grid units, areas, and each triangle's index box
@@ -1938,7 +1962,7 @@ int slp_debug_copy_near(const slp_geom *G, int64_t *rowptr, int32_t *cols, doubl
     HIP_TRY(hipMemcpy(pc.data(), G->nf_cols, (size_t)S * 4, hipMemcpyDeviceToHost));
   }
   if (vals) {
-    if (G->prec == SLP_FP64) {
+    if (G->nf_prec == SLP_FP64) {
       HIP_TRY(hipMemcpy(pv.data(), G->nf_vals, (size_t)S * 8, hipMemcpyDeviceToHost));
     } else {
       std::vector<float> f((size_t)S);

@@ -200,3 +200,56 @@ def test_cube64_full_size_sampled_rows():
         want = far[i] + near_i
         log(f"  row {i}: {a.size} pairs, phi {phi[i]:.9e} oracle {want:.9e}")
         assert abs(phi[i] - want) <= 1e-6 * np.abs(far).max(), i
+
+
+def test_near_field_fp32_storage_in_fp64_context(sphere3):
+    """Values stored in FP32 in an FP64 context (slp_setup_near_field_stored):
+    each stored value is the FP64-stored one rounded once, the potential meets
+    the FP64 gate against the oracle and stays within 10^-7 of the FP64-stored
+    context's, in single, batched and graph-replayed evaluations, and the
+    storage survives the rebuild by integrated-window gridding."""
+    wl, prob, exact, far, eps, (near, *_) = sphere3
+    log("case near sphere_l3 FP64 context, FP32 storage")
+    w, g = es_for(wl)
+    d = torch.as_tensor(wl.dens).cuda()
+    G64 = slp.Geometry(wl.nodes, wl.tris, wl.grid, 8, w, g, wl.alpha, slp.FP64, wl.eta2)
+    G64.setup_near_field(eps)
+    G32 = slp.Geometry(wl.nodes, wl.tris, wl.grid, 8, w, g, wl.alpha, slp.FP64, wl.eta2)
+    G32.setup_near_field(eps, storage=slp.FP32)
+    assert G32.info["device_bytes"] < G64.info["device_bytes"]
+    rp64, c64, v64 = slp.debug_copy_near(G64.handle)
+    rp32, c32, v32 = slp.debug_copy_near(G32.handle)
+    assert np.array_equal(rp64, rp32) and np.array_equal(c64, c32)
+    assert np.array_equal(v32, v64.astype(np.float32).astype(np.float64))
+    ref64 = G64.solve(d).cpu().numpy()
+    got = G32.solve(d).cpu().numpy()
+    torch.cuda.synchronize()
+    e_o, e_64 = rel_l2(got, far + near), rel_l2(got, ref64)
+    log(f"  rel-L2 vs oracle {e_o:.2e}, vs FP64 storage {e_64:.2e}")
+    assert e_o <= 1e-6 and e_64 <= 1e-7 and e_64 > 0.0
+    # batched and graph-replayed evaluations give the single one
+    rng = np.random.default_rng(12)
+    dens = [torch.as_tensor(rng.normal(size=wl.n_src)).cuda() for _ in range(5)]
+    phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda") for _ in dens]
+    slp.eval_batched([G32.handle] * len(dens), dens, phis)
+    singles = [G32.solve(x) for x in dens]
+    slp.set_graph(G32.handle, True)
+    for _ in range(3):
+        replay = [G32.solve(x) for x in dens]
+        torch.cuda.synchronize()
+        for k in range(len(dens)):
+            s_k = singles[k].cpu().numpy()
+            assert rel_l2(phis[k].cpu().numpy(), s_k) <= 1e-14, k
+            assert rel_l2(replay[k].cpu().numpy(), s_k) <= 1e-14, k
+    slp.set_graph(G32.handle, False)
+    # the integrated gridding rebuilds the near field with the same storage
+    G32.setup_integrated_gridding(8)
+    _, _, v32i = slp.debug_copy_near(G32.handle)
+    assert np.array_equal(v32i, v32i.astype(np.float32).astype(np.float64))
+    G32.setup_integrated_gridding(0)
+    _, _, v32b = slp.debug_copy_near(G32.handle)
+    assert np.array_equal(v32b, v32)
+    with pytest.raises(slp.SlpError, match="storage"):
+        G32.setup_near_field(eps, storage=7)
+    G64.close()
+    G32.close()
