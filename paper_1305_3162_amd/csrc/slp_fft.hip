@@ -1,0 +1,368 @@
+// Batched 1-D FFT passes of the pruned 3-D transform (eq. FFT and the
+// inverse transform of the type-2 step; the multiplier of eq. deconv and
+// Alg. 1 fused into the z pass).
+//
+// A pass transforms "lines" of a 3-D array along one axis (FftPass). Each
+// line of length N is held by TL = N / E threads, E complex elements per
+// thread in registers; thread t always holds the positions t + TL i,
+// i = 0 .. E-1. The transform is a Stockham autosort FFT whose stages have
+// radix E (the last one radix N / E^(s-1)): a stage's butterflies are DFTs of
+// size R evaluated in registers, and between stages the line goes once
+// through LDS (write in Stockham order, read back positions t + TL i). The
+// first stage reads its inputs straight from global memory and the last one
+// leaves its outputs in the registers whose positions they belong to, so a
+// 1024-point line costs two LDS round trips (radices 16, 16, 4) instead of
+// five radix-4 passes.
+//
+// Two lane maps:
+//  * contiguous lines (element stride 1, the x passes): the TL threads of a
+//    line are consecutive lanes, so a wave reads consecutive elements;
+//  * strided lines (y and z passes, element stride > 1, consecutive lines
+//    adjacent in memory): consecutive lanes take G consecutive lines at the
+//    same element, so a wave reads runs of G adjacent complex values (at least
+//    64 bytes) instead of one value per cache line. The LDS copy of the lines
+//    is then stored element-major ([position][line]).
+// LDS positions are padded by one slot per R0 (the first radix), which keeps
+// the strided writes of the first exchange free of bank conflicts.
+//
+// Workgroups are renumbered so that each of the eight XCDs (which receive
+// consecutive workgroups round robin and have their own L2) processes a
+// contiguous range of line groups: neighbouring groups share cache lines.
+#include "slp_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace slp {
+
+namespace {
+
+template <typename T>
+struct Cx;
+template <>
+struct Cx<float> { using type = float2; };
+template <>
+struct Cx<double> { using type = double2; };
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+
+// cos(2 pi k / 16) for k = 0..4
+constexpr double kCos16[5] = {1.0, 0.92387953251128675612818318939678829,
+                              0.70710678118654752440084436210484904,
+                              0.38268343236508977172845998403039886, 0.0};
+
+// b * exp(sign 2 pi i q / 16), q = 0..7 (compile-time q)
+template <int SIGN, int Q, typename C>
+__device__ __forceinline__ C rot16(C b) {
+  using T = decltype(b.x);
+  static_assert(Q >= 0 && Q < 8, "rotation index");
+  if constexpr (Q == 0) {
+    return b;
+  } else if constexpr (Q == 4) {
+    C r;   // multiply by sign * i
+    r.x = SIGN > 0 ? -b.y : b.y;
+    r.y = SIGN > 0 ? b.x : -b.x;
+    return r;
+  } else {
+    constexpr double c = Q < 4 ? kCos16[Q] : -kCos16[8 - Q];
+    constexpr double s0 = Q < 4 ? kCos16[4 - Q] : kCos16[Q - 4];
+    constexpr double s = SIGN > 0 ? s0 : -s0;
+    C r;
+    r.x = b.x * (T)c - b.y * (T)s;
+    r.y = b.x * (T)s + b.y * (T)c;
+    return r;
+  }
+}
+
+constexpr int bitrev(int i, int R) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) {
+    r <<= 1;
+    if (i & b) r |= 1;
+  }
+  return r;
+}
+
+// One radix-2 butterfly group of the in-register DFT: for the block starting
+// at I of length LEN, pair K with K + LEN/2.
+template <int SIGN, int R, int LEN, int I, int K, typename C>
+__device__ __forceinline__ void dft_bf(C (&y)[R]) {
+  if constexpr (K < LEN / 2) {
+    const C a = y[I + K];
+    const C b = rot16<SIGN, K * (16 / LEN)>(y[I + K + LEN / 2]);
+    y[I + K] = cadd(a, b);
+    y[I + K + LEN / 2] = csub(a, b);
+    dft_bf<SIGN, R, LEN, I, K + 1>(y);
+  }
+}
+template <int SIGN, int R, int LEN, int I, typename C>
+__device__ __forceinline__ void dft_blocks(C (&y)[R]) {
+  if constexpr (I < R) {
+    dft_bf<SIGN, R, LEN, I, 0>(y);
+    dft_blocks<SIGN, R, LEN, I + LEN>(y);
+  }
+}
+template <int SIGN, int R, int LEN, typename C>
+__device__ __forceinline__ void dft_levels(C (&y)[R]) {
+  if constexpr (LEN <= R) {
+    dft_blocks<SIGN, R, LEN, 0>(y);
+    dft_levels<SIGN, R, LEN * 2>(y);
+  }
+}
+
+// In-place DFT of size R (2, 4, 8 or 16) in registers:
+// x_k <- sum_j x_j exp(sign 2 pi i j k / R) (radix-2 decimation in time).
+template <int SIGN, int R, typename C>
+__device__ __forceinline__ void dft(C (&x)[R]) {
+  static_assert(R == 2 || R == 4 || R == 8 || R == 16, "radix");
+  C y[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) y[bitrev(i, R)] = x[i];
+  dft_levels<SIGN, R, 2>(y);
+#pragma unroll
+  for (int i = 0; i < R; ++i) x[i] = y[i];
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
+template <typename T, int N, bool STRIDED>
+struct FftCfg {
+  using C = typename Cx<T>::type;
+  static constexpr int NL = N;                       // line length
+  static constexpr bool STR = STRIDED;
+  static constexpr int E = N < 16 ? N : 16;          // elements per thread
+  static constexpr int TL = N / E;                   // threads per line
+  static constexpr int STAGES = (ilog2(N) + ilog2(E) - 1) / ilog2(E);
+  static constexpr int R0 = E;                       // first radix
+  static constexpr int NPAD = N + N / R0;            // padded LDS positions per line
+  static constexpr int GMIN = STRIDED ? (64 / (int)sizeof(C) > 1 ? 64 / (int)sizeof(C) : 1) : 1;
+  static constexpr int G0 = 256 / TL > GMIN ? 256 / TL : GMIN;
+  static constexpr int LDS_CAP = 80 * 1024;
+  static constexpr int G1 = G0 * NPAD * (int)sizeof(C) > LDS_CAP
+                                ? (LDS_CAP / (NPAD * (int)sizeof(C)) > 0 ? LDS_CAP / (NPAD * (int)sizeof(C)) : 1)
+                                : G0;
+  static constexpr int G = STAGES > 1 ? G1 : G0;     // lines per workgroup
+  static constexpr int THREADS = G * TL;
+  static constexpr int LDS = STAGES > 1 ? G * NPAD : 1;
+  // radix of stage s and the product of the radices before it
+  static constexpr int radix(int s) {
+    return s < STAGES - 1 ? E : N / ipow(E, STAGES - 1);
+  }
+  static constexpr int span(int s) { return ipow(E, s); }
+  static constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+  // LDS slot of (padded) position pp of a line: line-major for contiguous
+  // lines, position-major for strided ones
+  static __device__ __forceinline__ int slot(int pos, int line) {
+    const int pp = pos + pos / R0;
+    return STRIDED ? pp * G + line : line * NPAD + pp;
+  }
+};
+
+// Logical workgroup index: the hardware hands consecutive workgroups to the
+// eight XCDs in turn; give each XCD a contiguous range instead.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
+  constexpr int64_t kXcd = 8;
+  const int64_t q = nblk / kXcd, r = nblk % kXcd;
+  const int64_t x = b % kXcd, i = b / kXcd;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// One Stockham stage for the thread's E registers. Butterfly j = t + b TL
+// (b < E / R) takes positions j + r N / R = t + TL (b + r E / R), i.e.
+// registers b + r E / R; with k = j mod Ns, input r is twiddled by
+// w^(r k), w = exp(sign 2 pi i / (R Ns)), and output r belongs at position
+// (j - k) R + k + r Ns. The last stage (R Ns = N) keeps each output in the
+// register it came from; others write it to LDS.
+template <typename F, int S, int SIGN, bool LAST>
+__device__ __forceinline__ void fft_stage(typename F::C (&v)[F::E], int t, int line,
+                                          const typename F::C *__restrict__ tw,
+                                          typename F::C *lds) {
+  using C = typename F::C;
+  constexpr int R = F::radix(S);
+  constexpr int NS = F::span(S);
+  constexpr int NB = F::E / R;                         // butterflies per thread
+  static_assert(F::TL * F::E == F::NL && NB * R == F::E, "plan");
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = t + b * F::TL;
+    const int k = j & (NS - 1);
+    C x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = v[b + r * NB];
+    if constexpr (NS > 1) {
+      constexpr int step = F::NL / (R * NS);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = tw[r * k * step];
+        if (SIGN > 0) w.y = -w.y;
+        x[r] = cmul(x[r], w);
+      }
+    }
+    dft<SIGN, R>(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b + r * NB] = x[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        lds[F::slot((j - k) * R + k + r * NS, line)] = x[r];
+      }
+    }
+  }
+}
+
+// Read positions t + TL i of the line back from LDS.
+template <typename F>
+__device__ __forceinline__ void lds_gather(typename F::C (&v)[F::E], int t, int line,
+                                           const typename F::C *lds) {
+#pragma unroll
+  for (int i = 0; i < F::E; ++i) v[i] = lds[F::slot(t + F::TL * i, line)];
+}
+
+// All stages of one transform direction, from registers to registers.
+template <typename F, int SIGN, int S = 0>
+__device__ __forceinline__ void fft_all(typename F::C (&v)[F::E], int t, int line,
+                                        const typename F::C *__restrict__ tw,
+                                        typename F::C *lds) {
+  if constexpr (S < F::STAGES) {
+    constexpr bool last = S == F::STAGES - 1;
+    fft_stage<F, S, SIGN, last>(v, t, line, tw, lds);
+    if constexpr (!last) {
+      __syncthreads();
+      lds_gather<F>(v, t, line, lds);
+      __syncthreads();
+    }
+    fft_all<F, SIGN, S + 1>(v, t, line, tw, lds);
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void fft_dir(typename F::C (&v)[F::E], int sign, int t, int line,
+                                        const typename F::C *__restrict__ tw,
+                                        typename F::C *lds) {
+  if (sign < 0) fft_all<F, -1>(v, t, line, tw, lds);
+  else fft_all<F, +1>(v, t, line, tw, lds);
+}
+
+template <typename T, int N, bool STRIDED>
+__global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS)) void k_fft(FftPass<T> p) {
+  using F = FftCfg<T, N, STRIDED>;
+  using C = typename F::C;
+  constexpr int E = F::E, TL = F::TL, G = F::G;
+  __shared__ C lds[F::LDS];
+  const C *tw = reinterpret_cast<const C *>(p.tw);
+  const int tid = threadIdx.x;
+  const int line = STRIDED ? tid % G : tid / TL;
+  const int t = STRIDED ? tid / G : tid % TL;
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+  const int64_t lb = xcd_block((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x, nblk);
+  const int64_t item = lb / gridDim.x;
+  const int64_t L = (lb % gridDim.x) * G + line;
+  const bool live = L < p.n_lines;
+  int64_t mbase = 0, ibase = 0, obase = 0;
+  if (live) {
+    const int64_t l1i = L % p.l1, l2i = L / p.l1;
+    mbase = l1i * p.in_s1 + l2i * p.in_s2;
+    ibase = mbase + item * p.in_bstride;
+    obase = l1i * p.out_s1 + l2i * p.out_s2 + item * p.out_bstride;
+  }
+  // gather: position pos holds element (pos - in_shift) mod N if that is
+  // below in_cnt; a Hermitian input also fills position pos with
+  // conj(element N - pos); every other position is zero
+  C v[E];
+  T mu[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int pos = t + TL * i;
+    const int e = (pos - p.in_shift) & (N - 1);
+    v[i].x = T(0);
+    v[i].y = T(0);
+    if (live) {
+      if (e < p.in_cnt) {
+        const int64_t off = ibase + (int64_t)e * p.in_es;
+        if (p.in_real) v[i].x = reinterpret_cast<const T *>(p.in)[off];
+        else v[i] = reinterpret_cast<const C *>(p.in)[off];
+      } else if (p.in_hermitian && pos > 0 && N - pos < p.in_cnt) {
+        const C c = reinterpret_cast<const C *>(p.in)[ibase + (int64_t)(N - pos) * p.in_es];
+        v[i].x = c.x;
+        v[i].y = -c.y;
+      }
+    }
+    mu[i] = T(0);
+    if (p.mul_inv && live) {
+      const int em = (pos - p.mu_shift) & (N - 1);
+      if (em < p.mu_cnt) mu[i] = p.mu[mbase + (int64_t)em * p.in_es];
+    }
+  }
+  fft_dir<F>(v, p.sign, t, line, tw, lds);
+  if (p.mul_inv) {
+    // registers hold positions t + TL i again: multiply and transform back
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      v[i].x *= mu[i];
+      v[i].y *= mu[i];
+    }
+    fft_dir<F>(v, -p.sign, t, line, tw, lds);
+  }
+  if (!live) return;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int pos = t + TL * i;
+    const int e = (pos - p.out_shift) & (N - 1);
+    if (e < p.out_cnt) {
+      const int64_t off = obase + (int64_t)e * p.out_es;
+      if (p.out_real) reinterpret_cast<T *>(p.out)[off] = v[i].x;
+      else reinterpret_cast<C *>(p.out)[off] = v[i];
+    }
+  }
+}
+
+template <typename T, int N, bool STRIDED>
+hipError_t fft_n(const FftPass<T> &p, int nb, hipStream_t s) {
+  using F = FftCfg<T, N, STRIDED>;
+  if (p.n_lines == 0) return hipSuccess;
+  const int64_t blocks = (p.n_lines + F::G - 1) / F::G;
+  hipLaunchKernelGGL((k_fft<T, N, STRIDED>), dim3((unsigned)blocks, (unsigned)nb),
+                     dim3(F::THREADS), 0, s, p);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t fft_map(const FftPass<T> &p, int nb, hipStream_t s) {
+  // both sides of a pass use the same lane map
+  if ((p.in_es == 1) != (p.out_es == 1)) return hipErrorInvalidValue;
+  return p.in_es == 1 ? fft_n<T, N, false>(p, nb, s) : fft_n<T, N, true>(p, nb, s);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s) {
+  if (p.in_hermitian && p.in_shift != 0) return hipErrorInvalidValue;
+  switch (N) {
+    case 8: return fft_map<T, 8>(p, nb, s);
+    case 16: return fft_map<T, 16>(p, nb, s);
+    case 32: return fft_map<T, 32>(p, nb, s);
+    case 64: return fft_map<T, 64>(p, nb, s);
+    case 128: return fft_map<T, 128>(p, nb, s);
+    case 256: return fft_map<T, 256>(p, nb, s);
+    case 512: return fft_map<T, 512>(p, nb, s);
+    case 1024: return fft_map<T, 1024>(p, nb, s);
+    case 2048: return fft_map<T, 2048>(p, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
+template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
+
+}  // namespace slp

@@ -3,7 +3,8 @@
 // Stages (Sec. 3, Alg. 1 computation phase, eq. BEM_NFFT_compact2):
 //   spread   a_r = sum_k q_k prod_q psi(t_kq - r_q), with the charges
 //            q_k = w_k g_k formed while staging          (eq. gridding, naive_gridding)
-//   fft      pruned 3-D FFT, multiply by mu, inverse FFT    (eq. FFT, deconv, Alg. 1)
+//   fft      pruned 3-D FFT, multiply by mu, inverse FFT    (eq. FFT, deconv, Alg. 1;
+//            in slp_fft.hip)
 //   interp   phi_i = sum_r g_r prod_q psi(t_iq - r_q)       (type-2 NFFT)
 // mu folds the two window deconvolutions, c_l(N_s), the Hermitian weights of
 // the asymmetric index set and 1/(4 pi) into one real factor per mode.
@@ -13,13 +14,6 @@
 #include <hip/hip_runtime.h>
 
 namespace slp {
-
-template <typename T>
-struct Cplx;
-template <>
-struct Cplx<float> { using type = float2; };
-template <>
-struct Cplx<double> { using type = double2; };
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef double dbl2 __attribute__((ext_vector_type(2)));
@@ -629,231 +623,6 @@ hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_activ
   }
 }
 
-// -------------------------------------------------------------------- fft ---
-template <typename C>
-__device__ __forceinline__ C cmul(C a, C b) {
-  C r;
-  r.x = a.x * b.x - a.y * b.y;
-  r.y = a.x * b.y + a.y * b.x;
-  return r;
-}
-template <typename C>
-__device__ __forceinline__ C cadd(C a, C b) { C r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
-template <typename C>
-__device__ __forceinline__ C csub(C a, C b) { C r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
-// multiply by sign * i
-template <typename C>
-__device__ __forceinline__ C cmul_si(C a, int sign) {
-  C r;
-  r.x = sign > 0 ? -a.y : a.y;
-  r.y = sign > 0 ? a.x : -a.x;
-  return r;
-}
-
-// Stockham autosort FFT of B lines of length N held in LDS (radix 4, one
-// radix-2 stage when log2 N is odd). Returns the buffer holding the result.
-template <typename T, int N>
-__device__ typename Cplx<T>::type *lds_fft(typename Cplx<T>::type *src,
-                                           typename Cplx<T>::type *dst, int B, int sign,
-                                           const typename Cplx<T>::type *__restrict__ tw) {
-  using C = typename Cplx<T>::type;
-  for (int Ns = 1; Ns < N; ) {
-    if (N / Ns >= 4) {
-      constexpr int Q = N / 4;
-      for (int j = threadIdx.x; j < B * Q; j += blockDim.x) {
-        const int b = j / Q, jj = j % Q;
-        const int k = jj & (Ns - 1);
-        const C *s = src + b * N;
-        C v0 = s[jj], v1 = s[jj + Q], v2 = s[jj + 2 * Q], v3 = s[jj + 3 * Q];
-        const int st = N / (4 * Ns);
-        if (Ns > 1) {
-          C w1 = tw[k * st], w2 = tw[2 * k * st], w3 = tw[3 * k * st];
-          if (sign > 0) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
-          v1 = cmul(v1, w1); v2 = cmul(v2, w2); v3 = cmul(v3, w3);
-        }
-        const C a0 = cadd(v0, v2), a1 = csub(v0, v2);
-        const C b0 = cadd(v1, v3), b1 = cmul_si(csub(v1, v3), sign);
-        C *d = dst + b * N + (jj - k) * 4 + k;
-        d[0] = cadd(a0, b0);
-        d[Ns] = cadd(a1, b1);
-        d[2 * Ns] = csub(a0, b0);
-        d[3 * Ns] = csub(a1, b1);
-      }
-      Ns *= 4;
-    } else {
-      constexpr int H = N / 2;
-      for (int j = threadIdx.x; j < B * H; j += blockDim.x) {
-        const int b = j / H, jj = j % H;
-        const int k = jj & (Ns - 1);
-        const C *s = src + b * N;
-        C v0 = s[jj], v1 = s[jj + H];
-        C w = tw[k * (N / (2 * Ns))];
-        if (sign > 0) w.y = -w.y;
-        v1 = cmul(v1, w);
-        C *d = dst + b * N + (jj - k) * 2 + k;
-        d[0] = cadd(v0, v1);
-        d[Ns] = csub(v0, v1);
-      }
-      Ns *= 2;
-    }
-    __syncthreads();
-    C *t = src; src = dst; dst = t;
-  }
-  return src;
-}
-
-__device__ __forceinline__ int wrap_pos(int e, int shift, int N) {
-  int p = (e + shift) % N;
-  return p < 0 ? p + N : p;
-}
-
-// A workgroup of 128 threads transforms B = 512 / N lines (at least one) held
-// in LDS: 16 KiB (FP64) per workgroup, so many workgroups share a CU and hide
-// the latency of the pruned loads and stores. Line base offsets are computed
-// once per line; elements are mapped to threads without divisions: along the
-// line when the element stride is 1, across lines otherwise (coalesced).
-constexpr int kFftThreads = 128;
-constexpr int kFftElems = 512;
-
-template <int N>
-struct FftShape {
-  static constexpr int B = (kFftElems / N) > 0 ? (kFftElems / N) : 1;     // lines per block
-  static constexpr int TPL = kFftThreads / B > 0 ? kFftThreads / B : 1;   // threads per line
-  static constexpr int PER = (B * N + kFftThreads - 1) / kFftThreads;     // elements per thread
-};
-
-template <typename T, int N>
-__global__ __launch_bounds__(kFftThreads) void k_fft(FftPass<T> p) {
-  using C = typename Cplx<T>::type;
-  using F = FftShape<N>;
-  constexpr int B = F::B, TPL = F::TPL, PER = F::PER;
-  __shared__ C buf0[B * N];
-  __shared__ C buf1[B * N];
-  __shared__ int64_t in_base[B], out_base[B];
-  const C *tw = reinterpret_cast<const C *>(p.tw);
-  const int64_t L0 = (int64_t)blockIdx.x * B;
-  const int nb = (int)min((int64_t)B, p.n_lines - L0);
-  const int tid = threadIdx.x;
-
-  if (tid < nb) {
-    const int64_t L = L0 + tid;
-    const int64_t l1i = L % p.l1, l2i = L / p.l1;
-    in_base[tid] = l1i * p.in_s1 + l2i * p.in_s2 + blockIdx.y * p.in_bstride;
-    out_base[tid] = l1i * p.out_s1 + l2i * p.out_s2 + blockIdx.y * p.out_bstride;
-  }
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int j = tid + k * kFftThreads;
-    if (j < B * N) { buf0[j].x = T(0); buf0[j].y = T(0); }
-  }
-  __syncthreads();
-
-  // thread -> (line, element) maps
-  const bool in_contig = p.in_es == 1;
-  auto map_in = [&](int k, int &b, int &e) {
-    if (in_contig) { b = tid / TPL; e = tid % TPL + k * TPL; }
-    else { b = tid % B; e = tid / B + k * (kFftThreads / B); }
-  };
-  // issue every global load (data and multiplier) before touching LDS
-  C v[PER];
-  T mu[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int b, e;
-    map_in(k, b, e);
-    if (b < nb && e < p.in_cnt) {
-      const int64_t off = in_base[b] + (int64_t)e * p.in_es;
-      if (p.in_real) { v[k].x = reinterpret_cast<const T *>(p.in)[off]; v[k].y = T(0); }
-      else { v[k] = reinterpret_cast<const C *>(p.in)[off]; }
-    }
-    mu[k] = T(0);
-    if (p.mul_inv && b < nb && e < p.mu_cnt)
-      mu[k] = p.mu[in_base[b] - blockIdx.y * p.in_bstride + (int64_t)e * p.in_es];
-  }
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int b, e;
-    map_in(k, b, e);
-    if (b < nb && e < p.in_cnt) {
-      const int pos = wrap_pos(e, p.in_shift, N);
-      buf0[b * N + pos] = v[k];
-      if (p.in_hermitian && e > 0) {
-        C c = v[k];
-        c.y = -c.y;
-        buf0[b * N + (N - pos)] = c;
-      }
-    }
-  }
-  __syncthreads();
-
-  C *res = lds_fft<T, N>(buf0, buf1, B, p.sign, tw);
-
-  if (p.mul_inv) {
-    C *oth = (res == buf0) ? buf1 : buf0;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int j = tid + k * kFftThreads;
-      if (j < B * N) { oth[j].x = T(0); oth[j].y = T(0); }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      int b, e;
-      map_in(k, b, e);
-      if (b < nb && e < p.mu_cnt) {
-        const int ps = wrap_pos(e, p.mu_shift, N);
-        C x = res[b * N + ps];
-        x.x *= mu[k];
-        x.y *= mu[k];
-        oth[b * N + ps] = x;
-      }
-    }
-    __syncthreads();
-    C *spare = (oth == buf0) ? buf1 : buf0;
-    res = lds_fft<T, N>(oth, spare, B, -p.sign, tw);
-  }
-
-  const bool out_contig = p.out_es == 1;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int b, e;
-    if (out_contig) { b = tid / TPL; e = tid % TPL + k * TPL; }
-    else { b = tid % B; e = tid / B + k * (kFftThreads / B); }
-    if (b < nb && e < p.out_cnt) {
-      const int64_t off = out_base[b] + (int64_t)e * p.out_es;
-      const C x = res[b * N + wrap_pos(e, p.out_shift, N)];
-      if (p.out_real) reinterpret_cast<T *>(p.out)[off] = x.x;
-      else reinterpret_cast<C *>(p.out)[off] = x;
-    }
-  }
-}
-
-template <typename T, int N>
-static hipError_t fft_n(const FftPass<T> &p, int nb, hipStream_t s) {
-  constexpr int B = FftShape<N>::B;
-  if (p.n_lines == 0) return hipSuccess;
-  const int64_t blocks = (p.n_lines + B - 1) / B;
-  hipLaunchKernelGGL((k_fft<T, N>), dim3((unsigned)blocks, (unsigned)nb), dim3(kFftThreads), 0, s,
-                     p);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s) {
-  switch (N) {
-    case 8: return fft_n<T, 8>(p, nb, s);
-    case 16: return fft_n<T, 16>(p, nb, s);
-    case 32: return fft_n<T, 32>(p, nb, s);
-    case 64: return fft_n<T, 64>(p, nb, s);
-    case 128: return fft_n<T, 128>(p, nb, s);
-    case 256: return fft_n<T, 256>(p, nb, s);
-    case 512: return fft_n<T, 512>(p, nb, s);
-    case 1024: return fft_n<T, 1024>(p, nb, s);
-    case 2048: return fft_n<T, 2048>(p, nb, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 // ---------------------------------------------------------------- density ---
 // Element-constant density of the P1 ansatz: the integral mean of the affine
 // m . n over a flat triangle is its value at the centroid, i.e. the vertex mean;
@@ -1362,8 +1131,6 @@ template hipError_t launch_iw_apply<float>(const NearArgs<float> &, const IwOut<
                                            const BatchPtrs &, int, bool, bool, hipStream_t);
 template hipError_t launch_iw_apply<double>(const NearArgs<double> &, const IwOut<double> &,
                                             const BatchPtrs &, int, bool, bool, hipStream_t);
-template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
-template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,
                                      const double *, int32_t, const int32_t *, const int32_t *,
                                      const double *, const double *, const double *, hipStream_t);
