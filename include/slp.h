@@ -168,6 +168,26 @@ int slp_set_density_from_m(slp_geom *g, const double *m_nodes, const double *dph
  *         units (the 1/(4 pi) of the Newton kernel included). */
 int slp_eval_single_layer(slp_geom *g, double *phi, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as slp_eval_single_layer (same kernels, same result up to the
+ * rounding order of the gridding's block accumulation), but every work buffer
+ * of the evaluation (gridding blocks, region grid, half spectra, grid after
+ * the inverse FFT, element means of a near field or of integrated-window
+ * gridding) is carved out of one static device array of
+ * SLP_STATIC_WORKSPACE_BYTES per device instead of the context's own buffers.
+ * The call allocates nothing (no hipMalloc/hipFree); the first call on a
+ * device looks up the array's address there. Evaluations whose work buffers
+ * exceed the workspace fail with SLP_ENOMEM and a message giving the bytes
+ * needed (cube64 with the Gaussian m = 8 in FP64 needs ~40 MiB; the 1024 x
+ * 1024 x 64 film needs several hundred). Every call on a device shares that
+ * device's array and leaves its contents behind (nothing in it has to start
+ * at zero): calls whose work overlaps on one device, on any streams, race and
+ * must be ordered by the caller. Direct kernel launches only (graph replay of
+ * slp_set_graph does not apply). phi as for slp_eval_single_layer. */
+#define SLP_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int slp_eval_single_layer_static(slp_geom *g, double *phi, void *stream);
+
 /* Batched evaluation: item b uses geometry geoms[b], density dens[b] (device
  * float64 [3 * n_tris(geoms[b])]) and writes phi[b] (device float64
  * [n_targets(geoms[b])]). Repeating one geometry evaluates several densities on

@@ -89,6 +89,7 @@ def load_library():
         "slp_set_density": [_VP, _VP, _VP],
         "slp_set_density_from_m": [_VP, _VP, _VP, _VP],
         "slp_eval_single_layer": [_VP, _VP, _VP],
+        "slp_eval_single_layer_static": [_VP, _VP, _VP],
         "slp_eval_batched": [_VP, _VP, _VP, ctypes.c_int32, _VP],
         "slp_geom_get_info": [_VP, ctypes.POINTER(GeomInfo)],
         "slp_set_timing": [_VP, ctypes.c_int32],
@@ -344,6 +345,19 @@ def eval_single_layer(geom, phi, stream=None):
     info = geom_get_info(geom)
     _check(load_library().slp_eval_single_layer(_VP(geom), _dev_f64(phi, info["n_targets"], "phi"),
                                                 _stream_ptr(stream)))
+
+
+# bytes of the static device workspace of eval_single_layer_static
+# (SLP_STATIC_WORKSPACE_BYTES in include/slp.h)
+STATIC_WORKSPACE_BYTES = 64 << 20
+
+
+def eval_single_layer_static(geom, phi, stream=None):
+    """slp_eval_single_layer_static: the evaluation with every work buffer in
+    the library's static device workspace (allocates nothing)."""
+    info = geom_get_info(geom)
+    _check(load_library().slp_eval_single_layer_static(
+        _VP(geom), _dev_f64(phi, info["n_targets"], "phi"), _stream_ptr(stream)))
 
 
 def eval_batched(geoms, dens, phis, stream=None):

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libslp.so")
 
-SOURCES = ["slp_kernels.hip", "slp_fft.hip", "slp_fem.hip", "slp_api.cpp", "slp_near.cpp", "slp_fem.cpp",
+SOURCES = ["slp_kernels.hip", "slp_fft.hip", "slp_fem.hip", "slp_static.hip", "slp_api.cpp", "slp_near.cpp", "slp_fem.cpp",
            "slp_amg.cpp", "slp_server.cpp"]
 ARCH = os.environ.get("SLP_OFFLOAD_ARCH", "gfx950")
 

@@ -369,8 +369,32 @@ int ensure_capacity(slp_geom *G, int nb, hipStream_t st) {
   return SLP_OK;
 }
 
+// Per-evaluation work buffers of one evaluation (blocks of the gridding
+// segments, region grid, both half spectra, grid after the inverse FFT,
+// element means of the near field and of integrated-window gridding) and
+// their per-item element counts: the context's own buffers, or a carve-out
+// of the static workspace (slp_eval_single_layer_static).
+struct WorkBufs {
+  void *scratch = nullptr, *grid_a = nullptr, *S1 = nullptr, *S2 = nullptr, *grid_g = nullptr;
+  double *nf_gbar = nullptr, *iw_gbar = nullptr;
+  int64_t elems[5]{};
+};
+
+WorkBufs ctx_work(const slp_geom *G) {
+  WorkBufs W;
+  W.scratch = G->scratch;
+  W.grid_a = G->grid_a;
+  W.S1 = G->S1;
+  W.S2 = G->S2;
+  W.grid_g = G->grid_g;
+  W.nf_gbar = G->nf_gbar;
+  W.iw_gbar = G->iw_gbar;
+  for (int i = 0; i < 5; ++i) W.elems[i] = G->item_elems[i];
+  return W;
+}
+
 template <typename T>
-slp::SpreadBinsArgs<T> spread_args(const slp_geom *G) {
+slp::SpreadBinsArgs<T> spread_args(const slp_geom *G, const WorkBufs &W) {
   slp::SpreadBinsArgs<T> a{};
   a.frac = static_cast<const T *>(G->src_frac);
   a.w = G->src_w;
@@ -380,9 +404,9 @@ slp::SpreadBinsArgs<T> spread_args(const slp_geom *G) {
   a.segs = G->segs;
   a.chunks = G->chunks;
   a.runs = G->runs;
-  a.scratch = static_cast<T *>(G->scratch);
+  a.scratch = static_cast<T *>(W.scratch);
   a.ns = G->n_src;
-  a.scratch_bstride = G->item_elems[0];
+  a.scratch_bstride = W.elems[0];
   a.inv_b = (T)(1.0 / G->b);
   a.step_ratio = (T)std::exp(-2.0 / G->b);
   a.window = G->window;
@@ -392,15 +416,15 @@ slp::SpreadBinsArgs<T> spread_args(const slp_geom *G) {
 }
 
 template <typename T>
-slp::InterpArgs<T> interp_args(const slp_geom *G) {
+slp::InterpArgs<T> interp_args(const slp_geom *G, const WorkBufs &W) {
   slp::InterpArgs<T> a{};
   a.cell = G->tgt_cell;
   a.frac = static_cast<const T *>(G->tgt_frac);
   a.perm = G->tgt_perm;
   a.tile_start = G->tgt_tile_start;
   a.active = G->tgt_active;
-  a.g = static_cast<const T *>(G->grid_g);
-  a.g_bstride = G->item_elems[4];
+  a.g = static_cast<const T *>(W.grid_g);
+  a.g_bstride = W.elems[4];
   for (int i = 0; i < 3; ++i) {
     a.R[i] = G->R[i];
     a.tiles[i] = G->tiles[i];
@@ -414,14 +438,14 @@ slp::InterpArgs<T> interp_args(const slp_geom *G) {
 }
 
 template <typename T>
-slp::NearArgs<T> near_args(const slp_geom *G) {
+slp::NearArgs<T> near_args(const slp_geom *G, const WorkBufs &W) {
   slp::NearArgs<T> a{};
   a.rowptr = G->nf_rowptr;
   a.cols = G->nf_cols;
   a.bases = G->nf_bases;
   a.offs = G->nf_offs;
   a.vals = static_cast<T *>(G->nf_vals);
-  a.gbar = G->nf_gbar;
+  a.gbar = W.nf_gbar;
   a.rows = G->n_tgt;
   a.M = G->n_tris;
   return a;
@@ -429,49 +453,51 @@ slp::NearArgs<T> near_args(const slp_geom *G) {
 
 // The near-field product in the values' storage precision (FP32 storage in an
 // FP64 context halves the bytes of the HBM-bound product; the sums stay FP64).
-hipError_t near_apply(const slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
+hipError_t near_apply(const slp_geom *G, const WorkBufs &W, const slp::BatchPtrs &ptrs, int nb,
+                      hipStream_t st) {
   if (G->nf_prec == SLP_FP64)
-    return slp::launch_near_apply<double>(near_args<double>(G), ptrs, nb, G->nf_packed, st);
-  return slp::launch_near_apply<float>(near_args<float>(G), ptrs, nb, G->nf_packed, st);
+    return slp::launch_near_apply<double>(near_args<double>(G, W), ptrs, nb, G->nf_packed, st);
+  return slp::launch_near_apply<float>(near_args<float>(G, W), ptrs, nb, G->nf_packed, st);
 }
 
 template <typename T>
-slp::NearArgs<T> iw_args(const slp_geom *G) {
+slp::NearArgs<T> iw_args(const slp_geom *G, const WorkBufs &W) {
   slp::NearArgs<T> a{};
   a.rowptr = G->iw_rowptr;
   a.cols = G->iw_cols;
   a.bases = G->iw_bases;
   a.offs = G->iw_offs;
   a.vals = static_cast<T *>(G->iw_vals);
-  a.gbar = G->iw_gbar;
+  a.gbar = W.iw_gbar;
   a.rows = G->iw_rows;
   a.M = G->n_tris;
   return a;
 }
 
 template <typename T>
-int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bool tm) {
+int run_eval(slp_geom *G, const WorkBufs &W, const slp::BatchPtrs &ptrs, int nb, hipStream_t st,
+             bool tm) {
   if (G->nf_nnz > 0 && G->nf_rule != G->iw_order)
     return fail(SLP_EINVAL, "the near field was built for another gridding (set it up again)");
   if (G->iw_order > 0) {
     // integrated-window gridding: a = A gbar (the whole gridding stage; the
     // block-sum stage takes no time)
     slp::IwOut<T> o{};
-    o.grid = static_cast<T *>(G->grid_a);
-    o.bstride = G->item_elems[1];
+    o.grid = static_cast<T *>(W.grid_a);
+    o.bstride = W.elems[1];
     for (int i = 0; i < 3; ++i) { o.R[i] = G->R[i]; o.P[i] = G->P[i]; }
     const bool short_rows = !G->iw_packed && G->iw_stored < 512 * G->iw_rows;
-    HIP_TRY(slp::launch_iw_apply<T>(iw_args<T>(G), o, ptrs, nb, G->iw_packed, short_rows, st));
+    HIP_TRY(slp::launch_iw_apply<T>(iw_args<T>(G, W), o, ptrs, nb, G->iw_packed, short_rows, st));
     if (tm) HIP_TRY(hipEventRecord(G->evs()[1], st));
   } else {
     // spread (the charges q = w g are formed inside the gridding)
-    const slp::SpreadBinsArgs<T> a = spread_args<T>(G);
+    const slp::SpreadBinsArgs<T> a = spread_args<T>(G, W);
     slp::SpreadReduceArgs<T> r{};
-    r.scratch = static_cast<const T *>(G->scratch);
+    r.scratch = static_cast<const T *>(W.scratch);
     r.tile_slots = G->tile_slots;
-    r.grid = static_cast<T *>(G->grid_a);
-    r.scratch_bstride = G->item_elems[0];
-    r.grid_bstride = G->item_elems[1];
+    r.grid = static_cast<T *>(W.grid_a);
+    r.scratch_bstride = W.elems[0];
+    r.grid_bstride = W.elems[1];
     for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
     HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_units, G->m, nb, st,
                                   tm ? G->evs()[1] : nullptr));
@@ -484,74 +510,74 @@ int run_eval(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st, bo
   // x forward: real region rows -> kx = 0..n_x/2
   {
     slp::FftPass<T> p{};
-    p.in = G->grid_a; p.out = G->S1; p.tw = G->tw[0];
+    p.in = W.grid_a; p.out = W.S1; p.tw = G->tw[0];
     p.n_lines = Ry * Rz; p.l1 = Ry;
     p.in_s1 = Px; p.in_s2 = Py * Px; p.in_es = 1; p.in_cnt = (int)Rx; p.in_shift = G->lo[0];
     p.out_s1 = Kx; p.out_s2 = Ry * Kx; p.out_es = 1; p.out_cnt = (int)Kx; p.out_shift = 0;
     p.sign = -1; p.in_real = 1;
-    p.in_bstride = G->item_elems[1]; p.out_bstride = G->item_elems[2];
+    p.in_bstride = W.elems[1]; p.out_bstride = W.elems[2];
     HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
   // y forward: region y -> ky = -n_y/2..n_y/2
   {
     slp::FftPass<T> p{};
-    p.in = G->S1; p.out = G->S2; p.tw = G->tw[1];
+    p.in = W.S1; p.out = W.S2; p.tw = G->tw[1];
     p.n_lines = Kx * Rz; p.l1 = Kx;
     p.in_s1 = 1; p.in_s2 = Ry * Kx; p.in_es = Kx; p.in_cnt = (int)Ry; p.in_shift = G->lo[1];
     p.out_s1 = 1; p.out_s2 = Ky * Kx; p.out_es = Kx; p.out_cnt = (int)Ky; p.out_shift = -ny / 2;
     p.sign = -1;
-    p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[3];
+    p.in_bstride = W.elems[2]; p.out_bstride = W.elems[3];
     HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
   // z forward, multiply by mu on kz = -n_z/2..n_z/2, z inverse back to the region
   {
     slp::FftPass<T> p{};
-    p.in = G->S2; p.out = G->S2; p.tw = G->tw[2];
+    p.in = W.S2; p.out = W.S2; p.tw = G->tw[2];
     p.mu = static_cast<const T *>(G->mu);
     p.n_lines = Kx * Ky; p.l1 = Kx;
     p.in_s1 = 1; p.in_s2 = Kx; p.in_es = Ky * Kx; p.in_cnt = (int)Rz; p.in_shift = G->lo[2];
     p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
     p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
     p.sign = -1; p.mul_inv = 1;
-    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[3];
+    p.in_bstride = W.elems[3]; p.out_bstride = W.elems[3];
     HIP_TRY(slp::launch_fft<T>(p, G->N[2], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
   // y inverse: ky -> region y
   {
     slp::FftPass<T> p{};
-    p.in = G->S2; p.out = G->S1; p.tw = G->tw[1];
+    p.in = W.S2; p.out = W.S1; p.tw = G->tw[1];
     p.n_lines = Kx * Rz; p.l1 = Kx;
     p.in_s1 = 1; p.in_s2 = Ky * Kx; p.in_es = Kx; p.in_cnt = (int)Ky; p.in_shift = -ny / 2;
     p.out_s1 = 1; p.out_s2 = Ry * Kx; p.out_es = Kx; p.out_cnt = (int)Ry; p.out_shift = G->lo[1];
     p.sign = +1;
-    p.in_bstride = G->item_elems[3]; p.out_bstride = G->item_elems[2];
+    p.in_bstride = W.elems[3]; p.out_bstride = W.elems[2];
     HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
   // x inverse (Hermitian half spectrum -> real region rows)
   {
     slp::FftPass<T> p{};
-    p.in = G->S1; p.out = G->grid_g; p.tw = G->tw[0];
+    p.in = W.S1; p.out = W.grid_g; p.tw = G->tw[0];
     p.n_lines = Ry * Rz; p.l1 = Ry;
     p.in_s1 = Kx; p.in_s2 = Ry * Kx; p.in_es = 1; p.in_cnt = (int)Kx; p.in_shift = 0;
     p.in_hermitian = 1;
     p.out_s1 = Rx; p.out_s2 = Ry * Rx; p.out_es = 1; p.out_cnt = (int)Rx; p.out_shift = G->lo[0];
     p.out_real = 1; p.sign = +1;
-    p.in_bstride = G->item_elems[2]; p.out_bstride = G->item_elems[4];
+    p.in_bstride = W.elems[2]; p.out_bstride = W.elems[4];
     HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
   }
   (void)nx;
   if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
   {
-    const slp::InterpArgs<T> a = interp_args<T>(G);
+    const slp::InterpArgs<T> a = interp_args<T>(G, W);
     HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
   }
   const bool near = G->nf_nnz > 0;
   if (tm && near) HIP_TRY(hipEventRecord(G->evs()[8], st));
-  if (near) HIP_TRY(near_apply(G, ptrs, nb, st));
+  if (near) HIP_TRY(near_apply(G, W, ptrs, nb, st));
   if (tm) {
     G->with_near[G->cur] = near;
     HIP_TRY(hipEventRecord(G->evs()[slp_geom::kStages], st));
@@ -576,7 +602,7 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     slp_geom::Captured c;
     c.nb = nb;
     HIP_TRY(hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeThreadLocal));
-    const int rc = run_eval<T>(G, ptrs, nb, G->cap_stream, false);
+    const int rc = run_eval<T>(G, ctx_work(G), ptrs, nb, G->cap_stream, false);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(G->cap_stream, &graph);
     if (rc) {
@@ -615,8 +641,9 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
     cg = &G->graphs.back();
   }
   slp::BatchPtrs p = ptrs;
-  slp::SpreadBinsArgs<T> sa = spread_args<T>(G);
-  slp::InterpArgs<T> ia = interp_args<T>(G);
+  const WorkBufs W = ctx_work(G);
+  slp::SpreadBinsArgs<T> sa = spread_args<T>(G, W);
+  slp::InterpArgs<T> ia = interp_args<T>(G, W);
   void *sargs[2] = {&sa, &p};
   void *iargs[2] = {&ia, &p};
   hipKernelNodeParams kp = cg->spread_p;
@@ -629,10 +656,10 @@ int run_graph(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) {
   HIP_TRY(hipGraphExecKernelNodeSetParams(cg->exec, cg->interp_node, &kp));
   if (cg->near_node) {
     // the two argument types differ only in the type of the value pointer
-    slp::NearArgs<double> nad = near_args<double>(G);
-    slp::NearArgs<float> naf = near_args<float>(G);
+    slp::NearArgs<double> nad = near_args<double>(G, W);
+    slp::NearArgs<float> naf = near_args<float>(G, W);
     int32_t nbv = nb;
-    double *gbar = G->nf_gbar;
+    double *gbar = W.nf_gbar;
     int64_t M = G->n_tris;
     void *gargs[3] = {&p, &gbar, &M};
     kp = cg->gbar_p;
@@ -662,7 +689,7 @@ int eval_items(slp_geom *G, const slp::BatchPtrs &ptrs, int nb, hipStream_t st) 
     const int rc = begin_timed(G, st);
     if (rc) return rc;
   }
-  return run_eval<T>(G, ptrs, nb, st, tm);
+  return run_eval<T>(G, ctx_work(G), ptrs, nb, st, tm);
 }
 
 int collect_one(slp_geom *G, int r) {
@@ -1312,6 +1339,55 @@ int run_group(slp_geom *G, const double *const *dens, double *const *phi, int nb
 
 }  // namespace
 
+int slp_eval_single_layer_static(slp_geom *G, double *phi, void *stream) {
+  if (!G || !phi) return fail(SLP_EINVAL, "geometry and phi must be non-NULL");
+  if (!G->dens) return fail(SLP_EINVAL, "no density set (slp_set_density)");
+  // carve the work buffers of one item out of the static workspace, each
+  // 256-byte aligned
+  const size_t e = G->esz();
+  const size_t per[5] = {e, e, 2 * e, 2 * e, e};
+  size_t off[7], need = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = need;
+    need += (bytes + 255) / 256 * 256;
+    return at;
+  };
+  for (int i = 0; i < 5; ++i) off[i] = take((size_t)G->item_elems[i] * per[i]);
+  const bool nf = G->nf_nnz > 0, iw = G->iw_order > 0;
+  off[5] = take(nf ? (size_t)G->n_tris * 8 : 0);
+  off[6] = take(iw ? (size_t)G->n_tris * 8 : 0);
+  if (need > slp::kStaticWorkspaceBytes)
+    return fail(SLP_ENOMEM,
+                "static workspace: this evaluation needs %zu bytes of work buffers, the workspace "
+                "holds %zu (use slp_eval_single_layer)",
+                need, slp::kStaticWorkspaceBytes);
+  void *base = nullptr;
+  HIP_TRY(slp::static_workspace(&base));
+  char *b = static_cast<char *>(base);
+  WorkBufs W;
+  W.scratch = b + off[0];
+  W.grid_a = b + off[1];
+  W.S1 = b + off[2];
+  W.S2 = b + off[3];
+  W.grid_g = b + off[4];
+  W.nf_gbar = nf ? reinterpret_cast<double *>(b + off[5]) : nullptr;
+  W.iw_gbar = iw ? reinterpret_cast<double *>(b + off[6]) : nullptr;
+  for (int i = 0; i < 5; ++i) W.elems[i] = G->item_elems[i];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  slp::BatchPtrs ptrs{};
+  ptrs.dens[0] = G->dens;
+  ptrs.phi[0] = phi;
+  // direct launches (no captured graph: it would hold the context's buffers);
+  // the sampled stage events are recorded as for the other evaluations
+  const bool tm = G->timing && (G->evals++ % G->every == 0);
+  if (tm) {
+    const int rc = begin_timed(G, st);
+    if (rc) return rc;
+  }
+  return G->prec == SLP_FP64 ? run_eval<double>(G, W, ptrs, 1, st, tm)
+                             : run_eval<float>(G, W, ptrs, 1, st, tm);
+}
+
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
                      int32_t batch, void *stream) {
   if (batch < 1 || !geoms || !dens || !phi) return fail(SLP_EINVAL, "batched: batch >= 1 and non-NULL arrays");
@@ -1700,12 +1776,12 @@ int slp_setup_near_field_stored(slp_geom *G, double eps, int32_t storage, void *
   const int32_t npts = (int32_t)(rule.size() / 3);
   G->nf_rule = G->iw_order;
   if (storage == SLP_FP64) {
-    slp::NearArgs<double> na = near_args<double>(G);
+    slp::NearArgs<double> na = near_args<double>(G, ctx_work(G));
     na.cols = d_cols;
     HIP_TRY(slp::launch_near_values<double>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S,
                                             d_rule, npts, st));
   } else {
-    slp::NearArgs<float> na = near_args<float>(G);
+    slp::NearArgs<float> na = near_args<float>(G, ctx_work(G));
     na.cols = d_cols;
     HIP_TRY(slp::launch_near_values<float>(na, d_tg, d_nodes, d_tris, d_terms, d_terms + S, S,
                                            d_rule, npts, st));
@@ -1896,11 +1972,11 @@ int slp_setup_integrated_gridding(slp_geom *G, int32_t order, void *stream) {
   g.b = G->b;
   g.kb_inv_norm = G->kb_inv_norm;
   if (G->prec == SLP_FP64) {
-    slp::NearArgs<double> a = iw_args<double>(G);
+    slp::NearArgs<double> a = iw_args<double>(G, ctx_work(G));
     a.cols = d_cols;
     HIP_TRY(slp::launch_iw_values<double>(a, g, st));
   } else {
-    slp::NearArgs<float> a = iw_args<float>(G);
+    slp::NearArgs<float> a = iw_args<float>(G, ctx_work(G));
     a.cols = d_cols;
     HIP_TRY(slp::launch_iw_values<float>(a, g, st));
   }

@@ -26,6 +26,14 @@ constexpr int kComputeUnits = 256;
 // Densities evaluated on one geometry by one launch of every stage.
 constexpr int kMaxBatch = 64;
 
+// Static device workspace of the evaluation that allocates nothing
+// (slp_eval_single_layer_static): one array of this many bytes per device,
+// held from the moment the library is loaded on that device until the process
+// ends. static_workspace() returns its device address on the current device.
+constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_workspace(void **ptr);
+
 // Per-item caller pointers of a batched launch (passed by value).
 struct BatchPtrs {
   const double *dens[kMaxBatch];
