@@ -34,6 +34,19 @@ constexpr size_t kStaticWorkspaceBytes = size_t(64) << 20;
 constexpr int kMaxDevices = 64;
 hipError_t static_workspace(void **ptr);
 
+// Kaiser-Bessel window factors in the gridding and interpolation kernels: on
+// each unit interval of the stencil the window is a polynomial in
+// u = 2 (t - floor(t)) - 1, fitted on the host at setup by interpolation at the
+// Chebyshev points of that degree (max error over the interval, relative to
+// the window's peak: below 1.1e-14 in FP64 at degree 16, below FP32 rounding at
+// degree 8, for every m <= kMaxM). Coefficients of stencil point j at
+// [j * (deg + 1) + d], d = 0 .. deg (monomial, ascending).
+constexpr int kKbDeg64 = 16;
+constexpr int kKbDeg32 = 8;
+constexpr int kKbCoef = 2 * kMaxM * (kKbDeg64 + 1);
+template <typename T>
+constexpr int kb_degree() { return sizeof(T) == 8 ? kKbDeg64 : kKbDeg32; }
+
 // Per-item caller pointers of a batched launch (passed by value).
 struct BatchPtrs {
   const double *dens[kMaxBatch];
@@ -55,8 +68,7 @@ struct SpreadBinsArgs {
   T inv_b;               // 1 / b of the Gaussian exp(-tau^2 / b)
   T step_ratio;          // exp(-2 / b): ratio of consecutive weight ratios
   int32_t window;        // 0 Gaussian (recurrence), 1 Kaiser-Bessel
-  T kb_b;                // b of the Kaiser-Bessel window
-  T kb_inv_norm;         // m / sinh(b m): the KB window scaled to 1 at tau = 0
+  T kb_c[kKbCoef];       // Kaiser-Bessel window polynomials (see kKbDeg64)
 };
 
 // Sum of the padded blocks of the segments in the neighbouring tiles into the
@@ -85,7 +97,7 @@ struct InterpArgs {
   int64_t nt;
   T inv_b;
   int32_t window;
-  T kb_b, kb_inv_norm;
+  T kb_b, kb_inv_norm;   // Kaiser-Bessel b and m / sinh(b m) (window scaled to 1 at 0)
 };
 
 // One batched 1-D FFT pass over "lines" of a 3-D array. Element e of line L is
@@ -213,6 +225,20 @@ hipError_t launch_iw_apply(const NearArgs<T> &a, const IwOut<T> &o, const BatchP
 const void *near_gbar_kernel();
 template <typename T>
 const void *near_apply_kernel(int nb, bool packed);
+
+}  // namespace slp
+
+struct slp_geom;
+
+namespace slp {
+
+// For the request server (host only): bytes of one item's work buffers; grow a
+// context's work buffers to nb items (synchronises `s`, and the device only if
+// captured graphs of the context may still run); destroy a context whose
+// launches have all completed (no device-wide synchronisation).
+int64_t item_device_bytes(const slp_geom *g);
+int reserve_items(slp_geom *g, int nb, hipStream_t s);
+void destroy_idle(slp_geom *g);
 
 // Message returned by slp_last_error() on the calling thread.
 void set_error_message(const char *msg);

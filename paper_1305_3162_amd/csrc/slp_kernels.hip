@@ -43,6 +43,22 @@ __device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
   return (e - T(1) / e) * T(0.5) / s * inv_norm;
 }
 
+// Kaiser-Bessel window at the 2m stencil points of a point with fraction f,
+// u = 2 f - 1: out[j] = q * P_j(u), P_j the polynomial fitted on the host for
+// the window at tau = f + m - 1 - j (Horner; the coefficient indices are
+// compile-time, so they are read as wave-uniform kernel arguments).
+template <typename T, int M>
+__device__ __forceinline__ void kb_stencil(const T (&c)[kKbCoef], T u, T q, T *out) {
+  constexpr int D = kb_degree<T>();
+#pragma unroll
+  for (int j = 0; j < 2 * M; ++j) {
+    T p = c[j * (D + 1) + D];
+#pragma unroll
+    for (int d = D - 1; d >= 0; --d) p = p * u + c[j * (D + 1) + d];
+    out[j] = p * q;
+  }
+}
+
 // ----------------------------------------------------------------- spread ---
 // Phase A (one workgroup of 8 or 16 waves per work unit; the setup gives every
 // unit one segment, the sources of one tile or an equal piece of a crowded
@@ -82,7 +98,7 @@ struct SpreadShape {
   static constexpr int P3 = PD * PD * PD;
   static constexpr int COLS = W * W;
   static constexpr int NP = (COLS + 63) / 64;          // column passes per wave
-  static constexpr int WAVES = M <= 5 ? 16 : 8;
+  static constexpr int WAVES = 8;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int SBW = 12;                       // sources per wave chunk of factors
   static constexpr int WST = 3 * W + 1;                // LDS stride of one source's factors
@@ -243,14 +259,16 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
               }
             }
           } else {
-            // Kaiser-Bessel: every lane evaluates stencil points directly
-            for (int idx = lane; idx < 3 * n * W; idx += 64) {
-              const int j = idx % W, rest = idx / W;
-              const int ax = rest / n, sl = rest - ax * n;
+            // Kaiser-Bessel: one (source, axis) per lane evaluates the window
+            // polynomials of the 2m stencil points at u = 2 frac - 1 (the
+            // coefficients are the same on every lane)
+            if (lane < 3 * n) {
+              const int ax = lane / n, sl = lane - ax * n;
               const int si = off + c0 + sl;
-              T w = kb_weight<T>(src[ax][si] + T(M - 1 - j), T(M), a.kb_b, a.kb_inv_norm);
-              if (ax == 0) w *= src[3][si];
-              ww[sl * FST + ax * W + j] = w;
+              const T u = T(2) * src[ax][si] - T(1);
+              const T q = ax == 0 ? src[3][si] : T(1);
+              T *dst = ww + sl * FST + ax * W;
+              kb_stencil<T, M>(a.kb_c, u, q, dst);
             }
           }
           wave_sync();
