@@ -471,9 +471,19 @@ const char *slp_last_error(void);
  * geometries are evicted, least recently used first, and rebuilt on their next
  * request. Requests are admitted in arrival order as slots and memory free up,
  * except that a request whose geometry is already running never blocks later
- * requests for other geometries; it is chained onto that geometry's stream
- * instead (continuous batching). A geometry larger than the whole budget fails
- * its requests with SLP_ENOMEM. The server calls are thread-safe. */
+ * requests for other geometries. The pending requests of one geometry are
+ * coalesced into one batched evaluation (as slp_eval_batched; up to 8 per
+ * launch, as many as the geometry's work buffers were sized for at setup, which
+ * counts towards the budget), launched on a free stream or chained behind the
+ * geometry's running work (continuous batching, up to 4 launches in flight per
+ * stream). Once an older request waits for a stream or for memory, nothing more
+ * is chained onto busy streams, so waiting is bounded under any load. A device
+ * error fails the requests of its launch only. A geometry larger than the whole
+ * budget fails its requests with SLP_ENOMEM. The server calls are thread-safe;
+ * submissions never wait for setups, evictions or launches (a worker thread
+ * does those). Latency is measured from the moment slp_server_submit is
+ * entered. Statistics reset (slp_server_get_stats with reset != 0) clears the
+ * latencies and every counter. */
 typedef struct slp_server slp_server;
 
 typedef struct {
@@ -482,6 +492,7 @@ typedef struct {
                                    first submission) */
   int64_t completed, failed, queued, in_flight;
   int64_t resident_bytes, setups, evictions;
+  int64_t launches;             /* batched launches that served the completed requests */
 } slp_server_stats;
 
 /* n_slots in [1, 64] streams; device_budget_bytes > 0 bounds the device memory

@@ -64,7 +64,7 @@ class ServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
                 ("resident_bytes", ctypes.c_int64), ("setups", ctypes.c_int64),
-                ("evictions", ctypes.c_int64)]
+                ("evictions", ctypes.c_int64), ("launches", ctypes.c_int64)]
 
 
 _lib = None

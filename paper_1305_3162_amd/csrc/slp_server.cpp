@@ -1,33 +1,28 @@
 // Request server: a worker thread that keeps geometries resident on the
-// device, admits solves by memory, runs them on a pool of streams and
-// chains requests for a running geometry onto its stream (the policy is in
-// slp_scheduler.hpp). Latency is measured from submit to the moment the
-// worker observes the solve's completion event.
+// device, admits solves by memory, coalesces the pending requests of one
+// geometry into batched launches on a pool of streams (the policy is in
+// slp_scheduler.hpp, the threading in slp_server_core.hpp). Latency is
+// measured from submission to the moment the worker observes the launch's
+// completion event.
 #include "slp.h"
 #include "slp_internal.hpp"
 #include "slp_scheduler.hpp"
+#include "slp_server_core.hpp"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
-#include <chrono>
 #include <cmath>
-#include <condition_variable>
 #include <cstring>
 #include <map>
-#include <mutex>
 #include <new>
 #include <string>
-#include <thread>
 #include <vector>
 
 namespace {
 
-double now_s() {
-  using namespace std::chrono;
-  return duration<double>(steady_clock::now().time_since_epoch()).count();
-}
+constexpr int kServerBatch = 8;        // largest launch of one geometry
+constexpr int kServerLaunches = 4;     // launches in flight per stream
 
 struct HostGeometry {
   std::vector<double> nodes;
@@ -37,47 +32,71 @@ struct HostGeometry {
   double near_eps = 0.0;         // near-field correction within this distance (0: none)
   slp_geom *geom = nullptr;
   int64_t points = 0;
+  int batch = 1;                 // requests one launch takes (work buffers reserved for them)
 };
 
+// The device side of the scheduler; every method runs on the worker thread.
 struct HipDevice {
-  std::vector<HostGeometry> *geoms = nullptr;
+  using Payload = HostGeometry;
+  std::vector<HostGeometry> geoms;
   std::vector<hipStream_t> streams;
   hipStream_t setup_stream = nullptr;
-  std::map<uint64_t, hipEvent_t> events;   // ticket -> completion event
+  int64_t budget = 0;
+  std::map<uint64_t, hipEvent_t> events;   // first ticket of a launch -> completion event
   std::vector<hipEvent_t> free_events;
 
+  void add(HostGeometry &&h) { geoms.push_back(std::move(h)); }
+
   int setup(int64_t g, int64_t *bytes) {
-    HostGeometry &h = (*geoms)[g];
+    HostGeometry &h = geoms[g];
     slp_params p = h.params;
     p.es_w = h.es_w.data();
     p.es_gamma = h.es_gamma.data();
     int rc = slp_setup_geometry(&h.geom, h.nodes.data(), (int64_t)h.nodes.size() / 3, h.tris.data(),
                                 (int64_t)h.tris.size() / 3, &p, setup_stream);
-    if (rc) return rc;
-    if (h.near_eps > 0.0) {
-      rc = slp_setup_near_field(h.geom, h.near_eps, setup_stream);
-      if (rc) {
-        slp_geom_destroy(h.geom);
-        h.geom = nullptr;
-        return rc;
-      }
+    if (!rc && h.near_eps > 0.0) rc = slp_setup_near_field(h.geom, h.near_eps, setup_stream);
+    // work buffers for batched launches: as many more items as fit in 1/16 of
+    // the budget (at most kServerBatch in all; one where even that is too much)
+    if (!rc) {
+      const int64_t ib = std::max<int64_t>(slp::item_device_bytes(h.geom), 1);
+      h.batch = (int)std::min<int64_t>(kServerBatch, 1 + (budget / 16) / ib);
+      if (slp::reserve_items(h.geom, h.batch, setup_stream) != SLP_OK) h.batch = 1;
+    }
+    if (rc) {
+      if (h.geom) slp::destroy_idle(h.geom);
+      h.geom = nullptr;
+      return rc;
     }
     slp_geom_info info;
     slp_geom_get_info(h.geom, &info);
     *bytes = info.device_bytes;
-    h.points = info.n_src + info.n_nodes;
+    h.points = info.n_src + info.n_targets;
     return 0;
   }
   void release(int64_t g) {
-    HostGeometry &h = (*geoms)[g];
-    if (h.geom) slp_geom_destroy(h.geom);
+    HostGeometry &h = geoms[g];
+    // the scheduler evicts only geometries whose launches have all completed
+    if (h.geom) slp::destroy_idle(h.geom);
     h.geom = nullptr;
   }
-  int launch(int slot, const slp::SchedRequest &r) {
-    HostGeometry &h = (*geoms)[r.geom];
+  int max_batch(int64_t g) { return geoms[g].batch; }
+  int launch(int slot, const std::vector<slp::SchedRequest> &grp) {
+    HostGeometry &h = geoms[grp[0].geom];
     hipStream_t st = streams[slot];
-    int rc = slp_set_density(h.geom, static_cast<const double *>(r.dens), st);
-    if (!rc) rc = slp_eval_single_layer(h.geom, static_cast<double *>(r.phi), st);
+    int rc;
+    if (grp.size() == 1) {
+      rc = slp_set_density(h.geom, static_cast<const double *>(grp[0].dens), st);
+      if (!rc) rc = slp_eval_single_layer(h.geom, static_cast<double *>(grp[0].phi), st);
+    } else {
+      std::vector<slp_geom *> gs(grp.size(), h.geom);
+      std::vector<const double *> ds(grp.size());
+      std::vector<double *> ps(grp.size());
+      for (size_t i = 0; i < grp.size(); ++i) {
+        ds[i] = static_cast<const double *>(grp[i].dens);
+        ps[i] = static_cast<double *>(grp[i].phi);
+      }
+      rc = slp_eval_batched(gs.data(), ds.data(), ps.data(), (int32_t)grp.size(), st);
+    }
     if (rc) return rc;
     hipEvent_t ev;
     if (!free_events.empty()) {
@@ -90,12 +109,12 @@ struct HipDevice {
       free_events.push_back(ev);
       return SLP_EDEVICE;
     }
-    events[r.ticket] = ev;
+    events[grp[0].ticket] = ev;
     return 0;
   }
-  int query(int slot, const slp::SchedRequest &r) {
+  int query(int slot, const std::vector<slp::SchedRequest> &grp) {
     (void)slot;
-    auto it = events.find(r.ticket);
+    auto it = events.find(grp[0].ticket);
     if (it == events.end()) return SLP_EDEVICE;
     const hipError_t e = hipEventQuery(it->second);
     if (e == hipErrorNotReady) return 1;
@@ -103,7 +122,7 @@ struct HipDevice {
     events.erase(it);
     return e == hipSuccess ? 0 : SLP_EDEVICE;
   }
-  int64_t points(int64_t g) { return (*geoms)[g].points; }
+  int64_t points(int64_t g) { return geoms[g].points; }
 };
 
 int srv_fail(int code, const char *msg) {
@@ -114,37 +133,15 @@ int srv_fail(int code, const char *msg) {
 }  // namespace
 
 struct slp_server {
-  std::vector<HostGeometry> geoms;
   HipDevice dev;
-  slp::Scheduler<HipDevice> *sched = nullptr;
+  slp::ServerCore<HipDevice> *core = nullptr;
   int device = 0;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread worker;
-  bool stop = false;
-  bool worker_ok = true;
-  std::string worker_err;
-
-  void run() {
-    if (hipSetDevice(device) != hipSuccess) {
-      std::lock_guard<std::mutex> lk(mu);
-      worker_ok = false;
-      worker_err = "worker: hipSetDevice failed";
-      cv_done.notify_all();
-      return;
-    }
-    std::unique_lock<std::mutex> lk(mu);
-    while (!stop) {
-      const int64_t before = sched->stats().completed + sched->stats().failed;
-      sched->step(now_s());
-      if (sched->stats().completed + sched->stats().failed != before) cv_done.notify_all();
-      if (sched->idle()) {
-        cv_work.wait(lk, [&] { return stop || !sched->idle(); });
-      } else {
-        // poll the completion events again shortly; submissions wake us earlier
-        cv_work.wait_for(lk, std::chrono::microseconds(20));
-      }
-    }
+  ~slp_server() {
+    delete core;   // finishes admitted work and releases the geometries
+    for (auto &kv : dev.events) (void)hipEventDestroy(kv.second);
+    for (hipEvent_t e : dev.free_events) (void)hipEventDestroy(e);
+    for (hipStream_t st : dev.streams) (void)hipStreamDestroy(st);
+    if (dev.setup_stream) (void)hipStreamDestroy(dev.setup_stream);
   }
 };
 
@@ -160,27 +157,29 @@ int slp_server_create(slp_server **out, size_t device_budget_bytes, int32_t n_sl
     delete s;
     return srv_fail(SLP_EDEVICE, "server: hipGetDevice failed");
   }
-  s->dev.geoms = &s->geoms;
+  s->dev.budget = (int64_t)device_budget_bytes;
   for (int i = 0; i < n_slots; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t x : s->dev.streams) (void)hipStreamDestroy(x);
       delete s;
       return srv_fail(SLP_EDEVICE, "server: hipStreamCreate failed");
     }
     s->dev.streams.push_back(st);
   }
   if (hipStreamCreateWithFlags(&s->dev.setup_stream, hipStreamNonBlocking) != hipSuccess) {
-    for (hipStream_t x : s->dev.streams) (void)hipStreamDestroy(x);
     delete s;
     return srv_fail(SLP_EDEVICE, "server: hipStreamCreate failed");
   }
-  s->sched = new (std::nothrow) slp::Scheduler<HipDevice>(s->dev, (int64_t)device_budget_bytes, n_slots);
-  if (!s->sched) {
+  const int device = s->device;
+  s->core = new (std::nothrow) slp::ServerCore<HipDevice>(
+      s->dev, (int64_t)device_budget_bytes, n_slots, kServerLaunches, slp::kMaxBatch,
+      [device]() -> std::string {
+        return hipSetDevice(device) == hipSuccess ? std::string() : "worker: hipSetDevice failed";
+      });
+  if (!s->core) {
     delete s;
     return srv_fail(SLP_ENOMEM, "server: host allocation failed");
   }
-  s->worker = std::thread([s] { s->run(); });
   *out = s;
   return SLP_OK;
 }
@@ -208,9 +207,7 @@ int slp_server_add_geometry_near(slp_server *s, const double *nodes, int64_t n_n
     if (rc) return rc;
     bytes += nb;
   }
-  std::lock_guard<std::mutex> lk(s->mu);
-  s->geoms.push_back(std::move(h));
-  *geom_id = s->sched->add_geometry(bytes);
+  *geom_id = s->core->add_geometry(bytes, std::move(h));
   return SLP_OK;
 }
 
@@ -222,23 +219,22 @@ int slp_server_add_geometry(slp_server *s, const double *nodes, int64_t n_nodes,
 int slp_server_submit(slp_server *s, int64_t geom_id, const double *dens, double *phi,
                       uint64_t *ticket) {
   if (!s || !dens || !phi || !ticket) return srv_fail(SLP_EINVAL, "server: NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  if (!s->worker_ok) return srv_fail(SLP_EDEVICE, s->worker_err.c_str());
-  if (geom_id < 0 || geom_id >= (int64_t)s->geoms.size())
+  if (geom_id < 0 || geom_id >= s->core->geometries())
     return srv_fail(SLP_EINVAL, "server: unknown geometry id");
-  slp::SchedRequest r;
-  r.geom = geom_id;
-  r.dens = dens;
-  r.phi = phi;
-  *ticket = s->sched->submit(r, now_s());
-  s->cv_work.notify_one();
+  const uint64_t t = s->core->submit(geom_id, dens, phi);
+  if (t == 0) {
+    std::string err;
+    s->core->worker_ok(&err);
+    slp::set_error_message(err.c_str());
+    return SLP_EDEVICE;
+  }
+  *ticket = t;
   return SLP_OK;
 }
 
 int slp_server_poll(slp_server *s, uint64_t ticket, int32_t *done) {
   if (!s || !done) return srv_fail(SLP_EINVAL, "server: NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  const int st = s->sched->state(ticket);
+  const int st = s->core->state(ticket);
   if (st == slp::kUnknown) return srv_fail(SLP_EINVAL, "server: unknown ticket");
   if (st < 0) {
     *done = 1;
@@ -250,75 +246,39 @@ int slp_server_poll(slp_server *s, uint64_t ticket, int32_t *done) {
 
 int slp_server_wait(slp_server *s, uint64_t ticket, double timeout_s) {
   if (!s) return srv_fail(SLP_EINVAL, "server: NULL argument");
-  std::unique_lock<std::mutex> lk(s->mu);
-  const auto deadline = std::chrono::steady_clock::now() +
-                        std::chrono::duration_cast<std::chrono::steady_clock::duration>(
-                            std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 1e9));
-  for (;;) {
-    const int st = s->sched->state(ticket);
-    if (st == slp::kUnknown) return srv_fail(SLP_EINVAL, "server: unknown ticket");
-    if (st == slp::kDone) return SLP_OK;
-    if (st < 0) return srv_fail(st, "server: request failed");
-    if (!s->worker_ok) return srv_fail(SLP_EDEVICE, s->worker_err.c_str());
-    if (s->cv_done.wait_until(lk, deadline) == std::cv_status::timeout &&
-        s->sched->state(ticket) != slp::kDone)
-      return srv_fail(SLP_ENOTREADY, "server: wait timed out");
-  }
+  const int st = s->core->wait(ticket, timeout_s);
+  if (st == slp::kDone) return SLP_OK;
+  if (st < 0 && st != slp::kUnknown) return srv_fail(st, "server: request failed");
+  std::string err;
+  if (!s->core->worker_ok(&err)) return srv_fail(SLP_EDEVICE, err.c_str());
+  if (st == slp::kUnknown) return srv_fail(SLP_EINVAL, "server: unknown ticket");
+  return srv_fail(SLP_ENOTREADY, "server: wait timed out");
 }
 
 int slp_server_get_stats(slp_server *s, slp_server_stats *out, int32_t reset) {
   if (!s || !out) return srv_fail(SLP_EINVAL, "server: NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto &st = s->sched->stats();
+  slp::ServerTotals t = s->core->totals(reset != 0);
   std::memset(out, 0, sizeof(*out));
-  std::vector<double> lat = st.latency;
-  std::sort(lat.begin(), lat.end());
-  auto pct = [&](double q) {
-    if (lat.empty()) return 0.0;
-    const double pos = q * (lat.size() - 1);
-    const size_t i = (size_t)std::floor(pos);
-    const double f = pos - i;
-    return i + 1 < lat.size() ? lat[i] * (1 - f) + lat[i + 1] * f : lat[i];
-  };
-  out->p50_s = pct(0.50);
-  out->p99_s = pct(0.99);
+  std::sort(t.latency.begin(), t.latency.end());
+  out->p50_s = slp::quantile_sorted(t.latency, 0.50);
+  out->p99_s = slp::quantile_sorted(t.latency, 0.99);
   double sum = 0;
-  for (double v : lat) sum += v;
-  out->mean_s = lat.empty() ? 0.0 : sum / lat.size();
-  const double span = st.last_done - st.first_submit;
-  out->pts_per_s = span > 0 ? st.points / span : 0.0;
-  out->completed = st.completed;
-  out->failed = st.failed;
-  out->queued = s->sched->queued();
-  out->in_flight = s->sched->in_flight();
-  out->resident_bytes = s->sched->resident_bytes();
-  out->setups = st.setups;
-  out->evictions = st.evictions;
-  if (reset) {
-    st.latency.clear();
-    st.completed = st.failed = st.points = 0;
-    st.first_submit = st.last_done = -1.0;
-  }
+  for (double v : t.latency) sum += v;
+  out->mean_s = t.latency.empty() ? 0.0 : sum / (double)t.latency.size();
+  const double span = t.last_done - t.first_submit;
+  out->pts_per_s = span > 0 ? (double)t.points / span : 0.0;
+  out->completed = t.completed;
+  out->failed = t.failed;
+  out->queued = t.queued;
+  out->in_flight = t.in_flight;
+  out->resident_bytes = t.resident_bytes;
+  out->setups = t.setups;
+  out->evictions = t.evictions;
+  out->launches = t.launches;
   return SLP_OK;
 }
 
 int slp_server_destroy(slp_server *s) {
-  if (!s) return SLP_OK;
-  {
-    std::unique_lock<std::mutex> lk(s->mu);
-    // finish what was admitted
-    while (s->worker_ok && !s->sched->idle()) s->cv_done.wait_for(lk, std::chrono::milliseconds(1));
-    s->stop = true;
-    s->cv_work.notify_all();
-  }
-  if (s->worker.joinable()) s->worker.join();
-  for (hipStream_t st : s->dev.streams) (void)hipStreamSynchronize(st);
-  s->sched->release_all();
-  for (auto &kv : s->dev.events) (void)hipEventDestroy(kv.second);
-  for (hipEvent_t e : s->dev.free_events) (void)hipEventDestroy(e);
-  for (hipStream_t st : s->dev.streams) (void)hipStreamDestroy(st);
-  if (s->dev.setup_stream) (void)hipStreamDestroy(s->dev.setup_stream);
-  delete s->sched;
   delete s;
   return SLP_OK;
 }

@@ -1,8 +1,9 @@
 // CPU simulation of the request scheduler (paper_1305_3162_amd/csrc/slp_scheduler.hpp)
 // against a fake device with a simulated clock: checks admission by memory,
-// back-pressure, eviction, continuous batching, fairness, error isolation and
-// that no slot or ticket leaks. Prints "OK <scenario>" lines; exits non-zero on
-// the first violated invariant.
+// back-pressure, eviction, continuous batching (coalescing of pending requests
+// for one geometry into one launch), bounded waiting under sustained load,
+// error isolation and that no slot or ticket leaks. Prints "OK <scenario>"
+// lines; exits non-zero on the first violated invariant.
 #include "slp_scheduler.hpp"
 
 #include <cstdio>
@@ -29,7 +30,9 @@ struct FakeDevice {
   std::map<uint64_t, int> slot_of;
   std::vector<double> slot_free;      // time the slot's stream drains
   std::set<uint64_t> fail_tickets;    // injected device errors
-  int setups = 0, releases = 0;
+  int setups = 0, releases = 0, launches = 0;
+  int batch_cap = 64;
+  std::vector<size_t> group_sizes;
   int64_t live_bytes = 0, peak_bytes = 0;
   std::vector<std::vector<uint64_t>> order;   // completion order per geometry
 
@@ -48,19 +51,33 @@ struct FakeDevice {
     live_bytes -= size[g];
     ++releases;
   }
-  int launch(int slot, const slp::SchedRequest &r) {
-    CHECK(resident[r.geom]);
+  int max_batch(int64_t) { return batch_cap; }
+  // a launch of n requests costs dur * (1 + (n - 1) / 4): batching pays
+  int launch(int slot, const std::vector<slp::SchedRequest> &grp) {
+    CHECK(!grp.empty() && (int)grp.size() <= batch_cap);
+    const int64_t g = grp[0].geom;
+    CHECK(resident[g]);
+    for (const auto &r : grp) CHECK(r.geom == g);
     const double start = std::max(now, slot_free[slot]);
-    slot_free[slot] = start + dur[r.geom];
-    finish[r.ticket] = slot_free[slot];
-    slot_of[r.ticket] = slot;
+    slot_free[slot] = start + dur[g] * (1.0 + 0.25 * (double)(grp.size() - 1));
+    for (const auto &r : grp) {
+      finish[r.ticket] = slot_free[slot];
+      slot_of[r.ticket] = slot;
+    }
+    ++launches;
+    group_sizes.push_back(grp.size());
     return 0;
   }
-  int query(int slot, const slp::SchedRequest &r) {
-    CHECK(slot_of.at(r.ticket) == slot);
-    if (now < finish.at(r.ticket)) return 1;
-    order[r.geom].push_back(r.ticket);
-    return fail_tickets.count(r.ticket) ? -3 : 0;
+  int query(int slot, const std::vector<slp::SchedRequest> &grp) {
+    const uint64_t t0 = grp[0].ticket;
+    CHECK(slot_of.at(t0) == slot);
+    if (now < finish.at(t0)) return 1;
+    bool failed = false;
+    for (const auto &r : grp) {
+      order[r.geom].push_back(r.ticket);
+      failed = failed || fail_tickets.count(r.ticket);
+    }
+    return failed ? -3 : 0;
   }
   int64_t points(int64_t g) { return 1000 + g; }
 };
@@ -96,14 +113,114 @@ static void scenario_chain_and_skip() {
   r.geom = g1;
   const uint64_t c = s.submit(r, d.now);                             // g1 behind them
   s.step(d.now);
-  // both g0 requests chained on one slot, g1 on the other: all running at once
+  // both g0 requests in one batched launch on one slot, g1 on the other: all
+  // running at once
   CHECK(s.state(a) == slp::kRunning && s.state(b) == slp::kRunning && s.state(c) == slp::kRunning);
   CHECK(s.busy_slots() == 2 && d.setups == 2);
+  CHECK(d.launches == 2 && d.group_sizes[0] == 2 && d.group_sizes[1] == 1);
   run_until_idle(s, d, 0.25, 100);
   CHECK(s.state(a) == slp::kDone && s.state(b) == slp::kDone && s.state(c) == slp::kDone);
   CHECK(d.order[g0].size() == 2 && d.order[g0][0] == a && d.order[g0][1] == b);
   CHECK(s.busy_slots() == 0 && s.in_flight() == 0 && s.queued() == 0);
+  // a request for a running geometry is chained behind its work
+  r.geom = g0;
+  const uint64_t e = s.submit(r, d.now);
+  s.step(d.now);
+  const uint64_t f = s.submit(r, d.now);
+  s.step(d.now);
+  CHECK(s.state(e) == slp::kRunning && s.state(f) == slp::kRunning && s.busy_slots() == 1);
+  run_until_idle(s, d, 0.25, 100);
+  CHECK(s.state(e) == slp::kDone && s.state(f) == slp::kDone);
   std::printf("OK chain_and_skip\n");
+}
+
+static void scenario_burst_is_one_launch() {
+  // 70 requests for one geometry arrive at once: two launches (64 + 6), the
+  // second chained behind the first; results complete in arrival order
+  FakeDevice d = make_dev({40}, {1.0}, 2);
+  slp::Scheduler<FakeDevice> s(d, 100, 2);
+  const int64_t g0 = s.add_geometry();
+  slp::SchedRequest r;
+  r.geom = g0;
+  std::vector<uint64_t> t;
+  for (int i = 0; i < 70; ++i) t.push_back(s.submit(r, d.now));
+  s.step(d.now);
+  CHECK(d.launches == 2 && d.group_sizes[0] == 64 && d.group_sizes[1] == 6);
+  CHECK(s.busy_slots() == 1 && s.in_flight() == 70 && s.queued() == 0);
+  run_until_idle(s, d, 0.25, 100);
+  CHECK(s.stats().completed == 70 && s.stats().launches == 2);
+  CHECK(d.order[g0].size() == 70);
+  for (int i = 0; i < 70; ++i) CHECK(d.order[g0][i] == t[i]);
+  // a smaller batch limit of the device splits the burst accordingly
+  FakeDevice d2 = make_dev({40}, {1.0}, 1);
+  d2.batch_cap = 8;
+  slp::Scheduler<FakeDevice> s2(d2, 100, 1);
+  s2.add_geometry();
+  for (int i = 0; i < 20; ++i) s2.submit(r, d2.now);
+  s2.step(d2.now);
+  CHECK(d2.launches == 3 && d2.group_sizes[0] == 8 && d2.group_sizes[2] == 4);
+  run_until_idle(s2, d2, 0.25, 100);
+  CHECK(s2.stats().completed == 20);
+  std::printf("OK burst_is_one_launch\n");
+}
+
+static void scenario_bounded_wait_under_load() {
+  // five hot geometries, four slots, arrivals that never stop: without the
+  // fairness rule the four running geometries keep their slots by chaining
+  // and the fifth waits until arrivals end; with it, every request of the
+  // fifth waits a bounded time
+  const int G = 5, SLOTS = 4;
+  FakeDevice d = make_dev({10, 10, 10, 10, 10}, {0.1, 0.1, 0.1, 0.1, 0.1}, SLOTS);
+  slp::Scheduler<FakeDevice> s(d, 1000, SLOTS, 4);
+  for (int g = 0; g < G; ++g) s.add_geometry(10);
+  std::mt19937_64 rng(7);
+  std::map<uint64_t, double> t_sub;
+  std::map<uint64_t, int64_t> geom_of;
+  double worst5 = 0.0, worst = 0.0;
+  int submitted = 0, fifth = 0, done5 = 0;
+  for (int it = 0; it < 20000; ++it) {
+    // the first four geometries get a request every other step on average
+    // (25 per unit time each, below a slot's capacity, enough to keep it busy),
+    // the fifth now and then
+    for (int g = 0; g < 4; ++g) {
+      if (rng() % 2) continue;
+      slp::SchedRequest r;
+      r.geom = g;
+      const uint64_t t = s.submit(r, d.now);
+      t_sub[t] = d.now;
+      geom_of[t] = g;
+      ++submitted;
+    }
+    if (rng() % 50 == 0) {
+      slp::SchedRequest r;
+      r.geom = 4;
+      const uint64_t t = s.submit(r, d.now);
+      t_sub[t] = d.now;
+      geom_of[t] = 4;
+      ++submitted;
+      ++fifth;
+    }
+    s.step(d.now);
+    for (uint64_t t : s.changed())
+      if (s.state(t) == slp::kDone) {
+        const double lat = d.now - t_sub[t];
+        worst = std::max(worst, lat);
+        if (geom_of[t] == 4) {
+          worst5 = std::max(worst5, lat);
+          ++done5;
+        }
+      }
+    CHECK(s.busy_slots() <= SLOTS);
+    d.now += 0.02;
+  }
+  // the longest launch: 64 requests at 0.1 (1 + 63/4) = 1.675; a waiter gets the
+  // next slot to drain, which holds at most 4 launches
+  CHECK(fifth > 100);
+  CHECK(done5 >= fifth - 4);   // all but the last few (still in flight) completed
+  CHECK(worst5 <= 4 * 1.675 + 1.0);
+  CHECK(worst <= 4 * 1.675 * 3 + 1.0);
+  std::printf("OK bounded_wait_under_load worst_fifth=%.3f worst=%.3f submitted=%d\n", worst5,
+              worst, submitted);
 }
 
 static void scenario_memory_backpressure_and_eviction() {
@@ -140,13 +257,20 @@ static void scenario_oversized_and_errors() {
   r.geom = big;
   const uint64_t a = s.submit(r, d.now);
   r.geom = small;
-  const uint64_t b = s.submit(r, d.now), c = s.submit(r, d.now), e = s.submit(r, d.now);
+  const uint64_t b = s.submit(r, d.now);
+  s.step(d.now);                               // b launched alone
+  const uint64_t c = s.submit(r, d.now), e = s.submit(r, d.now);
+  s.step(d.now);                               // c and e: one launch chained behind b
+  CHECK(d.launches == 2 && d.group_sizes[1] == 2);
   d.fail_tickets.insert(c);
   run_until_idle(s, d, 0.1, 100);
+  const uint64_t f = s.submit(r, d.now);
+  run_until_idle(s, d, 0.1, 100);
   CHECK(s.state(a) == -2);                      // can never fit
-  CHECK(s.state(b) == slp::kDone && s.state(e) == slp::kDone);
-  CHECK(s.state(c) == -3);                      // injected device error, isolated
-  CHECK(s.stats().failed == 2 && s.stats().completed == 2);
+  CHECK(s.state(b) == slp::kDone && s.state(f) == slp::kDone);
+  // an injected device error fails its launch (both requests), nothing else
+  CHECK(s.state(c) == -3 && s.state(e) == -3);
+  CHECK(s.stats().failed == 3 && s.stats().completed == 2);
   CHECK(s.state(999999) == slp::kUnknown);
   std::printf("OK oversized_and_errors\n");
 }
@@ -200,6 +324,8 @@ static void scenario_random_stress() {
 
 int main() {
   scenario_chain_and_skip();
+  scenario_burst_is_one_launch();
+  scenario_bounded_wait_under_load();
   scenario_memory_backpressure_and_eviction();
   scenario_oversized_and_errors();
   scenario_random_stress();

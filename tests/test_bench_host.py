@@ -1,7 +1,8 @@
 """bench.py's host logic (no GPU): the algorithmic bytes of the near-field
 product for either storage of its values, the storage option, the committed
-HBM-traffic table (its source hash must match the gridding kernels as they
-stand, or the bench reports no traffic), and the one-GPU refusal."""
+HBM-traffic table (its source hashes must match the kernels as they stand, or
+the bench reports no traffic), the window choice at the precision gates, and
+the one-GPU refusal."""
 import argparse
 import json
 import os
@@ -42,16 +43,41 @@ def test_near_storage_option():
 
 
 def test_traffic_table_matches_the_kernels_as_they_stand():
-    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_cube64.json")))
-    args = argparse.Namespace(workload="cube64", precision="fp64", window="gauss",
-                              near_tol=None, near_storage="context", integrated=0)
-    t = bench.measured_traffic(args, 8, "spread_bins", 1)
-    assert t is not None and t == rec["entries"]["cube64/fp64/gauss/m8"]["bytes_per_launch"]
-    # configurations no counter run covers report none
-    assert bench.measured_traffic(args, 8, "interp", 1) is None
-    assert bench.measured_traffic(args, 8, "spread_bins", 2) is None
-    args.near_tol, args.near_storage = 1e-4, "fp32"
-    assert bench.measured_traffic(args, 8, "near", 1) is None
+    """Every committed counter entry is reported only while the kernel sources
+    it was taken on are unchanged (comments aside); a changed kernel source
+    makes the bench report no traffic until the counters are retaken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        assert bench.measured_traffic("film512/fp64/kb/m4", "spread_bins", 1) is None
+        return
+    rec = json.load(open(path))
+    for key, e in rec["entries"].items():
+        t = bench.measured_traffic(key, e["stage"], 1)
+        assert t == e["bytes_per_launch"], key
+        # another stage, a batch, or an unknown workload report none
+        assert bench.measured_traffic(key, "no_such_stage", 1) is None
+        assert bench.measured_traffic(key, e["stage"], 2) is None
+    assert bench.measured_traffic("no/such/key", "spread_bins", 1) is None
+
+
+def test_traffic_keys():
+    assert bench.traffic_key("film512", "fp64", "kb", 4) == "film512/fp64/kb/m4"
+    assert bench.traffic_key("cube64", "fp64", "gauss", 8, 1e-4, "fp32") == \
+        "cube64/fp64/gauss/m8/near0.0001/storedfp32"
+    assert bench.traffic_key("cube64", "fp64", "gauss", 8, 1e-4, "context") == \
+        "cube64/fp64/gauss/m8/near0.0001"
+
+
+def test_window_choice_follows_the_precision_gate():
+    a = argparse.Namespace(m=None, window=None, tol=None, precision="fp64")
+    assert bench.resolve_window(a, slp, slp.FP64) == slp.choose_cutoff(1e-6, slp.FP64)
+    a.precision = "fp32"
+    assert bench.resolve_window(a, slp, slp.FP32) == slp.choose_cutoff(1e-4, slp.FP32)
+    a.window = "gauss"
+    w, m = bench.resolve_window(a, slp, slp.FP32)
+    assert w == slp.WINDOW_GAUSS and (w, m) == slp.choose_cutoff(1e-4, slp.FP32, slp.WINDOW_GAUSS)
+    a.m = 6
+    assert bench.resolve_window(a, slp, slp.FP32) == (slp.WINDOW_GAUSS, 6)
 
 
 def test_more_than_one_gpu_is_refused():

@@ -1,6 +1,7 @@
 """The request server on the GPU: every result is the same alone and in the mix
 (within rounding: the gridding's LDS accumulation order may differ), under
-memory pressure (evictions and rebuilds) and with an oversized geometry."""
+memory pressure (evictions and rebuilds) and with an oversized geometry; a
+burst of requests for one geometry is served by a few batched launches."""
 import numpy as np
 import pytest
 
@@ -137,4 +138,29 @@ def test_near_field_served_and_estimated():
         phi = torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
         srv.wait(srv.submit(gid, dens, phi), 60.0)
         assert rel_l2(phi.cpu().numpy(), want.cpu().numpy()) <= _tol(prec)
+    srv.close()
+
+
+def test_burst_is_served_by_batched_launches():
+    """16 requests for one geometry submitted while it is being set up: the
+    pending ones are coalesced (up to 8 per launch), so far fewer than 16
+    launches serve them, and every result equals its solo evaluation."""
+    wl = sphere_random(3, 18, 64, 5)
+    w, g = es_for(wl)
+    rng = np.random.default_rng(9)
+    srv = slp.Server(1 << 30, 2)
+    gid = srv.add_geometry(wl.nodes, wl.tris, wl.grid, wl.m, w, g, wl.alpha, slp.FP64, wl.eta2)
+    dens = [torch.as_tensor(rng.normal(size=wl.n_src), device="cuda") for _ in range(16)]
+    phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+            for _ in range(16)]
+    torch.cuda.synchronize()
+    tks = [srv.submit(gid, d, p) for d, p in zip(dens, phis)]
+    for tk in tks:
+        srv.wait(tk, 60.0)
+    st = srv.stats()
+    log(f"case burst of 16: launches {st['launches']}, p50 {st['p50_s'] * 1e3:.3f} ms")
+    assert st["completed"] == 16 and st["failed"] == 0
+    assert st["launches"] <= 8
+    for d, p in zip(dens, phis):
+        assert rel_l2(p.cpu().numpy(), _solo(wl, slp.FP64, d).cpu().numpy()) <= _tol(slp.FP64)
     srv.close()
