@@ -146,6 +146,8 @@ struct slp_geom {
   int32_t *tgt_perm = nullptr;
   int32_t *tgt_tile_start = nullptr;
   int32_t *tgt_active = nullptr;
+  int32_t *tgt_box = nullptr;    // per tile: bounding box of its targets' cells
+  void *kb_tab = nullptr;        // Kaiser-Bessel window polynomials in the working precision
   void *grid_a = nullptr;
   void *S1 = nullptr;
   void *S2 = nullptr;
@@ -353,7 +355,7 @@ std::vector<double> kb_polynomials(int m, double b, double inv_norm, int deg) {
     return std::sinh(b * s) / s * inv_norm;
   };
   const int n = deg + 1;
-  for (int j = 0; j < 2 * m; ++j) {
+  for (int j = 0; j < m; ++j) {
     // Chebyshev coefficients from the values at the Chebyshev points
     std::vector<double> y(n), cc(n, 0.0);
     for (int k = 0; k < n; ++k) {
@@ -378,7 +380,12 @@ std::vector<double> kb_polynomials(int m, double b, double inv_norm, int deg) {
       tprev.swap(tcur);
       tcur.swap(tnext);
     }
-    for (int d = 0; d < n; ++d) out[(size_t)j * n + d] = mono[d];
+    // the window is even, so the interval 2m - 1 - j holds P_j(-u): stored
+    // exactly so (the kernels evaluate each pair from P_j's coefficients)
+    for (int d = 0; d < n; ++d) {
+      out[(size_t)j * n + d] = mono[d];
+      out[(size_t)(2 * m - 1 - j) * n + d] = (d % 2 ? -mono[d] : mono[d]);
+    }
   }
   return out;
 }
@@ -474,6 +481,8 @@ slp::InterpArgs<T> interp_args(const slp_geom *G, const WorkBufs &W) {
   a.perm = G->tgt_perm;
   a.tile_start = G->tgt_tile_start;
   a.active = G->tgt_active;
+  a.tile_box = G->tgt_box;
+  a.kb_tab = static_cast<const T *>(G->kb_tab);
   a.g = static_cast<const T *>(W.grid_g);
   a.g_bstride = W.elems[4];
   for (int i = 0; i < 3; ++i) {
@@ -483,8 +492,6 @@ slp::InterpArgs<T> interp_args(const slp_geom *G, const WorkBufs &W) {
   a.nt = G->n_tgt;
   a.inv_b = (T)(1.0 / G->b);
   a.window = G->window;
-  a.kb_b = (T)G->b;
-  a.kb_inv_norm = (T)G->kb_inv_norm;
   return a;
 }
 
@@ -1042,6 +1049,14 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   std::vector<int64_t> seg_size;
   {
     const int CH = slp::kSpreadChunk;
+    // a chunk's runs longest first: the vector form processes several runs of a
+    // wave side by side, for as many steps as the longest of them
+    auto close_chunk = [&](const int4 &c) {
+      std::stable_sort(runs.begin() + c.z, runs.begin() + c.z + c.w, [](int32_t x, int32_t y) {
+        return ((x >> 19) & 2047) > ((y >> 19) & 2047);
+      });
+      chunks.push_back(c);
+    };
     int64_t i = 0;
     while (i < Ms) {
       const int32_t tile = skey[sorder[i]] / 512;
@@ -1063,7 +1078,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
           int64_t pos = k;
           while (pos < e) {
             if (cur.y == CH) {
-              chunks.push_back(cur);
+              close_chunk(cur);
               cur = {(int)pos, 0, (int)runs.size(), 0};
             }
             const int take = (int)std::min<int64_t>(e - pos, CH - cur.y);
@@ -1074,7 +1089,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
           }
           k = e;
         }
-        chunks.push_back(cur);
+        close_chunk(cur);
         sg.y = (int)chunks.size();
         segs.push_back(sg);
         seg_size.push_back(pe - pb);
@@ -1110,17 +1125,24 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
         const int4 ch = chunks[c];
         ok = ch.x == next_src && ch.y >= 1 && ch.y <= slp::kSpreadChunk && ch.w >= 1 &&
              ch.w <= slp::kSpreadChunk && ch.z + ch.w <= (int)runs.size();
-        int expect_off = 0;
+        // the chunk's runs (in any order) cover its sources exactly once
+        std::vector<std::pair<int, int>> span;
         for (int r = 0; ok && r < ch.w; ++r) {
           const int32_t rec = runs[ch.z + r];
           const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
-          ok = off == expect_off && cnt >= 1;
+          ok = cnt >= 1 && off + cnt <= ch.y;
           for (int k = 0; ok && k < cnt; ++k) {
             const int32_t key = skey[sorder[ch.x + off + k]];
             const int32_t cl = key % 512;
             ok = key / 512 == sg.z && (rec & 511) == cl;
           }
-          expect_off += cnt;
+          span.emplace_back(off, cnt);
+        }
+        std::sort(span.begin(), span.end());
+        int expect_off = 0;
+        for (size_t r = 0; ok && r < span.size(); ++r) {
+          ok = span[r].first == expect_off;
+          expect_off += span[r].second;
         }
         ok = ok && expect_off == ch.y;
         next_src += ch.y;
@@ -1144,6 +1166,25 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     return tstart[a + 1] - tstart[a] > tstart[b + 1] - tstart[b];
   });
   G->n_tgt_tiles = (int32_t)tgt_active.size();
+  // per tile the bounding box of its targets' cells (3 bits per bound): the
+  // interpolation stages only the grid values their stencils reach
+  std::vector<int32_t> tgt_box(ntiles, 0);
+  {
+    std::vector<int32_t> blo(3 * ntiles, 7), bhi(3 * ntiles, 0);
+    for (int64_t i = 0; i < n_tgt; ++i) {
+      const int64_t t = tbin[i] / 512;
+      const int c = tbin[i] % 512;
+      const int in[3] = {c & 7, (c >> 3) & 7, c >> 6};
+      for (int q = 0; q < 3; ++q) {
+        blo[3 * t + q] = std::min(blo[3 * t + q], in[q]);
+        bhi[3 * t + q] = std::max(bhi[3 * t + q], in[q]);
+      }
+    }
+    for (int64_t t = 0; t < ntiles; ++t)
+      if (tstart[t + 1] > tstart[t])
+        tgt_box[t] = blo[3 * t] | blo[3 * t + 1] << 3 | blo[3 * t + 2] << 6 | bhi[3 * t] << 9 |
+                     bhi[3 * t + 1] << 12 | bhi[3 * t + 2] << 15;
+  }
 
   // device allocations
   const size_t e = G->esz();
@@ -1174,6 +1215,8 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
       {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
       {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
+      {reinterpret_cast<void **>(&G->tgt_box), (size_t)ntiles * 4},
+      {&G->kb_tab, (size_t)slp::kKbCoef * e},
       {reinterpret_cast<void **>(&G->tgt_cell), (size_t)(3 * n_tgt) * 4},
       {&G->tgt_frac, (size_t)(3 * n_tgt) * e},
       {reinterpret_cast<void **>(&G->tgt_perm), (size_t)n_tgt * 4},
@@ -1228,6 +1271,13 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int2), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_box, tgt_box.data(), (size_t)ntiles * 4, hipMemcpyHostToDevice, st));
+  std::vector<float> kbt32(slp::kKbCoef);
+  for (int i = 0; i < slp::kKbCoef; ++i) kbt32[i] = (float)G->kb_coef[i];
+  if (G->prec == SLP_FP64)
+    HIP_TRY(hipMemcpyAsync(G->kb_tab, G->kb_coef.data(), slp::kKbCoef * 8, hipMemcpyHostToDevice, st));
+  else
+    HIP_TRY(hipMemcpyAsync(G->kb_tab, kbt32.data(), slp::kKbCoef * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_perm, torder.data(), n_tgt * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tri_v, tv.data(), tv.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tri_n, tnrm.data(), tnrm.size() * 8, hipMemcpyHostToDevice, st));

@@ -97,7 +97,8 @@ struct InterpArgs {
   int64_t nt;
   T inv_b;
   int32_t window;
-  T kb_b, kb_inv_norm;   // Kaiser-Bessel b and m / sinh(b m) (window scaled to 1 at 0)
+  const int32_t *tile_box;   // [tiles] cells of the tile's targets: lo x|y<<3|z<<6, hi <<9|<<12|<<15
+  const T *kb_tab;           // [2m (deg + 1)] Kaiser-Bessel window polynomials (see kKbDeg64)
 };
 
 // One batched 1-D FFT pass over "lines" of a 3-D array. Element e of line L is

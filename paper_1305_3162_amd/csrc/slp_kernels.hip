@@ -45,34 +45,66 @@ __device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
 
 // Kaiser-Bessel window at the 2m stencil points of a point with fraction f,
 // u = 2 f - 1: out[j] = q * P_j(u), P_j the polynomial fitted on the host for
-// the window at tau = f + m - 1 - j (Horner; the coefficient indices are
-// compile-time, so they are read as wave-uniform kernel arguments).
+// the window at tau = f + m - 1 - j. The window is even, so the stencil point
+// 2m - 1 - j sees P_j(-u): with P_j(u) = E_j(u^2) + u O_j(u^2) one pass over
+// the even and odd coefficients of P_j gives both points (the host stores the
+// mirrored polynomials exactly so). The coefficient indices are compile-time,
+// so they are read as wave-uniform kernel arguments.
 template <typename T, int M>
 __device__ __forceinline__ void kb_stencil(const T (&c)[kKbCoef], T u, T q, T *out) {
   constexpr int D = kb_degree<T>();
+  static_assert(D % 2 == 0, "even polynomial degree");
+  const T v = u * u;
 #pragma unroll
-  for (int j = 0; j < 2 * M; ++j) {
-    T p = c[j * (D + 1) + D];
+  for (int j = 0; j < M; ++j) {
+    const T *cj = c + j * (D + 1);
+    T e = cj[D], o = cj[D - 1];
 #pragma unroll
-    for (int d = D - 1; d >= 0; --d) p = p * u + c[j * (D + 1) + d];
-    out[j] = p * q;
+    for (int d = D - 2; d >= 0; d -= 2) e = e * v + cj[d];
+#pragma unroll
+    for (int d = D - 3; d >= 1; d -= 2) o = o * v + cj[d];
+    const T uo = u * o;
+    out[j] = (e + uo) * q;
+    out[2 * M - 1 - j] = (e - uo) * q;
+  }
+}
+
+// The 2m window factors of one source along one axis (fraction f of its
+// coordinate), times q: Gaussian by the fast-Gaussian-gridding recurrence
+// w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b) (two exponentials), Kaiser-Bessel
+// by the fitted polynomials.
+template <typename T, int M, typename A>
+__device__ __forceinline__ void stencil_factors(const A &a, T f, T q, T *dst) {
+  if (a.window == 0) {
+    const T fm = f + T(M - 1);
+    T w = wexp(-fm * fm * a.inv_b) * q;
+    T rr = wexp((T(2) * fm - T(1)) * a.inv_b);
+#pragma unroll
+    for (int j = 0; j < 2 * M; ++j) {
+      dst[j] = w;
+      w *= rr;
+      rr *= a.step_ratio;
+    }
+  } else {
+    kb_stencil<T, M>(a.kb_c, T(2) * f - T(1), q, dst);
   }
 }
 
 // ----------------------------------------------------------------- spread ---
-// Phase A (one workgroup of 8 or 16 waves per work unit; the setup gives every
-// unit one segment, the sources of one tile or an equal piece of a crowded
-// tile, longest first): the segment's sources are scattered into an FP64 LDS
-// block covering the tile plus the stencil halo, (8 + 2m - 1)^3 cells, which is
-// then stored to the segment's slot. Each wave independently takes every
-// WAVES-th run of sources that share one grid cell; its lanes cover the 2m x 2m
-// (dx, dy) columns of the stencil in ceil(4m^2 / 64) passes and keep the 2m
-// z-values of each column in registers over the whole run, adding them to the
-// LDS block once per run. The 1-D window factors of up to SBW sources at a time
-// are built in a wave-private LDS slice: Gaussian factors with the
+// Phase A (one workgroup of 8 waves per work unit; the setup gives every unit
+// one segment, the sources of one tile or an equal piece of a crowded tile,
+// longest first): the segment's sources are scattered into an FP64 LDS block
+// covering the tile plus the stencil halo, (8 + 2m - 1)^3 cells, which is then
+// stored to the segment's slot. The sources are staged in chunks; a chunk's
+// runs (sources sharing one grid cell) are ordered longest first. A wave takes
+// R runs side by side, L lanes per run: each lane keeps the 2m z-values of a
+// few (dx, dy) columns of its run's stencil in registers over the whole run
+// and adds them to the LDS block once per run. The 1-D window factors of SB
+// sources of each of the R runs are built per step in a wave-private LDS
+// slice, one (run, source, axis) per lane: Gaussian factors with the
 // fast-Gaussian-gridding recurrence w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b)
-// (two exponentials per source and axis), Kaiser-Bessel factors directly, one
-// stencil point per lane.
+// (two exponentials per source and axis), Kaiser-Bessel factors from the
+// fitted polynomials (one pass per mirrored pair of stencil points).
 // With FP64 and 2m = 16 a run is instead accumulated by the matrix cores: for
 // the sources k of a run (cell fixed, so the stencil offsets are the same),
 // the block update is sum_k fz_k[dz] fy_k[dy] fx_k[dx], for every dy a
@@ -96,18 +128,28 @@ struct SpreadShape {
   static constexpr int W = 2 * M;
   static constexpr int PD = kTile + W - 1;
   static constexpr int P3 = PD * PD * PD;
-  static constexpr int COLS = W * W;
-  static constexpr int NP = (COLS + 63) / 64;          // column passes per wave
   static constexpr int WAVES = 8;
   static constexpr int THREADS = WAVES * 64;
-  static constexpr int SBW = 12;                       // sources per wave chunk of factors
-  static constexpr int WST = 3 * W + 1;                // LDS stride of one source's factors
+  static constexpr int SBW = 12;                       // sources per factor batch (matrix form)
   static constexpr int CH = kSpreadChunk;              // sources staged per block chunk
   static constexpr int PER = (4 * CH + THREADS - 1) / THREADS;
   // FP64 with 2m = 16: a run's update goes to the matrix cores (see
   // k_spread_bins); the factors of a source then sit 16-byte aligned
   static constexpr bool MX = sizeof(T) == 8 && W == 16;
-  static constexpr int FST = MX ? 3 * W + 2 : WST;     // LDS stride of one source's factors
+  // vector form: a lane holds a CX x CY set of (dx, dy) columns (1 x 1 for
+  // 2m <= 4; 2 x 1 for FP64 up to 2m = 8, where 2 x 2 takes more registers than
+  // two workgroups per CU leave), L lanes cover one run's stencil, R runs share
+  // a wave, and the factors of SB sources of each of the R runs are built per
+  // batch
+  static constexpr int CX = W <= 4 ? 1 : 2;
+  static constexpr int CY = (W <= 4 || (sizeof(T) == 8 && W <= 8)) ? 1 : 2;
+  static constexpr int L = (W / CX) * (W / CY);
+  static constexpr int R = 64 / L;
+  static constexpr int SB0 = 64 / (3 * R);
+  static constexpr int SB = SB0 > 12 ? 12 : SB0;
+  static constexpr int NFAC = MX ? SBW : R * SB;       // factor slots per wave
+  static constexpr int FST = MX ? 3 * W + 2 : 3 * W + 1;   // LDS stride of one source's factors
+  static_assert(W % CX == 0 && W % CY == 0 && L <= 64 && R >= 1 && SB >= 1, "gridding shape");
 };
 
 int64_t pad_cells(int m) {
@@ -118,7 +160,7 @@ int64_t pad_cells(int m) {
 int spread_units_per_cu(int m, bool fp64) {
   auto lds = [](auto shape, size_t esz) {
     using S = decltype(shape);
-    return (size_t)S::P3 * 8 + (size_t)S::WAVES * S::SBW * S::FST * esz +
+    return (size_t)S::P3 * 8 + (size_t)S::WAVES * S::NFAC * S::FST * esz +
            4 * (size_t)S::CH * esz + (size_t)S::CH * 4;
   };
   size_t b = 0;
@@ -166,13 +208,13 @@ template <typename T, int M>
 __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a,
                                                                                BatchPtrs ptrs) {
   using S = SpreadShape<T, M>;
-  constexpr int W = S::W, PD = S::PD, NP = S::NP, CH = S::CH;
+  constexpr int W = S::W, PD = S::PD, CH = S::CH;
   // The block is accumulated in FP64 in both precisions: LDS FP64 atomic adds
   // are native and fast on gfx950, FP32 LDS atomic adds measured several times
   // slower; the block is stored in T.
   constexpr int FST = S::FST;
   __shared__ double pad[S::P3];
-  __shared__ __attribute__((aligned(16))) T wts[S::WAVES * S::SBW * FST];
+  __shared__ __attribute__((aligned(16))) T wts[S::WAVES * S::NFAC * FST];
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
 
@@ -180,15 +222,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   const double *dens = ptrs.dens[blockIdx.y];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  T *ww = wts + wave * S::SBW * FST;
-  int dxp[NP], dyp[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int col = lane + 64 * p;
-    dxp[p] = col % W;
-    dyp[p] = col / W;
-  }
-  const bool last_act = (lane + 64 * (NP - 1)) < S::COLS;
+  T *ww = wts + wave * S::NFAC * FST;
   const int64_t ns = a.ns;
 
   for (int q = a.unit_segs[unit]; q < a.unit_segs[unit + 1]; ++q) {
@@ -222,57 +256,24 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
       if (tid < ch.w) rrec[tid] = rv;
       __syncthreads();
 
-      for (int r = wave; r < ch.w; r += S::WAVES) {
-        const int rec = rrec[r];
-        const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
-        const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
-        // vector form: acc[p][j] for column lane + 64 p and dz = j; matrix
-        // form: macc[dy][r] for dx = lane % 16, dz = 4 r + lane / 16
-        T acc[S::MX ? 1 : NP][S::MX ? 1 : W];
-        dbl4 macc[S::MX ? W : 1];
-        if constexpr (S::MX) {
+      if constexpr (S::MX) {
+        // matrix-core form: each wave takes every WAVES-th run
+        for (int r = wave; r < ch.w; r += S::WAVES) {
+          const int rec = rrec[r];
+          const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
+          const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
+          // macc[dy][r] for dx = lane % 16, dz = 4 r + lane / 16
+          dbl4 macc[W];
 #pragma unroll
           for (int t = 0; t < W; ++t) macc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-        } else {
-#pragma unroll
-          for (int p = 0; p < NP; ++p)
-#pragma unroll
-            for (int j = 0; j < W; ++j) acc[p][j] = T(0);
-        }
-        for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
-          const int n = min(S::SBW, cnt - c0);
-          if (a.window == 0) {
-            // Gaussian: w_{j+1} = w_j r_j, r_{j+1} = r_j exp(-2/b), two exponentials per axis
+          for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
+            const int n = min(S::SBW, cnt - c0);
             if (lane < 3 * n) {
               const int ax = lane / n, sl = lane - ax * n;
               const int si = off + c0 + sl;
-              const T f = src[ax][si] + T(M - 1);
-              T w = wexp(-f * f * a.inv_b);
-              T rr = wexp((T(2) * f - T(1)) * a.inv_b);
-              if (ax == 0) w *= src[3][si];
-              T *dst = ww + sl * FST + ax * W;
-#pragma unroll
-              for (int j = 0; j < W; ++j) {
-                dst[j] = w;
-                w *= rr;
-                rr *= a.step_ratio;
-              }
+              stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), ww + sl * FST + ax * W);
             }
-          } else {
-            // Kaiser-Bessel: one (source, axis) per lane evaluates the window
-            // polynomials of the 2m stencil points at u = 2 frac - 1 (the
-            // coefficients are the same on every lane)
-            if (lane < 3 * n) {
-              const int ax = lane / n, sl = lane - ax * n;
-              const int si = off + c0 + sl;
-              const T u = T(2) * src[ax][si] - T(1);
-              const T q = ax == 0 ? src[3][si] : T(1);
-              T *dst = ww + sl * FST + ax * W;
-              kb_stencil<T, M>(a.kb_c, u, q, dst);
-            }
-          }
-          wave_sync();
-          if constexpr (S::MX) {
+            wave_sync();
             const int lk = lane >> 4, li = lane & 15;
             for (int g = 0; g < n; g += 4) {
               const int sl = g + lk;
@@ -290,36 +291,87 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
                     __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.y, bx, macc[2 * t2 + 1], 0, 0, 0);
               }
             }
-          } else {
-            for (int sl = 0; sl < n; ++sl) {
-              const T *f3 = ww + sl * FST;
-              T wz[W];
-#pragma unroll
-              for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
-#pragma unroll
-              for (int p = 0; p < NP; ++p) {
-                if (p == NP - 1 && !last_act) continue;
-                const T pw = f3[dxp[p]] * f3[W + dyp[p]];
-#pragma unroll
-                for (int j = 0; j < W; ++j) acc[p][j] += pw * wz[j];
-              }
-            }
+            wave_sync();
           }
-          wave_sync();
-        }
-        if constexpr (S::MX) {
           double *base = pad + (cz + (lane >> 4)) * PD * PD + cy * PD + cx + (lane & 15);
 #pragma unroll
           for (int t = 0; t < W; ++t)
 #pragma unroll
             for (int rg = 0; rg < 4; ++rg) atomicAdd(base + 4 * rg * PD * PD + t * PD, macc[t][rg]);
-        } else {
+        }
+      } else {
+        // vector form: a wave takes R runs at a time, L lanes per run; a lane
+        // keeps the W z-values of CX x CY (dx, dy) columns W / CX and W / CY
+        // apart in registers over the run (the z factors of a source are read
+        // once per CX CY columns instead of once per column; neighbouring lanes
+        // hold neighbouring x, so each flush instruction covers whole x rows)
+        constexpr int R = S::R, L = S::L, CX = S::CX, CY = S::CY, SB = S::SB;
+        const int g = lane / L, lc = lane - g * L;
+        const int dx0 = lc % (W / CX), dy0 = lc / (W / CX);
+        for (int rb = wave * R; rb < ch.w; rb += S::WAVES * R) {
+          const int r = rb + g;
+          const bool act = g < R && r < ch.w;
+          const int rec = act ? rrec[r] : 0;
+          const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
+          const int cnt = act ? (rec >> 19) & 2047 : 0;
+          int maxc = cnt;
 #pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            if (p == NP - 1 && !last_act) continue;
-            double *base = pad + (cz * PD + cy + dyp[p]) * PD + cx + dxp[p];
+          for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o));
+          T acc[CX * CY][W];
 #pragma unroll
-            for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[p][j]);
+          for (int c = 0; c < CX * CY; ++c)
+#pragma unroll
+            for (int j = 0; j < W; ++j) acc[c][j] = T(0);
+          for (int c0 = 0; c0 < maxc; c0 += SB) {
+            // factors of source c0 + b of each of the R runs: one (run, source,
+            // axis) per lane; sources beyond a run's end get zero factors
+            if (lane < R * SB * 3) {
+              const int g2 = lane / (SB * 3), b = (lane / 3) % SB, ax = lane % 3;
+              const int r2 = rb + g2;
+              T *dst = ww + (g2 * SB + b) * FST + ax * W;
+              const int rec2 = r2 < ch.w ? rrec[r2] : 0;
+              const int off2 = (rec2 >> 9) & 1023, cnt2 = r2 < ch.w ? (rec2 >> 19) & 2047 : 0;
+              if (c0 + b < cnt2) {
+                const int si = off2 + c0 + b;
+                stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), dst);
+              } else {
+#pragma unroll
+                for (int j = 0; j < W; ++j) dst[j] = T(0);
+              }
+            }
+            wave_sync();
+            if (g < R) {
+              const int nb = min(SB, maxc - c0);
+              for (int b = 0; b < nb; ++b) {
+                const T *f3 = ww + (g * SB + b) * FST;
+                T wz[W], fx[CX], fy[CY];
+#pragma unroll
+                for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
+#pragma unroll
+                for (int i = 0; i < CX; ++i) fx[i] = f3[dx0 + i * (W / CX)];
+#pragma unroll
+                for (int i = 0; i < CY; ++i) fy[i] = f3[W + dy0 + i * (W / CY)];
+#pragma unroll
+                for (int iy = 0; iy < CY; ++iy)
+#pragma unroll
+                  for (int ix = 0; ix < CX; ++ix) {
+                    const T pw = fx[ix] * fy[iy];
+#pragma unroll
+                    for (int j = 0; j < W; ++j) acc[iy * CX + ix][j] += pw * wz[j];
+                  }
+              }
+            }
+            wave_sync();
+          }
+          if (act) {
+#pragma unroll
+            for (int iy = 0; iy < CY; ++iy)
+#pragma unroll
+              for (int ix = 0; ix < CX; ++ix) {
+                double *base = pad + (cz * PD + cy + dy0 + iy * (W / CY)) * PD + cx + dx0 + ix * (W / CX);
+#pragma unroll
+                for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[iy * CX + ix][j]);
+              }
           }
         }
       }
@@ -431,33 +483,43 @@ hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &
 }
 
 // ----------------------------------------------------------------- interp ---
-// One workgroup per tile holding targets: the grid values of the tile plus the
-// stencil halo are staged in LDS, the 1-D factors of a batch of 64 targets are
-// computed, then each wave takes its targets one at a time, or two of one
-// cell together: its lanes cover the (dy, dz) rows of the stencil, sum the
-// 2m values of each row in T and accumulate row * wy * wz in FP64; a wave
-// reduction gives the node value.
+// One workgroup per tile holding targets (largest tiles first). The grid values
+// of the bounding box of the tile's target stencils (within the tile plus its
+// halo) are staged in LDS; then every wave works through its own contiguous
+// share of the tile's targets, TG at a time, with no further workgroup
+// barrier: the target data of the next group is loaded one group ahead, the
+// 1-D window factors of a group are computed one stencil point per lane into
+// the wave's LDS slice (Gaussian: one exponential; Kaiser-Bessel: the fitted
+// polynomial, coefficients staged in LDS), and the lanes cover the (dy, dz)
+// rows of a target's stencil, sum the 2m values of each row in T (x factors
+// moved to scalar registers by readlane) and accumulate row * wy * wz in FP64.
+// Targets are sorted by cell, so two consecutive targets of one cell share
+// each row read. The TG sums are reduced across the wave together. Workgroups
+// are sized so that several share a CU (the staged block sets the LDS).
 template <typename T, int M>
 struct InterpShape {
   static constexpr int W = 2 * M;
   static constexpr int PD = kTile + W - 1;
   static constexpr int P3 = PD * PD * PD;
-  static constexpr int WAVES = 16;
+  static constexpr int TG = 4;                                     // targets per wave group
+  static constexpr int FIT = (160 * 1024) / (P3 * (int)sizeof(T) + 6 * 1024);
+  static constexpr int WAVES = FIT >= 4 ? 4 : (FIT >= 2 ? 8 : 16);
   static constexpr int THREADS = WAVES * 64;
-  static constexpr int TB = 64;       // targets per batch
-  static constexpr int PERG = (P3 + THREADS - 1) / THREADS;
+  static constexpr int PERG = (P3 + THREADS - 1) / THREADS;       // staged cells per thread
+  static constexpr int NKB = W * (kKbDeg64 + 1);                  // KB coefficient slots
 };
 
 template <typename T, int M>
 __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpArgs<T> a,
                                                                           BatchPtrs ptrs) {
   using S = InterpShape<T, M>;
-  constexpr int W = S::W, PD = S::PD;
+  constexpr int W = S::W, PD = S::PD, TG = S::TG, D = kb_degree<T>();
   __shared__ T gt[S::P3];
-  __shared__ T wts[S::TB][3][W];
-  __shared__ int32_t tcell[S::TB][3];
-  __shared__ T tfrac[S::TB][3];
-  __shared__ int32_t tperm[S::TB];
+  __shared__ T wf[S::WAVES][TG][3][W];     // window factors of each wave's group
+  __shared__ T tfr[S::WAVES][TG][3];       // fractions of each wave's group
+  __shared__ int32_t tcl[S::WAVES][TG][3]; // cells (in the tile) of each wave's group
+  __shared__ int32_t tpm[S::WAVES][TG];    // caller indices of each wave's group
+  __shared__ T kbc[S::NKB];
 
   const int tid = threadIdx.x;
   const int tile = a.active[blockIdx.x];
@@ -471,29 +533,14 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
   const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t nt = a.nt;
-  // target data of a batch (3 cells, 3 fractions, permutation), loaded into
-  // registers one batch ahead so that its latency overlaps the previous batch
-  constexpr int LPT = (7 * S::TB + S::THREADS - 1) / S::THREADS;
-  int32_t ci[LPT];
-  T fr[LPT];
-  auto load_batch = [&](int b0) {
-    const int nb = min(S::TB, t1 - b0);
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int idx = tid + k * S::THREADS;
-      const int item = idx % S::TB, kind = idx / S::TB;   // kind 0..2 cell, 3..5 frac, 6 perm
-      ci[k] = 0;
-      fr[k] = T(0);
-      if (item < nb && kind < 7) {
-        const int64_t i = b0 + item;
-        if (kind < 3) ci[k] = a.cell[kind * nt + i];
-        else if (kind < 6) fr[k] = a.frac[(kind - 3) * nt + i];
-        else ci[k] = a.perm[i];
-      }
-    }
-  };
+  // stencil box of the tile's targets in pad coordinates: cells lo..hi (in
+  // the tile) per axis, stencils reaching W - 1 further
+  const int32_t box = a.tile_box[tile];
+  const int bx0 = box & 7, by0 = (box >> 3) & 7, bz0 = (box >> 6) & 7;
+  const int bx1 = ((box >> 9) & 7) + W - 1, by1 = ((box >> 12) & 7) + W - 1,
+            bz1 = ((box >> 15) & 7) + W - 1;
   {
-    // issue all loads of the tile + halo and of the first batch before writing LDS
+    // issue every load of the box before writing LDS
     T v[S::PERG];
 #pragma unroll
     for (int k = 0; k < S::PERG; ++k) {
@@ -502,73 +549,92 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
       if (i < S::P3) {
         const int ix = i % PD, iy = (i / PD) % PD, iz = i / (PD * PD);
         const int gx = ox + ix, gy = oy + iy, gz = oz + iz;
-        if (gx >= 0 && gx < a.R[0] && gy >= 0 && gy < a.R[1] && gz >= 0 && gz < a.R[2])
+        if (ix >= bx0 && ix <= bx1 && iy >= by0 && iy <= by1 && iz >= bz0 && iz <= bz1 &&
+            gx >= 0 && gx < a.R[0] && gy >= 0 && gy < a.R[1] && gz >= 0 && gz < a.R[2])
           v[k] = gsrc[((int64_t)gz * Ry + gy) * Rx + gx];
       }
     }
-    load_batch(t0);
+    if (a.window != 0)
+      for (int i = tid; i < W * (D + 1); i += S::THREADS) kbc[i] = a.kb_tab[i];
 #pragma unroll
     for (int k = 0; k < S::PERG; ++k) {
       const int i = tid + k * S::THREADS;
       if (i < S::P3) gt[i] = v[k];
     }
   }
-  for (int b0 = t0; b0 < t1; b0 += S::TB) {
-    const int nb = min(S::TB, t1 - b0);
-    __syncthreads();   // grid tile loaded / previous batch finished
-#pragma unroll
-    for (int k = 0; k < LPT; ++k) {
-      const int idx = tid + k * S::THREADS;
-      const int item = idx % S::TB, kind = idx / S::TB;
-      if (item < nb && kind < 7) {
-        if (kind < 3) tcell[item][kind] = ci[k];
-        else if (kind == 6) tperm[item] = ci[k];
-        else tfrac[item][kind - 3] = fr[k];
-      }
+  __syncthreads();
+
+  // this wave's contiguous share of the tile's targets, in groups of TG
+  const int ntile = t1 - t0;
+  const int per = ((ntile + S::WAVES - 1) / S::WAVES + TG - 1) / TG * TG;
+  const int ws = t0 + wave * per, we = min(t1, ws + per);
+  // target data of a group: lane l < 7 TG holds item l % TG, kind l / TG
+  // (0..2 cell, 3..5 fraction, 6 caller index), loaded one group ahead
+  const int item = lane % TG, kind = lane / TG;
+  int32_t ci = 0;
+  T fr = T(0);
+  auto load_group = [&](int g0) {
+    ci = 0;
+    fr = T(0);
+    if (kind < 7 && g0 + item < we) {
+      const int64_t i = g0 + item;
+      if (kind < 3) ci = a.cell[kind * nt + i];
+      else if (kind < 6) fr = a.frac[(kind - 3) * nt + i];
+      else ci = a.perm[i];
     }
-    if (b0 + S::TB < t1) load_batch(b0 + S::TB);
-    __syncthreads();
-    // the 1-D window factors of the batch, one stencil point per thread
-    for (int idx = tid; idx < nb * 3 * W; idx += S::THREADS) {
+  };
+  if (ws < we) load_group(ws);
+  for (int g0 = ws; g0 < we; g0 += TG) {
+    const int ng = min(TG, we - g0);
+    if (kind < 7 && item < ng) {
+      if (kind < 3) tcl[wave][item][kind] = ci;
+      else if (kind < 6) tfr[wave][item][kind - 3] = fr;
+      else tpm[wave][item] = ci;
+    }
+    if (g0 + TG < we) load_group(g0 + TG);
+    wave_sync();
+    // window factors of the group, one stencil point per lane
+    for (int idx = lane; idx < ng * 3 * W; idx += 64) {
       const int j = idx % W, rest = idx / W;
       const int ax = rest % 3, it = rest / 3;
-      const T d = tfrac[it][ax] - T(j - M + 1);
-      wts[it][ax][j] = a.window == 0 ? wexp(-d * d * a.inv_b)
-                                     : kb_weight<T>(d, T(M), a.kb_b, a.kb_inv_norm);
-    }
-    __syncthreads();
-    // each wave takes TPW targets of the batch and reduces their sums together,
-    // so the latency of the cross-lane reduction is paid once per TPW targets
-    // each wave takes TPW consecutive targets of the batch (sorted by cell);
-    // two consecutive targets of one cell read each stencil row once. A
-    // target's sum is formed in the same order either way.
-    constexpr int TPW = S::TB / S::WAVES;
-    double acc[TPW];
+      const T f = tfr[wave][it][ax];
+      T w;
+      if (a.window == 0) {
+        const T d = f - T(j - M + 1);
+        w = wexp(-d * d * a.inv_b);
+      } else {
+        const T u = T(2) * f - T(1);
+        const T *c = kbc + j * (D + 1);
+        w = c[D];
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) acc[q] = 0.0;
-    const int sb = wave * TPW;
+        for (int d = D - 1; d >= 0; --d) w = w * u + c[d];
+      }
+      wf[wave][it][ax][j] = w;
+    }
+    wave_sync();
+    double acc[TG];
+#pragma unroll
+    for (int q = 0; q < TG; ++q) acc[q] = 0.0;
     bool consumed = false;   // the previous slot took this target as its pair
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
+    for (int q = 0; q < TG; ++q) {
       if (consumed) {
         consumed = false;
         continue;
       }
-      const int s = sb + q;
-      if (s >= nb) continue;
-      const bool two = q + 1 < TPW && s + 1 < nb && tcell[s + 1][0] == tcell[s][0] &&
-                       tcell[s + 1][1] == tcell[s][1] && tcell[s + 1][2] == tcell[s][2];
-      const int cx = tcell[s][0] - tx * kTile, cy = tcell[s][1] - ty * kTile,
-                cz = tcell[s][2] - tz * kTile;
-      // x factors are the same for every lane: one LDS read per lane, then
-      // moved to scalar registers (readlane) instead of W LDS broadcasts
-      const T wxl = wts[s][0][lane % W];
+      if (q >= ng) continue;
+      const bool two = q + 1 < ng && tcl[wave][q + 1][0] == tcl[wave][q][0] &&
+                       tcl[wave][q + 1][1] == tcl[wave][q][1] &&
+                       tcl[wave][q + 1][2] == tcl[wave][q][2];
+      const int cx = tcl[wave][q][0] - tx * kTile, cy = tcl[wave][q][1] - ty * kTile,
+                cz = tcl[wave][q][2] - tz * kTile;
+      const T wxl = wf[wave][q][0][lane % W];
       T wx[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) wx[j] = read_lane(wxl, j);
       if (two) {
-        const int q1 = q + 1 < TPW ? q + 1 : q;
-        const T wxl1 = wts[s + 1][0][lane % W];
+        const int q1 = q + 1 < TG ? q + 1 : q;
+        const T wxl1 = wf[wave][q1][0][lane % W];
         T wx1[W];
 #pragma unroll
         for (int j = 0; j < W; ++j) wx1[j] = read_lane(wxl1, j);
@@ -578,14 +644,14 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
           T a0 = T(0), a1 = T(0), c0 = T(0), c1 = T(0);
 #pragma unroll
           for (int j = 0; j < W; j += 2) {
-            const T g0 = row[j], g1 = row[j + 1];
-            a0 += g0 * wx[j];
-            a1 += g1 * wx[j + 1];
-            c0 += g0 * wx1[j];
-            c1 += g1 * wx1[j + 1];
+            const T g0v = row[j], g1v = row[j + 1];
+            a0 += g0v * wx[j];
+            a1 += g1v * wx[j + 1];
+            c0 += g0v * wx1[j];
+            c1 += g1v * wx1[j + 1];
           }
-          acc[q] += (double)((a0 + a1) * (wts[s][1][dy] * wts[s][2][dz]));
-          acc[q1] += (double)((c0 + c1) * (wts[s + 1][1][dy] * wts[s + 1][2][dz]));
+          acc[q] += (double)((a0 + a1) * (wf[wave][q][1][dy] * wf[wave][q][2][dz]));
+          acc[q1] += (double)((c0 + c1) * (wf[wave][q1][1][dy] * wf[wave][q1][2][dz]));
         }
         consumed = true;
       } else {
@@ -598,21 +664,19 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
             a0 += row[j] * wx[j];
             a1 += row[j + 1] * wx[j + 1];
           }
-          acc[q] += (double)((a0 + a1) * (wts[s][1][dy] * wts[s][2][dz]));
+          acc[q] += (double)((a0 + a1) * (wf[wave][q][1][dy] * wf[wave][q][2][dz]));
         }
       }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) acc[q] += __shfl_xor(acc[q], o);
-    if (lane == 0) {
+      for (int q = 0; q < TG; ++q) acc[q] += __shfl_xor(acc[q], o);
+    if (lane == 0)
 #pragma unroll
-      for (int q = 0; q < TPW; ++q) {
-        const int s = sb + q;
-        if (s < nb) phi[tperm[s]] = acc[q];
-      }
-    }
+      for (int q = 0; q < TG; ++q)
+        if (q < ng) phi[tpm[wave][q]] = acc[q];
+    wave_sync();   // the slices are rewritten by the next group
   }
 }
 
