@@ -413,6 +413,17 @@ int slp_fem_set_preconditioner(slp_fem *f, int32_t kind, void *stream);
  * small for *n_levels. */
 int slp_fem_amg_info(const slp_fem *f, int32_t *n_levels, int64_t *rows, int64_t *nnz,
                      int32_t cap);
+/* Host only (no device work): the mesh analysis and stiffness assembly of
+ * slp_fem_setup (eq. varu1 / poisson: S_ij = sum_T |T| grad eta_i . grad eta_j
+ * over the free, i.e. non-boundary, nodes; entries whose element contributions
+ * cancel to within their rounding are not stored). *n_free and *nnz receive
+ * the sizes; the arrays (host, may be NULL to learn the sizes first): rowptr
+ * int64 [n_free + 1], cols int32 [nnz] (free-node numbers, ascending per row),
+ * vals float64 [nnz], free_nodes int32 [n_free] (the mesh node of each free
+ * node). Errors as slp_fem_setup. */
+int slp_fem_assemble_host(const double *nodes, int64_t n_nodes, const int32_t *tets,
+                          int64_t n_tets, int64_t *n_free, int64_t *nnz, int64_t *rowptr,
+                          int32_t *cols, double *vals, int32_t *free_nodes);
 /* Host-only: builds the hierarchy of SLP_PRECOND_AMG for the symmetric
  * positive definite CSR matrix (rowptr int64 [n + 1], cols int32, vals float64,
  * host memory) and applies one cycle on the host, z = B r (host float64 [n]),

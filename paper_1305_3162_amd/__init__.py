@@ -133,6 +133,9 @@ def load_library():
                                _VP],
         "slp_fem_dphi1_dn": [_VP, _VP, _VP, _VP],
         "slp_fem_set_preconditioner": [_VP, ctypes.c_int32, _VP],
+        "slp_fem_assemble_host": [_VP, ctypes.c_int64, _VP, ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                  _VP, _VP, _VP, _VP],
         "slp_amg_apply_host": [ctypes.c_int64, _VP, _VP, _VP, _VP, _VP, ctypes.POINTER(ctypes.c_int32)],
         "slp_setup_integrated_gridding": [_VP, ctypes.c_int32, _VP],
         "slp_integrated_gridding_info": [_VP, ctypes.POINTER(ctypes.c_int32),
@@ -551,6 +554,25 @@ def integrated_gridding_info(geom):
     _check(load_library().slp_integrated_gridding_info(_VP(geom), ctypes.byref(o), ctypes.byref(n),
                                                        ctypes.byref(st), ctypes.byref(pk)))
     return {"order": o.value, "nnz": n.value, "stored": st.value, "packed": bool(pk.value)}
+
+
+def fem_assemble_host(nodes, tets):
+    """slp_fem_assemble_host: (rowptr, cols, vals, free_nodes) of the free-node
+    stiffness matrix, assembled on the host."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    lib = load_library()
+    nf, nnz = ctypes.c_int64(0), ctypes.c_int64(0)
+    args = (nodes.ctypes.data, nodes.shape[0], tets.ctypes.data, tets.shape[0])
+    _check(lib.slp_fem_assemble_host(*args, ctypes.byref(nf), ctypes.byref(nnz), None, None, None,
+                                     None))
+    rp = np.empty(nf.value + 1, dtype=np.int64)
+    ci = np.empty(nnz.value, dtype=np.int32)
+    v = np.empty(nnz.value, dtype=np.float64)
+    fn = np.empty(nf.value, dtype=np.int32)
+    _check(lib.slp_fem_assemble_host(*args, ctypes.byref(nf), ctypes.byref(nnz), rp.ctypes.data,
+                                     ci.ctypes.data, v.ctypes.data, fn.ctypes.data))
+    return rp, ci, v, fn
 
 
 def amg_apply_host(rowptr, cols, vals, r):

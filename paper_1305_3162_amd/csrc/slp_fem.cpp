@@ -124,10 +124,17 @@ struct Face {
   int32_t tet, local;
 };
 
+// The free-node stiffness matrix and the free nodes, for the host-only
+// assembly (slp_fem_assemble_host).
+struct HostAssembly {
+  std::vector<int32_t> rp, ci, free_node;
+  std::vector<double> val;
+};
+
 int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t *tets, int64_t T,
-                   hipStream_t st) {
-  if (!out) return fail(SLP_EINVAL, "out is NULL");
-  *out = nullptr;
+                   hipStream_t st, HostAssembly *host = nullptr) {
+  if (!out && !host) return fail(SLP_EINVAL, "out is NULL");
+  if (out) *out = nullptr;
   if (!nodes || !tets || N < 4 || T < 1) return fail(SLP_EINVAL, "need >= 4 nodes and >= 1 tetrahedron");
   if (N > INT32_MAX || 4 * T > INT32_MAX) return fail(SLP_EINVAL, "mesh too large for 32-bit indices");
   for (int64_t i = 0; i < 4 * T; ++i)
@@ -348,6 +355,14 @@ int fem_setup_impl(slp_fem **out, const double *nodes, int64_t N, const int32_t 
       }
     }
 
+    if (host) {
+      // host-only: the assembled matrix, no device work
+      host->rp = rp;
+      host->ci = ci;
+      host->val = val;
+      host->free_node = free_node;
+      return SLP_OK;
+    }
     F->n_free = Nf;
     F->h_S.rows = F->h_S.cols = Nf;
     F->h_S.rp = std::move(rp);
@@ -679,6 +694,23 @@ int slp_fem_set_preconditioner(slp_fem *F, int32_t kind, void *stream) {
     if (rc) return rc;
   }
   F->precond = kind;
+  return SLP_OK;
+}
+
+int slp_fem_assemble_host(const double *nodes, int64_t n_nodes, const int32_t *tets,
+                          int64_t n_tets, int64_t *n_free, int64_t *nnz, int64_t *rowptr,
+                          int32_t *cols, double *vals, int32_t *free_nodes) {
+  if (!n_free || !nnz) return fail(SLP_EINVAL, "n_free and nnz must be non-NULL");
+  HostAssembly h;
+  const int rc = fem_setup_impl(nullptr, nodes, n_nodes, tets, n_tets, nullptr, &h);
+  if (rc) return rc;
+  *n_free = (int64_t)h.free_node.size();
+  *nnz = (int64_t)h.ci.size();
+  if (rowptr)
+    for (size_t i = 0; i < h.rp.size(); ++i) rowptr[i] = h.rp[i];
+  if (cols) std::copy(h.ci.begin(), h.ci.end(), cols);
+  if (vals) std::copy(h.val.begin(), h.val.end(), vals);
+  if (free_nodes) std::copy(h.free_node.begin(), h.free_node.end(), free_nodes);
   return SLP_OK;
 }
 
