@@ -105,3 +105,31 @@ def test_full_coefficients_against_3d_quadrature():
         ref = (W * f * e).sum()
         got = full[l[0] + n[0] // 2, l[1] + n[1] // 2, l[2] + n[2] // 2]
         assert abs(got - ref) < 1e-13 * abs(full).max(), l
+
+
+def test_fourier_coeff_at_the_film_extremes():
+    """The factor tables of the thin film (grid 1024 x 1024 x 64, n = 512, 512,
+    32) at its largest kept exponents: along x (n = 512, gamma_{t,x} ~ 1.7e4,
+    e^{-gamma/4} far below rounding) the coefficients equal the whole-line
+    transform sqrt(pi/g) e^{-pi^2 l^2/g} for every l <= 256; along z (n = 32,
+    gamma_{t,z} ~ 68, where the cell truncation still matters) they equal the
+    erf closed form; both to 4e-15 of the peak, the rounding of the composite
+    rule's sum over ~4000 points. This is the film's coefficient setup at its
+    hardest terms."""
+    from oracle import direct
+    from synth.workloads import make_workload
+    wl = make_workload("film512")
+    p = direct.prepare_workload(wl)
+    assert list(p.n) == [512, 512, 32]
+    gx = p.gamma.max() / p.s[0] ** 2
+    gz = p.gamma.max() / p.s[2] ** 2
+    assert gx > 1e4 and 30 < gz < 100
+    Cx = kernel.fourier_coeff_1d(np.array([gx]), 512)[0]
+    l = np.arange(257)
+    ref = np.sqrt(np.pi / gx) * np.exp(-np.pi ** 2 * l ** 2 / gx)
+    assert np.max(np.abs(Cx - ref)) <= 4e-15 * ref[0]
+    Cz = kernel.fourier_coeff_1d(np.array([gz]), 32)[0]
+    for lz in range(17):
+        assert abs(Cz[lz] - _erf_closed_form(gz, lz)) <= 1e-14 * Cz[0], lz
+    # the table row the oracle builds for the film meets the same closed form
+    assert np.max(np.abs(p.C[0][np.argmax(p.gamma)] - ref)) <= 4e-15 * ref[0]
