@@ -134,9 +134,7 @@ struct slp_geom {
   void *src_frac = nullptr;
   double *src_w = nullptr;
   int32_t *src_perm = nullptr;
-  int32_t *unit_segs = nullptr;
-  int32_t *seg_list = nullptr;
-  int4 *segs = nullptr;
+  int4 *units = nullptr;
   int4 *chunks = nullptr;
   int32_t *runs = nullptr;
   int2 *tile_slots = nullptr;
@@ -458,9 +456,7 @@ slp::SpreadBinsArgs<T> spread_args(const slp_geom *G, const WorkBufs &W) {
   a.frac = static_cast<const T *>(G->src_frac);
   a.w = G->src_w;
   a.perm = G->src_perm;
-  a.unit_segs = G->unit_segs;
-  a.seg_list = G->seg_list;
-  a.segs = G->segs;
+  a.units = G->units;
   a.chunks = G->chunks;
   a.runs = G->runs;
   a.scratch = static_cast<T *>(W.scratch);
@@ -1101,22 +1097,27 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   // workgroups in launch order to whichever CU frees up, which balances the
   // actual run times better than any static packing by source count
   const int64_t n_units = (int64_t)segs.size();
-  std::vector<int32_t> unit_segs(n_units + 1, 0), seg_list(segs.size());
+  std::vector<int4> units(n_units);
   {
-    for (size_t k = 0; k < seg_list.size(); ++k) seg_list[k] = (int32_t)k;
-    std::stable_sort(seg_list.begin(), seg_list.end(),
+    std::vector<int32_t> order(segs.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
+    std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return seg_size[a] > seg_size[b]; });
-    for (int64_t u = 0; u < n_units; ++u) unit_segs[u + 1] = (int32_t)(u + 1);
+    for (int64_t u = 0; u < n_units; ++u) {
+      const int4 sg = segs[order[u]];
+      units[u] = {order[u], sg.x, sg.y, sg.z};
+    }
   }
   // consistency of the tables the gridding kernel indexes with (cheap, host side)
   {
     int64_t next_src = 0;
-    bool ok = unit_segs.back() == (int32_t)segs.size();
-    for (size_t u = 0; ok && u + 1 < unit_segs.size(); ++u) ok = unit_segs[u] <= unit_segs[u + 1];
+    bool ok = true;
     std::vector<char> seen(segs.size(), 0);
-    for (size_t k = 0; ok && k < seg_list.size(); ++k) {
-      ok = seg_list[k] >= 0 && seg_list[k] < (int32_t)segs.size() && !seen[seg_list[k]];
-      if (ok) seen[seg_list[k]] = 1;
+    for (size_t u = 0; ok && u < units.size(); ++u) {
+      const int4 un = units[u];
+      ok = un.x >= 0 && un.x < (int32_t)segs.size() && !seen[un.x] && un.y == segs[un.x].x &&
+           un.z == segs[un.x].y && un.w == segs[un.x].z;
+      if (ok) seen[un.x] = 1;
     }
     for (size_t sgi = 0; ok && sgi < segs.size(); ++sgi) {
       const int4 sg = segs[sgi];
@@ -1206,9 +1207,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {&G->src_frac, (size_t)(3 * Ms) * e},
       {reinterpret_cast<void **>(&G->src_w), (size_t)Ms * 8},
       {reinterpret_cast<void **>(&G->src_perm), (size_t)Ms * 4},
-      {reinterpret_cast<void **>(&G->unit_segs), unit_segs.size() * sizeof(int32_t)},
-      {reinterpret_cast<void **>(&G->segs), segs.size() * sizeof(int4)},
-      {reinterpret_cast<void **>(&G->seg_list), seg_list.size() * sizeof(int32_t)},
+      {reinterpret_cast<void **>(&G->units), units.size() * sizeof(int4)},
       {reinterpret_cast<void **>(&G->chunks), chunks.size() * sizeof(int4)},
       {reinterpret_cast<void **>(&G->runs), runs.size() * sizeof(int32_t)},
       {reinterpret_cast<void **>(&G->tile_slots), (size_t)ntiles * sizeof(int2)},
@@ -1263,9 +1262,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
 
   HIP_TRY(hipMemcpyAsync(G->src_w, wsorted.data(), Ms * 8, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->src_perm, sorder.data(), Ms * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->unit_segs, unit_segs.data(), unit_segs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->segs, segs.data(), segs.size() * sizeof(int4), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->seg_list, seg_list.data(), seg_list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int2), hipMemcpyHostToDevice, st));

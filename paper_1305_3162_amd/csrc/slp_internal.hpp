@@ -57,9 +57,7 @@ struct SpreadBinsArgs {
   const T *frac;         // [3][ns] t - floor(t), sorted order
   const double *w;       // [ns] quadrature weights, sorted order
   const int32_t *perm;   // [ns] sorted -> caller (long) index of the density
-  const int32_t *unit_segs;  // [n_units + 1] first entry of each unit in seg_list
-  const int32_t *seg_list;   // [n_slots] segments of unit u: seg_list[unit_segs[u] ..]
-  const int4 *segs;          // [n_slots] {first chunk, end chunk, tile id, 0}
+  const int4 *units;         // [n_units] {slot (segment), first chunk, end chunk, tile id}
   const int4 *chunks;        // {first source, source count, first run, run count}
   const int32_t *runs;       // cell x | y << 3 | z << 6 | offset in chunk << 9 | count << 19
   T *scratch;            // [n_slots][PD^3], blocked layout

@@ -136,20 +136,22 @@ struct SpreadShape {
   // FP64 with 2m = 16: a run's update goes to the matrix cores (see
   // k_spread_bins); the factors of a source then sit 16-byte aligned
   static constexpr bool MX = sizeof(T) == 8 && W == 16;
-  // vector form: a lane holds a CX x CY set of (dx, dy) columns (1 x 1 for
-  // 2m <= 4; 2 x 1 for FP64 up to 2m = 8, where 2 x 2 takes more registers than
-  // two workgroups per CU leave), L lanes cover one run's stencil, R runs share
-  // a wave, and the factors of SB sources of each of the R runs are built per
-  // batch
+  // vector form: a lane holds CX x CY x CZ cells of a run's stencil (CX x CY
+  // whole (dx, dy) columns, except FP64 with 2m = 8, where 2 x 2 x 4 keeps the
+  // registers within two workgroups per CU), L lanes cover one run's stencil,
+  // R runs share a wave, and the factors of SB sources of each of the R runs
+  // are built per batch
   static constexpr int CX = W <= 4 ? 1 : 2;
-  static constexpr int CY = (W <= 4 || (sizeof(T) == 8 && W <= 8)) ? 1 : 2;
-  static constexpr int L = (W / CX) * (W / CY);
+  static constexpr int CY = (W <= 4 || (sizeof(T) == 8 && W == 6)) ? 1 : 2;
+  static constexpr int CZ = sizeof(T) == 8 && W == 8 ? W / 2 : W;
+  static constexpr int L = (W / CX) * (W / CY) * (W / CZ);
   static constexpr int R = 64 / L;
   static constexpr int SB0 = 64 / (3 * R);
   static constexpr int SB = SB0 > 12 ? 12 : SB0;
   static constexpr int NFAC = MX ? SBW : R * SB;       // factor slots per wave
   static constexpr int FST = MX ? 3 * W + 2 : 3 * W + 1;   // LDS stride of one source's factors
-  static_assert(W % CX == 0 && W % CY == 0 && L <= 64 && R >= 1 && SB >= 1, "gridding shape");
+  static_assert(W % CX == 0 && W % CY == 0 && W % CZ == 0 && L <= 64 && R >= 1 && SB >= 1,
+                "gridding shape");
 };
 
 int64_t pad_cells(int m) {
@@ -218,183 +220,192 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
 
-  const int unit = blockIdx.x;
   const double *dens = ptrs.dens[blockIdx.y];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   T *ww = wts + wave * S::NFAC * FST;
   const int64_t ns = a.ns;
+  const int4 ui = a.units[blockIdx.x];   // {slot, first chunk, end chunk, tile}
 
-  for (int q = a.unit_segs[unit]; q < a.unit_segs[unit + 1]; ++q) {
-    const int sg = a.seg_list[q];
-    const int4 bc = a.segs[sg];
-    for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
-    for (int c = bc.x; c < bc.y; ++c) {
-      const int4 ch = a.chunks[c];     // {first source, count, first run, run count}
-      // issue every global load of the chunk before writing LDS
-      T v[S::PER];
-      int32_t rv = 0;
+  // The global loads of a chunk are issued one chunk ahead: those of chunk
+  // c + 1 fly while chunk c is gridded (and the header of chunk c + 2 with
+  // them), so only the first chunk's loads are waited for in full.
+  T v[S::PER];
+  int32_t rv = 0;
+  auto load_chunk = [&](const int4 &h) {
 #pragma unroll
-      for (int k = 0; k < S::PER; ++k) {
-        const int i = tid + k * S::THREADS;
-        if (i < 4 * ch.y) {
-          const int comp = i / ch.y, sl = i - comp * ch.y;
-          const int64_t si = (int64_t)ch.x + sl;
-          v[k] = comp < 3 ? a.frac[comp * ns + si] : (T)(a.w[si] * dens[a.perm[si]]);
-        }
-      }
-      if (tid < ch.w) rv = a.runs[ch.z + tid];
-      __syncthreads();                 // previous chunk finished with src / rrec
-#pragma unroll
-      for (int k = 0; k < S::PER; ++k) {
-        const int i = tid + k * S::THREADS;
-        if (i < 4 * ch.y) {
-          const int comp = i / ch.y, sl = i - comp * ch.y;
-          src[comp][sl] = v[k];
-        }
-      }
-      if (tid < ch.w) rrec[tid] = rv;
-      __syncthreads();
-
-      if constexpr (S::MX) {
-        // matrix-core form: each wave takes every WAVES-th run
-        for (int r = wave; r < ch.w; r += S::WAVES) {
-          const int rec = rrec[r];
-          const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
-          const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
-          // macc[dy][r] for dx = lane % 16, dz = 4 r + lane / 16
-          dbl4 macc[W];
-#pragma unroll
-          for (int t = 0; t < W; ++t) macc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
-          for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
-            const int n = min(S::SBW, cnt - c0);
-            if (lane < 3 * n) {
-              const int ax = lane / n, sl = lane - ax * n;
-              const int si = off + c0 + sl;
-              stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), ww + sl * FST + ax * W);
-            }
-            wave_sync();
-            const int lk = lane >> 4, li = lane & 15;
-            for (int g = 0; g < n; g += 4) {
-              const int sl = g + lk;
-              const bool ok = sl < n;
-              // slot 0 holds this batch's factors, so the loads stay finite
-              const double *f3 = reinterpret_cast<const double *>(ww) + (ok ? sl : 0) * FST;
-              const double bx = ok ? f3[li] : 0.0;
-              const double az = ok ? f3[2 * W + li] : 0.0;
-              const dbl2 *fy2 = reinterpret_cast<const dbl2 *>(f3 + W);
-#pragma unroll
-              for (int t2 = 0; t2 < W / 2; ++t2) {
-                const dbl2 fy = fy2[t2];
-                macc[2 * t2] = __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.x, bx, macc[2 * t2], 0, 0, 0);
-                macc[2 * t2 + 1] =
-                    __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.y, bx, macc[2 * t2 + 1], 0, 0, 0);
-              }
-            }
-            wave_sync();
-          }
-          double *base = pad + (cz + (lane >> 4)) * PD * PD + cy * PD + cx + (lane & 15);
-#pragma unroll
-          for (int t = 0; t < W; ++t)
-#pragma unroll
-            for (int rg = 0; rg < 4; ++rg) atomicAdd(base + 4 * rg * PD * PD + t * PD, macc[t][rg]);
-        }
-      } else {
-        // vector form: a wave takes R runs at a time, L lanes per run; a lane
-        // keeps the W z-values of CX x CY (dx, dy) columns W / CX and W / CY
-        // apart in registers over the run (the z factors of a source are read
-        // once per CX CY columns instead of once per column; neighbouring lanes
-        // hold neighbouring x, so each flush instruction covers whole x rows)
-        constexpr int R = S::R, L = S::L, CX = S::CX, CY = S::CY, SB = S::SB;
-        const int g = lane / L, lc = lane - g * L;
-        const int dx0 = lc % (W / CX), dy0 = lc / (W / CX);
-        for (int rb = wave * R; rb < ch.w; rb += S::WAVES * R) {
-          const int r = rb + g;
-          const bool act = g < R && r < ch.w;
-          const int rec = act ? rrec[r] : 0;
-          const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
-          const int cnt = act ? (rec >> 19) & 2047 : 0;
-          int maxc = cnt;
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o));
-          T acc[CX * CY][W];
-#pragma unroll
-          for (int c = 0; c < CX * CY; ++c)
-#pragma unroll
-            for (int j = 0; j < W; ++j) acc[c][j] = T(0);
-          for (int c0 = 0; c0 < maxc; c0 += SB) {
-            // factors of source c0 + b of each of the R runs: one (run, source,
-            // axis) per lane; sources beyond a run's end get zero factors
-            if (lane < R * SB * 3) {
-              const int g2 = lane / (SB * 3), b = (lane / 3) % SB, ax = lane % 3;
-              const int r2 = rb + g2;
-              T *dst = ww + (g2 * SB + b) * FST + ax * W;
-              const int rec2 = r2 < ch.w ? rrec[r2] : 0;
-              const int off2 = (rec2 >> 9) & 1023, cnt2 = r2 < ch.w ? (rec2 >> 19) & 2047 : 0;
-              if (c0 + b < cnt2) {
-                const int si = off2 + c0 + b;
-                stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), dst);
-              } else {
-#pragma unroll
-                for (int j = 0; j < W; ++j) dst[j] = T(0);
-              }
-            }
-            wave_sync();
-            if (g < R) {
-              const int nb = min(SB, maxc - c0);
-              for (int b = 0; b < nb; ++b) {
-                const T *f3 = ww + (g * SB + b) * FST;
-                T wz[W], fx[CX], fy[CY];
-#pragma unroll
-                for (int j = 0; j < W; ++j) wz[j] = f3[2 * W + j];
-#pragma unroll
-                for (int i = 0; i < CX; ++i) fx[i] = f3[dx0 + i * (W / CX)];
-#pragma unroll
-                for (int i = 0; i < CY; ++i) fy[i] = f3[W + dy0 + i * (W / CY)];
-#pragma unroll
-                for (int iy = 0; iy < CY; ++iy)
-#pragma unroll
-                  for (int ix = 0; ix < CX; ++ix) {
-                    const T pw = fx[ix] * fy[iy];
-#pragma unroll
-                    for (int j = 0; j < W; ++j) acc[iy * CX + ix][j] += pw * wz[j];
-                  }
-              }
-            }
-            wave_sync();
-          }
-          if (act) {
-#pragma unroll
-            for (int iy = 0; iy < CY; ++iy)
-#pragma unroll
-              for (int ix = 0; ix < CX; ++ix) {
-                double *base = pad + (cz * PD + cy + dy0 + iy * (W / CY)) * PD + cx + dx0 + ix * (W / CX);
-#pragma unroll
-                for (int j = 0; j < W; ++j) atomicAdd(base + j * PD * PD, (double)acc[iy * CX + ix][j]);
-              }
-          }
-        }
+    for (int k = 0; k < S::PER; ++k) {
+      const int i = tid + k * S::THREADS;
+      if (i < 4 * h.y) {
+        const int comp = i / h.y, sl = i - comp * h.y;
+        const int64_t si = (int64_t)h.x + sl;
+        v[k] = comp < 3 ? a.frac[comp * ns + si] : (T)(a.w[si] * dens[a.perm[si]]);
       }
     }
+    if (tid < h.w) rv = a.runs[h.z + tid];
+  };
+  int4 ch = a.chunks[ui.y];            // {first source, count, first run, run count}
+  int4 hn = ui.y + 1 < ui.z ? a.chunks[ui.y + 1] : ch;
+  load_chunk(ch);
+  for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
+  for (int c = ui.y; c < ui.z; ++c) {
+    __syncthreads();                   // the previous chunk is done with src / rrec
+#pragma unroll
+    for (int k = 0; k < S::PER; ++k) {
+      const int i = tid + k * S::THREADS;
+      if (i < 4 * ch.y) {
+        const int comp = i / ch.y, sl = i - comp * ch.y;
+        src[comp][sl] = v[k];
+      }
+    }
+    if (tid < ch.w) rrec[tid] = rv;
+    const int nrun = ch.w;
     __syncthreads();
-    T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)sg * S::P3;
-    {
-      // 32 lanes per pad row: x is fixed per thread, rows advance
-      const int x = tid & 31;
-      if (x < PD) {
-        int px, sx, lx;
-        pad_part<M>(x, px, sx, lx);
-        for (int rw = tid >> 5; rw < PD * PD; rw += S::THREADS / 32) {
-          const int y = rw % PD, z = rw / PD;
-          int py, sy, ly, pz, sz, lz;
-          pad_part<M>(y, py, sy, ly);
-          pad_part<M>(z, pz, sz, lz);
-          dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
-              (T)pad[rw * PD + x];
+    if (c + 1 < ui.z) {
+      ch = hn;
+      load_chunk(ch);
+      if (c + 2 < ui.z) hn = a.chunks[c + 2];
+    }
+
+    if constexpr (S::MX) {
+      // matrix-core form: each wave takes every WAVES-th run
+      for (int r = wave; r < nrun; r += S::WAVES) {
+        const int rec = rrec[r];
+        const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
+        const int off = (rec >> 9) & 1023, cnt = (rec >> 19) & 2047;
+        // macc[dy][r] for dx = lane % 16, dz = 4 r + lane / 16
+        dbl4 macc[W];
+#pragma unroll
+        for (int t = 0; t < W; ++t) macc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int c0 = 0; c0 < cnt; c0 += S::SBW) {
+          const int n = min(S::SBW, cnt - c0);
+          if (lane < 3 * n) {
+            const int ax = lane / n, sl = lane - ax * n;
+            const int si = off + c0 + sl;
+            stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), ww + sl * FST + ax * W);
+          }
+          wave_sync();
+          const int lk = lane >> 4, li = lane & 15;
+          for (int g = 0; g < n; g += 4) {
+            const int sl = g + lk;
+            const bool ok = sl < n;
+            // slot 0 holds this batch's factors, so the loads stay finite
+            const double *f3 = reinterpret_cast<const double *>(ww) + (ok ? sl : 0) * FST;
+            const double bx = ok ? f3[li] : 0.0;
+            const double az = ok ? f3[2 * W + li] : 0.0;
+            const dbl2 *fy2 = reinterpret_cast<const dbl2 *>(f3 + W);
+#pragma unroll
+            for (int t2 = 0; t2 < W / 2; ++t2) {
+              const dbl2 fy = fy2[t2];
+              macc[2 * t2] = __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.x, bx, macc[2 * t2], 0, 0, 0);
+              macc[2 * t2 + 1] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(az * fy.y, bx, macc[2 * t2 + 1], 0, 0, 0);
+            }
+          }
+          wave_sync();
+        }
+        double *base = pad + (cz + (lane >> 4)) * PD * PD + cy * PD + cx + (lane & 15);
+#pragma unroll
+        for (int t = 0; t < W; ++t)
+#pragma unroll
+          for (int rg = 0; rg < 4; ++rg) atomicAdd(base + 4 * rg * PD * PD + t * PD, macc[t][rg]);
+      }
+    } else {
+      // vector form: a wave takes R runs at a time, L lanes per run; a lane
+      // keeps CX x CY x CZ stencil cells of its run in registers over the run,
+      // W / CX, W / CY and W / CZ apart (the factors of a source are read once
+      // per CX, CY and CZ cells; neighbouring lanes hold neighbouring x, so each
+      // flush instruction covers whole x rows)
+      constexpr int R = S::R, L = S::L, CX = S::CX, CY = S::CY, CZ = S::CZ, SB = S::SB;
+      constexpr int SX = W / CX, SY = W / CY, SZ = W / CZ;
+      const int g = lane / L, lc = lane - g * L;
+      const int dx0 = lc % SX, dy0 = (lc / SX) % SY, dz0 = lc / (SX * SY);
+      for (int rb = wave * R; rb < nrun; rb += S::WAVES * R) {
+        const int r = rb + g;
+        const bool act = g < R && r < nrun;
+        const int rec = act ? rrec[r] : 0;
+        const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
+        const int cnt = act ? (rec >> 19) & 2047 : 0;
+        int maxc = cnt;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o));
+        T acc[CX * CY][CZ];
+#pragma unroll
+        for (int c2 = 0; c2 < CX * CY; ++c2)
+#pragma unroll
+          for (int j = 0; j < CZ; ++j) acc[c2][j] = T(0);
+        for (int c0 = 0; c0 < maxc; c0 += SB) {
+          // factors of source c0 + b of each of the R runs: one (run, source,
+          // axis) per lane; sources beyond a run's end get zero factors
+          if (lane < R * SB * 3) {
+            const int g2 = lane / (SB * 3), b = (lane / 3) % SB, ax = lane % 3;
+            const int r2 = rb + g2;
+            T *dst = ww + (g2 * SB + b) * FST + ax * W;
+            const int rec2 = r2 < nrun ? rrec[r2] : 0;
+            const int off2 = (rec2 >> 9) & 1023, cnt2 = r2 < nrun ? (rec2 >> 19) & 2047 : 0;
+            if (c0 + b < cnt2) {
+              const int si = off2 + c0 + b;
+              stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), dst);
+            } else {
+#pragma unroll
+              for (int j = 0; j < W; ++j) dst[j] = T(0);
+            }
+          }
+          wave_sync();
+          if (g < R) {
+            const int nb = min(SB, maxc - c0);
+            for (int b = 0; b < nb; ++b) {
+              const T *f3 = ww + (g * SB + b) * FST;
+              T wz[CZ], fx[CX], fy[CY];
+#pragma unroll
+              for (int j = 0; j < CZ; ++j) wz[j] = f3[2 * W + dz0 + j * SZ];
+#pragma unroll
+              for (int i = 0; i < CX; ++i) fx[i] = f3[dx0 + i * SX];
+#pragma unroll
+              for (int i = 0; i < CY; ++i) fy[i] = f3[W + dy0 + i * SY];
+#pragma unroll
+              for (int iy = 0; iy < CY; ++iy)
+#pragma unroll
+                for (int ix = 0; ix < CX; ++ix) {
+                  const T pw = fx[ix] * fy[iy];
+#pragma unroll
+                  for (int j = 0; j < CZ; ++j) acc[iy * CX + ix][j] += pw * wz[j];
+                }
+            }
+          }
+          wave_sync();
+        }
+        if (act) {
+#pragma unroll
+          for (int iy = 0; iy < CY; ++iy)
+#pragma unroll
+            for (int ix = 0; ix < CX; ++ix) {
+              double *base = pad + ((cz + dz0) * PD + cy + dy0 + iy * SY) * PD + cx + dx0 + ix * SX;
+#pragma unroll
+              for (int j = 0; j < CZ; ++j)
+                atomicAdd(base + j * SZ * PD * PD, (double)acc[iy * CX + ix][j]);
+            }
         }
       }
     }
-    __syncthreads();                   // block stored before the next segment clears it
+  }
+  __syncthreads();
+  T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)ui.x * S::P3;
+  {
+    // 32 lanes per pad row: x is fixed per thread, rows advance
+    const int x = tid & 31;
+    if (x < PD) {
+      int px, sx, lx;
+      pad_part<M>(x, px, sx, lx);
+      for (int rw = tid >> 5; rw < PD * PD; rw += S::THREADS / 32) {
+        const int y = rw % PD, z = rw / PD;
+        int py, sy, ly, pz, sz, lz;
+        pad_part<M>(y, py, sy, ly);
+        pad_part<M>(z, pz, sz, lz);
+        dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
+            (T)pad[rw * PD + x];
+      }
+    }
   }
 }
 
