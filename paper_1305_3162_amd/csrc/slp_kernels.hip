@@ -31,6 +31,26 @@ __device__ __forceinline__ double read_lane(double v, int j) {
   return __hiloint2double(hi, lo);
 }
 
+// v from the lane N places further round its row of 16 lanes (DPP row_ror).
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  constexpr int ctrl = 0x120 + N;
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of v over the 64 lanes of the wave, in every lane: four rotations within
+// each row of 16 lanes (register moves, no LDS traffic), then the four row
+// sums.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += row_ror<8>(v);
+  v += row_ror<4>(v);
+  v += row_ror<2>(v);
+  v += row_ror<1>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Kaiser-Bessel window of eq. KBfct in grid units, scaled to 1 at tau = 0:
 // sinh(b s) / s * inv_norm with s = sqrt(m^2 - tau^2) (|tau| <= m on every
 // stencil point; the limit b at s = 0).
@@ -499,13 +519,14 @@ hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &
 // halo) are staged in LDS; then every wave works through its own contiguous
 // share of the tile's targets, TG at a time, with no further workgroup
 // barrier: the target data of the next group is loaded one group ahead, the
-// 1-D window factors of a group are computed one stencil point per lane into
-// the wave's LDS slice (Gaussian: one exponential; Kaiser-Bessel: the fitted
-// polynomial, coefficients staged in LDS), and the lanes cover the (dy, dz)
-// rows of a target's stencil, sum the 2m values of each row in T (x factors
-// moved to scalar registers by readlane) and accumulate row * wy * wz in FP64.
-// Targets are sorted by cell, so two consecutive targets of one cell share
-// each row read. The TG sums are reduced across the wave together. Workgroups
+// 1-D window factors of a group are computed one mirrored pair of stencil
+// points per lane into the wave's LDS slice (Gaussian: an exponential per
+// point; Kaiser-Bessel: one pass over the fitted polynomial's coefficients,
+// staged in LDS), and the lanes cover the (dy, dz) rows of a target's stencil, sum
+// the 2m values of each row in T (x factors moved to scalar registers by
+// readlane) and accumulate row * wy * wz in FP64. Targets are sorted by cell,
+// so two consecutive targets of one cell share each row read. Each target's
+// sum is reduced across the wave with register moves (DPP). Workgroups
 // are sized so that several share a CU (the staged block sets the LDS).
 template <typename T, int M>
 struct InterpShape {
@@ -604,23 +625,31 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
     }
     if (g0 + TG < we) load_group(g0 + TG);
     wave_sync();
-    // window factors of the group, one stencil point per lane
-    for (int idx = lane; idx < ng * 3 * W; idx += 64) {
-      const int j = idx % W, rest = idx / W;
+    // window factors of the group, one mirrored pair of stencil points (j,
+    // 2m - 1 - j) per lane; Kaiser-Bessel: P_j(u) = E_j(u^2) + u O_j(u^2) and
+    // P_j(-u) from one pass over the coefficients
+    for (int idx = lane; idx < ng * 3 * M; idx += 64) {
+      const int j = idx % M, rest = idx / M;
       const int ax = rest % 3, it = rest / 3;
       const T f = tfr[wave][it][ax];
-      T w;
+      T w0, w1;
       if (a.window == 0) {
-        const T d = f - T(j - M + 1);
-        w = wexp(-d * d * a.inv_b);
+        const T d0 = f - T(j - M + 1), d1 = f - T(M - j);
+        w0 = wexp(-d0 * d0 * a.inv_b);
+        w1 = wexp(-d1 * d1 * a.inv_b);
       } else {
-        const T u = T(2) * f - T(1);
+        const T u = T(2) * f - T(1), v = u * u;
         const T *c = kbc + j * (D + 1);
-        w = c[D];
+        T e = c[D], o = c[D - 1];
 #pragma unroll
-        for (int d = D - 1; d >= 0; --d) w = w * u + c[d];
+        for (int d = D - 2; d >= 0; d -= 2) e = e * v + c[d];
+#pragma unroll
+        for (int d = D - 3; d >= 1; d -= 2) o = o * v + c[d];
+        w0 = e + u * o;
+        w1 = e - u * o;
       }
-      wf[wave][it][ax][j] = w;
+      wf[wave][it][ax][j] = w0;
+      wf[wave][it][ax][W - 1 - j] = w1;
     }
     wave_sync();
     double acc[TG];
@@ -680,9 +709,7 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
       }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-      for (int q = 0; q < TG; ++q) acc[q] += __shfl_xor(acc[q], o);
+    for (int q = 0; q < TG; ++q) acc[q] = wave_sum(acc[q]);
     if (lane == 0)
 #pragma unroll
       for (int q = 0; q < TG; ++q)
