@@ -182,7 +182,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblk) {
 // w^(r k), w = exp(sign 2 pi i / (R Ns)), and output r belongs at position
 // (j - k) R + k + r Ns. The last stage (R Ns = N) keeps each output in the
 // register it came from; others write it to LDS.
-template <typename F, int S, int SIGN, bool LAST>
+template <typename F, int S, int SIGN, bool LAST, int TWS>
 __device__ __forceinline__ void fft_stage(typename F::C (&v)[F::E], int t, int line,
                                           const typename F::C *__restrict__ tw,
                                           typename F::C *lds) {
@@ -202,7 +202,7 @@ __device__ __forceinline__ void fft_stage(typename F::C (&v)[F::E], int t, int l
       constexpr int step = F::NL / (R * NS);
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        C w = tw[r * k * step];
+        C w = tw[r * k * step * TWS];
         if (SIGN > 0) w.y = -w.y;
         x[r] = cmul(x[r], w);
       }
@@ -228,20 +228,22 @@ __device__ __forceinline__ void lds_gather(typename F::C (&v)[F::E], int t, int 
   for (int i = 0; i < F::E; ++i) v[i] = lds[F::slot(t + F::TL * i, line)];
 }
 
-// All stages of one transform direction, from registers to registers.
-template <typename F, int SIGN, int S = 0>
+// All stages of one transform direction, from registers to registers. The
+// twiddle table holds exp(-2 pi i k / (TWS N)) (a table of a TWS times longer
+// transform, read with stride TWS).
+template <typename F, int SIGN, int TWS = 1, int S = 0>
 __device__ __forceinline__ void fft_all(typename F::C (&v)[F::E], int t, int line,
                                         const typename F::C *__restrict__ tw,
                                         typename F::C *lds) {
   if constexpr (S < F::STAGES) {
     constexpr bool last = S == F::STAGES - 1;
-    fft_stage<F, S, SIGN, last>(v, t, line, tw, lds);
+    fft_stage<F, S, SIGN, last, TWS>(v, t, line, tw, lds);
     if constexpr (!last) {
       __syncthreads();
       lds_gather<F>(v, t, line, lds);
       __syncthreads();
     }
-    fft_all<F, SIGN, S + 1>(v, t, line, tw, lds);
+    fft_all<F, SIGN, TWS, S + 1>(v, t, line, tw, lds);
   }
 }
 
@@ -326,6 +328,123 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS)) void k_fft(FftPas
   }
 }
 
+// Real lines of length N (contiguous lines only) through a complex transform
+// of length N / 2, which halves the butterflies, the registers and the LDS
+// per line. Forward (real in, half spectrum out): the line is packed as
+// z[k] = a[2k] + i a[2k+1]; with Z = FFT(z), E[l] = (Z[l] + conj Z[N/2 - l]) / 2
+// and O[l] = -i (Z[l] - conj Z[N/2 - l]) / 2 are the transforms of the even and
+// odd samples, and X[l] = E[l] + w^l O[l], w = exp(sign 2 pi i / N), for
+// l = 0 .. N/2 (X[N/2] = E[0] - O[0]). Inverse (half spectrum X[0 .. N/2] in,
+// Hermitian, real out): Z[l] = (X[l] + conj X[N/2 - l]) + i (X[l] - conj
+// X[N/2 - l]) w^l, and z = FFT(Z) holds a[2k] + i a[2k+1]. The pairing of l
+// with N/2 - l goes through LDS (forward) or is read from global memory
+// (inverse).
+template <typename T, int N>
+__global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS)) void k_fft_real(FftPass<T> p) {
+  constexpr int NH = N / 2;
+  using F = FftCfg<T, NH, false>;
+  using C = typename F::C;
+  constexpr int E = F::E, TL = F::TL, G = F::G;
+  static_assert(F::STAGES > 1, "the pairing exchange uses the stages' LDS");
+  __shared__ C lds[G * F::NPAD];
+  const C *tw = reinterpret_cast<const C *>(p.tw);
+  const int tid = threadIdx.x;
+  const int line = tid / TL, t = tid % TL;
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+  const int64_t lb = xcd_block((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x, nblk);
+  const int64_t item = lb / gridDim.x;
+  const int64_t L = (lb % gridDim.x) * G + line;
+  const bool live = L < p.n_lines;
+  int64_t ibase = 0, obase = 0;
+  if (live) {
+    const int64_t l1i = L % p.l1, l2i = L / p.l1;
+    ibase = l1i * p.in_s1 + l2i * p.in_s2 + item * p.in_bstride;
+    obase = l1i * p.out_s1 + l2i * p.out_s2 + item * p.out_bstride;
+  }
+  const bool fwd = !p.out_real;
+  // w^l = exp(sign 2 pi i l / N) from the table of exp(-2 pi i k / N)
+  auto wl = [&](int l) {
+    C w = tw[l];
+    if (p.sign > 0) w.y = -w.y;
+    return w;
+  };
+  C v[E];
+  if (fwd) {
+    const T *in = reinterpret_cast<const T *>(p.in);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int k = t + TL * i;
+      const int e0 = (2 * k - p.in_shift) & (N - 1), e1 = (2 * k + 1 - p.in_shift) & (N - 1);
+      v[i].x = live && e0 < p.in_cnt ? in[ibase + e0] : T(0);
+      v[i].y = live && e1 < p.in_cnt ? in[ibase + e1] : T(0);
+    }
+    if (p.sign < 0) fft_all<F, -1, 2>(v, t, line, tw, lds);
+    else fft_all<F, +1, 2>(v, t, line, tw, lds);
+#pragma unroll
+    for (int i = 0; i < E; ++i) lds[F::slot(t + TL * i, line)] = v[i];
+    __syncthreads();
+    if (!live) return;
+    C *out = reinterpret_cast<C *>(p.out);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int l = t + TL * i;
+      if (l >= p.out_cnt) continue;
+      const C zl = v[i], zm = lds[F::slot((NH - l) & (NH - 1), line)];
+      C ev, od;
+      ev.x = T(0.5) * (zl.x + zm.x);
+      ev.y = T(0.5) * (zl.y - zm.y);
+      od.x = T(0.5) * (zl.y + zm.y);
+      od.y = T(-0.5) * (zl.x - zm.x);
+      out[obase + l] = cadd(ev, cmul(wl(l), od));
+    }
+    if (t == 0 && NH < p.out_cnt) {
+      C x;
+      x.x = v[0].x - v[0].y;
+      x.y = T(0);
+      out[obase + NH] = x;
+    }
+  } else {
+    const C *in = reinterpret_cast<const C *>(p.in);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int l = t + TL * i, j = NH - l;
+      C xl, xm;
+      xl.x = xl.y = xm.x = xm.y = T(0);
+      if (live && l < p.in_cnt) xl = in[ibase + l];
+      if (live && j < p.in_cnt) xm = in[ibase + j];
+      C a, b;
+      a.x = xl.x + xm.x;
+      a.y = xl.y - xm.y;
+      b.x = xl.x - xm.x;
+      b.y = xl.y + xm.y;
+      const C bw = cmul(b, wl(l));
+      v[i].x = a.x - bw.y;
+      v[i].y = a.y + bw.x;
+    }
+    if (p.sign < 0) fft_all<F, -1, 2>(v, t, line, tw, lds);
+    else fft_all<F, +1, 2>(v, t, line, tw, lds);
+    if (!live) return;
+    T *out = reinterpret_cast<T *>(p.out);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int k = t + TL * i;
+      const int e0 = (2 * k - p.out_shift) & (N - 1), e1 = (2 * k + 1 - p.out_shift) & (N - 1);
+      if (e0 < p.out_cnt) out[obase + e0] = v[i].x;
+      if (e1 < p.out_cnt) out[obase + e1] = v[i].y;
+    }
+  }
+}
+
+template <typename T, int N>
+hipError_t fft_real_n(const FftPass<T> &p, int nb, hipStream_t s) {
+  using F = FftCfg<T, N / 2, false>;
+  if (p.n_lines == 0) return hipSuccess;
+  const int64_t blocks = (p.n_lines + F::G - 1) / F::G;
+  hipLaunchKernelGGL((k_fft_real<T, N>), dim3((unsigned)blocks, (unsigned)nb), dim3(F::THREADS), 0,
+                     s, p);
+  return hipGetLastError();
+}
+
 template <typename T, int N, bool STRIDED>
 hipError_t fft_n(const FftPass<T> &p, int nb, hipStream_t s) {
   using F = FftCfg<T, N, STRIDED>;
@@ -340,6 +459,14 @@ template <typename T, int N>
 hipError_t fft_map(const FftPass<T> &p, int nb, hipStream_t s) {
   // both sides of a pass use the same lane map
   if ((p.in_es == 1) != (p.out_es == 1)) return hipErrorInvalidValue;
+  if constexpr (N >= 64) {
+    // real contiguous lines: half-length complex transform
+    const bool r2c = p.in_real && !p.in_hermitian && !p.out_real && p.out_shift == 0 &&
+                     p.out_cnt <= N / 2 + 1;
+    const bool c2r = p.in_hermitian && !p.in_real && p.out_real && p.in_shift == 0 &&
+                     p.in_cnt <= N / 2 + 1;
+    if (p.in_es == 1 && !p.mul_inv && (r2c || c2r)) return fft_real_n<T, N>(p, nb, s);
+  }
   return p.in_es == 1 ? fft_n<T, N, false>(p, nb, s) : fft_n<T, N, true>(p, nb, s);
 }
 
