@@ -137,7 +137,7 @@ struct slp_geom {
   int4 *units = nullptr;
   int4 *chunks = nullptr;
   int32_t *runs = nullptr;
-  int2 *tile_slots = nullptr;
+  int4 *tile_slots = nullptr;
   void *scratch = nullptr;
   int32_t *tgt_cell = nullptr;
   void *tgt_frac = nullptr;
@@ -1097,7 +1097,40 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   // workgroups in launch order to whichever CU frees up, which balances the
   // actual run times better than any static packing by source count
   const int64_t n_units = (int64_t)segs.size();
-  std::vector<int4> units(n_units);
+  // sub-blocks of a tile's padded block that its sources reach: along each
+  // axis the part before the tile (m - 1 cells) if a source cell lies below
+  // m - 1, the tile's own part always, the part after it if a source cell
+  // lies at 8 - m or above; bit 9 pz + 3 py + px (blocks of that tile store,
+  // and the sum reads, only those)
+  std::vector<int32_t> tile_mask(ntiles, 0);
+  {
+    const int mm = G->m;
+    for (const int4 &sg : segs) {
+      int lo[3] = {7, 7, 7}, hi[3] = {0, 0, 0};
+      for (int c = sg.x; c < sg.y; ++c)
+        for (int r = 0; r < chunks[c].w; ++r) {
+          const int32_t rec = runs[chunks[c].z + r];
+          const int cc[3] = {rec & 7, (rec >> 3) & 7, (rec >> 6) & 7};
+          for (int q = 0; q < 3; ++q) {
+            lo[q] = std::min(lo[q], cc[q]);
+            hi[q] = std::max(hi[q], cc[q]);
+          }
+        }
+      int parts[3];
+      for (int q = 0; q < 3; ++q)
+        parts[q] = (lo[q] < mm - 1 ? 1 : 0) | 2 | (hi[q] >= slp::kTile - mm ? 4 : 0);
+      int32_t mask = 0;
+      for (int pz = 0; pz < 3; ++pz)
+        for (int py = 0; py < 3; ++py)
+          for (int px = 0; px < 3; ++px)
+            if (((parts[2] >> pz) & 1) && ((parts[1] >> py) & 1) && ((parts[0] >> px) & 1))
+              mask |= 1 << (pz * 9 + py * 3 + px);
+      tile_mask[sg.z] |= mask;
+    }
+  }
+  // unit u: {slot, first chunk, end chunk, tile's sub-block mask} and the
+  // first chunk's record
+  std::vector<int4> units(2 * n_units);
   {
     std::vector<int32_t> order(segs.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = (int32_t)k;
@@ -1105,7 +1138,8 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
                      [&](int32_t a, int32_t b) { return seg_size[a] > seg_size[b]; });
     for (int64_t u = 0; u < n_units; ++u) {
       const int4 sg = segs[order[u]];
-      units[u] = {order[u], sg.x, sg.y, sg.z};
+      units[2 * u] = {order[u], sg.x, sg.y, tile_mask[sg.z]};
+      units[2 * u + 1] = chunks[sg.x];
     }
   }
   // consistency of the tables the gridding kernel indexes with (cheap, host side)
@@ -1113,10 +1147,11 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     int64_t next_src = 0;
     bool ok = true;
     std::vector<char> seen(segs.size(), 0);
-    for (size_t u = 0; ok && u < units.size(); ++u) {
-      const int4 un = units[u];
+    for (int64_t u = 0; ok && u < n_units; ++u) {
+      const int4 un = units[2 * u], c0 = units[2 * u + 1];
       ok = un.x >= 0 && un.x < (int32_t)segs.size() && !seen[un.x] && un.y == segs[un.x].x &&
-           un.z == segs[un.x].y && un.w == segs[un.x].z;
+           un.z == segs[un.x].y && un.w == tile_mask[segs[un.x].z] && c0.x == chunks[un.y].x &&
+           c0.y == chunks[un.y].y && c0.z == chunks[un.y].z && c0.w == chunks[un.y].w;
       if (ok) seen[un.x] = 1;
     }
     for (size_t sgi = 0; ok && sgi < segs.size(); ++sgi) {
@@ -1152,11 +1187,12 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     if (!ok || next_src != Ms) return fail(SLP_EDEVICE, "internal error: gridding tables inconsistent");
   }
   // the segments of one tile are consecutive (sources sorted by tile)
-  std::vector<int2> tile_slots(ntiles, int2{0, 0});
+  std::vector<int4> tile_slots(ntiles, int4{0, 0, 0, 0});
   for (size_t sgi = 0; sgi < segs.size(); ++sgi) {
-    int2 &slot = tile_slots[segs[sgi].z];
+    int4 &slot = tile_slots[segs[sgi].z];
     if (slot.y == 0) slot.x = (int)sgi;
     slot.y += 1;
+    slot.z = tile_mask[segs[sgi].z];
   }
   G->n_units = (int32_t)n_units;
   G->n_slots = (int32_t)segs.size();
@@ -1210,7 +1246,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {reinterpret_cast<void **>(&G->units), units.size() * sizeof(int4)},
       {reinterpret_cast<void **>(&G->chunks), chunks.size() * sizeof(int4)},
       {reinterpret_cast<void **>(&G->runs), runs.size() * sizeof(int32_t)},
-      {reinterpret_cast<void **>(&G->tile_slots), (size_t)ntiles * sizeof(int2)},
+      {reinterpret_cast<void **>(&G->tile_slots), (size_t)ntiles * sizeof(int4)},
       {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
       {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
       {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
@@ -1265,7 +1301,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   HIP_TRY(hipMemcpyAsync(G->units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int2), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tgt_box, tgt_box.data(), (size_t)ntiles * 4, hipMemcpyHostToDevice, st));

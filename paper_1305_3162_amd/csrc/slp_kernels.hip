@@ -245,7 +245,9 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   T *ww = wts + wave * S::NFAC * FST;
   const int64_t ns = a.ns;
-  const int4 ui = a.units[blockIdx.x];   // {slot, first chunk, end chunk, tile}
+  // {slot, first chunk, end chunk, sub-block mask of the tile} and the first
+  // chunk's record, side by side (one round trip)
+  const int4 ui = a.units[2 * blockIdx.x];
 
   // The global loads of a chunk are issued one chunk ahead: those of chunk
   // c + 1 fly while chunk c is gridded (and the header of chunk c + 2 with
@@ -264,7 +266,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
     }
     if (tid < h.w) rv = a.runs[h.z + tid];
   };
-  int4 ch = a.chunks[ui.y];            // {first source, count, first run, run count}
+  int4 ch = a.units[2 * blockIdx.x + 1];   // {first source, count, first run, run count}
   int4 hn = ui.y + 1 < ui.z ? a.chunks[ui.y + 1] : ch;
   load_chunk(ch);
   for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
@@ -412,7 +414,8 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   __syncthreads();
   T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)ui.x * S::P3;
   {
-    // 32 lanes per pad row: x is fixed per thread, rows advance
+    // 32 lanes per pad row: x is fixed per thread, rows advance; sub-blocks
+    // that no source of the tile reaches are not stored (nor read back)
     const int x = tid & 31;
     if (x < PD) {
       int px, sx, lx;
@@ -422,6 +425,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
         int py, sy, ly, pz, sz, lz;
         pad_part<M>(y, py, sy, ly);
         pad_part<M>(z, pz, sz, lz);
+        if (!((ui.w >> (pz * 9 + py * 3 + px)) & 1)) continue;
         dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
             (T)pad[rw * PD + x];
       }
@@ -446,11 +450,12 @@ __global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
   T *grid = a.grid + blockIdx.y * a.grid_bstride;
   const int c = threadIdx.x;
   const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
-  // the segment ranges of the 27 neighbouring tiles, read once per workgroup
-  __shared__ int2 nts[27];
+  // the segment ranges and sub-block masks of the 27 neighbouring tiles,
+  // read once per workgroup
+  __shared__ int4 nts[27];
   if (c < 27) {
     const int bx = tx + c % 3 - 1, by = ty + (c / 3) % 3 - 1, bz = tz + c / 9 - 1;
-    int2 ts = make_int2(0, 0);
+    int4 ts = make_int4(0, 0, 0, 0);
     if (bx >= 0 && bx < a.tiles[0] && by >= 0 && by < a.tiles[1] && bz >= 0 && bz < a.tiles[2])
       ts = a.tile_slots[bx + a.tiles[0] * (by + a.tiles[1] * bz)];
     nts[c] = ts;
@@ -459,12 +464,17 @@ __global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
   T v = T(0);
 #pragma unroll
   for (int d = 0; d < 27; ++d) {
-    const int2 ts = nts[d];
+    const int4 ts = nts[d];
     if (ts.y == 0) continue;
     const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
     // pad coordinate of this cell in the neighbour's block
     const int ix = cx - kTile * dx + M - 1, iy = cy - kTile * dy + M - 1, iz = cz - kTile * dz + M - 1;
     if (ix < 0 || ix >= PD || iy < 0 || iy >= PD || iz < 0 || iz >= PD) continue;
+    // sub-blocks of that tile that none of its sources reaches were not stored
+    const int bit = (iz < M - 1 ? 0 : (iz < M + kTile - 1 ? 9 : 18)) +
+                    (iy < M - 1 ? 0 : (iy < M + kTile - 1 ? 3 : 6)) +
+                    (ix < M - 1 ? 0 : (ix < M + kTile - 1 ? 1 : 2));
+    if (!((ts.z >> bit) & 1)) continue;
     const int off = pad_block_index<M>(ix, iy, iz);
     // the first two segments without a loop, so that the loads of all
     // neighbours can be issued before any of them is waited for
