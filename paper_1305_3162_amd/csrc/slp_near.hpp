@@ -77,6 +77,9 @@ __host__ __device__ inline double triangle_potential(const double x[3], const do
 // point is found by classifying x against the vertex, edge and face regions
 // of the triangle with the dot products of x - vertex with the two edge
 // vectors (the face region yields barycentric coordinates of the foot point).
+// This is the published Voronoi-region test of C. Ericson, Real-Time
+// Collision Detection (Morgan Kaufmann, 2005), Sec. 5.1.5, written here from
+// its description.
 inline double point_triangle_distance(const double x[3], const double a[3], const double b[3],
                                       const double c[3]) {
   double ab[3], ac[3], ap[3], bp[3], cp[3];
