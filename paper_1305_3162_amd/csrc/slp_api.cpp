@@ -1097,38 +1097,31 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   // workgroups in launch order to whichever CU frees up, which balances the
   // actual run times better than any static packing by source count
   const int64_t n_units = (int64_t)segs.size();
-  // sub-blocks of a tile's padded block that its sources reach: along each
-  // axis the part before the tile (m - 1 cells) if a source cell lies below
-  // m - 1, the tile's own part always, the part after it if a source cell
-  // lies at 8 - m or above; bit 9 pz + 3 py + px (blocks of that tile store,
-  // and the sum reads, only those)
-  std::vector<int32_t> tile_mask(ntiles, 0);
+  // pad cells of a tile's padded block that its sources reach: per axis from
+  // the lowest source cell (in the tile) to the highest plus 2m - 1, packed
+  // lo x | y << 5 | z << 10, hi << 15 | << 20 | << 25; the blocks of that tile
+  // store, and the sum reads, only that box
+  std::vector<int32_t> tile_box(ntiles, 0);
   {
-    const int mm = G->m;
+    const int w1 = 2 * G->m - 1;
+    std::vector<int4> tlo(ntiles, int4{7, 7, 7, 0}), thi(ntiles, int4{0, 0, 0, 0});
     for (const int4 &sg : segs) {
-      int lo[3] = {7, 7, 7}, hi[3] = {0, 0, 0};
+      int4 &lo = tlo[sg.z], &hi = thi[sg.z];
       for (int c = sg.x; c < sg.y; ++c)
         for (int r = 0; r < chunks[c].w; ++r) {
           const int32_t rec = runs[chunks[c].z + r];
-          const int cc[3] = {rec & 7, (rec >> 3) & 7, (rec >> 6) & 7};
-          for (int q = 0; q < 3; ++q) {
-            lo[q] = std::min(lo[q], cc[q]);
-            hi[q] = std::max(hi[q], cc[q]);
-          }
+          const int x = rec & 7, y = (rec >> 3) & 7, z = (rec >> 6) & 7;
+          lo.x = std::min(lo.x, x); lo.y = std::min(lo.y, y); lo.z = std::min(lo.z, z);
+          hi.x = std::max(hi.x, x); hi.y = std::max(hi.y, y); hi.z = std::max(hi.z, z);
         }
-      int parts[3];
-      for (int q = 0; q < 3; ++q)
-        parts[q] = (lo[q] < mm - 1 ? 1 : 0) | 2 | (hi[q] >= slp::kTile - mm ? 4 : 0);
-      int32_t mask = 0;
-      for (int pz = 0; pz < 3; ++pz)
-        for (int py = 0; py < 3; ++py)
-          for (int px = 0; px < 3; ++px)
-            if (((parts[2] >> pz) & 1) && ((parts[1] >> py) & 1) && ((parts[0] >> px) & 1))
-              mask |= 1 << (pz * 9 + py * 3 + px);
-      tile_mask[sg.z] |= mask;
+    }
+    for (const int4 &sg : segs) {
+      const int4 lo = tlo[sg.z], hi = thi[sg.z];
+      tile_box[sg.z] = lo.x | (lo.y << 5) | (lo.z << 10) | ((hi.x + w1) << 15) |
+                        ((hi.y + w1) << 20) | ((hi.z + w1) << 25);
     }
   }
-  // unit u: {slot, first chunk, end chunk, tile's sub-block mask} and the
+  // unit u: {slot, first chunk, end chunk, tile's reach box} and the
   // first chunk's record
   std::vector<int4> units(2 * n_units);
   {
@@ -1138,7 +1131,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
                      [&](int32_t a, int32_t b) { return seg_size[a] > seg_size[b]; });
     for (int64_t u = 0; u < n_units; ++u) {
       const int4 sg = segs[order[u]];
-      units[2 * u] = {order[u], sg.x, sg.y, tile_mask[sg.z]};
+      units[2 * u] = {order[u], sg.x, sg.y, tile_box[sg.z]};
       units[2 * u + 1] = chunks[sg.x];
     }
   }
@@ -1150,7 +1143,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     for (int64_t u = 0; ok && u < n_units; ++u) {
       const int4 un = units[2 * u], c0 = units[2 * u + 1];
       ok = un.x >= 0 && un.x < (int32_t)segs.size() && !seen[un.x] && un.y == segs[un.x].x &&
-           un.z == segs[un.x].y && un.w == tile_mask[segs[un.x].z] && c0.x == chunks[un.y].x &&
+           un.z == segs[un.x].y && un.w == tile_box[segs[un.x].z] && c0.x == chunks[un.y].x &&
            c0.y == chunks[un.y].y && c0.z == chunks[un.y].z && c0.w == chunks[un.y].w;
       if (ok) seen[un.x] = 1;
     }
@@ -1192,7 +1185,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     int4 &slot = tile_slots[segs[sgi].z];
     if (slot.y == 0) slot.x = (int)sgi;
     slot.y += 1;
-    slot.z = tile_mask[segs[sgi].z];
+    slot.z = tile_box[segs[sgi].z];
   }
   G->n_units = (int32_t)n_units;
   G->n_slots = (int32_t)segs.size();

@@ -57,8 +57,8 @@ struct SpreadBinsArgs {
   const T *frac;         // [3][ns] t - floor(t), sorted order
   const double *w;       // [ns] quadrature weights, sorted order
   const int32_t *perm;   // [ns] sorted -> caller (long) index of the density
-  const int4 *units;         // [n_units][2] {slot (segment), first chunk, end chunk, sub-block
-                             // mask of the tile}, the first chunk's record
+  const int4 *units;         // [n_units][2] {slot (segment), first chunk, end chunk, reach box
+                             // of the tile}, the first chunk's record
   const int4 *chunks;        // {first source, source count, first run, run count}
   const int32_t *runs;       // cell x | y << 3 | z << 6 | offset in chunk << 9 | count << 19
   T *scratch;            // [n_slots][PD^3], blocked layout
@@ -75,8 +75,9 @@ struct SpreadBinsArgs {
 template <typename T>
 struct SpreadReduceArgs {
   const T *scratch;
-  const int4 *tile_slots;        // [tiles] {first slot, slot count, sub-block mask, 0}: bit
-                                 // 9 pz + 3 py + px set if a source reaches the sub-block
+  const int4 *tile_slots;        // [tiles] {first slot, slot count, reach box, 0}: the pad
+                                 // cells the tile's sources reach, lo x | y << 5 | z << 10,
+                                 // hi << 15 | << 20 | << 25 (inclusive)
   T *grid;                       // [P_z][P_y][P_x]
   int32_t tiles[3];
   int64_t scratch_bstride, grid_bstride;

@@ -157,17 +157,25 @@ struct SpreadShape {
   // k_spread_bins); the factors of a source then sit 16-byte aligned
   static constexpr bool MX = sizeof(T) == 8 && W == 16;
   // vector form: a lane holds CX x CY x CZ cells of a run's stencil (CX x CY
-  // whole (dx, dy) columns, except FP64 with 2m = 8, where 2 x 2 x 4 keeps the
-  // registers within two workgroups per CU), L lanes cover one run's stencil,
-  // R runs share a wave, and the factors of SB sources of each of the R runs
-  // are built per batch
-  static constexpr int CX = W <= 4 ? 1 : 2;
-  static constexpr int CY = (W <= 4 || (sizeof(T) == 8 && W == 6)) ? 1 : 2;
-  static constexpr int CZ = sizeof(T) == 8 && W == 8 ? W / 2 : W;
+  // whole (dx, dy) columns, except FP64 with 2m = 8), L lanes cover one run's
+  // stencil, R runs share a wave, and the factors of SB sources of each of
+  // the R runs are built per batch; RP and PP are the LDS block's row and
+  // plane pitch, PL its size
+  // FP64 with 2m = 8: a lane holds 1 x 4 x 4 cells (x on consecutive lanes,
+  // y and z 2 apart) and the LDS block has rows of 16 and planes of 264
+  // doubles, so that a run's 32 lanes flushing one register hit 32 distinct
+  // (double-wide) banks: x 0..7, y adds 0 or 16, z adds 0 or 8 (mod 32)
+  static constexpr bool LAY8 = sizeof(T) == 8 && W == 8;
+  static constexpr int CX = (W <= 4 || LAY8) ? 1 : 2;
+  static constexpr int CY = LAY8 ? 4 : ((W <= 4 || (sizeof(T) == 8 && W == 6)) ? 1 : 2);
+  static constexpr int CZ = LAY8 ? 4 : W;
+  static constexpr int RP = LAY8 ? 16 : PD;
+  static constexpr int PP = LAY8 ? 264 : PD * PD;
+  static constexpr int PL = PP * PD;
   static constexpr int L = (W / CX) * (W / CY) * (W / CZ);
   static constexpr int R = 64 / L;
   static constexpr int SB0 = 64 / (3 * R);
-  static constexpr int SB = SB0 > 12 ? 12 : SB0;
+  static constexpr int SB = LAY8 ? 8 : (SB0 > 12 ? 12 : SB0);
   static constexpr int NFAC = MX ? SBW : R * SB;       // factor slots per wave
   static constexpr int FST = MX ? 3 * W + 2 : 3 * W + 1;   // LDS stride of one source's factors
   static_assert(W % CX == 0 && W % CY == 0 && W % CZ == 0 && L <= 64 && R >= 1 && SB >= 1,
@@ -182,7 +190,7 @@ int64_t pad_cells(int m) {
 int spread_units_per_cu(int m, bool fp64) {
   auto lds = [](auto shape, size_t esz) {
     using S = decltype(shape);
-    return (size_t)S::P3 * 8 + (size_t)S::WAVES * S::NFAC * S::FST * esz +
+    return (size_t)S::PL * 8 + (size_t)S::WAVES * S::NFAC * S::FST * esz +
            4 * (size_t)S::CH * esz + (size_t)S::CH * 4;
   };
   size_t b = 0;
@@ -235,7 +243,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   // are native and fast on gfx950, FP32 LDS atomic adds measured several times
   // slower; the block is stored in T.
   constexpr int FST = S::FST;
-  __shared__ double pad[S::P3];
+  __shared__ double pad[S::PL];
   __shared__ __attribute__((aligned(16))) T wts[S::WAVES * S::NFAC * FST];
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
@@ -245,7 +253,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   T *ww = wts + wave * S::NFAC * FST;
   const int64_t ns = a.ns;
-  // {slot, first chunk, end chunk, sub-block mask of the tile} and the first
+  // {slot, first chunk, end chunk, reach of the tile's sources} and the first
   // chunk's record, side by side (one round trip)
   const int4 ui = a.units[2 * blockIdx.x];
 
@@ -269,7 +277,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   int4 ch = a.units[2 * blockIdx.x + 1];   // {first source, count, first run, run count}
   int4 hn = ui.y + 1 < ui.z ? a.chunks[ui.y + 1] : ch;
   load_chunk(ch);
-  for (int i = tid; i < S::P3; i += S::THREADS) pad[i] = 0.0;
+  for (int i = tid; i < S::PL; i += S::THREADS) pad[i] = 0.0;
   for (int c = ui.y; c < ui.z; ++c) {
     __syncthreads();                   // the previous chunk is done with src / rrec
 #pragma unroll
@@ -326,11 +334,11 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
           }
           wave_sync();
         }
-        double *base = pad + (cz + (lane >> 4)) * PD * PD + cy * PD + cx + (lane & 15);
+        double *base = pad + (cz + (lane >> 4)) * S::PP + cy * S::RP + cx + (lane & 15);
 #pragma unroll
         for (int t = 0; t < W; ++t)
 #pragma unroll
-          for (int rg = 0; rg < 4; ++rg) atomicAdd(base + 4 * rg * PD * PD + t * PD, macc[t][rg]);
+          for (int rg = 0; rg < 4; ++rg) atomicAdd(base + 4 * rg * S::PP + t * S::RP, macc[t][rg]);
       }
     } else {
       // vector form: a wave takes R runs at a time, L lanes per run; a lane
@@ -402,10 +410,10 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
           for (int iy = 0; iy < CY; ++iy)
 #pragma unroll
             for (int ix = 0; ix < CX; ++ix) {
-              double *base = pad + ((cz + dz0) * PD + cy + dy0 + iy * SY) * PD + cx + dx0 + ix * SX;
+              double *base = pad + (cz + dz0) * S::PP + (cy + dy0 + iy * SY) * S::RP + cx + dx0 + ix * SX;
 #pragma unroll
               for (int j = 0; j < CZ; ++j)
-                atomicAdd(base + j * SZ * PD * PD, (double)acc[iy * CX + ix][j]);
+                atomicAdd(base + j * SZ * S::PP, (double)acc[iy * CX + ix][j]);
             }
         }
       }
@@ -414,10 +422,12 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   __syncthreads();
   T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)ui.x * S::P3;
   {
-    // 32 lanes per pad row: x is fixed per thread, rows advance; sub-blocks
-    // that no source of the tile reaches are not stored (nor read back)
+    // 32 lanes per pad row: x is fixed per thread, rows advance; only the box
+    // of pad cells that the tile's sources reach is stored (and read back)
     const int x = tid & 31;
-    if (x < PD) {
+    const int bxl = ui.w & 31, byl = (ui.w >> 5) & 31, bzl = (ui.w >> 10) & 31;
+    const int bxh = (ui.w >> 15) & 31, byh = (ui.w >> 20) & 31, bzh = (ui.w >> 25) & 31;
+    if (x >= bxl && x <= bxh) {
       int px, sx, lx;
       pad_part<M>(x, px, sx, lx);
       for (int rw = tid >> 5; rw < PD * PD; rw += S::THREADS / 32) {
@@ -425,9 +435,9 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
         int py, sy, ly, pz, sz, lz;
         pad_part<M>(y, py, sy, ly);
         pad_part<M>(z, pz, sz, lz);
-        if (!((ui.w >> (pz * 9 + py * 3 + px)) & 1)) continue;
+        if (y < byl || y > byh || z < bzl || z > bzh) continue;
         dst[sz * PD * PD + lz * sy * PD + lz * ly * sx + ((z - sz) * ly + (y - sy)) * lx + (x - sx)] =
-            (T)pad[rw * PD + x];
+            (T)pad[z * S::PP + y * S::RP + x];
       }
     }
   }
@@ -450,8 +460,8 @@ __global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
   T *grid = a.grid + blockIdx.y * a.grid_bstride;
   const int c = threadIdx.x;
   const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
-  // the segment ranges and sub-block masks of the 27 neighbouring tiles,
-  // read once per workgroup
+  // the segment ranges and reach boxes of the 27 neighbouring tiles, read
+  // once per workgroup
   __shared__ int4 nts[27];
   if (c < 27) {
     const int bx = tx + c % 3 - 1, by = ty + (c / 3) % 3 - 1, bz = tz + c / 9 - 1;
@@ -467,17 +477,16 @@ __global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
     const int4 ts = nts[d];
     if (ts.y == 0) continue;
     const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
-    // pad coordinate of this cell in the neighbour's block
+    // pad coordinate of this cell in the neighbour's block; pad cells of that
+    // tile that none of its sources reaches were not stored
     const int ix = cx - kTile * dx + M - 1, iy = cy - kTile * dy + M - 1, iz = cz - kTile * dz + M - 1;
-    if (ix < 0 || ix >= PD || iy < 0 || iy >= PD || iz < 0 || iz >= PD) continue;
-    // sub-blocks of that tile that none of its sources reaches were not stored
-    const int bit = (iz < M - 1 ? 0 : (iz < M + kTile - 1 ? 9 : 18)) +
-                    (iy < M - 1 ? 0 : (iy < M + kTile - 1 ? 3 : 6)) +
-                    (ix < M - 1 ? 0 : (ix < M + kTile - 1 ? 1 : 2));
-    if (!((ts.z >> bit) & 1)) continue;
+    const int bx = ts.z;
+    if (ix < (bx & 31) || ix > ((bx >> 15) & 31) || iy < ((bx >> 5) & 31) ||
+        iy > ((bx >> 20) & 31) || iz < ((bx >> 10) & 31) || iz > ((bx >> 25) & 31))
+      continue;
     const int off = pad_block_index<M>(ix, iy, iz);
-    // the first two segments without a loop, so that the loads of all
-    // neighbours can be issued before any of them is waited for
+    // (issuing the neighbours' loads together, nine tiles at a time into
+    // registers, measured slower: 100-133 against 75 us on the film)
     const T *p0 = scr + (int64_t)ts.x * S::P3 + off;
     v += p0[0];
     if (ts.y > 1) v += p0[S::P3];
