@@ -593,6 +593,7 @@ int run_eval(slp_geom *G, const WorkBufs &W, const slp::BatchPtrs &ptrs, int nb,
     p.n_lines = Kx * Ky; p.l1 = Kx;
     p.in_s1 = 1; p.in_s2 = Kx; p.in_es = Ky * Kx; p.in_cnt = (int)Rz; p.in_shift = G->lo[2];
     p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
+    for (int q = 0; q < 3; ++q) p.mu_n[q] = G->n[q];
     p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
     p.sign = -1; p.mul_inv = 1;
     p.in_bstride = W.elems[3]; p.out_bstride = W.elems[3];
@@ -1222,7 +1223,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   const int64_t S1n = (int64_t)G->R[2] * G->R[1] * G->K[0];
   const int64_t S2n = (int64_t)G->R[2] * G->K[1] * G->K[0];
   const int64_t gn = (int64_t)G->R[0] * G->R[1] * G->R[2];
-  const int64_t mun = (int64_t)G->K[0] * G->K[1] * G->K[2];
+  const int64_t mun = (int64_t)(G->n[0] / 2 + 1) * (G->n[1] / 2 + 1) * (G->n[2] / 2 + 1);
   G->item_elems[0] = (int64_t)G->n_slots * slp::pad_cells(G->m);
   G->item_elems[1] = Gsz;
   G->item_elems[2] = S1n;
@@ -1380,10 +1381,10 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       HIP_TRY(hipMemcpyAsync(d_dec[q], dec.data(), dec.size() * 8, hipMemcpyHostToDevice, st));
     }
     if (G->prec == SLP_FP64)
-      HIP_TRY(slp::launch_mu<double>((double *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->K,
+      HIP_TRY(slp::launch_mu<double>((double *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n,
                                      d_dec[0], d_dec[1], d_dec[2], st));
     else
-      HIP_TRY(slp::launch_mu<float>((float *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n, G->K,
+      HIP_TRY(slp::launch_mu<float>((float *)G->mu, d_C[0], d_C[1], d_C[2], d_om, S, G->n,
                                     d_dec[0], d_dec[1], d_dec[2], st));
     HIP_TRY(hipStreamSynchronize(st));
   }

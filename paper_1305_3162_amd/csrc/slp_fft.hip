@@ -11,8 +11,8 @@
 // through LDS (write in Stockham order, read back positions t + TL i). The
 // first stage reads its inputs straight from global memory and the last one
 // leaves its outputs in the registers whose positions they belong to, so a
-// 1024-point line costs two LDS round trips (radices 16, 16, 4) instead of
-// five radix-4 passes.
+// 1024-point line costs three LDS round trips at E = 8 (radices 8, 8, 8, 2)
+// instead of nine radix-2 or five radix-4 passes.
 //
 // Two lane maps:
 //  * contiguous lines (element stride 1, the x passes): the TL threads of a
@@ -139,7 +139,12 @@ struct FftCfg {
   using C = typename Cx<T>::type;
   static constexpr int NL = N;                       // line length
   static constexpr bool STR = STRIDED;
-  static constexpr int E = N < 16 ? N : 16;          // elements per thread
+  // elements per thread: 8 (radix-8 stages) for lines of 64 and more, 16
+  // below: 16 complex values and the radix-16 temporaries take 200+ VGPRs in
+  // FP64 (two waves per SIMD) and 155+ in FP32; at 8 the kernels fit 128
+  // VGPRs, four waves per SIMD (MINW), for one more LDS round trip per line
+  static constexpr int E = N < 16 ? N : (N >= 64 ? 8 : 16);
+  static constexpr int MINW = N >= 64 ? 4 : 1;
   static constexpr int TL = N / E;                   // threads per line
   static constexpr int STAGES = (ilog2(N) + ilog2(E) - 1) / ilog2(E);
   static constexpr int R0 = E;                       // first radix
@@ -255,8 +260,23 @@ __device__ __forceinline__ void fft_dir(typename F::C (&v)[F::E], int sign, int 
   else fft_all<F, +1>(v, t, line, tw, lds);
 }
 
-template <typename T, int N, bool STRIDED>
-__global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS)) void k_fft(FftPass<T> p) {
+// The multiplier at mode (kx, ky, kz) of a z-pass line (kx, ky index) and
+// element kz index em: h(l) F(kx, |ky|, |kz|), with the weight
+// h(l) = ([l in I_n] + [-l in I_n]) / 2 of the asymmetric index set I_n
+// (1 inside, 1/2 or 0 on its boundary planes; exact in T).
+template <typename T>
+__device__ __forceinline__ T mu_at(const FftPass<T> &p, int2 line, int em) {
+  const int hx = p.mu_n[0] / 2, hy = p.mu_n[1] / 2, hz = p.mu_n[2] / 2;
+  const int kx = line.x, ky = line.y - hy, kz = em - hz;
+  const bool in_i = kx <= hx - 1 && ky >= -hy && ky <= hy - 1 && kz >= -hz && kz <= hz - 1;
+  const bool in_mi = kx >= -hx + 1 && ky >= -hy + 1 && ky <= hy && kz >= -hz + 1 && kz <= hz;
+  const int ay = ky < 0 ? -ky : ky, az = kz < 0 ? -kz : kz;
+  const T f = p.mu[((int64_t)az * (hy + 1) + ay) * (hx + 1) + kx];
+  return (in_i && in_mi) ? f : ((in_i || in_mi) ? T(0.5) * f : T(0));
+}
+
+template <typename T, int N, bool STRIDED, bool MULINV>
+__global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STRIDED>::MINW)) void k_fft(FftPass<T> p) {
   using F = FftCfg<T, N, STRIDED>;
   using C = typename F::C;
   constexpr int E = F::E, TL = F::TL, G = F::G;
@@ -270,11 +290,12 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS)) void k_fft(FftPas
   const int64_t item = lb / gridDim.x;
   const int64_t L = (lb % gridDim.x) * G + line;
   const bool live = L < p.n_lines;
-  int64_t mbase = 0, ibase = 0, obase = 0;
+  int64_t ibase = 0, obase = 0;
+  int2 mline = make_int2(0, 0);   // (kx, ky index) of a z-pass line
   if (live) {
     const int64_t l1i = L % p.l1, l2i = L / p.l1;
-    mbase = l1i * p.in_s1 + l2i * p.in_s2;
-    ibase = mbase + item * p.in_bstride;
+    mline = make_int2((int)l1i, (int)l2i);
+    ibase = l1i * p.in_s1 + l2i * p.in_s2 + item * p.in_bstride;
     obase = l1i * p.out_s1 + l2i * p.out_s2 + item * p.out_bstride;
   }
   // gather: position pos holds element (pos - in_shift) mod N if that is
@@ -300,13 +321,13 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS)) void k_fft(FftPas
       }
     }
     mu[i] = T(0);
-    if (p.mul_inv && live) {
+    if (MULINV && live) {
       const int em = (pos - p.mu_shift) & (N - 1);
-      if (em < p.mu_cnt) mu[i] = p.mu[mbase + (int64_t)em * p.in_es];
+      if (em < p.mu_cnt) mu[i] = mu_at(p, mline, em);
     }
   }
   fft_dir<F>(v, p.sign, t, line, tw, lds);
-  if (p.mul_inv) {
+  if constexpr (MULINV) {
     // registers hold positions t + TL i again: multiply and transform back
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -340,7 +361,7 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS)) void k_fft(FftPas
 // with N/2 - l goes through LDS (forward) or is read from global memory
 // (inverse).
 template <typename T, int N>
-__global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS)) void k_fft_real(FftPass<T> p) {
+__global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 2, false>::MINW)) void k_fft_real(FftPass<T> p) {
   constexpr int NH = N / 2;
   using F = FftCfg<T, NH, false>;
   using C = typename F::C;
@@ -450,8 +471,14 @@ hipError_t fft_n(const FftPass<T> &p, int nb, hipStream_t s) {
   using F = FftCfg<T, N, STRIDED>;
   if (p.n_lines == 0) return hipSuccess;
   const int64_t blocks = (p.n_lines + F::G - 1) / F::G;
-  hipLaunchKernelGGL((k_fft<T, N, STRIDED>), dim3((unsigned)blocks, (unsigned)nb),
-                     dim3(F::THREADS), 0, s, p);
+  // the fused multiply-and-inverse form (the z pass) is a kernel of its own,
+  // so that the other passes do not hold its registers
+  if (p.mul_inv)
+    hipLaunchKernelGGL((k_fft<T, N, STRIDED, true>), dim3((unsigned)blocks, (unsigned)nb),
+                       dim3(F::THREADS), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_fft<T, N, STRIDED, false>), dim3((unsigned)blocks, (unsigned)nb),
+                       dim3(F::THREADS), 0, s, p);
   return hipGetLastError();
 }
 

@@ -119,6 +119,10 @@ struct FftPass {
   int32_t in_cnt, in_shift;
   int32_t out_cnt, out_shift;
   int32_t mu_cnt, mu_shift;
+  // fused multiplier: mu = h(l) F(kx, |ky|, |kz|), F folded over the signs of
+  // ky and kz ([n_z/2 + 1][n_y/2 + 1][n_x/2 + 1]); line (kx, ky index) of the z
+  // pass, element kz index = (pos - mu_shift) mod N
+  int32_t mu_n[3];       // n_x, n_y, n_z
   int32_t sign;          // -1 forward, +1 inverse
   int32_t in_real;       // input is real (T) instead of complex
   int32_t in_hermitian;  // also place conj(v_e) at N - e (e >= 1)
@@ -255,12 +259,12 @@ hipError_t launch_density_from_m(const int32_t *tri_v, const double *tri_n, cons
 hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t L,
                        const double *gl_x, const double *gl_w, int32_t order, int32_t panels,
                        hipStream_t s);
-// mu_l = h(l) c_l dec_x[|l_x|] dec_y[|l_y|] dec_z[|l_z|] / (4 pi), with dec_q the
-// per-axis deconvolution factors 1 / u^(l_q / N_q)^2 of the window (FP64 tables
-// of n_q/2 + 1 entries each).
+// F(kx, |ky|, |kz|) = c_l dec_x[kx] dec_y[|ky|] dec_z[|kz|] / (4 pi), with dec_q
+// the per-axis deconvolution factors 1 / u^(l_q / N_q)^2 of the window (FP64
+// tables of n_q/2 + 1 entries each); the z pass multiplies by mu_l = h(l) F.
 template <typename T>
 hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2,
-                     const double *omega, int32_t S, const int32_t n[3], const int32_t K[3],
-                     const double *dec0, const double *dec1, const double *dec2, hipStream_t s);
+                     const double *omega, int32_t S, const int32_t n[3], const double *dec0,
+                     const double *dec1, const double *dec2, hipStream_t s);
 
 }  // namespace slp

@@ -827,51 +827,41 @@ hipError_t launch_chat(double *C, const double *gamma_scaled, int32_t S, int32_t
   return hipGetLastError();
 }
 
-// mu over the stored half spectrum kx = 0..n_x/2, ky = -n_y/2..n_y/2,
-// kz = -n_z/2..n_z/2 (layout [K_z][K_y][K_x]):
-//   mu = h(l) c_l prod_q exp(2 b (pi l_q / N_q)^2) / (pi b) / (4 pi)
+// The multiplier without its Hermitian weight, folded over the signs of ky
+// and kz: F(kx, |ky|, |kz|) for kx = 0..n_x/2, |ky| = 0..n_y/2, |kz| = 0..n_z/2
+// (layout [n_z/2 + 1][n_y/2 + 1][n_x/2 + 1]), a quarter of the stored half
+// spectrum. The z pass multiplies by mu = h(l) F (see fft_mul_weight):
+//   F = c_l prod_q exp(2 b (pi l_q / N_q)^2) / (pi b) / (4 pi)
 // c_l = sum_t omega_t prod_q c_{t,q}(|l_q|) (Sec. 3.3 separable coefficients),
 // exp(2 b ...) / (pi b): the two deconvolutions by the window coefficients
 // (eq. deconv and the type-2 counterpart) for the unnormalised window
-// exp(-tau^2 / b); h(l) = ([l in I_n] + [-l in I_n]) / 2 is the real part of
-// the sum over the asymmetric index set.
+// exp(-tau^2 / b) (the Kaiser-Bessel window's own factors in its place).
 template <typename T>
 __global__ void k_mu(T *mu, const double *__restrict__ C0, const double *__restrict__ C1,
                      const double *__restrict__ C2, const double *__restrict__ omega, int32_t S,
-                     int3 n, int3 K, const double *__restrict__ dec0,
-                     const double *__restrict__ dec1, const double *__restrict__ dec2) {
+                     int3 n, const double *__restrict__ dec0, const double *__restrict__ dec1,
+                     const double *__restrict__ dec2) {
+  const int Lx = n.x / 2 + 1, Ly = n.y / 2 + 1, Lz = n.z / 2 + 1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = (int64_t)K.x * K.y * K.z;
+  const int64_t tot = (int64_t)Lx * Ly * Lz;
   if (i >= tot) return;
-  const int kx = (int)(i % K.x);
-  const int ky = (int)((i / K.x) % K.y) - n.y / 2;
-  const int kz = (int)(i / ((int64_t)K.x * K.y)) - n.z / 2;
-  const bool inI = (kx <= n.x / 2 - 1) && (ky >= -n.y / 2) && (ky <= n.y / 2 - 1) &&
-                   (kz >= -n.z / 2) && (kz <= n.z / 2 - 1);
-  const bool inmI = (kx >= -n.x / 2 + 1) && (ky >= -n.y / 2 + 1) && (ky <= n.y / 2) &&
-                    (kz >= -n.z / 2 + 1) && (kz <= n.z / 2);
-  const double h = 0.5 * ((inI ? 1.0 : 0.0) + (inmI ? 1.0 : 0.0));
-  double v = 0.0;
-  if (h > 0.0) {
-    const int ax = kx, ay = ky < 0 ? -ky : ky, az = kz < 0 ? -kz : kz;
-    const int Lx = n.x / 2 + 1, Ly = n.y / 2 + 1, Lz = n.z / 2 + 1;
-    double c = 0.0;
-    for (int t = 0; t < S; ++t)
-      c += omega[t] * C0[(int64_t)t * Lx + ax] * C1[(int64_t)t * Ly + ay] * C2[(int64_t)t * Lz + az];
-    const double pi = 3.141592653589793238462643383279502884;
-    v = h * c * dec0[ax] * dec1[ay] * dec2[az] / (4.0 * pi);
-  }
-  mu[i] = (T)v;
+  const int ax = (int)(i % Lx);
+  const int ay = (int)((i / Lx) % Ly);
+  const int az = (int)(i / ((int64_t)Lx * Ly));
+  double c = 0.0;
+  for (int t = 0; t < S; ++t)
+    c += omega[t] * C0[(int64_t)t * Lx + ax] * C1[(int64_t)t * Ly + ay] * C2[(int64_t)t * Lz + az];
+  const double pi = 3.141592653589793238462643383279502884;
+  mu[i] = (T)(c * dec0[ax] * dec1[ay] * dec2[az] / (4.0 * pi));
 }
 
 template <typename T>
 hipError_t launch_mu(T *mu, const double *C0, const double *C1, const double *C2,
-                     const double *omega, int32_t S, const int32_t n[3], const int32_t K[3],
-                     const double *dec0, const double *dec1, const double *dec2, hipStream_t s) {
-  const int64_t tot = (int64_t)K[0] * K[1] * K[2];
+                     const double *omega, int32_t S, const int32_t n[3], const double *dec0,
+                     const double *dec1, const double *dec2, hipStream_t s) {
+  const int64_t tot = (int64_t)(n[0] / 2 + 1) * (n[1] / 2 + 1) * (n[2] / 2 + 1);
   hipLaunchKernelGGL(k_mu<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, mu, C0, C1, C2,
-                     omega, S, make_int3(n[0], n[1], n[2]), make_int3(K[0], K[1], K[2]), dec0,
-                     dec1, dec2);
+                     omega, S, make_int3(n[0], n[1], n[2]), dec0, dec1, dec2);
   return hipGetLastError();
 }
 
@@ -1271,10 +1261,10 @@ template hipError_t launch_iw_apply<float>(const NearArgs<float> &, const IwOut<
 template hipError_t launch_iw_apply<double>(const NearArgs<double> &, const IwOut<double> &,
                                             const BatchPtrs &, int, bool, bool, hipStream_t);
 template hipError_t launch_mu<float>(float *, const double *, const double *, const double *,
-                                     const double *, int32_t, const int32_t *, const int32_t *,
-                                     const double *, const double *, const double *, hipStream_t);
+                                     const double *, int32_t, const int32_t[3], const double *,
+                                     const double *, const double *, hipStream_t);
 template hipError_t launch_mu<double>(double *, const double *, const double *, const double *,
-                                      const double *, int32_t, const int32_t *, const int32_t *,
-                                      const double *, const double *, const double *, hipStream_t);
+                                      const double *, int32_t, const int32_t[3], const double *,
+                                      const double *, const double *, hipStream_t);
 
 }  // namespace slp
