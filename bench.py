@@ -364,8 +364,10 @@ def grid_rule(nodes, tris):
 def multi_mesh(args, prec, window, m, steps, warmup):
     """Multi-mesh batch: 32 icospheres, levels uniform in {2..6} (seed 4100), each with
     its own seeded magnetisation (seeds 4101-4132) and grid by the rule above, evaluated
-    by one slp_eval_batched call per step (groups of different meshes overlap on the
-    library's lanes); beside it the same items one after the other on one stream."""
+    by one slp_eval_batched_mode call per step with fused launches (one launch per stage
+    for all meshes); beside it the same batch with the per-mesh launch sequences
+    overlapped on the library's four streams, and the items one after the other on one
+    stream."""
     import torch
 
     import paper_1305_3162_amd as slp
@@ -396,7 +398,10 @@ def multi_mesh(args, prec, window, m, steps, warmup):
     stream = torch.cuda.current_stream()
 
     def batched():
-        slp.eval_batched(handles, dens, phis, stream)
+        slp.eval_batched(handles, dens, phis, stream, mode=slp.BATCH_FUSED)
+
+    def lanes():
+        slp.eval_batched(handles, dens, phis, stream, mode=slp.BATCH_LANES)
 
     def one_by_one():
         for G, d, p in zip(geos, dens, phis):
@@ -404,7 +409,7 @@ def multi_mesh(args, prec, window, m, steps, warmup):
             G.eval(p, stream)
 
     out = {}
-    for name, fn in (("batched", batched), ("one_by_one", one_by_one)):
+    for name, fn in (("batched", batched), ("lanes", lanes), ("one_by_one", one_by_one)):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
@@ -421,6 +426,9 @@ def multi_mesh(args, prec, window, m, steps, warmup):
         "steps": steps, "warmup": warmup, "ms_per_step": round(out["batched"] * 1e3, 5),
         "dtype": "f64" if prec == slp.FP64 else "f32",
         "window": "kb" if window == slp.WINDOW_KB else "gauss", "m": m,
+        "launches": "fused: one launch per stage for all meshes (FFT passes per line length)",
+        "lanes_pts_per_s": round(pts / out["lanes"], 1),
+        "lanes_ms_per_step": round(out["lanes"] * 1e3, 5),
         "one_by_one_pts_per_s": round(pts / out["one_by_one"], 1),
         "one_by_one_ms_per_step": round(out["one_by_one"] * 1e3, 5),
         "config": {"workload": "32 icospheres, levels uniform in 2..6 (seed 4100), seeded "
@@ -432,7 +440,11 @@ def multi_mesh(args, prec, window, m, steps, warmup):
 
 
 def mix32(args):
+    import torch
+
     import paper_1305_3162_amd as slp
+    torch.cuda.init()          # the device is set up by torch before the library allocates
+    torch.cuda.synchronize()
     prec = slp.FP64 if args.precision == "fp64" else slp.FP32
     window, m = resolve_window(args, slp, prec)
     rec = multi_mesh(args, prec, window, m, args.steps, args.warmup)

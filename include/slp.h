@@ -191,10 +191,43 @@ int slp_eval_single_layer_static(slp_geom *g, double *phi, void *stream);
 /* Batched evaluation: item b uses geometry geoms[b], density dens[b] (device
  * float64 [3 * n_tris(geoms[b])]) and writes phi[b] (device float64
  * [n_targets(geoms[b])]). Repeating one geometry evaluates several densities on
- * one mesh. Items run in order on `stream`; equal to calling set_density +
- * eval for each item. geoms/dens/phi are host arrays of length batch >= 1. */
+ * one mesh. The work is ordered on `stream` (the call returns once it is
+ * enqueued); the result equals calling set_density + eval for each item, up to
+ * the rounding order of the gridding's block accumulation. geoms/dens/phi are
+ * host arrays of length batch >= 1. Same as slp_eval_batched_mode with
+ * SLP_BATCH_AUTO. */
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
                      int32_t batch, void *stream);
+
+/* How slp_eval_batched_mode runs a batch (the steps of Sec. 3 per item either
+ * way):
+ *  SLP_BATCH_LANES  consecutive items on one geometry share every launch (the
+ *                   density index is a launch dimension); the launch sequences
+ *                   of different geometries overlap on four library streams
+ *                   forked from and joined back into `stream`;
+ *  SLP_BATCH_FUSED  one launch per stage for up to 64 items on any geometries
+ *                   (gridding, block sum, each FFT pass once per line length,
+ *                   interpolation), the workgroups taken from work lists in
+ *                   device memory (the gridding's units longest first over all
+ *                   items); the tables are built on the first call for a batch
+ *                   composition (synchronous upload) and cached (8 per
+ *                   process; eviction synchronises the device). Needs one
+ *                   precision, cut-off m and window (kind and shape b) on every
+ *                   item and the point-source gridding (SLP_EINVAL
+ *                   otherwise); a near field is applied
+ *                   per geometry after the interpolation. Stage timing
+ *                   (slp_set_timing) and graph replay (slp_set_graph) do not
+ *                   apply; a geometry occurring k times grows its per-item
+ *                   buffers to k items;
+ *  SLP_BATCH_AUTO   FUSED when the batch holds more than one geometry and
+ *                   FUSED applies, else LANES.
+ * Errors: SLP_EINVAL for NULL arrays or items, batch < 1 or an unknown mode;
+ * SLP_ENOMEM when buffers or tables cannot be allocated. */
+#define SLP_BATCH_AUTO 0
+#define SLP_BATCH_LANES 1
+#define SLP_BATCH_FUSED 2
+int slp_eval_batched_mode(slp_geom *const *geoms, const double *const *dens, double *const *phi,
+                          int32_t batch, int32_t mode, void *stream);
 
 int slp_geom_get_info(const slp_geom *g, slp_geom_info *info);
 

@@ -91,6 +91,7 @@ def load_library():
         "slp_eval_single_layer": [_VP, _VP, _VP],
         "slp_eval_single_layer_static": [_VP, _VP, _VP],
         "slp_eval_batched": [_VP, _VP, _VP, ctypes.c_int32, _VP],
+        "slp_eval_batched_mode": [_VP, _VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP],
         "slp_geom_get_info": [_VP, ctypes.POINTER(GeomInfo)],
         "slp_set_timing": [_VP, ctypes.c_int32],
         "slp_set_graph": [_VP, ctypes.c_int32],
@@ -363,7 +364,12 @@ def eval_single_layer_static(geom, phi, stream=None):
         _VP(geom), _dev_f64(phi, info["n_targets"], "phi"), _stream_ptr(stream)))
 
 
-def eval_batched(geoms, dens, phis, stream=None):
+BATCH_AUTO, BATCH_LANES, BATCH_FUSED = 0, 1, 2
+
+
+def eval_batched(geoms, dens, phis, stream=None, mode=None):
+    """slp_eval_batched (mode None) or slp_eval_batched_mode (BATCH_AUTO,
+    BATCH_LANES or BATCH_FUSED)."""
     n = len(geoms)
     if not (len(dens) == len(phis) == n) or n < 1:
         raise ValueError("geoms, dens and phis must have the same length >= 1")
@@ -377,7 +383,10 @@ def eval_batched(geoms, dens, phis, stream=None):
             info = infos[g] = geom_get_info(g)
         D[i] = _dev_f64(dens[i], info["n_src"], f"dens[{i}]").value
         P[i] = _dev_f64(phis[i], info["n_targets"], f"phi[{i}]").value
-    _check(load_library().slp_eval_batched(G, D, P, n, _stream_ptr(stream)))
+    if mode is None:
+        _check(load_library().slp_eval_batched(G, D, P, n, _stream_ptr(stream)))
+    else:
+        _check(load_library().slp_eval_batched_mode(G, D, P, n, int(mode), _stream_ptr(stream)))
 
 
 def geom_get_info(geom):

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <utility>
 #include <cmath>
 #include <cstdarg>
@@ -111,7 +113,10 @@ void counting_sort(const std::vector<int32_t> &bin, int64_t nbins, std::vector<i
 
 void slp::set_error_message(const char *msg) { g_err = msg; }
 
+static std::atomic<uint64_t> g_geom_serial{1};
+
 struct slp_geom {
+  uint64_t serial = g_geom_serial++;   // never reused: identifies the context in cached plans
   int prec = SLP_FP64;
   int N[3]{}, n[3]{}, alpha = 2, m = 4;
   double b = 0.0;                // window shape
@@ -130,6 +135,8 @@ struct slp_geom {
   int64_t item_elems[5]{};       // per item: scratch, grid_a, S1 (complex), S2 (complex), grid_g
   const double *dens = nullptr;  // density of the next single evaluation (caller's device buffer)
   int32_t n_tgt_tiles = 0;       // tiles holding targets
+  std::vector<int32_t> unit_len; // host: sources of each gridding work unit (unit order)
+  std::vector<int32_t> tgt_len;  // host: targets of each active tile (active order)
   // device buffers
   void *src_frac = nullptr;
   double *src_w = nullptr;
@@ -492,6 +499,84 @@ slp::InterpArgs<T> interp_args(const slp_geom *G, const WorkBufs &W) {
 }
 
 template <typename T>
+slp::SpreadReduceArgs<T> reduce_args(const slp_geom *G, const WorkBufs &W) {
+  slp::SpreadReduceArgs<T> r{};
+  r.scratch = static_cast<const T *>(W.scratch);
+  r.tile_slots = G->tile_slots;
+  r.grid = static_cast<T *>(W.grid_a);
+  r.scratch_bstride = W.elems[0];
+  r.grid_bstride = W.elems[1];
+  for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
+  return r;
+}
+
+// The five FFT passes of an evaluation (Sec. 3, steps 2-4): x forward (real
+// region rows -> kx = 0..n_x/2), y forward (region y -> ky = -n_y/2..n_y/2),
+// z forward with the multiplication by mu on kz = -n_z/2..n_z/2 and the z
+// inverse back to the region, y inverse (ky -> region y), x inverse
+// (Hermitian half spectrum -> real region rows). Line lengths in G->N.
+template <typename T>
+void fft_passes(const slp_geom *G, const WorkBufs &W, slp::FftPass<T> (&ps)[5]) {
+  const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
+  const int64_t Px = G->P[0], Py = G->P[1];
+  const int64_t Kx = G->K[0], Ky = G->K[1], Kz = G->K[2];
+  const int ny = G->n[1], nz = G->n[2];
+  for (slp::FftPass<T> &p : ps) p = slp::FftPass<T>{};
+  {
+    slp::FftPass<T> &p = ps[0];
+    p.in = W.grid_a; p.out = W.S1; p.tw = G->tw[0];
+    p.n_lines = Ry * Rz; p.l1 = Ry;
+    p.in_s1 = Px; p.in_s2 = Py * Px; p.in_es = 1; p.in_cnt = (int)Rx; p.in_shift = G->lo[0];
+    p.out_s1 = Kx; p.out_s2 = Ry * Kx; p.out_es = 1; p.out_cnt = (int)Kx; p.out_shift = 0;
+    p.sign = -1; p.in_real = 1;
+    p.in_bstride = W.elems[1]; p.out_bstride = W.elems[2];
+  }
+  {
+    slp::FftPass<T> &p = ps[1];
+    p.in = W.S1; p.out = W.S2; p.tw = G->tw[1];
+    p.n_lines = Kx * Rz; p.l1 = Kx;
+    p.in_s1 = 1; p.in_s2 = Ry * Kx; p.in_es = Kx; p.in_cnt = (int)Ry; p.in_shift = G->lo[1];
+    p.out_s1 = 1; p.out_s2 = Ky * Kx; p.out_es = Kx; p.out_cnt = (int)Ky; p.out_shift = -ny / 2;
+    p.sign = -1;
+    p.in_bstride = W.elems[2]; p.out_bstride = W.elems[3];
+  }
+  {
+    slp::FftPass<T> &p = ps[2];
+    p.in = W.S2; p.out = W.S2; p.tw = G->tw[2];
+    p.mu = static_cast<const T *>(G->mu);
+    p.n_lines = Kx * Ky; p.l1 = Kx;
+    p.in_s1 = 1; p.in_s2 = Kx; p.in_es = Ky * Kx; p.in_cnt = (int)Rz; p.in_shift = G->lo[2];
+    p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
+    for (int q = 0; q < 3; ++q) p.mu_n[q] = G->n[q];
+    p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
+    p.sign = -1; p.mul_inv = 1;
+    p.in_bstride = W.elems[3]; p.out_bstride = W.elems[3];
+  }
+  {
+    slp::FftPass<T> &p = ps[3];
+    p.in = W.S2; p.out = W.S1; p.tw = G->tw[1];
+    p.n_lines = Kx * Rz; p.l1 = Kx;
+    p.in_s1 = 1; p.in_s2 = Ky * Kx; p.in_es = Kx; p.in_cnt = (int)Ky; p.in_shift = -ny / 2;
+    p.out_s1 = 1; p.out_s2 = Ry * Kx; p.out_es = Kx; p.out_cnt = (int)Ry; p.out_shift = G->lo[1];
+    p.sign = +1;
+    p.in_bstride = W.elems[3]; p.out_bstride = W.elems[2];
+  }
+  {
+    slp::FftPass<T> &p = ps[4];
+    p.in = W.S1; p.out = W.grid_g; p.tw = G->tw[0];
+    p.n_lines = Ry * Rz; p.l1 = Ry;
+    p.in_s1 = Kx; p.in_s2 = Ry * Kx; p.in_es = 1; p.in_cnt = (int)Kx; p.in_shift = 0;
+    p.in_hermitian = 1;
+    p.out_s1 = Rx; p.out_s2 = Ry * Rx; p.out_es = 1; p.out_cnt = (int)Rx; p.out_shift = G->lo[0];
+    p.out_real = 1; p.sign = +1;
+    p.in_bstride = W.elems[2]; p.out_bstride = W.elems[4];
+  }
+}
+
+// Axis of each of the five passes.
+constexpr int kPassAxis[5] = {0, 1, 2, 1, 0};
+
+template <typename T>
 slp::NearArgs<T> near_args(const slp_geom *G, const WorkBufs &W) {
   slp::NearArgs<T> a{};
   a.rowptr = G->nf_rowptr;
@@ -546,86 +631,18 @@ int run_eval(slp_geom *G, const WorkBufs &W, const slp::BatchPtrs &ptrs, int nb,
   } else {
     // spread (the charges q = w g are formed inside the gridding)
     const slp::SpreadBinsArgs<T> a = spread_args<T>(G, W);
-    slp::SpreadReduceArgs<T> r{};
-    r.scratch = static_cast<const T *>(W.scratch);
-    r.tile_slots = G->tile_slots;
-    r.grid = static_cast<T *>(W.grid_a);
-    r.scratch_bstride = W.elems[0];
-    r.grid_bstride = W.elems[1];
-    for (int i = 0; i < 3; ++i) r.tiles[i] = G->tiles[i];
+    const slp::SpreadReduceArgs<T> r = reduce_args<T>(G, W);
     HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_units, G->m, nb, st,
                                   tm ? G->evs()[1] : nullptr));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
-  const int64_t Rx = G->R[0], Ry = G->R[1], Rz = G->R[2];
-  const int64_t Px = G->P[0], Py = G->P[1];
-  const int64_t Kx = G->K[0], Ky = G->K[1], Kz = G->K[2];
-  const int nx = G->n[0], ny = G->n[1], nz = G->n[2];
-  // x forward: real region rows -> kx = 0..n_x/2
-  {
-    slp::FftPass<T> p{};
-    p.in = W.grid_a; p.out = W.S1; p.tw = G->tw[0];
-    p.n_lines = Ry * Rz; p.l1 = Ry;
-    p.in_s1 = Px; p.in_s2 = Py * Px; p.in_es = 1; p.in_cnt = (int)Rx; p.in_shift = G->lo[0];
-    p.out_s1 = Kx; p.out_s2 = Ry * Kx; p.out_es = 1; p.out_cnt = (int)Kx; p.out_shift = 0;
-    p.sign = -1; p.in_real = 1;
-    p.in_bstride = W.elems[1]; p.out_bstride = W.elems[2];
-    HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
+  slp::FftPass<T> ps[5];
+  fft_passes<T>(G, W, ps);
+  for (int k = 0; k < 5; ++k) {
+    HIP_TRY(slp::launch_fft<T>(ps[k], G->N[kPassAxis[k]], nb, st));
+    if (tm) HIP_TRY(hipEventRecord(G->evs()[3 + k], st));
   }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[3], st));
-  // y forward: region y -> ky = -n_y/2..n_y/2
-  {
-    slp::FftPass<T> p{};
-    p.in = W.S1; p.out = W.S2; p.tw = G->tw[1];
-    p.n_lines = Kx * Rz; p.l1 = Kx;
-    p.in_s1 = 1; p.in_s2 = Ry * Kx; p.in_es = Kx; p.in_cnt = (int)Ry; p.in_shift = G->lo[1];
-    p.out_s1 = 1; p.out_s2 = Ky * Kx; p.out_es = Kx; p.out_cnt = (int)Ky; p.out_shift = -ny / 2;
-    p.sign = -1;
-    p.in_bstride = W.elems[2]; p.out_bstride = W.elems[3];
-    HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
-  }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[4], st));
-  // z forward, multiply by mu on kz = -n_z/2..n_z/2, z inverse back to the region
-  {
-    slp::FftPass<T> p{};
-    p.in = W.S2; p.out = W.S2; p.tw = G->tw[2];
-    p.mu = static_cast<const T *>(G->mu);
-    p.n_lines = Kx * Ky; p.l1 = Kx;
-    p.in_s1 = 1; p.in_s2 = Kx; p.in_es = Ky * Kx; p.in_cnt = (int)Rz; p.in_shift = G->lo[2];
-    p.mu_cnt = (int)Kz; p.mu_shift = -nz / 2;
-    for (int q = 0; q < 3; ++q) p.mu_n[q] = G->n[q];
-    p.out_s1 = 1; p.out_s2 = Kx; p.out_es = Ky * Kx; p.out_cnt = (int)Rz; p.out_shift = G->lo[2];
-    p.sign = -1; p.mul_inv = 1;
-    p.in_bstride = W.elems[3]; p.out_bstride = W.elems[3];
-    HIP_TRY(slp::launch_fft<T>(p, G->N[2], nb, st));
-  }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[5], st));
-  // y inverse: ky -> region y
-  {
-    slp::FftPass<T> p{};
-    p.in = W.S2; p.out = W.S1; p.tw = G->tw[1];
-    p.n_lines = Kx * Rz; p.l1 = Kx;
-    p.in_s1 = 1; p.in_s2 = Ky * Kx; p.in_es = Kx; p.in_cnt = (int)Ky; p.in_shift = -ny / 2;
-    p.out_s1 = 1; p.out_s2 = Ry * Kx; p.out_es = Kx; p.out_cnt = (int)Ry; p.out_shift = G->lo[1];
-    p.sign = +1;
-    p.in_bstride = W.elems[3]; p.out_bstride = W.elems[2];
-    HIP_TRY(slp::launch_fft<T>(p, G->N[1], nb, st));
-  }
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[6], st));
-  // x inverse (Hermitian half spectrum -> real region rows)
-  {
-    slp::FftPass<T> p{};
-    p.in = W.S1; p.out = W.grid_g; p.tw = G->tw[0];
-    p.n_lines = Ry * Rz; p.l1 = Ry;
-    p.in_s1 = Kx; p.in_s2 = Ry * Kx; p.in_es = 1; p.in_cnt = (int)Kx; p.in_shift = 0;
-    p.in_hermitian = 1;
-    p.out_s1 = Rx; p.out_s2 = Ry * Rx; p.out_es = 1; p.out_cnt = (int)Rx; p.out_shift = G->lo[0];
-    p.out_real = 1; p.sign = +1;
-    p.in_bstride = W.elems[2]; p.out_bstride = W.elems[4];
-    HIP_TRY(slp::launch_fft<T>(p, G->N[0], nb, st));
-  }
-  (void)nx;
-  if (tm) HIP_TRY(hipEventRecord(G->evs()[7], st));
+
   {
     const slp::InterpArgs<T> a = interp_args<T>(G, W);
     HIP_TRY(slp::launch_interp<T>(a, ptrs, G->n_tgt_tiles, G->m, nb, st));
@@ -1190,6 +1207,8 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   }
   G->n_units = (int32_t)n_units;
   G->n_slots = (int32_t)segs.size();
+  G->unit_len.resize(n_units);
+  for (int64_t u = 0; u < n_units; ++u) G->unit_len[u] = (int32_t)seg_size[units[2 * u].x];
   std::vector<int32_t> tgt_active;
   for (int64_t t = 0; t < ntiles; ++t)
     if (tstart[t + 1] > tstart[t]) tgt_active.push_back((int32_t)t);
@@ -1197,6 +1216,9 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
     return tstart[a + 1] - tstart[a] > tstart[b + 1] - tstart[b];
   });
   G->n_tgt_tiles = (int32_t)tgt_active.size();
+  G->tgt_len.resize(tgt_active.size());
+  for (size_t k = 0; k < tgt_active.size(); ++k)
+    G->tgt_len[k] = tstart[tgt_active[k] + 1] - tstart[tgt_active[k]];
   // per tile the bounding box of its targets' cells (3 bits per bound): the
   // interpolation stages only the grid values their stencils reach
   std::vector<int32_t> tgt_box(ntiles, 0);
@@ -1486,6 +1508,253 @@ int run_group(slp_geom *G, const double *const *dens, double *const *phi, int nb
 
 }  // namespace
 
+// C++ linkage for the templates of the fused path (this part of the file is
+// inside the C-linkage block of the entry points).
+extern "C++" {
+namespace {
+
+// ----------------------------------------------------------- fused batches
+// Items on several geometries evaluated with one launch per stage for all of
+// them (gridding, block sum, each FFT pass once per line length and kernel,
+// interpolation) instead of one launch sequence per geometry: small meshes
+// that leave most of the chip idle on their own fill it together, and the
+// gridding's longest-first order runs over the units of every item. Item i of
+// a geometry that occurs k times in the batch uses that context's per-item
+// buffers of slot k (the context grows them as for a batch of its own). The
+// device tables of a batch composition (the per-item arguments with their
+// buffers offset to the slot, the FFT pass tables, the work lists) are built
+// once and cached; the density and potential pointers travel as kernel
+// arguments.
+struct FusedPlan {
+  int dev = -1, prec = 0, m = 0;
+  std::vector<uint64_t> key;            // per item: context serial, slot
+  std::vector<const void *> bufs;       // per item: the five work buffers it was built for
+  void *mem = nullptr;                  // device tables
+  size_t off_items = 0, off_bins = 0, off_red = 0, off_interp = 0;
+  int64_t n_bins = 0, n_red = 0, n_interp = 0;
+  struct Fft {
+    int variant, N;
+    size_t off_passes, off_work;
+    int64_t n;
+  };
+  std::vector<Fft> ffts;                // in pass order
+  uint64_t last_use = 0;
+};
+std::mutex g_fused_mu;
+std::vector<FusedPlan> g_fused;
+uint64_t g_fused_clock = 0;
+constexpr size_t kFusedPlans = 8;
+
+// The work buffers of item slot `slot` of a context.
+WorkBufs slot_work(const slp_geom *G, int slot) {
+  WorkBufs W = ctx_work(G);
+  const size_t e = G->esz();
+  const size_t per[5] = {e, e, 2 * e, 2 * e, e};
+  void **b[5] = {&W.scratch, &W.grid_a, &W.S1, &W.S2, &W.grid_g};
+  for (int k = 0; k < 5; ++k)
+    *b[k] = static_cast<char *>(*b[k]) + (size_t)slot * (size_t)W.elems[k] * per[k];
+  return W;
+}
+
+template <typename T>
+int build_fused(FusedPlan &P, slp_geom *const *geoms, const std::vector<int32_t> &slot) {
+  const int n = (int)slot.size();
+  std::vector<slp::MultiItem<T>> items(n);
+  std::vector<std::array<slp::FftPass<T>, 5>> passes(n);
+  for (int i = 0; i < n; ++i) {
+    const slp_geom *G = geoms[i];
+    const WorkBufs W = slot_work(G, slot[i]);
+    items[i].sp = spread_args<T>(G, W);
+    items[i].rd = reduce_args<T>(G, W);
+    items[i].ip = interp_args<T>(G, W);
+    slp::FftPass<T> ps[5];
+    fft_passes<T>(G, W, ps);
+    for (int k = 0; k < 5; ++k) passes[i][k] = ps[k];
+  }
+  // gridding units of every item, longest first (ties: item, then unit order)
+  struct U { int32_t len, i, u; };
+  std::vector<U> us;
+  for (int i = 0; i < n; ++i)
+    for (int32_t u = 0; u < geoms[i]->n_units; ++u) us.push_back({geoms[i]->unit_len[u], i, u});
+  std::stable_sort(us.begin(), us.end(), [](const U &a, const U &b) { return a.len > b.len; });
+  std::vector<int2> bins(us.size());
+  for (size_t k = 0; k < us.size(); ++k) bins[k] = make_int2(us[k].i, us[k].u);
+  std::vector<int2> red;
+  for (int i = 0; i < n; ++i) {
+    const int64_t t = (int64_t)geoms[i]->tiles[0] * geoms[i]->tiles[1] * geoms[i]->tiles[2];
+    for (int64_t k = 0; k < t; ++k) red.push_back(make_int2(i, (int)k));
+  }
+  us.clear();
+  for (int i = 0; i < n; ++i)
+    for (int32_t k = 0; k < geoms[i]->n_tgt_tiles; ++k) us.push_back({geoms[i]->tgt_len[k], i, k});
+  std::stable_sort(us.begin(), us.end(), [](const U &a, const U &b) { return a.len > b.len; });
+  std::vector<int2> interp(us.size());
+  for (size_t k = 0; k < us.size(); ++k) interp[k] = make_int2(us[k].i, us[k].u);
+  // FFT launches: per pass, the items grouped by line length and kernel
+  struct FftHost { int variant, N; std::vector<slp::FftPass<T>> ps; std::vector<int2> work; };
+  std::vector<FftHost> fh;
+  for (int k = 0; k < 5; ++k) {
+    const size_t first = fh.size();
+    for (int i = 0; i < n; ++i) {
+      const int N = geoms[i]->N[kPassAxis[k]];
+      int64_t blocks = 0;
+      const int v = slp::fft_variant<T>(passes[i][k], N, &blocks);
+      if (v < 0) return fail(SLP_EINVAL, "fused batch: FFT pass %d of item %d is not supported", k, i);
+      size_t g = first;
+      while (g < fh.size() && !(fh[g].variant == v && fh[g].N == N)) ++g;
+      if (g == fh.size()) fh.push_back({v, N, {}, {}});
+      const int j = (int)fh[g].ps.size();
+      fh[g].ps.push_back(passes[i][k]);
+      for (int64_t b = 0; b < blocks; ++b) fh[g].work.push_back(make_int2(j, (int)b));
+    }
+  }
+  // one device allocation for every table
+  size_t bytes = 0;
+  auto take = [&](size_t sz) {
+    const size_t at = bytes;
+    bytes += (sz + 255) / 256 * 256;
+    return at;
+  };
+  P.off_items = take(items.size() * sizeof(items[0]));
+  P.off_bins = take(bins.size() * sizeof(int2));
+  P.off_red = take(red.size() * sizeof(int2));
+  P.off_interp = take(interp.size() * sizeof(int2));
+  P.ffts.clear();
+  for (const FftHost &f : fh)
+    P.ffts.push_back({f.variant, f.N, take(f.ps.size() * sizeof(f.ps[0])),
+                      take(f.work.size() * sizeof(int2)), (int64_t)f.work.size()});
+  std::vector<char> host(bytes, 0);
+  auto put = [&](size_t off, const void *src, size_t sz) {
+    if (sz) std::memcpy(host.data() + off, src, sz);
+  };
+  put(P.off_items, items.data(), items.size() * sizeof(items[0]));
+  put(P.off_bins, bins.data(), bins.size() * sizeof(int2));
+  put(P.off_red, red.data(), red.size() * sizeof(int2));
+  put(P.off_interp, interp.data(), interp.size() * sizeof(int2));
+  for (size_t g = 0; g < fh.size(); ++g) {
+    put(P.ffts[g].off_passes, fh[g].ps.data(), fh[g].ps.size() * sizeof(fh[g].ps[0]));
+    put(P.ffts[g].off_work, fh[g].work.data(), fh[g].work.size() * sizeof(int2));
+  }
+  P.n_bins = (int64_t)bins.size();
+  P.n_red = (int64_t)red.size();
+  P.n_interp = (int64_t)interp.size();
+  if (hipMalloc(&P.mem, bytes ? bytes : 256) != hipSuccess)
+    return fail(SLP_ENOMEM, "fused batch: %zu bytes of device tables: allocation failed", bytes);
+  HIP_TRY(hipMemcpy(P.mem, host.data(), bytes, hipMemcpyHostToDevice));
+  return SLP_OK;
+}
+
+template <typename T>
+int launch_fused(const FusedPlan &P, const slp_geom *G0, const slp::BatchPtrs &ptrs, hipStream_t st) {
+  const char *b = static_cast<const char *>(P.mem);
+  const auto *items = reinterpret_cast<const slp::MultiItem<T> *>(b + P.off_items);
+  // the window of every item (the pointer fields are not read)
+  const slp::SpreadBinsArgs<T> win = spread_args<T>(G0, ctx_work(G0));
+  HIP_TRY(slp::launch_spread_multi<T>(items, reinterpret_cast<const int2 *>(b + P.off_bins), P.n_bins,
+                                      reinterpret_cast<const int2 *>(b + P.off_red), P.n_red, P.m,
+                                      ptrs, win, st));
+  for (const FusedPlan::Fft &f : P.ffts)
+    HIP_TRY(slp::launch_fft_multi<T>(f.variant, f.N,
+                                     reinterpret_cast<const slp::FftPass<T> *>(b + f.off_passes),
+                                     reinterpret_cast<const int2 *>(b + f.off_work), f.n, st));
+  HIP_TRY(slp::launch_interp_multi<T>(items, reinterpret_cast<const int2 *>(b + P.off_interp),
+                                      P.n_interp, P.m, ptrs, st));
+  return SLP_OK;
+}
+
+// Whether the items can share fused launches: one precision, cut-off and
+// window (kind and shape), the point-source gridding (no integrated-window
+// gridding).
+bool fusable(slp_geom *const *geoms, int32_t batch) {
+  for (int32_t b = 0; b < batch; ++b) {
+    const slp_geom *G = geoms[b], *G0 = geoms[0];
+    if (G->prec != G0->prec || G->m != G0->m || G->window != G0->window || G->b != G0->b ||
+        G->iw_order > 0)
+      return false;
+    if (G->nf_nnz > 0 && G->nf_rule != 0) return false;
+  }
+  return true;
+}
+
+// At most kMaxBatch items.
+int run_fused(slp_geom *const *geoms, const double *const *dens, double *const *phi, int n,
+              hipStream_t st) {
+  std::vector<int32_t> slot(n);
+  std::map<slp_geom *, int> count;
+  for (int i = 0; i < n; ++i) slot[i] = count[geoms[i]]++;
+  for (auto &gc : count) {
+    const int rc = ensure_capacity(gc.first, gc.second, st);
+    if (rc) return rc;
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::vector<uint64_t> key(2 * (size_t)n);
+  std::vector<const void *> bufs(5 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    key[2 * i] = geoms[i]->serial;
+    key[2 * i + 1] = (uint64_t)slot[i];
+    const slp_geom *G = geoms[i];
+    const void *bs[5] = {G->scratch, G->grid_a, G->S1, G->S2, G->grid_g};
+    for (int k = 0; k < 5; ++k) bufs[5 * i + k] = bs[k];
+  }
+  const int prec = geoms[0]->prec, m = geoms[0]->m;
+  std::lock_guard<std::mutex> lock(g_fused_mu);
+  FusedPlan *P = nullptr;
+  for (FusedPlan &q : g_fused)
+    if (q.dev == dev && q.prec == prec && q.m == m && q.key == key && q.bufs == bufs) P = &q;
+  if (!P) {
+    if (g_fused.size() >= kFusedPlans) {
+      // evict the least recently used plan; its tables may still be read by
+      // launches in flight
+      size_t lru = 0;
+      for (size_t k = 1; k < g_fused.size(); ++k)
+        if (g_fused[k].last_use < g_fused[lru].last_use) lru = k;
+      HIP_TRY(hipDeviceSynchronize());
+      if (g_fused[lru].mem) HIP_TRY(hipFree(g_fused[lru].mem));
+      g_fused.erase(g_fused.begin() + (std::ptrdiff_t)lru);
+    }
+    FusedPlan q;
+    q.dev = dev;
+    q.prec = prec;
+    q.m = m;
+    q.key = key;
+    q.bufs = bufs;
+    const int rc = prec == SLP_FP64 ? build_fused<double>(q, geoms, slot)
+                                    : build_fused<float>(q, geoms, slot);
+    if (rc) {
+      if (q.mem) (void)hipFree(q.mem);
+      return rc;
+    }
+    g_fused.push_back(q);
+    P = &g_fused.back();
+  }
+  P->last_use = ++g_fused_clock;
+  slp::BatchPtrs ptrs{};
+  for (int i = 0; i < n; ++i) {
+    ptrs.dens[i] = dens[i];
+    ptrs.phi[i] = phi[i];
+  }
+  int rc = prec == SLP_FP64 ? launch_fused<double>(*P, geoms[0], ptrs, st)
+                            : launch_fused<float>(*P, geoms[0], ptrs, st);
+  if (rc) return rc;
+  // near-field corrections, per geometry for its items in slot order
+  for (auto &gc : count) {
+    slp_geom *G = gc.first;
+    if (G->nf_nnz == 0) continue;
+    slp::BatchPtrs np{};
+    for (int i = 0; i < n; ++i)
+      if (geoms[i] == G) {
+        np.dens[slot[i]] = dens[i];
+        np.phi[slot[i]] = phi[i];
+      }
+    HIP_TRY(near_apply(G, ctx_work(G), np, gc.second, st));
+  }
+  return SLP_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
 int slp_eval_single_layer_static(slp_geom *G, double *phi, void *stream) {
   if (!G || !phi) return fail(SLP_EINVAL, "geometry and phi must be non-NULL");
   if (!G->dens) return fail(SLP_EINVAL, "no density set (slp_set_density)");
@@ -1537,10 +1806,31 @@ int slp_eval_single_layer_static(slp_geom *G, double *phi, void *stream) {
 
 int slp_eval_batched(slp_geom *const *geoms, const double *const *dens, double *const *phi,
                      int32_t batch, void *stream) {
+  return slp_eval_batched_mode(geoms, dens, phi, batch, SLP_BATCH_AUTO, stream);
+}
+
+int slp_eval_batched_mode(slp_geom *const *geoms, const double *const *dens, double *const *phi,
+                          int32_t batch, int32_t mode, void *stream) {
   if (batch < 1 || !geoms || !dens || !phi) return fail(SLP_EINVAL, "batched: batch >= 1 and non-NULL arrays");
   for (int32_t b = 0; b < batch; ++b)
     if (!geoms[b] || !dens[b] || !phi[b]) return fail(SLP_EINVAL, "batched: item %d has a NULL pointer", b);
+  if (mode != SLP_BATCH_AUTO && mode != SLP_BATCH_LANES && mode != SLP_BATCH_FUSED)
+    return fail(SLP_EINVAL, "batched: unknown mode %d", mode);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  bool fuse = mode == SLP_BATCH_FUSED;
+  if (fuse && !fusable(geoms, batch))
+    return fail(SLP_EINVAL, "batched: fused launches need one precision, cut-off and window and "
+                            "the point-source gridding on every item");
+  if (mode == SLP_BATCH_AUTO && fusable(geoms, batch))
+    for (int32_t b = 1; b < batch && !fuse; ++b) fuse = geoms[b] != geoms[0];
+  if (fuse) {
+    for (int32_t b = 0; b < batch; b += slp::kMaxBatch) {
+      const int n = std::min<int32_t>(slp::kMaxBatch, batch - b);
+      const int rc = run_fused(geoms + b, dens + b, phi + b, n, st);
+      if (rc) return rc;
+    }
+    return SLP_OK;
+  }
   // launch groups: consecutive items on one geometry share every launch
   struct Group { slp_geom *G; int32_t b, e; };
   std::vector<Group> groups;

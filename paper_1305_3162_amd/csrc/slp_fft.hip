@@ -275,8 +275,9 @@ __device__ __forceinline__ T mu_at(const FftPass<T> &p, int2 line, int em) {
   return (in_i && in_mi) ? f : ((in_i || in_mi) ? T(0.5) * f : T(0));
 }
 
+// Lines blk G .. blk G + G - 1 of pass p for batch item `item`.
 template <typename T, int N, bool STRIDED, bool MULINV>
-__global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STRIDED>::MINW)) void k_fft(FftPass<T> p) {
+__device__ __forceinline__ void fft_body(const FftPass<T> p, int64_t item, int64_t blk) {
   using F = FftCfg<T, N, STRIDED>;
   using C = typename F::C;
   constexpr int E = F::E, TL = F::TL, G = F::G;
@@ -285,10 +286,7 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STR
   const int tid = threadIdx.x;
   const int line = STRIDED ? tid % G : tid / TL;
   const int t = STRIDED ? tid / G : tid % TL;
-  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
-  const int64_t lb = xcd_block((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x, nblk);
-  const int64_t item = lb / gridDim.x;
-  const int64_t L = (lb % gridDim.x) * G + line;
+  const int64_t L = blk * G + line;
   const bool live = L < p.n_lines;
   int64_t ibase = 0, obase = 0;
   int2 mline = make_int2(0, 0);   // (kx, ky index) of a z-pass line
@@ -349,6 +347,22 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STR
   }
 }
 
+template <typename T, int N, bool STRIDED, bool MULINV>
+__global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STRIDED>::MINW)) void k_fft(FftPass<T> p) {
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+  const int64_t lb = xcd_block((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x, nblk);
+  fft_body<T, N, STRIDED, MULINV>(p, lb / gridDim.x, lb % gridDim.x);
+}
+
+// Several passes (one per geometry of a batch) in one launch: logical
+// workgroup i takes block work[i].y of pass work[i].x.
+template <typename T, int N, bool STRIDED, bool MULINV>
+__global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STRIDED>::MINW)) void k_fft_multi(
+    const FftPass<T> *__restrict__ passes, const int2 *__restrict__ work) {
+  const int2 w = work[xcd_block(blockIdx.x, gridDim.x)];
+  fft_body<T, N, STRIDED, MULINV>(passes[w.x], 0, w.y);
+}
+
 // Real lines of length N (contiguous lines only) through a complex transform
 // of length N / 2, which halves the butterflies, the registers and the LDS
 // per line. Forward (real in, half spectrum out): the line is packed as
@@ -361,7 +375,7 @@ __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STR
 // with N/2 - l goes through LDS (forward) or is read from global memory
 // (inverse).
 template <typename T, int N>
-__global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 2, false>::MINW)) void k_fft_real(FftPass<T> p) {
+__device__ __forceinline__ void fft_real_body(const FftPass<T> p, int64_t item, int64_t blk) {
   constexpr int NH = N / 2;
   using F = FftCfg<T, NH, false>;
   using C = typename F::C;
@@ -371,10 +385,7 @@ __global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 
   const C *tw = reinterpret_cast<const C *>(p.tw);
   const int tid = threadIdx.x;
   const int line = tid / TL, t = tid % TL;
-  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
-  const int64_t lb = xcd_block((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x, nblk);
-  const int64_t item = lb / gridDim.x;
-  const int64_t L = (lb % gridDim.x) * G + line;
+  const int64_t L = blk * G + line;
   const bool live = L < p.n_lines;
   int64_t ibase = 0, obase = 0;
   if (live) {
@@ -457,66 +468,146 @@ __global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 
 }
 
 template <typename T, int N>
-hipError_t fft_real_n(const FftPass<T> &p, int nb, hipStream_t s) {
-  using F = FftCfg<T, N / 2, false>;
-  if (p.n_lines == 0) return hipSuccess;
-  const int64_t blocks = (p.n_lines + F::G - 1) / F::G;
-  hipLaunchKernelGGL((k_fft_real<T, N>), dim3((unsigned)blocks, (unsigned)nb), dim3(F::THREADS), 0,
-                     s, p);
-  return hipGetLastError();
-}
-
-template <typename T, int N, bool STRIDED>
-hipError_t fft_n(const FftPass<T> &p, int nb, hipStream_t s) {
-  using F = FftCfg<T, N, STRIDED>;
-  if (p.n_lines == 0) return hipSuccess;
-  const int64_t blocks = (p.n_lines + F::G - 1) / F::G;
-  // the fused multiply-and-inverse form (the z pass) is a kernel of its own,
-  // so that the other passes do not hold its registers
-  if (p.mul_inv)
-    hipLaunchKernelGGL((k_fft<T, N, STRIDED, true>), dim3((unsigned)blocks, (unsigned)nb),
-                       dim3(F::THREADS), 0, s, p);
-  else
-    hipLaunchKernelGGL((k_fft<T, N, STRIDED, false>), dim3((unsigned)blocks, (unsigned)nb),
-                       dim3(F::THREADS), 0, s, p);
-  return hipGetLastError();
+__global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 2, false>::MINW)) void k_fft_real(FftPass<T> p) {
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+  const int64_t lb = xcd_block((int64_t)blockIdx.x + (int64_t)blockIdx.y * gridDim.x, nblk);
+  fft_real_body<T, N>(p, lb / gridDim.x, lb % gridDim.x);
 }
 
 template <typename T, int N>
-hipError_t fft_map(const FftPass<T> &p, int nb, hipStream_t s) {
+__global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 2, false>::MINW)) void k_fft_real_multi(
+    const FftPass<T> *__restrict__ passes, const int2 *__restrict__ work) {
+  const int2 w = work[xcd_block(blockIdx.x, gridDim.x)];
+  fft_real_body<T, N>(passes[w.x], 0, w.y);
+}
+
+// Which kernel takes pass p of length N: 0 / 1 contiguous lines without /
+// with the fused multiply-and-inverse, 2 / 3 the same on strided lines, 4 real
+// contiguous lines through the half-length transform; -1 if unsupported.
+template <typename T, int N>
+int fft_kind(const FftPass<T> &p) {
   // both sides of a pass use the same lane map
-  if ((p.in_es == 1) != (p.out_es == 1)) return hipErrorInvalidValue;
+  if ((p.in_es == 1) != (p.out_es == 1)) return -1;
+  if (p.in_hermitian && p.in_shift != 0) return -1;
   if constexpr (N >= 64) {
     // real contiguous lines: half-length complex transform
     const bool r2c = p.in_real && !p.in_hermitian && !p.out_real && p.out_shift == 0 &&
                      p.out_cnt <= N / 2 + 1;
     const bool c2r = p.in_hermitian && !p.in_real && p.out_real && p.in_shift == 0 &&
                      p.in_cnt <= N / 2 + 1;
-    if (p.in_es == 1 && !p.mul_inv && (r2c || c2r)) return fft_real_n<T, N>(p, nb, s);
+    if (p.in_es == 1 && !p.mul_inv && (r2c || c2r)) return 4;
   }
-  return p.in_es == 1 ? fft_n<T, N, false>(p, nb, s) : fft_n<T, N, true>(p, nb, s);
+  return (p.in_es == 1 ? 0 : 2) + (p.mul_inv ? 1 : 0);
+}
+
+// Lines per workgroup of kernel `kind`.
+template <typename T, int N>
+int fft_lines(int kind) {
+  if (kind == 4) return FftCfg<T, N / 2, false>::G;
+  return kind >= 2 ? FftCfg<T, N, true>::G : FftCfg<T, N, false>::G;
+}
+
+template <typename T, int N>
+int fft_threads(int kind) {
+  if (kind == 4) return FftCfg<T, N / 2, false>::THREADS;
+  return kind >= 2 ? FftCfg<T, N, true>::THREADS : FftCfg<T, N, false>::THREADS;
+}
+
+template <typename T, int N>
+hipError_t fft_map(const FftPass<T> &p, int nb, hipStream_t s) {
+  const int kind = fft_kind<T, N>(p);
+  if (kind < 0) return hipErrorInvalidValue;
+  if (p.n_lines == 0) return hipSuccess;
+  const int G = fft_lines<T, N>(kind);
+  const dim3 grid((unsigned)((p.n_lines + G - 1) / G), (unsigned)nb), block(fft_threads<T, N>(kind));
+  // the fused multiply-and-inverse form (the z pass) is a kernel of its own,
+  // so that the other passes do not hold its registers
+  switch (kind) {
+    case 0: hipLaunchKernelGGL((k_fft<T, N, false, false>), grid, block, 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_fft<T, N, false, true>), grid, block, 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_fft<T, N, true, false>), grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_fft<T, N, true, true>), grid, block, 0, s, p); break;
+    default:
+      if constexpr (N >= 64) hipLaunchKernelGGL((k_fft_real<T, N>), grid, block, 0, s, p);
+      else return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+hipError_t fft_map_multi(int kind, const FftPass<T> *passes, const int2 *work, int64_t n,
+                         hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)n), block(fft_threads<T, N>(kind));
+  switch (kind) {
+    case 0: hipLaunchKernelGGL((k_fft_multi<T, N, false, false>), grid, block, 0, s, passes, work); break;
+    case 1: hipLaunchKernelGGL((k_fft_multi<T, N, false, true>), grid, block, 0, s, passes, work); break;
+    case 2: hipLaunchKernelGGL((k_fft_multi<T, N, true, false>), grid, block, 0, s, passes, work); break;
+    case 3: hipLaunchKernelGGL((k_fft_multi<T, N, true, true>), grid, block, 0, s, passes, work); break;
+    case 4:
+      if constexpr (N >= 64) {
+        hipLaunchKernelGGL((k_fft_real_multi<T, N>), grid, block, 0, s, passes, work);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+int fft_variant_n(const FftPass<T> &p, int64_t *blocks) {
+  const int kind = fft_kind<T, N>(p);
+  if (kind >= 0) {
+    const int G = fft_lines<T, N>(kind);
+    *blocks = (p.n_lines + G - 1) / G;
+  }
+  return kind;
 }
 
 }  // namespace
 
+#define SLP_FFT_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048)
+
 template <typename T>
 hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s) {
-  if (p.in_hermitian && p.in_shift != 0) return hipErrorInvalidValue;
   switch (N) {
-    case 8: return fft_map<T, 8>(p, nb, s);
-    case 16: return fft_map<T, 16>(p, nb, s);
-    case 32: return fft_map<T, 32>(p, nb, s);
-    case 64: return fft_map<T, 64>(p, nb, s);
-    case 128: return fft_map<T, 128>(p, nb, s);
-    case 256: return fft_map<T, 256>(p, nb, s);
-    case 512: return fft_map<T, 512>(p, nb, s);
-    case 1024: return fft_map<T, 1024>(p, nb, s);
-    case 2048: return fft_map<T, 2048>(p, nb, s);
+#define SLP_CASE(SZ) case SZ: return fft_map<T, SZ>(p, nb, s);
+    SLP_FFT_SIZES(SLP_CASE)
+#undef SLP_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+int fft_variant(const FftPass<T> &p, int N, int64_t *blocks) {
+  *blocks = 0;
+  switch (N) {
+#define SLP_CASE(SZ) case SZ: return fft_variant_n<T, SZ>(p, blocks);
+    SLP_FFT_SIZES(SLP_CASE)
+#undef SLP_CASE
+    default: return -1;
+  }
+}
+
+template <typename T>
+hipError_t launch_fft_multi(int variant, int N, const FftPass<T> *passes, const int2 *work,
+                            int64_t n, hipStream_t s) {
+  switch (N) {
+#define SLP_CASE(SZ) case SZ: return fft_map_multi<T, SZ>(variant, passes, work, n, s);
+    SLP_FFT_SIZES(SLP_CASE)
+#undef SLP_CASE
     default: return hipErrorInvalidValue;
   }
 }
 
 template hipError_t launch_fft<float>(const FftPass<float> &, int, int, hipStream_t);
 template hipError_t launch_fft<double>(const FftPass<double> &, int, int, hipStream_t);
+template int fft_variant<float>(const FftPass<float> &, int, int64_t *);
+template int fft_variant<double>(const FftPass<double> &, int, int64_t *);
+template hipError_t launch_fft_multi<float>(int, int, const FftPass<float> *, const int2 *,
+                                            int64_t, hipStream_t);
+template hipError_t launch_fft_multi<double>(int, int, const FftPass<double> *, const int2 *,
+                                             int64_t, hipStream_t);
 
 }  // namespace slp

@@ -148,6 +148,40 @@ int64_t pad_cells(int m);
 template <typename T>
 hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s);
 
+// Fused launches over several geometries (a batch of different meshes): one
+// launch per stage for all items, an item being one density on one geometry.
+// The arguments of every item sit in a device table, the pointers of its work
+// buffers already offset to that item (the batch-stride fields are unused);
+// a work list in device memory maps workgroup i to {item, unit} (gridding:
+// work unit; block sum: region tile; interpolation: position in `active`).
+// The density and potential of item i are p.dens[i] and p.phi[i] (at most
+// kMaxBatch items per launch). The gridding's window (window, inv_b,
+// step_ratio, kb_c of `win`; its other fields unused) is one for all items.
+template <typename T>
+struct MultiItem {
+  SpreadBinsArgs<T> sp;
+  SpreadReduceArgs<T> rd;
+  InterpArgs<T> ip;
+};
+template <typename T>
+hipError_t launch_spread_multi(const MultiItem<T> *items, const int2 *bins_work, int64_t n_bins,
+                               const int2 *red_work, int64_t n_red, int m, const BatchPtrs &p,
+                               const SpreadBinsArgs<T> &win, hipStream_t s);
+template <typename T>
+hipError_t launch_interp_multi(const MultiItem<T> *items, const int2 *work, int64_t n, int m,
+                               const BatchPtrs &p, hipStream_t s);
+// The kernel that launch_fft uses for pass p of length N (an id >= 0 shared
+// by passes that can go into one fused launch), with the workgroups one item
+// of it takes in *blocks; -1 if launch_fft rejects the pass. Host-only.
+template <typename T>
+int fft_variant(const FftPass<T> &p, int N, int64_t *blocks);
+// One launch of that kernel over several passes: workgroup i (after the
+// same XCD-aware renumbering as launch_fft) takes block work[i].y of pass
+// work[i].x of the device table `passes`.
+template <typename T>
+hipError_t launch_fft_multi(int variant, int N, const FftPass<T> *passes, const int2 *work,
+                            int64_t n, hipStream_t s);
+
 // Host handles of the two kernels that take the per-item pointers (their
 // launches are updated in place when a captured evaluation is replayed).
 template <typename T>

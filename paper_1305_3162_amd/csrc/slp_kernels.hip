@@ -234,9 +234,13 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One workgroup per work unit `unit` of the geometry `a` describes, for the
+// density `dens` of batch item `item` (whose blocks lie item * scratch_bstride
+// further); the window (window, inv_b, step_ratio, kb_c) is read from `win`.
 template <typename T, int M>
-__global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a,
-                                                                               BatchPtrs ptrs) {
+__device__ __forceinline__ void spread_bins_body(const SpreadBinsArgs<T> &a,
+                                                 const SpreadBinsArgs<T> &win, const double *dens,
+                                                 int64_t unit, int item) {
   using S = SpreadShape<T, M>;
   constexpr int W = S::W, PD = S::PD, CH = S::CH;
   // The block is accumulated in FP64 in both precisions: LDS FP64 atomic adds
@@ -248,14 +252,13 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   __shared__ T src[4][CH];          // fractions x, y, z and charge of the staged chunk
   __shared__ int32_t rrec[CH];      // runs of the chunk
 
-  const double *dens = ptrs.dens[blockIdx.y];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   T *ww = wts + wave * S::NFAC * FST;
   const int64_t ns = a.ns;
   // {slot, first chunk, end chunk, reach of the tile's sources} and the first
   // chunk's record, side by side (one round trip)
-  const int4 ui = a.units[2 * blockIdx.x];
+  const int4 ui = a.units[2 * unit];
 
   // The global loads of a chunk are issued one chunk ahead: those of chunk
   // c + 1 fly while chunk c is gridded (and the header of chunk c + 2 with
@@ -274,7 +277,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
     }
     if (tid < h.w) rv = a.runs[h.z + tid];
   };
-  int4 ch = a.units[2 * blockIdx.x + 1];   // {first source, count, first run, run count}
+  int4 ch = a.units[2 * unit + 1];   // {first source, count, first run, run count}
   int4 hn = ui.y + 1 < ui.z ? a.chunks[ui.y + 1] : ch;
   load_chunk(ch);
   for (int i = tid; i < S::PL; i += S::THREADS) pad[i] = 0.0;
@@ -312,7 +315,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
           if (lane < 3 * n) {
             const int ax = lane / n, sl = lane - ax * n;
             const int si = off + c0 + sl;
-            stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), ww + sl * FST + ax * W);
+            stencil_factors<T, M>(win, src[ax][si], ax == 0 ? src[3][si] : T(1), ww + sl * FST + ax * W);
           }
           wave_sync();
           const int lk = lane >> 4, li = lane & 15;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
             const int off2 = (rec2 >> 9) & 1023, cnt2 = r2 < nrun ? (rec2 >> 19) & 2047 : 0;
             if (c0 + b < cnt2) {
               const int si = off2 + c0 + b;
-              stencil_factors<T, M>(a, src[ax][si], ax == 0 ? src[3][si] : T(1), dst);
+              stencil_factors<T, M>(win, src[ax][si], ax == 0 ? src[3][si] : T(1), dst);
             } else {
 #pragma unroll
               for (int j = 0; j < W; ++j) dst[j] = T(0);
@@ -420,7 +423,7 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
     }
   }
   __syncthreads();
-  T *dst = a.scratch + blockIdx.y * a.scratch_bstride + (int64_t)ui.x * S::P3;
+  T *dst = a.scratch + item * a.scratch_bstride + (int64_t)ui.x * S::P3;
   {
     // 32 lanes per pad row: x is fixed per thread, rows advance; only the box
     // of pad cells that the tile's sources reach is stored (and read back)
@@ -443,21 +446,36 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(Sp
   }
 }
 
+template <typename T, int M>
+__global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins(SpreadBinsArgs<T> a,
+                                                                               BatchPtrs ptrs) {
+  spread_bins_body<T, M>(a, a, ptrs.dens[blockIdx.y], blockIdx.x, blockIdx.y);
+}
+
+// Several geometries in one launch: workgroup i takes unit work[i].y of item
+// work[i].x (the list holds the units of every item, longest first over all).
+// The window, the same for every item, comes with the launch.
+template <typename T, int M>
+__global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins_multi(
+    const MultiItem<T> *__restrict__ items, const int2 *__restrict__ work, BatchPtrs ptrs,
+    SpreadBinsArgs<T> win) {
+  const int2 w = work[blockIdx.x];
+  spread_bins_body<T, M>(items[w.x].sp, win, ptrs.dens[w.x], w.y, 0);
+}
+
 // One workgroup of 512 threads per region tile, one thread per cell. For each
 // of the 27 neighbouring tiles (fixed order) and each of its segments, the
 // threads whose cell the block covers read the matching sub-block, which is
 // contiguous in the blocked layout.
 template <typename T, int M>
-__global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
+__device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs<T> a, int tile, int item) {
   using S = SpreadShape<T, M>;
-  constexpr int PD = S::PD;
-  const int tile = blockIdx.x;
   const int tx = tile % a.tiles[0];
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int64_t Px = (int64_t)a.tiles[0] * kTile, Py = (int64_t)a.tiles[1] * kTile;
-  const T *scr = a.scratch + blockIdx.y * a.scratch_bstride;
-  T *grid = a.grid + blockIdx.y * a.grid_bstride;
+  const T *scr = a.scratch + item * a.scratch_bstride;
+  T *grid = a.grid + item * a.grid_bstride;
   const int c = threadIdx.x;
   const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
   // the segment ranges and reach boxes of the 27 neighbouring tiles, read
@@ -493,6 +511,20 @@ __global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
     for (int k = 2; k < ts.y; ++k) v += p0[(int64_t)k * S::P3];
   }
   grid[((tz * kTile + cz) * Py + ty * kTile + cy) * Px + tx * kTile + cx] = v;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
+  spread_reduce_body<T, M>(a, blockIdx.x, blockIdx.y);
+}
+
+// Several geometries in one launch: workgroup i sums tile work[i].y of item
+// work[i].x.
+template <typename T, int M>
+__global__ __launch_bounds__(512) void k_spread_reduce_multi(const MultiItem<T> *__restrict__ items,
+                                                             const int2 *__restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  spread_reduce_body<T, M>(items[w.x].rd, w.y, 0);
 }
 
 template <typename T, int M>
@@ -532,6 +564,32 @@ hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &
   }
 }
 
+template <typename T, int M>
+static hipError_t spread_multi_m(const MultiItem<T> *items, const int2 *bins_work, int64_t n_bins,
+                                 const int2 *red_work, int64_t n_red, const BatchPtrs &p,
+                                 const SpreadBinsArgs<T> &win, hipStream_t s) {
+  if (n_bins > 0)
+    hipLaunchKernelGGL((k_spread_bins_multi<T, M>), dim3((unsigned)n_bins),
+                       dim3(SpreadShape<T, M>::THREADS), 0, s, items, bins_work, p, win);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_red == 0) return e;
+  hipLaunchKernelGGL((k_spread_reduce_multi<T, M>), dim3((unsigned)n_red), dim3(512), 0, s, items,
+                     red_work);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spread_multi(const MultiItem<T> *items, const int2 *bins_work, int64_t n_bins,
+                               const int2 *red_work, int64_t n_red, int m, const BatchPtrs &p,
+                               const SpreadBinsArgs<T> &win, hipStream_t s) {
+  switch (m) {
+#define SLP_CASE(MM) case MM: return spread_multi_m<T, MM>(items, bins_work, n_bins, red_work, n_red, p, win, s);
+    SLP_CASE(1) SLP_CASE(2) SLP_CASE(3) SLP_CASE(4) SLP_CASE(5) SLP_CASE(6) SLP_CASE(7) SLP_CASE(8)
+#undef SLP_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 // ----------------------------------------------------------------- interp ---
 // One workgroup per tile holding targets (largest tiles first). The grid values
 // of the bounding box of the tile's target stencils (within the tile plus its
@@ -560,9 +618,11 @@ struct InterpShape {
   static constexpr int NKB = W * (kKbDeg64 + 1);                  // KB coefficient slots
 };
 
+// One workgroup for the active tile at position `slot` of a.active, batch
+// item `bitem` (grid bitem * g_bstride further), potentials into `phi`.
 template <typename T, int M>
-__global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpArgs<T> a,
-                                                                          BatchPtrs ptrs) {
+__device__ __forceinline__ void interp_body(const InterpArgs<T> a, double *phi, int64_t slot,
+                                            int bitem) {
   using S = InterpShape<T, M>;
   constexpr int W = S::W, PD = S::PD, TG = S::TG, D = kb_degree<T>();
   __shared__ T gt[S::P3];
@@ -573,14 +633,13 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
   __shared__ T kbc[S::NKB];
 
   const int tid = threadIdx.x;
-  const int tile = a.active[blockIdx.x];
+  const int tile = a.active[slot];
   const int tx = tile % a.tiles[0];
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int ox = tx * kTile - M + 1, oy = ty * kTile - M + 1, oz = tz * kTile - M + 1;
   const int64_t Rx = a.R[0], Ry = a.R[1];
-  const T *gsrc = a.g + blockIdx.y * a.g_bstride;
-  double *phi = ptrs.phi[blockIdx.y];
+  const T *gsrc = a.g + bitem * a.g_bstride;
   const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t nt = a.nt;
@@ -738,6 +797,21 @@ __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpA
 }
 
 template <typename T, int M>
+__global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp(InterpArgs<T> a,
+                                                                          BatchPtrs ptrs) {
+  interp_body<T, M>(a, ptrs.phi[blockIdx.y], blockIdx.x, blockIdx.y);
+}
+
+// Several geometries in one launch: workgroup i takes active tile slot
+// work[i].y of item work[i].x (largest tiles first over all items).
+template <typename T, int M>
+__global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp_multi(
+    const MultiItem<T> *__restrict__ items, const int2 *__restrict__ work, BatchPtrs ptrs) {
+  const int2 w = work[blockIdx.x];
+  interp_body<T, M>(items[w.x].ip, ptrs.phi[w.x], w.y, 0);
+}
+
+template <typename T, int M>
 static hipError_t interp_m(const InterpArgs<T> &a, const BatchPtrs &p, int n_active, int nb,
                            hipStream_t s) {
   if (n_active == 0) return hipSuccess;
@@ -758,6 +832,26 @@ hipError_t launch_interp(const InterpArgs<T> &a, const BatchPtrs &p, int n_activ
     case 6: return interp_m<T, 6>(a, p, n_active, nb, s);
     case 7: return interp_m<T, 7>(a, p, n_active, nb, s);
     case 8: return interp_m<T, 8>(a, p, n_active, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int M>
+static hipError_t interp_multi_m(const MultiItem<T> *items, const int2 *work, int64_t n,
+                                 const BatchPtrs &p, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_interp_multi<T, M>), dim3((unsigned)n), dim3(InterpShape<T, M>::THREADS), 0,
+                     s, items, work, p);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp_multi(const MultiItem<T> *items, const int2 *work, int64_t n, int m,
+                               const BatchPtrs &p, hipStream_t s) {
+  switch (m) {
+#define SLP_CASE(MM) case MM: return interp_multi_m<T, MM>(items, work, n, p, s);
+    SLP_CASE(1) SLP_CASE(2) SLP_CASE(3) SLP_CASE(4) SLP_CASE(5) SLP_CASE(6) SLP_CASE(7) SLP_CASE(8)
+#undef SLP_CASE
     default: return hipErrorInvalidValue;
   }
 }
@@ -1236,6 +1330,16 @@ template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
 template hipError_t launch_spread<double>(const SpreadBinsArgs<double> &,
                                           const SpreadReduceArgs<double> &, const BatchPtrs &,
                                           int, int, int, hipStream_t, hipEvent_t);
+template hipError_t launch_spread_multi<float>(const MultiItem<float> *, const int2 *, int64_t,
+                                               const int2 *, int64_t, int, const BatchPtrs &,
+                                               const SpreadBinsArgs<float> &, hipStream_t);
+template hipError_t launch_spread_multi<double>(const MultiItem<double> *, const int2 *, int64_t,
+                                                const int2 *, int64_t, int, const BatchPtrs &,
+                                                const SpreadBinsArgs<double> &, hipStream_t);
+template hipError_t launch_interp_multi<float>(const MultiItem<float> *, const int2 *, int64_t, int,
+                                               const BatchPtrs &, hipStream_t);
+template hipError_t launch_interp_multi<double>(const MultiItem<double> *, const int2 *, int64_t,
+                                                int, const BatchPtrs &, hipStream_t);
 template hipError_t launch_interp<float>(const InterpArgs<float> &, const BatchPtrs &, int, int,
                                          int, hipStream_t);
 template hipError_t launch_interp<double>(const InterpArgs<double> &, const BatchPtrs &, int, int,
