@@ -149,9 +149,7 @@ struct slp_geom {
   int32_t *tgt_cell = nullptr;
   void *tgt_frac = nullptr;
   int32_t *tgt_perm = nullptr;
-  int32_t *tgt_tile_start = nullptr;
-  int32_t *tgt_active = nullptr;
-  int32_t *tgt_box = nullptr;    // per tile: bounding box of its targets' cells
+  int4 *tgt_rec = nullptr;       // per active tile: {tile, first target, end target, cell box}
   void *kb_tab = nullptr;        // Kaiser-Bessel window polynomials in the working precision
   void *grid_a = nullptr;
   void *S1 = nullptr;
@@ -482,9 +480,7 @@ slp::InterpArgs<T> interp_args(const slp_geom *G, const WorkBufs &W) {
   a.cell = G->tgt_cell;
   a.frac = static_cast<const T *>(G->tgt_frac);
   a.perm = G->tgt_perm;
-  a.tile_start = G->tgt_tile_start;
-  a.active = G->tgt_active;
-  a.tile_box = G->tgt_box;
+  a.rec = G->tgt_rec;
   a.kb_tab = static_cast<const T *>(G->kb_tab);
   a.g = static_cast<const T *>(W.grid_g);
   a.g_bstride = W.elems[4];
@@ -1238,6 +1234,12 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
         tgt_box[t] = blo[3 * t] | blo[3 * t + 1] << 3 | blo[3 * t + 2] << 6 | bhi[3 * t] << 9 |
                      bhi[3 * t + 1] << 12 | bhi[3 * t + 2] << 15;
   }
+  // one record per active tile (a single load at the start of its workgroup)
+  std::vector<int4> tgt_rec(tgt_active.size());
+  for (size_t k = 0; k < tgt_active.size(); ++k) {
+    const int32_t t = tgt_active[k];
+    tgt_rec[k] = int4{t, tstart[t], tstart[t + 1], tgt_box[t]};
+  }
 
   // device allocations
   const size_t e = G->esz();
@@ -1264,9 +1266,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       {reinterpret_cast<void **>(&G->runs), runs.size() * sizeof(int32_t)},
       {reinterpret_cast<void **>(&G->tile_slots), (size_t)ntiles * sizeof(int4)},
       {&G->scratch, (size_t)G->n_slots * (size_t)slp::pad_cells(G->m) * e},
-      {reinterpret_cast<void **>(&G->tgt_tile_start), (size_t)(ntiles + 1) * 4},
-      {reinterpret_cast<void **>(&G->tgt_active), tgt_active.size() * 4},
-      {reinterpret_cast<void **>(&G->tgt_box), (size_t)ntiles * 4},
+      {reinterpret_cast<void **>(&G->tgt_rec), tgt_rec.size() * sizeof(int4)},
       {&G->kb_tab, (size_t)slp::kKbCoef * e},
       {reinterpret_cast<void **>(&G->tgt_cell), (size_t)(3 * n_tgt) * 4},
       {&G->tgt_frac, (size_t)(3 * n_tgt) * e},
@@ -1318,9 +1318,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   HIP_TRY(hipMemcpyAsync(G->chunks, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->runs, runs.data(), runs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->tile_slots, tile_slots.data(), (size_t)ntiles * sizeof(int4), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->tgt_tile_start, tstart.data(), (ntiles + 1) * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->tgt_active, tgt_active.data(), tgt_active.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(G->tgt_box, tgt_box.data(), (size_t)ntiles * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->tgt_rec, tgt_rec.data(), tgt_rec.size() * sizeof(int4), hipMemcpyHostToDevice, st));
   std::vector<float> kbt32(slp::kKbCoef);
   for (int i = 0; i < slp::kKbCoef; ++i) kbt32[i] = (float)G->kb_coef[i];
   if (G->prec == SLP_FP64)

@@ -89,8 +89,9 @@ struct InterpArgs {
   const int32_t *cell;   // [3][nt] local cell, sorted by tile
   const T *frac;         // [3][nt]
   const int32_t *perm;   // [nt] sorted -> caller index
-  const int32_t *tile_start;  // [tiles + 1]
-  const int32_t *active;      // [n_active] tiles holding targets
+  const int4 *rec;       // [n_active] tiles holding targets, most targets first: {tile, first
+                         // target, end target, cell box of its targets: lo x|y<<3|z<<6,
+                         // hi <<9|<<12|<<15}
   const T *g;            // [R_z][R_y][R_x] grid after the inverse FFT
   int64_t g_bstride;
   int32_t R[3];
@@ -98,7 +99,6 @@ struct InterpArgs {
   int64_t nt;
   T inv_b;
   int32_t window;
-  const int32_t *tile_box;   // [tiles] cells of the tile's targets: lo x|y<<3|z<<6, hi <<9|<<12|<<15
   const T *kb_tab;           // [2m (deg + 1)] Kaiser-Bessel window polynomials (see kKbDeg64)
 };
 
@@ -153,7 +153,7 @@ hipError_t launch_fft(const FftPass<T> &p, int N, int nb, hipStream_t s);
 // The arguments of every item sit in a device table, the pointers of its work
 // buffers already offset to that item (the batch-stride fields are unused);
 // a work list in device memory maps workgroup i to {item, unit} (gridding:
-// work unit; block sum: region tile; interpolation: position in `active`).
+// work unit; block sum: region tile; interpolation: position in `rec`).
 // The density and potential of item i are p.dens[i] and p.phi[i] (at most
 // kMaxBatch items per launch). The gridding's window (window, inv_b,
 // step_ratio, kb_c of `win`; its other fields unused) is one for all items.

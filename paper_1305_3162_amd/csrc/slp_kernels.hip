@@ -21,36 +21,6 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
-// Value of v in lane j (j the same on every lane), as a wave-uniform value.
-__device__ __forceinline__ float read_lane(float v, int j) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-}
-__device__ __forceinline__ double read_lane(double v, int j) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
-  return __hiloint2double(hi, lo);
-}
-
-// v from the lane N places further round its row of 16 lanes (DPP row_ror).
-template <int N>
-__device__ __forceinline__ double row_ror(double v) {
-  constexpr int ctrl = 0x120 + N;
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum of v over the 64 lanes of the wave, in every lane: four rotations within
-// each row of 16 lanes (register moves, no LDS traffic), then the four row
-// sums.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += row_ror<8>(v);
-  v += row_ror<4>(v);
-  v += row_ror<2>(v);
-  v += row_ror<1>(v);
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-
 // Kaiser-Bessel window of eq. KBfct in grid units, scaled to 1 at tau = 0:
 // sinh(b s) / s * inv_norm with s = sqrt(m^2 - tau^2) (|tau| <= m on every
 // stencil point; the limit b at s = 0).
@@ -152,7 +122,6 @@ struct SpreadShape {
   static constexpr int THREADS = WAVES * 64;
   static constexpr int SBW = 12;                       // sources per factor batch (matrix form)
   static constexpr int CH = kSpreadChunk;              // sources staged per block chunk
-  static constexpr int PER = (4 * CH + THREADS - 1) / THREADS;
   // FP64 with 2m = 16: a run's update goes to the matrix cores (see
   // k_spread_bins); the factors of a source then sit 16-byte aligned
   static constexpr bool MX = sizeof(T) == 8 && W == 16;
@@ -262,18 +231,23 @@ __device__ __forceinline__ void spread_bins_body(const SpreadBinsArgs<T> &a,
 
   // The global loads of a chunk are issued one chunk ahead: those of chunk
   // c + 1 fly while chunk c is gridded (and the header of chunk c + 2 with
-  // them), so only the first chunk's loads are waited for in full.
-  T v[S::PER];
+  // them), so only the first chunk's loads are waited for in full. Thread t
+  // loads source t of the chunk (its three fractions, weight and density);
+  // the charge q = w g is formed when the values are stored to LDS, so that
+  // no arithmetic waits on the loads in flight.
+  static_assert(S::CH <= S::THREADS, "one source per thread and chunk");
+  T v[3];
+  double wq = 0.0, dv = 0.0;
   int32_t rv = 0;
-  auto load_chunk = [&](const int4 &h) {
-#pragma unroll
-    for (int k = 0; k < S::PER; ++k) {
-      const int i = tid + k * S::THREADS;
-      if (i < 4 * h.y) {
-        const int comp = i / h.y, sl = i - comp * h.y;
-        const int64_t si = (int64_t)h.x + sl;
-        v[k] = comp < 3 ? a.frac[comp * ns + si] : (T)(a.w[si] * dens[a.perm[si]]);
-      }
+  auto load_chunk = [&](const int4 h) {
+    if (tid < h.y) {
+      const int64_t si = (int64_t)h.x + tid;
+      const int32_t pm = a.perm[si];
+      v[0] = a.frac[si];
+      v[1] = a.frac[ns + si];
+      v[2] = a.frac[2 * ns + si];
+      wq = a.w[si];
+      dv = dens[pm];
     }
     if (tid < h.w) rv = a.runs[h.z + tid];
   };
@@ -283,13 +257,11 @@ __device__ __forceinline__ void spread_bins_body(const SpreadBinsArgs<T> &a,
   for (int i = tid; i < S::PL; i += S::THREADS) pad[i] = 0.0;
   for (int c = ui.y; c < ui.z; ++c) {
     __syncthreads();                   // the previous chunk is done with src / rrec
-#pragma unroll
-    for (int k = 0; k < S::PER; ++k) {
-      const int i = tid + k * S::THREADS;
-      if (i < 4 * ch.y) {
-        const int comp = i / ch.y, sl = i - comp * ch.y;
-        src[comp][sl] = v[k];
-      }
+    if (tid < ch.y) {
+      src[0][tid] = v[0];
+      src[1][tid] = v[1];
+      src[2][tid] = v[2];
+      src[3][tid] = (T)(wq * dv);
     }
     if (tid < ch.w) rrec[tid] = rv;
     const int nrun = ch.w;
@@ -297,7 +269,13 @@ __device__ __forceinline__ void spread_bins_body(const SpreadBinsArgs<T> &a,
     if (c + 1 < ui.z) {
       ch = hn;
       load_chunk(ch);
-      if (c + 2 < ui.z) hn = a.chunks[c + 2];
+      if (c + 2 < ui.z) {
+        // a scalar load: the header is the same for the whole workgroup, and
+        // the wave need not wait for the vector loads above to take it over
+        const __attribute__((address_space(4))) int32_t *hp =
+            (const __attribute__((address_space(4))) int32_t *)(a.chunks + c + 2);
+        hn = make_int4(hp[0], hp[1], hp[2], hp[3]);
+      }
     }
 
     if constexpr (S::MX) {
@@ -594,61 +572,95 @@ hipError_t launch_spread_multi(const MultiItem<T> *items, const int2 *bins_work,
 // One workgroup per tile holding targets (largest tiles first). The grid values
 // of the bounding box of the tile's target stencils (within the tile plus its
 // halo) are staged in LDS; then every wave works through its own contiguous
-// share of the tile's targets, TG at a time, with no further workgroup
-// barrier: the target data of the next group is loaded one group ahead, the
-// 1-D window factors of a group are computed one mirrored pair of stencil
-// points per lane into the wave's LDS slice (Gaussian: an exponential per
-// point; Kaiser-Bessel: one pass over the fitted polynomial's coefficients,
-// staged in LDS), and the lanes cover the (dy, dz) rows of a target's stencil, sum
-// the 2m values of each row in T (x factors moved to scalar registers by
-// readlane) and accumulate row * wy * wz in FP64. Targets are sorted by cell,
-// so two consecutive targets of one cell share each row read. Each target's
-// sum is reduced across the wave with register moves (DPP). Workgroups
+// share of the tile's targets, TPW = 64 / 2m at a time, with no further
+// workgroup barrier. A target takes 2m lanes, lane dz summing the stencil
+// plane cz + dz: sum over dy of w_y[dy] sum over dx of w_x[dx] g (the 2m values
+// of a row in T, the plane in FP64), times w_z[dz]; the 2m plane sums of a
+// target are added in a fixed order by one lane, so each target costs its
+// (2m)^3 multiply-adds plus O(2m) work and no cross-lane reduction. The target
+// data of the next group is loaded one group ahead; the 1-D window factors of
+// a group are computed one mirrored pair of stencil points per lane into the
+// wave's LDS slice (Gaussian: an exponential per point; Kaiser-Bessel: one
+// pass over the fitted polynomial's coefficients, read as scalars). Workgroups
 // are sized so that several share a CU (the staged block sets the LDS).
 template <typename T, int M>
 struct InterpShape {
   static constexpr int W = 2 * M;
   static constexpr int PD = kTile + W - 1;
   static constexpr int P3 = PD * PD * PD;
-  static constexpr int TG = 4;                                     // targets per wave group
-  static constexpr int FIT = (160 * 1024) / (P3 * (int)sizeof(T) + 6 * 1024);
-  static constexpr int WAVES = FIT >= 4 ? 4 : (FIT >= 2 ? 8 : 16);
+  static constexpr int TPW = 64 / W;                               // targets per wave pass
+  // LDS of one wave besides the staged block: factors, fractions, cells,
+  // caller indices, plane sums
+  static constexpr int WAVE_LDS = TPW * (3 * W + 3) * (int)sizeof(T) + TPW * 4 * 4 + 64 * 8;
+  static constexpr int fit(int waves) {
+    return (160 * 1024) / (P3 * (int)sizeof(T) + waves * WAVE_LDS);
+  }
+  static constexpr int WAVES = fit(4) >= 4 ? 4 : (fit(8) >= 2 ? 8 : 16);
   static constexpr int THREADS = WAVES * 64;
   static constexpr int PERG = (P3 + THREADS - 1) / THREADS;       // staged cells per thread
-  static constexpr int NKB = W * (kKbDeg64 + 1);                  // KB coefficient slots
+  static constexpr int NLD = (7 * TPW + 63) / 64;                 // target fields per lane
 };
 
-// One workgroup for the active tile at position `slot` of a.active, batch
-// item `bitem` (grid bitem * g_bstride further), potentials into `phi`.
+// One workgroup for the active tile at position `slot` of a.rec, batch item
+// `bitem` (grid bitem * g_bstride further), potentials into `phi`.
 template <typename T, int M>
 __device__ __forceinline__ void interp_body(const InterpArgs<T> a, double *phi, int64_t slot,
                                             int bitem) {
   using S = InterpShape<T, M>;
-  constexpr int W = S::W, PD = S::PD, TG = S::TG, D = kb_degree<T>();
+  constexpr int W = S::W, PD = S::PD, TPW = S::TPW, D = kb_degree<T>();
   __shared__ T gt[S::P3];
-  __shared__ T wf[S::WAVES][TG][3][W];     // window factors of each wave's group
-  __shared__ T tfr[S::WAVES][TG][3];       // fractions of each wave's group
-  __shared__ int32_t tcl[S::WAVES][TG][3]; // cells (in the tile) of each wave's group
-  __shared__ int32_t tpm[S::WAVES][TG];    // caller indices of each wave's group
-  __shared__ T kbc[S::NKB];
+  __shared__ T wf[S::WAVES][TPW][3][W];     // window factors of each wave's group
+  __shared__ T tfr[S::WAVES][TPW][3];       // fractions of each wave's group
+  __shared__ int32_t tcl[S::WAVES][TPW][3]; // cells (in the tile) of each wave's group
+  __shared__ int32_t tpm[S::WAVES][TPW];    // caller indices of each wave's group
+  __shared__ double psum[S::WAVES][64];     // plane sums
 
   const int tid = threadIdx.x;
-  const int tile = a.active[slot];
+  const int4 rec = a.rec[slot];
+  const int tile = rec.x;
   const int tx = tile % a.tiles[0];
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int ox = tx * kTile - M + 1, oy = ty * kTile - M + 1, oz = tz * kTile - M + 1;
   const int64_t Rx = a.R[0], Ry = a.R[1];
   const T *gsrc = a.g + bitem * a.g_bstride;
-  const int t0 = a.tile_start[tile], t1 = a.tile_start[tile + 1];
+  const int t0 = rec.y, t1 = rec.z;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int64_t nt = a.nt;
   // stencil box of the tile's targets in pad coordinates: cells lo..hi (in
   // the tile) per axis, stencils reaching W - 1 further
-  const int32_t box = a.tile_box[tile];
+  const int32_t box = rec.w;
   const int bx0 = box & 7, by0 = (box >> 3) & 7, bz0 = (box >> 6) & 7;
   const int bx1 = ((box >> 9) & 7) + W - 1, by1 = ((box >> 12) & 7) + W - 1,
             bz1 = ((box >> 15) & 7) + W - 1;
+  // this wave's contiguous share of the tile's targets, in groups of TPW
+  const int ntile = t1 - t0;
+  const int per = ((ntile + S::WAVES - 1) / S::WAVES + TPW - 1) / TPW * TPW;
+  const int ws = t0 + wave * per, we = min(t1, ws + per);
+  // target data of a group: field f = lane + 64 k (k < NLD) holds item f % TPW,
+  // kind f / TPW (0..2 cell, 3..5 fraction, 6 caller index), loaded one group
+  // ahead. Every lane loads unconditionally (items past the group's end read
+  // its last target, an integer and a fraction per field, the kind choosing
+  // only the addresses): a load under a branch leaves other lanes to set its
+  // register, and a register written while its load is in flight makes the
+  // wave wait for that load.
+  int32_t ci[S::NLD];
+  T fr[S::NLD];
+  auto load_group = [&](int g0) {
+#pragma unroll
+    for (int k = 0; k < S::NLD; ++k) {
+      const int f = lane + 64 * k, item = f % TPW, kind = f / TPW;
+      const int64_t i = min(g0 + item, we - 1);
+      const int32_t *ip = kind < 3 ? a.cell + kind * nt + i : a.perm + i;
+      const int fk = (kind >= 3 && kind < 6) ? kind - 3 : 0;
+      ci[k] = *ip;
+      fr[k] = a.frac[fk * nt + i];
+    }
+  };
+  // this lane's target in the group and stencil plane
+  const int tq = lane / W, dz = lane % W;
+  // the first group's target data is loaded together with the staged block
+  if (ws < we) load_group(ws);
   {
     // issue every load of the box before writing LDS
     T v[S::PERG];
@@ -664,8 +676,6 @@ __device__ __forceinline__ void interp_body(const InterpArgs<T> a, double *phi, 
           v[k] = gsrc[((int64_t)gz * Ry + gy) * Rx + gx];
       }
     }
-    if (a.window != 0)
-      for (int i = tid; i < W * (D + 1); i += S::THREADS) kbc[i] = a.kb_tab[i];
 #pragma unroll
     for (int k = 0; k < S::PERG; ++k) {
       const int i = tid + k * S::THREADS;
@@ -674,124 +684,83 @@ __device__ __forceinline__ void interp_body(const InterpArgs<T> a, double *phi, 
   }
   __syncthreads();
 
-  // this wave's contiguous share of the tile's targets, in groups of TG
-  const int ntile = t1 - t0;
-  const int per = ((ntile + S::WAVES - 1) / S::WAVES + TG - 1) / TG * TG;
-  const int ws = t0 + wave * per, we = min(t1, ws + per);
-  // target data of a group: lane l < 7 TG holds item l % TG, kind l / TG
-  // (0..2 cell, 3..5 fraction, 6 caller index), loaded one group ahead
-  const int item = lane % TG, kind = lane / TG;
-  int32_t ci = 0;
-  T fr = T(0);
-  auto load_group = [&](int g0) {
-    ci = 0;
-    fr = T(0);
-    if (kind < 7 && g0 + item < we) {
-      const int64_t i = g0 + item;
-      if (kind < 3) ci = a.cell[kind * nt + i];
-      else if (kind < 6) fr = a.frac[(kind - 3) * nt + i];
-      else ci = a.perm[i];
+  for (int g0 = ws; g0 < we; g0 += TPW) {
+    const int ng = min(TPW, we - g0);
+#pragma unroll
+    for (int k = 0; k < S::NLD; ++k) {
+      const int f = lane + 64 * k, item = f % TPW, kind = f / TPW;
+      if (kind < 7 && item < ng) {
+        if (kind < 3) tcl[wave][item][kind] = ci[k];
+        else if (kind < 6) tfr[wave][item][kind - 3] = fr[k];
+        else tpm[wave][item] = ci[k];
+      }
     }
-  };
-  if (ws < we) load_group(ws);
-  for (int g0 = ws; g0 < we; g0 += TG) {
-    const int ng = min(TG, we - g0);
-    if (kind < 7 && item < ng) {
-      if (kind < 3) tcl[wave][item][kind] = ci;
-      else if (kind < 6) tfr[wave][item][kind - 3] = fr;
-      else tpm[wave][item] = ci;
-    }
-    if (g0 + TG < we) load_group(g0 + TG);
+    if (g0 + TPW < we) load_group(g0 + TPW);
     wave_sync();
     // window factors of the group, one mirrored pair of stencil points (j,
-    // 2m - 1 - j) per lane; Kaiser-Bessel: P_j(u) = E_j(u^2) + u O_j(u^2) and
-    // P_j(-u) from one pass over the coefficients
-    for (int idx = lane; idx < ng * 3 * M; idx += 64) {
-      const int j = idx % M, rest = idx / M;
-      const int ax = rest % 3, it = rest / 3;
-      const T f = tfr[wave][it][ax];
-      T w0, w1;
-      if (a.window == 0) {
+    // 2m - 1 - j) per (lane, pass). Gaussian: lanes over (j, axis, target).
+    // Kaiser-Bessel: P_j(u) = E_j(u^2) + u O_j(u^2) and P_j(-u) from one pass
+    // over the coefficients; one pass per j with the lanes over (axis,
+    // target), so that the coefficients are wave-uniform scalar loads (no LDS
+    // traffic)
+    if (a.window == 0) {
+      for (int idx = lane; idx < ng * 3 * M; idx += 64) {
+        const int j = idx % M, rest = idx / M;
+        const int ax = rest % 3, it = rest / 3;
+        const T f = tfr[wave][it][ax];
         const T d0 = f - T(j - M + 1), d1 = f - T(M - j);
-        w0 = wexp(-d0 * d0 * a.inv_b);
-        w1 = wexp(-d1 * d1 * a.inv_b);
-      } else {
-        const T u = T(2) * f - T(1), v = u * u;
-        const T *c = kbc + j * (D + 1);
-        T e = c[D], o = c[D - 1];
-#pragma unroll
-        for (int d = D - 2; d >= 0; d -= 2) e = e * v + c[d];
-#pragma unroll
-        for (int d = D - 3; d >= 1; d -= 2) o = o * v + c[d];
-        w0 = e + u * o;
-        w1 = e - u * o;
+        wf[wave][it][ax][j] = wexp(-d0 * d0 * a.inv_b);
+        wf[wave][it][ax][W - 1 - j] = wexp(-d1 * d1 * a.inv_b);
       }
-      wf[wave][it][ax][j] = w0;
-      wf[wave][it][ax][W - 1 - j] = w1;
+    } else {
+      const __attribute__((address_space(4))) T *kb =
+          (const __attribute__((address_space(4))) T *)a.kb_tab;
+      for (int j = 0; j < M; ++j) {
+        T c[D + 1];
+#pragma unroll
+        for (int d = 0; d <= D; ++d) c[d] = kb[j * (D + 1) + d];
+        for (int idx = lane; idx < ng * 3; idx += 64) {
+          const int ax = idx % 3, it = idx / 3;
+          const T u = T(2) * tfr[wave][it][ax] - T(1), v = u * u;
+          T e = c[D], o = c[D - 1];
+#pragma unroll
+          for (int d = D - 2; d >= 0; d -= 2) e = e * v + c[d];
+#pragma unroll
+          for (int d = D - 3; d >= 1; d -= 2) o = o * v + c[d];
+          wf[wave][it][ax][j] = e + u * o;
+          wf[wave][it][ax][W - 1 - j] = e - u * o;
+        }
+      }
     }
     wave_sync();
-    double acc[TG];
-#pragma unroll
-    for (int q = 0; q < TG; ++q) acc[q] = 0.0;
-    bool consumed = false;   // the previous slot took this target as its pair
-#pragma unroll
-    for (int q = 0; q < TG; ++q) {
-      if (consumed) {
-        consumed = false;
-        continue;
-      }
-      if (q >= ng) continue;
-      const bool two = q + 1 < ng && tcl[wave][q + 1][0] == tcl[wave][q][0] &&
-                       tcl[wave][q + 1][1] == tcl[wave][q][1] &&
-                       tcl[wave][q + 1][2] == tcl[wave][q][2];
-      const int cx = tcl[wave][q][0] - tx * kTile, cy = tcl[wave][q][1] - ty * kTile,
-                cz = tcl[wave][q][2] - tz * kTile;
-      const T wxl = wf[wave][q][0][lane % W];
+    if (tq < ng) {
+      const int cx = tcl[wave][tq][0] - tx * kTile, cy = tcl[wave][tq][1] - ty * kTile,
+                cz = tcl[wave][tq][2] - tz * kTile;
+      const T *plane = gt + ((cz + dz) * PD + cy) * PD + cx;
       T wx[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) wx[j] = read_lane(wxl, j);
-      if (two) {
-        const int q1 = q + 1 < TG ? q + 1 : q;
-        const T wxl1 = wf[wave][q1][0][lane % W];
-        T wx1[W];
+      for (int j = 0; j < W; ++j) wx[j] = wf[wave][tq][0][j];
+      double acc = 0.0;
 #pragma unroll
-        for (int j = 0; j < W; ++j) wx1[j] = read_lane(wxl1, j);
-        for (int r = lane; r < W * W; r += 64) {
-          const int dy = r % W, dz = r / W;
-          const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
-          T a0 = T(0), a1 = T(0), c0 = T(0), c1 = T(0);
+      for (int dy = 0; dy < W; ++dy) {
+        const T *row = plane + dy * PD;
+        T s0 = T(0), s1 = T(0);
 #pragma unroll
-          for (int j = 0; j < W; j += 2) {
-            const T g0v = row[j], g1v = row[j + 1];
-            a0 += g0v * wx[j];
-            a1 += g1v * wx[j + 1];
-            c0 += g0v * wx1[j];
-            c1 += g1v * wx1[j + 1];
-          }
-          acc[q] += (double)((a0 + a1) * (wf[wave][q][1][dy] * wf[wave][q][2][dz]));
-          acc[q1] += (double)((c0 + c1) * (wf[wave][q1][1][dy] * wf[wave][q1][2][dz]));
+        for (int j = 0; j < W; j += 2) {
+          s0 += row[j] * wx[j];
+          s1 += row[j + 1] * wx[j + 1];
         }
-        consumed = true;
-      } else {
-        for (int r = lane; r < W * W; r += 64) {
-          const int dy = r % W, dz = r / W;
-          const T *row = gt + ((cz + dz) * PD + cy + dy) * PD + cx;
-          T a0 = T(0), a1 = T(0);
-#pragma unroll
-          for (int j = 0; j < W; j += 2) {
-            a0 += row[j] * wx[j];
-            a1 += row[j + 1] * wx[j + 1];
-          }
-          acc[q] += (double)((a0 + a1) * (wf[wave][q][1][dy] * wf[wave][q][2][dz]));
-        }
+        acc += (double)(s0 + s1) * (double)wf[wave][tq][1][dy];
       }
+      psum[wave][lane] = acc * (double)wf[wave][tq][2][dz];
     }
+    wave_sync();
+    if (lane < ng) {
+      double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < TG; ++q) acc[q] = wave_sum(acc[q]);
-    if (lane == 0)
-#pragma unroll
-      for (int q = 0; q < TG; ++q)
-        if (q < ng) phi[tpm[wave][q]] = acc[q];
+      for (int k = 0; k < W; ++k) sum += psum[wave][lane * W + k];
+      phi[tpm[wave][lane]] = sum;
+    }
     wave_sync();   // the slices are rewritten by the next group
   }
 }
