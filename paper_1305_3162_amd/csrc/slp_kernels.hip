@@ -38,15 +38,18 @@ __device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
 // the window at tau = f + m - 1 - j. The window is even, so the stencil point
 // 2m - 1 - j sees P_j(-u): with P_j(u) = E_j(u^2) + u O_j(u^2) one pass over
 // the even and odd coefficients of P_j gives both points (the host stores the
-// mirrored polynomials exactly so). The coefficient indices are compile-time,
-// so they are read as wave-uniform kernel arguments.
+// mirrored polynomials exactly so). The coefficients are wave-uniform kernel
+// arguments. When all pairs' coefficients take more than 48 scalar
+// registers, the pairs are a loop that is not unrolled, so that only one
+// pair's coefficients are held at a time (all of them at once overflow the
+// scalar registers into vector-register lanes, and every use then costs a
+// vector instruction).
 template <typename T, int M>
 __device__ __forceinline__ void kb_stencil(const T (&c)[kKbCoef], T u, T q, T *out) {
   constexpr int D = kb_degree<T>();
   static_assert(D % 2 == 0, "even polynomial degree");
   const T v = u * u;
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
+  auto pair = [&](int j) {
     const T *cj = c + j * (D + 1);
     T e = cj[D], o = cj[D - 1];
 #pragma unroll
@@ -56,6 +59,13 @@ __device__ __forceinline__ void kb_stencil(const T (&c)[kKbCoef], T u, T q, T *o
     const T uo = u * o;
     out[j] = (e + uo) * q;
     out[2 * M - 1 - j] = (e - uo) * q;
+  };
+  if constexpr (M * (D + 1) * sizeof(T) / 4 > 48) {
+#pragma unroll 1
+    for (int j = 0; j < M; ++j) pair(j);
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) pair(j);
   }
 }
 
@@ -337,9 +347,12 @@ __device__ __forceinline__ void spread_bins_body(const SpreadBinsArgs<T> &a,
         const int rec = act ? rrec[r] : 0;
         const int cx = rec & 7, cy = (rec >> 3) & 7, cz = (rec >> 6) & 7;
         const int cnt = act ? (rec >> 19) & 2047 : 0;
-        int maxc = cnt;
+        int maxv = cnt;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) maxc = max(maxc, __shfl_xor(maxc, o));
+        for (int o = 32; o > 0; o >>= 1) maxv = max(maxv, __shfl_xor(maxv, o));
+        // the same on every lane: a scalar, so that the source loop below is
+        // a scalar loop with compile-time factor offsets
+        const int maxc = __builtin_amdgcn_readfirstlane(maxv);
         T acc[CX * CY][CZ];
 #pragma unroll
         for (int c2 = 0; c2 < CX * CY; ++c2)
@@ -365,23 +378,26 @@ __device__ __forceinline__ void spread_bins_body(const SpreadBinsArgs<T> &a,
           wave_sync();
           if (g < R) {
             const int nb = min(SB, maxc - c0);
-            for (int b = 0; b < nb; ++b) {
-              const T *f3 = ww + (g * SB + b) * FST;
-              T wz[CZ], fx[CX], fy[CY];
 #pragma unroll
-              for (int j = 0; j < CZ; ++j) wz[j] = f3[2 * W + dz0 + j * SZ];
+            for (int b = 0; b < SB; ++b) {
+              if (b < nb) {
+                const T *f3 = ww + (g * SB + b) * FST;
+                T wz[CZ], fx[CX], fy[CY];
 #pragma unroll
-              for (int i = 0; i < CX; ++i) fx[i] = f3[dx0 + i * SX];
+                for (int j = 0; j < CZ; ++j) wz[j] = f3[2 * W + dz0 + j * SZ];
 #pragma unroll
-              for (int i = 0; i < CY; ++i) fy[i] = f3[W + dy0 + i * SY];
+                for (int i = 0; i < CX; ++i) fx[i] = f3[dx0 + i * SX];
 #pragma unroll
-              for (int iy = 0; iy < CY; ++iy)
+                for (int i = 0; i < CY; ++i) fy[i] = f3[W + dy0 + i * SY];
 #pragma unroll
-                for (int ix = 0; ix < CX; ++ix) {
-                  const T pw = fx[ix] * fy[iy];
+                for (int iy = 0; iy < CY; ++iy)
 #pragma unroll
-                  for (int j = 0; j < CZ; ++j) acc[iy * CX + ix][j] += pw * wz[j];
-                }
+                  for (int ix = 0; ix < CX; ++ix) {
+                    const T pw = fx[ix] * fy[iy];
+#pragma unroll
+                    for (int j = 0; j < CZ; ++j) acc[iy * CX + ix][j] += pw * wz[j];
+                  }
+              }
             }
           }
           wave_sync();
