@@ -904,7 +904,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       G->b = pi * (2.0 - 1.0 / p->alpha);
       G->kb_inv_norm = p->m / std::sinh(G->b * p->m);
       G->kb_coef = kb_polynomials(p->m, G->b, G->kb_inv_norm,
-                                  p->precision == SLP_FP64 ? slp::kKbDeg64 : slp::kKbDeg32);
+                                  slp::kb_degree(p->precision == SLP_FP64, p->m));
     }
   }
   G->n_nodes = n_nodes;

@@ -38,14 +38,16 @@ hipError_t static_workspace(void **ptr);
 // each unit interval of the stencil the window is a polynomial in
 // u = 2 (t - floor(t)) - 1, fitted on the host at setup by interpolation at the
 // Chebyshev points of that degree (max error over the interval, relative to
-// the window's peak: below 1.1e-14 in FP64 at degree 16, below FP32 rounding at
-// degree 8, for every m <= kMaxM). Coefficients of stencil point j at
-// [j * (deg + 1) + d], d = 0 .. deg (monomial, ascending).
+// the window's peak: below 1e-14 in FP64 at degree 16 for m <= 2 and at
+// degree 14 for m >= 3, below FP32 rounding at degree 8, for every
+// m <= kMaxM). Coefficients of stencil point j at [j * (deg + 1) + d],
+// d = 0 .. deg (monomial, ascending).
 constexpr int kKbDeg64 = 16;
 constexpr int kKbDeg32 = 8;
 constexpr int kKbCoef = 2 * kMaxM * (kKbDeg64 + 1);
-template <typename T>
-constexpr int kb_degree() { return sizeof(T) == 8 ? kKbDeg64 : kKbDeg32; }
+constexpr int kb_degree(bool fp64, int m) { return fp64 ? (m <= 2 ? kKbDeg64 : 14) : kKbDeg32; }
+template <typename T, int M>
+constexpr int kb_degree() { return kb_degree(sizeof(T) == 8, M); }
 
 // Per-item caller pointers of a batched launch (passed by value).
 struct BatchPtrs {

@@ -46,7 +46,7 @@ __device__ __forceinline__ T kb_weight(T tau, T m, T b, T inv_norm) {
 // vector instruction).
 template <typename T, int M>
 __device__ __forceinline__ void kb_stencil(const T (&c)[kKbCoef], T u, T q, T *out) {
-  constexpr int D = kb_degree<T>();
+  constexpr int D = kb_degree<T, M>();
   static_assert(D % 2 == 0, "even polynomial degree");
   const T v = u * u;
   auto pair = [&](int j) {
@@ -630,7 +630,7 @@ template <typename T, int M>
 __device__ __forceinline__ void interp_body(const InterpArgs<T> a, double *phi, int64_t slot,
                                             int bitem) {
   using S = InterpShape<T, M>;
-  constexpr int W = S::W, PD = S::PD, TPW = S::TPW, D = kb_degree<T>();
+  constexpr int W = S::W, PD = S::PD, TPW = S::TPW, D = kb_degree<T, M>();
   __shared__ T gt[S::GT];
   __shared__ T wf[S::WAVES][TPW][3][W];     // window factors of each wave's group
   __shared__ T tfr[S::WAVES][TPW][3];       // fractions of each wave's group
