@@ -275,6 +275,23 @@ __device__ __forceinline__ T mu_at(const FftPass<T> &p, int2 line, int em) {
   return (in_i && in_mi) ? f : ((in_i || in_mi) ? T(0.5) * f : T(0));
 }
 
+// A pass read from a table in memory, its pointers marked as pointing to
+// global memory (so that accesses through them are global rather than flat
+// instructions).
+template <typename P>
+__device__ __forceinline__ P *gptr(P *p) {
+  return (P *)(__attribute__((address_space(1))) P *)(uintptr_t)p;
+}
+template <typename T>
+__device__ __forceinline__ FftPass<T> global_pass(const FftPass<T> &q) {
+  FftPass<T> p = q;
+  p.in = gptr(p.in);
+  p.out = gptr(p.out);
+  p.tw = gptr(p.tw);
+  p.mu = gptr(p.mu);
+  return p;
+}
+
 // Lines blk G .. blk G + G - 1 of pass p for batch item `item`.
 template <typename T, int N, bool STRIDED, bool MULINV>
 __device__ __forceinline__ void fft_body(const FftPass<T> p, int64_t item, int64_t blk) {
@@ -360,7 +377,7 @@ template <typename T, int N, bool STRIDED, bool MULINV>
 __global__ __launch_bounds__((FftCfg<T, N, STRIDED>::THREADS), (FftCfg<T, N, STRIDED>::MINW)) void k_fft_multi(
     const FftPass<T> *__restrict__ passes, const int2 *__restrict__ work) {
   const int2 w = work[xcd_block(blockIdx.x, gridDim.x)];
-  fft_body<T, N, STRIDED, MULINV>(passes[w.x], 0, w.y);
+  fft_body<T, N, STRIDED, MULINV>(global_pass(passes[w.x]), 0, w.y);
 }
 
 // Real lines of length N (contiguous lines only) through a complex transform
@@ -478,7 +495,7 @@ template <typename T, int N>
 __global__ __launch_bounds__((FftCfg<T, N / 2, false>::THREADS), (FftCfg<T, N / 2, false>::MINW)) void k_fft_real_multi(
     const FftPass<T> *__restrict__ passes, const int2 *__restrict__ work) {
   const int2 w = work[xcd_block(blockIdx.x, gridDim.x)];
-  fft_real_body<T, N>(passes[w.x], 0, w.y);
+  fft_real_body<T, N>(global_pass(passes[w.x]), 0, w.y);
 }
 
 // Which kernel takes pass p of length N: 0 / 1 contiguous lines without /

@@ -21,6 +21,15 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float wexp(float x) { return __expf(x); }
 __device__ __forceinline__ double wexp(double x) { return exp(x); }
 
+// A pointer read from memory (the argument tables of the fused launches)
+// marked as pointing to global memory, so that accesses through it are
+// global rather than flat instructions (flat accesses also count against the
+// LDS wait counter, and a wait for LDS then waits for them too).
+template <typename P>
+__device__ __forceinline__ P *gptr(P *p) {
+  return (P *)(__attribute__((address_space(1))) P *)(uintptr_t)p;
+}
+
 // Kaiser-Bessel window of eq. KBfct in grid units, scaled to 1 at tau = 0:
 // sinh(b s) / s * inv_norm with s = sqrt(m^2 - tau^2) (|tau| <= m on every
 // stencil point; the limit b at s = 0).
@@ -454,7 +463,18 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins_mu
     const MultiItem<T> *__restrict__ items, const int2 *__restrict__ work, BatchPtrs ptrs,
     SpreadBinsArgs<T> win) {
   const int2 w = work[blockIdx.x];
-  spread_bins_body<T, M>(items[w.x].sp, win, ptrs.dens[w.x], w.y, 0);
+  const SpreadBinsArgs<T> &it = items[w.x].sp;
+  SpreadBinsArgs<T> a;
+  a.frac = gptr(it.frac);
+  a.w = gptr(it.w);
+  a.perm = gptr(it.perm);
+  a.units = gptr(it.units);
+  a.chunks = gptr(it.chunks);
+  a.runs = gptr(it.runs);
+  a.scratch = gptr(it.scratch);
+  a.ns = it.ns;
+  a.scratch_bstride = 0;
+  spread_bins_body<T, M>(a, win, gptr(ptrs.dens[w.x]), w.y, 0);
 }
 
 // One workgroup of 512 threads per region tile, one thread per cell. For each
@@ -518,7 +538,11 @@ template <typename T, int M>
 __global__ __launch_bounds__(512) void k_spread_reduce_multi(const MultiItem<T> *__restrict__ items,
                                                              const int2 *__restrict__ work) {
   const int2 w = work[blockIdx.x];
-  spread_reduce_body<T, M>(items[w.x].rd, w.y, 0);
+  SpreadReduceArgs<T> a = items[w.x].rd;
+  a.scratch = gptr(a.scratch);
+  a.tile_slots = gptr(a.tile_slots);
+  a.grid = gptr(a.grid);
+  spread_reduce_body<T, M>(a, w.y, 0);
 }
 
 template <typename T, int M>
@@ -800,7 +824,14 @@ template <typename T, int M>
 __global__ __launch_bounds__((InterpShape<T, M>::THREADS)) void k_interp_multi(
     const MultiItem<T> *__restrict__ items, const int2 *__restrict__ work, BatchPtrs ptrs) {
   const int2 w = work[blockIdx.x];
-  interp_body<T, M>(items[w.x].ip, ptrs.phi[w.x], w.y, 0);
+  InterpArgs<T> a = items[w.x].ip;
+  a.cell = gptr(a.cell);
+  a.frac = gptr(a.frac);
+  a.perm = gptr(a.perm);
+  a.rec = gptr(a.rec);
+  a.g = gptr(a.g);
+  a.kb_tab = gptr(a.kb_tab);
+  interp_body<T, M>(a, gptr(ptrs.phi[w.x]), w.y, 0);
 }
 
 template <typename T, int M>
