@@ -477,19 +477,27 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins_mu
   spread_bins_body<T, M>(a, win, gptr(ptrs.dens[w.x]), w.y, 0);
 }
 
-// One workgroup of 512 threads per region tile, one thread per cell. For each
-// of the 27 neighbouring tiles (fixed order) and each of its segments, the
-// threads whose cell the block covers read the matching sub-block, which is
+// Region tiles (times batch items) from which the block sum takes two cells
+// per thread in workgroups of 256 (below: one cell per thread, 512). At the
+// threshold the 256-thread form has 32 waves per CU.
+constexpr int64_t kReduceTwoCells = 2048;
+
+// One workgroup per region tile, one or two cells per thread. For each of the
+// 27 neighbouring tiles (fixed order) and each of its segments, the threads
+// whose cell the block covers read the matching sub-block, which is
 // contiguous in the blocked layout.
-template <typename T, int M>
+template <typename T, int M, int CPT>
 __device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs<T> a, int tile, int item) {
   using S = SpreadShape<T, M>;
+  constexpr int ZS = kTile / CPT;    // planes between a thread's cells
   const int tx = tile % a.tiles[0];
   const int ty = (tile / a.tiles[0]) % a.tiles[1];
   const int tz = tile / (a.tiles[0] * a.tiles[1]);
   const int64_t Px = (int64_t)a.tiles[0] * kTile, Py = (int64_t)a.tiles[1] * kTile;
   const T *scr = a.scratch + item * a.scratch_bstride;
   T *grid = a.grid + item * a.grid_bstride;
+  // CPT cells per thread, planes cz, cz + ZS, ...: the neighbour's record and
+  // the x, y tests are shared, the loads independent
   const int c = threadIdx.x;
   const int cx = c & 7, cy = (c >> 3) & 7, cz = c >> 6;
   // the segment ranges and reach boxes of the 27 neighbouring tiles, read
@@ -503,46 +511,50 @@ __device__ __forceinline__ void spread_reduce_body(const SpreadReduceArgs<T> a, 
     nts[c] = ts;
   }
   __syncthreads();
-  T v = T(0);
+  T v[CPT];
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) v[j] = T(0);
 #pragma unroll
   for (int d = 0; d < 27; ++d) {
     const int4 ts = nts[d];
     if (ts.y == 0) continue;
     const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
-    // pad coordinate of this cell in the neighbour's block; pad cells of that
-    // tile that none of its sources reaches were not stored
+    // pad coordinates of the cells in the neighbour's block; pad cells of
+    // that tile that none of its sources reaches were not stored
     const int ix = cx - kTile * dx + M - 1, iy = cy - kTile * dy + M - 1, iz = cz - kTile * dz + M - 1;
     const int bx = ts.z;
-    if (ix < (bx & 31) || ix > ((bx >> 15) & 31) || iy < ((bx >> 5) & 31) ||
-        iy > ((bx >> 20) & 31) || iz < ((bx >> 10) & 31) || iz > ((bx >> 25) & 31))
+    if (ix < (bx & 31) || ix > ((bx >> 15) & 31) || iy < ((bx >> 5) & 31) || iy > ((bx >> 20) & 31))
       continue;
-    const int off = pad_block_index<M>(ix, iy, iz);
-    // (issuing the neighbours' loads together, nine tiles at a time into
-    // registers, measured slower: 100-133 against 75 us on the film)
-    const T *p0 = scr + (int64_t)ts.x * S::P3 + off;
-    v += p0[0];
-    if (ts.y > 1) v += p0[S::P3];
-    for (int k = 2; k < ts.y; ++k) v += p0[(int64_t)k * S::P3];
+    const int zl = (bx >> 10) & 31, zh = (bx >> 25) & 31;
+    const T *p0 = scr + (int64_t)ts.x * S::P3;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int izj = iz + j * ZS;
+      if (izj >= zl && izj <= zh) {
+        const T *q = p0 + pad_block_index<M>(ix, iy, izj);
+        for (int k = 0; k < ts.y; ++k) v[j] += q[(int64_t)k * S::P3];
+      }
+    }
   }
-  grid[((tz * kTile + cz) * Py + ty * kTile + cy) * Px + tx * kTile + cx] = v;
+  T *out = grid + ((tz * kTile + cz) * Py + ty * kTile + cy) * Px + tx * kTile + cx;
+#pragma unroll
+  for (int j = 0; j < CPT; ++j) out[(int64_t)j * ZS * Py * Px] = v[j];
 }
 
-template <typename T, int M>
-__global__ __launch_bounds__(512) void k_spread_reduce(SpreadReduceArgs<T> a) {
-  spread_reduce_body<T, M>(a, blockIdx.x, blockIdx.y);
+template <typename T, int M, int CPT>
+__global__ __launch_bounds__(512 / CPT) void k_spread_reduce(SpreadReduceArgs<T> a) {
+  spread_reduce_body<T, M, CPT>(a, blockIdx.x, blockIdx.y);
 }
 
-// Several geometries in one launch: workgroup i sums tile work[i].y of item
-// work[i].x.
-template <typename T, int M>
-__global__ __launch_bounds__(512) void k_spread_reduce_multi(const MultiItem<T> *__restrict__ items,
+template <typename T, int M, int CPT>
+__global__ __launch_bounds__(512 / CPT) void k_spread_reduce_multi(const MultiItem<T> *__restrict__ items,
                                                              const int2 *__restrict__ work) {
   const int2 w = work[blockIdx.x];
   SpreadReduceArgs<T> a = items[w.x].rd;
   a.scratch = gptr(a.scratch);
   a.tile_slots = gptr(a.tile_slots);
   a.grid = gptr(a.grid);
-  spread_reduce_body<T, M>(a, w.y, 0);
+  spread_reduce_body<T, M, CPT>(a, w.y, 0);
 }
 
 template <typename T, int M>
@@ -560,8 +572,15 @@ static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T>
     if (e != hipSuccess) return e;
   }
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
-  hipLaunchKernelGGL((k_spread_reduce<T, M>), dim3((unsigned)tiles, (unsigned)nb), dim3(512), 0, s,
-                     r);
+  // two cells per thread where there are enough tiles to fill the chip (film
+  // regions of 5,408 and 8,427 tiles: 51 -> 42 and 74 -> 59 us); one where
+  // there are few (a cube surface, 512 tiles: 16 against 22 us)
+  if (tiles * nb >= kReduceTwoCells)
+    hipLaunchKernelGGL((k_spread_reduce<T, M, 2>), dim3((unsigned)tiles, (unsigned)nb), dim3(256), 0,
+                       s, r);
+  else
+    hipLaunchKernelGGL((k_spread_reduce<T, M, 1>), dim3((unsigned)tiles, (unsigned)nb), dim3(512), 0,
+                       s, r);
   return hipGetLastError();
 }
 
@@ -591,8 +610,12 @@ static hipError_t spread_multi_m(const MultiItem<T> *items, const int2 *bins_wor
                        dim3(SpreadShape<T, M>::THREADS), 0, s, items, bins_work, p, win);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_red == 0) return e;
-  hipLaunchKernelGGL((k_spread_reduce_multi<T, M>), dim3((unsigned)n_red), dim3(512), 0, s, items,
-                     red_work);
+  if (n_red >= kReduceTwoCells)
+    hipLaunchKernelGGL((k_spread_reduce_multi<T, M, 2>), dim3((unsigned)n_red), dim3(256), 0, s, items,
+                       red_work);
+  else
+    hipLaunchKernelGGL((k_spread_reduce_multi<T, M, 1>), dim3((unsigned)n_red), dim3(512), 0, s, items,
+                       red_work);
   return hipGetLastError();
 }
 
