@@ -384,12 +384,12 @@ def multi_mesh(args, prec, window, m, steps, warmup):
             w, g = slp.expsum_sinc(0.2, r_lo, r_hi, 1e-12)
             cache[L] = (nodes, tris, w, g, grid_rule(nodes, tris))
         nodes, tris, w, g, N = cache[L]
-        share = 0
+        share, cells = 0, 0
         if args.autotune:
-            share = tuned_share(args, nodes, tris, (N,) * 3, m, w, g, 2, prec, 37.0,
-                                window, None)["seg_share"]
+            t = tuned_share(args, nodes, tris, (N,) * 3, m, w, g, 2, prec, 37.0, window, None)
+            share, cells = t["seg_share"], t["reduce_cells"]
         geos.append(slp.Geometry(nodes, tris, (N,) * 3, m, w, g, 2, prec, window=window,
-                                 seg_share=share))
+                                 seg_share=share, reduce_cells=cells))
         mf = RandomSmoothMagnetisation(4101 + i, nodes.min(0), nodes.max(0))
         dens.append(torch.as_tensor(density_from_magnetisation(nodes, tris, mf), device="cuda"))
         phis.append(torch.empty(nodes.shape[0], dtype=torch.float64, device="cuda"))
@@ -609,13 +609,16 @@ def near_storage(args, slp, prec):
 
 
 def tuned_share(args, nodes, tris, grid, m, w, g, alpha, prec, eta2, window, targets):
-    """The autotuner's split for this workload (timed now or read from the cache)."""
+    """The autotuner's split and block-sum form for this workload (timed now or
+    read from the cache)."""
     from paper_1305_3162_amd import autotune
     cache = None if args.autotune == "-" else args.autotune
     r = autotune.tune_share(nodes, tris, grid, m, w, g, alpha, prec, eta2, window=window,
                             targets=targets, cache=cache)
-    return {"seg_share": r["seg_share"], "auto_share": r["auto_share"], "cached": r["cached"],
-            "candidates_us": {str(c["seg_share"]): round(c["us"], 2) for c in r["candidates"]}}
+    return {"seg_share": r["seg_share"], "reduce_cells": r["reduce_cells"],
+            "auto_share": r["auto_share"], "auto_cells": r["auto_cells"], "cached": r["cached"],
+            "candidates_us": {f'{c["seg_share"]}/{c["reduce_cells"]}': round(c["us"], 2)
+                              for c in r["candidates"]}}
 
 
 GATE = {"fp64": 1e-6, "fp32": 1e-4}   # stated relative L2 tolerances
@@ -744,7 +747,8 @@ def solve_line(args, slp, torch, wl, prec, window, m, steps, warmup, err="auto")
                                    traffic_key(wl.name, pname, wname, m), cnt),
            "setup_s": round(t_setup, 3),
            "gridding_split": {"seg_share": int(info["seg_share"]),
-                              "segments": int(info["n_segments"])}}
+                              "segments": int(info["n_segments"]),
+                              "reduce_cells": int(info["reduce_cells"])}}
     if err == "golden":
         e, n = golden_error(wl, geom, out)
         rec["rel_l2_err_vs_oracle"] = e
@@ -911,7 +915,8 @@ def main():
     t1 = time.perf_counter()
     geom = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2,
                         window=window, targets=targets,
-                        seg_share=tune["seg_share"] if tune else 0)
+                        seg_share=tune["seg_share"] if tune else 0,
+                        reduce_cells=tune["reduce_cells"] if tune else 0)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t1
     near_cfg = None
@@ -936,6 +941,7 @@ def main():
                   "device_bytes": slp.geom_get_info(geom.handle)["device_bytes"]}
     n_tgt = geom.info["n_targets"]
     geom_share, geom_segments = int(geom.info["seg_share"]), int(geom.info["n_segments"])
+    geom_cells = int(geom.info["reduce_cells"])
     info = dict(geom.info)
     info["_n"] = [wl.grid[q] // wl.alpha for q in range(3)]
     info["_stored"] = 0 if near_cfg is None else near_cfg["stored"]
@@ -1096,7 +1102,7 @@ def main():
                    "points": pts, "densities_per_step": nb, "near_field": near_cfg,
                    "integrated_gridding": iw_cfg, "setup_s": round(t_setup, 3),
                    "gridding_split": {"seg_share": geom_share, "segments": geom_segments,
-                                      "autotune": tune}},
+                                      "reduce_cells": geom_cells, "autotune": tune}},
         "rel_l2_err_vs_oracle": rel_err,
         "err_kind": err_kind,
         **err_extra,

@@ -85,6 +85,14 @@ typedef struct {
                              for FP64 with m = 8); otherwise
                              64 <= seg_share <= 2^24 (EINVAL outside). A timing autotuner
                              sets it; the automatic value is reported in slp_geom_info. */
+  int32_t reduce_cells;   /* cells per thread of the gridding's block sum (no effect on the
+                             result: each cell adds its terms in one fixed order either way):
+                             1 (workgroups of 512 threads) or 2 (of 256); 0 = automatic, 2
+                             where the region has 2048 tiles or more (times the densities of
+                             a batched call), else 1; fused multi-geometry batches take the
+                             automatic rule over all their items. EINVAL outside 0..2. A timing
+                             autotuner sets it; the value in effect for one density is
+                             reported in slp_geom_info. */
 } slp_params;
 
 typedef struct slp_geom slp_geom;   /* opaque; owns device tables and work buffers */
@@ -104,6 +112,7 @@ typedef struct {
   int64_t device_bytes;   /* device memory held by the context */
   int64_t seg_share;      /* sources per gridding piece in effect (see slp_params) */
   int64_t n_segments;     /* gridding workgroups (padded blocks) per density */
+  int32_t reduce_cells;   /* block-sum cells per thread for one density (see slp_params) */
 } slp_geom_info;
 
 /* Setup phase of Alg. 1 for one surface (Sec. 3.1-3.3). Scales the body into

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("es_w", ctypes.POINTER(ctypes.c_double)),
                 ("es_gamma", ctypes.POINTER(ctypes.c_double)), ("es_terms", ctypes.c_int32),
                 ("window", ctypes.c_int32), ("eta2", ctypes.c_double),
-                ("seg_share", ctypes.c_int32)]
+                ("seg_share", ctypes.c_int32), ("reduce_cells", ctypes.c_int32)]
 
 
 class GeomInfo(ctypes.Structure):
@@ -55,7 +55,7 @@ class GeomInfo(ctypes.Structure):
                 ("n_targets", ctypes.c_int64), ("terms_kept", ctypes.c_int32), ("lo", ctypes.c_int32 * 3),
                 ("extent", ctypes.c_int32 * 3), ("tiles", ctypes.c_int32 * 3),
                 ("device_bytes", ctypes.c_int64), ("seg_share", ctypes.c_int64),
-                ("n_segments", ctypes.c_int64)]
+                ("n_segments", ctypes.c_int64), ("reduce_cells", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -204,7 +204,7 @@ def expsum_sinc(h, r_lo, r_hi, tol):
 
 
 def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, window=0,
-             seg_share=0):
+             seg_share=0, reduce_cells=0):
     nodes = np.ascontiguousarray(nodes, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     if nodes.ndim != 2 or nodes.shape[1] != 3 or tris.ndim != 2 or tris.shape[1] != 3:
@@ -222,16 +222,18 @@ def _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, windo
     p.eta2 = float(eta2)
     p.window = int(window)
     p.seg_share = int(seg_share)
+    p.reduce_cells = int(reduce_cells)
     return nodes, tris, es_w, es_gamma, p     # arrays kept alive by the caller
 
 
 def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
-                   stream=None, window=WINDOW_GAUSS, targets=None, seg_share=0):
+                   stream=None, window=WINDOW_GAUSS, targets=None, seg_share=0, reduce_cells=0):
     """slp_setup_geometry (slp_setup_geometry_targets when `targets` [P, 3] is given):
-    returns an opaque handle (int). seg_share 0 = automatic gridding split."""
+    returns an opaque handle (int). seg_share 0 = automatic gridding split;
+    reduce_cells 0 = automatic block-sum form (1 or 2 cells per thread)."""
     lib = load_library()
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                              precision, eta2, window, seg_share)
+                                              precision, eta2, window, seg_share, reduce_cells)
     h = _VP()
     if targets is None:
         _check(lib.slp_setup_geometry(ctypes.byref(h), nodes.ctypes.data, nodes.shape[0],
@@ -249,11 +251,11 @@ def setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64
 
 
 def geometry_device_bytes(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                          eta2=37.0, window=WINDOW_GAUSS, seg_share=0):
+                          eta2=37.0, window=WINDOW_GAUSS, seg_share=0, reduce_cells=0):
     """slp_geometry_device_bytes: device bytes a context would hold (host only)."""
     lib = load_library()
     nodes, tris, es_w, es_gamma, p = _marshal(nodes, tris, grid, m, es_w, es_gamma, alpha,
-                                              precision, eta2, window, seg_share)
+                                              precision, eta2, window, seg_share, reduce_cells)
     out = ctypes.c_int64(0)
     _check(lib.slp_geometry_device_bytes(nodes.ctypes.data, nodes.shape[0], tris.ctypes.data,
                                          tris.shape[0], ctypes.byref(p), ctypes.byref(out)))
@@ -397,7 +399,8 @@ def geom_get_info(geom):
             "n_targets": gi.n_targets,
             "terms_kept": gi.terms_kept, "lo": list(gi.lo), "extent": list(gi.extent),
             "tiles": list(gi.tiles), "device_bytes": gi.device_bytes,
-            "seg_share": gi.seg_share, "n_segments": gi.n_segments}
+            "seg_share": gi.seg_share, "n_segments": gi.n_segments,
+            "reduce_cells": gi.reduce_cells}
 
 
 def choose_cutoff(tol, precision=FP64, window=None):
@@ -662,9 +665,10 @@ class Geometry:
     """Owning wrapper around one slp_geom context."""
 
     def __init__(self, nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64,
-                 eta2=37.0, stream=None, window=WINDOW_GAUSS, targets=None, seg_share=0):
+                 eta2=37.0, stream=None, window=WINDOW_GAUSS, targets=None, seg_share=0,
+                 reduce_cells=0):
         self.handle = setup_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision,
-                                     eta2, stream, window, targets, seg_share)
+                                     eta2, stream, window, targets, seg_share, reduce_cells)
         self.info = geom_get_info(self.handle)
         self.precision = precision
 

@@ -1,4 +1,4 @@
-"""Timing autotuner for the two choices the library leaves open without
+"""Timing autotuner for the choices the library leaves open without
 changing the result beyond rounding order or the stated tolerance:
 
 * the gridding split (``slp_params.seg_share``): how many sources one gridding
@@ -6,6 +6,11 @@ changing the result beyond rounding order or the stated tolerance:
   block. Fewer, fuller pieces store and sum fewer blocks; more pieces balance
   the compute units better. The automatic rule shares the chip's workgroup
   slots out evenly; the tuner times the candidates around it on the device.
+* the block-sum form (``slp_params.reduce_cells``): one cell per thread in
+  workgroups of 512 or two in workgroups of 256. Two share a thread's
+  neighbour tests and keep two load chains in flight; one keeps twice the
+  waves, which small regions need. Both are timed at the tuned split (the
+  result is the same bit for bit).
 * the window and cut-off m at a requested tolerance (the paper's Gaussian or
   Kaiser-Bessel window, Sec. 3.2): every window whose smallest predicted m
   meets the tolerance (``choose_cutoff``) is timed, the fastest is kept and its
@@ -33,7 +38,7 @@ def _device_name():
     return torch.cuda.get_device_name(torch.cuda.current_device()).replace("|", "/")
 
 
-def cache_key(info, grid, m, window, precision, device, kind="share"):
+def cache_key(info, grid, m, window, precision, device, kind="split"):
     """Key of one tuning result: everything the split and the timings depend on."""
     return "|".join([kind, device, "fp64" if precision == FP64 else "fp32",
                      "kb" if window == WINDOW_KB else "gauss", f"m{int(m)}",
@@ -97,9 +102,10 @@ def _density(n_src, seed=0):
 
 def tune_share(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
                window=WINDOW_GAUSS, targets=None, cache=None, reps=30, force=False):
-    """Times the gridding split candidates of one workload; returns
-    {"seg_share", "us", "auto_share", "candidates": [...], "cached"}.
-    Splits giving the same segment count as one already timed are skipped."""
+    """Times the gridding split candidates of one workload, then both block-sum
+    forms at the fastest split; returns {"seg_share", "reduce_cells", "us",
+    "auto_share", "auto_cells", "candidates": [...], "cached"}. Splits giving
+    the same segment count as one already timed are skipped."""
     G = Geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2,
                  window=window, targets=targets)
     info = dict(G.info)
@@ -109,6 +115,7 @@ def tune_share(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, et
         G.close()
         return dict(data[key], cached=True)
     auto = int(info["seg_share"])
+    auto_cells = int(info["reduce_cells"])
     dens = _density(int(info["n_src"]))
     results, seen = [], {}
     try:
@@ -122,15 +129,29 @@ def tune_share(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, et
                     continue
                 us = time_steps(H, dens, reps=reps)
                 seen[nseg] = share
-                results.append({"seg_share": share, "n_segments": nseg, "us": us})
+                results.append({"seg_share": share, "reduce_cells": auto_cells,
+                                "n_segments": nseg, "us": us})
             finally:
                 if H is not G:
                     H.close()
+        best = min(results, key=lambda r: r["us"])
+        for cells in (1, 2):
+            if cells == auto_cells:
+                continue
+            H = Geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2,
+                         window=window, targets=targets, seg_share=best["seg_share"],
+                         reduce_cells=cells)
+            try:
+                results.append({"seg_share": best["seg_share"], "reduce_cells": cells,
+                                "n_segments": int(H.info["n_segments"]),
+                                "us": time_steps(H, dens, reps=reps)})
+            finally:
+                H.close()
     finally:
         G.close()
     best = min(results, key=lambda r: r["us"])
-    out = {"seg_share": best["seg_share"], "us": best["us"], "auto_share": auto,
-           "candidates": results}
+    out = {"seg_share": best["seg_share"], "reduce_cells": best["reduce_cells"], "us": best["us"],
+           "auto_share": auto, "auto_cells": auto_cells, "candidates": results}
     data = load_cache(cache)
     data[key] = out
     store_cache(cache, data)
@@ -140,7 +161,8 @@ def tune_share(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, et
 def tune_cutoff(tol, nodes, tris, grid, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
                 targets=None, cache=None, reps=30, force=False):
     """Fastest (window, m) predicted to meet `tol`, with its tuned split;
-    returns {"window", "m", "seg_share", "us", "candidates": [...], "cached"}."""
+    returns {"window", "m", "seg_share", "reduce_cells", "us", "candidates": [...],
+    "cached"}."""
     cands = []
     for w in (WINDOW_GAUSS, WINDOW_KB):
         try:
@@ -153,7 +175,8 @@ def tune_cutoff(tol, nodes, tris, grid, es_w, es_gamma, alpha=2, precision=FP64,
     for w, m in cands:
         r = tune_share(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, window=w,
                        targets=targets, cache=cache, reps=reps, force=force)
-        timed.append({"window": w, "m": m, "seg_share": r["seg_share"], "us": r["us"],
+        timed.append({"window": w, "m": m, "seg_share": r["seg_share"],
+                      "reduce_cells": r.get("reduce_cells", 0), "us": r["us"],
                       "cached": r["cached"]})
     best = min(timed, key=lambda r: r["us"])
     return dict(best, candidates=timed, cached=all(t["cached"] for t in timed))
@@ -161,11 +184,12 @@ def tune_cutoff(tol, nodes, tris, grid, es_w, es_gamma, alpha=2, precision=FP64,
 
 def tuned_geometry(nodes, tris, grid, m, es_w, es_gamma, alpha=2, precision=FP64, eta2=37.0,
                    window=WINDOW_GAUSS, targets=None, cache=None):
-    """Geometry with the tuned gridding split (timed now or read from `cache`)."""
+    """Geometry with the tuned gridding split and block-sum form (timed now or
+    read from `cache`)."""
     r = tune_share(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, window=window,
                    targets=targets, cache=cache)
     G = Geometry(nodes, tris, grid, m, es_w, es_gamma, alpha, precision, eta2, window=window,
-                 targets=targets, seg_share=r["seg_share"])
+                 targets=targets, seg_share=r["seg_share"], reduce_cells=r.get("reduce_cells", 0))
     return G, r
 
 

@@ -130,6 +130,7 @@ struct slp_geom {
   int32_t terms_kept = 0;
   int32_t n_slots = 0;           // segments (padded gridding blocks)
   int64_t share = 0;             // sources per segment piece in effect
+  int32_t reduce_cells = 0;      // block-sum cells per thread (0 = automatic)
   int32_t n_units = 0;           // gridding work units (workgroups per item)
   int32_t cap = 1;               // batch items the per-item buffers hold
   int64_t item_elems[5]{};       // per item: scratch, grid_a, S1 (complex), S2 (complex), grid_g
@@ -290,6 +291,9 @@ int validate_params(const slp_params *p) {
   if (p->seg_share != 0 && (p->seg_share < 64 || p->seg_share > (1 << 24)))
     return fail(SLP_EINVAL, "seg_share must be 0 (automatic) or in [64, 2^24] (got %d)",
                 p->seg_share);
+  if (p->reduce_cells < 0 || p->reduce_cells > 2)
+    return fail(SLP_EINVAL, "reduce_cells must be 0 (automatic), 1 or 2 (got %d)",
+                p->reduce_cells);
   return SLP_OK;
 }
 
@@ -628,7 +632,7 @@ int run_eval(slp_geom *G, const WorkBufs &W, const slp::BatchPtrs &ptrs, int nb,
     // spread (the charges q = w g are formed inside the gridding)
     const slp::SpreadBinsArgs<T> a = spread_args<T>(G, W);
     const slp::SpreadReduceArgs<T> r = reduce_args<T>(G, W);
-    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_units, G->m, nb, st,
+    HIP_TRY(slp::launch_spread<T>(a, r, ptrs, G->n_units, G->m, nb, G->reduce_cells, st,
                                   tm ? G->evs()[1] : nullptr));
   }
   if (tm) HIP_TRY(hipEventRecord(G->evs()[2], st));
@@ -1054,6 +1058,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
                             ? (int64_t)p->seg_share
                             : std::max<int64_t>(mx ? 150 : 300, (Ms + max_units - 1) / max_units);
   G->share = share;
+  G->reduce_cells = p->reduce_cells;
   std::vector<int4> segs, chunks;
   std::vector<int32_t> runs;
   std::vector<int64_t> seg_size;
@@ -1893,6 +1898,8 @@ int slp_geom_get_info(const slp_geom *G, slp_geom_info *info) {
   info->device_bytes = G->bytes;
   info->seg_share = G->share;
   info->n_segments = G->n_slots;
+  const int64_t ntiles = (int64_t)G->tiles[0] * G->tiles[1] * G->tiles[2];
+  info->reduce_cells = G->reduce_cells ? G->reduce_cells : (ntiles >= slp::kReduceTwoCells ? 2 : 1);
   return SLP_OK;
 }
 

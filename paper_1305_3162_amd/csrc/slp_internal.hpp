@@ -133,11 +133,17 @@ struct FftPass {
   int64_t in_bstride, out_bstride;   // per batch item (blockIdx.y)
 };
 
+// Region tiles (times batch items) from which the block sum takes two cells
+// per thread in workgroups of 256 when left automatic (below: one cell per
+// thread in workgroups of 512). Both forms add a cell's terms in one order.
+constexpr int64_t kReduceTwoCells = 2048;
+
 // Every launch covers nb batch items (gridDim.y = nb, 1 <= nb <= kMaxBatch).
 // The gridding forms the charges q = w g itself from the density pointers.
+// cells: block-sum cells per thread, 1 or 2, 0 = automatic (kReduceTwoCells).
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                         const BatchPtrs &p, int n_units, int m, int nb, hipStream_t s,
+                         const BatchPtrs &p, int n_units, int m, int nb, int cells, hipStream_t s,
                          hipEvent_t between);   // recorded between the two kernels if set
 // Work units per compute unit for the gridding kernel of cut-off m (how many
 // of its workgroups fit in one CU's LDS, at most 2). Host-only.

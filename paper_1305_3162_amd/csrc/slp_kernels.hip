@@ -477,11 +477,6 @@ __global__ __launch_bounds__((SpreadShape<T, M>::THREADS)) void k_spread_bins_mu
   spread_bins_body<T, M>(a, win, gptr(ptrs.dens[w.x]), w.y, 0);
 }
 
-// Region tiles (times batch items) from which the block sum takes two cells
-// per thread in workgroups of 256 (below: one cell per thread, 512). At the
-// threshold the 256-thread form has 32 waves per CU.
-constexpr int64_t kReduceTwoCells = 2048;
-
 // One workgroup per region tile, one or two cells per thread. For each of the
 // 27 neighbouring tiles (fixed order) and each of its segments, the threads
 // whose cell the block covers read the matching sub-block, which is
@@ -559,7 +554,7 @@ __global__ __launch_bounds__(512 / CPT) void k_spread_reduce_multi(const MultiIt
 
 template <typename T, int M>
 static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                           const BatchPtrs &p, int n_units, int nb, hipStream_t s,
+                           const BatchPtrs &p, int n_units, int nb, int cells, hipStream_t s,
                            hipEvent_t between) {
   using S = SpreadShape<T, M>;
   if (n_units > 0)
@@ -572,10 +567,11 @@ static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T>
     if (e != hipSuccess) return e;
   }
   const int64_t tiles = (int64_t)r.tiles[0] * r.tiles[1] * r.tiles[2];
-  // two cells per thread where there are enough tiles to fill the chip (film
-  // regions of 5,408 and 8,427 tiles: 51 -> 42 and 74 -> 59 us); one where
-  // there are few (a cube surface, 512 tiles: 16 against 22 us)
-  if (tiles * nb >= kReduceTwoCells)
+  // automatic: two cells per thread where there are enough tiles to fill the
+  // chip (film regions of 5,408 and 8,427 tiles: 51 -> 42 and 74 -> 59 us; at
+  // the threshold the 256-thread form has 32 waves per CU); one where there
+  // are few (a cube surface, 512 tiles: 16 against 22 us)
+  if (cells == 2 || (cells == 0 && tiles * nb >= kReduceTwoCells))
     hipLaunchKernelGGL((k_spread_reduce<T, M, 2>), dim3((unsigned)tiles, (unsigned)nb), dim3(256), 0,
                        s, r);
   else
@@ -586,17 +582,18 @@ static hipError_t spread_m(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T>
 
 template <typename T>
 hipError_t launch_spread(const SpreadBinsArgs<T> &a, const SpreadReduceArgs<T> &r,
-                         const BatchPtrs &p, int n_units, int m, int nb, hipStream_t s,
+                         const BatchPtrs &p, int n_units, int m, int nb, int cells, hipStream_t s,
                          hipEvent_t between) {
+  if (cells < 0 || cells > 2) return hipErrorInvalidValue;
   switch (m) {
-    case 1: return spread_m<T, 1>(a, r, p, n_units, nb, s, between);
-    case 2: return spread_m<T, 2>(a, r, p, n_units, nb, s, between);
-    case 3: return spread_m<T, 3>(a, r, p, n_units, nb, s, between);
-    case 4: return spread_m<T, 4>(a, r, p, n_units, nb, s, between);
-    case 5: return spread_m<T, 5>(a, r, p, n_units, nb, s, between);
-    case 6: return spread_m<T, 6>(a, r, p, n_units, nb, s, between);
-    case 7: return spread_m<T, 7>(a, r, p, n_units, nb, s, between);
-    case 8: return spread_m<T, 8>(a, r, p, n_units, nb, s, between);
+    case 1: return spread_m<T, 1>(a, r, p, n_units, nb, cells, s, between);
+    case 2: return spread_m<T, 2>(a, r, p, n_units, nb, cells, s, between);
+    case 3: return spread_m<T, 3>(a, r, p, n_units, nb, cells, s, between);
+    case 4: return spread_m<T, 4>(a, r, p, n_units, nb, cells, s, between);
+    case 5: return spread_m<T, 5>(a, r, p, n_units, nb, cells, s, between);
+    case 6: return spread_m<T, 6>(a, r, p, n_units, nb, cells, s, between);
+    case 7: return spread_m<T, 7>(a, r, p, n_units, nb, cells, s, between);
+    case 8: return spread_m<T, 8>(a, r, p, n_units, nb, cells, s, between);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1372,10 +1369,10 @@ template const void *interp_kernel<float>(int);
 template const void *interp_kernel<double>(int);
 template hipError_t launch_spread<float>(const SpreadBinsArgs<float> &,
                                          const SpreadReduceArgs<float> &, const BatchPtrs &, int,
-                                         int, int, hipStream_t, hipEvent_t);
+                                         int, int, int, hipStream_t, hipEvent_t);
 template hipError_t launch_spread<double>(const SpreadBinsArgs<double> &,
                                           const SpreadReduceArgs<double> &, const BatchPtrs &,
-                                          int, int, int, hipStream_t, hipEvent_t);
+                                          int, int, int, int, hipStream_t, hipEvent_t);
 template hipError_t launch_spread_multi<float>(const MultiItem<float> *, const int2 *, int64_t,
                                                const int2 *, int64_t, int, const BatchPtrs &,
                                                const SpreadBinsArgs<float> &, hipStream_t);

@@ -61,3 +61,17 @@ def test_seg_share_validation_and_device_bytes():
     for bad in (1, 63, (1 << 24) + 1, -5):
         with pytest.raises(slp.SlpError, match="seg_share"):
             slp.geometry_device_bytes(*args, seg_share=bad)
+
+
+def test_reduce_cells_validation():
+    """The block-sum form (slp_params.reduce_cells): 0 automatic, 1 or 2 cells
+    per thread; it changes no buffer, so the device bytes are the same."""
+    wl = cube_random(16, 2, 64, 4)
+    w, g = es_for(wl)
+    args = (wl.nodes, wl.tris, wl.grid, 4, w, g, wl.alpha, slp.FP64)
+    auto = slp.geometry_device_bytes(*args)
+    for cells in (1, 2):
+        assert slp.geometry_device_bytes(*args, reduce_cells=cells) == auto
+    for bad in (-1, 3, 4):
+        with pytest.raises(slp.SlpError, match="reduce_cells"):
+            slp.geometry_device_bytes(*args, reduce_cells=bad)

@@ -1,8 +1,10 @@
-"""The gridding split (slp_params.seg_share) and the timing autotuner on the
-device: every split gives the automatic split's potential up to rounding, the
-segment count follows the share, the tuner keeps the fastest timed candidate
-and reads it back from its cache, and the tuned window and cut-off meet the
-requested tolerance against the oracle's non-uniform DFT."""
+"""The gridding split (slp_params.seg_share), the block-sum form
+(slp_params.reduce_cells) and the timing autotuner on the device: every split
+and both block-sum forms give the automatic potential up to rounding, the
+segment count follows the share, the tuner keeps the
+fastest timed candidate and reads it back from its cache, and the tuned window
+and cut-off meet the requested tolerance against the oracle's non-uniform
+DFT."""
 import numpy as np
 import pytest
 
@@ -62,14 +64,19 @@ def test_tune_share_keeps_the_fastest_and_caches(tmp_path):
     log(f"case tune sphere_l4 m=6: {r}")
     assert not r["cached"] and r["candidates"]
     assert r["us"] == min(c["us"] for c in r["candidates"])
-    assert r["seg_share"] in [c["seg_share"] for c in r["candidates"]]
+    assert (r["seg_share"], r["reduce_cells"]) in [(c["seg_share"], c["reduce_cells"])
+                                                   for c in r["candidates"]]
     assert any(c["seg_share"] == r["auto_share"] for c in r["candidates"])
+    # both block-sum forms timed at the fastest split
+    assert {c["reduce_cells"] for c in r["candidates"]} == {1, 2}
     r2 = at.tune_share(wl.nodes, wl.tris, wl.grid, 6, w, g, wl.alpha, slp.FP64, wl.eta2,
                        cache=cache, reps=5)
     assert r2["cached"] and r2["seg_share"] == r["seg_share"]
+    assert r2["reduce_cells"] == r["reduce_cells"]
     G, r3 = at.tuned_geometry(wl.nodes, wl.tris, wl.grid, 6, w, g, wl.alpha, slp.FP64, wl.eta2,
                               cache=cache)
     assert r3["cached"] and G.info["seg_share"] == r["seg_share"]
+    assert G.info["reduce_cells"] == r["reduce_cells"]
     d = torch.as_tensor(wl.dens).cuda()
     got = G.solve(d).cpu().numpy()
     G0 = slp.Geometry(wl.nodes, wl.tris, wl.grid, 6, w, g, wl.alpha, slp.FP64, wl.eta2)
@@ -98,3 +105,44 @@ def test_tune_cutoff_meets_the_tolerance(prec, tol, tmp_path):
     log(f"  rel-L2 vs oracle NDFT {e:.2e}")
     assert e <= tol
     G.close()
+
+
+@pytest.mark.parametrize("prec,m,window", [(slp.FP64, 4, slp.WINDOW_KB), (slp.FP32, 3, slp.WINDOW_KB),
+                                           (slp.FP64, 8, slp.WINDOW_GAUSS)])
+def test_block_sum_forms_agree(prec, m, window):
+    """slp_params.reduce_cells: one or two cells per thread of the block sum add
+    each cell's terms in one order, so the potentials differ only by the
+    gridding's own rounding order (its LDS accumulation order varies with
+    scheduling), single and batched. The region of this cube (512 or 729
+    tiles) takes one cell per thread automatically, and two in a batch of four
+    densities (at least 2048 tiles)."""
+    wl = cube_random(32, 3, 128, m)
+    w, g = es_for(wl)
+    geos = {c: slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, prec, wl.eta2,
+                            window=window, reduce_cells=c) for c in (0, 1, 2)}
+    tiles = int(np.prod(geos[0].info["tiles"]))
+    log(f"case block-sum forms prec={prec} m={m}: {tiles} tiles")
+    assert tiles < 2048 <= 4 * tiles
+    assert [geos[c].info["reduce_cells"] for c in (0, 1, 2)] == [1, 1, 2]
+    tol = 1e-14 if prec == slp.FP64 else 1e-6
+    rng = np.random.default_rng(11)
+    dens = [torch.as_tensor(rng.normal(size=wl.n_src)).cuda() for _ in range(4)]
+    single = {c: geos[c].solve(dens[0]) for c in (0, 1, 2)}
+    batched = {}
+    for c in (0, 1, 2):
+        phis = [torch.full((wl.n_nodes,), float("nan"), dtype=torch.float64, device="cuda")
+                for _ in range(4)]
+        slp.eval_batched([geos[c].handle] * 4, dens, phis)
+        batched[c] = [p.cpu().numpy() for p in phis]
+    torch.cuda.synchronize()
+    single = {c: v.cpu().numpy() for c, v in single.items()}
+    assert np.isfinite(single[1]).all()
+    for c in (0, 2):
+        assert rel_l2(single[c], single[1]) <= tol, c
+    for k in range(4):
+        assert np.isfinite(batched[1][k]).all()
+        for c in (0, 2):
+            assert rel_l2(batched[c][k], batched[1][k]) <= tol, (c, k)
+    assert rel_l2(batched[2][0], single[1]) <= tol
+    for G in geos.values():
+        G.close()
