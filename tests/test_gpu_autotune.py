@@ -146,3 +146,26 @@ def test_block_sum_forms_agree(prec, m, window):
     assert rel_l2(batched[2][0], single[1]) <= tol
     for G in geos.values():
         G.close()
+
+
+def test_block_sum_forms_on_the_smallest_regions():
+    """Both block-sum forms on regions of one to a few tiles (an icosphere on
+    16^3 and 32^3 grids), where the two-cell form has more threads' cells on
+    the region's edge than inside it."""
+    for level, grid, m in ((1, 16, 3), (2, 32, 4), (2, 32, 2)):
+        wl = sphere_random(level, 90 + level, grid, m)
+        w, g = es_for(wl)
+        d = torch.as_tensor(wl.dens).cuda()
+        out = {}
+        for c in (1, 2):
+            G = slp.Geometry(wl.nodes, wl.tris, wl.grid, m, w, g, wl.alpha, slp.FP64, wl.eta2,
+                             window=slp.WINDOW_KB, reduce_cells=c)
+            out[c] = G.solve(d).cpu().numpy()
+            tiles = G.info["tiles"]
+            G.close()
+        log(f"case block-sum forms small region: level {level}, grid {grid}, m {m}, tiles {tiles}")
+        assert np.isfinite(out[1]).all()
+        assert rel_l2(out[2], out[1]) <= 1e-14
+        e = rel_l2(out[2], direct.phi_ndft(oracle_problem(wl)))
+        log(f"  rel-L2 vs oracle NDFT {e:.2e}")
+        assert e <= 4 * np.exp(-2 * np.pi * m / 3)
