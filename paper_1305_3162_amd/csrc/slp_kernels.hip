@@ -662,7 +662,10 @@ struct InterpShape {
   static constexpr int fit(int waves) {
     return (160 * 1024) / (GT * (int)sizeof(T) + waves * WAVE_LDS);
   }
-  static constexpr int WAVES = fit(4) >= 4 ? 4 : (fit(8) >= 2 ? 8 : 16);
+  // FP64 with 2m = 8: eight waves share a tile's targets, three workgroups per
+  // CU (cube64: 17 -> 14 us; the film, with fewer targets per tile, unchanged)
+  static constexpr int WAVES =
+      (sizeof(T) == 8 && W == 8) ? 8 : (fit(4) >= 4 ? 4 : (fit(8) >= 2 ? 8 : 16));
   static constexpr int THREADS = WAVES * 64;
   static constexpr int PERG = (P3 + THREADS - 1) / THREADS;       // staged cells per thread
   static constexpr int NLD = (7 * TPW + 63) / 64;                 // target fields per lane
