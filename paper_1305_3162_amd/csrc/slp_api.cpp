@@ -1037,7 +1037,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   // segments: the sources of one tile, cut into equal pieces where a tile holds
   // more than 1.5x the average share of one workgroup slot of the chip (every
   // CU holding as many gridding workgroups as its LDS allows). Each segment is
-  // cut into chunks of <= kSpreadChunk sources and runs of sources sharing one
+  // cut into chunks of <= spread_chunk(fp64, m) sources and runs of sources sharing one
   // cell. (At least max(64, (8 + 2m - 1)^3 / 20) sources per share, / 80 for the
   // matrix-core form, so that
   // small problems do not pay more for storing and summing blocks than for
@@ -1063,7 +1063,7 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
   std::vector<int32_t> runs;
   std::vector<int64_t> seg_size;
   {
-    const int CH = slp::kSpreadChunk;
+    const int CH = slp::spread_chunk(p->precision == SLP_FP64, p->m);
     // a chunk's runs longest first: the vector form processes several runs of a
     // wave side by side, for as many steps as the longest of them
     auto close_chunk = [&](const int4 &c) {
@@ -1171,8 +1171,9 @@ int setup_impl(slp_geom **out, const double *nodes, int64_t n_nodes, const int32
       ok = sg.x < sg.y && sg.z >= 0 && sg.z < ntiles;
       for (int c = sg.x; ok && c < sg.y; ++c) {
         const int4 ch = chunks[c];
-        ok = ch.x == next_src && ch.y >= 1 && ch.y <= slp::kSpreadChunk && ch.w >= 1 &&
-             ch.w <= slp::kSpreadChunk && ch.z + ch.w <= (int)runs.size();
+        const int CH = slp::spread_chunk(G->prec == SLP_FP64, G->m);
+        ok = ch.x == next_src && ch.y >= 1 && ch.y <= CH && ch.w >= 1 && ch.w <= CH &&
+             ch.z + ch.w <= (int)runs.size();
         // the chunk's runs (in any order) cover its sources exactly once
         std::vector<std::pair<int, int>> span;
         for (int r = 0; ok && r < ch.w; ++r) {

@@ -18,9 +18,11 @@ constexpr int kMaxM = 8;      // largest supported window cut-off
 // segment index, the segments of a tile consecutive; blocked layout, see
 // pad_block_index). A work unit (one workgroup) takes a list of segments; the
 // setup gives every unit one segment, longest first. A segment is cut into
-// chunks of at most kSpreadChunk sources; a run is a sequence of sources of one
-// chunk that share one grid cell.
-constexpr int kSpreadChunk = 512;
+// chunks of at most spread_chunk(fp64, m) sources; a run is a sequence of
+// sources of one chunk that share one grid cell. FP64 with m = 4 stages fewer
+// sources per chunk so that its larger factor batches (ten sources per run)
+// still leave two gridding workgroups per CU.
+constexpr int spread_chunk(bool fp64, int m) { return fp64 && m == 4 ? 448 : 512; }
 // Units are sized for this many compute units (MI355X).
 constexpr int kComputeUnits = 256;
 // Densities evaluated on one geometry by one launch of every stage.

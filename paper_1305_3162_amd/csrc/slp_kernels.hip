@@ -140,7 +140,7 @@ struct SpreadShape {
   static constexpr int WAVES = 8;
   static constexpr int THREADS = WAVES * 64;
   static constexpr int SBW = 12;                       // sources per factor batch (matrix form)
-  static constexpr int CH = kSpreadChunk;              // sources staged per block chunk
+  static constexpr int CH = spread_chunk(sizeof(T) == 8, M);   // sources staged per block chunk
   // FP64 with 2m = 16: a run's update goes to the matrix cores (see
   // k_spread_bins); the factors of a source then sit 16-byte aligned
   static constexpr bool MX = sizeof(T) == 8 && W == 16;
@@ -163,7 +163,7 @@ struct SpreadShape {
   static constexpr int L = (W / CX) * (W / CY) * (W / CZ);
   static constexpr int R = 64 / L;
   static constexpr int SB0 = 64 / (3 * R);
-  static constexpr int SB = LAY8 ? 8 : (SB0 > 12 ? 12 : SB0);
+  static constexpr int SB = LAY8 ? 10 : (SB0 > 12 ? 12 : SB0);
   static constexpr int NFAC = MX ? SBW : R * SB;       // factor slots per wave
   static constexpr int FST = MX ? 3 * W + 2 : 3 * W + 1;   // LDS stride of one source's factors
   static_assert(W % CX == 0 && W % CY == 0 && W % CZ == 0 && L <= 64 && R >= 1 && SB >= 1,
