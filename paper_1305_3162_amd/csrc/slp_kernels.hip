@@ -168,6 +168,8 @@ struct SpreadShape {
   static constexpr int FST = MX ? 3 * W + 2 : 3 * W + 1;   // LDS stride of one source's factors
   static_assert(W % CX == 0 && W % CY == 0 && W % CZ == 0 && L <= 64 && R >= 1 && SB >= 1,
                 "gridding shape");
+  // the factors of a step are built one (run, source, axis) per lane
+  static_assert(MX || 3 * R * SB <= 64, "factor step larger than a wave");
 };
 
 int64_t pad_cells(int m) {
